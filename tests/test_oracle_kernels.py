@@ -1,0 +1,111 @@
+"""Pins of the oracle's covariance functions and rounding (CPU only).
+
+Each check compares the oracle with something other than itself: brute-force
+loops, closed-form values of the kernels, an independent library
+implementation (scikit-learn's RBF / Matern kernels, scipy's cdist), finite
+differences, or hand-derived rounding cases.
+"""
+
+import numpy as np
+import pytest
+import scipy.spatial.distance as ssd
+from sklearn.gaussian_process import kernels as skk
+
+from oracle import kernels as K
+from oracle import precision as P
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+
+def test_sqdist_brute_force():
+    g = np.random.default_rng(0)
+    X = g.standard_normal((7, 3))
+    D = K.sqdist(X)
+    for i in range(7):
+        for j in range(7):
+            s = 0.0
+            for t in range(3):
+                s += (X[i, t] - X[j, t]) ** 2
+            assert abs(D[i, j] - s) <= 1e-14 * max(1.0, s)
+    assert np.all(np.diag(D) == 0.0)
+    Y = g.standard_normal((5, 3))
+    np.testing.assert_allclose(K.sqdist(X, Y), ssd.cdist(X, Y, "sqeuclidean"),
+                               rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("ell,s2", [(1.0, 1.0), (0.7, 2.5), (3.3, 0.4)])
+def test_kernel_closed_forms(ell, s2):
+    # r = 0 gives the signal variance for every kernel
+    for kern in (K.RBF, K.MATERN32, K.MATERN52):
+        assert K.kernel_from_r2(0.0, kern, ell, s2) == pytest.approx(s2, rel=1e-15)
+    e = np.exp(-1.0)
+    # RBF at r^2 = 2 ell^2: s2 e^-1
+    assert K.kernel_from_r2(2 * ell * ell, K.RBF, ell, s2) == pytest.approx(s2 * e, rel=1e-14)
+    # Matern-3/2 at r = ell/sqrt3: t = 1 -> s2 (1 + 1) e^-1
+    assert K.kernel_from_r2(ell * ell / 3, K.MATERN32, ell, s2) == pytest.approx(2 * s2 * e, rel=1e-14)
+    # Matern-5/2 at r = ell/sqrt5: t = 1 -> s2 (1 + 1 + 1/3) e^-1
+    assert K.kernel_from_r2(ell * ell / 5, K.MATERN52, ell, s2) == pytest.approx(7 / 3 * s2 * e, rel=1e-14)
+
+
+@pytest.mark.parametrize("kern,sk", [
+    (K.RBF, lambda ell: skk.RBF(length_scale=ell)),
+    (K.MATERN32, lambda ell: skk.Matern(length_scale=ell, nu=1.5)),
+    (K.MATERN52, lambda ell: skk.Matern(length_scale=ell, nu=2.5)),
+])
+def test_gram_matches_sklearn(kern, sk):
+    g = np.random.default_rng(1)
+    X = g.standard_normal((40, 5))
+    ell, s2 = 1.7, 1.3
+    ref = s2 * sk(ell)(X)
+    np.testing.assert_allclose(K.gram(X, kern, ell, s2), ref, rtol=1e-12, atol=1e-14)
+
+
+def test_operator_spd_and_blocked_matvec():
+    g = np.random.default_rng(2)
+    X = g.standard_normal((300, 4))
+    A = K.operator(X, K.MATERN52, 1.1, 1.0, 1e-3)
+    assert np.allclose(A, A.T)
+    assert np.linalg.eigvalsh(A).min() > 0.9e-3
+    V = g.standard_normal((300, 3))
+    np.testing.assert_allclose(K.matvec_blocked(X, K.MATERN52, 1.1, 1.0, 1e-3, V, block=37),
+                               A @ V, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("kern", [K.RBF, K.MATERN32, K.MATERN52])
+def test_dgram_dlog_ell_finite_difference(kern):
+    g = np.random.default_rng(3)
+    X = g.standard_normal((30, 3))
+    ell, s2, h = 1.4, 0.8, 1e-5
+    fd = (K.gram(X, kern, ell * np.exp(h), s2) - K.gram(X, kern, ell * np.exp(-h), s2)) / (2 * h)
+    np.testing.assert_allclose(K.dgram_dlog_ell(X, kern, ell, s2), fd, rtol=1e-7, atol=1e-9)
+
+
+def test_round_bf16_hand_cases():
+    u = 2.0 ** -7                     # bf16 spacing just above 1
+    cases = [
+        (1.0, 1.0),
+        (1.0 + u / 2, 1.0),                     # tie -> even (1.0)
+        (1.0 + 3 * u / 2, 1.0 + 2 * u),         # tie -> even (mantissa ...010)
+        (1.0 + u / 2 + 2.0 ** -30, 1.0 + u),    # just above the tie: single rounding rounds up
+        (-(1.0 + u / 2 + 2.0 ** -30), -(1.0 + u)),
+        (3.14159265358979, 3.140625),
+        (255.5, 256.0),
+        (0.1, 0.10009765625),
+        (1e-3, 0.00099945068359375),
+        (0.0, 0.0),
+    ]
+    for x, want in cases:
+        assert P.round_bf16(np.array([x]))[0] == want, x
+
+
+def test_round_bf16_matches_torch_on_fp32_values():
+    torch = pytest.importorskip("torch")
+    g = np.random.default_rng(4)
+    x = g.uniform(-4, 4, 20000).astype(np.float32).astype(np.float64)
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).double().numpy()
+    np.testing.assert_array_equal(P.round_bf16(x), ref)
+
+
+def test_round_fp32():
+    assert P.round_fp32(np.array([0.1]))[0] == float(np.float32(0.1))
+    assert P.round_points(np.array([[0.1]]), P.PREC_FP64)[0, 0] == 0.1

@@ -1,0 +1,256 @@
+"""Pins of the oracle's CG, def-CG, harmonic Ritz, sequence, refinement and
+GP-gradient functions (CPU only).
+
+What pins them (none of these re-types the oracle's own formulas):
+* a Cholesky solve (LAPACK via scipy) for final solutions;
+* finite termination of CG in at most (#distinct eigenvalues) steps, and of
+  def-CG with exact eigenvectors in at most (#remaining distinct eigenvalues);
+* the Galerkin optimality of the def-CG iterate, checked by a dense A-norm
+  least-squares solve over the same search space;
+* the invariants the method fixes: W^T r_j = 0, W^T A p_j = 0, r_i^T r_j = 0,
+  p_i^T A p_j = 0;
+* scipy.linalg.eigh(G, F) for the harmonic Ritz pairs, and exact eigenvalues
+  when span(Z) holds an invariant subspace;
+* central finite differences and a deterministic exact trace for the GP
+  gradient.
+"""
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import cg as C
+from oracle import gp as GP
+from oracle import kernels as K
+from oracle import precision as P
+from oracle import refine as R
+from oracle import ritz as RZ
+from oracle import sequence as S
+import workloads
+
+
+def _kernel_system(n=200, d=3, ell=1.0, sigma2=1e-2, seed=0, kern=K.RBF):
+    g = np.random.default_rng(seed)
+    X = g.standard_normal((n, d))
+    A = K.operator(X, kern, ell, 1.0, sigma2)
+    b = g.standard_normal(n)
+    return X, A, b
+
+
+def test_cg_matches_cholesky():
+    _, A, b = _kernel_system()
+    res = C.cg(A, b, tol=1e-12)
+    x_ref = scipy.linalg.cho_solve(scipy.linalg.cho_factor(A), b)
+    assert res.converged
+    assert np.linalg.norm(b - A @ res.x) / np.linalg.norm(b) <= 1.5e-12
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(res.x - x_ref) / np.linalg.norm(x_ref) <= 10 * kappa * 1e-12
+
+
+def test_cg_finite_termination():
+    eigs = np.repeat([1.0, 2.0, 5.0, 11.0, 40.0], 20)   # 5 distinct eigenvalues
+    A, _ = workloads.spd_with_spectrum(eigs)
+    b = np.random.default_rng(1).standard_normal(100)
+    res = C.cg(A, b, tol=1e-10)
+    assert res.converged and res.iters <= 5
+
+
+def test_cg_invariants():
+    _, A, b = _kernel_system(n=150)
+    res = C.cg(A, b, tol=1e-10, store_all=True)
+    Rm, Pm = res.all_r[:, :12], res.all_p[:, :12]
+    Rn = Rm / np.linalg.norm(Rm, axis=0)
+    G = Rn.T @ Rn
+    assert np.abs(G - np.eye(12)).max() < 1e-8        # residuals orthogonal
+    H = Pm.T @ A @ Pm
+    dH = np.sqrt(np.diag(H))
+    Hn = H / dH[:, None] / dH[None, :]
+    # directions A-conjugate: exactly for neighbours, up to the slow FP64
+    # loss of global conjugacy (grows like kappa * eps) otherwise
+    assert np.abs(np.diag(Hn, 1)).max() < 1e-12
+    assert np.abs(Hn - np.eye(12)).max() < 1e-6
+
+
+def test_defcg_empty_W_is_cg_bitwise():
+    _, A, b = _kernel_system(n=120, seed=3)
+    r1 = C.cg(A, b, tol=1e-9, L=10)
+    r2 = C.defcg(A, b, W=np.zeros((120, 0)), tol=1e-9, L=10)
+    assert r1.iters == r2.iters
+    assert np.array_equal(r1.x, r2.x)
+    assert np.array_equal(r1.P, r2.P)
+
+
+def _deflation_case():
+    # k = 6 large outlying eigenvalues + 8 distinct small ones (each x10)
+    big = [500.0, 420.0, 300.0, 250.0, 180.0, 120.0]
+    small = np.repeat([1.0, 1.3, 1.7, 2.2, 2.8, 3.5, 4.1, 5.0], 10)
+    eigs = np.concatenate([small, big])
+    A, Q = workloads.spd_with_spectrum(eigs, seed=11)
+    W = Q[:, -6:]          # exact eigenvectors of the 6 largest eigenvalues
+    b = np.random.default_rng(5).standard_normal(len(eigs))
+    return A, W, b
+
+
+def test_defcg_exact_eigenvectors_finite_termination():
+    A, W, b = _deflation_case()
+    plain = C.cg(A, b, tol=1e-10)
+    defl = C.defcg(A, b, W=W, tol=1e-10)
+    assert defl.converged and defl.iters <= 8      # only the 8 small clusters remain
+    assert plain.iters > defl.iters
+    x_ref = np.linalg.solve(A, b)
+    assert np.linalg.norm(defl.x - x_ref) / np.linalg.norm(x_ref) < 1e-9
+
+
+def test_defcg_invariants_and_galerkin_optimality():
+    X, A, b = _kernel_system(n=160, seed=7)
+    g = np.random.default_rng(8)
+    W = g.standard_normal((160, 5))
+    x_init = g.standard_normal(160)
+    res = C.defcg(A, b, x_init=x_init, W=W, tol=1e-10, store_all=True)
+    R_, P_ = res.all_r, res.all_p
+    nW = np.linalg.norm(W, axis=0)
+    for j in range(min(15, R_.shape[1])):
+        rj = R_[:, j]
+        assert np.abs(W.T @ rj).max() <= 1e-9 * np.linalg.norm(rj) * nW.max()
+        pj = P_[:, j]
+        assert np.abs(W.T @ A @ pj).max() <= 1e-9 * np.linalg.norm(A @ pj) * nW.max()
+    Pm = P_[:, :10]
+    H = Pm.T @ A @ Pm
+    dH = np.sqrt(np.diag(H))
+    Hn = H / dH[:, None] / dH[None, :]
+    assert np.abs(np.diag(Hn, 1)).max() < 1e-12
+    assert np.abs(Hn - np.eye(10)).max() < 1e-6
+    # x_j is the A-norm best approximation of x* over x_{-1} + span(W, p_0..p_{j-1})
+    res_j = C.defcg(A, b, x_init=x_init, W=W, tol=0.0, max_iter=6)
+    Sbasis = np.hstack([W, res.all_p[:, :6]])
+    x_star = np.linalg.solve(A, b)
+    y = np.linalg.solve(Sbasis.T @ A @ Sbasis, Sbasis.T @ A @ (x_star - x_init))
+    x_best = x_init + Sbasis @ y
+    assert np.linalg.norm(res_j.x - x_best) <= 1e-8 * np.linalg.norm(x_best)
+    # true residual matches the recursive one
+    assert np.linalg.norm(b - A @ res.x - res.r_final) <= 1e-9 * np.linalg.norm(b)
+
+
+def test_harmonic_ritz_matches_scipy_eigh():
+    _, A, b = _kernel_system(n=120, seed=9)
+    res = C.cg(A, b, tol=1e-12, L=15)
+    F, G = RZ.harmonic_ritz_FG(res.P, res.AP)
+    theta, U = RZ.harmonic_ritz_pairs(F, G)
+    ref = scipy.linalg.eigh(G, F, eigvals_only=True)
+    np.testing.assert_allclose(theta, ref, rtol=1e-9)
+    np.testing.assert_allclose(U.T @ F @ U, np.eye(U.shape[1]), atol=1e-9)
+    # harmonic Ritz values of an SPD matrix lie inside its spectrum
+    lam = np.linalg.eigvalsh(A)
+    assert theta.min() >= lam.min() * (1 - 1e-9) and theta.max() <= lam.max() * (1 + 1e-9)
+
+
+def test_harmonic_ritz_full_basis_gives_eigenvalues():
+    A, _ = workloads.spd_with_spectrum(np.linspace(1.0, 9.0, 12), seed=3)
+    Z = np.random.default_rng(0).standard_normal((12, 12))
+    theta, _ = RZ.harmonic_ritz_pairs(*RZ.harmonic_ritz_FG(Z, A @ Z))
+    np.testing.assert_allclose(theta, np.linspace(1.0, 9.0, 12), rtol=1e-10)
+
+
+def test_harmonic_ritz_invariant_subspace_exact():
+    A, W, _ = _deflation_case()
+    g = np.random.default_rng(2)
+    Z = np.hstack([W[:, :3], g.standard_normal((A.shape[0], 4))])
+    Wn, AWn, theta, U = RZ.harmonic_ritz(Z, A @ Z, k=3)
+    np.testing.assert_allclose(np.sort(theta), [300.0, 420.0, 500.0], rtol=1e-10)
+    # W'^T A W' = I (U is F-orthonormal)
+    np.testing.assert_allclose(Wn.T @ A @ Wn, np.eye(3), atol=1e-9)
+    np.testing.assert_allclose(AWn, A @ Wn, rtol=1e-10, atol=1e-10)
+
+
+def test_harmonic_ritz_rank_deficient_F():
+    _, A, b = _kernel_system(n=80, seed=4)
+    res = C.cg(A, b, tol=1e-12, L=6)
+    Z = np.hstack([res.P, res.P[:, :2]])           # duplicated columns
+    Wn, _, theta, U = RZ.harmonic_ritz(Z, A @ Z, k=4)
+    F, G = RZ.harmonic_ritz_FG(res.P, res.AP)
+    ref = np.sort(scipy.linalg.eigh(G, F, eigvals_only=True))[::-1][:4]
+    np.testing.assert_allclose(theta, ref, rtol=1e-7)
+    assert np.all(np.isfinite(Wn))
+
+
+def test_sequence_first_system_is_cg_and_deflation_helps():
+    w = workloads.small(n=400, d=4, systems=4)
+    mats = [K.operator(w["X"], w["kernel"], ell, w["s2"], w["sigma2"]) for ell in w["ells"]]
+    bs = [A @ w["xstar"] + w["noise"][i][:400] for i, A in enumerate(mats)]
+    rec = S.solve_sequence(mats, bs, k=8, L=12, tol=1e-8)
+    plain = S.solve_sequence(mats, bs, k=8, L=12, tol=1e-8, recycle=False)
+    assert rec[0].iters == plain[0].iters
+    assert np.array_equal(rec[0].x, plain[0].x)
+    for r, p, A, b in zip(rec, plain, mats, bs):
+        x_ref = scipy.linalg.cho_solve(scipy.linalg.cho_factor(A), b)
+        assert np.linalg.norm(b - A @ r.x) / np.linalg.norm(b) <= 1.01e-8
+        assert np.linalg.norm(r.x - x_ref) <= 1e-5 * np.linalg.norm(x_ref)
+    assert sum(r.iters for r in rec[1:]) < sum(p.iters for p in plain[1:])
+
+
+def test_sequence_sigma_shift_update_equals_recompute():
+    X, _, b = _kernel_system(n=150, seed=12, kern=K.MATERN52)
+    s2s = [1e-2, 9e-3, 8.1e-3]
+    mats = [K.operator(X, K.MATERN52, 1.0, 1.0, s) for s in s2s]
+    upd = S.solve_sequence(mats, [b] * 3, k=6, L=9, tol=1e-9, sigma2s=s2s)
+    rec = S.solve_sequence(mats, [b] * 3, k=6, L=9, tol=1e-9)
+    # same method up to rounding: iteration counts within 2, same solution
+    for a, c, A in zip(upd, rec, mats):
+        assert abs(a.iters - c.iters) <= 2
+        assert np.linalg.norm(b - A @ a.x) <= 1.01e-9 * np.linalg.norm(b)
+        assert np.linalg.norm(a.x - c.x) <= 1e-6 * np.linalg.norm(c.x)
+
+
+def test_refine_recovers_fp64_solution_from_bf16_operator():
+    g = np.random.default_rng(13)
+    X = g.uniform(-1, 1, (300, 6))
+    ell = 0.5 * workloads.median_distance(X)
+    A64 = K.operator(X, K.MATERN52, ell, 1.0, 1e-3)
+    Xl = P.round_bf16(X)
+    Alow = K.operator(Xl, K.MATERN52, ell, 1.0, 1e-3)
+    b = g.standard_normal(300)
+    x, hist, inner = R.refine(A64, Alow, b, tol=1e-8, inner_tol=1e-4, k=6, L=9)
+    assert hist[-1] <= 1e-8
+    x_ref = np.linalg.solve(A64, b)
+    assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) < 1e-6
+    rho = np.abs(np.linalg.eigvals(np.linalg.solve(Alow, A64 - Alow))).max()
+    for a, c in zip(hist[1:], hist[:-1]):
+        assert a <= 3 * (rho + 1e-4) * np.linalg.cond(A64) ** 0.5 * c
+
+
+def test_gp_gradient_matches_finite_differences():
+    g = np.random.default_rng(14)
+    X = g.standard_normal((120, 3))
+    y = np.sin(X[:, 0]) + 0.1 * g.standard_normal(120)
+    th = np.array([np.log(1.2), np.log(0.9), np.log(0.05)])
+
+    def f(t):
+        return GP.lml(X, y, K.RBF, np.exp(t[0]), np.exp(t[1]), np.exp(t[2]))
+
+    grad = GP.lml_grad_exact(X, y, K.RBF, *np.exp(th))
+    h = 1e-5
+    for j in range(3):
+        e = np.zeros(3)
+        e[j] = h
+        fd = (f(th + e) - f(th - e)) / (2 * h)
+        assert grad[j] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+def test_gp_hutchinson_exact_with_unit_probes_and_unbiased():
+    g = np.random.default_rng(15)
+    X = g.standard_normal((90, 3))
+    y = g.standard_normal(90)
+    par = (K.RBF, 1.1, 1.0, 0.1)
+    exact = GP.lml_grad_exact(X, y, *par)
+    # probes = sqrt(n) e_i (E[z z^T] = I over the n of them): the trace is exact
+    est = GP.lml_grad_hutchinson(X, y, *par, probes=np.sqrt(90.0) * np.eye(90))
+    np.testing.assert_allclose(est, exact, rtol=1e-10, atol=1e-10)
+    # Rademacher probes: unbiased, error within 4 standard errors
+    Z = workloads.rademacher(90, 4000, step=0)
+    est = GP.lml_grad_hutchinson(X, y, *par, probes=Z)
+    A = K.operator(X, *par)
+    Ainv = np.linalg.inv(A)
+    for j, D in enumerate(GP.dA_list(X, *par)):
+        samples = np.sum((Ainv @ Z) * (D @ Z), axis=0)
+        se = 0.5 * samples.std() / np.sqrt(Z.shape[1])
+        assert abs(est[j] - exact[j]) <= 4 * se + 1e-12
