@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Time-to-tolerance of deflated CG on a sequence of kernel systems, one MI355X.
+
+Workload (the precision-form sequence): X is 65536 x 32 drawn U[-1, 1]; the
+operator is Matern-5/2 with ell = 0.5 x median pairwise distance, distances on
+bf16 MFMA with FP32 kernel evaluation and FP64 CG recurrences; the sequence
+steps sigma2_i = 1e-3 * 0.9^i with a fixed b ~ N(0, 1); each system is solved
+by deflated CG with k = 64 recycled harmonic Ritz vectors (L = 96 stored
+directions) inside an iterative refinement against the FP64 operator, to a
+relative residual of 1e-8.
+
+One step = one system of the sequence: set sigma2_i, the deflated solve (all
+CG iterations, deflation projections, refinement residuals with the exact
+FP64 product) and the harmonic Ritz refresh of W.  Warm-up steps are the
+first systems of the sequence (system 0 is plain CG, W is empty); the timed
+steps are the systems after them.  The same timed systems are then solved by
+plain CG (no recycling) for comparison.
+
+Printed: one JSON line with value = time-to-tol per solve (ms), the plain-CG
+time, matvec GFLOP/s = n^2 (2d + 2) / t_sweep, the roofline of the matvec
+sweep (ALU-bound, measured live with HIP events on the operator's stream),
+and the FP64 oracle timed on a bounded sample on the host cores.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz of non-packed VALU issue
+PEAK_VALU_SLOTS = 256 * 64 * 2.4e9
+# VALU issue slots per unique pair of the symmetric sweep (transcendentals
+# v_exp_f32 / v_sqrt_f32 count 2 slots: measured half rate on gfx950):
+#   RBF        exp2(c r2)                    mul + exp(2) + 2 fma        = 5
+#   Matern-3/2 sqrt, exp, (1 + c t) e        sqrt(2) + mul + exp(2) + fma + mul + 2 fma = 8
+#   Matern-5/2 sqrt, exp, (1 + t + t^2/3) e  sqrt(2) + mul + exp(2) + 2 fma + mul + 2 fma = 10
+SLOTS_PER_PAIR = {0: 5, 1: 8, 2: 10}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--literal", action="store_true",
+                    help="ell = 0.5 as written (an almost diagonal operator)")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, matvecs_per_solve, exact_per_solve, rows=384):
+    """The FP64 oracle's blocked matvec on `rows` rows of the same operator,
+    scaled to a full product and to the GPU's products per solve."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import kernels as OK
+    X = w["X"]
+    n = X.shape[0]
+    v = np.random.default_rng(0).standard_normal(n)
+    idx = np.arange(rows)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        y = OK.gram(X[idx], w["kernel"], w["ell"], 1.0, X) @ v
+        t = time.perf_counter() - t0
+    assert np.all(np.isfinite(y))
+    per_matvec = t * n / rows
+    total = per_matvec * (matvecs_per_solve + exact_per_solve)
+    return {"value": round(total * 1e3, 1), "unit": "ms/solve", "cores": 1, "kind": "oracle",
+            "sample": f"oracle FP64 dense-row product on {rows} of {n} rows ({t:.2f} s), "
+                      f"scaled to one full product ({per_matvec:.1f} s) times the "
+                      f"{matvecs_per_solve + exact_per_solve:.1f} products per solve of the "
+                      f"GPU run; one thread"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the row-sharded multi-GPU design is described, not built)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1706_00241_amd as dcg
+    import workloads
+
+    dcg.load()
+    w = workloads.bf16_shift(n=args.n, systems=args.warmup + args.steps, literal=args.literal)
+    n, d = w["X"].shape
+    dev = torch.device("cuda:0")
+    X = torch.as_tensor(w["X"], device=dev)
+    b = torch.as_tensor(w["b"], device=dev)
+    op = dcg.Operator(X, w["kernel"], w["ell"], 1.0, w["sigma2s"][0], prec=dcg.PREC_BF16)
+    rc = dcg.Recycle(n, w["k"], w["L"], device=dev)
+    ws = dcg.SolveWorkspace(n, dev)
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    kw = dict(tol=w["tol"], refine=True, inner_tol=w["inner_tol"], ws=ws, out=x,
+              check_every=8)
+
+    for i in range(args.warmup):
+        op.set_hyper(w["ell"], 1.0, w["sigma2s"][i])
+        _, st = dcg.solve(op, b, rc=rc, **kw)
+        print(f"warmup system {i}: {st['iters']} its, {st['outer_steps']} outer, "
+              f"{st['t_total_ms']:.1f} ms, res {st['rel_res_true']:.2e}", file=sys.stderr,
+              flush=True)
+
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.warmup, args.warmup + args.steps):
+        op.set_hyper(w["ell"], 1.0, w["sigma2s"][i])
+        _, st = dcg.solve(op, b, rc=rc, profile=True, **kw)
+        stats.append(st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    for i, st in enumerate(stats):
+        print(f"system {args.warmup + i}: {st['iters']} its, {st['outer_steps']} outer, "
+              f"{st['t_total_ms']:.1f} ms, res {st['rel_res_true']:.2e}, status {st['status']}",
+              file=sys.stderr, flush=True)
+    bad = [st for st in stats if st["status"] != 0 or st["rel_res_true"] > w["tol"]]
+    if bad:
+        print(f"bench.py: {len(bad)} solves missed the tolerance", file=sys.stderr)
+        sys.exit(1)
+
+    sweeps = sum(st["sweeps_timed"] for st in stats)
+    t_sweep = sum(st["t_sweeps_ms"] for st in stats) / max(1, sweeps) * 1e-3   # s
+    pairs = n * (n + 1) / 2.0
+    slots = pairs * SLOTS_PER_PAIR[w["kernel"]]
+    achieved = slots / t_sweep
+    gflops = n * n * (2 * d + 2) / t_sweep / 1e9
+
+    out = {
+        "metric": "time-to-tol per solve: deflated vs plain CG, n=65536, 1 GPU",
+        "value": round(ms_per_step, 2),
+        "unit": "ms/solve",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 MFMA distances, f32 kernel values, f64 CG",
+        "data": "synthetic",
+        "config": {"workload": ("bf16_shift" + ("_literal" if args.literal else "")
+                                + f": n={n} d={d} X~U[-1,1] matern52 ell={w['ell']:.4f} "
+                                f"sigma2=1e-3*0.9^i k={w['k']} L={w['L']} refine to 1e-8"),
+                   "systems_timed": args.steps, "first_system": args.warmup},
+        "iters_per_solve": round(sum(s["iters"] for s in stats) / args.steps, 1),
+        "matvecs_per_solve": round(sum(s["matvecs"] for s in stats) / args.steps, 1),
+        "exact_matvecs_per_solve": round(sum(s["matvecs_exact"] for s in stats) / args.steps, 1),
+        "matvec_ms": round(t_sweep * 1e3, 4),
+        "matvec_gflops": round(gflops, 1),
+        "gpair_per_s": round(n * n / t_sweep / 1e9, 1),
+        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 2),
+                     "peak": round(PEAK_VALU_SLOTS / 1e12, 2), "unit": "TOP/s",
+                     "frac": round(achieved / PEAK_VALU_SLOTS, 3), "traffic": None,
+                     "kernel": "symv_kernel (symmetric pair sweep)",
+                     "per_launch": f"{pairs:.4g} unique pairs x {SLOTS_PER_PAIR[w['kernel']]} "
+                                   "VALU slots"},
+    }
+
+    if not args.no_plain:
+        # the same systems by plain CG inside the same refinement
+        tp = []
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for i in range(args.warmup, args.warmup + args.steps):
+            op.set_hyper(w["ell"], 1.0, w["sigma2s"][i])
+            _, st = dcg.solve(op, b, rc=None, **kw)
+            tp.append(st)
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - p0) * 1e3 / args.steps
+        out["plain_ms_per_solve"] = round(plain_ms, 2)
+        out["plain_matvecs_per_solve"] = round(sum(s["matvecs"] for s in tp) / args.steps, 1)
+        out["plain_exact_matvecs_per_solve"] = round(
+            sum(s["matvecs_exact"] for s in tp) / args.steps, 1)
+        out["speedup_vs_plain"] = round(plain_ms / ms_per_step, 3)
+        print(f"plain CG: {plain_ms:.1f} ms/solve, {out['plain_matvecs_per_solve']} matvecs",
+              file=sys.stderr, flush=True)
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, out["matvecs_per_solve"],
+                                           out["exact_matvecs_per_solve"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * dcg.h -- C ABI of the MI355X deflated-CG library (libdcg.so).
+ *
+ * Deflated conjugate gradients with Krylov subspace recycling for sequences
+ * of SPD kernel systems A_i x_i = b_i, A_i = K_theta_i(X, X) + sigma_i^2 I
+ * (de Roos & Hennig, arXiv 1706.00241: sequence of Eq. 1, deflated CG of
+ * section 2.2 / Algorithm 1, harmonic Ritz extraction of section 2.3 /
+ * Eq. 7).
+ *
+ * Conventions (apply to every entry point):
+ *  - Array arguments are DEVICE pointers unless the comment says "host".
+ *    Vectors are FP64 and have n entries; blocks of vectors are FP64,
+ *    column-major n x m (leading dimension n).  X is FP64, row-major n x d.
+ *  - All device memory is owned by the caller (allocated e.g. with
+ *    PyTorch).  The library never allocates device memory: each handle
+ *    lives in a caller-provided workspace whose size the *_workspace_bytes
+ *    query returns.  A workspace must stay valid and untouched by the caller
+ *    until the handle is destroyed.  Handles themselves are small host
+ *    objects freed by the matching *_destroy call.
+ *  - Every function returns a status code (dcg_status) and never aborts or
+ *    throws across the ABI.  On an error, output arrays are unspecified
+ *    unless stated otherwise.
+ *  - Work is enqueued on the stream given to dcg_create_operator.  Calls
+ *    that return results to host memory (dcg_solve, dcg_recycle_get_*)
+ *    synchronise that stream before returning; dcg_matvec* do not.
+ *  - One operator belongs to one stream.  Calls on different operators and
+ *    streams may run concurrently; calls on one operator (or one recycle
+ *    handle) must not overlap.
+ */
+#ifndef DCG_H
+#define DCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dcg_operator_s *dcg_op_t;      /* opaque */
+typedef struct dcg_recycle_s *dcg_recycle_t;  /* opaque */
+
+/* Covariance functions.  RBF is the kernel of the paper's experiments
+ * (section 3): s2 exp(-r^2 / (2 ell^2)).  The Matern kernels are the
+ * textbook forms s2 (1 + t) e^-t, t = sqrt3 r/ell, and
+ * s2 (1 + t + t^2/3) e^-t, t = sqrt5 r/ell. */
+enum dcg_kernel { DCG_RBF = 0, DCG_MATERN32 = 1, DCG_MATERN52 = 2 };
+
+/* Compute precision of the distance GEMM (points are rounded to it once, at
+ * operator creation; the operator is the exact kernel matrix of the rounded
+ * points evaluated with FP32 accumulation).  FP64 is the exact operator. */
+enum dcg_prec { DCG_PREC_FP32 = 0, DCG_PREC_BF16 = 1, DCG_PREC_FP64 = 3 };
+
+enum dcg_status {
+  DCG_OK = 0,
+  DCG_NOT_CONVERGED = 1,   /* max_iter reached; x and stats are valid      */
+  DCG_E_ARG = -1,          /* invalid argument (size, pointer, enum value)  */
+  DCG_E_NOT_SPD = -2,      /* p^T A p <= 0 or W^T A W not positive definite */
+  DCG_E_NONFINITE = -3,    /* NaN/Inf met in the iteration                  */
+  DCG_E_W_RANK = -4,       /* recycled basis numerically rank deficient     */
+  DCG_E_HIP = -5,          /* a HIP runtime call failed                     */
+  DCG_E_WORKSPACE = -6     /* workspace too small or misaligned             */
+};
+
+/* Solver parameters (host struct). */
+typedef struct {
+  double tol;          /* stop when |r_j|_2 / |b|_2 <= tol (recursive residual,
+                          the relative error of section 3)                   */
+  int max_iter;        /* CG steps per solve (<= 0: 10 n)                   */
+  int L;               /* leading iterations stored for the extraction; the
+                          "l" of def-CG(k, l) (section 2.2); <= rc's L       */
+  int select_largest;  /* 1: keep the largest harmonic Ritz values (the
+                          paper's experiments), 0: the smallest              */
+  int check_every;     /* iterations between host convergence checks (>= 1) */
+  int refine;          /* 1: iterative refinement against the FP64 operator */
+  double inner_tol;    /* relative tolerance of each inner solve (refine)   */
+  int refine_max;      /* maximum outer refinement steps                    */
+  int use_graph;       /* 1: capture each chunk of iterations in a hipGraph */
+  int true_residual;   /* 1: also compute |b - A x| / |b| at exit (one more
+                          product; always done when refine = 1)              */
+  int profile;         /* 1: time every matvec sweep with HIP events on the
+                          operator's stream (iterations run without graphs) */
+} dcg_params;
+
+/* Per-solve statistics (host struct, filled by dcg_solve). */
+typedef struct {
+  int iters;                 /* CG steps (sum over inner solves if refine)   */
+  int matvecs;               /* products with the low-precision operator     */
+  int matvecs_exact;         /* products with the FP64 operator (refine)     */
+  int k_used;                /* columns of W used in this solve              */
+  int k_next;                /* columns of W' extracted for the next solve   */
+  int outer_steps;           /* refinement steps                             */
+  int status;                /* dcg_status of the solve                      */
+  double rel_res_recursive;  /* final |r_j| / |b|, recursive residual        */
+  double rel_res_true;       /* |b - A x| / |b| with the FP64 operator if
+                                refine, else with the solve's operator       */
+  double t_init_ms, t_loop_ms, t_refresh_ms, t_total_ms;
+  int sweeps_timed;          /* profile = 1: matvec sweeps timed             */
+  double t_sweeps_ms;        /* profile = 1: their summed device time        */
+} dcg_stats;
+
+/* ---------------------------------------------------------------- operator
+ * The matrix A = K_theta(X, X) + sigma2 I of the paper's sequence (Eq. 1,
+ * Gram matrix over X of section 1), applied matrix-free. */
+
+/* Bytes of workspace the operator needs (256-byte aligned base required). */
+size_t dcg_operator_workspace_bytes(int64_t n, int64_t d, int prec);
+
+/* Round X to prec, store it with its squared norms in the workspace, and
+ * keep (kernel, ell, s2, sigma2).  X: device FP64 row-major n x d, read
+ * only here (a copy is kept).  stream: a hipStream_t (NULL = default).
+ * Requires n >= 1, 1 <= d <= 64, ell > 0, s2 > 0, sigma2 >= 0.
+ * Returns DCG_E_NONFINITE if X holds NaN/Inf. */
+int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel,
+                        double ell, double s2, double sigma2, int prec,
+                        void *workspace, size_t ws_bytes, void *stream,
+                        dcg_op_t *out);
+
+/* Change the hyperparameters (the next system of a sequence). */
+int dcg_set_hyper(dcg_op_t op, double ell, double s2, double sigma2);
+
+/* Y = A V with the operator's compute precision; V, Y device FP64
+ * column-major n x m, m >= 1, V and Y must not overlap (Algorithm 1's
+ * products A p_j; m > 1 is the block product used for AW). */
+int dcg_matvec(dcg_op_t op, const double *V, double *Y, int64_t m);
+
+/* Y = A V with the FP64 operator on the unrounded points (residuals of the
+ * iterative refinement).  Same layout rules as dcg_matvec. */
+int dcg_matvec_exact(dcg_op_t op, const double *V, double *Y, int64_t m);
+
+void dcg_destroy_operator(dcg_op_t op);
+
+/* ---------------------------------------------------------- recycle handle
+ * Holds the recycled basis W (n x k) of section 2.1, its product AW with the
+ * operator it was last used with, and the storage for the first L search
+ * directions P_L and A P_L of a solve (section 2.3, Z = [W, P_L]).  A new
+ * handle has no W, so the first solve is plain CG (Fig. 1). */
+
+size_t dcg_recycle_workspace_bytes(int64_t n, int k, int L);
+
+/* k >= 1, L >= k (the first extraction draws k vectors from P_L alone). */
+int dcg_recycle_create(int64_t n, int k, int L, void *workspace,
+                       size_t ws_bytes, dcg_recycle_t *out);
+
+/* Set W from a device FP64 n x kw block (kw <= k, kw = 0 clears it); AW is
+ * recomputed for the operator of the next solve. */
+int dcg_recycle_set_W(dcg_recycle_t rc, const double *W, int kw);
+
+/* Copy the current W (n x k_used) to the device array W_out (may be NULL)
+ * and write k_used to *k_used (host). */
+int dcg_recycle_get_W(dcg_recycle_t rc, double *W_out, int *k_used);
+
+/* Copy AW (n x k_used), the product of W with the operator of the last
+ * solve, to the device array AW_out.  Returns DCG_E_ARG if no AW is held
+ * (no solve since the last dcg_recycle_set_W). */
+int dcg_recycle_get_AW(dcg_recycle_t rc, double *AW_out);
+
+/* Host copy of the harmonic Ritz values selected at the last extraction
+ * (theta_out holds at least k doubles; *count receives how many). */
+int dcg_recycle_get_theta(dcg_recycle_t rc, double *theta_out, int *count);
+
+void dcg_recycle_destroy(dcg_recycle_t rc);
+
+/* ------------------------------------------------------------------- solve */
+
+size_t dcg_solve_workspace_bytes(int64_t n, int k, int L);
+
+/* Solve A x = b by deflated CG (Algorithm 1).
+ *  b   device FP64 n-vector.
+ *  x   device FP64 n-vector: on entry x_{-1} if x_given, else ignored
+ *      (x_{-1} = 0); on exit the solution (also on DCG_NOT_CONVERGED).
+ *  rc  recycle handle, or NULL for plain CG without extraction.  With a
+ *      handle the solve starts from its W (if any) and ends by extracting
+ *      the next W' = Z U from the harmonic Ritz problem G u = theta F u
+ *      (Eq. 7), keeping the k largest (or smallest) theta.
+ *  p   host parameters; st host statistics (may be NULL).
+ *  ws  solve workspace of dcg_solve_workspace_bytes(n, k, L) bytes, where
+ *      k and L are those of rc (0, 0 for rc = NULL).
+ * With p->refine = 1 the solve runs iterative refinement: residuals with the
+ * FP64 operator, inner deflated solves to p->inner_tol with the operator's
+ * precision, until |b - A x| / |b| <= p->tol (the recycled W carries over
+ * between the inner solves). */
+int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given,
+              dcg_recycle_t rc, const dcg_params *p, dcg_stats *st, void *ws,
+              size_t ws_bytes);
+
+/* Human-readable name of a status code (static string). */
+const char *dcg_status_string(int status);
+
+/* Library version string. */
+const char *dcg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DCG_H */

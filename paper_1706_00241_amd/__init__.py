@@ -1,0 +1,331 @@
+"""Python binding of libdcg.so: deflated CG with Krylov subspace recycling on MI355X.
+
+Argument marshalling only.  Every step of the method (distance GEMM, kernel
+evaluation, CG recurrences, deflation projections, harmonic Ritz extraction,
+iterative refinement) runs in the library's HIP kernels; PyTorch provides the
+device memory and the stream.  The names follow the C ABI in include/dcg.h.
+
+There is no fallback: if the library is not built, or no GPU is present,
+every entry point raises.
+
+Typical use (a sequence of related systems, section 1 of de Roos & Hennig)::
+
+    op = Operator(X, kernel=RBF, ell=1.0, s2=1.0, sigma2=1e-2, prec=PREC_FP32)
+    rc = Recycle(n, k=32, L=48)
+    for ell in ells:
+        op.set_hyper(ell, 1.0, 1e-2)
+        x, st = solve(op, b, rc=rc, tol=1e-6)
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdcg.so")
+
+RBF, MATERN32, MATERN52 = 0, 1, 2
+PREC_FP32, PREC_BF16, PREC_FP64 = 0, 1, 3
+STATUS = {0: "ok", 1: "not converged", -1: "invalid argument", -2: "not SPD",
+          -3: "non-finite", -4: "W rank deficient", -5: "HIP error",
+          -6: "workspace"}
+
+
+class DcgError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__(f"{where}: {STATUS.get(status, status)} (status {status})")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("L", ctypes.c_int), ("select_largest", ctypes.c_int),
+                ("check_every", ctypes.c_int), ("refine", ctypes.c_int),
+                ("inner_tol", ctypes.c_double), ("refine_max", ctypes.c_int),
+                ("use_graph", ctypes.c_int), ("true_residual", ctypes.c_int),
+                ("profile", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("matvecs", ctypes.c_int),
+                ("matvecs_exact", ctypes.c_int), ("k_used", ctypes.c_int),
+                ("k_next", ctypes.c_int), ("outer_steps", ctypes.c_int),
+                ("status", ctypes.c_int), ("rel_res_recursive", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double), ("t_init_ms", ctypes.c_double),
+                ("t_loop_ms", ctypes.c_double), ("t_refresh_ms", ctypes.c_double),
+                ("t_total_ms", ctypes.c_double), ("sweeps_timed", ctypes.c_int),
+                ("t_sweeps_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+_SIGS = {
+    "dcg_operator_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int]),
+    "dcg_create_operator": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_int, ctypes.c_void_p,
+                                           ctypes.c_size_t, ctypes.c_void_p,
+                                           ctypes.POINTER(ctypes.c_void_p)]),
+    "dcg_set_hyper": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double]),
+    "dcg_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "dcg_matvec_exact": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_int64]),
+    "dcg_destroy_operator": (None, [ctypes.c_void_p]),
+    "dcg_recycle_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int, ctypes.c_int]),
+    "dcg_recycle_create": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_size_t,
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "dcg_recycle_set_W": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "dcg_recycle_get_W": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_int)]),
+    "dcg_recycle_get_AW": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "dcg_recycle_get_theta": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_int)]),
+    "dcg_recycle_destroy": (None, [ctypes.c_void_p]),
+    "dcg_solve_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int, ctypes.c_int]),
+    "dcg_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                 ctypes.c_void_p, ctypes.POINTER(Params), ctypes.POINTER(Stats),
+                                 ctypes.c_void_p, ctypes.c_size_t]),
+    "dcg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "dcg_version": (ctypes.c_char_p, []),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def load(path=LIB_PATH):
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python -m paper_1706_00241_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status, where):
+    if status < 0:
+        raise DcgError(status, where)
+    return status
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU: the deflated-CG library runs on an MI355X only")
+    return torch
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    t = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-t.data_ptr()) % 256
+    return t, t.data_ptr() + off, int(nbytes)
+
+
+class _ordered:
+    """Order the library's stream after the caller's current stream on entry
+    and the caller's stream after the library's on exit."""
+
+    def __init__(self, stream):
+        self.stream = stream
+
+    def __enter__(self):
+        torch = _torch()
+        self.cur = torch.cuda.current_stream(self.stream.device)
+        self.stream.wait_stream(self.cur)
+        return self
+
+    def __exit__(self, *exc):
+        self.cur.wait_stream(self.stream)
+        return False
+
+
+def _colmajor(V):
+    """(n,) or (n, m) tensor -> contiguous (m, n) FP64 buffer = n x m column-major."""
+    torch = _torch()
+    if V.dim() == 1:
+        return V.to(torch.float64).contiguous().view(1, -1)
+    return V.to(torch.float64).t().contiguous()
+
+
+class Operator:
+    """A = K_theta(X, X) + sigma2 I applied matrix-free on the GPU."""
+
+    def __init__(self, X, kernel, ell, s2, sigma2, prec=PREC_FP32, stream=None):
+        torch = _torch()
+        lib = load()
+        X = X.to(device="cuda", dtype=torch.float64).contiguous()
+        self.n, self.d = X.shape
+        self.device = X.device
+        self.kernel, self.prec = int(kernel), int(prec)
+        # a dedicated stream (default priority): the library captures its
+        # iteration chunks as hipGraphs, which the legacy default stream
+        # cannot do; every call orders it against the caller's stream.
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        nbytes = lib.dcg_operator_workspace_bytes(self.n, self.d, self.prec)
+        if nbytes == 0:
+            raise DcgError(-1, "dcg_operator_workspace_bytes")
+        self._ws, ptr, size = _workspace(nbytes, self.device)
+        h = ctypes.c_void_p()
+        with _ordered(self.stream):
+            _check(lib.dcg_create_operator(X.data_ptr(), self.n, self.d, self.kernel, float(ell),
+                                           float(s2), float(sigma2), self.prec, ptr, size,
+                                           self.stream.cuda_stream, ctypes.byref(h)),
+                   "dcg_create_operator")
+        self.handle = h
+        self.ell, self.s2, self.sigma2 = float(ell), float(s2), float(sigma2)
+
+    def set_hyper(self, ell, s2, sigma2):
+        _check(load().dcg_set_hyper(self.handle, float(ell), float(s2), float(sigma2)),
+               "dcg_set_hyper")
+        self.ell, self.s2, self.sigma2 = float(ell), float(s2), float(sigma2)
+
+    def _mv(self, fn, V):
+        torch = _torch()
+        Vc = _colmajor(V.to(self.device))
+        Y = torch.empty_like(Vc)
+        with _ordered(self.stream):
+            _check(fn(self.handle, Vc.data_ptr(), Y.data_ptr(), Vc.shape[0]), fn.__name__)
+        return Y.view(-1) if V.dim() == 1 else Y.t()
+
+    def matvec(self, V):
+        """A V with the operator's compute precision (V: (n,) or (n, m))."""
+        return self._mv(load().dcg_matvec, V)
+
+    def matvec_exact(self, V):
+        """A V with the FP64 operator on the unrounded points."""
+        return self._mv(load().dcg_matvec_exact, V)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            load().dcg_destroy_operator(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Recycle:
+    """Recycled basis W (n x k) and the storage of the first L directions."""
+
+    def __init__(self, n, k, L, device="cuda"):
+        lib = load()
+        _torch()
+        self.n, self.k, self.L = int(n), int(k), int(L)
+        nbytes = lib.dcg_recycle_workspace_bytes(self.n, self.k, self.L)
+        if nbytes == 0:
+            raise DcgError(-1, "dcg_recycle_workspace_bytes")
+        self._ws, ptr, size = _workspace(nbytes, device)
+        h = ctypes.c_void_p()
+        _check(lib.dcg_recycle_create(self.n, self.k, self.L, ptr, size, ctypes.byref(h)),
+               "dcg_recycle_create")
+        self.handle = h
+        self.device = device
+
+    def set_W(self, W):
+        torch = _torch()
+        if W is None or W.numel() == 0:
+            _check(load().dcg_recycle_set_W(self.handle, None, 0), "dcg_recycle_set_W")
+            return
+        Wc = _colmajor(W.to(self.device))
+        torch.cuda.synchronize()
+        _check(load().dcg_recycle_set_W(self.handle, Wc.data_ptr(), Wc.shape[0]),
+               "dcg_recycle_set_W")
+
+    def get_W(self):
+        torch = _torch()
+        k = ctypes.c_int()
+        _check(load().dcg_recycle_get_W(self.handle, None, ctypes.byref(k)), "dcg_recycle_get_W")
+        out = torch.empty((k.value, self.n), dtype=torch.float64, device=self.device)
+        torch.cuda.synchronize()
+        if k.value:
+            _check(load().dcg_recycle_get_W(self.handle, out.data_ptr(), ctypes.byref(k)),
+                   "dcg_recycle_get_W")
+        return out.t()
+
+    def get_AW(self):
+        """AW for the operator of the last solve (n x k_used)."""
+        torch = _torch()
+        k = ctypes.c_int()
+        _check(load().dcg_recycle_get_W(self.handle, None, ctypes.byref(k)), "dcg_recycle_get_W")
+        out = torch.empty((k.value, self.n), dtype=torch.float64, device=self.device)
+        torch.cuda.synchronize()
+        if k.value:
+            _check(load().dcg_recycle_get_AW(self.handle, out.data_ptr()), "dcg_recycle_get_AW")
+        return out.t()
+
+    def theta(self):
+        buf = (ctypes.c_double * max(1, self.k))()
+        cnt = ctypes.c_int()
+        _check(load().dcg_recycle_get_theta(self.handle, buf, ctypes.byref(cnt)),
+               "dcg_recycle_get_theta")
+        return [buf[i] for i in range(cnt.value)]
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            load().dcg_recycle_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SolveWorkspace:
+    def __init__(self, n, device="cuda"):
+        nbytes = load().dcg_solve_workspace_bytes(int(n), 0, 0)
+        self._ws, self.ptr, self.size = _workspace(nbytes, device)
+
+
+def solve(op, b, x0=None, rc=None, tol=1e-6, max_iter=0, L=0, select_largest=True,
+          check_every=8, refine=False, inner_tol=1e-4, refine_max=20, use_graph=True,
+          true_residual=False, profile=False, ws=None, out=None):
+    """Deflated CG (Algorithm 1) for A x = b; returns (x, stats dict).
+
+    rc=None runs plain CG; with a Recycle the solve uses its W and leaves the
+    next W' (harmonic Ritz vectors, Eq. 7) in it.  refine=True runs iterative
+    refinement to ``tol`` against the FP64 operator.
+    """
+    torch = _torch()
+    lib = load()
+    b = b.to(device=op.device, dtype=torch.float64).contiguous()
+    if out is None:
+        out = torch.empty_like(b)
+    x_given = 0
+    if x0 is not None:
+        out.copy_(x0)
+        x_given = 1
+    if ws is None:
+        ws = SolveWorkspace(op.n, op.device)
+    p = Params(tol=float(tol), max_iter=int(max_iter), L=int(L),
+               select_largest=1 if select_largest else 0, check_every=int(check_every),
+               refine=1 if refine else 0, inner_tol=float(inner_tol), refine_max=int(refine_max),
+               use_graph=1 if use_graph else 0, true_residual=1 if true_residual else 0,
+               profile=1 if profile else 0)
+    st = Stats()
+    with _ordered(op.stream):
+        status = lib.dcg_solve(op.handle, b.data_ptr(), out.data_ptr(), x_given,
+                               rc.handle if rc is not None else None, ctypes.byref(p),
+                               ctypes.byref(st), ws.ptr, ws.size)
+    _check(status, "dcg_solve")
+    return out, st.as_dict()
+
+
+def version():
+    return load().dcg_version().decode()

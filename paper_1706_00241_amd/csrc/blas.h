@@ -1,0 +1,104 @@
+// Device-side state and kernel entry points shared by the HIP sources.
+#pragma once
+
+#include "common.h"
+
+namespace dcg {
+
+// Partial sums of the symmetric matvec and how to finish a product.
+struct ReduceArgs {
+  const double *prow;
+  const float *pcol;
+  int64_t n, n_pad;
+  int nchunk, dmax, blk, nb, mv;
+  double s2, sigma2;
+  const double *V;   // n x mv (ld n)
+  double *Y;         // n x mv (ld n)
+};
+
+// Row i of vector m: the row partials of every chunk, then the column
+// partials of every block offset that owns a pair with row block i/blk (for
+// even nb the offset nb/2 belongs to row blocks >= nb/2 only), in a fixed
+// order.
+__device__ __forceinline__ double sum_partials(const ReduceArgs &A, int m, int64_t i) {
+  double s = 0.0;
+  for (int c = 0; c < A.nchunk; ++c) s += A.prow[(int64_t(c) * A.mv + m) * A.n_pad + i];
+  const int J = static_cast<int>(i / A.blk);
+  const bool skip_last = (A.nb % 2 == 0) && (J < A.nb / 2);
+  const int dlim = skip_last ? A.dmax - 1 : A.dmax;
+  for (int dl = 1; dl <= dlim; ++dl) s += A.pcol[(int64_t(dl - 1) * A.mv + m) * A.n_pad + i];
+  return s;
+}
+
+// Scalars of one deflated-CG solve, resident on the device.
+struct SolveState {
+  double rho;       // r_j^T r_j
+  double alpha, beta, d;
+  double bnorm;     // |b|_2
+  double relres;    // |r_j| / |b|
+  int iter;         // CG steps done
+  int done;         // 1 once converged, failed or out of iterations
+  int status;       // 0 or a negative dcg_status
+  int pad;
+  double mu[kMaxK]; // mu_j of Algorithm 1
+  double cvec[kMaxK];
+};
+
+struct CgArgs {
+  SolveState *S;
+  ReduceArgs red;
+  const double *qdirect;  // FP64 operator: the finished product (else null)
+  int64_t n;
+  double *x, *r, *p, *q;
+  float *p32;
+  const double *W, *AW, *Minv;
+  const double *N;  // (AW)^T AW, k x k
+  int k;
+  double *Z, *AZ;   // storage of p_j / A p_j for j < L at column koff + j
+  int koff, L;
+  double *part, *part_h;
+  unsigned *counter;
+  double *hist_d, *hist_alpha, *hist_beta, *hist_res;
+  int hist_cap;
+  double tol;
+  int max_iter;
+};
+
+__global__ void cg_matvec_finish(CgArgs a);
+__global__ void cg_update_xr(CgArgs a);
+__global__ void cg_update_p(CgArgs a);
+__global__ void init_residual(const double *b, const double *Ax, double *x, double *r, int64_t n,
+                              int x_given, double *part, unsigned *counter, SolveState *S);
+__global__ void defl_start(double *x, double *t, const double *W, const double *cvec, int64_t n,
+                           int k);
+__global__ void init_direction(const double *r, const double *W, const double *mu, int64_t n,
+                               int64_t n_pad, int k, double *p, float *p32, double *part,
+                               unsigned *counter, SolveState *S, double tol, double *hist_res);
+
+__global__ void residual_norms(const double *b, const double *Ax, int64_t n, double *out,
+                               double *part, unsigned *counter, double *sums);
+void enqueue_ts_dot(hipStream_t s, const double *Y, int64_t n, int m, const double *v,
+                    double *part, unsigned *counter, const double *Minv, double *out);
+void enqueue_tsgemm_tn(hipStream_t s, const double *A, const double *B, int64_t n, int ma, int mb,
+                       double *part, size_t part_cap, double *C, int ldc, int symmetrise);
+void enqueue_ts_times_small(hipStream_t s, const double *X, int64_t n, int m, const double *U,
+                            int ldu, int kout, double *Y);
+void enqueue_block_axpy(hipStream_t s, double *Y, const double *X, double alpha, int64_t count);
+void enqueue_small_spd_inverse(hipStream_t s, const double *M, int k, double *Minv, double *work,
+                               int *info);
+void enqueue_harmonic_ritz(hipStream_t s, const double *F, const double *G, int m, int k,
+                           int largest, double tau, double *work, double *U, double *theta,
+                           int *info);
+size_t harmonic_ritz_work_doubles();
+
+// matvec.hip
+void kernel_constants(int kernel, double ell, float *c0, float *c1, float *c2);
+int launch_symv_sweep(const dcg_operator_s *op, int mv, const int *done);
+ReduceArgs reduce_args(const dcg_operator_s *op, int mv, const double *V, double *Y);
+int matvec_lowprec(const dcg_operator_s *op, const double *V, double *Y, int64_t m);
+int matvec_exact(const dcg_operator_s *op, const double *V, double *Y, int64_t m);
+int matvec_exact_done(const dcg_operator_s *op, const double *V, double *Y, int64_t m,
+                      const int *done);
+int prepare_operator(dcg_operator_s *op, const double *X);
+
+}  // namespace dcg

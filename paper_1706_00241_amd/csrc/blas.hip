@@ -1,0 +1,563 @@
+// FP64 vector kernels of the deflated CG iteration (Algorithm 1), the
+// deflation projections W (W^T A W)^{-1} W^T r, and the tall-skinny products
+// of the harmonic Ritz extraction (F = (AZ)^T Z, G = (AZ)^T AZ, W' = Z U).
+//
+// Scalars of the iteration live on the device (SolveState); reductions are
+// done in a fixed order by the last block to finish (a per-kernel counter),
+// so results are bitwise reproducible and no host round trip is needed.
+#include <algorithm>
+#include <cmath>
+
+#include "blas.h"
+
+namespace dcg {
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------- reductions
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) lds[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < NT / 64; ++i) s += lds[i];
+  }
+  return s;  // valid in thread 0
+}
+
+// Returns true in every thread of the block that finished last.  The block's
+// partial results must have been written before the call.
+__device__ __forceinline__ bool last_block(unsigned *counter) {
+  __shared__ bool is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(counter, 1u);
+    is_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (is_last) __threadfence();
+  return is_last;
+}
+
+// mu = Minv h (k x k dense, row-major), by the first k threads.
+__device__ __forceinline__ void small_gemv(const double *Minv, const double *h, double *mu, int k) {
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s += Minv[c * k + j] * h[j];
+    mu[c] = s;
+  }
+}
+
+// ------------------------------------------------------ CG iteration kernels
+
+// q = s2 * sum(partials) + sigma2 p; d = p^T q; alpha = rho / d.
+// Also stores p_{j-1} and q = A p_{j-1} into Z / AZ while j-1 < L.
+__global__ __launch_bounds__(256) void cg_matvec_finish(CgArgs a) {
+  SolveState *S = a.S;
+  if (S->done) return;
+  __shared__ double lds[8];
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  double pq = 0.0;
+  if (i < a.n) {
+    const double pi = a.p[i];
+    const double qi = (a.qdirect != nullptr)
+                          ? a.qdirect[i]
+                          : a.red.s2 * sum_partials(a.red, 0, i) + a.red.sigma2 * pi;
+    a.q[i] = qi;
+    pq = pi * qi;
+    const int j = S->iter;  // index of p being multiplied (p_j)
+    if (a.Z != nullptr && j < a.L) {
+      a.Z[int64_t(a.koff + j) * a.n + i] = pi;
+      a.AZ[int64_t(a.koff + j) * a.n + i] = qi;
+    }
+  }
+  const double bs = block_sum<256>(pq, lds);
+  if (threadIdx.x == 0) a.part[blockIdx.x] = bs;
+  if (last_block(a.counter)) {
+    if (threadIdx.x == 0) {
+      double d = 0.0;
+      for (unsigned b = 0; b < gridDim.x; ++b) d += a.part[b];
+      S->d = d;
+      if (!(d > 0.0) || !isfinite(d)) {
+        S->status = isfinite(d) ? DCG_E_NOT_SPD : DCG_E_NONFINITE;
+        S->done = 1;
+        S->alpha = 0.0;
+      } else {
+        S->alpha = S->rho / d;
+      }
+      const int j = S->iter;
+      if (j < a.L) {
+        a.hist_d[j] = d;
+        a.hist_alpha[j] = S->alpha;
+      }
+      *a.counter = 0;
+    }
+  }
+}
+
+// x += alpha p; r -= alpha q; partial sums of rho' = r^T r, h = (AW)^T r and
+// g = W^T r.  Last block: the re-projection c = (W^T A W)^{-1} g of the
+// residual (zero in exact arithmetic, where W^T r_j = 0), and with
+// r' = r - AW c: mu = (W^T A W)^{-1} (AW)^T r', beta = |r'|^2 / |r|^2 and the
+// convergence test on |r'| / |b|.
+__global__ __launch_bounds__(256) void cg_update_xr(CgArgs a) {
+  SolveState *S = a.S;
+  if (S->done) return;
+  __shared__ double lds[8];
+  __shared__ double rl[256];
+  const int64_t i0 = int64_t(blockIdx.x) * 256;
+  const int64_t i = i0 + threadIdx.x;
+  const double alpha = S->alpha;
+  double rr = 0.0;
+  double ri = 0.0;
+  if (i < a.n) {
+    a.x[i] += alpha * a.p[i];
+    ri = a.r[i] - alpha * a.q[i];
+    a.r[i] = ri;
+    rr = ri * ri;
+  }
+  rl[threadIdx.x] = ri;
+  const double bs = block_sum<256>(rr, lds);
+  if (threadIdx.x == 0) a.part[blockIdx.x] = bs;
+  // partial dots: wave w takes columns w, w+4, ... of [AW | W]; lanes cover
+  // the block's 4 x 64 rows.
+  const int k = a.k;
+  if (k > 0) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    for (int c = w; c < 2 * k; c += 4) {
+      const double *Y = (c < k) ? a.AW + int64_t(c) * a.n : a.W + int64_t(c - k) * a.n;
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t ii = i0 + 64 * t + l;
+        if (ii < a.n) s += Y[ii] * rl[64 * t + l];
+      }
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+      if (l == 0) a.part_h[int64_t(blockIdx.x) * 2 * k + c] = s;
+    }
+  }
+  if (last_block(a.counter)) {
+    __shared__ double hg[2 * kMaxK];   // h = (AW)^T r, then g = W^T r
+    __shared__ double cv[kMaxK];       // c = M^-1 g
+    __shared__ double nc[kMaxK];       // N c
+    __shared__ double hn[kMaxK];       // h - N c
+    for (int c = threadIdx.x; c < 2 * k; c += 256) {
+      double s = 0.0;
+      for (unsigned b = 0; b < gridDim.x; ++b) s += a.part_h[int64_t(b) * 2 * k + c];
+      hg[c] = s;
+    }
+    __syncthreads();
+    small_gemv(a.Minv, hg + k, cv, k);
+    __syncthreads();
+    small_gemv(a.N, cv, nc, k);
+    __syncthreads();
+    for (int c = threadIdx.x; c < k; c += 256) {
+      hn[c] = hg[c] - nc[c];
+      S->cvec[c] = cv[c];
+    }
+    __syncthreads();
+    small_gemv(a.Minv, hn, S->mu, k);
+    if (threadIdx.x == 0) {
+      double rho_new = 0.0;
+      for (unsigned b = 0; b < gridDim.x; ++b) rho_new += a.part[b];
+      // |r - AW c|^2 = |r|^2 - 2 c^T h + c^T N c
+      double corr = 0.0;
+      for (int c = 0; c < k; ++c) corr += cv[c] * (nc[c] - 2.0 * hg[c]);
+      rho_new = fmax(rho_new + corr, 0.0);
+      const double beta = rho_new / S->rho;
+      S->beta = beta;
+      S->rho = rho_new;
+      const int j = S->iter;
+      if (j < a.L) a.hist_beta[j] = beta;
+      S->iter = j + 1;
+      const double rel = std::sqrt(rho_new) / S->bnorm;
+      S->relres = rel;
+      if (j + 1 < a.hist_cap) a.hist_res[j + 1] = rel;
+      if (!isfinite(rho_new)) {
+        S->status = DCG_E_NONFINITE;
+        S->done = 1;
+      } else if (rel <= a.tol || j + 1 >= a.max_iter) {
+        S->done = 1;
+      }
+      *a.counter = 0;
+    }
+  }
+}
+
+// Apply the re-projection (x += W c, r -= AW c) and the direction update
+// p = beta p + r - W mu; the FP32 copy of p feeds the next matvec.
+__global__ __launch_bounds__(256) void cg_update_p(CgArgs a) {
+  SolveState *S = a.S;
+  if (S->done) return;
+  __shared__ double mu[kMaxK];
+  __shared__ double cv[kMaxK];
+  for (int c = threadIdx.x; c < a.k; c += 256) {
+    mu[c] = S->mu[c];
+    cv[c] = S->cvec[c];
+  }
+  __syncthreads();
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= a.n) return;
+  double ri = a.r[i];
+  double xi = 0.0;
+  double wmu = 0.0;
+  for (int c = 0; c < a.k; ++c) {
+    const double wv = a.W[int64_t(c) * a.n + i];
+    ri -= a.AW[int64_t(c) * a.n + i] * cv[c];
+    xi += wv * cv[c];
+    wmu += wv * mu[c];
+  }
+  if (a.k > 0) {
+    a.r[i] = ri;
+    a.x[i] += xi;
+  }
+  const double s = ri + S->beta * a.p[i] - wmu;
+  a.p[i] = s;
+  a.p32[i] = static_cast<float>(s);
+}
+
+// -------------------------------------------------- initialisation kernels
+
+// out[c] = sum_i Y[i, c] v[i] for c < m; with Minv != null, out = Minv * out.
+// Grid-stride over rows; last block sums the partials in block order.
+__global__ __launch_bounds__(256) void ts_dot(const double *Y, int64_t n, int m, const double *v,
+                                              double *part, unsigned *counter, const double *Minv,
+                                              double *out) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int c = w; c < m; c += 4) {
+    double s = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 64 + l; i < n; i += int64_t(gridDim.x) * 64)
+      s += Y[int64_t(c) * n + i] * v[i];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    if (l == 0) part[int64_t(blockIdx.x) * m + c] = s;
+  }
+  if (last_block(counter)) {
+    __shared__ double h[kMaxZ];
+    for (int c = threadIdx.x; c < m; c += 256) {
+      double s = 0.0;
+      for (unsigned b = 0; b < gridDim.x; ++b) s += part[int64_t(b) * m + c];
+      h[c] = s;
+    }
+    __syncthreads();
+    if (Minv != nullptr) small_gemv(Minv, h, out, m);
+    else
+      for (int c = threadIdx.x; c < m; c += 256) out[c] = h[c];
+    if (threadIdx.x == 0) *counter = 0;
+  }
+}
+
+// x += W c and t = W c (deflated start, Algorithm 1 initialisation; the
+// residual is then formed with the product A t).
+__global__ __launch_bounds__(256) void defl_start(double *x, double *t, const double *W,
+                                                  const double *cvec, int64_t n, int k) {
+  __shared__ double cc[kMaxK];
+  for (int c = threadIdx.x; c < k; c += 256) cc[c] = cvec[c];
+  __syncthreads();
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  double ts = 0.0;
+  for (int c = 0; c < k; ++c) ts += W[int64_t(c) * n + i] * cc[c];
+  x[i] += ts;
+  t[i] = ts;
+}
+
+// r = b - Ax (or b when Ax is null), x = 0 unless given; partial |b|^2.
+__global__ __launch_bounds__(256) void init_residual(const double *b, const double *Ax, double *x,
+                                                     double *r, int64_t n, int x_given,
+                                                     double *part, unsigned *counter,
+                                                     SolveState *S) {
+  __shared__ double lds[8];
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  double bb = 0.0;
+  if (i < n) {
+    const double bi = b[i];
+    if (!x_given) x[i] = 0.0;
+    r[i] = (Ax != nullptr) ? bi - Ax[i] : bi;
+    bb = bi * bi;
+  }
+  const double bs = block_sum<256>(bb, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = bs;
+  if (last_block(counter)) {
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (unsigned k = 0; k < gridDim.x; ++k) s += part[k];
+      S->bnorm = std::sqrt(s);
+      *counter = 0;
+    }
+  }
+}
+
+// p_0 = r_0 - W mu_0, rho = r_0^T r_0, FP32 copy of p (padded with zeros).
+__global__ __launch_bounds__(256) void init_direction(const double *r, const double *W,
+                                                      const double *mu, int64_t n, int64_t n_pad,
+                                                      int k, double *p, float *p32, double *part,
+                                                      unsigned *counter, SolveState *S,
+                                                      double tol, double *hist_res) {
+  __shared__ double lds[8];
+  __shared__ double mm[kMaxK];
+  for (int c = threadIdx.x; c < k; c += 256) mm[c] = mu[c];
+  __syncthreads();
+  double rr = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n_pad;
+       i += int64_t(gridDim.x) * 256) {
+    if (i < n) {
+      const double ri = r[i];
+      double s = ri;
+      for (int c = 0; c < k; ++c) s -= W[int64_t(c) * n + i] * mm[c];
+      p[i] = s;
+      p32[i] = static_cast<float>(s);
+      rr += ri * ri;
+    } else {
+      p32[i] = 0.0f;
+    }
+  }
+  const double bs = block_sum<256>(rr, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = bs;
+  if (last_block(counter)) {
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (unsigned b = 0; b < gridDim.x; ++b) s += part[b];
+      S->rho = s;
+      S->iter = 0;
+      S->status = 0;
+      const double rel = (S->bnorm > 0.0) ? std::sqrt(s) / S->bnorm : 0.0;
+      S->relres = rel;
+      hist_res[0] = rel;
+      S->done = (rel <= tol || !isfinite(s)) ? 1 : 0;
+      if (!isfinite(s)) S->status = DCG_E_NONFINITE;
+      *counter = 0;
+    }
+  }
+}
+
+// --------------------------------------------------- tall-skinny products
+
+// part[chunk] = A[rows of chunk]^T B[rows of chunk] (ma x mb, row-major).
+// Block: a 32x32 output tile over a 1024-row chunk, 64-row LDS sub-chunks.
+__global__ __launch_bounds__(256) void tsgemm_tn(const double *A, const double *B, int64_t n,
+                                                 int ma, int mb, double *part, int64_t chunk_rows) {
+  __shared__ double As[64][33];
+  __shared__ double Bs[64][33];
+  const int tiles_b = (mb + 31) / 32;
+  const int ta = blockIdx.x / tiles_b, tb = blockIdx.x % tiles_b;
+  const int chunk = blockIdx.y;
+  const int64_t r0 = int64_t(chunk) * chunk_rows;
+  const int64_t r1 = std::min<int64_t>(n, r0 + chunk_rows);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;  // 16 x 16 threads, 2x2 outputs each
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  for (int64_t s = r0; s < r1; s += 64) {
+    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+      const int rr = e % 64, cc = e / 64;
+      const int64_t row = s + rr;
+      const int ca = ta * 32 + cc, cb = tb * 32 + cc;
+      As[rr][cc] = (row < r1 && ca < ma) ? A[int64_t(ca) * n + row] : 0.0;
+      Bs[rr][cc] = (row < r1 && cb < mb) ? B[int64_t(cb) * n + row] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int rr = 0; rr < 64; ++rr) {
+      const double a0 = As[rr][ty], a1 = As[rr][ty + 16];
+      const double b0 = Bs[rr][tx], b1 = Bs[rr][tx + 16];
+      acc[0][0] += a0 * b0;
+      acc[0][1] += a0 * b1;
+      acc[1][0] += a1 * b0;
+      acc[1][1] += a1 * b1;
+    }
+    __syncthreads();
+  }
+  double *out = part + int64_t(chunk) * ma * mb;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int ia = ta * 32 + ty + 16 * u, ib = tb * 32 + tx + 16 * v;
+      if (ia < ma && ib < mb) out[int64_t(ia) * mb + ib] = acc[u][v];
+    }
+}
+
+// C = sum over chunks of the partials (fixed order), optionally symmetrised.
+__global__ __launch_bounds__(256) void tsgemm_sum(const double *part, int nchunk, int ma, int mb,
+                                                  double *C, int ldc, int symmetrise) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= ma * mb) return;
+  const int i = e / mb, j = e % mb;
+  double s = 0.0, t = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[int64_t(c) * ma * mb + e];
+  if (symmetrise) {
+    for (int c = 0; c < nchunk; ++c) t += part[int64_t(c) * ma * mb + j * mb + i];
+    s = 0.5 * (s + t);
+  }
+  C[i * ldc + j] = s;
+}
+
+// Y[:, j] = X[:, 0:m] U[:, j] for j < kout (U row-major m x ldu), 32 columns
+// per pass with U staged in LDS.
+__global__ __launch_bounds__(256) void ts_times_small(const double *X, int64_t n, int m,
+                                                      const double *U, int ldu, int kout,
+                                                      double *Y) {
+  __shared__ double Us[kMaxZ][32];
+  const int j0 = blockIdx.y * 32;
+  const int jn = std::min(32, kout - j0);
+  for (int e = threadIdx.x; e < m * 32; e += 256) {
+    const int c = e / 32, j = e % 32;
+    Us[c][j] = (j < jn) ? U[c * ldu + j0 + j] : 0.0;
+  }
+  __syncthreads();
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  double acc[32];
+#pragma unroll
+  for (int j = 0; j < 32; ++j) acc[j] = 0.0;
+  for (int c = 0; c < m; ++c) {
+    const double xv = X[int64_t(c) * n + i];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) acc[j] += xv * Us[c][j];
+  }
+#pragma unroll
+  for (int j = 0; j < 32; ++j)
+    if (j < jn) Y[int64_t(j0 + j) * n + i] = acc[j];
+}
+
+// Y += alpha X (n x m blocks, same layout).
+__global__ __launch_bounds__(256) void block_axpy(double *Y, const double *X, double alpha,
+                                                  int64_t count) {
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e < count) Y[e] += alpha * X[e];
+}
+
+// Symmetrise M (k x k, row-major), Cholesky M = R R^T, Minv = M^{-1}.
+// One block; info = 0 on success, 1 if a pivot is not positive.
+__global__ __launch_bounds__(256) void small_spd_inverse(const double *Min, int k, double *Minv,
+                                                         double *work, int *info) {
+  __shared__ double Ls[kMaxK][kMaxK + 1];
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  for (int e = threadIdx.x; e < k * k; e += 256) {
+    const int i = e / k, j = e % k;
+    Ls[i][j] = 0.5 * (Min[i * k + j] + Min[j * k + i]);
+  }
+  __syncthreads();
+  // right-looking Cholesky, lower triangle
+  for (int j = 0; j < k; ++j) {
+    if (threadIdx.x == 0) {
+      const double piv = Ls[j][j];
+      if (!(piv > 0.0)) bad = 1;
+      Ls[j][j] = (piv > 0.0) ? std::sqrt(piv) : 1.0;
+    }
+    __syncthreads();
+    const double djj = Ls[j][j];
+    for (int i = j + 1 + threadIdx.x; i < k; i += 256) Ls[i][j] /= djj;
+    __syncthreads();
+    for (int e = threadIdx.x; e < (k - j - 1) * (k - j - 1); e += 256) {
+      const int i = j + 1 + e / (k - j - 1), c = j + 1 + e % (k - j - 1);
+      if (c <= i) Ls[i][c] -= Ls[i][j] * Ls[c][j];
+    }
+    __syncthreads();
+  }
+  // inverse of L by columns (thread c solves L y = e_c), then Minv = L^-T L^-1
+  for (int c = threadIdx.x; c < k; c += 256) {
+    for (int i = 0; i < k; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int t = c; t < i; ++t) s -= Ls[i][t] * work[t * kMaxK + c];
+      work[i * kMaxK + c] = (i < c) ? 0.0 : s / Ls[i][i];
+    }
+  }
+  __syncthreads();
+  __threadfence_block();
+  for (int e = threadIdx.x; e < k * k; e += 256) {
+    const int i = e / k, j = e % k;
+    double s = 0.0;
+    for (int t = std::max(i, j); t < k; ++t) s += work[t * kMaxK + i] * work[t * kMaxK + j];
+    Minv[i * k + j] = s;
+  }
+  if (threadIdx.x == 0) *info = bad;
+}
+
+// ---------------------------------------------------------- host wrappers
+
+void enqueue_ts_dot(hipStream_t s, const double *Y, int64_t n, int m, const double *v,
+                    double *part, unsigned *counter, const double *Minv, double *out) {
+  const int grid = static_cast<int>(std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, cdiv(n, 256))));
+  hipLaunchKernelGGL(ts_dot, dim3(grid), dim3(256), 0, s, Y, n, m, v, part, counter, Minv, out);
+}
+
+void enqueue_tsgemm_tn(hipStream_t s, const double *A, const double *B, int64_t n, int ma, int mb,
+                       double *part, size_t part_cap, double *C, int ldc, int symmetrise) {
+  int64_t chunk_rows = 1024;
+  int64_t nchunk = cdiv(n, chunk_rows);
+  while (size_t(nchunk) * ma * mb > part_cap) {
+    chunk_rows *= 2;
+    nchunk = cdiv(n, chunk_rows);
+  }
+  const int tiles = ((ma + 31) / 32) * ((mb + 31) / 32);
+  hipLaunchKernelGGL(tsgemm_tn, dim3(tiles, static_cast<unsigned>(nchunk)), dim3(256), 0, s, A, B,
+                     n, ma, mb, part, chunk_rows);
+  hipLaunchKernelGGL(tsgemm_sum, dim3(static_cast<unsigned>(cdiv(int64_t(ma) * mb, 256))), dim3(256),
+                     0, s, part, static_cast<int>(nchunk), ma, mb, C, ldc, symmetrise);
+}
+
+void enqueue_ts_times_small(hipStream_t s, const double *X, int64_t n, int m, const double *U,
+                            int ldu, int kout, double *Y) {
+  if (kout <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(ts_times_small, dim3(static_cast<unsigned>(cdiv(n, 256)), (kout + 31) / 32),
+                     dim3(256), 0, s, X, n, m, U, ldu, kout, Y);
+}
+
+void enqueue_block_axpy(hipStream_t s, double *Y, const double *X, double alpha, int64_t count) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(block_axpy, dim3(static_cast<unsigned>(cdiv(count, 256))), dim3(256), 0, s, Y,
+                     X, alpha, count);
+}
+
+void enqueue_small_spd_inverse(hipStream_t s, const double *M, int k, double *Minv, double *work,
+                               int *info) {
+  hipLaunchKernelGGL(small_spd_inverse, dim3(1), dim3(256), 0, s, M, k, Minv, work, info);
+}
+
+}  // namespace dcg
+
+namespace dcg {
+
+// out = b - Ax; sums[0] = |out|^2, sums[1] = |b|^2 (last block, fixed order).
+__global__ __launch_bounds__(256) void residual_norms(const double *b, const double *Ax, int64_t n,
+                                                     double *out, double *part, unsigned *counter,
+                                                     double *sums) {
+  __shared__ double lds[8];
+  double rr = 0.0, bb = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const double bi = b[i];
+    const double ri = bi - Ax[i];
+    out[i] = ri;
+    rr += ri * ri;
+    bb += bi * bi;
+  }
+  const double s1 = block_sum<256>(rr, lds);
+  const double s2 = block_sum<256>(bb, lds);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s1;
+    part[2 * blockIdx.x + 1] = s2;
+  }
+  if (last_block(counter)) {
+    if (threadIdx.x == 0) {
+      double a = 0.0, c = 0.0;
+      for (unsigned k = 0; k < gridDim.x; ++k) {
+        a += part[2 * k];
+        c += part[2 * k + 1];
+      }
+      sums[0] = a;
+      sums[1] = c;
+      *counter = 0;
+    }
+  }
+}
+
+}  // namespace dcg

@@ -1,0 +1,103 @@
+// Internal declarations shared by the HIP sources of libdcg.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/dcg.h"
+
+namespace dcg {
+
+// Rows (and columns) per block of the symmetric matvec schedule.
+constexpr int kBlk1 = 256;   // single-vector kernel: 4 waves x 64 rows
+constexpr int kBlk4 = 128;   // 4-vector kernel:      4 waves x 32 rows
+constexpr int kMaxD = 64;
+constexpr int kMaxK = 64;          // columns of W
+constexpr int kMaxZ = 192;         // k + L (columns of Z)
+constexpr int kRedBlocks = 256;    // blocks of the grid-stride FP64 reductions
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Simple bump allocator over a caller workspace.
+struct Carve {
+  char *base;
+  size_t off = 0, cap;
+  Carve(void *b, size_t c) : base(static_cast<char *>(b)), cap(c) {}
+  template <class T>
+  T *take(size_t count) {
+    size_t o = align256(off);
+    off = o + count * sizeof(T);
+    return base ? reinterpret_cast<T *>(base + o) : nullptr;
+  }
+  bool fits() const { return off <= cap; }
+};
+
+// Geometry of the augmented point arrays used by the distance GEMM.
+// Row operand  xr_i = [-2 x_i, 1.., a_i parts, 0 pad]
+// Col operand  xc_j = [  x_j, a_j parts, 1.., 0 pad]
+// so that <xr_i, xc_j> = a_i + a_j - 2 x_i.x_j = |x_i - x_j|^2.
+struct Geometry {
+  int64_t n, n_pad;  // n_pad: multiple of the block size of both schedules
+  int d;
+  int prec;
+  int ksteps;        // MFMA K steps (bf16: 16 per step, fp32: 2 per step)
+  int kstride;       // elements per point row in the stored operand arrays
+};
+
+Geometry make_geometry(int64_t n, int d, int prec);
+
+struct MatvecPlan {
+  int blk;      // rows per block
+  int nb;       // number of blocks
+  int dmax;     // largest block offset delta
+  int chunk;    // column blocks per work item
+  int nchunk;   // work items per row block
+  int64_t grid;
+};
+
+MatvecPlan make_plan(int64_t n_pad, int mv);
+size_t matvec_partial_floats(int64_t n_pad, int mv);
+
+}  // namespace dcg
+
+struct dcg_operator_s {
+  dcg::Geometry g;
+  int kernel;
+  double ell, s2, sigma2;
+  hipStream_t stream;
+  uint64_t generation;   // bumped by every hyperparameter change
+  double *X64;           // n x d FP64 copy (exact operator)
+  void *xr, *xc;         // augmented operands (bf16 or fp32)
+  float *vin;            // staged FP32 input vectors, n_pad x 4
+  float *part;           // partial sums of the symmetric matvec
+  double *ytmp;          // n_pad x 4 FP64 staging for products
+};
+
+struct dcg_recycle_s {
+  int64_t n;
+  int k, L;
+  int k_used;            // columns of W currently valid
+  int L_eff;             // stored directions of the last solve
+  int aw_state;          // 0: AW invalid, 1: AW valid for (op, generation)
+  const dcg_operator_s *aw_op;
+  uint64_t aw_gen;
+  double aw_ell, aw_s2, aw_sigma2;
+  int n_theta;
+  double theta[dcg::kMaxK];
+  double *Z;             // n x (k + L): [W | P_L]
+  double *AZ;            // n x (k + L): [AW | A P_L]
+  double *Wt, *AWt;      // n x k staging for W' = Z U, AW' = (AZ) U
+  double *F, *G;         // (k+L)^2
+  double *U;             // (k+L) x k
+  double *eigw;          // eigen-solver workspace
+  double *M, *Minv;      // k x k: W^T A W and its inverse
+  double *Mwork;         // k x k scratch of the inverse
+  double *N;             // k x k: (AW)^T AW
+  double *small;         // misc small device scalars / vectors
+  int *info;             // device status words of the extraction
+  double *gemm;          // split-K partials of the tall-skinny products
+  int rank_F;            // numerical rank of F at the last extraction
+  int sweeps[2];         // Jacobi sweeps of the last extraction
+};

@@ -1,0 +1,469 @@
+// Matrix-free kernel matvec Y = (K_theta(X, X) + sigma2 I) V.
+//
+// The products A p_j of Algorithm 1 (one per CG step) and the block products
+// A W.  K is symmetric, so every unordered pair of points is evaluated once
+// and feeds both its row sum and its column sum.
+//
+// Schedule.  Rows are cut into nb blocks of BLK points.  Block pairs (I, J)
+// are visited in circulant order: row block I owns the column blocks
+// J = I + delta (mod nb) for delta = 0 .. nb/2 (for even nb the offset nb/2
+// is owned only by I < nb/2).  Every unordered block pair is then owned once
+// and each row block owns the same amount of work.  A work item (one
+// workgroup) is a row block and a contiguous range of offsets; its row sums
+// go to prow[chunk], the column sums of each off-diagonal block pair to
+// pcol[delta], and a second kernel adds the partials in a fixed order (the
+// result is bitwise reproducible).
+//
+// Tile.  A wave owns 32*TR rows and steps through 32-column tiles.  The
+// squared distances of a 32x32 tile come straight out of MFMA, because the
+// operands are augmented: <[-2x_i, 1, a_i], [x_j, a_j, 1]> = |x_i - x_j|^2
+// (a = |x|^2, split over three bf16 terms in bf16 mode).  The kernel value is
+// evaluated in registers on the MFMA output layout (lane l holds column
+// l%32, rows 8(v/4) + 4(l/32) + v%4 for v < 16) and folded into the row
+// accumulators and a per-lane column sum.
+#include <algorithm>
+#include <cmath>
+
+#include "blas.h"
+
+namespace dcg {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+static int fp32_bucket(int ks) {
+  const int b[] = {5, 9, 13, 17, 25, 33};
+  for (int v : b)
+    if (ks <= v) return v;
+  return -1;
+}
+
+Geometry make_geometry(int64_t n, int d, int prec) {
+  Geometry g;
+  g.n = n;
+  g.d = d;
+  g.prec = prec;
+  g.n_pad = ((n + 255) / 256) * 256;
+  if (prec == DCG_PREC_FP64) {
+    g.ksteps = 0;  // the exact FP64 product needs no MFMA operands
+    g.kstride = 0;
+  } else if (prec == DCG_PREC_BF16) {
+    g.ksteps = (d + 6 + 15) / 16;
+    g.kstride = 16 * g.ksteps;
+  } else {
+    g.ksteps = fp32_bucket((d + 2 + 1) / 2);
+    g.kstride = 2 * ((g.ksteps + 3) / 4) * 4;
+  }
+  return g;
+}
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+MatvecPlan make_plan(int64_t n_pad, int mv) {
+  MatvecPlan p;
+  p.blk = (mv == 1) ? kBlk1 : kBlk4;
+  p.nb = static_cast<int>(n_pad / p.blk);
+  p.dmax = p.nb / 2;
+  const int ndelta = p.dmax + 1;
+  p.chunk = static_cast<int>(std::max<int64_t>(1, cdiv(int64_t(ndelta) * p.nb, 2048)));
+  p.nchunk = static_cast<int>(cdiv(ndelta, p.chunk));
+  p.grid = int64_t(p.nb) * p.nchunk;
+  return p;
+}
+
+size_t matvec_partial_floats(int64_t n_pad, int mv) {
+  MatvecPlan p = make_plan(n_pad, mv);
+  // row partials are FP64 (two floats each), column partials FP32
+  return size_t(2 * p.nchunk + p.dmax) * size_t(n_pad) * size_t(mv);
+}
+
+// Kernel value without the s2 factor, from the squared distance.
+//   RBF:        exp2(c0 r2),                 c0 = -log2(e) / (2 ell^2)
+//   Matern-3/2: (1 + c1 t) exp2(c0 t),       t = |r|, c0 = -sqrt3 log2(e)/ell, c1 = sqrt3/ell
+//   Matern-5/2: (1 + c1 t + c2 t^2) exp2(c0 t), c0 = -sqrt5 log2(e)/ell,
+//               c1 = sqrt5/ell, c2 = 5/(3 ell^2)
+// |r2| absorbs the tiny negative values FP32 rounding can give at r ~ 0.
+template <int KERN>
+__device__ __forceinline__ float kval(float r2, float c0, float c1, float c2) {
+  if constexpr (KERN == DCG_RBF) {
+    return __builtin_amdgcn_exp2f(r2 * c0);
+  } else {
+    const float t = __builtin_amdgcn_sqrtf(fabsf(r2));
+    const float e = __builtin_amdgcn_exp2f(t * c0);
+    if constexpr (KERN == DCG_MATERN32) {
+      return fmaf(t, c1, 1.0f) * e;
+    } else {
+      return fmaf(t, fmaf(t, c2, c1), 1.0f) * e;
+    }
+  }
+}
+
+template <bool BF16, int KS>
+struct Operand;
+
+template <int KS>
+struct Operand<true, KS> {
+  bf16x8 v[KS];
+  __device__ __forceinline__ void load(const void *base, int64_t point, int kstride, int lh) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(
+        static_cast<const uint16_t *>(base) + point * kstride + 8 * lh);
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      uint4 u = p[2 * s];
+      v[s] = __builtin_bit_cast(bf16x8, u);
+    }
+  }
+};
+
+template <int KS>
+struct Operand<false, KS> {
+  static constexpr int KS4 = (KS + 3) / 4;
+  float v[KS4 * 4];
+  __device__ __forceinline__ void load(const void *base, int64_t point, int kstride, int lh) {
+    const float4 *p = reinterpret_cast<const float4 *>(
+        static_cast<const float *>(base) + point * kstride + lh * (kstride / 2));
+#pragma unroll
+    for (int s = 0; s < KS4; ++s) {
+      float4 u = p[s];
+      v[4 * s + 0] = u.x;
+      v[4 * s + 1] = u.y;
+      v[4 * s + 2] = u.z;
+      v[4 * s + 3] = u.w;
+    }
+  }
+};
+
+template <bool BF16, int KS>
+__device__ __forceinline__ f32x16 tile_r2(const Operand<BF16, KS> &a, const Operand<BF16, KS> &b) {
+  f32x16 acc = {};
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    if constexpr (BF16)
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v[s], b.v[s], acc, 0, 0, 0);
+    else
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[s], b.v[s], acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+struct SymvArgs {
+  const void *xr, *xc;
+  int kstride;
+  const float *vin;   // n_pad x MV, leading dimension n_pad
+  double *prow;
+  float *pcol;
+  int64_t n_pad;
+  int nb, dmax, chunk, nchunk;
+  float c0, c1, c2;
+  const int *done;    // optional: skip the launch once the solve converged
+};
+
+template <int KERN, int KS, int MV, bool BF16>
+__global__ __launch_bounds__(256, 2) void symv_kernel(SymvArgs A) {
+  if (A.done != nullptr && *A.done != 0) return;
+  constexpr int TR = (MV == 1) ? 2 : 1;
+  constexpr int BLK = 4 * 32 * TR;
+  constexpr int NCT = BLK / 32;
+  __shared__ float colpart[MV][4][BLK];
+
+  // Spread consecutive work items over one XCD (workgroups are dealt to the
+  // 8 XCDs round-robin): neighbouring row blocks share most column blocks,
+  // so they then share that XCD's L2.
+  const int64_t G = int64_t(A.nb) * A.nchunk;
+  const int64_t bid = blockIdx.x;
+  const int64_t Gm = G - G % 8;
+  const int64_t item = (bid < Gm) ? (bid % 8) * (Gm / 8) + bid / 8 : bid;
+  const int I = static_cast<int>(item / A.nchunk);
+  const int c = static_cast<int>(item % A.nchunk);
+
+  const int nb = A.nb;
+  const int ndel = ((nb % 2) == 0 && I >= nb / 2) ? A.dmax : A.dmax + 1;
+  const int d0 = c * A.chunk;
+  const int d1 = min(d0 + A.chunk, ndel);
+
+  const int w = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63;
+  const int lc = l & 31, lh = l >> 5;
+  const int64_t n_pad = A.n_pad;
+  const int64_t rowbase = int64_t(I) * BLK + w * 32 * TR;
+
+  // Row sums: FP32 runs over the 8 column tiles of one block pair, then FP64
+  // across block pairs (single-vector kernel; the 4-vector kernel keeps FP32
+  // to stay within its register budget).
+  constexpr bool ACC64 = (MV == 1);
+  Operand<BF16, KS> ra[TR];
+  float pi[MV][TR][16];
+  float accr[MV][TR][16];
+  double acc64[ACC64 ? MV : 1][TR][16];
+#pragma unroll
+  for (int tr = 0; tr < TR; ++tr) {
+    ra[tr].load(A.xr, rowbase + 32 * tr + lc, A.kstride, lh);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t i = rowbase + 32 * tr + 8 * (v >> 2) + 4 * lh + (v & 3);
+#pragma unroll
+      for (int m = 0; m < MV; ++m) {
+        pi[m][tr][v] = A.vin[m * n_pad + i];
+        accr[m][tr][v] = 0.0f;
+        if constexpr (ACC64) acc64[m][tr][v] = 0.0;
+      }
+    }
+  }
+
+  const int tiles = (d1 > d0) ? (d1 - d0) * NCT : 0;
+  auto colbase_of = [&](int t) -> int64_t {
+    int J = I + d0 + t / NCT;
+    if (J >= nb) J -= nb;
+    return int64_t(J) * BLK + 32 * (t % NCT);
+  };
+
+  Operand<BF16, KS> cb, cbn;
+  float pj[MV], pjn[MV];
+  if (tiles > 0) {
+    const int64_t cb0 = colbase_of(0);
+    cb.load(A.xc, cb0 + lc, A.kstride, lh);
+#pragma unroll
+    for (int m = 0; m < MV; ++m) pj[m] = A.vin[m * n_pad + cb0 + lc];
+  }
+  const float c0 = A.c0, c1 = A.c1, c2 = A.c2;
+
+  for (int t = 0; t < tiles; ++t) {
+    const int dl = d0 + t / NCT;
+    const int ct = t % NCT;
+    const bool diag = (dl == 0);
+    if (t + 1 < tiles) {
+      const int64_t cbx = colbase_of(t + 1);
+      cbn.load(A.xc, cbx + lc, A.kstride, lh);
+#pragma unroll
+      for (int m = 0; m < MV; ++m) pjn[m] = A.vin[m * n_pad + cbx + lc];
+    }
+    float cs[MV];
+#pragma unroll
+    for (int m = 0; m < MV; ++m) cs[m] = 0.0f;
+#pragma unroll
+    for (int tr = 0; tr < TR; ++tr) {
+      f32x16 r2 = tile_r2<BF16, KS>(ra[tr], cb);
+      if (diag && ct == w * TR + tr) {
+        // the exact diagonal: distance zero by definition
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          if (8 * (v >> 2) + 4 * lh + (v & 3) == lc) r2[v] = 0.0f;
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const float kv = kval<KERN>(r2[v], c0, c1, c2);
+#pragma unroll
+        for (int m = 0; m < MV; ++m) {
+          accr[m][tr][v] = fmaf(kv, pj[m], accr[m][tr][v]);
+          cs[m] = fmaf(kv, pi[m][tr][v], cs[m]);
+        }
+      }
+    }
+    if (!diag) {
+#pragma unroll
+      for (int m = 0; m < MV; ++m) {
+        cs[m] += __shfl_xor(cs[m], 32);
+        if (lh == 0) colpart[m][w][32 * ct + lc] = cs[m];
+      }
+      if (ct == NCT - 1) {
+        __syncthreads();
+        int J = I + dl;
+        if (J >= nb) J -= nb;
+        for (int e = threadIdx.x; e < MV * BLK; e += 256) {
+          const int m = e / BLK, col = e % BLK;
+          const float s = (colpart[m][0][col] + colpart[m][1][col]) +
+                          (colpart[m][2][col] + colpart[m][3][col]);
+          A.pcol[(int64_t(dl - 1) * MV + m) * n_pad + int64_t(J) * BLK + col] = s;
+        }
+        __syncthreads();
+      }
+    }
+    if constexpr (ACC64) {
+      if (ct == NCT - 1) {
+#pragma unroll
+        for (int m = 0; m < MV; ++m)
+#pragma unroll
+          for (int tr = 0; tr < TR; ++tr)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              acc64[m][tr][v] += static_cast<double>(accr[m][tr][v]);
+              accr[m][tr][v] = 0.0f;
+            }
+      }
+    }
+    if (t + 1 < tiles) {
+      cb = cbn;
+#pragma unroll
+      for (int m = 0; m < MV; ++m) pj[m] = pjn[m];
+    }
+  }
+
+  // Row sums: reduce over the 32 lanes that hold the same rows.
+#pragma unroll
+  for (int m = 0; m < MV; ++m) {
+#pragma unroll
+    for (int tr = 0; tr < TR; ++tr) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        double s;
+        if constexpr (ACC64) s = acc64[m][tr][v];
+        else s = static_cast<double>(accr[m][tr][v]);
+        s += __shfl_xor(s, 1);
+        s += __shfl_xor(s, 2);
+        s += __shfl_xor(s, 4);
+        s += __shfl_xor(s, 8);
+        s += __shfl_xor(s, 16);
+        if (lc == v) {
+          const int64_t i = rowbase + 32 * tr + 8 * (v >> 2) + 4 * lh + (v & 3);
+          A.prow[(int64_t(c) * MV + m) * n_pad + i] = s;
+        }
+      }
+    }
+  }
+}
+
+// Finish y = s2 * (sum of partials) + sigma2 v for the first `cols` vectors.
+__global__ __launch_bounds__(256) void symv_reduce(ReduceArgs A, int cols) {
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= A.n * cols) return;
+  const int m = static_cast<int>(e / A.n);
+  const int64_t i = e % A.n;
+  const double s = sum_partials(A, m, i);
+  A.Y[m * A.n + i] = A.s2 * s + A.sigma2 * A.V[m * A.n + i];
+}
+
+// FP64 -> FP32 staging of up to 4 vectors, zero padded to n_pad.
+__global__ __launch_bounds__(256) void stage_vectors(const double *V, int64_t n, int64_t n_pad,
+                                                     int mv, int mvs, float *out) {
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= n_pad * mvs) return;
+  const int m = static_cast<int>(e / n_pad);
+  const int64_t i = e % n_pad;
+  out[e] = (m < mv && i < n) ? static_cast<float>(V[m * n + i]) : 0.0f;
+}
+
+// ----------------------------------------------------------------- dispatch
+
+void kernel_constants(int kernel, double ell, float *c0, float *c1, float *c2) {
+  const double log2e = 1.4426950408889634;
+  if (kernel == DCG_RBF) {
+    *c0 = static_cast<float>(-log2e / (2.0 * ell * ell));
+    *c1 = *c2 = 0.0f;
+  } else if (kernel == DCG_MATERN32) {
+    *c0 = static_cast<float>(-std::sqrt(3.0) * log2e / ell);
+    *c1 = static_cast<float>(std::sqrt(3.0) / ell);
+    *c2 = 0.0f;
+  } else {
+    *c0 = static_cast<float>(-std::sqrt(5.0) * log2e / ell);
+    *c1 = static_cast<float>(std::sqrt(5.0) / ell);
+    *c2 = static_cast<float>(5.0 / (3.0 * ell * ell));
+  }
+}
+
+template <int KERN, int KS, int MV, bool BF16>
+static void launch_symv(const SymvArgs &a, int64_t grid, hipStream_t s) {
+  hipLaunchKernelGGL((symv_kernel<KERN, KS, MV, BF16>), dim3(static_cast<unsigned>(grid)),
+                     dim3(256), 0, s, a);
+}
+
+template <int KERN, int MV>
+static int dispatch_ks(const dcg_operator_s *op, const SymvArgs &a, int64_t grid) {
+  const int ks = op->g.ksteps;
+  hipStream_t s = op->stream;
+  if (op->g.prec == DCG_PREC_BF16) {
+    switch (ks) {
+      case 1: launch_symv<KERN, 1, MV, true>(a, grid, s); return 0;
+      case 2: launch_symv<KERN, 2, MV, true>(a, grid, s); return 0;
+      case 3: launch_symv<KERN, 3, MV, true>(a, grid, s); return 0;
+      case 4: launch_symv<KERN, 4, MV, true>(a, grid, s); return 0;
+      case 5: launch_symv<KERN, 5, MV, true>(a, grid, s); return 0;
+    }
+  } else {
+    switch (ks) {
+      case 5: launch_symv<KERN, 5, MV, false>(a, grid, s); return 0;
+      case 9: launch_symv<KERN, 9, MV, false>(a, grid, s); return 0;
+      case 13: launch_symv<KERN, 13, MV, false>(a, grid, s); return 0;
+      case 17: launch_symv<KERN, 17, MV, false>(a, grid, s); return 0;
+      case 25: launch_symv<KERN, 25, MV, false>(a, grid, s); return 0;
+      case 33: launch_symv<KERN, 33, MV, false>(a, grid, s); return 0;
+    }
+  }
+  return -1;
+}
+
+// Enqueue the symmetric pair sweep over op->vin (mv = 1 or 4 vectors).
+int launch_symv_sweep(const dcg_operator_s *op, int mv, const int *done) {
+  MatvecPlan p = make_plan(op->g.n_pad, mv);
+  SymvArgs a;
+  a.xr = op->xr;
+  a.xc = op->xc;
+  a.kstride = op->g.kstride;
+  a.vin = op->vin;
+  a.prow = reinterpret_cast<double *>(op->part);
+  a.pcol = op->part + size_t(2 * p.nchunk) * op->g.n_pad * mv;
+  a.n_pad = op->g.n_pad;
+  a.nb = p.nb;
+  a.dmax = p.dmax;
+  a.chunk = p.chunk;
+  a.nchunk = p.nchunk;
+  a.done = done;
+  kernel_constants(op->kernel, op->ell, &a.c0, &a.c1, &a.c2);
+  int rc = -1;
+  if (mv == 1) {
+    if (op->kernel == DCG_RBF) rc = dispatch_ks<DCG_RBF, 1>(op, a, p.grid);
+    else if (op->kernel == DCG_MATERN32) rc = dispatch_ks<DCG_MATERN32, 1>(op, a, p.grid);
+    else rc = dispatch_ks<DCG_MATERN52, 1>(op, a, p.grid);
+  } else {
+    if (op->kernel == DCG_RBF) rc = dispatch_ks<DCG_RBF, 4>(op, a, p.grid);
+    else if (op->kernel == DCG_MATERN32) rc = dispatch_ks<DCG_MATERN32, 4>(op, a, p.grid);
+    else rc = dispatch_ks<DCG_MATERN52, 4>(op, a, p.grid);
+  }
+  if (rc != 0) return DCG_E_ARG;
+  return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
+}
+
+ReduceArgs reduce_args(const dcg_operator_s *op, int mv, const double *V, double *Y) {
+  MatvecPlan p = make_plan(op->g.n_pad, mv);
+  ReduceArgs r;
+  r.prow = reinterpret_cast<const double *>(op->part);
+  r.pcol = op->part + size_t(2 * p.nchunk) * op->g.n_pad * mv;
+  r.n = op->g.n;
+  r.n_pad = op->g.n_pad;
+  r.nchunk = p.nchunk;
+  r.dmax = p.dmax;
+  r.blk = p.blk;
+  r.nb = p.nb;
+  r.mv = mv;
+  r.s2 = op->s2;
+  r.sigma2 = op->sigma2;
+  r.V = V;
+  r.Y = Y;
+  return r;
+}
+
+// Y = A V for m vectors (groups of 4, a last single vector group of 1).
+int matvec_lowprec(const dcg_operator_s *op, const double *V, double *Y, int64_t m) {
+  if (op->g.prec == DCG_PREC_FP64) return matvec_exact(op, V, Y, m);
+  const int64_t n = op->g.n, n_pad = op->g.n_pad;
+  int64_t done_cols = 0;
+  while (done_cols < m) {
+    const int64_t left = m - done_cols;
+    const int mv = (left >= 2) ? 4 : 1;
+    const int cols = static_cast<int>(std::min<int64_t>(left, mv));
+    const double *Vc = V + done_cols * n;
+    double *Yc = Y + done_cols * n;
+    hipLaunchKernelGGL(stage_vectors, dim3(static_cast<unsigned>(cdiv(n_pad * mv, 256))), dim3(256),
+                       0, op->stream, Vc, n, n_pad, cols, mv, op->vin);
+    int rc = launch_symv_sweep(op, mv, nullptr);
+    if (rc != DCG_OK) return rc;
+    // only the first `cols` staged vectors are real; reduce those
+    ReduceArgs r = reduce_args(op, mv, Vc, Yc);
+    hipLaunchKernelGGL(symv_reduce, dim3(static_cast<unsigned>(cdiv(n * cols, 256))), dim3(256),
+                       0, op->stream, r, cols);
+    if (hipGetLastError() != hipSuccess) return DCG_E_HIP;
+    done_cols += cols;
+  }
+  return DCG_OK;
+}
+
+}  // namespace dcg

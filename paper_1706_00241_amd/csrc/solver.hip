@@ -1,0 +1,572 @@
+// Host driver of deflated CG (Algorithm 1 of the paper) with the harmonic
+// Ritz refresh of the recycled basis (section 2.3, Eq. 7), plus the
+// mixed-precision iterative refinement around it.
+//
+// Per CG step four kernels run on the operator's stream: the symmetric pair
+// sweep (q = A p partials), the product finish with d = p^T q and alpha, the
+// x / r update with rho and h = (AW)^T r, and the direction update
+// p = beta p + r - W mu.  All scalars stay on the device; the host reads the
+// solve state once per chunk of iterations (optionally replayed as one
+// captured hipGraph), so the loop has one host round trip per chunk.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "blas.h"
+
+namespace dcg {
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+constexpr int kHistCap = 1 << 16;
+constexpr size_t kGemmPartDoubles = size_t(64) * kMaxZ * kMaxZ;
+
+struct SolveLayout {
+  size_t S, counter, r, p, q, part, part_h, hist_res, hist_d, hist_alpha, hist_beta, tmp1, tmp2,
+      tmp3, total;
+};
+
+static SolveLayout solve_layout(int64_t n) {
+  SolveLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = align256(off);
+    const size_t o = off;
+    off += bytes;
+    return o;
+  };
+  const size_t nb = size_t(std::max<int64_t>(cdiv(n, 256), kRedBlocks));
+  L.S = take(sizeof(SolveState));
+  L.counter = take(sizeof(unsigned) * 4);
+  L.r = take(size_t(n) * 8);
+  L.p = take(size_t(n) * 8);
+  L.q = take(size_t(n) * 8);
+  L.part = take(nb * 8);
+  L.part_h = take(nb * kMaxZ * 8);
+  L.hist_res = take(size_t(kHistCap) * 8);
+  L.hist_d = take(size_t(kMaxZ) * 8);
+  L.hist_alpha = take(size_t(kMaxZ) * 8);
+  L.hist_beta = take(size_t(kMaxZ) * 8);
+  L.tmp1 = take(size_t(n) * 8);
+  L.tmp2 = take(size_t(n) * 8);
+  L.tmp3 = take(size_t(n) * 8);
+  L.total = align256(off);
+  return L;
+}
+
+struct RecycleLayout {
+  size_t Z, AZ, Wt, AWt, F, G, U, eigw, M, Minv, Mwork, N, small, info, gemm, total;
+};
+
+static RecycleLayout recycle_layout(int64_t n, int k, int L) {
+  RecycleLayout R;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = align256(off);
+    const size_t o = off;
+    off += bytes;
+    return o;
+  };
+  const size_t kz = size_t(k + L);
+  R.Z = take(size_t(n) * kz * 8);
+  R.AZ = take(size_t(n) * kz * 8);
+  R.Wt = take(size_t(n) * k * 8);
+  R.AWt = take(size_t(n) * k * 8);
+  R.F = take(size_t(kMaxZ) * kMaxZ * 8);
+  R.G = take(size_t(kMaxZ) * kMaxZ * 8);
+  R.U = take(size_t(kMaxZ) * kMaxK * 8);
+  R.eigw = take(harmonic_ritz_work_doubles() * 8);
+  R.M = take(size_t(kMaxK) * kMaxK * 8);
+  R.Minv = take(size_t(kMaxK) * kMaxK * 8);
+  R.Mwork = take(size_t(kMaxK) * kMaxK * 8);
+  R.N = take(size_t(kMaxK) * kMaxK * 8);
+  R.small = take(size_t(kMaxZ) * 8);
+  R.info = take(64);
+  R.gemm = take(kGemmPartDoubles * 8);
+  R.total = align256(off);
+  return R;
+}
+
+struct SolveBuffers {
+  SolveState *S;
+  unsigned *counter;
+  double *r, *p, *q, *part, *part_h, *hist_res, *hist_d, *hist_alpha, *hist_beta;
+  double *tmp1, *tmp2, *tmp3;
+};
+
+static SolveBuffers solve_buffers(void *ws, int64_t n) {
+  const SolveLayout L = solve_layout(n);
+  char *b = static_cast<char *>(ws);
+  SolveBuffers B;
+  B.S = reinterpret_cast<SolveState *>(b + L.S);
+  B.counter = reinterpret_cast<unsigned *>(b + L.counter);
+  B.r = reinterpret_cast<double *>(b + L.r);
+  B.p = reinterpret_cast<double *>(b + L.p);
+  B.q = reinterpret_cast<double *>(b + L.q);
+  B.part = reinterpret_cast<double *>(b + L.part);
+  B.part_h = reinterpret_cast<double *>(b + L.part_h);
+  B.hist_res = reinterpret_cast<double *>(b + L.hist_res);
+  B.hist_d = reinterpret_cast<double *>(b + L.hist_d);
+  B.hist_alpha = reinterpret_cast<double *>(b + L.hist_alpha);
+  B.hist_beta = reinterpret_cast<double *>(b + L.hist_beta);
+  B.tmp1 = reinterpret_cast<double *>(b + L.tmp1);
+  B.tmp2 = reinterpret_cast<double *>(b + L.tmp2);
+  B.tmp3 = reinterpret_cast<double *>(b + L.tmp3);
+  return B;
+}
+
+using Clock = std::chrono::steady_clock;
+static double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+#define HIPCHK(x)                                      \
+  do {                                                 \
+    if ((x) != hipSuccess) return DCG_E_HIP;           \
+  } while (0)
+
+struct InnerResult {
+  int iters = 0, matvecs = 0, k_used = 0, k_next = 0, status = DCG_OK;
+  int sweeps_timed = 0;
+  double t_sweeps = 0.0;
+  double relres = 0.0;
+  double t_init = 0.0, t_loop = 0.0, t_refresh = 0.0;
+};
+
+// Make AZ[:, :k_used] the product of W with the current operator.
+static int refresh_AW(dcg_operator_s *op, dcg_recycle_s *rc, int *matvecs) {
+  const int k = rc->k_used;
+  if (k == 0) return DCG_OK;
+  const int64_t n = rc->n;
+  const bool same_op = rc->aw_state == 1 && rc->aw_op == op;
+  if (same_op && rc->aw_gen == op->generation) return DCG_OK;
+  if (same_op && rc->aw_ell == op->ell && rc->aw_s2 == op->s2) {
+    // only the diagonal shift changed: A_new W = A_old W + (s_new - s_old) W
+    enqueue_block_axpy(op->stream, rc->AZ, rc->Z, op->sigma2 - rc->aw_sigma2, n * k);
+  } else {
+    const int st = matvec_lowprec(op, rc->Z, rc->AZ, k);
+    if (st != DCG_OK) return st;
+    *matvecs += k;
+  }
+  rc->aw_state = 1;
+  rc->aw_op = op;
+  rc->aw_gen = op->generation;
+  rc->aw_ell = op->ell;
+  rc->aw_s2 = op->s2;
+  rc->aw_sigma2 = op->sigma2;
+  return DCG_OK;
+}
+
+static CgArgs cg_args(dcg_operator_s *op, const SolveBuffers &B, double *x, dcg_recycle_s *rc,
+                      const double *Minv, int k, int L, double tol, int max_iter) {
+  CgArgs a;
+  a.S = B.S;
+  a.red = reduce_args(op, 1, nullptr, nullptr);
+  a.qdirect = (op->g.prec == DCG_PREC_FP64) ? op->ytmp : nullptr;
+  a.n = op->g.n;
+  a.x = x;
+  a.r = B.r;
+  a.p = B.p;
+  a.q = B.q;
+  a.p32 = op->vin;
+  a.W = rc ? rc->Z : nullptr;
+  a.AW = rc ? rc->AZ : nullptr;
+  a.Minv = Minv;
+  a.N = rc ? rc->N : nullptr;
+  a.k = k;
+  a.Z = (rc && L > 0) ? rc->Z : nullptr;
+  a.AZ = (rc && L > 0) ? rc->AZ : nullptr;
+  a.koff = k;
+  a.L = L;
+  a.part = B.part;
+  a.part_h = B.part_h;
+  a.counter = B.counter;
+  a.hist_d = B.hist_d;
+  a.hist_alpha = B.hist_alpha;
+  a.hist_beta = B.hist_beta;
+  a.hist_res = B.hist_res;
+  a.hist_cap = kHistCap;
+  a.tol = tol;
+  a.max_iter = max_iter;
+  return a;
+}
+
+static int enqueue_cg_step(dcg_operator_s *op, const CgArgs &a, hipEvent_t ev0 = nullptr,
+                           hipEvent_t ev1 = nullptr) {
+  if (ev0 != nullptr && hipEventRecord(ev0, op->stream) != hipSuccess) return DCG_E_HIP;
+  const int st = (op->g.prec == DCG_PREC_FP64)
+                     ? matvec_exact_done(op, a.p, op->ytmp, 1, &a.S->done)
+                     : launch_symv_sweep(op, 1, &a.S->done);
+  if (ev1 != nullptr && hipEventRecord(ev1, op->stream) != hipSuccess) return DCG_E_HIP;
+  if (st != DCG_OK) return st;
+  const dim3 grid(static_cast<unsigned>(cdiv(op->g.n, 256)));
+  hipLaunchKernelGGL(cg_matvec_finish, grid, dim3(256), 0, op->stream, a);
+  hipLaunchKernelGGL(cg_update_xr, grid, dim3(256), 0, op->stream, a);
+  hipLaunchKernelGGL(cg_update_p, grid, dim3(256), 0, op->stream, a);
+  return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
+}
+
+// One deflated-CG solve of A x = b (Algorithm 1), then the extraction of the
+// next basis (section 2.3) when rc is given.
+static int inner_solve(dcg_operator_s *op, const double *b, double *x, int x_given,
+                       dcg_recycle_s *rc, const dcg_params *p, double tol, void *ws,
+                       InnerResult *out) {
+  const auto t0 = Clock::now();
+  hipStream_t s = op->stream;
+  const int64_t n = op->g.n, n_pad = op->g.n_pad;
+  SolveBuffers B = solve_buffers(ws, n);
+  const int max_iter = p->max_iter > 0 ? p->max_iter : static_cast<int>(std::min<int64_t>(10 * n, 1 << 30));
+  int L = 0;
+  int k = 0;
+  if (rc != nullptr) {
+    L = (p->L > 0) ? std::min(p->L, rc->L) : rc->L;
+    k = rc->k_used;
+  }
+  int matvecs = 0;
+  const double *Minv = nullptr;
+  HIPCHK(hipMemsetAsync(B.counter, 0, sizeof(unsigned) * 4, s));
+  HIPCHK(hipMemsetAsync(B.S, 0, sizeof(SolveState), s));
+  if (k > 0) {
+    int st = refresh_AW(op, rc, &matvecs);
+    if (st != DCG_OK) return st;
+    enqueue_tsgemm_tn(s, rc->Z, rc->AZ, n, k, k, rc->gemm, kGemmPartDoubles, rc->M, k, 1);
+    enqueue_tsgemm_tn(s, rc->AZ, rc->AZ, n, k, k, rc->gemm, kGemmPartDoubles, rc->N, k, 1);
+    enqueue_small_spd_inverse(s, rc->M, k, rc->Minv, rc->Mwork, rc->info);
+    Minv = rc->Minv;
+  }
+  // r = b - A x_{-1}
+  const double *Ax = nullptr;
+  if (x_given) {
+    int st = matvec_lowprec(op, x, B.q, 1);
+    if (st != DCG_OK) return st;
+    Ax = B.q;
+    matvecs += 1;
+  }
+  const dim3 grid(static_cast<unsigned>(cdiv(n, 256)));
+  hipLaunchKernelGGL(init_residual, grid, dim3(256), 0, s, b, Ax, x, B.r, n, x_given, B.part,
+                     B.counter, B.S);
+  if (k > 0) {
+    int info = 0;
+    HIPCHK(hipMemcpyAsync(&info, rc->info, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (info != 0) return DCG_E_NOT_SPD;
+    // x_0 = x_{-1} + W (W^T A W)^{-1} W^T r_{-1};  r_0 = b - A x_0, formed as
+    // r_{-1} - A (W c) with one product, so that r_0 is the residual of the
+    // operator itself and not of the (slightly inexact) stored AW
+    enqueue_ts_dot(s, rc->Z, n, k, B.r, B.part_h, B.counter + 1, Minv, B.S->cvec);
+    hipLaunchKernelGGL(defl_start, grid, dim3(256), 0, s, x, B.p, rc->Z, B.S->cvec, n, k);
+    int st = matvec_lowprec(op, B.p, B.q, 1);
+    if (st != DCG_OK) return st;
+    matvecs += 1;
+    enqueue_block_axpy(s, B.r, B.q, -1.0, n);
+    // W^T A W mu_0 = (AW)^T r_0
+    enqueue_ts_dot(s, rc->AZ, n, k, B.r, B.part_h, B.counter + 1, Minv, B.S->mu);
+  }
+  hipLaunchKernelGGL(init_direction, dim3(static_cast<unsigned>(cdiv(n_pad, 256))), dim3(256), 0, s,
+                     B.r, rc ? rc->Z : nullptr, B.S->mu, n, n_pad, k, B.p, op->vin, B.part,
+                     B.counter, B.S, tol, B.hist_res);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  out->t_init = ms_since(t0);
+
+  // ---- iteration loop
+  const auto t1 = Clock::now();
+  CgArgs a = cg_args(op, B, x, rc, Minv, k, L, tol, max_iter);
+  const int chunk = std::max(1, p->check_every);
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  // profiling: one event pair per step of a chunk, read back at each chunk end
+  hipEvent_t evs[2 * 64] = {};
+  const bool prof = p->profile != 0;
+  const int pchunk = prof ? std::min(chunk, 64) : chunk;
+  if (prof)
+    for (int e = 0; e < 2 * pchunk; ++e) HIPCHK(hipEventCreate(&evs[e]));
+  if (p->use_graph && !prof) {
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int st = DCG_OK;
+    for (int c = 0; c < chunk && st == DCG_OK; ++c) st = enqueue_cg_step(op, a);
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (st != DCG_OK || e != hipSuccess) return st != DCG_OK ? st : DCG_E_HIP;
+    HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+  }
+  SolveState hs;
+  hs.iter = 0;
+  hs.done = 0;
+  int status = DCG_OK;
+  while (true) {
+    if (gexec != nullptr) {
+      if (hipGraphLaunch(gexec, s) != hipSuccess) { status = DCG_E_HIP; break; }
+    } else {
+      for (int c = 0; c < pchunk; ++c) {
+        status = prof ? enqueue_cg_step(op, a, evs[2 * c], evs[2 * c + 1]) : enqueue_cg_step(op, a);
+        if (status != DCG_OK) break;
+      }
+      if (status != DCG_OK) break;
+    }
+    const int prev_iter = hs.iter;
+    if (hipMemcpyAsync(&hs, B.S, offsetof(SolveState, mu), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      status = DCG_E_HIP;
+      break;
+    }
+    if (prof) {
+      // sweeps that did work (those after convergence return at once)
+      const int ran = std::min(pchunk, hs.iter - prev_iter);
+      for (int c = 0; c < ran; ++c) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, evs[2 * c], evs[2 * c + 1]) == hipSuccess) {
+          out->t_sweeps += ms;
+          out->sweeps_timed += 1;
+        }
+      }
+    }
+    if (hs.done) break;
+  }
+  if (prof)
+    for (int e = 0; e < 2 * pchunk; ++e) (void)hipEventDestroy(evs[e]);
+  if (gexec != nullptr) (void)hipGraphExecDestroy(gexec);
+  if (graph != nullptr) (void)hipGraphDestroy(graph);
+  if (status != DCG_OK) return status;
+  out->t_loop = ms_since(t1);
+  out->iters = hs.iter;
+  out->relres = hs.relres;
+  matvecs += hs.iter;
+  out->status = hs.status != 0 ? hs.status : (hs.relres <= tol ? DCG_OK : DCG_NOT_CONVERGED);
+  out->k_used = k;
+  out->k_next = k;
+
+  // ---- harmonic Ritz extraction of W' = Z U (Eq. 7)
+  const auto t2 = Clock::now();
+  if (rc != nullptr && out->status >= 0) {
+    const int L_eff = std::min(L, hs.iter);
+    const int mz = k + L_eff;
+    if (mz > 0) {
+      enqueue_tsgemm_tn(s, rc->AZ, rc->Z, n, mz, mz, rc->gemm, kGemmPartDoubles, rc->F, mz, 1);
+      enqueue_tsgemm_tn(s, rc->AZ, rc->AZ, n, mz, mz, rc->gemm, kGemmPartDoubles, rc->G, mz, 1);
+      enqueue_harmonic_ritz(s, rc->F, rc->G, mz, rc->k, p->select_largest, 1e-12, rc->eigw, rc->U,
+                            rc->small, rc->info);
+      int info[4] = {0, 0, 0, 0};
+      HIPCHK(hipMemcpyAsync(info, rc->info, sizeof(info), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(rc->theta, rc->small, sizeof(double) * kMaxK, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      const int knew = info[0];
+      rc->rank_F = info[1];
+      rc->sweeps[0] = info[2];
+      rc->sweeps[1] = info[3];
+      if (knew > 0) {
+        enqueue_ts_times_small(s, rc->Z, n, mz, rc->U, kMaxK, knew, rc->Wt);
+        enqueue_ts_times_small(s, rc->AZ, n, mz, rc->U, kMaxK, knew, rc->AWt);
+        HIPCHK(hipMemcpyAsync(rc->Z, rc->Wt, size_t(n) * knew * 8, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(rc->AZ, rc->AWt, size_t(n) * knew * 8, hipMemcpyDeviceToDevice, s));
+      }
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(s));
+      rc->k_used = knew;
+      rc->n_theta = knew;
+      rc->L_eff = L_eff;
+      // AW' = (AZ) U is the product with this operator
+      rc->aw_state = 1;
+      rc->aw_op = op;
+      rc->aw_gen = op->generation;
+      rc->aw_ell = op->ell;
+      rc->aw_s2 = op->s2;
+      rc->aw_sigma2 = op->sigma2;
+      out->k_next = knew;
+    }
+  }
+  out->t_refresh = ms_since(t2);
+  out->matvecs = matvecs;
+  return DCG_OK;
+}
+
+// |b - A x| / |b| with the low-precision (exact = 0) or FP64 operator.
+static int true_residual(dcg_operator_s *op, const double *b, const double *x, int exact,
+                         const SolveBuffers &B, double *rel) {
+  hipStream_t s = op->stream;
+  const int64_t n = op->g.n;
+  int st = exact ? matvec_exact(op, x, B.tmp3, 1) : matvec_lowprec(op, x, B.tmp3, 1);
+  if (st != DCG_OK) return st;
+  HIPCHK(hipMemsetAsync(B.counter + 2, 0, sizeof(unsigned), s));
+  hipLaunchKernelGGL(residual_norms, dim3(static_cast<unsigned>(std::min<int64_t>(kRedBlocks, cdiv(n, 256)))),
+                     dim3(256), 0, s, b, B.tmp3, n, B.tmp2, B.part, B.counter + 2,
+                     B.S->cvec);
+  double h[2];
+  HIPCHK(hipMemcpyAsync(h, B.S->cvec, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *rel = (h[1] > 0.0) ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+  return DCG_OK;
+}
+
+}  // namespace dcg
+
+using namespace dcg;
+
+extern "C" {
+
+size_t dcg_recycle_workspace_bytes(int64_t n, int k, int L) {
+  if (n < 1 || k < 1 || k > kMaxK || L < k || k + L > kMaxZ) return 0;
+  return recycle_layout(n, k, L).total;
+}
+
+int dcg_recycle_create(int64_t n, int k, int L, void *workspace, size_t ws_bytes,
+                       dcg_recycle_t *out) {
+  if (out == nullptr) return DCG_E_ARG;
+  *out = nullptr;
+  if (n < 1 || k < 1 || k > kMaxK || L < k || k + L > kMaxZ) return DCG_E_ARG;
+  const RecycleLayout R = recycle_layout(n, k, L);
+  if (workspace == nullptr || ws_bytes < R.total) return DCG_E_WORKSPACE;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return DCG_E_WORKSPACE;
+  dcg_recycle_s *rc = new (std::nothrow) dcg_recycle_s;
+  if (rc == nullptr) return DCG_E_ARG;
+  std::memset(static_cast<void *>(rc), 0, sizeof(*rc));
+  char *b = static_cast<char *>(workspace);
+  rc->n = n;
+  rc->k = k;
+  rc->L = L;
+  rc->Z = reinterpret_cast<double *>(b + R.Z);
+  rc->AZ = reinterpret_cast<double *>(b + R.AZ);
+  rc->Wt = reinterpret_cast<double *>(b + R.Wt);
+  rc->AWt = reinterpret_cast<double *>(b + R.AWt);
+  rc->F = reinterpret_cast<double *>(b + R.F);
+  rc->G = reinterpret_cast<double *>(b + R.G);
+  rc->U = reinterpret_cast<double *>(b + R.U);
+  rc->eigw = reinterpret_cast<double *>(b + R.eigw);
+  rc->M = reinterpret_cast<double *>(b + R.M);
+  rc->Minv = reinterpret_cast<double *>(b + R.Minv);
+  rc->Mwork = reinterpret_cast<double *>(b + R.Mwork);
+  rc->N = reinterpret_cast<double *>(b + R.N);
+  rc->small = reinterpret_cast<double *>(b + R.small);
+  rc->info = reinterpret_cast<int *>(b + R.info);
+  rc->gemm = reinterpret_cast<double *>(b + R.gemm);
+  *out = rc;
+  return DCG_OK;
+}
+
+int dcg_recycle_set_W(dcg_recycle_t rc, const double *W, int kw) {
+  if (rc == nullptr || kw < 0 || kw > rc->k || (kw > 0 && W == nullptr)) return DCG_E_ARG;
+  if (kw > 0 && hipMemcpy(rc->Z, W, size_t(rc->n) * kw * 8, hipMemcpyDeviceToDevice) != hipSuccess)
+    return DCG_E_HIP;
+  rc->k_used = kw;
+  rc->aw_state = 0;
+  rc->n_theta = 0;
+  return DCG_OK;
+}
+
+int dcg_recycle_get_W(dcg_recycle_t rc, double *W_out, int *k_used) {
+  if (rc == nullptr) return DCG_E_ARG;
+  if (k_used != nullptr) *k_used = rc->k_used;
+  if (W_out != nullptr && rc->k_used > 0 &&
+      hipMemcpy(W_out, rc->Z, size_t(rc->n) * rc->k_used * 8, hipMemcpyDeviceToDevice) != hipSuccess)
+    return DCG_E_HIP;
+  return DCG_OK;
+}
+
+int dcg_recycle_get_AW(dcg_recycle_t rc, double *AW_out) {
+  if (rc == nullptr || AW_out == nullptr || rc->aw_state != 1) return DCG_E_ARG;
+  if (rc->k_used > 0 &&
+      hipMemcpy(AW_out, rc->AZ, size_t(rc->n) * rc->k_used * 8, hipMemcpyDeviceToDevice) != hipSuccess)
+    return DCG_E_HIP;
+  return DCG_OK;
+}
+
+int dcg_recycle_get_theta(dcg_recycle_t rc, double *theta_out, int *count) {
+  if (rc == nullptr) return DCG_E_ARG;
+  if (count != nullptr) *count = rc->n_theta;
+  if (theta_out != nullptr)
+    for (int i = 0; i < rc->n_theta; ++i) theta_out[i] = rc->theta[i];
+  return DCG_OK;
+}
+
+void dcg_recycle_destroy(dcg_recycle_t rc) { delete rc; }
+
+size_t dcg_solve_workspace_bytes(int64_t n, int k, int L) {
+  (void)k;
+  (void)L;
+  if (n < 1) return 0;
+  return solve_layout(n).total;
+}
+
+int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_t rc,
+              const dcg_params *p, dcg_stats *st, void *ws, size_t ws_bytes) {
+  dcg_stats local;
+  std::memset(&local, 0, sizeof(local));
+  if (st == nullptr) st = &local;
+  std::memset(st, 0, sizeof(*st));
+  if (op == nullptr || b == nullptr || x == nullptr || p == nullptr) return st->status = DCG_E_ARG;
+  if (!(p->tol >= 0.0) || p->check_every < 0) return st->status = DCG_E_ARG;
+  if (rc != nullptr && rc->n != op->g.n) return st->status = DCG_E_ARG;
+  if (ws == nullptr || ws_bytes < solve_layout(op->g.n).total) return st->status = DCG_E_WORKSPACE;
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return st->status = DCG_E_WORKSPACE;
+  const auto t0 = Clock::now();
+  hipStream_t s = op->stream;
+  const int64_t n = op->g.n;
+  SolveBuffers B = solve_buffers(ws, n);
+  if (!p->refine) {
+    InnerResult R;
+    int rcode = inner_solve(op, b, x, x_given, rc, p, p->tol, ws, &R);
+    if (rcode != DCG_OK) return st->status = rcode;
+    st->iters = R.iters;
+    st->matvecs = R.matvecs;
+    st->k_used = R.k_used;
+    st->k_next = R.k_next;
+    st->rel_res_recursive = R.relres;
+    st->t_init_ms = R.t_init;
+    st->t_loop_ms = R.t_loop;
+    st->t_refresh_ms = R.t_refresh;
+    st->status = R.status;
+    st->sweeps_timed = R.sweeps_timed;
+    st->t_sweeps_ms = R.t_sweeps;
+    if (p->true_residual) {
+      rcode = true_residual(op, b, x, 0, B, &st->rel_res_true);
+      if (rcode != DCG_OK) return st->status = rcode;
+      st->matvecs += 1;
+    }
+    st->t_total_ms = ms_since(t0);
+    return st->status;
+  }
+  // ---- iterative refinement: r_t = b - A64 x_t, A~ d_t = r_t, x += d_t
+  double *rhs = B.tmp1, *delta = B.tmp2;
+  if (!x_given) HIPCHK(hipMemsetAsync(x, 0, size_t(n) * 8, s));
+  const int outer_max = p->refine_max > 0 ? p->refine_max : 20;
+  double rel = 0.0;
+  int status = DCG_NOT_CONVERGED;
+  for (int t = 0; t <= outer_max; ++t) {
+    int rcode = matvec_exact(op, x, B.tmp3, 1);
+    if (rcode != DCG_OK) return st->status = rcode;
+    st->matvecs_exact += 1;
+    HIPCHK(hipMemsetAsync(B.counter + 2, 0, sizeof(unsigned), s));
+    hipLaunchKernelGGL(residual_norms, dim3(static_cast<unsigned>(std::min<int64_t>(kRedBlocks, cdiv(n, 256)))),
+                       dim3(256), 0, s, b, B.tmp3, n, rhs, B.part, B.counter + 2, B.S->cvec);
+    double h[2];
+    HIPCHK(hipMemcpyAsync(h, B.S->cvec, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    rel = (h[1] > 0.0) ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+    if (!std::isfinite(rel)) { status = DCG_E_NONFINITE; break; }
+    if (rel <= p->tol) { status = DCG_OK; break; }
+    if (t == outer_max) break;
+    InnerResult R;
+    rcode = inner_solve(op, rhs, delta, 0, rc, p, p->inner_tol, ws, &R);
+    if (rcode != DCG_OK) return st->status = rcode;
+    st->iters += R.iters;
+    st->matvecs += R.matvecs;
+    if (t == 0) st->k_used = R.k_used;
+    st->k_next = R.k_next;
+    st->t_init_ms += R.t_init;
+    st->t_loop_ms += R.t_loop;
+    st->t_refresh_ms += R.t_refresh;
+    st->sweeps_timed += R.sweeps_timed;
+    st->t_sweeps_ms += R.t_sweeps;
+    st->rel_res_recursive = R.relres;
+    st->outer_steps += 1;
+    if (R.status < 0) { status = R.status; break; }
+    enqueue_block_axpy(s, x, delta, 1.0, n);
+  }
+  st->rel_res_true = rel;
+  st->status = status;
+  st->t_total_ms = ms_since(t0);
+  return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point the
+header declares, sizes workspaces and rejects invalid arguments before any
+GPU call."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dcg.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dcg_[A-Za-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1706_00241_amd as dcg
+    if not os.path.exists(dcg.LIB_PATH):
+        pytest.fail("libdcg.so is not built (run python -m paper_1706_00241_amd.build)")
+    return dcg.load()
+
+
+def test_exports_every_declared_symbol(L):
+    import paper_1706_00241_amd as dcg
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(dcg.EXPORTED)
+
+
+def test_workspace_queries(L):
+    assert L.dcg_operator_workspace_bytes(65536, 32, 1) > 65536 * 32 * 8
+    assert L.dcg_operator_workspace_bytes(0, 32, 1) == 0
+    assert L.dcg_operator_workspace_bytes(100, 65, 1) == 0
+    assert L.dcg_operator_workspace_bytes(100, 8, 7) == 0
+    assert L.dcg_recycle_workspace_bytes(1000, 8, 12) >= 1000 * 20 * 8 * 2
+    assert L.dcg_recycle_workspace_bytes(1000, 8, 4) == 0       # L < k
+    assert L.dcg_recycle_workspace_bytes(1000, 65, 100) == 0    # k too large
+    assert L.dcg_solve_workspace_bytes(1000, 0, 0) > 0
+
+
+def test_argument_validation_without_gpu(L):
+    import paper_1706_00241_amd as dcg
+    h = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(1024)
+    # null X / bad sizes / bad kernel: rejected before any HIP call
+    assert L.dcg_create_operator(None, 10, 3, 0, 1.0, 1.0, 0.1, 0, buf, 1024, None, ctypes.byref(h)) == -1
+    assert L.dcg_create_operator(buf, 0, 3, 0, 1.0, 1.0, 0.1, 0, buf, 1024, None, ctypes.byref(h)) == -1
+    assert L.dcg_create_operator(buf, 10, 3, 9, 1.0, 1.0, 0.1, 0, buf, 1024, None, ctypes.byref(h)) == -1
+    assert L.dcg_create_operator(buf, 10, 3, 0, -1.0, 1.0, 0.1, 0, buf, 1024, None, ctypes.byref(h)) == -1
+    assert L.dcg_create_operator(buf, 10, 3, 0, 1.0, 1.0, -0.1, 0, buf, 1024, None, ctypes.byref(h)) == -1
+    # workspace too small
+    assert L.dcg_create_operator(buf, 10, 3, 0, 1.0, 1.0, 0.1, 0, buf, 16, None, ctypes.byref(h)) == -6
+    assert L.dcg_recycle_create(10, 8, 4, buf, 1024, ctypes.byref(h)) == -1
+    p = dcg.Params(tol=1e-6)
+    st = dcg.Stats()
+    assert L.dcg_solve(None, None, None, 0, None, ctypes.byref(p), ctypes.byref(st), None, 0) == -1
+    assert L.dcg_set_hyper(None, 1.0, 1.0, 1.0) == -1
+    assert L.dcg_matvec(None, None, None, 1) == -1
+    assert L.dcg_status_string(-2).decode().startswith("operator not positive")
+    assert "gfx950" in L.dcg_version().decode()

@@ -1,0 +1,315 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (derivation in DESIGN.md, "Parity tolerances"):
+* low-precision products: |y_gpu - y_ref|_i <= 2e-5 * (|A| |v|)_i, with y_ref
+  the oracle's FP64 product on the *same rounded points* (the operator is the
+  exact kernel matrix of the rounded points; the only error left is FP32
+  evaluation and accumulation);
+* the FP64 product: 1e-12 relative to (|A| |v|)_i;
+* solves: the oracle's true residual of the GPU solution is at most
+  tol + 2 * floor, floor = |(A_gpu - A_ref) x| / |b| measured per case.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import cg as OC
+from oracle import kernels as OK
+from oracle import precision as OP
+from oracle import ritz as ORZ
+from oracle import sequence as OS
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float64), device="cuda")
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _points(n, d, seed, dist="normal"):
+    g = np.random.default_rng(seed)
+    if dist == "uniform":
+        return g.uniform(-1, 1, (n, d))
+    return g.standard_normal((n, d))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kern", [0, 1, 2])
+@pytest.mark.parametrize("n,d,m", [(1, 3, 1), (200, 3, 1), (777, 8, 2), (1500, 16, 5),
+                                   (2500, 32, 1), (600, 33, 3), (300, 1, 1)])
+def test_matvec_parity(lib, prec, kern, n, d, m):
+    X = _points(n, d, seed=n + d)
+    ell = max(0.5, workloads.median_distance(X)) if n > 1 else 1.0
+    s2, sigma2 = 1.3, 1e-2
+    op = lib.Operator(_dev(X), kern, ell, s2, sigma2, prec=prec)
+    g = np.random.default_rng(5)
+    V = g.standard_normal((n, m))
+    Y = _np(op.matvec(_dev(V)))
+    Xr = OP.round_points(X, OP.PREC_BF16 if prec == 1 else OP.PREC_FP32)
+    A = OK.operator(Xr, kern, ell, s2, sigma2)
+    ref = A @ V
+    scale = np.abs(A) @ np.abs(V)
+    err = np.abs(Y - ref) / scale
+    assert err.max() <= 2e-5, (err.max(), np.unravel_index(err.argmax(), err.shape))
+
+
+@pytest.mark.parametrize("kern", [0, 1, 2])
+def test_matvec_exact_parity(lib, kern):
+    n, d = 1100, 7
+    X = _points(n, d, seed=3)
+    ell = workloads.median_distance(X)
+    op = lib.Operator(_dev(X), kern, ell, 0.9, 1e-3, prec=1)
+    V = np.random.default_rng(1).standard_normal((n, 3))
+    Y = _np(op.matvec_exact(_dev(V)))
+    A = OK.operator(X, kern, ell, 0.9, 1e-3)
+    err = np.abs(Y - A @ V) / (np.abs(A) @ np.abs(V))
+    assert err.max() <= 1e-12
+
+
+def test_matvec_diagonal_exact(lib):
+    # one point: A = s2 + sigma2 exactly (the distance to itself is zero)
+    for kern in (0, 1, 2):
+        for prec in (0, 1):
+            op = lib.Operator(_dev([[0.3, -1.7, 2.2]]), kern, 0.7, 1.7, 0.25, prec=prec)
+            y = _np(op.matvec(_dev([2.0])))
+            assert abs(y[0] - 2.0 * (1.7 + 0.25)) <= 1e-6 * 3.9
+
+
+def test_matvec_full_size_sampled_rows(lib):
+    """n = 65536, d = 32, Matern-5/2, bf16: the launch configuration of the
+    benchmark, checked on 48 sampled rows computed one by one."""
+    w = workloads.bf16_shift()
+    X = w["X"]
+    n = X.shape[0]
+    op = lib.Operator(_dev(X), w["kernel"], w["ell"], 1.0, w["sigma2s"][0], prec=1)
+    v = np.random.default_rng(11).standard_normal(n)
+    y = _np(op.matvec(_dev(v)))
+    Xr = OP.round_bf16(X)
+    rows = np.random.default_rng(12).choice(n, 48, replace=False)
+    for i in rows:
+        krow = OK.gram(Xr[i:i + 1], w["kernel"], w["ell"], 1.0, Xr)[0]
+        ref = krow @ v + w["sigma2s"][0] * v[i]
+        scale = np.abs(krow) @ np.abs(v) + w["sigma2s"][0] * abs(v[i])
+        assert abs(y[i] - ref) <= 2e-5 * scale, (i, y[i], ref)
+
+
+def _floor(op, A, x, b):
+    """|(A_gpu - A_ref) x| / |b|: how far the GPU operator is from the oracle's."""
+    ax_gpu = _np(op.matvec(_dev(x)))
+    return np.linalg.norm(ax_gpu - A @ x) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("prec,tol,its_tol", [(3, 1e-8, 2), (0, 1e-5, 0)])
+def test_plain_cg_parity(lib, prec, tol, its_tol):
+    """Plain CG, n=1024 RBF system: FP64 operator at tol 1e-8 (iteration
+    counts within 2 of the oracle), FP32 operator at 1e-5 (above its floor)."""
+    w = workloads.small()
+    X = w["X"]
+    ell = w["ells"][0]
+    Xr = OP.round_fp32(X) if prec == 0 else X
+    A = OK.operator(Xr, w["kernel"], ell, 1.0, w["sigma2"])
+    b = A @ w["xstar"] + w["noise"][0]
+    op = lib.Operator(_dev(X), w["kernel"], ell, 1.0, w["sigma2"], prec=prec)
+    x, st = lib.solve(op, _dev(b), tol=tol, true_residual=True)
+    x = _np(x)
+    ref = OC.cg(A, b, tol=tol)
+    assert st["status"] == 0
+    assert abs(st["iters"] - ref.iters) <= max(its_tol, 0.1 * ref.iters), (st["iters"], ref.iters)
+    fl = _floor(op, A, x, b)
+    res = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    assert res <= tol + 2 * fl, (res, fl)
+    assert st["rel_res_recursive"] <= tol
+    if prec == 3:
+        np.testing.assert_allclose(x, ref.x, rtol=0, atol=1e-6 * np.abs(ref.x).max())
+
+
+def test_cg_graph_and_eager_bitwise_equal(lib):
+    w = workloads.small(n=700)
+    op = lib.Operator(_dev(w["X"]), 0, 1.0, 1.0, 1e-2, prec=0)
+    b = _dev(np.random.default_rng(2).standard_normal(700))
+    x1, s1 = lib.solve(op, b, tol=1e-9, use_graph=True)
+    x2, s2 = lib.solve(op, b, tol=1e-9, use_graph=False, check_every=3)
+    x3, s3 = lib.solve(op, b, tol=1e-9, use_graph=True)
+    assert s1["iters"] == s2["iters"] == s3["iters"]
+    assert torch.equal(x1, x2) and torch.equal(x1, x3)
+
+
+@pytest.mark.parametrize("prec,tol,th_rtol", [(3, 1e-8, 1e-6), (0, 1e-6, 2e-3)])
+def test_defcg_sequence_parity_small(lib, prec, tol, th_rtol):
+    """The n=1024 five-system sequence: def-CG(8, 12) against the oracle's
+    sequence (iteration counts, harmonic Ritz values, residuals)."""
+    w = workloads.small()
+    X = w["X"]
+    n = X.shape[0]
+    Xr = OP.round_fp32(X) if prec == 0 else X
+    mats = [OK.operator(Xr, w["kernel"], ell, 1.0, w["sigma2"]) for ell in w["ells"]]
+    bs = [A @ w["xstar"] + w["noise"][i] for i, A in enumerate(mats)]
+    ref = OS.solve_sequence(mats, bs, k=8, L=12, tol=tol)
+    op = lib.Operator(_dev(X), w["kernel"], w["ells"][0], 1.0, w["sigma2"], prec=prec)
+    rc = lib.Recycle(n, 8, 12)
+    its = []
+    for i, (ell, A, b) in enumerate(zip(w["ells"], mats, bs)):
+        op.set_hyper(ell, 1.0, w["sigma2"])
+        x, st = lib.solve(op, _dev(b), rc=rc, tol=tol)
+        x = _np(x)
+        assert st["status"] == 0
+        its.append(st["iters"])
+        fl = _floor(op, A, x, b)
+        res = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+        assert res <= tol + 2 * fl
+        # harmonic Ritz values of the extraction (largest first)
+        th = np.array(rc.theta())
+        assert len(th) == 8
+        np.testing.assert_allclose(th, ref[i].theta, rtol=th_rtol)
+    ref_its = [r.iters for r in ref]
+    # FP64 operator: the same iteration within rounding; FP32 operator: its
+    # evaluation error (~1e-7 of |A||p|) slows CG by a few percent
+    slack, frac = (2, 0.0) if prec == 3 else (3, 0.1)
+    for a, c in zip(its, ref_its):
+        assert abs(a - c) <= max(slack, frac * c), (its, ref_its)
+    # recycling pays: fewer steps than plain CG on the later systems
+    plain = OS.solve_sequence(mats, bs, k=8, L=12, tol=tol, recycle=False)
+    assert sum(its[1:]) < sum(p.iters for p in plain[1:])
+
+
+def test_recycled_basis_is_A_orthonormal(lib):
+    w = workloads.small(n=900)
+    X = w["X"][:900]
+    Xr = OP.round_fp32(X)
+    A = OK.operator(Xr, 0, 1.0, 1.0, 1e-2)
+    op = lib.Operator(_dev(X), 0, 1.0, 1.0, 1e-2, prec=0)
+    rc = lib.Recycle(900, 8, 12)
+    b = np.random.default_rng(4).standard_normal(900)
+    lib.solve(op, _dev(b), rc=rc, tol=1e-10)
+    W = _np(rc.get_W())
+    assert W.shape == (900, 8)
+    M = W.T @ A @ W
+    np.testing.assert_allclose(M, np.eye(8), atol=1e-5)
+    # oracle extraction from the same directions: compare the spanned spaces
+    ref = OC.cg(A, b, tol=1e-10, L=12)
+    Wr, _, th, _ = ORZ.harmonic_ritz(ref.P, ref.AP, 8)
+    Qa, _ = np.linalg.qr(W)
+    Qb, _ = np.linalg.qr(Wr)
+    s = np.linalg.svd(Qa.T @ Qb, compute_uv=False)
+    assert s.min() > 1 - 1e-4
+
+
+@pytest.mark.parametrize("prec,sigma2,tol", [(3, 1e-3, 1e-8), (0, 1e-2, 1e-6)])
+def test_exact_eigenvector_deflation(lib, prec, sigma2, tol):
+    """W = exact eigenvectors of the 8 largest eigenvalues (oracle eigh):
+    def-CG needs fewer steps than plain CG, as many as the oracle def-CG."""
+    n = 800
+    X = _points(n, 4, seed=21)
+    ell = workloads.median_distance(X)
+    Xr = OP.round_fp32(X) if prec == 0 else X
+    A = OK.operator(Xr, 0, ell, 1.0, sigma2)
+    lam, Q = np.linalg.eigh(A)
+    W = Q[:, -8:]
+    b = np.random.default_rng(3).standard_normal(n)
+    op = lib.Operator(_dev(X), 0, ell, 1.0, sigma2, prec=prec)
+    rc = lib.Recycle(n, 8, 12)
+    rc.set_W(_dev(W))
+    x, st = lib.solve(op, _dev(b), rc=rc, tol=tol)
+    plain_x, plain = lib.solve(op, _dev(b), tol=tol)
+    ref = OC.defcg(A, b, W=W, tol=tol)
+    ref_plain = OC.cg(A, b, tol=tol)
+    assert st["status"] == 0 and st["k_used"] == 8
+    assert st["iters"] < plain["iters"]
+    if prec == 3:
+        # FP64 operator: the same iteration up to rounding (kappa ~ 5e5)
+        assert abs(st["iters"] - ref.iters) <= max(3, 0.02 * ref.iters), (st["iters"], ref.iters)
+        assert abs(plain["iters"] - ref_plain.iters) <= max(3, 0.02 * ref_plain.iters)
+    else:
+        # FP32 operator: inexact products delay CG on this ill-conditioned
+        # system (kappa ~ 5e4; the oracle with 1e-8 |A||p| noise needs 1.8x
+        # the exact count); bound the delay
+        assert st["iters"] <= 1.5 * ref.iters, (st["iters"], ref.iters)
+    xn = _np(x)
+    assert np.linalg.norm(b - A @ xn) / np.linalg.norm(b) <= tol + 2 * _floor(op, A, xn, b)
+
+
+def test_refinement_reaches_1e8_bf16(lib):
+    """Precision form at small size: bf16 distances, FP64 refinement to 1e-8."""
+    w = workloads.bf16_shift(n=3000)
+    X = w["X"]
+    A64 = OK.operator(X, w["kernel"], w["ell"], 1.0, w["sigma2s"][0])
+    b = w["b"]
+    op = lib.Operator(_dev(X), w["kernel"], w["ell"], 1.0, w["sigma2s"][0], prec=1)
+    rc = lib.Recycle(3000, 16, 24)
+    x, st = lib.solve(op, _dev(b), rc=rc, tol=1e-8, refine=True, inner_tol=1e-4)
+    x = _np(x)
+    res = np.linalg.norm(b - A64 @ x) / np.linalg.norm(b)
+    assert st["status"] == 0
+    assert res <= 1.05e-8, res
+    assert abs(res - st["rel_res_true"]) <= 1e-3 * res + 1e-15
+    x_ref = np.linalg.solve(A64, b)
+    err_A = np.sqrt((x - x_ref) @ A64 @ (x - x_ref) / (x_ref @ A64 @ x_ref))
+    assert err_A <= 1e-7
+
+
+def test_sigma_shift_sequence_reuses_AW(lib):
+    """sigma^2-only changes: AW updated by the shift, no block product."""
+    w = workloads.bf16_shift(n=2048, systems=3)
+    op = lib.Operator(_dev(w["X"]), w["kernel"], w["ell"], 1.0, w["sigma2s"][0], prec=1)
+    rc = lib.Recycle(2048, 16, 24)
+    Xr = OP.round_bf16(w["X"])
+    for i, s2 in enumerate(w["sigma2s"]):
+        op.set_hyper(w["ell"], 1.0, s2)
+        x, st = lib.solve(op, _dev(w["b"]), rc=rc, tol=1e-6)
+        if i > 0:
+            assert st["k_used"] == 16
+            # one product for r_0 after the deflated start, no AW recompute
+            assert st["matvecs"] == st["iters"] + 1
+        A = OK.operator(Xr, w["kernel"], w["ell"], 1.0, s2)
+        x = _np(x)
+        fl = _floor(op, A, x, w["b"])
+        assert np.linalg.norm(w["b"] - A @ x) / np.linalg.norm(w["b"]) <= 1e-6 + 2 * fl
+
+
+def test_deterministic(lib):
+    w = workloads.fp32_walk(n=3000, systems=2)
+    def run():
+        op = lib.Operator(_dev(w["X"]), 0, w["ells"][0], 1.0, 1e-2, prec=0)
+        rc = lib.Recycle(3000, 16, 24)
+        xs = []
+        for ell in w["ells"]:
+            op.set_hyper(ell, 1.0, 1e-2)
+            x, _ = lib.solve(op, _dev(w["b"]), rc=rc, tol=1e-6)
+            xs.append(x.clone())
+        return xs, rc.get_W().clone()
+    a, Wa = run()
+    b, Wb = run()
+    for u, v in zip(a, b):
+        assert torch.equal(u, v)
+    assert torch.equal(Wa, Wb)
+
+
+def test_edge_cases(lib):
+    # converges before L directions are stored: k_next <= stored directions
+    X = _points(40, 2, seed=1)
+    op = lib.Operator(_dev(X), 0, 1.0, 1.0, 1.0, prec=0)
+    rc = lib.Recycle(40, 8, 12)
+    x, st = lib.solve(op, _dev(np.ones(40)), rc=rc, tol=1e-3)
+    assert st["status"] == 0 and st["k_next"] <= min(8, st["iters"])
+    # zero right-hand side: x = 0 at once
+    x, st = lib.solve(op, _dev(np.zeros(40)), tol=1e-8)
+    assert st["iters"] == 0 and float(x.abs().max()) == 0.0
+    # NaN in the points
+    Xn = X.copy()
+    Xn[3, 1] = np.nan
+    with pytest.raises(lib.DcgError) as e:
+        lib.Operator(_dev(Xn), 0, 1.0, 1.0, 1.0)
+    assert e.value.status == -3
+    # bad hyperparameters
+    with pytest.raises(lib.DcgError):
+        op.set_hyper(-1.0, 1.0, 1.0)
+    # max_iter reached: not converged, x still returned
+    x, st = lib.solve(op, _dev(np.ones(40)), tol=1e-14, max_iter=2)
+    assert st["status"] == 1 and st["iters"] == 2
