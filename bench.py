@@ -51,6 +51,10 @@ def parse():
                     help="ell = 0.5 as written (an almost diagonal operator)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--prec", choices=["bf16", "bf16x2", "fp32"], default="bf16",
+                    help="operator precision of the inner solves")
+    ap.add_argument("--inner-tol", type=float, default=1e-4,
+                    help="relative tolerance of each inner (bf16-operator) solve")
     return ap.parse_args()
 
 
@@ -96,11 +100,12 @@ def main():
     dev = torch.device("cuda:0")
     X = torch.as_tensor(w["X"], device=dev)
     b = torch.as_tensor(w["b"], device=dev)
-    op = dcg.Operator(X, w["kernel"], w["ell"], 1.0, w["sigma2s"][0], prec=dcg.PREC_BF16)
+    prec = {"bf16": dcg.PREC_BF16, "bf16x2": dcg.PREC_BF16X2, "fp32": dcg.PREC_FP32}[args.prec]
+    op = dcg.Operator(X, w["kernel"], w["ell"], 1.0, w["sigma2s"][0], prec=prec)
     rc = dcg.Recycle(n, w["k"], w["L"], device=dev)
     ws = dcg.SolveWorkspace(n, dev)
     x = torch.empty(n, dtype=torch.float64, device=dev)
-    kw = dict(tol=w["tol"], refine=True, inner_tol=w["inner_tol"], ws=ws, out=x,
+    kw = dict(tol=w["tol"], refine=True, inner_tol=args.inner_tol, ws=ws, out=x,
               check_every=8)
 
     for i in range(args.warmup):

@@ -49,7 +49,14 @@ enum dcg_kernel { DCG_RBF = 0, DCG_MATERN32 = 1, DCG_MATERN52 = 2 };
 /* Compute precision of the distance GEMM (points are rounded to it once, at
  * operator creation; the operator is the exact kernel matrix of the rounded
  * points evaluated with FP32 accumulation).  FP64 is the exact operator. */
-enum dcg_prec { DCG_PREC_FP32 = 0, DCG_PREC_BF16 = 1, DCG_PREC_FP64 = 3 };
+enum dcg_prec {
+  DCG_PREC_FP32 = 0,    /* fp32 points, fp32 MFMA                              */
+  DCG_PREC_BF16 = 1,    /* bf16 points (8 significant bits), bf16 MFMA         */
+  DCG_PREC_BF16X2 = 2,  /* points as a pair hi + lo of bf16 (16 significant
+                           bits); the distance GEMM takes the four bf16
+                           products hi.hi, hi.lo, lo.hi, lo.lo on MFMA         */
+  DCG_PREC_FP64 = 3     /* exact FP64 operator                                 */
+};
 
 enum dcg_status {
   DCG_OK = 0,
@@ -80,6 +87,9 @@ typedef struct {
                           product; always done when refine = 1)              */
   int profile;         /* 1: time every matvec sweep with HIP events on the
                           operator's stream (iterations run without graphs) */
+  int refresh_every;   /* refine = 1 only: 0 extracts W' after the first inner
+                          solve of each dcg_solve call (the operator does not
+                          change between its inner solves), 1 after every one */
 } dcg_params;
 
 /* Per-solve statistics (host struct, filled by dcg_solve). */

@@ -13,11 +13,12 @@ library implements, restated here from the number-format definitions:
 * bf16: bfloat16 = the upper 16 bits of binary32 (8 exponent bits, 7 stored
   mantissa bits).  Rounding is to nearest, ties to even, applied to the FP64
   value directly (one rounding, never via fp32 first).
+* bf16x2: the pair hi + lo with hi = bf16(x), lo = bf16(x - hi).
 """
 
 import numpy as np
 
-PREC_FP32, PREC_BF16, PREC_FP64 = 0, 1, 3
+PREC_FP32, PREC_BF16, PREC_BF16X2, PREC_FP64 = 0, 1, 2, 3
 
 
 def round_fp32(x):
@@ -45,12 +46,26 @@ def round_bf16(x):
     return out
 
 
+def round_bf16x2(x):
+    """A pair of bfloat16 values hi + lo: hi = bf16(x), lo = bf16(x - hi).
+
+    The pair carries 16 significant bits (|x - (hi + lo)| <= 2^-17 |x| up to
+    the bf16 spacing of lo), the representation of the split-bf16 operator.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    hi = round_bf16(x)
+    lo = round_bf16(x - hi)
+    return hi + lo
+
+
 def round_points(X, prec):
     """Points in the operator's compute precision (returned as FP64)."""
     if prec == PREC_FP32:
         return round_fp32(X)
     if prec == PREC_BF16:
         return round_bf16(X)
+    if prec == PREC_BF16X2:
+        return round_bf16x2(X)
     if prec == PREC_FP64:
         return np.asarray(X, dtype=np.float64).copy()
     raise ValueError(f"unknown precision {prec}")

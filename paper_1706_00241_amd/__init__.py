@@ -24,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdcg.so")
 
 RBF, MATERN32, MATERN52 = 0, 1, 2
-PREC_FP32, PREC_BF16, PREC_FP64 = 0, 1, 3
+PREC_FP32, PREC_BF16, PREC_BF16X2, PREC_FP64 = 0, 1, 2, 3
 STATUS = {0: "ok", 1: "not converged", -1: "invalid argument", -2: "not SPD",
           -3: "non-finite", -4: "W rank deficient", -5: "HIP error",
           -6: "workspace"}
@@ -42,7 +42,7 @@ class Params(ctypes.Structure):
                 ("check_every", ctypes.c_int), ("refine", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("refine_max", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("true_residual", ctypes.c_int),
-                ("profile", ctypes.c_int)]
+                ("profile", ctypes.c_int), ("refresh_every", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -295,7 +295,7 @@ class SolveWorkspace:
 
 def solve(op, b, x0=None, rc=None, tol=1e-6, max_iter=0, L=0, select_largest=True,
           check_every=8, refine=False, inner_tol=1e-4, refine_max=20, use_graph=True,
-          true_residual=False, profile=False, ws=None, out=None):
+          true_residual=False, profile=False, refresh_every=False, ws=None, out=None):
     """Deflated CG (Algorithm 1) for A x = b; returns (x, stats dict).
 
     rc=None runs plain CG; with a Recycle the solve uses its W and leaves the
@@ -317,7 +317,7 @@ def solve(op, b, x0=None, rc=None, tol=1e-6, max_iter=0, L=0, select_largest=Tru
                select_largest=1 if select_largest else 0, check_every=int(check_every),
                refine=1 if refine else 0, inner_tol=float(inner_tol), refine_max=int(refine_max),
                use_graph=1 if use_graph else 0, true_residual=1 if true_residual else 0,
-               profile=1 if profile else 0)
+               profile=1 if profile else 0, refresh_every=1 if refresh_every else 0)
     st = Stats()
     with _ordered(op.stream):
         status = lib.dcg_solve(op.handle, b.data_ptr(), out.data_ptr(), x_given,

@@ -30,6 +30,9 @@ __device__ __forceinline__ double sum_partials(const ReduceArgs &A, int m, int64
   return s;
 }
 
+// Rows finished per block by cg_matvec_finish.
+constexpr int kCgRows = 256;
+
 // Scalars of one deflated-CG solve, resident on the device.
 struct SolveState {
   double rho;       // r_j^T r_j
@@ -56,7 +59,8 @@ struct CgArgs {
   int k;
   double *Z, *AZ;   // storage of p_j / A p_j for j < L at column koff + j
   int koff, L;
-  double *part, *part_h;
+  double *part, *part2, *part_h;  // partials: d (finish), rho (update_xr), [h|g]
+  int64_t nblk_q, nblk_xr;         // blocks of cg_matvec_finish / cg_update_xr
   unsigned *counter;
   double *hist_d, *hist_alpha, *hist_beta, *hist_res;
   int hist_cap;
@@ -67,6 +71,7 @@ struct CgArgs {
 __global__ void cg_matvec_finish(CgArgs a);
 __global__ void cg_update_xr(CgArgs a);
 __global__ void cg_update_p(CgArgs a);
+__global__ void cg_finalize(CgArgs a);
 __global__ void init_residual(const double *b, const double *Ax, double *x, double *r, int64_t n,
                               int x_given, double *part, unsigned *counter, SolveState *S);
 __global__ void defl_start(double *x, double *t, const double *W, const double *cvec, int64_t n,

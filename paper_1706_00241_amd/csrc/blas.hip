@@ -31,6 +31,41 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
   return s;  // valid in thread 0
 }
 
+// Block-wide sum broadcast to every thread (fixed reduction tree).
+__device__ __forceinline__ double block_sum_all(double v, double *lds) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) lds[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) s += lds[i];
+  __syncthreads();
+  return s;
+}
+
+// Sum of part[0 .. count) (stride 1) by the whole block, fixed order.
+__device__ __forceinline__ double block_sum_array(const double *part, int64_t count, double *lds) {
+  double s = 0.0;
+  for (int64_t b = threadIdx.x; b < count; b += blockDim.x) s += part[b];
+  return block_sum_all(s, lds);
+}
+
+// out[c] = sum_b part[c * count + b] for c < m (column-major partials), one
+// wave per column at a time; writes to LDS/global `out` (any address space).
+__device__ __forceinline__ void column_sums(const double *part, int64_t count, int m, double *out) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  for (int c = w; c < m; c += nw) {
+    double s = 0.0;
+    for (int64_t b = l; b < count; b += 64) s += part[int64_t(c) * count + b];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    if (l == 0) out[c] = s;
+  }
+}
+
 // Returns true in every thread of the block that finished last.  The block's
 // partial results must have been written before the call.
 __device__ __forceinline__ bool last_block(unsigned *counter) {
@@ -46,7 +81,7 @@ __device__ __forceinline__ bool last_block(unsigned *counter) {
   return is_last;
 }
 
-// mu = Minv h (k x k dense, row-major), by the first k threads.
+// mu = Minv h (k x k dense, row-major), threads of the block over rows.
 __device__ __forceinline__ void small_gemv(const double *Minv, const double *h, double *mu, int k) {
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
     double s = 0.0;
@@ -57,137 +92,199 @@ __device__ __forceinline__ void small_gemv(const double *Minv, const double *h, 
 
 // ------------------------------------------------------ CG iteration kernels
 
-// q = s2 * sum(partials) + sigma2 p; d = p^T q; alpha = rho / d.
-// Also stores p_{j-1} and q = A p_{j-1} into Z / AZ while j-1 < L.
+// q = s2 * sum(partials) + sigma2 p and the block partials of d = p^T q.
+// Also stores p_j and q = A p_j into Z / AZ while j < L.  A block finishes
+// kCgRows rows in groups of 64; each row's partials are split over 4 threads
+// (memory parallelism), then added in a fixed order.  No cross-block step:
+// the next kernel forms d and alpha itself from the block partials.
 __global__ __launch_bounds__(256) void cg_matvec_finish(CgArgs a) {
   SolveState *S = a.S;
   if (S->done) return;
+  __shared__ double seg[4][64];
   __shared__ double lds[8];
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int r = threadIdx.x & 63, sg = threadIdx.x >> 6;
+  const int j = S->iter;  // index of the direction being multiplied
   double pq = 0.0;
-  if (i < a.n) {
-    const double pi = a.p[i];
-    const double qi = (a.qdirect != nullptr)
-                          ? a.qdirect[i]
-                          : a.red.s2 * sum_partials(a.red, 0, i) + a.red.sigma2 * pi;
-    a.q[i] = qi;
-    pq = pi * qi;
-    const int j = S->iter;  // index of p being multiplied (p_j)
-    if (a.Z != nullptr && j < a.L) {
-      a.Z[int64_t(a.koff + j) * a.n + i] = pi;
-      a.AZ[int64_t(a.koff + j) * a.n + i] = qi;
-    }
-  }
-  const double bs = block_sum<256>(pq, lds);
-  if (threadIdx.x == 0) a.part[blockIdx.x] = bs;
-  if (last_block(a.counter)) {
-    if (threadIdx.x == 0) {
-      double d = 0.0;
-      for (unsigned b = 0; b < gridDim.x; ++b) d += a.part[b];
-      S->d = d;
-      if (!(d > 0.0) || !isfinite(d)) {
-        S->status = isfinite(d) ? DCG_E_NOT_SPD : DCG_E_NONFINITE;
-        S->done = 1;
-        S->alpha = 0.0;
+  for (int grp = 0; grp < kCgRows / 64; ++grp) {
+    const int64_t i = int64_t(blockIdx.x) * kCgRows + grp * 64 + r;
+    double s = 0.0;
+    if (i < a.n) {
+      if (a.qdirect != nullptr) {
+        s = (sg == 0) ? a.qdirect[i] : 0.0;
       } else {
-        S->alpha = S->rho / d;
+        const ReduceArgs &R = a.red;
+        for (int c = sg; c < R.nchunk; c += 4) s += R.prow[int64_t(c) * R.n_pad + i];
+        const int J = static_cast<int>(i / R.blk);
+        const int dlim = ((R.nb % 2) == 0 && J < R.nb / 2) ? R.dmax - 1 : R.dmax;
+        double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int dl = 1 + sg;
+        for (; dl + 12 <= dlim; dl += 16) {
+          s += R.pcol[int64_t(dl - 1) * R.n_pad + i];
+          s1 += R.pcol[int64_t(dl + 3) * R.n_pad + i];
+          s2 += R.pcol[int64_t(dl + 7) * R.n_pad + i];
+          s3 += R.pcol[int64_t(dl + 11) * R.n_pad + i];
+        }
+        for (; dl <= dlim; dl += 4) s += R.pcol[int64_t(dl - 1) * R.n_pad + i];
+        s = (s + s1) + (s2 + s3);
       }
-      const int j = S->iter;
-      if (j < a.L) {
-        a.hist_d[j] = d;
-        a.hist_alpha[j] = S->alpha;
-      }
-      *a.counter = 0;
     }
+    seg[sg][r] = s;
+    __syncthreads();
+    if (sg == 0 && i < a.n) {
+      const double tot = (seg[0][r] + seg[1][r]) + (seg[2][r] + seg[3][r]);
+      const double pi = a.p[i];
+      const double qi = (a.qdirect != nullptr) ? tot : a.red.s2 * tot + a.red.sigma2 * pi;
+      a.q[i] = qi;
+      pq += pi * qi;
+      if (a.Z != nullptr && j < a.L) {
+        a.Z[int64_t(a.koff + j) * a.n + i] = pi;
+        a.AZ[int64_t(a.koff + j) * a.n + i] = qi;
+      }
+    }
+    __syncthreads();
   }
+  const double bs = block_sum_all(pq, lds);
+  if (threadIdx.x == 0) a.part[blockIdx.x] = bs;
 }
 
-// x += alpha p; r -= alpha q; partial sums of rho' = r^T r, h = (AW)^T r and
-// g = W^T r.  Last block: the re-projection c = (W^T A W)^{-1} g of the
-// residual (zero in exact arithmetic, where W^T r_j = 0), and with
-// r' = r - AW c: mu = (W^T A W)^{-1} (AW)^T r', beta = |r'|^2 / |r|^2 and the
-// convergence test on |r'| / |b|.
+// d = p^T q from the partials of cg_matvec_finish (every block forms it, in
+// the same order), alpha = rho / d; x += alpha p; r -= alpha q; block partials
+// of rho' = r^T r, h = (AW)^T r and g = W^T r.
 __global__ __launch_bounds__(256) void cg_update_xr(CgArgs a) {
   SolveState *S = a.S;
   if (S->done) return;
   __shared__ double lds[8];
   __shared__ double rl[256];
+  const double d = block_sum_array(a.part, a.nblk_q, lds);
+  const bool bad = !(d > 0.0) || !isfinite(d);
+  const double alpha = bad ? 0.0 : S->rho / d;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S->d = d;
+    S->alpha = alpha;
+    const int j = S->iter;
+    if (j < a.L) {
+      a.hist_d[j] = d;
+      a.hist_alpha[j] = alpha;
+    }
+  }
   const int64_t i0 = int64_t(blockIdx.x) * 256;
   const int64_t i = i0 + threadIdx.x;
-  const double alpha = S->alpha;
   double rr = 0.0;
   double ri = 0.0;
   if (i < a.n) {
-    a.x[i] += alpha * a.p[i];
+    if (!bad) a.x[i] += alpha * a.p[i];
     ri = a.r[i] - alpha * a.q[i];
-    a.r[i] = ri;
+    if (!bad) a.r[i] = ri;
     rr = ri * ri;
   }
   rl[threadIdx.x] = ri;
-  const double bs = block_sum<256>(rr, lds);
-  if (threadIdx.x == 0) a.part[blockIdx.x] = bs;
-  // partial dots: wave w takes columns w, w+4, ... of [AW | W]; lanes cover
-  // the block's 4 x 64 rows.
+  const double bs = block_sum_all(rr, lds);
+  if (threadIdx.x == 0) a.part2[blockIdx.x] = bad ? (isfinite(d) ? -1.0 : -2.0) : bs;
+  // partial dots with the columns of [AW | W]: wave w takes columns w, w+4,
+  // ...; eight columns' loads are issued before their reductions
   const int k = a.k;
+  const int64_t nblk = gridDim.x;
   if (k > 0) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    for (int c = w; c < 2 * k; c += 4) {
-      const double *Y = (c < k) ? a.AW + int64_t(c) * a.n : a.W + int64_t(c - k) * a.n;
-      double s = 0.0;
+    for (int cb = w; cb < 2 * k; cb += 32) {
+      double sv[8];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int64_t ii = i0 + 64 * t + l;
-        if (ii < a.n) s += Y[ii] * rl[64 * t + l];
+      for (int u = 0; u < 8; ++u) {
+        const int c = cb + 4 * u;
+        sv[u] = 0.0;
+        if (c < 2 * k) {
+          const double *Y = (c < k) ? a.AW + int64_t(c) * a.n : a.W + int64_t(c - k) * a.n;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int64_t ii = i0 + 64 * t + l;
+            if (ii < a.n) sv[u] += Y[ii] * rl[64 * t + l];
+          }
+        }
       }
 #pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-      if (l == 0) a.part_h[int64_t(blockIdx.x) * 2 * k + c] = s;
+      for (int u = 0; u < 8; ++u) {
+        double v = sv[u];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+        const int c = cb + 4 * u;
+        if (l == 0 && c < 2 * k) a.part_h[int64_t(c) * nblk + blockIdx.x] = v;
+      }
     }
   }
-  if (last_block(a.counter)) {
-    __shared__ double hg[2 * kMaxK];   // h = (AW)^T r, then g = W^T r
-    __shared__ double cv[kMaxK];       // c = M^-1 g
-    __shared__ double nc[kMaxK];       // N c
-    __shared__ double hn[kMaxK];       // h - N c
-    for (int c = threadIdx.x; c < 2 * k; c += 256) {
-      double s = 0.0;
-      for (unsigned b = 0; b < gridDim.x; ++b) s += a.part_h[int64_t(b) * 2 * k + c];
-      hg[c] = s;
-    }
-    __syncthreads();
-    small_gemv(a.Minv, hg + k, cv, k);
-    __syncthreads();
-    small_gemv(a.N, cv, nc, k);
-    __syncthreads();
-    for (int c = threadIdx.x; c < k; c += 256) {
-      hn[c] = hg[c] - nc[c];
-      S->cvec[c] = cv[c];
-    }
-    __syncthreads();
-    small_gemv(a.Minv, hn, S->mu, k);
+}
+
+// One block: the sums of cg_update_xr's partials in a fixed order, then the
+// re-projection c = (W^T A W)^{-1} g of the residual (zero in exact
+// arithmetic, where W^T r_j = 0), and with r' = r - AW c:
+// mu = (W^T A W)^{-1} (AW)^T r', beta = |r'|^2 / |r|^2 and the convergence
+// test on |r'| / |b|.
+__global__ __launch_bounds__(256) void cg_finalize(CgArgs a) {
+  SolveState *S = a.S;
+  if (S->done) return;
+  __shared__ double lds[8];
+  __shared__ double hg[2 * kMaxK];   // h = (AW)^T r, then g = W^T r
+  __shared__ double cv[kMaxK];       // c = M^-1 g
+  __shared__ double nc[kMaxK];       // N c
+  __shared__ double hn[kMaxK];       // h - N c
+  __shared__ int flag;
+  const int k = a.k;
+  const int64_t nblk = a.nblk_xr;
+  if (threadIdx.x == 0) flag = 0;
+  __syncthreads();
+  // a negative partial marks p^T A p <= 0 (-1) or non-finite (-2)
+  for (int64_t b = threadIdx.x; b < nblk; b += 256) {
+    const double v = a.part2[b];
+    if (v < 0.0) atomicMax(&flag, v < -1.5 ? 2 : 1);
+  }
+  __syncthreads();
+  if (flag != 0) {
     if (threadIdx.x == 0) {
-      double rho_new = 0.0;
-      for (unsigned b = 0; b < gridDim.x; ++b) rho_new += a.part[b];
-      // |r - AW c|^2 = |r|^2 - 2 c^T h + c^T N c
-      double corr = 0.0;
-      for (int c = 0; c < k; ++c) corr += cv[c] * (nc[c] - 2.0 * hg[c]);
-      rho_new = fmax(rho_new + corr, 0.0);
-      const double beta = rho_new / S->rho;
-      S->beta = beta;
-      S->rho = rho_new;
-      const int j = S->iter;
-      if (j < a.L) a.hist_beta[j] = beta;
-      S->iter = j + 1;
-      const double rel = std::sqrt(rho_new) / S->bnorm;
-      S->relres = rel;
-      if (j + 1 < a.hist_cap) a.hist_res[j + 1] = rel;
-      if (!isfinite(rho_new)) {
-        S->status = DCG_E_NONFINITE;
-        S->done = 1;
-      } else if (rel <= a.tol || j + 1 >= a.max_iter) {
-        S->done = 1;
-      }
-      *a.counter = 0;
+      S->status = (flag == 2) ? DCG_E_NONFINITE : DCG_E_NOT_SPD;
+      S->done = 1;
+    }
+    return;
+  }
+  // column sums of [h | g]: thread c sums its column with 8 accumulators
+  for (int c = threadIdx.x; c < 2 * k; c += 256) {
+    const double *pc = a.part_h + int64_t(c) * nblk;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t b = 0;
+    for (; b + 8 <= nblk; b += 8)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += pc[b + u];
+    for (; b < nblk; ++b) acc[0] += pc[b];
+    hg[c] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  }
+  const double rho_raw = block_sum_array(a.part2, nblk, lds);   // includes barriers
+  small_gemv(a.Minv, hg + k, cv, k);
+  __syncthreads();
+  small_gemv(a.N, cv, nc, k);
+  __syncthreads();
+  for (int c = threadIdx.x; c < k; c += 256) {
+    hn[c] = hg[c] - nc[c];
+    S->cvec[c] = cv[c];
+  }
+  __syncthreads();
+  small_gemv(a.Minv, hn, S->mu, k);
+  if (threadIdx.x == 0) {
+    // |r - AW c|^2 = |r|^2 - 2 c^T h + c^T N c
+    double corr = 0.0;
+    for (int c = 0; c < k; ++c) corr += cv[c] * (nc[c] - 2.0 * hg[c]);
+    const double rho_new = fmax(rho_raw + corr, 0.0);
+    const double beta = rho_new / S->rho;
+    S->beta = beta;
+    S->rho = rho_new;
+    const int j = S->iter;
+    if (j < a.L) a.hist_beta[j] = beta;
+    S->iter = j + 1;
+    const double rel = std::sqrt(rho_new) / S->bnorm;
+    S->relres = rel;
+    if (j + 1 < a.hist_cap) a.hist_res[j + 1] = rel;
+    if (!isfinite(rho_new)) {
+      S->status = DCG_E_NONFINITE;
+      S->done = 1;
+    } else if (rel <= a.tol || j + 1 >= a.max_iter) {
+      S->done = 1;
     }
   }
 }
@@ -227,26 +324,24 @@ __global__ __launch_bounds__(256) void cg_update_p(CgArgs a) {
 // -------------------------------------------------- initialisation kernels
 
 // out[c] = sum_i Y[i, c] v[i] for c < m; with Minv != null, out = Minv * out.
-// Grid-stride over rows; last block sums the partials in block order.
+// Grid-stride over rows; partials column-major [c][block]; the last block
+// sums them in a fixed order.
 __global__ __launch_bounds__(256) void ts_dot(const double *Y, int64_t n, int m, const double *v,
                                               double *part, unsigned *counter, const double *Minv,
                                               double *out) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t nblk = gridDim.x;
   for (int c = w; c < m; c += 4) {
     double s = 0.0;
-    for (int64_t i = int64_t(blockIdx.x) * 64 + l; i < n; i += int64_t(gridDim.x) * 64)
+    for (int64_t i = int64_t(blockIdx.x) * 64 + l; i < n; i += nblk * 64)
       s += Y[int64_t(c) * n + i] * v[i];
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-    if (l == 0) part[int64_t(blockIdx.x) * m + c] = s;
+    if (l == 0) part[int64_t(c) * nblk + blockIdx.x] = s;
   }
   if (last_block(counter)) {
     __shared__ double h[kMaxZ];
-    for (int c = threadIdx.x; c < m; c += 256) {
-      double s = 0.0;
-      for (unsigned b = 0; b < gridDim.x; ++b) s += part[int64_t(b) * m + c];
-      h[c] = s;
-    }
+    column_sums(part, nblk, m, h);
     __syncthreads();
     if (Minv != nullptr) small_gemv(Minv, h, out, m);
     else
@@ -287,9 +382,8 @@ __global__ __launch_bounds__(256) void init_residual(const double *b, const doub
   const double bs = block_sum<256>(bb, lds);
   if (threadIdx.x == 0) part[blockIdx.x] = bs;
   if (last_block(counter)) {
+    const double s = block_sum_array(part, gridDim.x, lds);
     if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (unsigned k = 0; k < gridDim.x; ++k) s += part[k];
       S->bnorm = std::sqrt(s);
       *counter = 0;
     }
@@ -323,9 +417,8 @@ __global__ __launch_bounds__(256) void init_direction(const double *r, const dou
   const double bs = block_sum<256>(rr, lds);
   if (threadIdx.x == 0) part[blockIdx.x] = bs;
   if (last_block(counter)) {
+    const double s = block_sum_array(part, gridDim.x, lds);
     if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (unsigned b = 0; b < gridDim.x; ++b) s += part[b];
       S->rho = s;
       S->iter = 0;
       S->status = 0;

@@ -10,9 +10,6 @@
 
 namespace dcg {
 
-// Rows (and columns) per block of the symmetric matvec schedule.
-constexpr int kBlk1 = 256;   // single-vector kernel: 4 waves x 64 rows
-constexpr int kBlk4 = 128;   // 4-vector kernel:      4 waves x 32 rows
 constexpr int kMaxD = 64;
 constexpr int kMaxK = 64;          // columns of W
 constexpr int kMaxZ = 192;         // k + L (columns of Z)
@@ -57,8 +54,16 @@ struct MatvecPlan {
   int64_t grid;
 };
 
-MatvecPlan make_plan(int64_t n_pad, int mv);
-size_t matvec_partial_floats(int64_t n_pad, int mv);
+// Tile rows (of 32) per wave in the symmetric sweep: two for the
+// single-vector kernel unless its bf16 operands are wide (register budget).
+// The device kernel applies the same rule to its template parameters.
+inline int sweep_tile_rows(int mv, int prec, int ksteps) {
+  return (mv == 1 && (prec == DCG_PREC_FP32 || ksteps <= 5)) ? 2 : 1;
+}
+inline int sweep_blk(const Geometry &g, int mv) { return 128 * sweep_tile_rows(mv, g.prec, g.ksteps); }
+
+MatvecPlan make_plan(int64_t n_pad, int blk);
+size_t matvec_partial_floats(int64_t n_pad, int mv, int blk);
 
 }  // namespace dcg
 
@@ -68,7 +73,9 @@ struct dcg_operator_s {
   double ell, s2, sigma2;
   hipStream_t stream;
   uint64_t generation;   // bumped by every hyperparameter change
-  double *X64;           // n x d FP64 copy (exact operator)
+  double *x64r, *x64c;   // FP64 augmented operands of the exact operator
+  double *vin64;         // staged FP64 input vector, n_pad
+  double *part64;        // partial sums of the FP64 sweep
   void *xr, *xc;         // augmented operands (bf16 or fp32)
   float *vin;            // staged FP32 input vectors, n_pad x 4
   float *part;           // partial sums of the symmetric matvec

@@ -1,0 +1,269 @@
+// The FP64 operator A = K(X, X) + sigma2 I on the unrounded points: the
+// residuals b - A x of iterative refinement and the FP64 operator mode.
+//
+// Same circulant block-pair schedule as the low-precision sweep (every
+// unordered pair once, row and column sums from the same kernel value), with
+// 128-point blocks and 16x16 FP64 MFMA tiles: the squared distance comes out
+// of the augmented product <[-2x_i, a_i, 1], [x_j, 1, a_j]> in FP64 (lane l
+// holds column l%16, rows l/16 + 4v for v < 4), the kernel value is
+// evaluated in FP64 (ocml exp / sqrt), and all sums are FP64.
+#include <algorithm>
+#include <cmath>
+
+#include "blas.h"
+
+namespace dcg {
+
+typedef __attribute__((ext_vector_type(4))) double f64x4;
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int exact_ksteps(int d) {
+  const int ks = (d + 2 + 3) / 4;
+  return ks <= 3 ? 3 : ks <= 5 ? 5 : ks <= 9 ? 9 : 17;
+}
+int exact_stride(int d) {
+  const int ks = exact_ksteps(d);
+  return 4 * (ks + (ks & 1));
+}
+
+MatvecPlan exact_plan(int64_t n_pad) {
+  MatvecPlan p;
+  p.blk = 128;
+  p.nb = static_cast<int>(n_pad / p.blk);
+  p.dmax = p.nb / 2;
+  const int ndelta = p.dmax + 1;
+  p.chunk = static_cast<int>(std::max<int64_t>(1, cdiv(int64_t(ndelta) * p.nb, 2048)));
+  p.nchunk = static_cast<int>(cdiv(ndelta, p.chunk));
+  p.grid = int64_t(p.nb) * p.nchunk;
+  return p;
+}
+
+size_t exact_partial_doubles(int64_t n_pad) {
+  const MatvecPlan p = exact_plan(n_pad);
+  return size_t(p.nchunk + p.dmax) * size_t(n_pad);
+}
+
+template <int KERN>
+__device__ __forceinline__ double kval64(double r2, double c0, double c1) {
+  if constexpr (KERN == DCG_RBF) {
+    return exp(r2 * c0);  // c0 = -1 / (2 ell^2)
+  } else {
+    const double t = sqrt(fabs(r2)) * c1;  // c1 = sqrt(3)/ell or sqrt(5)/ell
+    const double e = exp(-t);
+    if constexpr (KERN == DCG_MATERN32) return (1.0 + t) * e;
+    else return fma(t, fma(t, 1.0 / 3.0, 1.0), 1.0) * e;
+  }
+}
+
+template <int KS>
+struct Op64 {
+  static constexpr int KSP = KS + (KS & 1);
+  double v[KSP];
+  __device__ __forceinline__ void load(const double *base, int64_t point, int lh) {
+    const double2 *p = reinterpret_cast<const double2 *>(base + point * (4 * KSP) + lh * KSP);
+#pragma unroll
+    for (int s = 0; s < KSP / 2; ++s) {
+      const double2 u = p[s];
+      v[2 * s] = u.x;
+      v[2 * s + 1] = u.y;
+    }
+  }
+};
+
+struct Symv64Args {
+  const double *xr, *xc;
+  const double *vin;  // n_pad, zero padded
+  double *prow, *pcol;
+  int64_t n_pad;
+  int nb, dmax, chunk, nchunk;
+  double c0, c1;
+  const int *done;
+};
+
+template <int KERN, int KS>
+__global__ __launch_bounds__(256, 2) void symv64_kernel(Symv64Args A) {
+  if (A.done != nullptr && *A.done != 0) return;
+  constexpr int BLK = 128, NCT = 8, TR = 2;
+  __shared__ double colpart[4][BLK];
+  const int64_t G = int64_t(A.nb) * A.nchunk;
+  const int64_t bid = blockIdx.x;
+  const int64_t Gm = G - G % 8;
+  const int64_t item = (bid < Gm) ? (bid % 8) * (Gm / 8) + bid / 8 : bid;
+  const int I = static_cast<int>(item / A.nchunk);
+  const int c = static_cast<int>(item % A.nchunk);
+  const int nb = A.nb;
+  const int ndel = ((nb % 2) == 0 && I >= nb / 2) ? A.dmax : A.dmax + 1;
+  const int d0 = c * A.chunk;
+  const int d1 = min(d0 + A.chunk, ndel);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int lc = l & 15, lg = l >> 4;
+  const int64_t n_pad = A.n_pad;
+  const int64_t rowbase = int64_t(I) * BLK + w * 16 * TR;
+
+  Op64<KS> ra[TR];
+  double pi[TR][4], accr[TR][4];
+#pragma unroll
+  for (int tr = 0; tr < TR; ++tr) {
+    ra[tr].load(A.xr, rowbase + 16 * tr + lc, lg);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      pi[tr][v] = A.vin[rowbase + 16 * tr + lg + 4 * v];
+      accr[tr][v] = 0.0;
+    }
+  }
+  const int tiles = (d1 > d0) ? (d1 - d0) * NCT : 0;
+  auto colbase_of = [&](int t) -> int64_t {
+    int J = I + d0 + t / NCT;
+    if (J >= nb) J -= nb;
+    return int64_t(J) * BLK + 16 * (t % NCT);
+  };
+  Op64<KS> cb, cbn;
+  double pj = 0.0, pjn = 0.0;
+  if (tiles > 0) {
+    const int64_t c0b = colbase_of(0);
+    cb.load(A.xc, c0b + lc, lg);
+    pj = A.vin[c0b + lc];
+  }
+  for (int t = 0; t < tiles; ++t) {
+    const int dl = d0 + t / NCT;
+    const int ct = t % NCT;
+    const bool diag = (dl == 0);
+    if (t + 1 < tiles) {
+      const int64_t cx = colbase_of(t + 1);
+      cbn.load(A.xc, cx + lc, lg);
+      pjn = A.vin[cx + lc];
+    }
+    double cs = 0.0;
+#pragma unroll
+    for (int tr = 0; tr < TR; ++tr) {
+      f64x4 r2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+        r2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[tr].v[s], cb.v[s], r2, 0, 0, 0);
+      if (diag && ct == w * TR + tr) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (lg + 4 * v == lc) r2[v] = 0.0;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double kv = kval64<KERN>(r2[v], A.c0, A.c1);
+        accr[tr][v] = fma(kv, pj, accr[tr][v]);
+        cs = fma(kv, pi[tr][v], cs);
+      }
+    }
+    if (!diag) {
+      cs += __shfl_xor(cs, 16);
+      cs += __shfl_xor(cs, 32);
+      if (lg == 0) colpart[w][16 * ct + lc] = cs;
+      if (ct == NCT - 1) {
+        __syncthreads();
+        int J = I + dl;
+        if (J >= nb) J -= nb;
+        for (int e = threadIdx.x; e < BLK; e += 256)
+          A.pcol[int64_t(dl - 1) * n_pad + int64_t(J) * BLK + e] =
+              (colpart[0][e] + colpart[1][e]) + (colpart[2][e] + colpart[3][e]);
+        __syncthreads();
+      }
+    }
+    if (t + 1 < tiles) {
+      cb = cbn;
+      pj = pjn;
+    }
+  }
+#pragma unroll
+  for (int tr = 0; tr < TR; ++tr) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double s = accr[tr][v];
+      s += __shfl_xor(s, 1);
+      s += __shfl_xor(s, 2);
+      s += __shfl_xor(s, 4);
+      s += __shfl_xor(s, 8);
+      if (lc == v) A.prow[int64_t(c) * n_pad + rowbase + 16 * tr + lg + 4 * v] = s;
+    }
+  }
+}
+
+// v -> zero-padded FP64 copy (n_pad).
+__global__ __launch_bounds__(256) void stage64(const double *V, int64_t n, int64_t n_pad,
+                                               double *out, const int *done) {
+  if (done != nullptr && *done != 0) return;
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n_pad) out[i] = (i < n) ? V[i] : 0.0;
+}
+
+// y = s2 * (row partials + column partials, fixed order) + sigma2 v.
+__global__ __launch_bounds__(256) void reduce64(const double *prow, const double *pcol,
+                                                int64_t n, int64_t n_pad, int nchunk, int dmax,
+                                                int nb, double s2, double sigma2, const double *V,
+                                                double *Y, const int *done) {
+  if (done != nullptr && *done != 0) return;
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += prow[int64_t(c) * n_pad + i];
+  const int J = static_cast<int>(i / 128);
+  const int dlim = ((nb % 2) == 0 && J < nb / 2) ? dmax - 1 : dmax;
+  for (int dl = 1; dl <= dlim; ++dl) s += pcol[int64_t(dl - 1) * n_pad + i];
+  Y[i] = s2 * s + sigma2 * V[i];
+}
+
+template <int KERN>
+static void launch64(const dcg_operator_s *op, const Symv64Args &a, int64_t grid) {
+  const dim3 g(static_cast<unsigned>(grid)), b(256);
+  switch (exact_ksteps(op->g.d)) {
+    case 3: hipLaunchKernelGGL((symv64_kernel<KERN, 3>), g, b, 0, op->stream, a); break;
+    case 5: hipLaunchKernelGGL((symv64_kernel<KERN, 5>), g, b, 0, op->stream, a); break;
+    case 9: hipLaunchKernelGGL((symv64_kernel<KERN, 9>), g, b, 0, op->stream, a); break;
+    default: hipLaunchKernelGGL((symv64_kernel<KERN, 17>), g, b, 0, op->stream, a); break;
+  }
+}
+
+// Y = A V with the FP64 operator, vector by vector; `done` (optional) turns
+// every launch into a no-op once a solve has finished.
+int matvec_exact_done(const dcg_operator_s *op, const double *V, double *Y, int64_t m,
+                      const int *done) {
+  const int64_t n = op->g.n, n_pad = op->g.n_pad;
+  const MatvecPlan p = exact_plan(n_pad);
+  Symv64Args a;
+  a.xr = op->x64r;
+  a.xc = op->x64c;
+  a.vin = op->vin64;
+  a.prow = op->part64;
+  a.pcol = op->part64 + size_t(p.nchunk) * n_pad;
+  a.n_pad = n_pad;
+  a.nb = p.nb;
+  a.dmax = p.dmax;
+  a.chunk = p.chunk;
+  a.nchunk = p.nchunk;
+  a.done = done;
+  if (op->kernel == DCG_RBF) {
+    a.c0 = -1.0 / (2.0 * op->ell * op->ell);
+    a.c1 = 0.0;
+  } else {
+    a.c0 = 0.0;
+    a.c1 = std::sqrt(op->kernel == DCG_MATERN32 ? 3.0 : 5.0) / op->ell;
+  }
+  for (int64_t col = 0; col < m; ++col) {
+    const double *Vc = V + col * n;
+    double *Yc = Y + col * n;
+    hipLaunchKernelGGL(stage64, dim3(static_cast<unsigned>(cdiv(n_pad, 256))), dim3(256), 0,
+                       op->stream, Vc, n, n_pad, op->vin64, done);
+    if (op->kernel == DCG_RBF) launch64<DCG_RBF>(op, a, p.grid);
+    else if (op->kernel == DCG_MATERN32) launch64<DCG_MATERN32>(op, a, p.grid);
+    else launch64<DCG_MATERN52>(op, a, p.grid);
+    hipLaunchKernelGGL(reduce64, dim3(static_cast<unsigned>(cdiv(n, 256))), dim3(256), 0,
+                       op->stream, a.prow, a.pcol, n, n_pad, p.nchunk, p.dmax, p.nb, op->s2,
+                       op->sigma2, Vc, Yc, done);
+    if (hipGetLastError() != hipSuccess) return DCG_E_HIP;
+  }
+  return DCG_OK;
+}
+
+int matvec_exact(const dcg_operator_s *op, const double *V, double *Y, int64_t m) {
+  return matvec_exact_done(op, V, Y, m, nullptr);
+}
+
+}  // namespace dcg

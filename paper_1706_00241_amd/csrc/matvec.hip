@@ -31,6 +31,13 @@ namespace dcg {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 
+static int bf16_bucket(int ks) {
+  const int b[] = {1, 2, 3, 4, 5, 7, 9, 13, 17};
+  for (int v : b)
+    if (ks <= v) return v;
+  return -1;
+}
+
 static int fp32_bucket(int ks) {
   const int b[] = {5, 9, 13, 17, 25, 33};
   for (int v : b)
@@ -50,6 +57,9 @@ Geometry make_geometry(int64_t n, int d, int prec) {
   } else if (prec == DCG_PREC_BF16) {
     g.ksteps = (d + 6 + 15) / 16;
     g.kstride = 16 * g.ksteps;
+  } else if (prec == DCG_PREC_BF16X2) {
+    g.ksteps = bf16_bucket((4 * d + 6 + 15) / 16);
+    g.kstride = 16 * g.ksteps;
   } else {
     g.ksteps = fp32_bucket((d + 2 + 1) / 2);
     g.kstride = 2 * ((g.ksteps + 3) / 4) * 4;
@@ -59,9 +69,9 @@ Geometry make_geometry(int64_t n, int d, int prec) {
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-MatvecPlan make_plan(int64_t n_pad, int mv) {
+MatvecPlan make_plan(int64_t n_pad, int blk) {
   MatvecPlan p;
-  p.blk = (mv == 1) ? kBlk1 : kBlk4;
+  p.blk = blk;
   p.nb = static_cast<int>(n_pad / p.blk);
   p.dmax = p.nb / 2;
   const int ndelta = p.dmax + 1;
@@ -71,8 +81,8 @@ MatvecPlan make_plan(int64_t n_pad, int mv) {
   return p;
 }
 
-size_t matvec_partial_floats(int64_t n_pad, int mv) {
-  MatvecPlan p = make_plan(n_pad, mv);
+size_t matvec_partial_floats(int64_t n_pad, int mv, int blk) {
+  MatvecPlan p = make_plan(n_pad, blk);
   // row partials are FP64 (two floats each), column partials FP32
   return size_t(2 * p.nchunk + p.dmax) * size_t(n_pad) * size_t(mv);
 }
@@ -161,7 +171,7 @@ struct SymvArgs {
 template <int KERN, int KS, int MV, bool BF16>
 __global__ __launch_bounds__(256, 2) void symv_kernel(SymvArgs A) {
   if (A.done != nullptr && *A.done != 0) return;
-  constexpr int TR = (MV == 1) ? 2 : 1;
+  constexpr int TR = (MV == 1 && (!BF16 || KS <= 5)) ? 2 : 1;  // = sweep_tile_rows
   constexpr int BLK = 4 * 32 * TR;
   constexpr int NCT = BLK / 32;
   __shared__ float colpart[MV][4][BLK];
@@ -370,13 +380,17 @@ template <int KERN, int MV>
 static int dispatch_ks(const dcg_operator_s *op, const SymvArgs &a, int64_t grid) {
   const int ks = op->g.ksteps;
   hipStream_t s = op->stream;
-  if (op->g.prec == DCG_PREC_BF16) {
+  if (op->g.prec == DCG_PREC_BF16 || op->g.prec == DCG_PREC_BF16X2) {
     switch (ks) {
       case 1: launch_symv<KERN, 1, MV, true>(a, grid, s); return 0;
       case 2: launch_symv<KERN, 2, MV, true>(a, grid, s); return 0;
       case 3: launch_symv<KERN, 3, MV, true>(a, grid, s); return 0;
       case 4: launch_symv<KERN, 4, MV, true>(a, grid, s); return 0;
       case 5: launch_symv<KERN, 5, MV, true>(a, grid, s); return 0;
+      case 7: launch_symv<KERN, 7, MV, true>(a, grid, s); return 0;
+      case 9: launch_symv<KERN, 9, MV, true>(a, grid, s); return 0;
+      case 13: launch_symv<KERN, 13, MV, true>(a, grid, s); return 0;
+      case 17: launch_symv<KERN, 17, MV, true>(a, grid, s); return 0;
     }
   } else {
     switch (ks) {
@@ -393,7 +407,7 @@ static int dispatch_ks(const dcg_operator_s *op, const SymvArgs &a, int64_t grid
 
 // Enqueue the symmetric pair sweep over op->vin (mv = 1 or 4 vectors).
 int launch_symv_sweep(const dcg_operator_s *op, int mv, const int *done) {
-  MatvecPlan p = make_plan(op->g.n_pad, mv);
+  MatvecPlan p = make_plan(op->g.n_pad, sweep_blk(op->g, mv));
   SymvArgs a;
   a.xr = op->xr;
   a.xc = op->xc;
@@ -423,7 +437,7 @@ int launch_symv_sweep(const dcg_operator_s *op, int mv, const int *done) {
 }
 
 ReduceArgs reduce_args(const dcg_operator_s *op, int mv, const double *V, double *Y) {
-  MatvecPlan p = make_plan(op->g.n_pad, mv);
+  MatvecPlan p = make_plan(op->g.n_pad, sweep_blk(op->g, mv));
   ReduceArgs r;
   r.prow = reinterpret_cast<const double *>(op->part);
   r.pcol = op->part + size_t(2 * p.nchunk) * op->g.n_pad * mv;

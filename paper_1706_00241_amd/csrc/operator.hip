@@ -11,7 +11,8 @@ namespace dcg {
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-static int dp_bucket(int d) { return d <= 8 ? 8 : d <= 16 ? 16 : d <= 32 ? 32 : 64; }
+int exact_stride(int d);
+size_t exact_partial_doubles(int64_t n_pad);
 
 // Round an FP64 value to bfloat16, to nearest with ties to even, in one
 // rounding step from the FP64 value (8 significant bits).  Values below the
@@ -42,14 +43,44 @@ __global__ __launch_bounds__(256) void check_finite(const double *X, int64_t cou
 // One thread per (padded) point: rounded coordinates, squared norm from the
 // rounded coordinates, and the augmented row / column operands.
 __global__ __launch_bounds__(256) void prepare_points(const double *X, int64_t n, int64_t n_pad,
-                                                      int d, int prec, int kstride, int dp,
-                                                      void *xr, void *xc, double *X64) {
+                                                      int d, int prec, int kstride, int stride64,
+                                                      void *xr, void *xc, double *x64r,
+                                                      double *x64c) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n_pad) return;
   const bool real = i < n;
   double a = 0.0;
   if (prec == DCG_PREC_FP64) {
     // exact operator: only the FP64 copy below
+  } else if (prec == DCG_PREC_BF16X2) {
+    // x = hi + lo, both bf16; the operand columns hold the four product
+    // pairings so that <xr_i, xc_j> = a_i + a_j - 2 (hi_i + lo_i).(hi_j + lo_j)
+    uint16_t *r = static_cast<uint16_t *>(xr) + i * kstride;
+    uint16_t *c = static_cast<uint16_t *>(xc) + i * kstride;
+    for (int t = 0; t < d; ++t) {
+      const double xv0 = real ? X[i * d + t] : 0.0;
+      const uint16_t hi = bf16_from_double(xv0);
+      const uint16_t lo = bf16_from_double(xv0 - bf16_to_double(hi));
+      const double xv = bf16_to_double(hi) + bf16_to_double(lo);
+      a += xv * xv;
+      const uint16_t h2 = bf16_from_double(-2.0 * bf16_to_double(hi));
+      const uint16_t l2 = bf16_from_double(-2.0 * bf16_to_double(lo));
+      r[t] = h2;          c[t] = hi;
+      r[d + t] = h2;      c[d + t] = lo;
+      r[2 * d + t] = l2;  c[2 * d + t] = hi;
+      r[3 * d + t] = l2;  c[3 * d + t] = lo;
+    }
+    const uint16_t ah = bf16_from_double(a);
+    const double rem1 = a - bf16_to_double(ah);
+    const uint16_t am = bf16_from_double(rem1);
+    const uint16_t al = bf16_from_double(rem1 - bf16_to_double(am));
+    const uint16_t one = 0x3F80;
+    const int o = 4 * d;
+    r[o + 0] = one; r[o + 1] = one; r[o + 2] = one;
+    r[o + 3] = ah;  r[o + 4] = am;  r[o + 5] = al;
+    c[o + 0] = ah;  c[o + 1] = am;  c[o + 2] = al;
+    c[o + 3] = one; c[o + 4] = one; c[o + 5] = one;
+    for (int t = o + 6; t < kstride; ++t) r[t] = c[t] = 0;
   } else if (prec == DCG_PREC_BF16) {
     uint16_t *r = static_cast<uint16_t *>(xr) + i * kstride;
     uint16_t *c = static_cast<uint16_t *>(xc) + i * kstride;
@@ -87,119 +118,50 @@ __global__ __launch_bounds__(256) void prepare_points(const double *X, int64_t n
     c[(d & 1) * half + (d >> 1)] = af;
     c[((d + 1) & 1) * half + ((d + 1) >> 1)] = 1.0f;
   }
-  for (int t = 0; t < dp; ++t) X64[i * dp + t] = (real && t < d) ? X[i * d + t] : 0.0;
-}
-
-// ------------------------------------------------------ exact FP64 product
-
-template <int KERN>
-__device__ __forceinline__ double kval64(double r2, double ell) {
-  if constexpr (KERN == DCG_RBF) {
-    return exp(-r2 / (2.0 * ell * ell));
-  } else if constexpr (KERN == DCG_MATERN32) {
-    const double t = sqrt(3.0 * r2) / ell;
-    return (1.0 + t) * exp(-t);
-  } else {
-    const double t = sqrt(5.0 * r2) / ell;
-    return (1.0 + t + t * t / 3.0) * exp(-t);
+  // FP64 operands of the exact operator: [-2x, a, 1] and [x, 1, a] with a
+  // the squared norm of the unrounded point, element k stored at
+  // (k % 4) * ksp + k / 4 (the K-step layout of the 16x16x4 FP64 MFMA)
+  const int ksp = stride64 / 4;
+  double *r64 = x64r + i * stride64;
+  double *c64 = x64c + i * stride64;
+  double a64 = 0.0;
+  for (int t = 0; t < stride64; ++t) r64[t] = c64[t] = 0.0;
+  for (int t = 0; t < d; ++t) {
+    const double xv = real ? X[i * d + t] : 0.0;
+    a64 += xv * xv;
+    r64[(t & 3) * ksp + (t >> 2)] = -2.0 * xv;
+    c64[(t & 3) * ksp + (t >> 2)] = xv;
   }
-}
-
-// Y = s2 K V + sigma2 V in FP64 from the unrounded points (difference-form
-// distances), up to 4 vectors; one thread per row, column tiles in LDS.
-template <int KERN, int DP>
-__global__ __launch_bounds__(256) void exact_matvec_kernel(const double *Xp, int64_t n,
-                                                           int64_t n_pad, const double *V,
-                                                           double *Y, int m, double ell, double s2,
-                                                           double sigma2, const int *done) {
-  if (done != nullptr && *done != 0) return;
-  __shared__ double xs[64][DP + 1];
-  __shared__ double vs[4][64];
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  double xi[DP];
-#pragma unroll
-  for (int t = 0; t < DP; ++t) xi[t] = (i < n_pad) ? Xp[i * DP + t] : 0.0;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t j0 = 0; j0 < n; j0 += 64) {
-    for (int e = threadIdx.x; e < 64 * DP; e += 256) {
-      const int jj = e / DP, t = e % DP;
-      const int64_t j = j0 + jj;
-      xs[jj][t] = (j < n_pad) ? Xp[j * DP + t] : 0.0;
-    }
-    for (int e = threadIdx.x; e < 4 * 64; e += 256) {
-      const int mm = e / 64, jj = e % 64;
-      const int64_t j = j0 + jj;
-      vs[mm][jj] = (mm < m && j < n) ? V[mm * n + j] : 0.0;
-    }
-    __syncthreads();
-    const int jn = static_cast<int>(std::min<int64_t>(64, n - j0));
-    for (int jj = 0; jj < jn; ++jj) {
-      double r2 = 0.0;
-#pragma unroll
-      for (int t = 0; t < DP; ++t) {
-        const double df = xi[t] - xs[jj][t];
-        r2 = fma(df, df, r2);
-      }
-      const double kv = kval64<KERN>(r2, ell);
-#pragma unroll
-      for (int mm = 0; mm < 4; ++mm) acc[mm] = fma(kv, vs[mm][jj], acc[mm]);
-    }
-    __syncthreads();
-  }
-  if (i < n) {
-    for (int mm = 0; mm < m; ++mm) Y[mm * n + i] = s2 * acc[mm] + sigma2 * V[mm * n + i];
-  }
-}
-
-template <int KERN>
-static void launch_exact(const dcg_operator_s *op, const double *V, double *Y, int m,
-                         const int *done) {
-  const int dp = dp_bucket(op->g.d);
-  const dim3 grid(static_cast<unsigned>(cdiv(op->g.n, 256)));
-  const int64_t n = op->g.n, np = op->g.n_pad;
-  switch (dp) {
-    case 8: hipLaunchKernelGGL((exact_matvec_kernel<KERN, 8>), grid, dim3(256), 0, op->stream, op->X64, n, np, V, Y, m, op->ell, op->s2, op->sigma2, done); break;
-    case 16: hipLaunchKernelGGL((exact_matvec_kernel<KERN, 16>), grid, dim3(256), 0, op->stream, op->X64, n, np, V, Y, m, op->ell, op->s2, op->sigma2, done); break;
-    case 32: hipLaunchKernelGGL((exact_matvec_kernel<KERN, 32>), grid, dim3(256), 0, op->stream, op->X64, n, np, V, Y, m, op->ell, op->s2, op->sigma2, done); break;
-    default: hipLaunchKernelGGL((exact_matvec_kernel<KERN, 64>), grid, dim3(256), 0, op->stream, op->X64, n, np, V, Y, m, op->ell, op->s2, op->sigma2, done); break;
-  }
-}
-
-int matvec_exact_done(const dcg_operator_s *op, const double *V, double *Y, int64_t m,
-                      const int *done) {
-  for (int64_t c = 0; c < m; c += 4) {
-    const int mm = static_cast<int>(std::min<int64_t>(4, m - c));
-    const double *Vc = V + c * op->g.n;
-    double *Yc = Y + c * op->g.n;
-    if (op->kernel == DCG_RBF) launch_exact<DCG_RBF>(op, Vc, Yc, mm, done);
-    else if (op->kernel == DCG_MATERN32) launch_exact<DCG_MATERN32>(op, Vc, Yc, mm, done);
-    else launch_exact<DCG_MATERN52>(op, Vc, Yc, mm, done);
-    if (hipGetLastError() != hipSuccess) return DCG_E_HIP;
-  }
-  return DCG_OK;
-}
-
-int matvec_exact(const dcg_operator_s *op, const double *V, double *Y, int64_t m) {
-  return matvec_exact_done(op, V, Y, m, nullptr);
+  r64[(d & 3) * ksp + (d >> 2)] = a64;
+  r64[((d + 1) & 3) * ksp + ((d + 1) >> 2)] = 1.0;
+  c64[(d & 3) * ksp + (d >> 2)] = 1.0;
+  c64[((d + 1) & 3) * ksp + ((d + 1) >> 2)] = a64;
 }
 
 // ----------------------------------------------------------- workspace
 
 struct OpLayout {
-  size_t x64, xr, xc, vin, part, ytmp, flag, total;
+  size_t x64r, x64c, vin64, part64, xr, xc, vin, part, ytmp, flag, total;
 };
 
 static OpLayout op_layout(const Geometry &g) {
-  const int dp = dp_bucket(g.d);
-  const size_t esz = (g.prec == DCG_PREC_BF16) ? 2 : (g.prec == DCG_PREC_FP64 ? 0 : 4);
+  const int st64 = exact_stride(g.d);
+  const size_t esz = (g.prec == DCG_PREC_BF16 || g.prec == DCG_PREC_BF16X2)
+                         ? 2
+                         : (g.prec == DCG_PREC_FP64 ? 0 : 4);
   Carve c(nullptr, 0);
   OpLayout L;
-  L.x64 = c.off = align256(c.off); c.off += size_t(g.n_pad) * dp * 8;
+  L.x64r = c.off = align256(c.off); c.off += size_t(g.n_pad) * st64 * 8;
+  L.x64c = c.off = align256(c.off); c.off += size_t(g.n_pad) * st64 * 8;
+  L.vin64 = c.off = align256(c.off); c.off += size_t(g.n_pad) * 8;
+  L.part64 = c.off = align256(c.off); c.off += exact_partial_doubles(g.n_pad) * 8;
   L.xr = c.off = align256(c.off); c.off += size_t(g.n_pad) * g.kstride * esz;
   L.xc = c.off = align256(c.off); c.off += size_t(g.n_pad) * g.kstride * esz;
   L.vin = c.off = align256(c.off); c.off += size_t(g.n_pad) * 4 * 4;
   L.part = c.off = align256(c.off);
-  c.off += std::max(matvec_partial_floats(g.n_pad, 1), matvec_partial_floats(g.n_pad, 4)) * 4;
+  if (g.prec != DCG_PREC_FP64)
+    c.off += std::max(matvec_partial_floats(g.n_pad, 1, sweep_blk(g, 1)),
+                      matvec_partial_floats(g.n_pad, 4, sweep_blk(g, 4))) * 4;
   L.ytmp = c.off = align256(c.off); c.off += size_t(g.n_pad) * 4 * 8;
   L.flag = c.off = align256(c.off); c.off += 256;
   L.total = align256(c.off);
@@ -214,7 +176,7 @@ extern "C" {
 
 size_t dcg_operator_workspace_bytes(int64_t n, int64_t d, int prec) {
   if (n < 1 || d < 1 || d > kMaxD) return 0;
-  if (prec != DCG_PREC_FP32 && prec != DCG_PREC_BF16 && prec != DCG_PREC_FP64) return 0;
+  if (prec < DCG_PREC_FP32 || prec > DCG_PREC_FP64) return 0;
   return op_layout(make_geometry(n, static_cast<int>(d), prec)).total;
 }
 
@@ -225,7 +187,7 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel, doubl
   *out = nullptr;
   if (X == nullptr || n < 1 || d < 1 || d > kMaxD) return DCG_E_ARG;
   if (kernel < DCG_RBF || kernel > DCG_MATERN52) return DCG_E_ARG;
-  if (prec != DCG_PREC_FP32 && prec != DCG_PREC_BF16 && prec != DCG_PREC_FP64) return DCG_E_ARG;
+  if (prec < DCG_PREC_FP32 || prec > DCG_PREC_FP64) return DCG_E_ARG;
   if (!(ell > 0.0) || !(s2 > 0.0) || !(sigma2 >= 0.0) || !std::isfinite(ell) ||
       !std::isfinite(s2) || !std::isfinite(sigma2))
     return DCG_E_ARG;
@@ -245,7 +207,10 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel, doubl
   op->sigma2 = sigma2;
   op->stream = static_cast<hipStream_t>(stream);
   op->generation = 1;
-  op->X64 = reinterpret_cast<double *>(base + L.x64);
+  op->x64r = reinterpret_cast<double *>(base + L.x64r);
+  op->x64c = reinterpret_cast<double *>(base + L.x64c);
+  op->vin64 = reinterpret_cast<double *>(base + L.vin64);
+  op->part64 = reinterpret_cast<double *>(base + L.part64);
   op->xr = base + L.xr;
   op->xc = base + L.xc;
   op->vin = reinterpret_cast<float *>(base + L.vin);
@@ -258,8 +223,8 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel, doubl
   hipLaunchKernelGGL(check_finite, dim3(static_cast<unsigned>(std::min<int64_t>(1024, cdiv(count, 256)))),
                      dim3(256), 0, op->stream, X, count, flag);
   hipLaunchKernelGGL(prepare_points, dim3(static_cast<unsigned>(cdiv(g.n_pad, 256))), dim3(256), 0,
-                     op->stream, X, n, g.n_pad, g.d, g.prec, g.kstride, dp_bucket(g.d), op->xr,
-                     op->xc, op->X64);
+                     op->stream, X, n, g.n_pad, g.d, g.prec, g.kstride, exact_stride(g.d),
+                     op->xr, op->xc, op->x64r, op->x64c);
   ok = ok && hipGetLastError() == hipSuccess;
   ok = ok && hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, op->stream) == hipSuccess;
   ok = ok && hipStreamSynchronize(op->stream) == hipSuccess;

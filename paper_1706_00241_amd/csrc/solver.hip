@@ -37,7 +37,7 @@ static SolveLayout solve_layout(int64_t n) {
     off += bytes;
     return o;
   };
-  const size_t nb = size_t(std::max<int64_t>(cdiv(n, 256), kRedBlocks));
+  const size_t nb = size_t(std::max<int64_t>(2 * cdiv(n, 64) + 2, kRedBlocks));
   L.S = take(sizeof(SolveState));
   L.counter = take(sizeof(unsigned) * 4);
   L.r = take(size_t(n) * 8);
@@ -181,7 +181,10 @@ static CgArgs cg_args(dcg_operator_s *op, const SolveBuffers &B, double *x, dcg_
   a.koff = k;
   a.L = L;
   a.part = B.part;
+  a.part2 = B.part + std::max<int64_t>(cdiv(op->g.n, kCgRows), 1);
   a.part_h = B.part_h;
+  a.nblk_q = cdiv(op->g.n, kCgRows);
+  a.nblk_xr = cdiv(op->g.n, 256);
   a.counter = B.counter;
   a.hist_d = B.hist_d;
   a.hist_alpha = B.hist_alpha;
@@ -202,8 +205,10 @@ static int enqueue_cg_step(dcg_operator_s *op, const CgArgs &a, hipEvent_t ev0 =
   if (ev1 != nullptr && hipEventRecord(ev1, op->stream) != hipSuccess) return DCG_E_HIP;
   if (st != DCG_OK) return st;
   const dim3 grid(static_cast<unsigned>(cdiv(op->g.n, 256)));
-  hipLaunchKernelGGL(cg_matvec_finish, grid, dim3(256), 0, op->stream, a);
+  hipLaunchKernelGGL(cg_matvec_finish, dim3(static_cast<unsigned>(a.nblk_q)), dim3(256), 0,
+                     op->stream, a);
   hipLaunchKernelGGL(cg_update_xr, grid, dim3(256), 0, op->stream, a);
+  hipLaunchKernelGGL(cg_finalize, dim3(1), dim3(256), 0, op->stream, a);
   hipLaunchKernelGGL(cg_update_p, grid, dim3(256), 0, op->stream, a);
   return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
 }
@@ -212,7 +217,7 @@ static int enqueue_cg_step(dcg_operator_s *op, const CgArgs &a, hipEvent_t ev0 =
 // next basis (section 2.3) when rc is given.
 static int inner_solve(dcg_operator_s *op, const double *b, double *x, int x_given,
                        dcg_recycle_s *rc, const dcg_params *p, double tol, void *ws,
-                       InnerResult *out) {
+                       InnerResult *out, bool extract = true) {
   const auto t0 = Clock::now();
   hipStream_t s = op->stream;
   const int64_t n = op->g.n, n_pad = op->g.n_pad;
@@ -221,7 +226,7 @@ static int inner_solve(dcg_operator_s *op, const double *b, double *x, int x_giv
   int L = 0;
   int k = 0;
   if (rc != nullptr) {
-    L = (p->L > 0) ? std::min(p->L, rc->L) : rc->L;
+    L = extract ? ((p->L > 0) ? std::min(p->L, rc->L) : rc->L) : 0;
     k = rc->k_used;
   }
   int matvecs = 0;
@@ -339,7 +344,7 @@ static int inner_solve(dcg_operator_s *op, const double *b, double *x, int x_giv
 
   // ---- harmonic Ritz extraction of W' = Z U (Eq. 7)
   const auto t2 = Clock::now();
-  if (rc != nullptr && out->status >= 0) {
+  if (rc != nullptr && extract && out->status >= 0) {
     const int L_eff = std::min(L, hs.iter);
     const int mz = k + L_eff;
     if (mz > 0) {
@@ -547,7 +552,8 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
     if (rel <= p->tol) { status = DCG_OK; break; }
     if (t == outer_max) break;
     InnerResult R;
-    rcode = inner_solve(op, rhs, delta, 0, rc, p, p->inner_tol, ws, &R);
+    rcode = inner_solve(op, rhs, delta, 0, rc, p, p->inner_tol, ws, &R,
+                        p->refresh_every != 0 || st->outer_steps == 0);
     if (rcode != DCG_OK) return st->status = rcode;
     st->iters += R.iters;
     st->matvecs += R.matvecs;

@@ -106,6 +106,21 @@ def test_round_bf16_matches_torch_on_fp32_values():
     np.testing.assert_array_equal(P.round_bf16(x), ref)
 
 
+def test_round_bf16x2():
+    g = np.random.default_rng(6)
+    x = g.uniform(-3, 3, 5000)
+    y = P.round_bf16x2(x)
+    # 16 significant bits: relative error below 2^-16
+    assert np.all(np.abs(y - x) <= 2.0 ** -16 * np.abs(x))
+    # both parts are bf16 values, and values with 16 significant bits are kept
+    hi = P.round_bf16(x)
+    assert np.array_equal(P.round_bf16(y - hi), y - hi)
+    exact = np.ldexp(np.round(np.ldexp(x, 13)), -13)[np.abs(x) >= 0.5]
+    exact = exact[np.abs(exact) < 4]
+    np.testing.assert_array_equal(P.round_bf16x2(exact), exact)
+    assert P.round_points(np.array([[0.1]]), P.PREC_BF16X2)[0, 0] == P.round_bf16x2(np.array([0.1]))[0]
+
+
 def test_round_fp32():
     assert P.round_fp32(np.array([0.1]))[0] == float(np.float32(0.1))
     assert P.round_points(np.array([[0.1]]), P.PREC_FP64)[0, 0] == 0.1
