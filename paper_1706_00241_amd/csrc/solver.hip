@@ -287,7 +287,9 @@ static int inner_solve(dcg_operator_s *op, const double *b, double *x, int x_giv
   const bool prof = p->profile != 0;
   const int pchunk = prof ? std::min(chunk, 64) : chunk;
   if (prof)
-    for (int e = 0; e < 2 * pchunk; ++e) HIPCHK(hipEventCreate(&evs[e]));
+    // no system-scope fence: the events only time device work on this stream
+    for (int e = 0; e < 2 * pchunk; ++e)
+      HIPCHK(hipEventCreateWithFlags(&evs[e], hipEventDisableSystemFence));
   if (p->use_graph && !prof) {
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     int st = DCG_OK;
