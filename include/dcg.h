@@ -194,6 +194,34 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given,
               dcg_recycle_t rc, const dcg_params *p, dcg_stats *st, void *ws,
               size_t ws_bytes);
 
+/* ------------------------------------------------ many right-hand sides
+ * X = A^{-1} B for m <= 64 columns at once: every column runs its own
+ * deflated CG (Algorithm 1) with the basis W held by rc (reused as it is, no
+ * extraction; rc may be NULL or empty for plain CG).  The products of a step
+ * are block sweeps over four columns at a time, so each kernel value is
+ * evaluated once per four columns.  B, X: device FP64 n x m column-major;
+ * x_{-1} = 0.  p->tol, max_iter, check_every apply per column; st->iters is
+ * the largest column count, st->status the worst column status. */
+size_t dcg_solve_block_workspace_bytes(int64_t n, int64_t m);
+int dcg_solve_block(dcg_op_t op, const double *B, double *X, int64_t m,
+                    dcg_recycle_t rc, const dcg_params *p, dcg_stats *st,
+                    void *ws, size_t ws_bytes);
+
+/* ------------------------------------------ GP hyperparameter gradient
+ * For the operator A = s2 k(X, X) + sigma2 I, alpha = A^{-1} y and probe
+ * solves U = A^{-1} Z (Z: P <= 16 probe vectors, e.g. Rademacher), writes to
+ * grad3 (host) the gradient of the GP log marginal likelihood with respect to
+ * (log ell, log s2, log sigma2) with the Hutchinson trace estimate:
+ *   g_j = 1/2 sum_ij (dA/dtheta_j)_ij (alpha_i alpha_j - (1/P) sum_p U_ip Z_jp)
+ * (GP model adaptation, section 1; Rasmussen & Williams eq. 5.9).  The two
+ * kernel-matrix terms are taken in one symmetric sweep over the pairs.
+ * alpha: device n-vector; U, Z: device FP64 n x P column-major.  Operators
+ * of precision FP32 or BF16 only (DCG_E_ARG otherwise). */
+size_t dcg_mll_grad_workspace_bytes(int64_t n);
+int dcg_mll_grad(dcg_op_t op, const double *alpha, const double *U,
+                 const double *Z, int64_t P, double *grad3, void *ws,
+                 size_t ws_bytes);
+
 /* Human-readable name of a status code (static string). */
 const char *dcg_status_string(int status);
 

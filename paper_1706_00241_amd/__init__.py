@@ -89,6 +89,15 @@ _SIGS = {
     "dcg_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                  ctypes.c_void_p, ctypes.POINTER(Params), ctypes.POINTER(Stats),
                                  ctypes.c_void_p, ctypes.c_size_t]),
+    "dcg_solve_block_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int64]),
+    "dcg_solve_block": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(Params),
+                                       ctypes.POINTER(Stats), ctypes.c_void_p, ctypes.c_size_t]),
+    "dcg_mll_grad_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
+    "dcg_mll_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+                                    ctypes.c_size_t]),
     "dcg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "dcg_version": (ctypes.c_char_p, []),
 }
@@ -329,3 +338,106 @@ def solve(op, b, x0=None, rc=None, tol=1e-6, max_iter=0, L=0, select_largest=Tru
 
 def version():
     return load().dcg_version().decode()
+
+
+def solve_block(op, B, rc=None, tol=1e-6, max_iter=0, check_every=8, out=None):
+    """X = A^{-1} B for the columns of B (n x m, m <= 64), each by deflated CG
+    with the basis W of rc (reused, not refreshed); returns (X, stats)."""
+    torch = _torch()
+    lib = load()
+    Bc = _colmajor(B.to(op.device))
+    m = Bc.shape[0]
+    X = torch.empty_like(Bc)
+    nbytes = lib.dcg_solve_block_workspace_bytes(op.n, m)
+    if nbytes == 0:
+        raise DcgError(-1, "dcg_solve_block_workspace_bytes")
+    _wsbuf, ptr, size = _workspace(nbytes, op.device)
+    p = Params(tol=float(tol), max_iter=int(max_iter), check_every=int(check_every))
+    st = Stats()
+    with _ordered(op.stream):
+        status = lib.dcg_solve_block(op.handle, Bc.data_ptr(), X.data_ptr(), m,
+                                     rc.handle if rc is not None else None, ctypes.byref(p),
+                                     ctypes.byref(st), ptr, size)
+    _check(status, "dcg_solve_block")
+    torch.cuda.current_stream(op.device).synchronize()
+    return X.t(), st.as_dict()
+
+
+def mll_grad(op, alpha, U, Z):
+    """Gradient of the GP log marginal likelihood w.r.t. (log ell, log s2,
+    log sigma2) from alpha = A^{-1} y, probes Z (n x P) and U = A^{-1} Z."""
+    torch = _torch()
+    lib = load()
+    a = alpha.to(device=op.device, dtype=torch.float64).contiguous()
+    Uc = _colmajor(U.to(op.device))
+    Zc = _colmajor(Z.to(op.device))
+    nbytes = lib.dcg_mll_grad_workspace_bytes(op.n)
+    _wsbuf, ptr, size = _workspace(nbytes, op.device)
+    g = (ctypes.c_double * 3)()
+    with _ordered(op.stream):
+        _check(lib.dcg_mll_grad(op.handle, a.data_ptr(), Uc.data_ptr(), Zc.data_ptr(),
+                                Uc.shape[0], g, ptr, size), "dcg_mll_grad")
+    return [g[0], g[1], g[2]]
+
+
+class GPMarginalLikelihood:
+    """torch.autograd.Function for the GP log marginal likelihood in
+    theta = (log ell, log s2, log sigma2).
+
+    forward: alpha = A^{-1} y by deflated CG with the recycled basis of `rc`
+    (refreshed by every solve), value = -1/2 y^T alpha - n/2 log(2 pi).  The
+    value leaves out -1/2 log|A|: it is not formed.
+    backward: the probe solves U = A^{-1} Z reuse the same recycled W (the
+    adjoint of the symmetric solve is the same solve), then one fused sweep
+    gives the full gradient, log-determinant term included (Hutchinson).
+
+    Use through ``GPMarginalLikelihood.apply(theta, ctx_obj)`` where ctx_obj
+    is a ``GPContext`` holding the operator, y, the recycle handle and the
+    probes of the current step.
+    """
+
+    _fn = None
+
+    @classmethod
+    def apply(cls, theta, gpc):
+        if cls._fn is None:
+            cls._fn = _make_mll_function()
+        return cls._fn.apply(theta, gpc)
+
+
+class GPContext:
+    def __init__(self, op, y, rc, probes, tol=1e-6, probe_tol=None):
+        self.op, self.y, self.rc, self.probes = op, y, rc, probes
+        self.tol = tol
+        self.probe_tol = tol if probe_tol is None else probe_tol
+        self.last = {}
+
+
+def _make_mll_function():
+    import math
+    torch = _torch()
+
+    class _MLL(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, theta, gpc):
+            th = theta.detach().double().cpu().tolist()
+            op = gpc.op
+            op.set_hyper(math.exp(th[0]), math.exp(th[1]), math.exp(th[2]))
+            alpha, st = solve(op, gpc.y, rc=gpc.rc, tol=gpc.tol)
+            alpha = alpha.clone()
+            gpc.last = {"alpha_stats": st}
+            ctx.gpc = gpc
+            ctx.alpha = alpha
+            value = -0.5 * float(torch.dot(gpc.y.to(alpha), alpha)) - 0.5 * op.n * math.log(2 * math.pi)
+            return theta.new_tensor(value)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            gpc = ctx.gpc
+            U, st = solve_block(gpc.op, gpc.probes, rc=gpc.rc, tol=gpc.probe_tol)
+            gpc.last["probe_stats"] = st
+            g = mll_grad(gpc.op, ctx.alpha, U, gpc.probes)
+            gpc.last["grad"] = g
+            return grad_out * grad_out.new_tensor(g), None
+
+    return _MLL

@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdcg.so")
-SOURCES = ["matvec.hip", "exact.hip", "blas.hip", "eig.hip", "operator.hip", "solver.hip"]
+SOURCES = ["matvec.hip", "exact.hip", "blas.hip", "eig.hip", "operator.hip", "solver.hip",
+           "block.hip", "grad.hip"]
 ARCH = "gfx950"
 
 

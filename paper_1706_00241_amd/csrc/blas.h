@@ -51,6 +51,7 @@ struct CgArgs {
   SolveState *S;
   ReduceArgs red;
   const double *qdirect;  // FP64 operator: the finished product (else null)
+  int mcol;               // which vector of red's partial layout (red.mv vectors)
   int64_t n;
   double *x, *r, *p, *q;
   float *p32;
@@ -72,6 +73,10 @@ __global__ void cg_matvec_finish(CgArgs a);
 __global__ void cg_update_xr(CgArgs a);
 __global__ void cg_update_p(CgArgs a);
 __global__ void cg_finalize(CgArgs a);
+__global__ void cg_matvec_finish_multi(const CgArgs *args);
+__global__ void cg_update_xr_multi(const CgArgs *args);
+__global__ void cg_finalize_multi(const CgArgs *args);
+__global__ void cg_update_p_multi(const CgArgs *args);
 __global__ void init_residual(const double *b, const double *Ax, double *x, double *r, int64_t n,
                               int x_given, double *part, unsigned *counter, SolveState *S);
 __global__ void defl_start(double *x, double *t, const double *W, const double *cvec, int64_t n,
@@ -99,11 +104,15 @@ size_t harmonic_ritz_work_doubles();
 // matvec.hip
 void kernel_constants(int kernel, double ell, float *c0, float *c1, float *c2);
 int launch_symv_sweep(const dcg_operator_s *op, int mv, const int *done);
+int launch_symv_sweep_from(const dcg_operator_s *op, int mv, const float *vin, const int *done);
 ReduceArgs reduce_args(const dcg_operator_s *op, int mv, const double *V, double *Y);
 int matvec_lowprec(const dcg_operator_s *op, const double *V, double *Y, int64_t m);
 int matvec_exact(const dcg_operator_s *op, const double *V, double *Y, int64_t m);
 int matvec_exact_done(const dcg_operator_s *op, const double *V, double *Y, int64_t m,
                       const int *done);
 int prepare_operator(dcg_operator_s *op, const double *X);
+
+// solver.hip
+int deflation_setup(dcg_operator_s *op, dcg_recycle_s *rc, int *matvecs);
 
 }  // namespace dcg

@@ -97,7 +97,7 @@ __device__ __forceinline__ void small_gemv(const double *Minv, const double *h, 
 // kCgRows rows in groups of 64; each row's partials are split over 4 threads
 // (memory parallelism), then added in a fixed order.  No cross-block step:
 // the next kernel forms d and alpha itself from the block partials.
-__global__ __launch_bounds__(256) void cg_matvec_finish(CgArgs a) {
+__device__ __forceinline__ void cg_matvec_finish_body(const CgArgs &a, const unsigned bid) {
   SolveState *S = a.S;
   if (S->done) return;
   __shared__ double seg[4][64];
@@ -106,25 +106,29 @@ __global__ __launch_bounds__(256) void cg_matvec_finish(CgArgs a) {
   const int j = S->iter;  // index of the direction being multiplied
   double pq = 0.0;
   for (int grp = 0; grp < kCgRows / 64; ++grp) {
-    const int64_t i = int64_t(blockIdx.x) * kCgRows + grp * 64 + r;
+    const int64_t i = int64_t(bid) * kCgRows + grp * 64 + r;
     double s = 0.0;
     if (i < a.n) {
       if (a.qdirect != nullptr) {
         s = (sg == 0) ? a.qdirect[i] : 0.0;
       } else {
         const ReduceArgs &R = a.red;
-        for (int c = sg; c < R.nchunk; c += 4) s += R.prow[int64_t(c) * R.n_pad + i];
+        // vector a.mcol of an R.mv-vector partial layout
+        const int64_t ps = int64_t(R.mv) * R.n_pad;
+        const double *prow = R.prow + int64_t(a.mcol) * R.n_pad;
+        const float *pcol = R.pcol + int64_t(a.mcol) * R.n_pad;
+        for (int c = sg; c < R.nchunk; c += 4) s += prow[int64_t(c) * ps + i];
         const int J = static_cast<int>(i / R.blk);
         const int dlim = ((R.nb % 2) == 0 && J < R.nb / 2) ? R.dmax - 1 : R.dmax;
         double s1 = 0.0, s2 = 0.0, s3 = 0.0;
         int dl = 1 + sg;
         for (; dl + 12 <= dlim; dl += 16) {
-          s += R.pcol[int64_t(dl - 1) * R.n_pad + i];
-          s1 += R.pcol[int64_t(dl + 3) * R.n_pad + i];
-          s2 += R.pcol[int64_t(dl + 7) * R.n_pad + i];
-          s3 += R.pcol[int64_t(dl + 11) * R.n_pad + i];
+          s += pcol[int64_t(dl - 1) * ps + i];
+          s1 += pcol[int64_t(dl + 3) * ps + i];
+          s2 += pcol[int64_t(dl + 7) * ps + i];
+          s3 += pcol[int64_t(dl + 11) * ps + i];
         }
-        for (; dl <= dlim; dl += 4) s += R.pcol[int64_t(dl - 1) * R.n_pad + i];
+        for (; dl <= dlim; dl += 4) s += pcol[int64_t(dl - 1) * ps + i];
         s = (s + s1) + (s2 + s3);
       }
     }
@@ -144,13 +148,13 @@ __global__ __launch_bounds__(256) void cg_matvec_finish(CgArgs a) {
     __syncthreads();
   }
   const double bs = block_sum_all(pq, lds);
-  if (threadIdx.x == 0) a.part[blockIdx.x] = bs;
+  if (threadIdx.x == 0) a.part[bid] = bs;
 }
 
 // d = p^T q from the partials of cg_matvec_finish (every block forms it, in
 // the same order), alpha = rho / d; x += alpha p; r -= alpha q; block partials
 // of rho' = r^T r, h = (AW)^T r and g = W^T r.
-__global__ __launch_bounds__(256) void cg_update_xr(CgArgs a) {
+__device__ __forceinline__ void cg_update_xr_body(const CgArgs &a, const unsigned bid) {
   SolveState *S = a.S;
   if (S->done) return;
   __shared__ double lds[8];
@@ -158,7 +162,7 @@ __global__ __launch_bounds__(256) void cg_update_xr(CgArgs a) {
   const double d = block_sum_array(a.part, a.nblk_q, lds);
   const bool bad = !(d > 0.0) || !isfinite(d);
   const double alpha = bad ? 0.0 : S->rho / d;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bid == 0 && threadIdx.x == 0) {
     S->d = d;
     S->alpha = alpha;
     const int j = S->iter;
@@ -167,7 +171,7 @@ __global__ __launch_bounds__(256) void cg_update_xr(CgArgs a) {
       a.hist_alpha[j] = alpha;
     }
   }
-  const int64_t i0 = int64_t(blockIdx.x) * 256;
+  const int64_t i0 = int64_t(bid) * 256;
   const int64_t i = i0 + threadIdx.x;
   double rr = 0.0;
   double ri = 0.0;
@@ -179,11 +183,11 @@ __global__ __launch_bounds__(256) void cg_update_xr(CgArgs a) {
   }
   rl[threadIdx.x] = ri;
   const double bs = block_sum_all(rr, lds);
-  if (threadIdx.x == 0) a.part2[blockIdx.x] = bad ? (isfinite(d) ? -1.0 : -2.0) : bs;
+  if (threadIdx.x == 0) a.part2[bid] = bad ? (isfinite(d) ? -1.0 : -2.0) : bs;
   // partial dots with the columns of [AW | W]: wave w takes columns w, w+4,
   // ...; eight columns' loads are issued before their reductions
   const int k = a.k;
-  const int64_t nblk = gridDim.x;
+  const int64_t nblk = a.nblk_xr;
   if (k > 0) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     for (int cb = w; cb < 2 * k; cb += 32) {
@@ -207,7 +211,7 @@ __global__ __launch_bounds__(256) void cg_update_xr(CgArgs a) {
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
         const int c = cb + 4 * u;
-        if (l == 0 && c < 2 * k) a.part_h[int64_t(c) * nblk + blockIdx.x] = v;
+        if (l == 0 && c < 2 * k) a.part_h[int64_t(c) * nblk + bid] = v;
       }
     }
   }
@@ -218,7 +222,7 @@ __global__ __launch_bounds__(256) void cg_update_xr(CgArgs a) {
 // arithmetic, where W^T r_j = 0), and with r' = r - AW c:
 // mu = (W^T A W)^{-1} (AW)^T r', beta = |r'|^2 / |r|^2 and the convergence
 // test on |r'| / |b|.
-__global__ __launch_bounds__(256) void cg_finalize(CgArgs a) {
+__device__ __forceinline__ void cg_finalize_body(const CgArgs &a) {
   SolveState *S = a.S;
   if (S->done) return;
   __shared__ double lds[8];
@@ -291,7 +295,7 @@ __global__ __launch_bounds__(256) void cg_finalize(CgArgs a) {
 
 // Apply the re-projection (x += W c, r -= AW c) and the direction update
 // p = beta p + r - W mu; the FP32 copy of p feeds the next matvec.
-__global__ __launch_bounds__(256) void cg_update_p(CgArgs a) {
+__device__ __forceinline__ void cg_update_p_body(const CgArgs &a, const unsigned bid) {
   SolveState *S = a.S;
   if (S->done) return;
   __shared__ double mu[kMaxK];
@@ -301,7 +305,7 @@ __global__ __launch_bounds__(256) void cg_update_p(CgArgs a) {
     cv[c] = S->cvec[c];
   }
   __syncthreads();
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t i = int64_t(bid) * 256 + threadIdx.x;
   if (i >= a.n) return;
   double ri = a.r[i];
   double xi = 0.0;
@@ -319,6 +323,32 @@ __global__ __launch_bounds__(256) void cg_update_p(CgArgs a) {
   const double s = ri + S->beta * a.p[i] - wmu;
   a.p[i] = s;
   a.p32[i] = static_cast<float>(s);
+}
+
+// Kernels: one solve (arguments by value), or many columns / systems at once
+// (blockIdx.y selects the arguments of a column or system).
+__global__ __launch_bounds__(256) void cg_matvec_finish(CgArgs a) { cg_matvec_finish_body(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void cg_update_xr(CgArgs a) { cg_update_xr_body(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void cg_finalize(CgArgs a) { cg_finalize_body(a); }
+__global__ __launch_bounds__(256) void cg_update_p(CgArgs a) { cg_update_p_body(a, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void cg_matvec_finish_multi(const CgArgs *args) {
+  const CgArgs &a = args[blockIdx.y];
+  if (int64_t(blockIdx.x) * kCgRows >= a.n) return;
+  cg_matvec_finish_body(a, blockIdx.x);
+}
+__global__ __launch_bounds__(256) void cg_update_xr_multi(const CgArgs *args) {
+  const CgArgs &a = args[blockIdx.y];
+  if (int64_t(blockIdx.x) * 256 >= a.n) return;
+  cg_update_xr_body(a, blockIdx.x);
+}
+__global__ __launch_bounds__(256) void cg_finalize_multi(const CgArgs *args) {
+  cg_finalize_body(args[blockIdx.y]);
+}
+__global__ __launch_bounds__(256) void cg_update_p_multi(const CgArgs *args) {
+  const CgArgs &a = args[blockIdx.y];
+  if (int64_t(blockIdx.x) * 256 >= a.n) return;
+  cg_update_p_body(a, blockIdx.x);
 }
 
 // -------------------------------------------------- initialisation kernels

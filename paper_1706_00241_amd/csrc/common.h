@@ -105,6 +105,9 @@ struct dcg_recycle_s {
   double *small;         // misc small device scalars / vectors
   int *info;             // device status words of the extraction
   double *gemm;          // split-K partials of the tall-skinny products
+  uint64_t w_version;    // bumped whenever W or AW changes
+  uint64_t m_version;    // w_version when M, N, M^{-1} were formed
+  int m_valid;
   int rank_F;            // numerical rank of F at the last extraction
   int sweeps[2];         // Jacobi sweeps of the last extraction
 };

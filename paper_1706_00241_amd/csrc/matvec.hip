@@ -406,13 +406,13 @@ static int dispatch_ks(const dcg_operator_s *op, const SymvArgs &a, int64_t grid
 }
 
 // Enqueue the symmetric pair sweep over op->vin (mv = 1 or 4 vectors).
-int launch_symv_sweep(const dcg_operator_s *op, int mv, const int *done) {
+int launch_symv_sweep_from(const dcg_operator_s *op, int mv, const float *vin, const int *done) {
   MatvecPlan p = make_plan(op->g.n_pad, sweep_blk(op->g, mv));
   SymvArgs a;
   a.xr = op->xr;
   a.xc = op->xc;
   a.kstride = op->g.kstride;
-  a.vin = op->vin;
+  a.vin = vin;
   a.prow = reinterpret_cast<double *>(op->part);
   a.pcol = op->part + size_t(2 * p.nchunk) * op->g.n_pad * mv;
   a.n_pad = op->g.n_pad;
@@ -434,6 +434,10 @@ int launch_symv_sweep(const dcg_operator_s *op, int mv, const int *done) {
   }
   if (rc != 0) return DCG_E_ARG;
   return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
+}
+
+int launch_symv_sweep(const dcg_operator_s *op, int mv, const int *done) {
+  return launch_symv_sweep_from(op, mv, op->vin, done);
 }
 
 ReduceArgs reduce_args(const dcg_operator_s *op, int mv, const double *V, double *Y) {

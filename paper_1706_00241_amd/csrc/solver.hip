@@ -156,6 +156,29 @@ static int refresh_AW(dcg_operator_s *op, dcg_recycle_s *rc, int *matvecs) {
   rc->aw_ell = op->ell;
   rc->aw_s2 = op->s2;
   rc->aw_sigma2 = op->sigma2;
+  rc->w_version += 1;
+  return DCG_OK;
+}
+
+// AW for the current operator, then M = W^T A W, N = (AW)^T AW and M^{-1},
+// recomputed only when W or AW changed since the last time.
+int deflation_setup(dcg_operator_s *op, dcg_recycle_s *rc, int *matvecs) {
+  const int k = rc->k_used;
+  if (k == 0) return DCG_OK;
+  int st = refresh_AW(op, rc, matvecs);
+  if (st != DCG_OK) return st;
+  if (rc->m_valid && rc->m_version == rc->w_version) return DCG_OK;
+  hipStream_t s = op->stream;
+  const int64_t n = rc->n;
+  enqueue_tsgemm_tn(s, rc->Z, rc->AZ, n, k, k, rc->gemm, kGemmPartDoubles, rc->M, k, 1);
+  enqueue_tsgemm_tn(s, rc->AZ, rc->AZ, n, k, k, rc->gemm, kGemmPartDoubles, rc->N, k, 1);
+  enqueue_small_spd_inverse(s, rc->M, k, rc->Minv, rc->Mwork, rc->info);
+  int info = 0;
+  HIPCHK(hipMemcpyAsync(&info, rc->info, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (info != 0) return DCG_E_NOT_SPD;
+  rc->m_valid = 1;
+  rc->m_version = rc->w_version;
   return DCG_OK;
 }
 
@@ -165,6 +188,7 @@ static CgArgs cg_args(dcg_operator_s *op, const SolveBuffers &B, double *x, dcg_
   a.S = B.S;
   a.red = reduce_args(op, 1, nullptr, nullptr);
   a.qdirect = (op->g.prec == DCG_PREC_FP64) ? op->ytmp : nullptr;
+  a.mcol = 0;
   a.n = op->g.n;
   a.x = x;
   a.r = B.r;
@@ -234,11 +258,8 @@ static int inner_solve(dcg_operator_s *op, const double *b, double *x, int x_giv
   HIPCHK(hipMemsetAsync(B.counter, 0, sizeof(unsigned) * 4, s));
   HIPCHK(hipMemsetAsync(B.S, 0, sizeof(SolveState), s));
   if (k > 0) {
-    int st = refresh_AW(op, rc, &matvecs);
+    int st = deflation_setup(op, rc, &matvecs);
     if (st != DCG_OK) return st;
-    enqueue_tsgemm_tn(s, rc->Z, rc->AZ, n, k, k, rc->gemm, kGemmPartDoubles, rc->M, k, 1);
-    enqueue_tsgemm_tn(s, rc->AZ, rc->AZ, n, k, k, rc->gemm, kGemmPartDoubles, rc->N, k, 1);
-    enqueue_small_spd_inverse(s, rc->M, k, rc->Minv, rc->Mwork, rc->info);
     Minv = rc->Minv;
   }
   // r = b - A x_{-1}
@@ -253,10 +274,6 @@ static int inner_solve(dcg_operator_s *op, const double *b, double *x, int x_giv
   hipLaunchKernelGGL(init_residual, grid, dim3(256), 0, s, b, Ax, x, B.r, n, x_given, B.part,
                      B.counter, B.S);
   if (k > 0) {
-    int info = 0;
-    HIPCHK(hipMemcpyAsync(&info, rc->info, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (info != 0) return DCG_E_NOT_SPD;
     // x_0 = x_{-1} + W (W^T A W)^{-1} W^T r_{-1};  r_0 = b - A x_0, formed as
     // r_{-1} - A (W c) with one product, so that r_0 is the residual of the
     // operator itself and not of the (slightly inexact) stored AW
@@ -372,6 +389,7 @@ static int inner_solve(dcg_operator_s *op, const double *b, double *x, int x_giv
       HIPCHK(hipStreamSynchronize(s));
       rc->k_used = knew;
       rc->n_theta = knew;
+      rc->w_version += 1;
       rc->L_eff = L_eff;
       // AW' = (AZ) U is the product with this operator
       rc->aw_state = 1;
@@ -457,6 +475,7 @@ int dcg_recycle_set_W(dcg_recycle_t rc, const double *W, int kw) {
     return DCG_E_HIP;
   rc->k_used = kw;
   rc->aw_state = 0;
+  rc->w_version += 1;
   rc->n_theta = 0;
   return DCG_OK;
 }
