@@ -207,6 +207,34 @@ int dcg_solve_block(dcg_op_t op, const double *B, double *X, int64_t m,
                     dcg_recycle_t rc, const dcg_params *p, dcg_stats *st,
                     void *ws, size_t ws_bytes);
 
+/* ------------------------------------------------ many independent systems
+ * Solves A_s x_s = b_s for s < count (count <= 4096), each system with its
+ * own operator (size, points, kernel, hyperparameters may all differ) and
+ * its own recycle handle, by deflated CG (Algorithm 1) with the extraction
+ * of section 2.3 per system, exactly as dcg_solve would one by one.  The
+ * systems step in lockstep: one batched pair sweep over all of them, then
+ * one launch per CG vector kernel; a converged system skips its share.
+ *  ops    host array of count distinct operator handles, all created on the
+ *         same stream (DCG_E_ARG otherwise).
+ *  b, x   host arrays of count device FP64 vectors (length n of ops[s]);
+ *         x[s] as in dcg_solve (x_{-1} given when x_given).
+ *  rcs    host array of count recycle handles or NULL entries (plain CG for
+ *         that system); a non-NULL handle appears once.  May itself be NULL.
+ *  p      shared host parameters; p->refine must be 0.  p->tol, max_iter
+ *         apply per system.
+ *  stats  host array of count statistics (may be NULL); t_loop_ms is the
+ *         time of the shared iteration.
+ *  ws     workspace of dcg_solve_batched_workspace_bytes(count, n) bytes,
+ *         n[s] the size of system s, 256-byte aligned.
+ * Returns DCG_OK when every system converged, DCG_NOT_CONVERGED when one
+ * ran out of iterations, else the first negative per-system status (every
+ * system still finishes its solve; stats[s].status holds each one's). */
+size_t dcg_solve_batched_workspace_bytes(int count, const int64_t *n);
+int dcg_solve_batched(int count, const dcg_op_t *ops, const double *const *b,
+                      double *const *x, int x_given, const dcg_recycle_t *rcs,
+                      const dcg_params *p, dcg_stats *stats, void *ws,
+                      size_t ws_bytes);
+
 /* ------------------------------------------ GP hyperparameter gradient
  * For the operator A = s2 k(X, X) + sigma2 I, alpha = A^{-1} y and probe
  * solves U = A^{-1} Z (Z: P <= 16 probe vectors, e.g. Rademacher), writes to

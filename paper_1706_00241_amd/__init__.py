@@ -93,6 +93,13 @@ _SIGS = {
     "dcg_solve_block": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(Params),
                                        ctypes.POINTER(Stats), ctypes.c_void_p, ctypes.c_size_t]),
+    "dcg_solve_batched_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int,
+                                                           ctypes.POINTER(ctypes.c_int64)]),
+    "dcg_solve_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                                         ctypes.POINTER(ctypes.c_void_p),
+                                         ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Params),
+                                         ctypes.POINTER(Stats), ctypes.c_void_p, ctypes.c_size_t]),
     "dcg_mll_grad_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
     "dcg_mll_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_int64,
@@ -361,6 +368,49 @@ def solve_block(op, B, rc=None, tol=1e-6, max_iter=0, check_every=8, out=None):
     _check(status, "dcg_solve_block")
     torch.cuda.current_stream(op.device).synchronize()
     return X.t(), st.as_dict()
+
+
+def solve_batched(ops, bs, rcs=None, x0s=None, tol=1e-6, max_iter=0, L=0, select_largest=True,
+                  check_every=8, use_graph=True, true_residual=False, ws=None):
+    """Independent systems ops[s] x_s = bs[s], each by deflated CG with the
+    basis of rcs[s] (or plain CG for a None entry) and the extraction of the
+    next basis, iterated in lockstep.  The operators must share one stream.
+    Returns (list of x, list of stats dicts)."""
+    torch = _torch()
+    lib = load()
+    count = len(ops)
+    if len(bs) != count or (rcs is not None and len(rcs) != count):
+        raise ValueError("ops, bs and rcs must have the same length")
+    dev = ops[0].device
+    bs = [b.to(device=dev, dtype=torch.float64).contiguous() for b in bs]
+    xs = [torch.empty_like(b) for b in bs]
+    x_given = 0
+    if x0s is not None:
+        for x, x0 in zip(xs, x0s):
+            x.copy_(x0)
+        x_given = 1
+    VP = ctypes.c_void_p * count
+    h_ops = VP(*[op.handle for op in ops])
+    h_b = VP(*[b.data_ptr() for b in bs])
+    h_x = VP(*[x.data_ptr() for x in xs])
+    h_rc = VP(*[(rc.handle if rc is not None else None) for rc in (rcs or [None] * count)])
+    ns = (ctypes.c_int64 * count)(*[op.n for op in ops])
+    if ws is None:
+        nbytes = lib.dcg_solve_batched_workspace_bytes(count, ns)
+        if nbytes == 0:
+            raise DcgError(-1, "dcg_solve_batched_workspace_bytes")
+        _wsbuf, ptr, size = _workspace(nbytes, dev)
+    else:
+        _wsbuf, ptr, size = ws
+    p = Params(tol=float(tol), max_iter=int(max_iter), L=int(L),
+               select_largest=1 if select_largest else 0, check_every=int(check_every),
+               use_graph=1 if use_graph else 0, true_residual=1 if true_residual else 0)
+    st = (Stats * count)()
+    with _ordered(ops[0].stream):
+        status = lib.dcg_solve_batched(count, h_ops, h_b, h_x, x_given, h_rc, ctypes.byref(p),
+                                       st, ptr, size)
+    _check(status, "dcg_solve_batched")
+    return xs, [s.as_dict() for s in st]
 
 
 def mll_grad(op, alpha, U, Z):

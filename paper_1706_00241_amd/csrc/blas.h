@@ -5,6 +5,26 @@
 
 namespace dcg {
 
+// One symmetric pair sweep (the low-precision product's first kernel).
+struct SymvArgs {
+  const void *xr, *xc;
+  int kstride;
+  const float *vin;   // n_pad x MV, leading dimension n_pad
+  double *prow;
+  float *pcol;
+  int64_t n_pad;
+  int nb, dmax, chunk, nchunk;
+  float c0, c1, c2;
+  const int *done;    // optional: skip the launch once the solve converged
+};
+
+// One system of a batched sweep.
+struct BatchItem {
+  SymvArgs a;
+  int kernel;
+  int64_t item0;      // first work item of this system in the batched grid
+};
+
 // Partial sums of the symmetric matvec and how to finish a product.
 struct ReduceArgs {
   const double *prow;
@@ -105,6 +125,11 @@ size_t harmonic_ritz_work_doubles();
 void kernel_constants(int kernel, double ell, float *c0, float *c1, float *c2);
 int launch_symv_sweep(const dcg_operator_s *op, int mv, const int *done);
 int launch_symv_sweep_from(const dcg_operator_s *op, int mv, const float *vin, const int *done);
+SymvArgs symv_args(const dcg_operator_s *op, int mv, const float *vin, const int *done,
+                   int64_t *grid);
+bool symv_batched_supported(int prec, int ksteps);
+int launch_symv_batched(const BatchItem *d_items, int count, int64_t total, int ksteps, int prec,
+                        hipStream_t s);
 ReduceArgs reduce_args(const dcg_operator_s *op, int mv, const double *V, double *Y);
 int matvec_lowprec(const dcg_operator_s *op, const double *V, double *Y, int64_t m);
 int matvec_exact(const dcg_operator_s *op, const double *V, double *Y, int64_t m);

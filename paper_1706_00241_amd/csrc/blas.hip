@@ -93,6 +93,8 @@ __device__ __forceinline__ void small_gemv(const double *Minv, const double *h, 
 // ------------------------------------------------------ CG iteration kernels
 
 // q = s2 * sum(partials) + sigma2 p and the block partials of d = p^T q.
+// The fused multiply-add is written out so that every kernel built from
+// this body (one system or many) rounds q the same way.
 // Also stores p_j and q = A p_j into Z / AZ while j < L.  A block finishes
 // kCgRows rows in groups of 64; each row's partials are split over 4 threads
 // (memory parallelism), then added in a fixed order.  No cross-block step:
@@ -137,7 +139,7 @@ __device__ __forceinline__ void cg_matvec_finish_body(const CgArgs &a, const uns
     if (sg == 0 && i < a.n) {
       const double tot = (seg[0][r] + seg[1][r]) + (seg[2][r] + seg[3][r]);
       const double pi = a.p[i];
-      const double qi = (a.qdirect != nullptr) ? tot : a.red.s2 * tot + a.red.sigma2 * pi;
+      const double qi = (a.qdirect != nullptr) ? tot : fma(a.red.s2, tot, a.red.sigma2 * pi);
       a.q[i] = qi;
       pq += pi * qi;
       if (a.Z != nullptr && j < a.L) {

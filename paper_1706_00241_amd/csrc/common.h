@@ -14,6 +14,7 @@ constexpr int kMaxD = 64;
 constexpr int kMaxK = 64;          // columns of W
 constexpr int kMaxZ = 192;         // k + L (columns of Z)
 constexpr int kRedBlocks = 256;    // blocks of the grid-stride FP64 reductions
+constexpr int kMaxBatch = 4096;    // systems of one batched solve
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 

@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void reduce64(const double *prow, const double
   const int J = static_cast<int>(i / 128);
   const int dlim = ((nb % 2) == 0 && J < nb / 2) ? dmax - 1 : dmax;
   for (int dl = 1; dl <= dlim; ++dl) s += pcol[int64_t(dl - 1) * n_pad + i];
-  Y[i] = s2 * s + sigma2 * V[i];
+  Y[i] = fma(s2, s, sigma2 * V[i]);
 }
 
 template <int KERN>

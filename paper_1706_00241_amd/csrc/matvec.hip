@@ -156,33 +156,13 @@ __device__ __forceinline__ f32x16 tile_r2(const Operand<BF16, KS> &a, const Oper
   return acc;
 }
 
-struct SymvArgs {
-  const void *xr, *xc;
-  int kstride;
-  const float *vin;   // n_pad x MV, leading dimension n_pad
-  double *prow;
-  float *pcol;
-  int64_t n_pad;
-  int nb, dmax, chunk, nchunk;
-  float c0, c1, c2;
-  const int *done;    // optional: skip the launch once the solve converged
-};
 
 template <int KERN, int KS, int MV, bool BF16>
-__global__ __launch_bounds__(256, 2) void symv_kernel(SymvArgs A) {
-  if (A.done != nullptr && *A.done != 0) return;
+__device__ __forceinline__ void symv_body(const SymvArgs &A, const int64_t item) {
   constexpr int TR = (MV == 1 && (!BF16 || KS <= 5)) ? 2 : 1;  // = sweep_tile_rows
   constexpr int BLK = 4 * 32 * TR;
   constexpr int NCT = BLK / 32;
   __shared__ float colpart[MV][4][BLK];
-
-  // Spread consecutive work items over one XCD (workgroups are dealt to the
-  // 8 XCDs round-robin): neighbouring row blocks share most column blocks,
-  // so they then share that XCD's L2.
-  const int64_t G = int64_t(A.nb) * A.nchunk;
-  const int64_t bid = blockIdx.x;
-  const int64_t Gm = G - G % 8;
-  const int64_t item = (bid < Gm) ? (bid % 8) * (Gm / 8) + bid / 8 : bid;
   const int I = static_cast<int>(item / A.nchunk);
   const int c = static_cast<int>(item % A.nchunk);
 
@@ -332,6 +312,41 @@ __global__ __launch_bounds__(256, 2) void symv_kernel(SymvArgs A) {
   }
 }
 
+// Work items are dealt to the 8 XCDs round-robin; the remap gives one XCD a
+// run of consecutive items, i.e. neighbouring row blocks that share most
+// column blocks, so they share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t G) {
+  const int64_t Gm = G - G % 8;
+  return (bid < Gm) ? (bid % 8) * (Gm / 8) + bid / 8 : bid;
+}
+
+template <int KERN, int KS, int MV, bool BF16>
+__global__ __launch_bounds__(256, 2) void symv_kernel(SymvArgs A) {
+  if (A.done != nullptr && *A.done != 0) return;
+  symv_body<KERN, KS, MV, BF16>(A, xcd_remap(blockIdx.x, int64_t(A.nb) * A.nchunk));
+}
+
+// Many operators in one launch: the grid is the concatenation of every
+// system's work items; a workgroup finds its system by binary search over
+// the first-item offsets and skips systems that have converged.
+template <int KS, bool BF16>
+__global__ __launch_bounds__(256, 2) void symv_batched(const BatchItem *sys, int count,
+                                                       int64_t total) {
+  const int64_t g = xcd_remap(blockIdx.x, total);
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (sys[mid].item0 <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchItem &B = sys[lo];
+  if (B.a.done != nullptr && *B.a.done != 0) return;
+  const int64_t item = g - B.item0;
+  if (B.kernel == DCG_RBF) symv_body<DCG_RBF, KS, 1, BF16>(B.a, item);
+  else if (B.kernel == DCG_MATERN32) symv_body<DCG_MATERN32, KS, 1, BF16>(B.a, item);
+  else symv_body<DCG_MATERN52, KS, 1, BF16>(B.a, item);
+}
+
 // Finish y = s2 * (sum of partials) + sigma2 v for the first `cols` vectors.
 __global__ __launch_bounds__(256) void symv_reduce(ReduceArgs A, int cols) {
   const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
@@ -339,7 +354,7 @@ __global__ __launch_bounds__(256) void symv_reduce(ReduceArgs A, int cols) {
   const int m = static_cast<int>(e / A.n);
   const int64_t i = e % A.n;
   const double s = sum_partials(A, m, i);
-  A.Y[m * A.n + i] = A.s2 * s + A.sigma2 * A.V[m * A.n + i];
+  A.Y[m * A.n + i] = fma(A.s2, s, A.sigma2 * A.V[m * A.n + i]);
 }
 
 // FP64 -> FP32 staging of up to 4 vectors, zero padded to n_pad.
@@ -405,8 +420,10 @@ static int dispatch_ks(const dcg_operator_s *op, const SymvArgs &a, int64_t grid
   return -1;
 }
 
-// Enqueue the symmetric pair sweep over op->vin (mv = 1 or 4 vectors).
-int launch_symv_sweep_from(const dcg_operator_s *op, int mv, const float *vin, const int *done) {
+// Arguments of the symmetric pair sweep of op over vin (mv = 1 or 4
+// vectors) and its grid.
+SymvArgs symv_args(const dcg_operator_s *op, int mv, const float *vin, const int *done,
+                   int64_t *grid) {
   MatvecPlan p = make_plan(op->g.n_pad, sweep_blk(op->g, mv));
   SymvArgs a;
   a.xr = op->xr;
@@ -422,15 +439,55 @@ int launch_symv_sweep_from(const dcg_operator_s *op, int mv, const float *vin, c
   a.nchunk = p.nchunk;
   a.done = done;
   kernel_constants(op->kernel, op->ell, &a.c0, &a.c1, &a.c2);
+  if (grid != nullptr) *grid = p.grid;
+  return a;
+}
+
+// The batched sweep is built for the two-tile-row single-vector kernels.
+bool symv_batched_supported(int prec, int ksteps) {
+  if (prec == DCG_PREC_BF16 || prec == DCG_PREC_BF16X2) return ksteps >= 1 && ksteps <= 5;
+  if (prec == DCG_PREC_FP32) return ksteps == 5 || ksteps == 9 || ksteps == 13 || ksteps == 17;
+  return false;
+}
+
+int launch_symv_batched(const BatchItem *d_items, int count, int64_t total, int ksteps, int prec,
+                        hipStream_t s) {
+  if (!symv_batched_supported(prec, ksteps) || total < 1) return DCG_E_ARG;
+  const dim3 g(static_cast<unsigned>(total)), b(256);
+  if (prec == DCG_PREC_BF16 || prec == DCG_PREC_BF16X2) {
+    switch (ksteps) {
+      case 1: hipLaunchKernelGGL((symv_batched<1, true>), g, b, 0, s, d_items, count, total); break;
+      case 2: hipLaunchKernelGGL((symv_batched<2, true>), g, b, 0, s, d_items, count, total); break;
+      case 3: hipLaunchKernelGGL((symv_batched<3, true>), g, b, 0, s, d_items, count, total); break;
+      case 4: hipLaunchKernelGGL((symv_batched<4, true>), g, b, 0, s, d_items, count, total); break;
+      default: hipLaunchKernelGGL((symv_batched<5, true>), g, b, 0, s, d_items, count, total); break;
+    }
+  } else if (prec == DCG_PREC_FP32) {
+    switch (ksteps) {
+      case 5: hipLaunchKernelGGL((symv_batched<5, false>), g, b, 0, s, d_items, count, total); break;
+      case 9: hipLaunchKernelGGL((symv_batched<9, false>), g, b, 0, s, d_items, count, total); break;
+      case 13: hipLaunchKernelGGL((symv_batched<13, false>), g, b, 0, s, d_items, count, total); break;
+      case 17: hipLaunchKernelGGL((symv_batched<17, false>), g, b, 0, s, d_items, count, total); break;
+      default: return DCG_E_ARG;
+    }
+  } else {
+    return DCG_E_ARG;
+  }
+  return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
+}
+
+int launch_symv_sweep_from(const dcg_operator_s *op, int mv, const float *vin, const int *done) {
+  int64_t grid = 0;
+  const SymvArgs a = symv_args(op, mv, vin, done, &grid);
   int rc = -1;
   if (mv == 1) {
-    if (op->kernel == DCG_RBF) rc = dispatch_ks<DCG_RBF, 1>(op, a, p.grid);
-    else if (op->kernel == DCG_MATERN32) rc = dispatch_ks<DCG_MATERN32, 1>(op, a, p.grid);
-    else rc = dispatch_ks<DCG_MATERN52, 1>(op, a, p.grid);
+    if (op->kernel == DCG_RBF) rc = dispatch_ks<DCG_RBF, 1>(op, a, grid);
+    else if (op->kernel == DCG_MATERN32) rc = dispatch_ks<DCG_MATERN32, 1>(op, a, grid);
+    else rc = dispatch_ks<DCG_MATERN52, 1>(op, a, grid);
   } else {
-    if (op->kernel == DCG_RBF) rc = dispatch_ks<DCG_RBF, 4>(op, a, p.grid);
-    else if (op->kernel == DCG_MATERN32) rc = dispatch_ks<DCG_MATERN32, 4>(op, a, p.grid);
-    else rc = dispatch_ks<DCG_MATERN52, 4>(op, a, p.grid);
+    if (op->kernel == DCG_RBF) rc = dispatch_ks<DCG_RBF, 4>(op, a, grid);
+    else if (op->kernel == DCG_MATERN32) rc = dispatch_ks<DCG_MATERN32, 4>(op, a, grid);
+    else rc = dispatch_ks<DCG_MATERN52, 4>(op, a, grid);
   }
   if (rc != 0) return DCG_E_ARG;
   return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;

@@ -1,0 +1,63 @@
+// The phases of one deflated-CG solve (Algorithm 1 of the paper), shared by
+// the single-system driver and the batched driver.
+#pragma once
+
+#include <chrono>
+
+#include "blas.h"
+
+namespace dcg {
+
+using Clock = std::chrono::steady_clock;
+inline double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+#define HIPCHK(x)                                      \
+  do {                                                 \
+    if ((x) != hipSuccess) return DCG_E_HIP;           \
+  } while (0)
+
+// Device buffers of one solve, carved from the caller's solve workspace.
+struct SolveBuffers {
+  SolveState *S;
+  unsigned *counter;
+  double *r, *p, *q, *part, *part_h, *hist_res, *hist_d, *hist_alpha, *hist_beta;
+  double *tmp1, *tmp2, *tmp3;
+};
+
+struct InnerResult {
+  int iters = 0, matvecs = 0, k_used = 0, k_next = 0, status = DCG_OK;
+  int sweeps_timed = 0;
+  double t_sweeps = 0.0;
+  double relres = 0.0;
+  double t_init = 0.0, t_loop = 0.0, t_refresh = 0.0;
+};
+
+// State carried between the phases of one solve.
+struct SolveCtx {
+  SolveBuffers B;
+  CgArgs a;
+  int k = 0, L = 0, matvecs = 0;
+  double tol = 0.0;
+  bool extract = true;
+};
+
+size_t solve_workspace_total(int64_t n);
+SolveBuffers solve_buffers(void *ws, int64_t n);
+
+// Phase 1: AW, (W^T A W)^{-1}, r_0, the deflated start and p_0 (ends with a
+// stream synchronisation).
+int solve_init(dcg_operator_s *op, const double *b, double *x, int x_given, dcg_recycle_s *rc,
+               const dcg_params *p, double tol, void *ws, bool extract, SolveCtx *ctx,
+               InnerResult *out);
+// Phase 2: the CG steps until the device state says done.
+int solve_loop(dcg_operator_s *op, const dcg_params *p, SolveCtx *ctx, InnerResult *out);
+// Phase 3: the harmonic Ritz extraction of the next basis (section 2.3).
+int solve_extract(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_params *p, SolveCtx *ctx,
+                  InnerResult *out);
+// |b - A x| / |b| with the low-precision (exact = 0) or FP64 operator.
+int true_residual(dcg_operator_s *op, const double *b, const double *x, int exact,
+                  const SolveBuffers &B, double *rel);
+
+}  // namespace dcg

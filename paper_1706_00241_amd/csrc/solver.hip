@@ -14,7 +14,7 @@
 #include <cstring>
 #include <new>
 
-#include "blas.h"
+#include "solve.h"
 
 namespace dcg {
 
@@ -56,6 +56,8 @@ static SolveLayout solve_layout(int64_t n) {
   return L;
 }
 
+size_t solve_workspace_total(int64_t n) { return solve_layout(n).total; }
+
 struct RecycleLayout {
   size_t Z, AZ, Wt, AWt, F, G, U, eigw, M, Minv, Mwork, N, small, info, gemm, total;
 };
@@ -89,14 +91,7 @@ static RecycleLayout recycle_layout(int64_t n, int k, int L) {
   return R;
 }
 
-struct SolveBuffers {
-  SolveState *S;
-  unsigned *counter;
-  double *r, *p, *q, *part, *part_h, *hist_res, *hist_d, *hist_alpha, *hist_beta;
-  double *tmp1, *tmp2, *tmp3;
-};
-
-static SolveBuffers solve_buffers(void *ws, int64_t n) {
+SolveBuffers solve_buffers(void *ws, int64_t n) {
   const SolveLayout L = solve_layout(n);
   char *b = static_cast<char *>(ws);
   SolveBuffers B;
@@ -116,24 +111,6 @@ static SolveBuffers solve_buffers(void *ws, int64_t n) {
   B.tmp3 = reinterpret_cast<double *>(b + L.tmp3);
   return B;
 }
-
-using Clock = std::chrono::steady_clock;
-static double ms_since(Clock::time_point t0) {
-  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
-}
-
-#define HIPCHK(x)                                      \
-  do {                                                 \
-    if ((x) != hipSuccess) return DCG_E_HIP;           \
-  } while (0)
-
-struct InnerResult {
-  int iters = 0, matvecs = 0, k_used = 0, k_next = 0, status = DCG_OK;
-  int sweeps_timed = 0;
-  double t_sweeps = 0.0;
-  double relres = 0.0;
-  double t_init = 0.0, t_loop = 0.0, t_refresh = 0.0;
-};
 
 // Make AZ[:, :k_used] the product of W with the current operator.
 static int refresh_AW(dcg_operator_s *op, dcg_recycle_s *rc, int *matvecs) {
@@ -237,11 +214,11 @@ static int enqueue_cg_step(dcg_operator_s *op, const CgArgs &a, hipEvent_t ev0 =
   return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
 }
 
-// One deflated-CG solve of A x = b (Algorithm 1), then the extraction of the
-// next basis (section 2.3) when rc is given.
-static int inner_solve(dcg_operator_s *op, const double *b, double *x, int x_given,
-                       dcg_recycle_s *rc, const dcg_params *p, double tol, void *ws,
-                       InnerResult *out, bool extract = true) {
+// Phase 1 of a solve (Algorithm 1 initialisation): AW, M^{-1}, r_0, the
+// deflated start and p_0; leaves the device state ready for the iteration.
+int solve_init(dcg_operator_s *op, const double *b, double *x, int x_given,
+                      dcg_recycle_s *rc, const dcg_params *p, double tol, void *ws, bool extract,
+                      SolveCtx *ctx, InnerResult *out) {
   const auto t0 = Clock::now();
   hipStream_t s = op->stream;
   const int64_t n = op->g.n, n_pad = op->g.n_pad;
@@ -293,9 +270,24 @@ static int inner_solve(dcg_operator_s *op, const double *b, double *x, int x_giv
   HIPCHK(hipStreamSynchronize(s));
   out->t_init = ms_since(t0);
 
-  // ---- iteration loop
+  ctx->B = B;
+  ctx->a = cg_args(op, B, x, rc, Minv, k, L, tol, max_iter);
+  ctx->k = k;
+  ctx->L = L;
+  ctx->matvecs = matvecs;
+  ctx->tol = tol;
+  ctx->extract = extract;
+  return DCG_OK;
+}
+
+// Phase 2: the iteration, in chunks of check_every steps (one hipGraph per
+// chunk unless profiling), until the device state says done.
+int solve_loop(dcg_operator_s *op, const dcg_params *p, SolveCtx *ctx, InnerResult *out) {
+  hipStream_t s = op->stream;
+  const SolveBuffers &B = ctx->B;
+  const CgArgs &a = ctx->a;
+  const double tol = ctx->tol;
   const auto t1 = Clock::now();
-  CgArgs a = cg_args(op, B, x, rc, Minv, k, L, tol, max_iter);
   const int chunk = std::max(1, p->check_every);
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -356,15 +348,24 @@ static int inner_solve(dcg_operator_s *op, const double *b, double *x, int x_giv
   out->t_loop = ms_since(t1);
   out->iters = hs.iter;
   out->relres = hs.relres;
-  matvecs += hs.iter;
+  ctx->matvecs += hs.iter;
   out->status = hs.status != 0 ? hs.status : (hs.relres <= tol ? DCG_OK : DCG_NOT_CONVERGED);
-  out->k_used = k;
-  out->k_next = k;
+  out->k_used = ctx->k;
+  out->k_next = ctx->k;
+  return DCG_OK;
+}
 
-  // ---- harmonic Ritz extraction of W' = Z U (Eq. 7)
+
+// Phase 3: the harmonic Ritz extraction of W' = Z U (section 2.3, Eq. 7)
+// from Z = [W, P_L] of this solve.
+int solve_extract(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_params *p, SolveCtx *ctx,
+                         InnerResult *out) {
+  hipStream_t s = op->stream;
+  const int64_t n = op->g.n;
+  const int k = ctx->k;
   const auto t2 = Clock::now();
-  if (rc != nullptr && extract && out->status >= 0) {
-    const int L_eff = std::min(L, hs.iter);
+  if (rc != nullptr && ctx->extract && out->status >= 0) {
+    const int L_eff = std::min(ctx->L, out->iters);
     const int mz = k + L_eff;
     if (mz > 0) {
       enqueue_tsgemm_tn(s, rc->AZ, rc->Z, n, mz, mz, rc->gemm, kGemmPartDoubles, rc->F, mz, 1);
@@ -402,12 +403,26 @@ static int inner_solve(dcg_operator_s *op, const double *b, double *x, int x_giv
     }
   }
   out->t_refresh = ms_since(t2);
-  out->matvecs = matvecs;
+  out->matvecs = ctx->matvecs;
   return DCG_OK;
 }
 
+// One deflated-CG solve of A x = b (Algorithm 1), then the extraction of the
+// next basis (section 2.3) when rc is given.
+static int inner_solve(dcg_operator_s *op, const double *b, double *x, int x_given,
+                       dcg_recycle_s *rc, const dcg_params *p, double tol, void *ws,
+                       InnerResult *out, bool extract = true) {
+  SolveCtx ctx;
+  int st = solve_init(op, b, x, x_given, rc, p, tol, ws, extract, &ctx, out);
+  if (st != DCG_OK) return st;
+  st = solve_loop(op, p, &ctx, out);
+  if (st != DCG_OK) return st;
+  return solve_extract(op, rc, p, &ctx, out);
+}
+
+
 // |b - A x| / |b| with the low-precision (exact = 0) or FP64 operator.
-static int true_residual(dcg_operator_s *op, const double *b, const double *x, int exact,
+int true_residual(dcg_operator_s *op, const double *b, const double *x, int exact,
                          const SolveBuffers &B, double *rel) {
   hipStream_t s = op->stream;
   const int64_t n = op->g.n;

@@ -66,3 +66,25 @@ def test_argument_validation_without_gpu(L):
     assert L.dcg_matvec(None, None, None, 1) == -1
     assert L.dcg_status_string(-2).decode().startswith("operator not positive")
     assert "gfx950" in L.dcg_version().decode()
+
+
+def test_batched_arguments_without_gpu(L):
+    import paper_1706_00241_amd as dcg
+    ns = (ctypes.c_int64 * 3)(1000, 2048, 1)
+    one = L.dcg_solve_workspace_bytes(1000, 0, 0)
+    total = L.dcg_solve_batched_workspace_bytes(3, ns)
+    # every system's solve workspace plus the device tables
+    assert total >= one + L.dcg_solve_workspace_bytes(2048, 0, 0) + L.dcg_solve_workspace_bytes(1, 0, 0)
+    assert L.dcg_solve_batched_workspace_bytes(0, ns) == 0
+    assert L.dcg_solve_batched_workspace_bytes(5000, None) == 0
+    bad = (ctypes.c_int64 * 2)(10, 0)
+    assert L.dcg_solve_batched_workspace_bytes(2, bad) == 0
+    p = dcg.Params(tol=1e-6)
+    VP = ctypes.c_void_p * 2
+    null2 = VP(None, None)
+    st = (dcg.Stats * 2)()
+    assert L.dcg_solve_batched(0, null2, null2, null2, 0, None, ctypes.byref(p), st, None, 0) == -1
+    assert L.dcg_solve_batched(2, null2, null2, null2, 0, None, ctypes.byref(p), st, None, 0) == -1
+    assert L.dcg_solve_batched(2, None, null2, null2, 0, None, ctypes.byref(p), st, None, 0) == -1
+    pr = dcg.Params(tol=1e-6, refine=1)
+    assert L.dcg_solve_batched(2, null2, null2, null2, 0, None, ctypes.byref(pr), st, None, 0) == -1
