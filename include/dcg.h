@@ -138,6 +138,22 @@ int dcg_matvec(dcg_op_t op, const double *V, double *Y, int64_t m);
  * iterative refinement).  Same layout rules as dcg_matvec. */
 int dcg_matvec_exact(dcg_op_t op, const double *V, double *Y, int64_t m);
 
+/* Work-item target of the operator's low-precision pair sweep (256..8192,
+ * default 2048): the sweep groups block offsets into work items so that one
+ * launch has about this many.  More items balance the 256 compute units
+ * better; fewer items read fewer row partials when the product is finished.
+ * Any value gives the same product up to the FP64 summation order of the
+ * row partials.  DCG_E_ARG outside the range. */
+int dcg_set_sweep_items(dcg_op_t op, int items);
+
+/* Autotuner of the sweep plan: times `reps` single-vector sweeps (1..1000)
+ * for each distinct plan of the targets 256, 512, ..., 8192 on the
+ * operator's stream, keeps the fastest and returns it in *items_out with its
+ * time per sweep in *ms_out (either may be NULL).  Overwrites the operator's
+ * staged vector and partial sums, so it must not overlap a solve with the
+ * same operator.  FP64 operators have a fixed plan: nothing is timed. */
+int dcg_tune_operator(dcg_op_t op, int reps, int *items_out, double *ms_out);
+
 void dcg_destroy_operator(dcg_op_t op);
 
 /* ---------------------------------------------------------- recycle handle

@@ -73,6 +73,10 @@ _SIGS = {
     "dcg_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
     "dcg_matvec_exact": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_int64]),
+    "dcg_set_sweep_items": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "dcg_tune_operator": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_double)]),
     "dcg_destroy_operator": (None, [ctypes.c_void_p]),
     "dcg_recycle_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int, ctypes.c_int]),
     "dcg_recycle_create": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int, ctypes.c_int,
@@ -222,6 +226,18 @@ class Operator:
     def matvec_exact(self, V):
         """A V with the FP64 operator on the unrounded points."""
         return self._mv(load().dcg_matvec_exact, V)
+
+    def set_sweep_items(self, items):
+        """Work-item target of the pair sweep (256..8192)."""
+        _check(load().dcg_set_sweep_items(self.handle, int(items)), "dcg_set_sweep_items")
+
+    def tune(self, reps=5):
+        """Time the sweep plans and keep the fastest; returns (items, ms per sweep)."""
+        items, ms = ctypes.c_int(), ctypes.c_double()
+        with _ordered(self.stream):
+            _check(load().dcg_tune_operator(self.handle, int(reps), ctypes.byref(items),
+                                            ctypes.byref(ms)), "dcg_tune_operator")
+        return items.value, ms.value
 
     def close(self):
         if getattr(self, "handle", None) is not None:

@@ -63,7 +63,15 @@ inline int sweep_tile_rows(int mv, int prec, int ksteps) {
 }
 inline int sweep_blk(const Geometry &g, int mv) { return 128 * sweep_tile_rows(mv, g.prec, g.ksteps); }
 
-MatvecPlan make_plan(int64_t n_pad, int blk);
+// Work items of one pair sweep: the plan groups block offsets into chunks so
+// that a sweep has about `items` work items.  The default suits one large
+// operator; dcg_tune_operator picks the value per operator by timing.
+constexpr int kSweepItemsMin = 256;
+constexpr int kSweepItemsDefault = 2048;
+constexpr int kSweepItemsMax = 8192;
+
+MatvecPlan make_plan(int64_t n_pad, int blk, int items = kSweepItemsDefault);
+// Partial-sum floats of a sweep, for the largest plan any item target gives.
 size_t matvec_partial_floats(int64_t n_pad, int mv, int blk);
 
 }  // namespace dcg
@@ -74,6 +82,7 @@ struct dcg_operator_s {
   double ell, s2, sigma2;
   hipStream_t stream;
   uint64_t generation;   // bumped by every hyperparameter change
+  int sweep_items;       // work-item target of the low-precision pair sweep
   double *x64r, *x64c;   // FP64 augmented operands of the exact operator
   double *vin64;         // staged FP64 input vector, n_pad
   double *part64;        // partial sums of the FP64 sweep

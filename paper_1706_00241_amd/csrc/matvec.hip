@@ -69,20 +69,21 @@ Geometry make_geometry(int64_t n, int d, int prec) {
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-MatvecPlan make_plan(int64_t n_pad, int blk) {
+MatvecPlan make_plan(int64_t n_pad, int blk, int items) {
   MatvecPlan p;
   p.blk = blk;
   p.nb = static_cast<int>(n_pad / p.blk);
   p.dmax = p.nb / 2;
   const int ndelta = p.dmax + 1;
-  p.chunk = static_cast<int>(std::max<int64_t>(1, cdiv(int64_t(ndelta) * p.nb, 2048)));
+  p.chunk = static_cast<int>(std::max<int64_t>(1, cdiv(int64_t(ndelta) * p.nb, items)));
   p.nchunk = static_cast<int>(cdiv(ndelta, p.chunk));
   p.grid = int64_t(p.nb) * p.nchunk;
   return p;
 }
 
 size_t matvec_partial_floats(int64_t n_pad, int mv, int blk) {
-  MatvecPlan p = make_plan(n_pad, blk);
+  // chunks per row block grow with the item target
+  MatvecPlan p = make_plan(n_pad, blk, kSweepItemsMax);
   // row partials are FP64 (two floats each), column partials FP32
   return size_t(2 * p.nchunk + p.dmax) * size_t(n_pad) * size_t(mv);
 }
@@ -424,7 +425,7 @@ static int dispatch_ks(const dcg_operator_s *op, const SymvArgs &a, int64_t grid
 // vectors) and its grid.
 SymvArgs symv_args(const dcg_operator_s *op, int mv, const float *vin, const int *done,
                    int64_t *grid) {
-  MatvecPlan p = make_plan(op->g.n_pad, sweep_blk(op->g, mv));
+  MatvecPlan p = make_plan(op->g.n_pad, sweep_blk(op->g, mv), op->sweep_items);
   SymvArgs a;
   a.xr = op->xr;
   a.xc = op->xc;
@@ -498,7 +499,7 @@ int launch_symv_sweep(const dcg_operator_s *op, int mv, const int *done) {
 }
 
 ReduceArgs reduce_args(const dcg_operator_s *op, int mv, const double *V, double *Y) {
-  MatvecPlan p = make_plan(op->g.n_pad, sweep_blk(op->g, mv));
+  MatvecPlan p = make_plan(op->g.n_pad, sweep_blk(op->g, mv), op->sweep_items);
   ReduceArgs r;
   r.prow = reinterpret_cast<const double *>(op->part);
   r.pcol = op->part + size_t(2 * p.nchunk) * op->g.n_pad * mv;

@@ -207,6 +207,7 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel, doubl
   op->sigma2 = sigma2;
   op->stream = static_cast<hipStream_t>(stream);
   op->generation = 1;
+  op->sweep_items = kSweepItemsDefault;
   op->x64r = reinterpret_cast<double *>(base + L.x64r);
   op->x64c = reinterpret_cast<double *>(base + L.x64c);
   op->vin64 = reinterpret_cast<double *>(base + L.vin64);
@@ -260,6 +261,65 @@ int dcg_matvec(dcg_op_t op, const double *V, double *Y, int64_t m) {
 int dcg_matvec_exact(dcg_op_t op, const double *V, double *Y, int64_t m) {
   if (op == nullptr || V == nullptr || Y == nullptr || m < 1) return DCG_E_ARG;
   return matvec_exact(op, V, Y, m);
+}
+
+int dcg_set_sweep_items(dcg_op_t op, int items) {
+  if (op == nullptr || items < kSweepItemsMin || items > kSweepItemsMax) return DCG_E_ARG;
+  op->sweep_items = items;
+  return DCG_OK;
+}
+
+int dcg_tune_operator(dcg_op_t op, int reps, int *items_out, double *ms_out) {
+  if (op == nullptr || reps < 1 || reps > 1000) return DCG_E_ARG;
+  if (op->g.prec == DCG_PREC_FP64) {
+    // the FP64 sweep has a fixed plan
+    if (items_out != nullptr) *items_out = op->sweep_items;
+    if (ms_out != nullptr) *ms_out = 0.0;
+    return DCG_OK;
+  }
+  static const int cand[] = {256, 512, 1024, 2048, 4096, 8192};
+  hipStream_t s = op->stream;
+  // the sweep's cost does not depend on the vector's values
+  if (hipMemsetAsync(op->vin, 0, size_t(op->g.n_pad) * 4 * sizeof(float), s) != hipSuccess)
+    return DCG_E_HIP;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess) return DCG_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return DCG_E_HIP;
+  }
+  const int keep = op->sweep_items;
+  int best = keep, last_chunk = -1, status = DCG_OK;
+  float best_ms = -1.0f;
+  for (int items : cand) {
+    const MatvecPlan p = make_plan(op->g.n_pad, sweep_blk(op->g, 1), items);
+    if (p.chunk == last_chunk) continue;   // the same plan as the previous target
+    last_chunk = p.chunk;
+    op->sweep_items = items;
+    status = launch_symv_sweep(op, 1, nullptr);   // warm-up
+    if (status != DCG_OK) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { status = DCG_E_HIP; break; }
+    for (int r = 0; r < reps && status == DCG_OK; ++r) status = launch_symv_sweep(op, 1, nullptr);
+    if (status != DCG_OK) break;
+    float ms = 0.0f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      status = DCG_E_HIP;
+      break;
+    }
+    ms /= static_cast<float>(reps);
+    if (best_ms < 0.0f || ms < best_ms) {
+      best_ms = ms;
+      best = items;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  op->sweep_items = (status == DCG_OK) ? best : keep;
+  if (status != DCG_OK) return status;
+  if (items_out != nullptr) *items_out = best;
+  if (ms_out != nullptr) *ms_out = best_ms;
+  return DCG_OK;
 }
 
 void dcg_destroy_operator(dcg_op_t op) { delete op; }

@@ -63,6 +63,8 @@ def test_argument_validation_without_gpu(L):
     st = dcg.Stats()
     assert L.dcg_solve(None, None, None, 0, None, ctypes.byref(p), ctypes.byref(st), None, 0) == -1
     assert L.dcg_set_hyper(None, 1.0, 1.0, 1.0) == -1
+    assert L.dcg_set_sweep_items(None, 2048) == -1
+    assert L.dcg_tune_operator(None, 5, None, None) == -1
     assert L.dcg_matvec(None, None, None, 1) == -1
     assert L.dcg_status_string(-2).decode().startswith("operator not positive")
     assert "gfx950" in L.dcg_version().decode()
