@@ -660,7 +660,7 @@ __global__ __launch_bounds__(256) void residual_norms(const double *b, const dou
   double rr = 0.0, bb = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
     const double bi = b[i];
-    const double ri = bi - Ax[i];
+    const double ri = (Ax != nullptr) ? bi - Ax[i] : bi;
     out[i] = ri;
     rr += ri * ri;
     bb += bi * bi;

@@ -197,13 +197,19 @@ static CgArgs cg_args(dcg_operator_s *op, const SolveBuffers &B, double *x, dcg_
   return a;
 }
 
+// Timing events around the product: inside a stream capture they become
+// event-record nodes of the graph, so replays time the graph's own launches.
+static hipError_t record_event(hipEvent_t ev, hipStream_t s, bool in_graph) {
+  return in_graph ? hipEventRecordWithFlags(ev, s, hipEventRecordExternal) : hipEventRecord(ev, s);
+}
+
 static int enqueue_cg_step(dcg_operator_s *op, const CgArgs &a, hipEvent_t ev0 = nullptr,
-                           hipEvent_t ev1 = nullptr) {
-  if (ev0 != nullptr && hipEventRecord(ev0, op->stream) != hipSuccess) return DCG_E_HIP;
+                           hipEvent_t ev1 = nullptr, bool in_graph = false) {
+  if (ev0 != nullptr && record_event(ev0, op->stream, in_graph) != hipSuccess) return DCG_E_HIP;
   const int st = (op->g.prec == DCG_PREC_FP64)
                      ? matvec_exact_done(op, a.p, op->ytmp, 1, &a.S->done)
                      : launch_symv_sweep(op, 1, &a.S->done);
-  if (ev1 != nullptr && hipEventRecord(ev1, op->stream) != hipSuccess) return DCG_E_HIP;
+  if (ev1 != nullptr && record_event(ev1, op->stream, in_graph) != hipSuccess) return DCG_E_HIP;
   if (st != DCG_OK) return st;
   const dim3 grid(static_cast<unsigned>(cdiv(op->g.n, 256)));
   hipLaunchKernelGGL(cg_matvec_finish, dim3(static_cast<unsigned>(a.nblk_q)), dim3(256), 0,
@@ -299,13 +305,21 @@ int solve_loop(dcg_operator_s *op, const dcg_params *p, SolveCtx *ctx, InnerResu
     // no system-scope fence: the events only time device work on this stream
     for (int e = 0; e < 2 * pchunk; ++e)
       HIPCHK(hipEventCreateWithFlags(&evs[e], hipEventDisableSystemFence));
-  if (p->use_graph && !prof) {
+  if (p->use_graph) {
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     int st = DCG_OK;
-    for (int c = 0; c < chunk && st == DCG_OK; ++c) st = enqueue_cg_step(op, a);
+    for (int c = 0; c < pchunk && st == DCG_OK; ++c)
+      st = prof ? enqueue_cg_step(op, a, evs[2 * c], evs[2 * c + 1], true) : enqueue_cg_step(op, a);
     hipError_t e = hipStreamEndCapture(s, &graph);
-    if (st != DCG_OK || e != hipSuccess) return st != DCG_OK ? st : DCG_E_HIP;
-    HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    if (st == DCG_OK && e == hipSuccess) {
+      HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    } else {
+      if (graph != nullptr) (void)hipGraphDestroy(graph);
+      graph = nullptr;
+      // a runtime that cannot capture timing events: time eager launches
+      if (!prof) return st != DCG_OK ? st : DCG_E_HIP;
+      (void)hipGetLastError();
+    }
   }
   SolveState hs;
   hs.iter = 0;
@@ -574,12 +588,17 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
   double rel = 0.0;
   int status = DCG_NOT_CONVERGED;
   for (int t = 0; t <= outer_max; ++t) {
-    int rcode = matvec_exact(op, x, B.tmp3, 1);
-    if (rcode != DCG_OK) return st->status = rcode;
-    st->matvecs_exact += 1;
+    // from x = 0 the first residual is b itself
+    const bool zero_start = (t == 0 && !x_given);
+    if (!zero_start) {
+      int rcode = matvec_exact(op, x, B.tmp3, 1);
+      if (rcode != DCG_OK) return st->status = rcode;
+      st->matvecs_exact += 1;
+    }
     HIPCHK(hipMemsetAsync(B.counter + 2, 0, sizeof(unsigned), s));
     hipLaunchKernelGGL(residual_norms, dim3(static_cast<unsigned>(std::min<int64_t>(kRedBlocks, cdiv(n, 256)))),
-                       dim3(256), 0, s, b, B.tmp3, n, rhs, B.part, B.counter + 2, B.S->cvec);
+                       dim3(256), 0, s, b, zero_start ? nullptr : B.tmp3, n, rhs, B.part,
+                       B.counter + 2, B.S->cvec);
     double h[2];
     HIPCHK(hipMemcpyAsync(h, B.S->cvec, sizeof(h), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -588,7 +607,7 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
     if (rel <= p->tol) { status = DCG_OK; break; }
     if (t == outer_max) break;
     InnerResult R;
-    rcode = inner_solve(op, rhs, delta, 0, rc, p, p->inner_tol, ws, &R,
+    int rcode = inner_solve(op, rhs, delta, 0, rc, p, p->inner_tol, ws, &R,
                         p->refresh_every != 0 || st->outer_steps == 0);
     if (rcode != DCG_OK) return st->status = rcode;
     st->iters += R.iters;

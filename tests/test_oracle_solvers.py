@@ -218,6 +218,100 @@ def test_refine_recovers_fp64_solution_from_bf16_operator():
         assert a <= 3 * (rho + 1e-4) * np.linalg.cond(A64) ** 0.5 * c
 
 
+def _pcg_residuals(A, M_inv, b, steps):
+    """Textbook preconditioned CG (short recurrence), residual norms."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = M_inv @ r
+    p = z.copy()
+    rz = r @ z
+    out = [np.linalg.norm(r) / np.linalg.norm(b)]
+    for _ in range(steps):
+        q = A @ p
+        a = rz / (p @ q)
+        x += a * p
+        r -= a * q
+        out.append(np.linalg.norm(r) / np.linalg.norm(b))
+        z = M_inv @ r
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return np.array(out)
+
+
+def test_fcg_exact_preconditioner_one_step():
+    X, A, b = _kernel_system(n=150, sigma2=1e-3, seed=21)
+    x, hist, D, _ = R.fcg_outer(lambda v: A @ v, lambda r: np.linalg.solve(A, r), b, tol=1e-12)
+    assert len(D) == 1 and hist[-1] <= 1e-12
+    c = scipy.linalg.cho_factor(A)
+    xc = scipy.linalg.cho_solve(c, b)
+    assert np.linalg.norm(x - xc) / np.linalg.norm(xc) <= 1e-9
+
+
+def test_fcg_fixed_preconditioner_is_pcg():
+    """With a fixed SPD preconditioner flexible CG with full orthogonalisation
+    generates the PCG iterates: the same residual norms step by step."""
+    X, A, b = _kernel_system(n=120, sigma2=1e-2, seed=22)
+    g = np.random.default_rng(23)
+    # a fixed SPD approximation of A^{-1}: the inverse of a perturbed A
+    E = 0.05 * g.standard_normal(A.shape)
+    M_inv = np.linalg.inv(A + 0.1 * (E @ E.T) + 1e-3 * np.eye(120))
+    steps = 12
+    _, hist, D, AD = R.fcg_outer(lambda v: A @ v, lambda r: M_inv @ r, b, tol=0.0,
+                                 max_outer=steps)
+    ref = _pcg_residuals(A, M_inv, b, steps)
+    np.testing.assert_allclose(np.array(hist), ref, rtol=1e-6)
+
+
+def test_fcg_directions_A_orthogonal_with_variable_preconditioner():
+    X, A, b = _kernel_system(n=200, sigma2=1e-3, seed=24)
+    # the preconditioner: CG to 1e-2 on the operator of bf16-rounded points
+    Alow = K.operator(P.round_bf16(X), K.RBF, 1.0, 1.0, 1e-3)
+    pre = lambda r: C.defcg(Alow, r, tol=1e-2).x
+    x, hist, D, AD = R.fcg_outer(lambda v: A @ v, pre, b, tol=1e-10)
+    Dm = np.column_stack(D)
+    G = Dm.T @ A @ Dm
+    off = G - np.diag(np.diag(G))
+    assert np.abs(off).max() <= 1e-8 * np.abs(np.diag(G)).max()
+    # the products carried along are the products of the directions
+    np.testing.assert_allclose(np.column_stack(AD), A @ Dm, rtol=0, atol=1e-10 * np.abs(A @ Dm).max())
+    assert hist[-1] <= 1e-10
+    assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= 1e-9
+    # the A-norm of the error never grows
+    xs = np.linalg.solve(A, b)
+    errs = []
+    for t in range(1, len(D) + 1):
+        xt = sum(((Dm[:, j] @ b) / G[j, j]) * Dm[:, j] for j in range(t))
+        e = xt - xs
+        errs.append(e @ A @ e)
+    assert all(errs[i + 1] <= errs[i] * (1 + 1e-9) for i in range(len(errs) - 1))
+
+
+def test_fcg_zero_rhs():
+    A = np.eye(5) * 2.0
+    x, hist, D, _ = R.fcg_outer(lambda v: A @ v, lambda r: r / 2.0, np.zeros(5), tol=1e-8)
+    assert len(D) == 0 and hist == [0.0] and not np.any(x)
+
+
+def test_refine_fcg_beats_plain_refinement_on_bf16_operator():
+    g = np.random.default_rng(13)
+    X = g.uniform(-1, 1, (300, 6))
+    ell = 0.5 * workloads.median_distance(X)
+    A64 = K.operator(X, K.MATERN52, ell, 1.0, 1e-3)
+    # 4-bit mantissas: an operator error large enough that it, not the
+    # inner tolerance, limits plain refinement
+    mant, ex = np.frexp(X)
+    Xl = np.ldexp(np.rint(mant * 16.0) / 16.0, ex)
+    Alow = K.operator(Xl, K.MATERN52, ell, 1.0, 1e-3)
+    b = g.standard_normal(300)
+    x, hist, inner = R.refine_fcg(A64, Alow, b, tol=1e-8, inner_tol=1e-2, k=6, L=9)
+    assert hist[-1] <= 1e-8
+    assert np.linalg.norm(b - A64 @ x) / np.linalg.norm(b) <= 2e-8
+    _, hist_ir, inner_ir = R.refine(A64, Alow, b, tol=1e-8, inner_tol=1e-2, max_outer=60)
+    assert hist_ir[-1] <= 1e-8
+    assert len(inner) < len(inner_ir)
+
+
 def test_gp_gradient_matches_finite_differences():
     g = np.random.default_rng(14)
     X = g.standard_normal((120, 3))
