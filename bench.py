@@ -61,6 +61,8 @@ def parse():
                     help="relative tolerance of each inner (low-precision) solve; the bf16 "
                          "operator contracts the refinement error by ~0.1 per step, so "
                          "tighter inner solves only add iterations")
+    ap.add_argument("--refine", choices=["ir", "fcg"], default="ir",
+                    help="outer loop: iterative refinement or flexible CG in FP64")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default sweep plan instead of the autotuned one")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -128,7 +130,7 @@ def main():
     rc = dcg.Recycle(n, w["k"], w["L"], device=dev)
     ws = dcg.SolveWorkspace(n, dev)
     x = torch.empty(n, dtype=torch.float64, device=dev)
-    kw = dict(tol=w["tol"], refine=True, inner_tol=args.inner_tol, ws=ws, out=x,
+    kw = dict(tol=w["tol"], refine=args.refine, inner_tol=args.inner_tol, ws=ws, out=x,
               check_every=8)
 
     for i in range(args.warmup):

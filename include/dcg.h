@@ -79,15 +79,18 @@ typedef struct {
   int select_largest;  /* 1: keep the largest harmonic Ritz values (the
                           paper's experiments), 0: the smallest              */
   int check_every;     /* iterations between host convergence checks (>= 1) */
-  int refine;          /* 1: iterative refinement against the FP64 operator */
+  int refine;          /* 0: none; 1: iterative refinement against the FP64
+                          operator; 2: flexible-CG (Krylov-accelerated)
+                          refinement; DCG_E_ARG otherwise                     */
   double inner_tol;    /* relative tolerance of each inner solve (refine)   */
   int refine_max;      /* maximum outer refinement steps                    */
   int use_graph;       /* 1: capture each chunk of iterations in a hipGraph */
   int true_residual;   /* 1: also compute |b - A x| / |b| at exit (one more
-                          product; always done when refine = 1)              */
+                          product; always done when refine > 0)              */
   int profile;         /* 1: time every matvec sweep with HIP events on the
-                          operator's stream (iterations run without graphs) */
-  int refresh_every;   /* refine = 1 only: 0 extracts W' after the first inner
+                          operator's stream (recorded inside the iteration
+                          graph when use_graph = 1)                          */
+  int refresh_every;   /* refine > 0 only: 0 extracts W' after the first inner
                           solve of each dcg_solve call (the operator does not
                           change between its inner solves), 1 after every one */
 } dcg_params;
@@ -205,7 +208,13 @@ size_t dcg_solve_workspace_bytes(int64_t n, int k, int L);
  * With p->refine = 1 the solve runs iterative refinement: residuals with the
  * FP64 operator, inner deflated solves to p->inner_tol with the operator's
  * precision, until |b - A x| / |b| <= p->tol (the recycled W carries over
- * between the inner solves). */
+ * between the inner solves).  With p->refine = 2 the outer loop is flexible
+ * CG with full A-orthogonalisation (Notay 2000) in FP64, the inner deflated
+ * solve being its variable preconditioner: one FP64 product per outer step
+ * for the direction's product, the residual updated recursively and
+ * confirmed with one more FP64 product at the end (at most
+ * min(refine_max, 32) directions are kept; the loop restarts from the FP64
+ * residual beyond that). */
 int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given,
               dcg_recycle_t rc, const dcg_params *p, dcg_stats *st, void *ws,
               size_t ws_bytes);

@@ -325,14 +325,25 @@ class SolveWorkspace:
         self._ws, self.ptr, self.size = _workspace(nbytes, device)
 
 
+def _refine_mode(refine):
+    if refine in (False, None, 0):
+        return 0
+    if refine in (True, 1, "ir"):
+        return 1
+    if refine in (2, "fcg"):
+        return 2
+    raise ValueError(f"refine must be False, True/'ir' or 'fcg', not {refine!r}")
+
+
 def solve(op, b, x0=None, rc=None, tol=1e-6, max_iter=0, L=0, select_largest=True,
           check_every=8, refine=False, inner_tol=1e-4, refine_max=20, use_graph=True,
           true_residual=False, profile=False, refresh_every=False, ws=None, out=None):
     """Deflated CG (Algorithm 1) for A x = b; returns (x, stats dict).
 
     rc=None runs plain CG; with a Recycle the solve uses its W and leaves the
-    next W' (harmonic Ritz vectors, Eq. 7) in it.  refine=True runs iterative
-    refinement to ``tol`` against the FP64 operator.
+    next W' (harmonic Ritz vectors, Eq. 7) in it.  refine=True (or "ir") runs
+    iterative refinement to ``tol`` against the FP64 operator, refine="fcg"
+    flexible CG in FP64 with the inner deflated solve as preconditioner.
     """
     torch = _torch()
     lib = load()
@@ -347,7 +358,7 @@ def solve(op, b, x0=None, rc=None, tol=1e-6, max_iter=0, L=0, select_largest=Tru
         ws = SolveWorkspace(op.n, op.device)
     p = Params(tol=float(tol), max_iter=int(max_iter), L=int(L),
                select_largest=1 if select_largest else 0, check_every=int(check_every),
-               refine=1 if refine else 0, inner_tol=float(inner_tol), refine_max=int(refine_max),
+               refine=_refine_mode(refine), inner_tol=float(inner_tol), refine_max=int(refine_max),
                use_graph=1 if use_graph else 0, true_residual=1 if true_residual else 0,
                profile=1 if profile else 0, refresh_every=1 if refresh_every else 0)
     st = Stats()

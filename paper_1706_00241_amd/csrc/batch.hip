@@ -63,7 +63,7 @@ static BatchLayout batch_layout(int count, const int64_t *n) {
   L.args = take(sizeof(CgArgs) * size_t(count));
   L.heads = take(sizeof(StateHead) * size_t(count));
   L.sys.resize(count);
-  for (int s = 0; s < count; ++s) L.sys[s] = take(solve_workspace_total(n[s]));
+  for (int s = 0; s < count; ++s) L.sys[s] = take(solve_workspace_total(n[s], false));
   L.total = align256(off);
   return L;
 }

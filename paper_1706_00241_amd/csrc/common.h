@@ -59,7 +59,7 @@ struct MatvecPlan {
 // single-vector kernel unless its bf16 operands are wide (register budget).
 // The device kernel applies the same rule to its template parameters.
 inline int sweep_tile_rows(int mv, int prec, int ksteps) {
-  return (mv == 1 && (prec == DCG_PREC_FP32 || ksteps <= 5)) ? 2 : 1;
+  return (mv == 1 && (prec == DCG_PREC_FP32 || ksteps <= 9)) ? 2 : 1;
 }
 inline int sweep_blk(const Geometry &g, int mv) { return 128 * sweep_tile_rows(mv, g.prec, g.ksteps); }
 

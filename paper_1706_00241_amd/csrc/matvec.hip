@@ -160,7 +160,7 @@ __device__ __forceinline__ f32x16 tile_r2(const Operand<BF16, KS> &a, const Oper
 
 template <int KERN, int KS, int MV, bool BF16>
 __device__ __forceinline__ void symv_body(const SymvArgs &A, const int64_t item) {
-  constexpr int TR = (MV == 1 && (!BF16 || KS <= 5)) ? 2 : 1;  // = sweep_tile_rows
+  constexpr int TR = (MV == 1 && (!BF16 || KS <= 9)) ? 2 : 1;  // = sweep_tile_rows
   constexpr int BLK = 4 * 32 * TR;
   constexpr int NCT = BLK / 32;
   __shared__ float colpart[MV][4][BLK];
@@ -179,9 +179,12 @@ __device__ __forceinline__ void symv_body(const SymvArgs &A, const int64_t item)
   const int64_t rowbase = int64_t(I) * BLK + w * 32 * TR;
 
   // Row sums: FP32 runs over the 8 column tiles of one block pair, then FP64
-  // across block pairs (single-vector kernel; the 4-vector kernel keeps FP32
-  // to stay within its register budget).
-  constexpr bool ACC64 = (MV == 1);
+  // across block pairs for FP32 operands (single-vector kernel).  With bf16
+  // operands the operator's own error (the rounding of the points) is orders
+  // above FP32 summation over one work item's few block pairs, and dropping
+  // the FP64 accumulators frees the registers for two tile rows per wave and
+  // three waves per SIMD.  Work items are summed in FP64 either way.
+  constexpr bool ACC64 = (MV == 1) && !BF16;
   Operand<BF16, KS> ra[TR];
   float pi[MV][TR][16];
   float accr[MV][TR][16];
@@ -446,7 +449,8 @@ SymvArgs symv_args(const dcg_operator_s *op, int mv, const float *vin, const int
 
 // The batched sweep is built for the two-tile-row single-vector kernels.
 bool symv_batched_supported(int prec, int ksteps) {
-  if (prec == DCG_PREC_BF16 || prec == DCG_PREC_BF16X2) return ksteps >= 1 && ksteps <= 5;
+  if (prec == DCG_PREC_BF16 || prec == DCG_PREC_BF16X2)
+    return (ksteps >= 1 && ksteps <= 5) || ksteps == 7 || ksteps == 9;
   if (prec == DCG_PREC_FP32) return ksteps == 5 || ksteps == 9 || ksteps == 13 || ksteps == 17;
   return false;
 }
@@ -461,7 +465,9 @@ int launch_symv_batched(const BatchItem *d_items, int count, int64_t total, int 
       case 2: hipLaunchKernelGGL((symv_batched<2, true>), g, b, 0, s, d_items, count, total); break;
       case 3: hipLaunchKernelGGL((symv_batched<3, true>), g, b, 0, s, d_items, count, total); break;
       case 4: hipLaunchKernelGGL((symv_batched<4, true>), g, b, 0, s, d_items, count, total); break;
-      default: hipLaunchKernelGGL((symv_batched<5, true>), g, b, 0, s, d_items, count, total); break;
+      case 5: hipLaunchKernelGGL((symv_batched<5, true>), g, b, 0, s, d_items, count, total); break;
+      case 7: hipLaunchKernelGGL((symv_batched<7, true>), g, b, 0, s, d_items, count, total); break;
+      default: hipLaunchKernelGGL((symv_batched<9, true>), g, b, 0, s, d_items, count, total); break;
     }
   } else if (prec == DCG_PREC_FP32) {
     switch (ksteps) {

@@ -24,6 +24,7 @@ struct SolveBuffers {
   unsigned *counter;
   double *r, *p, *q, *part, *part_h, *hist_res, *hist_d, *hist_alpha, *hist_beta;
   double *tmp1, *tmp2, *tmp3;
+  double *fD, *fQ;   // refinement directions (only with a refinement-sized workspace)
 };
 
 struct InnerResult {
@@ -43,7 +44,9 @@ struct SolveCtx {
   bool extract = true;
 };
 
-size_t solve_workspace_total(int64_t n);
+// Bytes of one solve's workspace; without the refinement's direction blocks
+// when refine is false.
+size_t solve_workspace_total(int64_t n, bool refine);
 SolveBuffers solve_buffers(void *ws, int64_t n);
 
 // Phase 1: AW, (W^T A W)^{-1}, r_0, the deflated start and p_0 (ends with a

@@ -23,9 +23,12 @@ static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 constexpr int kHistCap = 1 << 16;
 constexpr size_t kGemmPartDoubles = size_t(64) * kMaxZ * kMaxZ;
 
+// Outer directions kept by the flexible-CG refinement.
+constexpr int kFcgCap = 32;
+
 struct SolveLayout {
   size_t S, counter, r, p, q, part, part_h, hist_res, hist_d, hist_alpha, hist_beta, tmp1, tmp2,
-      tmp3, total;
+      tmp3, core, fD, fQ, total;
 };
 
 static SolveLayout solve_layout(int64_t n) {
@@ -52,11 +55,18 @@ static SolveLayout solve_layout(int64_t n) {
   L.tmp1 = take(size_t(n) * 8);
   L.tmp2 = take(size_t(n) * 8);
   L.tmp3 = take(size_t(n) * 8);
+  L.core = align256(off);
+  // the refinement's outer directions and their FP64 products
+  L.fD = take(size_t(n) * kFcgCap * 8);
+  L.fQ = take(size_t(n) * kFcgCap * 8);
   L.total = align256(off);
   return L;
 }
 
-size_t solve_workspace_total(int64_t n) { return solve_layout(n).total; }
+size_t solve_workspace_total(int64_t n, bool refine) {
+  const SolveLayout L = solve_layout(n);
+  return refine ? L.total : L.core;
+}
 
 struct RecycleLayout {
   size_t Z, AZ, Wt, AWt, F, G, U, eigw, M, Minv, Mwork, N, small, info, gemm, total;
@@ -109,6 +119,8 @@ SolveBuffers solve_buffers(void *ws, int64_t n) {
   B.tmp1 = reinterpret_cast<double *>(b + L.tmp1);
   B.tmp2 = reinterpret_cast<double *>(b + L.tmp2);
   B.tmp3 = reinterpret_cast<double *>(b + L.tmp3);
+  B.fD = reinterpret_cast<double *>(b + L.fD);
+  B.fQ = reinterpret_cast<double *>(b + L.fQ);
   return B;
 }
 
@@ -453,6 +465,148 @@ int true_residual(dcg_operator_s *op, const double *b, const double *x, int exac
   return DCG_OK;
 }
 
+// ------------------------------------------------ flexible-CG refinement
+//
+// Krylov-accelerated refinement: flexible CG (full A-orthogonalisation) in
+// FP64 around a variable preconditioner, the deflated solve of the
+// low-precision operator to inner_tol.  Per outer step: z_t = inner solve of
+// r_t (written straight into D_t), Q_t = A z_t with the FP64 operator, then
+// D_t, Q_t -= sum_j c_j (D_j, Q_j) with c_j = Q_j^T z_t / gamma_j, and
+// alpha = D_t^T r / gamma_t, gamma_t = D_t^T Q_t.  The residual is updated
+// recursively with the FP64 products and confirmed with one FP64 product
+// before the solve returns (a restart from that residual if it disagrees).
+
+struct FcgCoef {
+  double c[kFcgCap];
+};
+
+__global__ __launch_bounds__(256) void fcg_orth(double *D, double *Q, int t, int64_t n, FcgCoef cf) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  double d = D[int64_t(t) * n + i], q = Q[int64_t(t) * n + i];
+  for (int j = 0; j < t; ++j) {
+    d -= cf.c[j] * D[int64_t(j) * n + i];
+    q -= cf.c[j] * Q[int64_t(j) * n + i];
+  }
+  D[int64_t(t) * n + i] = d;
+  Q[int64_t(t) * n + i] = q;
+}
+
+// Column dots out[c] = Y[:, c]^T v, c < m, read back to the host.
+static int host_dots(hipStream_t s, const double *Y, int64_t n, int m, const double *v,
+                     const SolveBuffers &B, double *out) {
+  enqueue_ts_dot(s, Y, n, m, v, B.part_h, B.counter + 1, nullptr, B.S->cvec);
+  HIPCHK(hipMemcpyAsync(out, B.S->cvec, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return DCG_OK;
+}
+
+// r = b - A x with the FP64 operator (r = b when zero); returns |r|^2, |b|^2.
+static int fp64_residual(dcg_operator_s *op, const double *b, const double *x, bool zero,
+                         const SolveBuffers &B, double *r, double *rr, double *bb, int *exact) {
+  hipStream_t s = op->stream;
+  const int64_t n = op->g.n;
+  if (!zero) {
+    const int st = matvec_exact(op, x, B.tmp3, 1);
+    if (st != DCG_OK) return st;
+    *exact += 1;
+  }
+  HIPCHK(hipMemsetAsync(B.counter + 2, 0, sizeof(unsigned), s));
+  hipLaunchKernelGGL(residual_norms, dim3(static_cast<unsigned>(std::min<int64_t>(kRedBlocks, cdiv(n, 256)))),
+                     dim3(256), 0, s, b, zero ? nullptr : B.tmp3, n, r, B.part, B.counter + 2,
+                     B.S->cvec);
+  double h[2];
+  HIPCHK(hipMemcpyAsync(h, B.S->cvec, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *rr = h[0];
+  *bb = h[1];
+  return DCG_OK;
+}
+
+static int refine_fcg(dcg_operator_s *op, const double *b, double *x, int x_given,
+                      dcg_recycle_s *rc, const dcg_params *p, dcg_stats *st, void *ws,
+                      const SolveBuffers &B) {
+  hipStream_t s = op->stream;
+  const int64_t n = op->g.n;
+  double *r = B.tmp1;
+  const int outer_max = p->refine_max > 0 ? p->refine_max : 20;
+  HIPCHK(hipMemsetAsync(B.counter, 0, sizeof(unsigned) * 4, s));
+  if (!x_given) HIPCHK(hipMemsetAsync(x, 0, size_t(n) * 8, s));
+  double rr = 0.0, bb = 0.0;
+  int code = fp64_residual(op, b, x, !x_given, B, r, &rr, &bb, &st->matvecs_exact);
+  if (code != DCG_OK) return code;
+  auto relof = [&](double v) { return bb > 0.0 ? std::sqrt(v / bb) : std::sqrt(v); };
+  double rel = relof(rr);
+  bool r_true = true;      // r is the FP64 residual of x (not the recursive one)
+  double gamma[kFcgCap];
+  int t = 0;               // directions kept
+  int status = DCG_NOT_CONVERGED;
+  while (true) {
+    if (!std::isfinite(rel)) { status = DCG_E_NONFINITE; break; }
+    if (rel <= p->tol || t == kFcgCap) {
+      if (r_true && rel <= p->tol) { status = DCG_OK; break; }
+      // confirm with the FP64 residual; continue from it (dropping the
+      // directions) if the recursive residual drifted or the store is full
+      code = fp64_residual(op, b, x, false, B, r, &rr, &bb, &st->matvecs_exact);
+      if (code != DCG_OK) return code;
+      rel = relof(rr);
+      r_true = true;
+      t = 0;
+      continue;
+    }
+    if (st->outer_steps == outer_max) break;
+    double *Dt = B.fD + int64_t(t) * n, *Qt = B.fQ + int64_t(t) * n;
+    InnerResult R;
+    code = inner_solve(op, r, Dt, 0, rc, p, p->inner_tol, ws, &R,
+                       p->refresh_every != 0 || st->outer_steps == 0);
+    if (code != DCG_OK) return code;
+    st->iters += R.iters;
+    st->matvecs += R.matvecs;
+    if (st->outer_steps == 0) st->k_used = R.k_used;
+    st->k_next = R.k_next;
+    st->t_init_ms += R.t_init;
+    st->t_loop_ms += R.t_loop;
+    st->t_refresh_ms += R.t_refresh;
+    st->sweeps_timed += R.sweeps_timed;
+    st->t_sweeps_ms += R.t_sweeps;
+    st->rel_res_recursive = R.relres;
+    st->outer_steps += 1;
+    if (R.status < 0) { status = R.status; break; }
+    code = matvec_exact(op, Dt, Qt, 1);
+    if (code != DCG_OK) return code;
+    st->matvecs_exact += 1;
+    if (t > 0) {
+      double h[kFcgCap];
+      code = host_dots(s, B.fQ, n, t, Dt, B, h);
+      if (code != DCG_OK) return code;
+      FcgCoef cf;
+      for (int j = 0; j < t; ++j) cf.c[j] = h[j] / gamma[j];
+      hipLaunchKernelGGL(fcg_orth, dim3(static_cast<unsigned>(cdiv(n, 256))), dim3(256), 0, s,
+                         B.fD, B.fQ, t, n, cf);
+      HIPCHK(hipGetLastError());
+    }
+    double g1[1], g2[1];
+    code = host_dots(s, Qt, n, 1, Dt, B, g1);
+    if (code == DCG_OK) code = host_dots(s, Dt, n, 1, r, B, g2);
+    if (code != DCG_OK) return code;
+    if (!std::isfinite(g1[0]) || !std::isfinite(g2[0])) { status = DCG_E_NONFINITE; break; }
+    if (!(g1[0] > 0.0)) { status = DCG_E_NOT_SPD; break; }
+    gamma[t] = g1[0];
+    const double alpha = g2[0] / g1[0];
+    enqueue_block_axpy(s, x, Dt, alpha, n);
+    enqueue_block_axpy(s, r, Qt, -alpha, n);
+    double rn[1];
+    code = host_dots(s, r, n, 1, r, B, rn);
+    if (code != DCG_OK) return code;
+    rel = relof(rn[0]);
+    r_true = false;
+    t += 1;
+  }
+  st->rel_res_true = rel;
+  st->status = status;
+  return status;
+}
+
 }  // namespace dcg
 
 using namespace dcg;
@@ -550,7 +704,8 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
   if (st == nullptr) st = &local;
   std::memset(st, 0, sizeof(*st));
   if (op == nullptr || b == nullptr || x == nullptr || p == nullptr) return st->status = DCG_E_ARG;
-  if (!(p->tol >= 0.0) || p->check_every < 0) return st->status = DCG_E_ARG;
+  if (!(p->tol >= 0.0) || p->check_every < 0 || p->refine < 0 || p->refine > 2)
+    return st->status = DCG_E_ARG;
   if (rc != nullptr && rc->n != op->g.n) return st->status = DCG_E_ARG;
   if (ws == nullptr || ws_bytes < solve_layout(op->g.n).total) return st->status = DCG_E_WORKSPACE;
   if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return st->status = DCG_E_WORKSPACE;
@@ -580,6 +735,11 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
     }
     st->t_total_ms = ms_since(t0);
     return st->status;
+  }
+  if (p->refine == 2) {
+    const int code = refine_fcg(op, b, x, x_given, rc, p, st, ws, B);
+    st->t_total_ms = ms_since(t0);
+    return code;
   }
   // ---- iterative refinement: r_t = b - A64 x_t, A~ d_t = r_t, x += d_t
   double *rhs = B.tmp1, *delta = B.tmp2;

@@ -258,6 +258,59 @@ def test_refinement_reaches_1e8_bf16(lib):
     assert err_A <= 1e-7
 
 
+@pytest.mark.parametrize("prec,inner_tol", [(1, 1e-2), (1, 1e-1), (0, 1e-3)])
+def test_refinement_fcg_matches_oracle(lib, prec, inner_tol):
+    """Flexible-CG refinement: FP64 outer directions around the inner
+    deflated solve of the rounded-points operator, against the oracle's
+    refine_fcg (same recycling: W extracted after the first inner solve)."""
+    from oracle import refine as ORF
+    w = workloads.bf16_shift(n=3000)
+    X, b = w["X"], w["b"]
+    s2 = w["sigma2s"][0]
+    A64 = OK.operator(X, w["kernel"], w["ell"], 1.0, s2)
+    Alow = OK.operator(OP.round_points(X, prec), w["kernel"], w["ell"], 1.0, s2)
+    xr, hist, inner = ORF.refine_fcg(A64, Alow, b, tol=1e-8, inner_tol=inner_tol, k=16, L=24)
+    op = lib.Operator(_dev(X), w["kernel"], w["ell"], 1.0, s2, prec=prec)
+    rc = lib.Recycle(3000, 16, 24)
+    x, st = lib.solve(op, _dev(b), rc=rc, tol=1e-8, refine="fcg", inner_tol=inner_tol)
+    x = _np(x)
+    res = np.linalg.norm(b - A64 @ x) / np.linalg.norm(b)
+    assert st["status"] == 0
+    assert res <= 1.05e-8, res
+    assert abs(res - st["rel_res_true"]) <= 1e-3 * res + 1e-15
+    # outer steps as the oracle's, within one; one FP64 product per step plus
+    # the final confirmation (the first residual from x = 0 is b)
+    assert abs(st["outer_steps"] - len(inner)) <= 1, (st["outer_steps"], len(inner))
+    assert st["matvecs_exact"] == st["outer_steps"] + 1
+    x_ref = np.linalg.solve(A64, b)
+    err_A = np.sqrt((x - x_ref) @ A64 @ (x - x_ref) / (x_ref @ A64 @ x_ref))
+    assert err_A <= 1e-7
+    rc2 = lib.Recycle(3000, 16, 24)
+    _, st_ir = lib.solve(op, _dev(b), rc=rc2, tol=1e-8, refine=True, inner_tol=inner_tol)
+    assert st_ir["status"] == 0
+    print(f"prec {prec} inner_tol {inner_tol}: fcg {st['outer_steps']} outer / {st['iters']} its, "
+          f"ir {st_ir['outer_steps']} outer / {st_ir['iters']} its", flush=True)
+
+
+def test_refinement_fcg_from_given_start_and_zero_rhs(lib):
+    w = workloads.bf16_shift(n=1500)
+    X, b = w["X"], w["b"]
+    s2 = w["sigma2s"][0]
+    A64 = OK.operator(X, w["kernel"], w["ell"], 1.0, s2)
+    op = lib.Operator(_dev(X), w["kernel"], w["ell"], 1.0, s2, prec=1)
+    x_ref = np.linalg.solve(A64, b)
+    x0 = x_ref * (1.0 + 1e-3 * np.random.default_rng(3).standard_normal(1500))
+    x, st = lib.solve(op, _dev(b), x0=_dev(x0), tol=1e-10, refine="fcg", inner_tol=1e-2)
+    x = _np(x)
+    assert st["status"] == 0
+    assert np.linalg.norm(b - A64 @ x) / np.linalg.norm(b) <= 1.05e-10
+    # the given start costs one FP64 product for r_0
+    assert st["matvecs_exact"] == st["outer_steps"] + 2
+    z, st0 = lib.solve(op, torch.zeros(1500, dtype=torch.float64, device="cuda"), tol=1e-8,
+                       refine="fcg")
+    assert st0["status"] == 0 and st0["outer_steps"] == 0 and torch.count_nonzero(z) == 0
+
+
 def test_sigma_shift_sequence_reuses_AW(lib):
     """sigma^2-only changes: AW updated by the shift, no block product."""
     w = workloads.bf16_shift(n=2048, systems=3)
