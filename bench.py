@@ -42,7 +42,7 @@ SLOTS_PER_PAIR = {0: 5, 1: 8, 2: 10}
 # HBM bytes per launch of the sweep measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled by a 256 MiB copy) for this workload and this version of
 # the kernel; None for any other configuration.
-SWEEP_TRAFFIC = {("bf16", 65536, 32, 2, 2048): 87.3e6}
+SWEEP_TRAFFIC = {("bf16", 65536, 32, 2, 8192): 115.8e6}
 
 
 def parse():
@@ -65,6 +65,9 @@ def parse():
                     help="outer loop: iterative refinement or flexible CG in FP64")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default sweep plan instead of the autotuned one")
+    ap.add_argument("--sweep-items", type=int, default=0, metavar="N",
+                    help="use this sweep plan (work-item target) instead of tuning; for "
+                         "profiling runs that should launch only the timed plan")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer (a kernel of known traffic "
                          "for scaling HBM counters)")
@@ -123,7 +126,10 @@ def main():
     prec = {"bf16": dcg.PREC_BF16, "bf16x2": dcg.PREC_BF16X2, "fp32": dcg.PREC_FP32}[args.prec]
     op = dcg.Operator(X, w["kernel"], w["ell"], 1.0, w["sigma2s"][0], prec=prec)
     items = 2048
-    if not args.no_tune:
+    if args.sweep_items > 0:
+        items = args.sweep_items
+        op.set_sweep_items(items)
+    elif not args.no_tune:
         items, tms = op.tune(reps=5)
         print(f"tuned sweep plan: {items} work items, {tms:.3f} ms per sweep", file=sys.stderr,
               flush=True)
