@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--sweep-items", type=int, default=0, metavar="N",
                     help="use this sweep plan (work-item target) instead of tuning; for "
                          "profiling runs that should launch only the timed plan")
+    ap.add_argument("--workload", choices=["bf16_shift", "ragged"], default="bf16_shift",
+                    help="bf16_shift: the headline sequence; ragged: the batching form (64 "
+                         "independent sequences, one batched solve per step)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer (a kernel of known traffic "
                          "for scaling HBM counters)")
@@ -98,12 +101,103 @@ def cpu_baseline(w, matvecs_per_solve, exact_per_solve, rows=384):
                       f"GPU run; one thread"}
 
 
+def main_ragged(args):
+    """Batching form: 64 independent sequences (n log-uniform in [2048, 32768],
+    d = 8, RBF / Matern-3/2, FP32 operator, k = 16, L = 24, tol 1e-6); one step
+    = one batched deflated solve of every sequence's next system.  The same
+    steps are then solved one system at a time for comparison."""
+    import torch
+
+    import paper_1706_00241_amd as dcg
+    import workloads
+
+    dcg.load()
+    steps = min(args.steps, 4)
+    warm = min(args.warmup, 5 - steps)
+    w = workloads.ragged(systems=warm + steps)
+    seqs = w["seqs"]
+    stream = torch.cuda.Stream()
+
+    def build():
+        ops, rcs = [], []
+        for q in seqs:
+            ops.append(dcg.Operator(torch.as_tensor(q["X"], device="cuda"), q["kernel"],
+                                    q["ells"][0], q["s2"], q["sigma2"], prec=dcg.PREC_FP32,
+                                    stream=stream))
+            rcs.append(dcg.Recycle(q["X"].shape[0], w["k"], w["L"]))
+        return ops, rcs
+
+    opsA, rcsA = build()
+    opsB, rcsB = build()
+    items = []
+    for a, b in zip(opsA, opsB):
+        it, _ = a.tune(reps=3)
+        b.set_sweep_items(it)
+        items.append(it)
+    bs = [torch.as_tensor(q["b"], device="cuda") for q in seqs]
+
+    def hyper(ops, t):
+        for op, q in zip(ops, seqs):
+            op.set_hyper(q["ells"][t], q["s2"], q["sigma2"])
+
+    for t in range(warm):
+        hyper(opsA, t)
+        dcg.solve_batched(opsA, bs, rcs=rcsA, tol=w["tol"])
+        hyper(opsB, t)
+        for op, b, rc in zip(opsB, bs, rcsB):
+            dcg.solve(op, b, rc=rc, tol=w["tol"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for t in range(warm, warm + steps):
+        hyper(opsA, t)
+        _, st = dcg.solve_batched(opsA, bs, rcs=rcsA, tol=w["tol"])
+        stats.append(st)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    bad = sum(1 for st in stats for s in st if s["status"] != 0)
+    t_single = None
+    if not args.no_plain:
+        t0 = time.perf_counter()
+        for t in range(warm, warm + steps):
+            hyper(opsB, t)
+            for op, b, rc in zip(opsB, bs, rcsB):
+                dcg.solve(op, b, rc=rc, tol=w["tol"])
+        torch.cuda.synchronize()
+        t_single = time.perf_counter() - t0
+    matvecs = sum(s["matvecs"] for st in stats for s in st)
+    ns = [q["X"].shape[0] for q in seqs]
+    pairs = sum(s["iters"] * n * (n + 1) / 2 for st in stats for s, n in zip(st, ns))
+    out = {
+        "metric": "aggregate matvecs/s, 64 ragged sequences batched, 1 GPU",
+        "value": round(matvecs / t_batched, 1),
+        "unit": "matvecs/s",
+        "n_gpus": 1, "steps": steps, "warmup": warm,
+        "ms_per_step": round(t_batched * 1e3 / steps, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32 MFMA distances, f32 kernel values, f64 CG", "data": "synthetic",
+        "config": {"workload": "ragged: 64 sequences, n log-uniform [2048, 32768], d=8, "
+                               "RBF/Matern-3/2, sigma2 log-uniform [1e-4, 1e-1], k=16 L=24 tol 1e-6",
+                   "sum_n": sum(ns), "sweep_items": sorted(set(items))},
+        "unique_pairs_per_s": round(pairs / t_batched, 1),
+        "one_by_one_ms_per_step": round(t_single * 1e3 / steps, 2) if t_single else None,
+        "speedup_vs_one_by_one": round(t_single / t_batched, 3) if t_single else None,
+        "iters_per_system": [[s["iters"] for s in st] for st in stats],
+        "failed_solves": bad,
+    }
+    print(json.dumps(out), flush=True)
+    if bad:
+        sys.exit(1)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the row-sharded multi-GPU design is described, not built)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "ragged":
+        return main_ragged(args)
     import numpy as np
     import torch
 

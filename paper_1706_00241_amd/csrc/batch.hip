@@ -7,9 +7,11 @@
 // Every system is initialised on its own; then one step of all of them is
 // one batched pair sweep (the grid is the concatenation of every system's
 // work items, grouped by operand layout) followed by one launch per CG
-// vector kernel with blockIdx.y selecting the system.  Systems that have
-// converged skip every kernel.  A chunk of steps is captured once as a
-// hipGraph; the host reads the packed per-system state once per chunk.
+// vector kernel with blockIdx.y selecting the system.  A chunk of steps is
+// captured as a hipGraph; the host reads the packed per-system state once per
+// chunk.  Systems that converge inside a chunk skip the rest of its kernels;
+// after the check they leave the tables and the chunk is re-captured for the
+// systems still running.
 // Each system's basis is refreshed on its own afterwards.
 #include <algorithm>
 #include <cmath>
@@ -105,6 +107,57 @@ static int enqueue_batch_step(hipStream_t s, int count, dcg_operator_s *const *o
   return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
 }
 
+// Device tables of the running systems `act` (positions in the tables are
+// positions in act; blockIdx.y of the vector kernels indexes them).
+static int build_tables(const std::vector<int> &act, dcg_operator_s *const *ops,
+                        const std::vector<SolveCtx> &ctx, hipStream_t strm, BatchItem *d_items,
+                        CgArgs *d_args, BatchPlan *plan) {
+  *plan = BatchPlan();
+  std::vector<BatchItem> items;
+  std::vector<CgArgs> args(act.size());
+  std::map<std::pair<int, int>, std::vector<int>> by_shape;
+  for (size_t i = 0; i < act.size(); ++i) {
+    const int s = act[i];
+    const dcg_operator_s *op = ops[s];
+    args[i] = ctx[s].a;
+    plan->nq_max = std::max(plan->nq_max, ctx[s].a.nblk_q);
+    plan->nx_max = std::max(plan->nx_max, ctx[s].a.nblk_xr);
+    // bf16 and bf16x2 operands share the bf16 kernels
+    const int pc = (op->g.prec == DCG_PREC_BF16X2) ? DCG_PREC_BF16 : op->g.prec;
+    if (symv_batched_supported(op->g.prec, op->g.ksteps))
+      by_shape[{pc, op->g.ksteps}].push_back(s);
+    else
+      plan->direct.push_back(s);
+  }
+  for (const auto &kv : by_shape) {
+    SweepGroup g;
+    g.prec = kv.first.first;
+    g.ksteps = kv.first.second;
+    g.first = static_cast<int>(items.size());
+    g.count = static_cast<int>(kv.second.size());
+    g.total = 0;
+    for (int s : kv.second) {
+      BatchItem it;
+      int64_t grid = 0;
+      it.a = symv_args(ops[s], 1, ops[s]->vin, &ctx[s].B.S->done, &grid);
+      it.kernel = ops[s]->kernel;
+      it.item0 = g.total;
+      g.total += grid;
+      items.push_back(it);
+    }
+    if (g.total > int64_t(0x7fffffff)) return DCG_E_ARG;
+    plan->groups.push_back(g);
+  }
+  if (!items.empty())
+    HIPCHK(hipMemcpyAsync(d_items, items.data(), sizeof(BatchItem) * items.size(),
+                          hipMemcpyHostToDevice, strm));
+  HIPCHK(hipMemcpyAsync(d_args, args.data(), sizeof(CgArgs) * args.size(),
+                        hipMemcpyHostToDevice, strm));
+  // the host vectors go out of scope: the copies must have read them
+  HIPCHK(hipStreamSynchronize(strm));
+  return DCG_OK;
+}
+
 static void fill_stats(dcg_stats *st, const InnerResult &R) {
   st->iters = R.iters;
   st->matvecs = R.matvecs;
@@ -173,93 +226,84 @@ int dcg_solve_batched(int count, const dcg_op_t *ops, const double *const *b, do
     }
   }
 
-  // ---- the sweep plan and the device tables
-  BatchPlan plan;
-  std::vector<BatchItem> items;
-  std::vector<CgArgs> args(count);
-  std::map<std::pair<int, int>, std::vector<int>> by_shape;
-  for (int s = 0; s < count; ++s) {
-    const dcg_operator_s *op = ops[s];
-    args[s] = ctx[s].a;
-    plan.nq_max = std::max(plan.nq_max, ctx[s].a.nblk_q);
-    plan.nx_max = std::max(plan.nx_max, ctx[s].a.nblk_xr);
-    // bf16 and bf16x2 operands share the bf16 kernels
-    const int pc = (op->g.prec == DCG_PREC_BF16X2) ? DCG_PREC_BF16 : op->g.prec;
-    if (symv_batched_supported(op->g.prec, op->g.ksteps))
-      by_shape[{pc, op->g.ksteps}].push_back(s);
-    else
-      plan.direct.push_back(s);
-  }
-  for (const auto &kv : by_shape) {
-    SweepGroup g;
-    g.prec = kv.first.first;
-    g.ksteps = kv.first.second;
-    g.first = static_cast<int>(items.size());
-    g.count = static_cast<int>(kv.second.size());
-    g.total = 0;
-    for (int s : kv.second) {
-      BatchItem it;
-      int64_t grid = 0;
-      it.a = symv_args(ops[s], 1, ops[s]->vin, &ctx[s].B.S->done, &grid);
-      it.kernel = ops[s]->kernel;
-      it.item0 = g.total;
-      g.total += grid;
-      items.push_back(it);
-    }
-    if (g.total > int64_t(0x7fffffff)) return DCG_E_ARG;
-    plan.groups.push_back(g);
-  }
-  if (!items.empty())
-    HIPCHK(hipMemcpyAsync(d_items, items.data(), sizeof(BatchItem) * items.size(),
-                          hipMemcpyHostToDevice, strm));
-  HIPCHK(hipMemcpyAsync(d_args, args.data(), sizeof(CgArgs) * size_t(count),
-                        hipMemcpyHostToDevice, strm));
-
-  // ---- phase 2: lockstep iteration
+  // ---- phase 2: lockstep iteration over the systems still running.  The
+  // device tables and the captured chunk cover only those; whenever a check
+  // finds systems done, the tables are rebuilt and the chunk re-captured, so
+  // converged systems stop costing launches.
   const auto t1 = Clock::now();
   const int chunk = std::max(1, p->check_every);
+  std::vector<int> act(count);
+  for (int s = 0; s < count; ++s) act[s] = s;
+  std::vector<StateHead> heads(count), hact(count);
+  for (int s = 0; s < count; ++s) {
+    heads[s].done = 0;
+    heads[s].iter = 0;
+    heads[s].status = 0;
+    heads[s].relres = 0.0;
+  }
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  if (p->use_graph) {
-    HIPCHK(hipStreamBeginCapture(strm, hipStreamCaptureModeThreadLocal));
-    int st = DCG_OK;
-    for (int c = 0; c < chunk && st == DCG_OK; ++c)
-      st = enqueue_batch_step(strm, count, ops, ctx, plan, d_items, d_args);
-    const hipError_t e = hipStreamEndCapture(strm, &graph);
-    if (st != DCG_OK || e != hipSuccess) {
-      if (graph != nullptr) (void)hipGraphDestroy(graph);
-      return st != DCG_OK ? st : DCG_E_HIP;
-    }
-    if (hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
-      (void)hipGraphDestroy(graph);
-      return DCG_E_HIP;
-    }
-  }
-  std::vector<StateHead> heads(count);
+  auto release = [&]() {
+    if (gexec != nullptr) (void)hipGraphExecDestroy(gexec);
+    if (graph != nullptr) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+  };
+  BatchPlan plan;
   int status = DCG_OK;
-  while (true) {
+  bool rebuild = true;
+  while (!act.empty()) {
+    const int na = static_cast<int>(act.size());
+    if (rebuild) {
+      release();
+      status = build_tables(act, ops, ctx, strm, d_items, d_args, &plan);
+      if (status != DCG_OK) break;
+      if (p->use_graph) {
+        if (hipStreamBeginCapture(strm, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+          status = DCG_E_HIP;
+          break;
+        }
+        int st = DCG_OK;
+        for (int c = 0; c < chunk && st == DCG_OK; ++c)
+          st = enqueue_batch_step(strm, na, ops, ctx, plan, d_items, d_args);
+        const hipError_t e = hipStreamEndCapture(strm, &graph);
+        if (st != DCG_OK || e != hipSuccess) {
+          status = st != DCG_OK ? st : DCG_E_HIP;
+          break;
+        }
+        if (hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+          status = DCG_E_HIP;
+          break;
+        }
+      }
+      rebuild = false;
+    }
     if (gexec != nullptr) {
       if (hipGraphLaunch(gexec, strm) != hipSuccess) { status = DCG_E_HIP; break; }
     } else {
       for (int c = 0; c < chunk && status == DCG_OK; ++c)
-        status = enqueue_batch_step(strm, count, ops, ctx, plan, d_items, d_args);
+        status = enqueue_batch_step(strm, na, ops, ctx, plan, d_items, d_args);
       if (status != DCG_OK) break;
     }
-    hipLaunchKernelGGL(gather_states, dim3(static_cast<unsigned>(bdiv(count, 256))), dim3(256), 0,
-                       strm, d_args, count, d_heads);
+    hipLaunchKernelGGL(gather_states, dim3(static_cast<unsigned>(bdiv(na, 256))), dim3(256), 0,
+                       strm, d_args, na, d_heads);
     if (hipGetLastError() != hipSuccess ||
-        hipMemcpyAsync(heads.data(), d_heads, sizeof(StateHead) * size_t(count),
+        hipMemcpyAsync(hact.data(), d_heads, sizeof(StateHead) * size_t(na),
                        hipMemcpyDeviceToHost, strm) != hipSuccess ||
         hipStreamSynchronize(strm) != hipSuccess) {
       status = DCG_E_HIP;
       break;
     }
-    bool all = true;
-    for (int s = 0; s < count && all; ++s) all = heads[s].done != 0;
-    if (all) break;
+    std::vector<int> next;
+    next.reserve(act.size());
+    for (int i = 0; i < na; ++i) {
+      heads[act[i]] = hact[i];
+      if (!hact[i].done) next.push_back(act[i]);
+    }
+    rebuild = next.size() != act.size();
+    act.swap(next);
   }
-  if (gexec != nullptr) (void)hipGraphExecDestroy(gexec);
-  if (graph != nullptr) (void)hipGraphDestroy(graph);
+  release();
   if (status != DCG_OK) return status;
   const double t_loop = ms_since(t1);
 

@@ -6,7 +6,8 @@
 // 128-point blocks and 16x16 FP64 MFMA tiles: the squared distance comes out
 // of the augmented product <[-2x_i, a_i, 1], [x_j, 1, a_j]> in FP64 (lane l
 // holds column l%16, rows l/16 + 4v for v < 4), the kernel value is
-// evaluated in FP64 (ocml exp / sqrt), and all sums are FP64.
+// evaluated in FP64 (exp and sqrt specialised to the arguments that occur),
+// and all sums are FP64.
 #include <algorithm>
 #include <cmath>
 
@@ -44,13 +45,55 @@ size_t exact_partial_doubles(int64_t n_pad) {
   return size_t(p.nchunk + p.dmax) * size_t(n_pad);
 }
 
+// e^x for x <= 0 (and small positive x), to within one ulp: Cody-Waite
+// reduction x = k ln2 + r with |r| <= ln2 / 2 (ln 2 split into a double and
+// its FP64 tail, so the fused reduction is exact to ~2^-106), the Taylor
+// series of e^r to degree 13 (remainder below 2e-18 relative), and 2^k
+// applied with ldexp.  Arguments below -745.5 give 0.
+__device__ __forceinline__ double exp_nonpos(double x) {
+  x = fmax(x, -745.5);
+  const double k = __builtin_rint(x * 1.4426950408889634);   // 1 / ln 2
+  double r = fma(-k, 0.6931471805599453, x);                  // ln 2, double part
+  r = fma(-k, 2.3190468138462996e-17, r);                     // ln 2, tail
+  double p = 1.6059043836821613e-10;                          // 1 / 13!
+  p = fma(p, r, 2.08767569878681e-09);                        // 1 / 12!
+  p = fma(p, r, 2.505210838544172e-08);
+  p = fma(p, r, 2.755731922398589e-07);
+  p = fma(p, r, 2.7557319223985893e-06);
+  p = fma(p, r, 2.48015873015873e-05);
+  p = fma(p, r, 0.0001984126984126984);
+  p = fma(p, r, 0.001388888888888889);
+  p = fma(p, r, 0.008333333333333333);
+  p = fma(p, r, 0.041666666666666664);
+  p = fma(p, r, 0.16666666666666666);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return __builtin_amdgcn_ldexp(p, static_cast<int>(k));
+}
+
+// sqrt(a) for a >= 0 (a = 0 returns 1e-150): the hardware reciprocal square
+// root refined by one coupled Newton step on (sqrt a, 1 / (2 sqrt a)) and a
+// final residual correction a - g^2 (Markstein's scheme); within half an ulp
+// on the probed range.
+__device__ __forceinline__ double sqrt_nonneg(double a) {
+  a = fmax(a, 1e-300);
+  const double y = __builtin_amdgcn_rsq(a);
+  double g = a * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, a);
+  return fma(d, h, g);
+}
+
 template <int KERN>
 __device__ __forceinline__ double kval64(double r2, double c0, double c1) {
   if constexpr (KERN == DCG_RBF) {
-    return exp(r2 * c0);  // c0 = -1 / (2 ell^2)
+    return exp_nonpos(r2 * c0);  // c0 = -1 / (2 ell^2)
   } else {
-    const double t = sqrt(fabs(r2)) * c1;  // c1 = sqrt(3)/ell or sqrt(5)/ell
-    const double e = exp(-t);
+    const double t = sqrt_nonneg(fabs(r2)) * c1;  // c1 = sqrt(3)/ell or sqrt(5)/ell
+    const double e = exp_nonpos(-t);
     if constexpr (KERN == DCG_MATERN32) return (1.0 + t) * e;
     else return fma(t, fma(t, 1.0 / 3.0, 1.0), 1.0) * e;
   }
@@ -114,44 +157,64 @@ __global__ __launch_bounds__(256, 2) void symv64_kernel(Symv64Args A) {
   }
   const int tiles = (d1 > d0) ? (d1 - d0) * NCT : 0;
   auto colbase_of = [&](int t) -> int64_t {
+    t = min(t, tiles - 1);   // past the end: a valid tile, its result unused
     int J = I + d0 + t / NCT;
     if (J >= nb) J -= nb;
     return int64_t(J) * BLK + 16 * (t % NCT);
   };
-  Op64<KS> cb, cbn;
-  double pj = 0.0, pjn = 0.0;
+  // Software pipeline: the MFMA products of tile t + 1 are issued before the
+  // kernel values of tile t are evaluated, and the operand of tile t + 2 is
+  // loaded meanwhile, so matrix and vector units work at the same time.
+  Op64<KS> cbn, cbn2;
+  double pjc = 0.0, pjn = 0.0, pjn2 = 0.0;
+  f64x4 r2c[TR], r2n[TR];
   if (tiles > 0) {
+    Op64<KS> cb0;
     const int64_t c0b = colbase_of(0);
-    cb.load(A.xc, c0b + lc, lg);
-    pj = A.vin[c0b + lc];
+    cb0.load(A.xc, c0b + lc, lg);
+    pjc = A.vin[c0b + lc];
+#pragma unroll
+    for (int tr = 0; tr < TR; ++tr) {
+      r2c[tr] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+        r2c[tr] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[tr].v[s], cb0.v[s], r2c[tr], 0, 0, 0);
+    }
+    const int64_t c1b = colbase_of(1);
+    cbn.load(A.xc, c1b + lc, lg);
+    pjn = A.vin[c1b + lc];
   }
   for (int t = 0; t < tiles; ++t) {
     const int dl = d0 + t / NCT;
     const int ct = t % NCT;
     const bool diag = (dl == 0);
-    if (t + 1 < tiles) {
-      const int64_t cx = colbase_of(t + 1);
-      cbn.load(A.xc, cx + lc, lg);
-      pjn = A.vin[cx + lc];
+#pragma unroll
+    for (int tr = 0; tr < TR; ++tr) {
+      r2n[tr] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+        r2n[tr] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[tr].v[s], cbn.v[s], r2n[tr], 0, 0, 0);
     }
+    const int64_t cx = colbase_of(t + 2);
+    cbn2.load(A.xc, cx + lc, lg);
+    pjn2 = A.vin[cx + lc];
     double cs = 0.0;
 #pragma unroll
     for (int tr = 0; tr < TR; ++tr) {
-      f64x4 r2 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < KS; ++s)
-        r2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[tr].v[s], cb.v[s], r2, 0, 0, 0);
-      if (diag && ct == w * TR + tr) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (lg + 4 * v == lc) r2[v] = 0.0;
-      }
+      const bool dz = diag && ct == w * TR + tr;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const double kv = kval64<KERN>(r2[v], A.c0, A.c1);
-        accr[tr][v] = fma(kv, pj, accr[tr][v]);
+        // the exact diagonal: distance zero by definition
+        const double r2v = (dz && lg + 4 * v == lc) ? 0.0 : r2c[tr][v];
+        const double kv = kval64<KERN>(r2v, A.c0, A.c1);
+        accr[tr][v] = fma(kv, pjc, accr[tr][v]);
         cs = fma(kv, pi[tr][v], cs);
       }
+    }
+#pragma unroll
+    for (int i = 0; i < TR * KS; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);
     }
     if (!diag) {
       cs += __shfl_xor(cs, 16);
@@ -167,10 +230,11 @@ __global__ __launch_bounds__(256, 2) void symv64_kernel(Symv64Args A) {
         __syncthreads();
       }
     }
-    if (t + 1 < tiles) {
-      cb = cbn;
-      pj = pjn;
-    }
+#pragma unroll
+    for (int tr = 0; tr < TR; ++tr) r2c[tr] = r2n[tr];
+    cbn = cbn2;
+    pjc = pjn;
+    pjn = pjn2;
   }
 #pragma unroll
   for (int tr = 0; tr < TR; ++tr) {
