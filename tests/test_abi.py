@@ -73,10 +73,13 @@ def test_argument_validation_without_gpu(L):
 def test_batched_arguments_without_gpu(L):
     import paper_1706_00241_amd as dcg
     ns = (ctypes.c_int64 * 3)(1000, 2048, 1)
-    one = L.dcg_solve_workspace_bytes(1000, 0, 0)
     total = L.dcg_solve_batched_workspace_bytes(3, ns)
-    # every system's solve workspace plus the device tables
-    assert total >= one + L.dcg_solve_workspace_bytes(2048, 0, 0) + L.dcg_solve_workspace_bytes(1, 0, 0)
+    # every system's CG vectors (r, p, q and three more FP64 n-vectors) and the
+    # device tables; batched solves do not refine, so no outer directions
+    assert total >= 8 * 6 * (1000 + 2048 + 1)
+    assert total < L.dcg_solve_workspace_bytes(1000, 0, 0) + L.dcg_solve_workspace_bytes(2048, 0, 0) \
+        + L.dcg_solve_workspace_bytes(1, 0, 0)
+    assert total > L.dcg_solve_batched_workspace_bytes(2, ns)
     assert L.dcg_solve_batched_workspace_bytes(0, ns) == 0
     assert L.dcg_solve_batched_workspace_bytes(5000, None) == 0
     bad = (ctypes.c_int64 * 2)(10, 0)
