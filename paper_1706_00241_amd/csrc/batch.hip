@@ -80,7 +80,7 @@ struct SweepGroup {
 struct BatchPlan {
   std::vector<SweepGroup> groups;
   std::vector<int> direct;    // systems swept one by one (FP64 or unsupported shapes)
-  int64_t nq_max = 1, nx_max = 1;
+  int64_t nq_max = 1, nx_max = 1, np_max = 1;   // grids of the per-step kernels
 };
 
 static int enqueue_batch_step(hipStream_t s, int count, dcg_operator_s *const *ops,
@@ -99,11 +99,12 @@ static int enqueue_batch_step(hipStream_t s, int count, dcg_operator_s *const *o
     if (st != DCG_OK) return st;
   }
   const unsigned cy = static_cast<unsigned>(count);
-  const dim3 gq(static_cast<unsigned>(plan.nq_max), cy), gx(static_cast<unsigned>(plan.nx_max), cy);
+  const dim3 gq(static_cast<unsigned>(plan.nq_max), cy), gx(static_cast<unsigned>(plan.nx_max), cy),
+      gp(static_cast<unsigned>(plan.np_max), cy);
   hipLaunchKernelGGL(cg_matvec_finish_multi, gq, dim3(256), 0, s, d_args);
   hipLaunchKernelGGL(cg_update_xr_multi, gx, dim3(256), 0, s, d_args);
   hipLaunchKernelGGL(cg_finalize_multi, dim3(1, cy), dim3(256), 0, s, d_args);
-  hipLaunchKernelGGL(cg_update_p_multi, gx, dim3(256), 0, s, d_args);
+  hipLaunchKernelGGL(cg_update_p_multi, gp, dim3(256), 0, s, d_args);
   return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
 }
 
@@ -121,7 +122,8 @@ static int build_tables(const std::vector<int> &act, dcg_operator_s *const *ops,
     const dcg_operator_s *op = ops[s];
     args[i] = ctx[s].a;
     plan->nq_max = std::max(plan->nq_max, ctx[s].a.nblk_q);
-    plan->nx_max = std::max(plan->nx_max, ctx[s].a.nblk_xr);
+    plan->nx_max = std::max(plan->nx_max, xr_grid(ctx[s].a));
+    plan->np_max = std::max(plan->np_max, ctx[s].a.nblk_p);
     // bf16 and bf16x2 operands share the bf16 kernels
     const int pc = (op->g.prec == DCG_PREC_BF16X2) ? DCG_PREC_BF16 : op->g.prec;
     if (symv_batched_supported(op->g.prec, op->g.ksteps))

@@ -51,7 +51,12 @@ __device__ __forceinline__ double sum_partials(const ReduceArgs &A, int m, int64
 }
 
 // Rows finished per block by cg_matvec_finish.
-constexpr int kCgRows = 256;
+constexpr int kCgRows = 64;
+// cg_update_xr: a grid of row blocks of kXrRows rows times groups of kXrCols
+// columns of [AW | W]; its partial sums are per row block.
+constexpr int kXrRows = 1024;
+constexpr int kXrCols = 8;
+__host__ __device__ inline int xr_groups(int k) { return k > 0 ? (2 * k + kXrCols - 1) / kXrCols : 1; }
 
 // Scalars of one deflated-CG solve, resident on the device.
 struct SolveState {
@@ -62,7 +67,7 @@ struct SolveState {
   int iter;         // CG steps done
   int done;         // 1 once converged, failed or out of iterations
   int status;       // 0 or a negative dcg_status
-  int pad;
+  int applied;      // iter as seen by the last cg_matvec_finish (see cg_update_p)
   double mu[kMaxK]; // mu_j of Algorithm 1
   double cvec[kMaxK];
 };
@@ -81,13 +86,23 @@ struct CgArgs {
   double *Z, *AZ;   // storage of p_j / A p_j for j < L at column koff + j
   int koff, L;
   double *part, *part2, *part_h;  // partials: d (finish), rho (update_xr), [h|g]
-  int64_t nblk_q, nblk_xr;         // blocks of cg_matvec_finish / cg_update_xr
+  int64_t nblk_q;                  // blocks of cg_matvec_finish (= its partials)
+  int64_t nblk_xr;                 // row blocks of cg_update_xr (= its partials)
+  int64_t nblk_p;                  // blocks of cg_update_p
   unsigned *counter;
   double *hist_d, *hist_alpha, *hist_beta, *hist_res;
   int hist_cap;
   double tol;
   int max_iter;
 };
+
+// Block counts of the per-step kernels for a.n and a.k.
+inline void cg_set_blocks(CgArgs &a) {
+  a.nblk_q = (a.n + kCgRows - 1) / kCgRows;
+  a.nblk_xr = (a.n + kXrRows - 1) / kXrRows;
+  a.nblk_p = (a.n + 255) / 256;
+}
+inline int64_t xr_grid(const CgArgs &a) { return a.nblk_xr * xr_groups(a.k); }
 
 __global__ void cg_matvec_finish(CgArgs a);
 __global__ void cg_update_xr(CgArgs a);

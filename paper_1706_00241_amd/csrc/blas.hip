@@ -101,6 +101,9 @@ __device__ __forceinline__ void small_gemv(const double *Minv, const double *h, 
 // the next kernel forms d and alpha itself from the block partials.
 __device__ __forceinline__ void cg_matvec_finish_body(const CgArgs &a, const unsigned bid) {
   SolveState *S = a.S;
+  // the step count when this step began: cg_update_p applies the step's
+  // x / r update when the solve was still running at that point
+  if (bid == 0 && threadIdx.x == 0) S->applied = S->iter;
   if (S->done) return;
   __shared__ double seg[4][64];
   __shared__ double lds[8];
@@ -154,13 +157,23 @@ __device__ __forceinline__ void cg_matvec_finish_body(const CgArgs &a, const uns
 }
 
 // d = p^T q from the partials of cg_matvec_finish (every block forms it, in
-// the same order), alpha = rho / d; x += alpha p; r -= alpha q; block partials
-// of rho' = r^T r, h = (AW)^T r and g = W^T r.
+// the same order), alpha = rho / d, and with r' = r - alpha q (formed here
+// and again, identically, by cg_update_p, which writes x and r): per row
+// block the partials of rho' = r'^T r' and of h = (AW)^T r', g = W^T r'.
+// Block (row block rb, column group grp) takes rows rb * kXrRows ... and
+// columns grp * kXrCols ... of [AW | W]; group 0 also forms rho'.  The
+// kernel writes no vector, so the column groups of one row block never see
+// each other's updates.
 __device__ __forceinline__ void cg_update_xr_body(const CgArgs &a, const unsigned bid) {
   SolveState *S = a.S;
   if (S->done) return;
+  const int64_t nrb = a.nblk_xr;
+  const int rb = static_cast<int>(bid % nrb);
+  const int grp = static_cast<int>(bid / nrb);
+  const int k = a.k;
+  if (grp >= xr_groups(k)) return;
   __shared__ double lds[8];
-  __shared__ double rl[256];
+  __shared__ double cpart[4][kXrCols];
   const double d = block_sum_array(a.part, a.nblk_q, lds);
   const bool bad = !(d > 0.0) || !isfinite(d);
   const double alpha = bad ? 0.0 : S->rho / d;
@@ -173,49 +186,54 @@ __device__ __forceinline__ void cg_update_xr_body(const CgArgs &a, const unsigne
       a.hist_alpha[j] = alpha;
     }
   }
-  const int64_t i0 = int64_t(bid) * 256;
-  const int64_t i = i0 + threadIdx.x;
+  constexpr int RPT = kXrRows / 256;
+  const int64_t i0 = int64_t(rb) * kXrRows + threadIdx.x;
+  double ri[RPT];
   double rr = 0.0;
-  double ri = 0.0;
-  if (i < a.n) {
-    if (!bad) a.x[i] += alpha * a.p[i];
-    ri = a.r[i] - alpha * a.q[i];
-    if (!bad) a.r[i] = ri;
-    rr = ri * ri;
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int64_t i = i0 + 256 * u;
+    ri[u] = 0.0;
+    if (i < a.n) {
+      ri[u] = a.r[i] - alpha * a.q[i];
+      rr += ri[u] * ri[u];
+    }
   }
-  rl[threadIdx.x] = ri;
-  const double bs = block_sum_all(rr, lds);
-  if (threadIdx.x == 0) a.part2[bid] = bad ? (isfinite(d) ? -1.0 : -2.0) : bs;
-  // partial dots with the columns of [AW | W]: wave w takes columns w, w+4,
-  // ...; eight columns' loads are issued before their reductions
-  const int k = a.k;
-  const int64_t nblk = a.nblk_xr;
-  if (k > 0) {
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    for (int cb = w; cb < 2 * k; cb += 32) {
-      double sv[8];
+  if (grp == 0) {
+    const double bs = block_sum_all(rr, lds);
+    if (threadIdx.x == 0) a.part2[rb] = bad ? (isfinite(d) ? -1.0 : -2.0) : bs;
+  }
+  if (k == 0) return;
+  // partial dots with kXrCols columns of [AW | W]; all loads issued first
+  double sv[kXrCols];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int c = cb + 4 * u;
-        sv[u] = 0.0;
-        if (c < 2 * k) {
-          const double *Y = (c < k) ? a.AW + int64_t(c) * a.n : a.W + int64_t(c - k) * a.n;
+  for (int cc = 0; cc < kXrCols; ++cc) {
+    const int c = grp * kXrCols + cc;
+    double acc = 0.0;
+    if (c < 2 * k) {
+      const double *Y = (c < k) ? a.AW + int64_t(c) * a.n : a.W + int64_t(c - k) * a.n;
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int64_t ii = i0 + 64 * t + l;
-            if (ii < a.n) sv[u] += Y[ii] * rl[64 * t + l];
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        double v = sv[u];
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-        const int c = cb + 4 * u;
-        if (l == 0 && c < 2 * k) a.part_h[int64_t(c) * nblk + bid] = v;
+      for (int u = 0; u < RPT; ++u) {
+        const int64_t i = i0 + 256 * u;
+        if (i < a.n) acc += Y[i] * ri[u];
       }
     }
+    sv[cc] = acc;
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int cc = 0; cc < kXrCols; ++cc) {
+    double v = sv[cc];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    if (l == 0) cpart[w][cc] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kXrCols) {
+    const int c = grp * kXrCols + threadIdx.x;
+    if (c < 2 * k)
+      a.part_h[int64_t(c) * nrb + rb] = (cpart[0][threadIdx.x] + cpart[1][threadIdx.x]) +
+                                         (cpart[2][threadIdx.x] + cpart[3][threadIdx.x]);
   }
 }
 
@@ -295,11 +313,15 @@ __device__ __forceinline__ void cg_finalize_body(const CgArgs &a) {
   }
 }
 
-// Apply the re-projection (x += W c, r -= AW c) and the direction update
-// p = beta p + r - W mu; the FP32 copy of p feeds the next matvec.
+// The step x += alpha p, r -= alpha q, then the re-projection (x += W c,
+// r -= AW c) and the direction update p = beta p + r - W mu; the FP32 copy of
+// p feeds the next matvec.
 __device__ __forceinline__ void cg_update_p_body(const CgArgs &a, const unsigned bid) {
   SolveState *S = a.S;
-  if (S->done) return;
+  // A step that converges (or reaches max_iter) still applies its update:
+  // cg_finalize has advanced iter past the count cg_matvec_finish recorded.
+  // Steps after the end, and a step that failed (iter not advanced), do not.
+  if (S->done && S->applied == S->iter) return;
   __shared__ double mu[kMaxK];
   __shared__ double cv[kMaxK];
   for (int c = threadIdx.x; c < a.k; c += 256) {
@@ -309,7 +331,10 @@ __device__ __forceinline__ void cg_update_p_body(const CgArgs &a, const unsigned
   __syncthreads();
   const int64_t i = int64_t(bid) * 256 + threadIdx.x;
   if (i >= a.n) return;
-  double ri = a.r[i];
+  const double alpha = S->alpha;
+  const double pi = a.p[i];
+  double ri = a.r[i] - alpha * a.q[i];
+  double xn = a.x[i] + alpha * pi;
   double xi = 0.0;
   double wmu = 0.0;
   for (int c = 0; c < a.k; ++c) {
@@ -318,11 +343,10 @@ __device__ __forceinline__ void cg_update_p_body(const CgArgs &a, const unsigned
     xi += wv * cv[c];
     wmu += wv * mu[c];
   }
-  if (a.k > 0) {
-    a.r[i] = ri;
-    a.x[i] += xi;
-  }
-  const double s = ri + S->beta * a.p[i] - wmu;
+  if (a.k > 0) xn += xi;
+  a.r[i] = ri;
+  a.x[i] = xn;
+  const double s = ri + S->beta * pi - wmu;
   a.p[i] = s;
   a.p32[i] = static_cast<float>(s);
 }
@@ -341,7 +365,7 @@ __global__ __launch_bounds__(256) void cg_matvec_finish_multi(const CgArgs *args
 }
 __global__ __launch_bounds__(256) void cg_update_xr_multi(const CgArgs *args) {
   const CgArgs &a = args[blockIdx.y];
-  if (int64_t(blockIdx.x) * 256 >= a.n) return;
+  if (int64_t(blockIdx.x) >= a.nblk_xr * xr_groups(a.k)) return;
   cg_update_xr_body(a, blockIdx.x);
 }
 __global__ __launch_bounds__(256) void cg_finalize_multi(const CgArgs *args) {
@@ -453,6 +477,7 @@ __global__ __launch_bounds__(256) void init_direction(const double *r, const dou
     if (threadIdx.x == 0) {
       S->rho = s;
       S->iter = 0;
+      S->applied = 0;
       S->status = 0;
       const double rel = (S->bnorm > 0.0) ? std::sqrt(s) / S->bnorm : 0.0;
       S->relres = rel;

@@ -66,6 +66,7 @@ __global__ __launch_bounds__(256) void block_init(const double *B, const double 
     s.bnorm = std::sqrt(b2);
     s.rho = r2;
     s.iter = 0;
+    s.applied = 0;
     s.status = 0;
     const double rel = (b2 > 0.0) ? std::sqrt(r2 / b2) : 0.0;
     s.relres = rel;
@@ -89,7 +90,7 @@ static BlockLayout block_layout(int64_t n, int64_t m) {
   };
   const int64_t n_pad = ((n + 255) / 256) * 256;
   const int64_t m4 = ((m + 3) / 4) * 4;
-  const int64_t nq = cdiv(n, kCgRows), nx = cdiv(n, 256);
+  const int64_t nq = cdiv(n, kCgRows), nx = cdiv(n, kXrRows);
   L.args = take(size_t(m) * sizeof(CgArgs));
   L.S = take(size_t(m) * sizeof(SolveState));
   L.R = take(size_t(n) * m * 8);
@@ -191,7 +192,7 @@ int dcg_solve_block(dcg_op_t op, const double *B, double *X, int64_t m, dcg_recy
   HIPCHK(hipGetLastError());
 
   // per-column arguments of the vector kernels
-  const int64_t nq = cdiv(n, kCgRows), nx = cdiv(n, 256);
+  const int64_t nq = cdiv(n, kCgRows), nx = cdiv(n, kXrRows);
   std::vector<CgArgs> args(static_cast<size_t>(m));
   for (int64_t c = 0; c < m; ++c) {
     CgArgs &a = args[static_cast<size_t>(c)];
@@ -218,8 +219,7 @@ int dcg_solve_block(dcg_op_t op, const double *B, double *X, int64_t m, dcg_recy
     a.part = part + c * nq;
     a.part2 = part2 + c * nx;
     a.part_h = parth + c * 2 * kMaxK * nx;
-    a.nblk_q = nq;
-    a.nblk_xr = nx;
+    cg_set_blocks(a);
     a.counter = nullptr;
     double *h = hist + c * (kBlockHist + 3 * kMaxZ);
     a.hist_res = h;
@@ -257,11 +257,11 @@ int dcg_solve_block(dcg_op_t op, const double *B, double *X, int64_t m, dcg_recy
           ++sweeps;
         }
       }
-      hipLaunchKernelGGL(cg_update_xr_multi, dim3(static_cast<unsigned>(nx), static_cast<unsigned>(m)), dim3(256),
-                         0, s, d_args);
+      hipLaunchKernelGGL(cg_update_xr_multi, dim3(static_cast<unsigned>(xr_grid(args[0])), static_cast<unsigned>(m)),
+                         dim3(256), 0, s, d_args);
       hipLaunchKernelGGL(cg_finalize_multi, dim3(1, static_cast<unsigned>(m)), dim3(256), 0, s, d_args);
-      hipLaunchKernelGGL(cg_update_p_multi, dim3(static_cast<unsigned>(nx), static_cast<unsigned>(m)), dim3(256),
-                         0, s, d_args);
+      hipLaunchKernelGGL(cg_update_p_multi, dim3(static_cast<unsigned>(args[0].nblk_p), static_cast<unsigned>(m)),
+                         dim3(256), 0, s, d_args);
       HIPCHK(hipGetLastError());
     }
     HIPCHK(hipMemcpyAsync(hs.data(), S, sizeof(SolveState) * m, hipMemcpyDeviceToHost, s));

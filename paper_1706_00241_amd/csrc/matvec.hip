@@ -24,6 +24,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <type_traits>
+
 #include "blas.h"
 
 namespace dcg {
@@ -221,10 +223,15 @@ __device__ __forceinline__ void symv_body(const SymvArgs &A, const int64_t item)
   }
   const float c0 = A.c0, c1 = A.c1, c2 = A.c2;
 
-  for (int t = 0; t < tiles; ++t) {
+  // One column tile.  DG: the tile lies in the diagonal block pair (offset
+  // 0), where the exact diagonal gets distance zero and no column partials
+  // are formed (the block's row sums already cover both triangles).  Only the
+  // first block pair of chunk 0 is diagonal, so the two cases run as separate
+  // loops and the plain one carries no diagonal test.
+  auto step = [&](const int t, auto dg) {
+    constexpr bool DG = decltype(dg)::value;
     const int dl = d0 + t / NCT;
     const int ct = t % NCT;
-    const bool diag = (dl == 0);
     if (t + 1 < tiles) {
       const int64_t cbx = colbase_of(t + 1);
       cbn.load(A.xc, cbx + lc, A.kstride, lh);
@@ -237,11 +244,13 @@ __device__ __forceinline__ void symv_body(const SymvArgs &A, const int64_t item)
 #pragma unroll
     for (int tr = 0; tr < TR; ++tr) {
       f32x16 r2 = tile_r2<BF16, KS>(ra[tr], cb);
-      if (diag && ct == w * TR + tr) {
-        // the exact diagonal: distance zero by definition
+      if constexpr (DG) {
+        if (ct == w * TR + tr) {
+          // the exact diagonal: distance zero by definition
 #pragma unroll
-        for (int v = 0; v < 16; ++v)
-          if (8 * (v >> 2) + 4 * lh + (v & 3) == lc) r2[v] = 0.0f;
+          for (int v = 0; v < 16; ++v)
+            if (8 * (v >> 2) + 4 * lh + (v & 3) == lc) r2[v] = 0.0f;
+        }
       }
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
@@ -249,11 +258,11 @@ __device__ __forceinline__ void symv_body(const SymvArgs &A, const int64_t item)
 #pragma unroll
         for (int m = 0; m < MV; ++m) {
           accr[m][tr][v] = fmaf(kv, pj[m], accr[m][tr][v]);
-          cs[m] = fmaf(kv, pi[m][tr][v], cs[m]);
+          if constexpr (!DG) cs[m] = fmaf(kv, pi[m][tr][v], cs[m]);
         }
       }
     }
-    if (!diag) {
+    if constexpr (!DG) {
 #pragma unroll
       for (int m = 0; m < MV; ++m) {
         cs[m] += __shfl_xor(cs[m], 32);
@@ -290,7 +299,11 @@ __device__ __forceinline__ void symv_body(const SymvArgs &A, const int64_t item)
 #pragma unroll
       for (int m = 0; m < MV; ++m) pj[m] = pjn[m];
     }
-  }
+  };
+  int t = 0;
+  if (d0 == 0)
+    for (const int tdiag = min(tiles, NCT); t < tdiag; ++t) step(t, std::true_type());
+  for (; t < tiles; ++t) step(t, std::false_type());
 
   // Row sums: reduce over the 32 lanes that hold the same rows.
 #pragma unroll

@@ -193,11 +193,10 @@ static CgArgs cg_args(dcg_operator_s *op, const SolveBuffers &B, double *x, dcg_
   a.AZ = (rc && L > 0) ? rc->AZ : nullptr;
   a.koff = k;
   a.L = L;
+  cg_set_blocks(a);
   a.part = B.part;
-  a.part2 = B.part + std::max<int64_t>(cdiv(op->g.n, kCgRows), 1);
+  a.part2 = B.part + std::max<int64_t>(a.nblk_q, 1);
   a.part_h = B.part_h;
-  a.nblk_q = cdiv(op->g.n, kCgRows);
-  a.nblk_xr = cdiv(op->g.n, 256);
   a.counter = B.counter;
   a.hist_d = B.hist_d;
   a.hist_alpha = B.hist_alpha;
@@ -223,12 +222,13 @@ static int enqueue_cg_step(dcg_operator_s *op, const CgArgs &a, hipEvent_t ev0 =
                      : launch_symv_sweep(op, 1, &a.S->done);
   if (ev1 != nullptr && record_event(ev1, op->stream, in_graph) != hipSuccess) return DCG_E_HIP;
   if (st != DCG_OK) return st;
-  const dim3 grid(static_cast<unsigned>(cdiv(op->g.n, 256)));
   hipLaunchKernelGGL(cg_matvec_finish, dim3(static_cast<unsigned>(a.nblk_q)), dim3(256), 0,
                      op->stream, a);
-  hipLaunchKernelGGL(cg_update_xr, grid, dim3(256), 0, op->stream, a);
+  hipLaunchKernelGGL(cg_update_xr, dim3(static_cast<unsigned>(xr_grid(a))), dim3(256), 0,
+                     op->stream, a);
   hipLaunchKernelGGL(cg_finalize, dim3(1), dim3(256), 0, op->stream, a);
-  hipLaunchKernelGGL(cg_update_p, grid, dim3(256), 0, op->stream, a);
+  hipLaunchKernelGGL(cg_update_p, dim3(static_cast<unsigned>(a.nblk_p)), dim3(256), 0,
+                     op->stream, a);
   return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
 }
 
