@@ -42,7 +42,7 @@ SLOTS_PER_PAIR = {0: 5, 1: 8, 2: 10}
 # HBM bytes per launch of the sweep measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled by a 256 MiB copy) for this workload and this version of
 # the kernel; None for any other configuration.
-SWEEP_TRAFFIC = {("bf16", 65536, 32, 2, 8192): 115.8e6}
+SWEEP_TRAFFIC = {("bf16", 65536, 32, 2, 8192): 115.3e6}
 
 
 def parse():
