@@ -22,29 +22,58 @@ from . import cg as _cg
 from . import ritz as _ritz
 
 
-def refine(A64, A_low, b, tol=1e-8, inner_tol=1e-4, k=0, L=0, max_outer=20):
-    """Returns (x, history of |r_t|/|b|, list of inner DefCGResult)."""
+def refine(A64, A_low, b, tol=1e-8, inner_tol=1e-4, k=0, L=0, max_outer=20, extract="every",
+           W=None, AW=None):
+    """Returns (x, history of |r_t|/|b|, list of inner DefCGResult, (W, AW)).
+
+    extract (with k > 0) says when the recycled basis is refreshed (section
+    2.3, Eq. 7) from Z = [W, stored directions]:
+      "every": after every inner solve, from that solve's first L directions;
+      "first": after the first inner solve only (the operator A~ is the same
+               for all inner solves of one call);
+      "accum": once, after the last inner solve, from the directions of the
+               inner solves in order, up to L of them (W is unchanged meanwhile).
+    W, AW: a basis carried in (AW its product with A~)."""
     mv64 = A64 if callable(A64) else (lambda v, A=np.asarray(A64): A @ v)
     mvl = A_low if callable(A_low) else (lambda v, A=np.asarray(A_low): A @ v)
+    if extract not in ("every", "first", "accum"):
+        raise ValueError(extract)
     b = np.asarray(b, dtype=np.float64)
     bn = np.linalg.norm(b)
     x = np.zeros_like(b)
     hist, inner = [], []
-    W = AW = None
+    P_acc, AP_acc = [], []
     for _ in range(max_outer + 1):
         r = b - mv64(x)
         hist.append(np.linalg.norm(r) / bn)
         if hist[-1] <= tol or len(inner) == max_outer:
             break
-        res = _cg.defcg(mvl, r, W=W, AW=AW, tol=inner_tol, L=L if k > 0 else 0)
+        if k == 0:
+            store = 0
+        elif extract == "every" or (extract == "first" and not inner):
+            store = L
+        elif extract == "accum":
+            store = L - sum(P.shape[1] for P in P_acc)
+        else:
+            store = 0
+        res = _cg.defcg(mvl, r, W=W, AW=AW, tol=inner_tol, L=store)
         inner.append(res)
         x = x + res.x
-        if k > 0:
-            Z = res.P if W is None else np.hstack([W, res.P])
-            AZ = res.AP if W is None else np.hstack([AW, res.AP])
-            if Z.shape[1] > 0:
+        if store > 0 and res.P.shape[1] > 0:
+            if extract == "accum":
+                P_acc.append(res.P)
+                AP_acc.append(res.AP)
+            else:
+                Z = res.P if W is None else np.hstack([W, res.P])
+                AZ = res.AP if W is None else np.hstack([AW, res.AP])
                 W, AW, _, _ = _ritz.harmonic_ritz(Z, AZ, k)
-    return x, hist, inner
+    if extract == "accum" and P_acc:
+        P = np.hstack(P_acc)
+        AP = np.hstack(AP_acc)
+        Z = P if W is None else np.hstack([W, P])
+        AZ = AP if W is None else np.hstack([AW, AP])
+        W, AW, _, _ = _ritz.harmonic_ritz(Z, AZ, k)
+    return x, hist, inner, (W, AW)
 
 
 def fcg_outer(mv64, precond, b, tol=1e-8, max_outer=20, x0=None):

@@ -209,7 +209,7 @@ def test_refine_recovers_fp64_solution_from_bf16_operator():
     Xl = P.round_bf16(X)
     Alow = K.operator(Xl, K.MATERN52, ell, 1.0, 1e-3)
     b = g.standard_normal(300)
-    x, hist, inner = R.refine(A64, Alow, b, tol=1e-8, inner_tol=1e-4, k=6, L=9)
+    x, hist, inner, _ = R.refine(A64, Alow, b, tol=1e-8, inner_tol=1e-4, k=6, L=9)
     assert hist[-1] <= 1e-8
     x_ref = np.linalg.solve(A64, b)
     assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) < 1e-6
@@ -307,9 +307,44 @@ def test_refine_fcg_beats_plain_refinement_on_bf16_operator():
     x, hist, inner = R.refine_fcg(A64, Alow, b, tol=1e-8, inner_tol=1e-2, k=6, L=9)
     assert hist[-1] <= 1e-8
     assert np.linalg.norm(b - A64 @ x) / np.linalg.norm(b) <= 2e-8
-    _, hist_ir, inner_ir = R.refine(A64, Alow, b, tol=1e-8, inner_tol=1e-2, max_outer=60)
+    _, hist_ir, inner_ir, _ = R.refine(A64, Alow, b, tol=1e-8, inner_tol=1e-2, max_outer=60)
     assert hist_ir[-1] <= 1e-8
     assert len(inner) < len(inner_ir)
+
+
+def test_refine_extraction_modes():
+    """When the recycled basis is refreshed inside refinement: every mode
+    converges; with a single inner solve all modes extract from the same Z;
+    "accum" extracts once from the directions of all inner solves in order
+    (up to L), giving an A~-orthonormal basis equal to the harmonic Ritz
+    extraction of that concatenated subspace."""
+    g = np.random.default_rng(14)
+    X = g.uniform(-1, 1, (400, 6))
+    ell = 0.5 * workloads.median_distance(X)
+    A64 = K.operator(X, K.MATERN52, ell, 1.0, 1e-3)
+    Alow = K.operator(P.round_bf16(X), K.MATERN52, ell, 1.0, 1e-3)
+    b = g.standard_normal(400)
+    outs = {m: R.refine(A64, Alow, b, tol=1e-8, inner_tol=1e-2, k=6, L=30, extract=m)
+            for m in ("every", "first", "accum")}
+    for m, (x, hist, inner, (W, AW)) in outs.items():
+        assert hist[-1] <= 1e-8, m
+        assert W.shape == (400, 6)
+        np.testing.assert_allclose(W.T @ Alow @ W, np.eye(6), atol=1e-8)
+        np.testing.assert_allclose(AW, Alow @ W, atol=1e-8 * np.abs(AW).max())
+    # accum: the extraction over the first L directions of the inner solves
+    _, _, inner, (W, _) = outs["accum"]
+    P_all = np.hstack([r.P for r in inner])[:, :30]
+    AP_all = np.hstack([r.AP for r in inner])[:, :30]
+    assert sum(min(r.iters, 30) for r in inner) >= 30
+    Wr, _, _, _ = RZ.harmonic_ritz(P_all, AP_all, 6)
+    # same span (signs and order within equal values aside)
+    s = np.linalg.svd(np.linalg.qr(W)[0].T @ np.linalg.qr(Wr)[0], compute_uv=False)
+    assert s.min() > 1 - 1e-8
+    # one inner solve: identical bases in all modes
+    single = [R.refine(A64, Alow, b, tol=1e-8, inner_tol=1e-2, k=6, L=30, max_outer=1, extract=m)[3][0]
+              for m in ("every", "first", "accum")]
+    np.testing.assert_allclose(single[0], single[1], rtol=0, atol=0)
+    np.testing.assert_allclose(single[0], single[2], rtol=0, atol=0)
 
 
 def test_gp_gradient_matches_finite_differences():
