@@ -61,6 +61,9 @@ def parse():
                     help="relative tolerance of each inner (low-precision) solve; the bf16 "
                          "operator contracts the refinement error by ~0.1 per step, so "
                          "tighter inner solves only add iterations")
+    ap.add_argument("--refresh", choices=["first", "accum"], default="first",
+                    help="refresh W after the first inner solve, or once per system from the "
+                         "directions of all its inner solves")
     ap.add_argument("--refine", choices=["ir", "fcg"], default="ir",
                     help="outer loop: iterative refinement or flexible CG in FP64")
     ap.add_argument("--no-tune", action="store_true",
@@ -231,6 +234,7 @@ def main():
     ws = dcg.SolveWorkspace(n, dev)
     x = torch.empty(n, dtype=torch.float64, device=dev)
     kw = dict(tol=w["tol"], refine=args.refine, inner_tol=args.inner_tol, ws=ws, out=x,
+              refresh_every=args.refresh,
               check_every=8)
 
     for i in range(args.warmup):
@@ -283,6 +287,7 @@ def main():
                                 + f": n={n} d={d} X~U[-1,1] matern52 ell={w['ell']:.4f} "
                                 f"sigma2=1e-3*0.9^i k={w['k']} L={w['L']} refine to 1e-8"),
                    "systems_timed": args.steps, "first_system": args.warmup,
+                   "refine": args.refine, "refresh": args.refresh, "inner_tol": args.inner_tol,
                    "sweep_items": items},
         "iters_per_solve": round(sum(s["iters"] for s in stats) / args.steps, 1),
         "matvecs_per_solve": round(sum(s["matvecs"] for s in stats) / args.steps, 1),

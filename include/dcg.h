@@ -90,9 +90,12 @@ typedef struct {
   int profile;         /* 1: time every matvec sweep with HIP events on the
                           operator's stream (recorded inside the iteration
                           graph when use_graph = 1)                          */
-  int refresh_every;   /* refine > 0 only: 0 extracts W' after the first inner
-                          solve of each dcg_solve call (the operator does not
-                          change between its inner solves), 1 after every one */
+  int refresh_every;   /* refine > 0 only, when the inner solves refresh W:
+                          0 after the first inner solve of each dcg_solve
+                          call (the operator does not change between them),
+                          1 after every one, 2 once after the last one, from
+                          the directions of all inner solves in order (up to
+                          L; W unchanged meanwhile); DCG_E_ARG otherwise     */
 } dcg_params;
 
 /* Per-solve statistics (host struct, filled by dcg_solve). */

@@ -325,6 +325,13 @@ class SolveWorkspace:
         self._ws, self.ptr, self.size = _workspace(nbytes, device)
 
 
+def _refresh_mode(mode):
+    modes = {False: 0, None: 0, 0: 0, "first": 0, True: 1, 1: 1, "every": 1, 2: 2, "accum": 2}
+    if mode not in modes:
+        raise ValueError(f"refresh_every must be 'first', 'every' or 'accum', not {mode!r}")
+    return modes[mode]
+
+
 def _refine_mode(refine):
     if refine in (False, None, 0):
         return 0
@@ -360,7 +367,7 @@ def solve(op, b, x0=None, rc=None, tol=1e-6, max_iter=0, L=0, select_largest=Tru
                select_largest=1 if select_largest else 0, check_every=int(check_every),
                refine=_refine_mode(refine), inner_tol=float(inner_tol), refine_max=int(refine_max),
                use_graph=1 if use_graph else 0, true_residual=1 if true_residual else 0,
-               profile=1 if profile else 0, refresh_every=1 if refresh_every else 0)
+               profile=1 if profile else 0, refresh_every=_refresh_mode(refresh_every))
     st = Stats()
     with _ordered(op.stream):
         status = lib.dcg_solve(op.handle, b.data_ptr(), out.data_ptr(), x_given,

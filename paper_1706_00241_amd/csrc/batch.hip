@@ -220,7 +220,7 @@ int dcg_solve_batched(int count, const dcg_op_t *ops, const double *const *b, do
   std::vector<InnerResult> R(count);
   for (int s = 0; s < count; ++s) {
     dcg_recycle_s *rc = rcs ? rcs[s] : nullptr;
-    const int st = solve_init(ops[s], b[s], x[s], x_given, rc, p, p->tol, base + BL.sys[s], true,
+    const int st = solve_init(ops[s], b[s], x[s], x_given, rc, p, p->tol, base + BL.sys[s], StorePlan(),
                               &ctx[s], &R[s]);
     if (st != DCG_OK) {
       if (stats != nullptr) stats[s].status = st;

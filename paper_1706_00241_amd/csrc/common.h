@@ -96,7 +96,7 @@ struct dcg_recycle_s {
   int64_t n;
   int k, L;
   int k_used;            // columns of W currently valid
-  int L_eff;             // stored directions of the last solve
+  int L_eff;             // columns of Z used by the last extraction
   int aw_state;          // 0: AW invalid, 1: AW valid for (op, generation)
   const dcg_operator_s *aw_op;
   uint64_t aw_gen;

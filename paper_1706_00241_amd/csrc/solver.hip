@@ -172,7 +172,7 @@ int deflation_setup(dcg_operator_s *op, dcg_recycle_s *rc, int *matvecs) {
 }
 
 static CgArgs cg_args(dcg_operator_s *op, const SolveBuffers &B, double *x, dcg_recycle_s *rc,
-                      const double *Minv, int k, int L, double tol, int max_iter) {
+                      const double *Minv, int k, int L, int koff, double tol, int max_iter) {
   CgArgs a;
   a.S = B.S;
   a.red = reduce_args(op, 1, nullptr, nullptr);
@@ -191,7 +191,7 @@ static CgArgs cg_args(dcg_operator_s *op, const SolveBuffers &B, double *x, dcg_
   a.k = k;
   a.Z = (rc && L > 0) ? rc->Z : nullptr;
   a.AZ = (rc && L > 0) ? rc->AZ : nullptr;
-  a.koff = k;
+  a.koff = koff;
   a.L = L;
   cg_set_blocks(a);
   a.part = B.part;
@@ -235,8 +235,8 @@ static int enqueue_cg_step(dcg_operator_s *op, const CgArgs &a, hipEvent_t ev0 =
 // Phase 1 of a solve (Algorithm 1 initialisation): AW, M^{-1}, r_0, the
 // deflated start and p_0; leaves the device state ready for the iteration.
 int solve_init(dcg_operator_s *op, const double *b, double *x, int x_given,
-                      dcg_recycle_s *rc, const dcg_params *p, double tol, void *ws, bool extract,
-                      SolveCtx *ctx, InnerResult *out) {
+                      dcg_recycle_s *rc, const dcg_params *p, double tol, void *ws,
+                      const StorePlan &sp, SolveCtx *ctx, InnerResult *out) {
   const auto t0 = Clock::now();
   hipStream_t s = op->stream;
   const int64_t n = op->g.n, n_pad = op->g.n_pad;
@@ -244,9 +244,12 @@ int solve_init(dcg_operator_s *op, const double *b, double *x, int x_given,
   const int max_iter = p->max_iter > 0 ? p->max_iter : static_cast<int>(std::min<int64_t>(10 * n, 1 << 30));
   int L = 0;
   int k = 0;
+  int koff = 0;
   if (rc != nullptr) {
-    L = extract ? ((p->L > 0) ? std::min(p->L, rc->L) : rc->L) : 0;
     k = rc->k_used;
+    koff = sp.off >= 0 ? sp.off : k;
+    L = sp.count >= 0 ? sp.count : ((p->L > 0) ? std::min(p->L, rc->L) : rc->L);
+    L = std::max(0, std::min(L, rc->k + rc->L - koff));
   }
   int matvecs = 0;
   const double *Minv = nullptr;
@@ -289,12 +292,13 @@ int solve_init(dcg_operator_s *op, const double *b, double *x, int x_given,
   out->t_init = ms_since(t0);
 
   ctx->B = B;
-  ctx->a = cg_args(op, B, x, rc, Minv, k, L, tol, max_iter);
+  ctx->a = cg_args(op, B, x, rc, Minv, k, L, koff, tol, max_iter);
   ctx->k = k;
   ctx->L = L;
+  ctx->koff = koff;
   ctx->matvecs = matvecs;
   ctx->tol = tol;
-  ctx->extract = extract;
+  ctx->extract = sp.extract && rc != nullptr;
   return DCG_OK;
 }
 
@@ -382,51 +386,56 @@ int solve_loop(dcg_operator_s *op, const dcg_params *p, SolveCtx *ctx, InnerResu
 }
 
 
-// Phase 3: the harmonic Ritz extraction of W' = Z U (section 2.3, Eq. 7)
-// from Z = [W, P_L] of this solve.
-int solve_extract(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_params *p, SolveCtx *ctx,
-                         InnerResult *out) {
+// The harmonic Ritz extraction of W' = Z U (section 2.3, Eq. 7) from the
+// first mz columns of Z = [W, stored directions] and AZ.
+int extract_basis(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_params *p, int mz,
+                  InnerResult *out) {
   hipStream_t s = op->stream;
   const int64_t n = op->g.n;
-  const int k = ctx->k;
+  if (mz <= 0) return DCG_OK;
+  enqueue_tsgemm_tn(s, rc->AZ, rc->Z, n, mz, mz, rc->gemm, kGemmPartDoubles, rc->F, mz, 1);
+  enqueue_tsgemm_tn(s, rc->AZ, rc->AZ, n, mz, mz, rc->gemm, kGemmPartDoubles, rc->G, mz, 1);
+  enqueue_harmonic_ritz(s, rc->F, rc->G, mz, rc->k, p->select_largest, 1e-12, rc->eigw, rc->U,
+                        rc->small, rc->info);
+  int info[4] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(info, rc->info, sizeof(info), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(rc->theta, rc->small, sizeof(double) * kMaxK, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int knew = info[0];
+  rc->rank_F = info[1];
+  rc->sweeps[0] = info[2];
+  rc->sweeps[1] = info[3];
+  if (knew > 0) {
+    enqueue_ts_times_small(s, rc->Z, n, mz, rc->U, kMaxK, knew, rc->Wt);
+    enqueue_ts_times_small(s, rc->AZ, n, mz, rc->U, kMaxK, knew, rc->AWt);
+    HIPCHK(hipMemcpyAsync(rc->Z, rc->Wt, size_t(n) * knew * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(rc->AZ, rc->AWt, size_t(n) * knew * 8, hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  rc->k_used = knew;
+  rc->n_theta = knew;
+  rc->w_version += 1;
+  rc->L_eff = mz;
+  // AW' = (AZ) U is the product with this operator
+  rc->aw_state = 1;
+  rc->aw_op = op;
+  rc->aw_gen = op->generation;
+  rc->aw_ell = op->ell;
+  rc->aw_s2 = op->s2;
+  rc->aw_sigma2 = op->sigma2;
+  out->k_next = knew;
+  return DCG_OK;
+}
+
+// Phase 3: the extraction from Z = [W, P_L] of this solve (the directions it
+// stored follow any stored before it).
+int solve_extract(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_params *p, SolveCtx *ctx,
+                  InnerResult *out) {
   const auto t2 = Clock::now();
   if (rc != nullptr && ctx->extract && out->status >= 0) {
-    const int L_eff = std::min(ctx->L, out->iters);
-    const int mz = k + L_eff;
-    if (mz > 0) {
-      enqueue_tsgemm_tn(s, rc->AZ, rc->Z, n, mz, mz, rc->gemm, kGemmPartDoubles, rc->F, mz, 1);
-      enqueue_tsgemm_tn(s, rc->AZ, rc->AZ, n, mz, mz, rc->gemm, kGemmPartDoubles, rc->G, mz, 1);
-      enqueue_harmonic_ritz(s, rc->F, rc->G, mz, rc->k, p->select_largest, 1e-12, rc->eigw, rc->U,
-                            rc->small, rc->info);
-      int info[4] = {0, 0, 0, 0};
-      HIPCHK(hipMemcpyAsync(info, rc->info, sizeof(info), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(rc->theta, rc->small, sizeof(double) * kMaxK, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      const int knew = info[0];
-      rc->rank_F = info[1];
-      rc->sweeps[0] = info[2];
-      rc->sweeps[1] = info[3];
-      if (knew > 0) {
-        enqueue_ts_times_small(s, rc->Z, n, mz, rc->U, kMaxK, knew, rc->Wt);
-        enqueue_ts_times_small(s, rc->AZ, n, mz, rc->U, kMaxK, knew, rc->AWt);
-        HIPCHK(hipMemcpyAsync(rc->Z, rc->Wt, size_t(n) * knew * 8, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(rc->AZ, rc->AWt, size_t(n) * knew * 8, hipMemcpyDeviceToDevice, s));
-      }
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipStreamSynchronize(s));
-      rc->k_used = knew;
-      rc->n_theta = knew;
-      rc->w_version += 1;
-      rc->L_eff = L_eff;
-      // AW' = (AZ) U is the product with this operator
-      rc->aw_state = 1;
-      rc->aw_op = op;
-      rc->aw_gen = op->generation;
-      rc->aw_ell = op->ell;
-      rc->aw_s2 = op->s2;
-      rc->aw_sigma2 = op->sigma2;
-      out->k_next = knew;
-    }
+    const int st = extract_basis(op, rc, p, ctx->koff + std::min(ctx->L, out->iters), out);
+    if (st != DCG_OK) return st;
   }
   out->t_refresh = ms_since(t2);
   out->matvecs = ctx->matvecs;
@@ -437,9 +446,9 @@ int solve_extract(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_params *p, So
 // next basis (section 2.3) when rc is given.
 static int inner_solve(dcg_operator_s *op, const double *b, double *x, int x_given,
                        dcg_recycle_s *rc, const dcg_params *p, double tol, void *ws,
-                       InnerResult *out, bool extract = true) {
+                       InnerResult *out, const StorePlan &sp = StorePlan()) {
   SolveCtx ctx;
-  int st = solve_init(op, b, x, x_given, rc, p, tol, ws, extract, &ctx, out);
+  int st = solve_init(op, b, x, x_given, rc, p, tol, ws, sp, &ctx, out);
   if (st != DCG_OK) return st;
   st = solve_loop(op, p, &ctx, out);
   if (st != DCG_OK) return st;
@@ -464,6 +473,47 @@ int true_residual(dcg_operator_s *op, const double *b, const double *x, int exac
   *rel = (h[1] > 0.0) ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
   return DCG_OK;
 }
+
+// When the inner solves of one refinement refresh the recycled basis:
+// refresh_every = 0 after the first inner solve (the operator is the same for
+// all of them), 1 after every inner solve, 2 once after the last one, from
+// the directions of all the inner solves in order (up to L; W is unchanged
+// meanwhile).
+struct RefineStore {
+  int mode = 0, Lcap = 0, stored = 0;
+  RefineStore(const dcg_params *p, const dcg_recycle_s *rc) : mode(p->refresh_every) {
+    if (rc != nullptr) Lcap = (p->L > 0) ? std::min(p->L, rc->L) : rc->L;
+  }
+  StorePlan plan(int t, const dcg_recycle_s *rc) const {
+    StorePlan sp;
+    if (rc == nullptr) {
+      sp.count = 0;
+      sp.extract = false;
+    } else if (mode == 2) {
+      sp.off = rc->k_used + stored;
+      sp.count = std::max(0, Lcap - stored);
+      sp.extract = false;
+    } else if (mode == 0 && t > 0) {
+      sp.count = 0;
+      sp.extract = false;
+    }
+    return sp;
+  }
+  void after(const StorePlan &sp, int iters) {
+    if (mode == 2) stored += std::min(iters, sp.count);
+  }
+  // the deferred extraction (mode 2)
+  int finish(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_params *p, dcg_stats *st) {
+    if (mode != 2 || rc == nullptr || rc->k_used + stored == 0) return DCG_OK;
+    const auto t0 = Clock::now();
+    InnerResult R;
+    R.k_next = rc->k_used;
+    const int code = extract_basis(op, rc, p, rc->k_used + stored, &R);
+    st->k_next = R.k_next;
+    st->t_refresh_ms += ms_since(t0);
+    return code;
+  }
+};
 
 // ------------------------------------------------ flexible-CG refinement
 //
@@ -539,6 +589,7 @@ static int refine_fcg(dcg_operator_s *op, const double *b, double *x, int x_give
   double rel = relof(rr);
   bool r_true = true;      // r is the FP64 residual of x (not the recursive one)
   double gamma[kFcgCap];
+  RefineStore store(p, rc);
   int t = 0;               // directions kept
   int status = DCG_NOT_CONVERGED;
   while (true) {
@@ -557,9 +608,10 @@ static int refine_fcg(dcg_operator_s *op, const double *b, double *x, int x_give
     if (st->outer_steps == outer_max) break;
     double *Dt = B.fD + int64_t(t) * n, *Qt = B.fQ + int64_t(t) * n;
     InnerResult R;
-    code = inner_solve(op, r, Dt, 0, rc, p, p->inner_tol, ws, &R,
-                       p->refresh_every != 0 || st->outer_steps == 0);
+    const StorePlan sp = store.plan(st->outer_steps, rc);
+    code = inner_solve(op, r, Dt, 0, rc, p, p->inner_tol, ws, &R, sp);
     if (code != DCG_OK) return code;
+    store.after(sp, R.iters);
     st->iters += R.iters;
     st->matvecs += R.matvecs;
     if (st->outer_steps == 0) st->k_used = R.k_used;
@@ -601,6 +653,10 @@ static int refine_fcg(dcg_operator_s *op, const double *b, double *x, int x_give
     rel = relof(rn[0]);
     r_true = false;
     t += 1;
+  }
+  if (status >= 0) {
+    code = store.finish(op, rc, p, st);
+    if (code != DCG_OK) return code;
   }
   st->rel_res_true = rel;
   st->status = status;
@@ -704,7 +760,8 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
   if (st == nullptr) st = &local;
   std::memset(st, 0, sizeof(*st));
   if (op == nullptr || b == nullptr || x == nullptr || p == nullptr) return st->status = DCG_E_ARG;
-  if (!(p->tol >= 0.0) || p->check_every < 0 || p->refine < 0 || p->refine > 2)
+  if (!(p->tol >= 0.0) || p->check_every < 0 || p->refine < 0 || p->refine > 2 ||
+      p->refresh_every < 0 || p->refresh_every > 2)
     return st->status = DCG_E_ARG;
   if (rc != nullptr && rc->n != op->g.n) return st->status = DCG_E_ARG;
   if (ws == nullptr || ws_bytes < solve_layout(op->g.n).total) return st->status = DCG_E_WORKSPACE;
@@ -747,6 +804,7 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
   const int outer_max = p->refine_max > 0 ? p->refine_max : 20;
   double rel = 0.0;
   int status = DCG_NOT_CONVERGED;
+  RefineStore store(p, rc);
   for (int t = 0; t <= outer_max; ++t) {
     // from x = 0 the first residual is b itself
     const bool zero_start = (t == 0 && !x_given);
@@ -767,9 +825,10 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
     if (rel <= p->tol) { status = DCG_OK; break; }
     if (t == outer_max) break;
     InnerResult R;
-    int rcode = inner_solve(op, rhs, delta, 0, rc, p, p->inner_tol, ws, &R,
-                        p->refresh_every != 0 || st->outer_steps == 0);
+    const StorePlan sp = store.plan(st->outer_steps, rc);
+    int rcode = inner_solve(op, rhs, delta, 0, rc, p, p->inner_tol, ws, &R, sp);
     if (rcode != DCG_OK) return st->status = rcode;
+    store.after(sp, R.iters);
     st->iters += R.iters;
     st->matvecs += R.matvecs;
     if (t == 0) st->k_used = R.k_used;
@@ -783,6 +842,10 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
     st->outer_steps += 1;
     if (R.status < 0) { status = R.status; break; }
     enqueue_block_axpy(s, x, delta, 1.0, n);
+  }
+  if (status >= 0) {
+    const int rcode = store.finish(op, rc, p, st);
+    if (rcode != DCG_OK) return st->status = rcode;
   }
   st->rel_res_true = rel;
   st->status = status;

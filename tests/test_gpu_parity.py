@@ -292,6 +292,70 @@ def test_refinement_fcg_matches_oracle(lib, prec, inner_tol):
           f"ir {st_ir['outer_steps']} outer / {st_ir['iters']} its", flush=True)
 
 
+@pytest.mark.parametrize("refine", [True, "fcg"])
+def test_refinement_accumulated_extraction_matches_oracle(lib, refine):
+    """refresh_every = "accum": the inner solves of one system store their
+    directions one after the other (up to L) and the basis is extracted once
+    at the end.  With the FP64 operator inside the refinement the inner solves
+    are those of the oracle step for step (the refinement converges by the
+    inner tolerance, 1e-2 per outer step), so the stored subspace and its
+    harmonic Ritz values match; two systems of the sigma^2 sequence.  (The
+    oracle runs plain refinement; the flexible variant takes the same inner
+    solves here, its outer directions being the inner solutions.)"""
+    from oracle import refine as ORF
+    w = workloads.bf16_shift(n=1200, systems=2)
+    X, b = w["X"], w["b"]
+    op = lib.Operator(_dev(X), w["kernel"], w["ell"], 1.0, w["sigma2s"][0], prec=3)
+    rc = lib.Recycle(1200, 16, 24)
+    W = AW = None
+    for i, s2 in enumerate(w["sigma2s"]):
+        op.set_hyper(w["ell"], 1.0, s2)
+        A = OK.operator(X, w["kernel"], w["ell"], 1.0, s2)
+        x, st = lib.solve(op, _dev(b), rc=rc, tol=1e-8, refine=refine, inner_tol=1e-2,
+                          refresh_every="accum")
+        if W is not None:
+            AW = A @ W
+        xr, hist, inner, (W, AW) = ORF.refine(A, A, b, tol=1e-8, inner_tol=1e-2, k=16,
+                                              L=24, extract="accum", W=W, AW=AW)
+        x = _np(x)
+        assert st["status"] == 0
+        assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= 1.05e-8
+        assert st["outer_steps"] == len(inner), (i, st["outer_steps"], len(inner))
+        its = [r.iters for r in inner]
+        assert abs(st["iters"] - sum(its)) <= len(its), (i, st["iters"], its)
+        assert st["k_next"] == 16
+        # theta_i = |A w_i|^2 for the A-orthonormal harmonic Ritz basis
+        th_ref = np.sort(np.sum(AW * AW, axis=0))[::-1]
+        np.testing.assert_allclose(np.array(rc.theta()), th_ref, rtol=1e-6)
+        Wg = _np(rc.get_W())
+        np.testing.assert_allclose(Wg.T @ A @ Wg, np.eye(16), atol=1e-8)
+
+
+def test_refinement_accumulated_extraction_bf16(lib):
+    """The accumulated schedule with the bf16 operator on a three-system
+    sequence: every solve reaches 1e-8 in the FP64 residual, the basis is
+    refreshed once per system and is A~-orthonormal for the rounded-points
+    operator (which of the inner solves' directions fill the L slots depends
+    on their iteration counts, so the Ritz values are not compared here)."""
+    w = workloads.bf16_shift(n=3000, systems=3)
+    X, b = w["X"], w["b"]
+    Xr = OP.round_bf16(X)
+    op = lib.Operator(_dev(X), w["kernel"], w["ell"], 1.0, w["sigma2s"][0], prec=1)
+    rc = lib.Recycle(3000, 16, 24)
+    for i, s2 in enumerate(w["sigma2s"]):
+        op.set_hyper(w["ell"], 1.0, s2)
+        A64 = OK.operator(X, w["kernel"], w["ell"], 1.0, s2)
+        x, st = lib.solve(op, _dev(b), rc=rc, tol=1e-8, refine=True, inner_tol=1e-2,
+                          refresh_every="accum")
+        x = _np(x)
+        assert st["status"] == 0
+        assert np.linalg.norm(b - A64 @ x) / np.linalg.norm(b) <= 1.05e-8
+        assert st["k_used"] == (0 if i == 0 else 16) and st["k_next"] == 16
+        Alow = OK.operator(Xr, w["kernel"], w["ell"], 1.0, s2)
+        Wg = _np(rc.get_W())
+        np.testing.assert_allclose(Wg.T @ Alow @ Wg, np.eye(16), atol=1e-4)
+
+
 def test_refinement_fcg_from_given_start_and_zero_rhs(lib):
     w = workloads.bf16_shift(n=1500)
     X, b = w["X"], w["b"]
