@@ -75,3 +75,25 @@ def lml_grad_hutchinson(X, y, kernel, ell, s2, sigma2, probes, alpha=None,
         tr = np.sum(U * (D @ probes)) / P
         g.append(0.5 * alpha @ D @ alpha - 0.5 * tr)
     return np.array(g)
+
+
+def lml_grad_hutchinson_blocked(X, kernel, ell, s2, sigma2, alpha, U, probes, block=2048):
+    """lml_grad_hutchinson for given alpha and U without forming n x n
+    matrices: the products dA alpha and dA probes are taken block of rows by
+    block of rows (same formulas, O(n * block) memory; distances in the
+    matrix-product form, kernels.sqdist_gemm)."""
+    n = X.shape[0]
+    P = probes.shape[1]
+    V = np.column_stack([alpha, probes])          # the vectors dA is applied to
+    dK_V = np.zeros_like(V)
+    K_V = np.zeros_like(V)
+    for i0 in range(0, n, block):
+        rows = slice(i0, min(n, i0 + block))
+        r2 = _k.sqdist_gemm(X[rows], X)
+        dK_V[rows] = _k.dkernel_dlog_ell_from_r2(r2, kernel, ell, s2) @ V
+        K_V[rows] = _k.kernel_from_r2(r2, kernel, ell, s2) @ V
+    g = []
+    for DV in (dK_V, K_V, sigma2 * V):
+        tr = np.sum(U * DV[:, 1:]) / P
+        g.append(0.5 * alpha @ DV[:, 0] - 0.5 * tr)
+    return np.array(g)

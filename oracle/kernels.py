@@ -78,8 +78,9 @@ def matvec_blocked(X, kernel, ell, s2, sigma2, V, block=1024):
     return out + sigma2 * V
 
 
-def dgram_dlog_ell(X, kernel, ell, s2):
-    """Derivative of K with respect to log(ell), dense FP64.
+def dgram_dlog_ell(X, kernel, ell, s2, Y=None):
+    """Derivative of K(X, Y) with respect to log(ell), dense FP64 (Y
+    defaults to X).
 
     For the RBF kernel dK/dlog(ell) = K * r^2 / ell^2 (chain rule on
     exp(-r^2 / (2 ell^2))).  For the Matern kernels, with t = c r / ell
@@ -87,7 +88,12 @@ def dgram_dlog_ell(X, kernel, ell, s2):
       Matern-3/2: dk/dlog(ell) = s2 t^2 exp(-t)
       Matern-5/2: dk/dlog(ell) = s2 (t^2 + t^3) / 3 exp(-t)
     """
-    r2 = sqdist(X)
+    return dkernel_dlog_ell_from_r2(sqdist(X, Y), kernel, ell, s2)
+
+
+def dkernel_dlog_ell_from_r2(r2, kernel, ell, s2):
+    """dk/dlog(ell) as a function of the squared distance (formulas above)."""
+    r2 = np.asarray(r2, dtype=np.float64)
     if kernel == RBF:
         return s2 * np.exp(-r2 / (2 * ell * ell)) * r2 / (ell * ell)
     r = np.sqrt(r2)
@@ -98,3 +104,14 @@ def dgram_dlog_ell(X, kernel, ell, s2):
         t = np.sqrt(5.0) * r / ell
         return s2 * (t * t + t ** 3) / 3.0 * np.exp(-t)
     raise ValueError(f"unknown kernel id {kernel}")
+
+
+def sqdist_gemm(X, Y):
+    """|x_i - y_j|^2 as |x_i|^2 + |y_j|^2 - 2 x_i . y_j in FP64 (clipped at
+    0): one matrix product, for blocks too large for the difference form.
+    The cancellation costs ~1e-16 (|x|^2 + |y|^2), far below what the
+    comparisons that use it resolve."""
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    r2 = np.sum(X * X, axis=1)[:, None] + np.sum(Y * Y, axis=1)[None, :] - 2.0 * (X @ Y.T)
+    return np.maximum(r2, 0.0)

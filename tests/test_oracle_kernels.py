@@ -124,3 +124,17 @@ def test_round_bf16x2():
 def test_round_fp32():
     assert P.round_fp32(np.array([0.1]))[0] == float(np.float32(0.1))
     assert P.round_points(np.array([[0.1]]), P.PREC_FP64)[0, 0] == 0.1
+
+
+def test_sqdist_gemm_matches_difference_form():
+    g = np.random.default_rng(44)
+    X = 3.0 * g.standard_normal((200, 7))
+    Y = g.uniform(-2, 2, (150, 7))
+    ref = K.sqdist(X, Y)
+    got = K.sqdist_gemm(X, Y)
+    scale = np.sum(X * X, 1)[:, None] + np.sum(Y * Y, 1)[None, :]
+    assert np.all(np.abs(got - ref) <= 1e-13 * scale)
+    # identical points: exactly zero after the clip, never negative
+    Z = K.sqdist_gemm(X, X)
+    assert np.all(Z >= 0.0)
+    assert np.all(np.diag(Z) <= 1e-13 * 2.0 * np.sum(X * X, 1))

@@ -347,6 +347,23 @@ def test_refine_extraction_modes():
     np.testing.assert_allclose(single[0], single[2], rtol=0, atol=0)
 
 
+@pytest.mark.parametrize("kern", [K.RBF, K.MATERN32, K.MATERN52])
+def test_gp_blocked_gradient_equals_dense(kern):
+    """The matrix-free, row-blocked Hutchinson gradient is the dense one
+    (same alpha, U, probes), for blocks that do and do not divide n."""
+    g = np.random.default_rng(41)
+    X = g.standard_normal((333, 4))
+    y = g.standard_normal(333)
+    Z = np.where(g.random((333, 5)) < 0.5, -1.0, 1.0)
+    A = K.operator(X, kern, 1.3, 0.8, 0.05)
+    alpha = np.linalg.solve(A, y)
+    U = np.linalg.solve(A, Z)
+    dense = GP.lml_grad_hutchinson(X, y, kern, 1.3, 0.8, 0.05, Z, alpha=alpha, U=U)
+    for block in (64, 100, 333, 1000):
+        blk = GP.lml_grad_hutchinson_blocked(X, kern, 1.3, 0.8, 0.05, alpha, U, Z, block=block)
+        np.testing.assert_allclose(blk, dense, rtol=1e-12, atol=1e-12 * np.abs(dense).max())
+
+
 def test_gp_gradient_matches_finite_differences():
     g = np.random.default_rng(14)
     X = g.standard_normal((120, 3))
