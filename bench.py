@@ -71,9 +71,13 @@ def parse():
     ap.add_argument("--sweep-items", type=int, default=0, metavar="N",
                     help="use this sweep plan (work-item target) instead of tuning; for "
                          "profiling runs that should launch only the timed plan")
-    ap.add_argument("--workload", choices=["bf16_shift", "ragged"], default="bf16_shift",
+    ap.add_argument("--workload", choices=["bf16_shift", "ragged", "gp_hyper"],
+                    default="bf16_shift",
                     help="bf16_shift: the headline sequence; ragged: the batching form (64 "
-                         "independent sequences, one batched solve per step)")
+                         "independent sequences, one batched solve per step); gp_hyper: the "
+                         "differentiation form (Adam on the GP marginal likelihood)")
+    ap.add_argument("--adam-steps", type=int, default=50,
+                    help="gp_hyper: Adam steps in all (the first --warmup are not timed)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer (a kernel of known traffic "
                          "for scaling HBM counters)")
@@ -193,6 +197,92 @@ def main_ragged(args):
         sys.exit(1)
 
 
+def main_gp(args):
+    """Differentiation form: GP hyperparameter optimisation, n = 32768, d = 16,
+    RBF, FP32 operator, Adam (lr 0.05) on theta = (log ell, log s2, log
+    sigma2).  One step = the marginal likelihood and its gradient: alpha =
+    A^{-1} y by deflated CG (the recycled W, k = 32, refreshed), 16 Rademacher
+    probe solves reusing W, one fused gradient sweep, the Adam update.  The
+    same steps (each step's recorded theta) are then run without recycling.""" 
+    import math
+
+    import torch
+
+    import paper_1706_00241_amd as dcg
+    import workloads
+
+    dcg.load()
+    w = workloads.gp_hyper()
+    n = w["X"].shape[0]
+    total = max(args.adam_steps, args.warmup + 1)
+    dev = torch.device("cuda:0")
+    X = torch.as_tensor(w["X"], device=dev)
+    y = torch.as_tensor(w["y"], device=dev)
+    probes = [torch.as_tensor(workloads.rademacher(n, w["probes"], step=t), device=dev)
+              for t in range(total)]
+
+    def run(steps, recycle, first=0, replay=None):
+        """Adam from theta_0, or (replay) the given theta of every step."""
+        theta = torch.tensor([w["log_ell"], w["log_s2"], w["log_sigma2"]], dtype=torch.float64,
+                             requires_grad=True)
+        opt = torch.optim.Adam([theta], lr=w["lr"])
+        thetas = []
+        op = dcg.Operator(X, w["kernel"], math.exp(w["log_ell"]), 1.0, math.exp(w["log_sigma2"]),
+                          prec=dcg.PREC_FP32)
+        op.tune(reps=3)
+        rc = dcg.Recycle(n, w["k"], w["L"], device=dev) if recycle else None
+        rows, t_timed = [], 0.0
+        for t in range(steps):
+            if replay is not None:
+                with torch.no_grad():
+                    theta.copy_(torch.tensor(replay[t], dtype=torch.float64))
+            thetas.append(theta.detach().tolist())
+            gpc = dcg.GPContext(op, y, rc, probes[t], tol=w["tol"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            opt.zero_grad()
+            val = dcg.GPMarginalLikelihood.apply(theta, gpc)
+            (-val).backward()
+            if replay is None:
+                opt.step()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if t >= first:
+                t_timed += dt
+            rows.append((float(val), gpc.last["alpha_stats"]["iters"],
+                         gpc.last["probe_stats"]["iters"], dt * 1e3))
+        return rows, t_timed / max(1, steps - first), theta.detach().tolist(), thetas
+
+    rows, ms, theta, thetas = run(total, True, first=args.warmup)
+    for t, r in enumerate(rows):
+        print(f"adam step {t}: data-fit {r[0]:.3f}, alpha its {r[1]}, probe its {r[2]}, "
+              f"{r[3]:.1f} ms", file=sys.stderr, flush=True)
+    out = {
+        "metric": "ms per Adam step (marginal likelihood + gradient), GP hyper-optimisation "
+                  "n=32768, 1 GPU",
+        "value": round(ms * 1e3, 2), "unit": "ms/step", "n_gpus": 1,
+        "steps": total - args.warmup, "warmup": args.warmup, "ms_per_step": round(ms * 1e3, 2),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32 MFMA distances, f32 kernel values, f64 CG", "data": "synthetic",
+        "config": {"workload": "gp_hyper: n=32768 d=16 RBF, y = sin-sum + 0.1 noise, "
+                               "16 Rademacher probes per step, k=32 L=48, tol 1e-6, Adam lr 0.05",
+                   "adam_steps": total},
+        "alpha_iters_per_step": round(sum(r[1] for r in rows[args.warmup:]) / (total - args.warmup), 1),
+        "probe_iters_per_step": round(sum(r[2] for r in rows[args.warmup:]) / (total - args.warmup), 1),
+        "theta_final": [round(v, 5) for v in theta],
+    }
+    if not args.no_plain:
+        # the same steps (the recorded theta of each) without recycling
+        prows, pms, _, _ = run(total, False, first=args.warmup, replay=thetas)
+        out["plain_ms_per_step"] = round(pms * 1e3, 2)
+        out["plain_alpha_iters_per_step"] = round(
+            sum(r[1] for r in prows[args.warmup:]) / (total - args.warmup), 1)
+        out["plain_probe_iters_per_step"] = round(
+            sum(r[2] for r in prows[args.warmup:]) / (total - args.warmup), 1)
+        out["speedup_vs_plain"] = round(pms / ms, 3)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -201,6 +291,8 @@ def main():
         sys.exit(2)
     if args.workload == "ragged":
         return main_ragged(args)
+    if args.workload == "gp_hyper":
+        return main_gp(args)
     import numpy as np
     import torch
 

@@ -77,7 +77,8 @@ def lml_grad_hutchinson(X, y, kernel, ell, s2, sigma2, probes, alpha=None,
     return np.array(g)
 
 
-def lml_grad_hutchinson_blocked(X, kernel, ell, s2, sigma2, alpha, U, probes, block=2048):
+def lml_grad_hutchinson_blocked(X, kernel, ell, s2, sigma2, alpha, U, probes, block=2048,
+                                with_scale=False):
     """lml_grad_hutchinson for given alpha and U without forming n x n
     matrices: the products dA alpha and dA probes are taken block of rows by
     block of rows (same formulas, O(n * block) memory; distances in the
@@ -85,15 +86,25 @@ def lml_grad_hutchinson_blocked(X, kernel, ell, s2, sigma2, alpha, U, probes, bl
     n = X.shape[0]
     P = probes.shape[1]
     V = np.column_stack([alpha, probes])          # the vectors dA is applied to
-    dK_V = np.zeros_like(V)
-    K_V = np.zeros_like(V)
+    Va = np.abs(V)
+    dK_V, K_V = np.zeros_like(V), np.zeros_like(V)
+    dK_Va, K_Va = np.zeros_like(V), np.zeros_like(V)
     for i0 in range(0, n, block):
         rows = slice(i0, min(n, i0 + block))
         r2 = _k.sqdist_gemm(X[rows], X)
-        dK_V[rows] = _k.dkernel_dlog_ell_from_r2(r2, kernel, ell, s2) @ V
-        K_V[rows] = _k.kernel_from_r2(r2, kernel, ell, s2) @ V
-    g = []
-    for DV in (dK_V, K_V, sigma2 * V):
+        D = _k.dkernel_dlog_ell_from_r2(r2, kernel, ell, s2)
+        Kb = _k.kernel_from_r2(r2, kernel, ell, s2)
+        dK_V[rows] = D @ V
+        K_V[rows] = Kb @ V
+        if with_scale:   # both matrices are elementwise non-negative
+            dK_Va[rows] = D @ Va
+            K_Va[rows] = Kb @ Va
+    g, scale = [], []
+    for DV, DVa in ((dK_V, dK_Va), (K_V, K_Va), (sigma2 * V, sigma2 * Va)):
         tr = np.sum(U * DV[:, 1:]) / P
         g.append(0.5 * alpha @ DV[:, 0] - 0.5 * tr)
+        # sum_ij |dA_ij| (|alpha_i alpha_j| + (1/P) sum_p |U_ip Z_jp|) / 2
+        scale.append(0.5 * (np.abs(alpha) @ DVa[:, 0] + np.sum(np.abs(U) * DVa[:, 1:]) / P))
+    if with_scale:
+        return np.array(g), np.array(scale)
     return np.array(g)

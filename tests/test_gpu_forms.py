@@ -126,3 +126,28 @@ def test_mll_autograd_against_exact_gradient(lib):
         fp = OG.lml(Xr, y, 0, *np.exp(th + e))
         fm = OG.lml(Xr, y, 0, *np.exp(th - e))
         assert exact[j] == pytest.approx((fp - fm) / (2 * h), rel=1e-5, abs=1e-6)
+
+
+def test_mll_grad_full_size_differentiation_workload(lib):
+    """The differentiation form at its stated size (n = 32768, d = 16, RBF,
+    16 Rademacher probes, k = 32): the solves alpha = A^{-1} y and
+    U = A^{-1} Z with recycling, then the fused gradient sweep against the
+    oracle's row-blocked Hutchinson gradient on the same alpha, U and probes
+    (FP32-rounded points), to the product tolerance of the small-size test."""
+    w = workloads.gp_hyper()
+    X, y = w["X"], w["y"]
+    n = X.shape[0]
+    ell, s2, sig2 = math.exp(w["log_ell"]), math.exp(w["log_s2"]), math.exp(w["log_sigma2"])
+    op = lib.Operator(_dev(X), 0, ell, s2, sig2, prec=0)
+    rc = lib.Recycle(n, w["k"], w["L"])
+    alpha, st = lib.solve(op, _dev(y), rc=rc, tol=w["tol"], true_residual=True)
+    assert st["status"] == 0 and st["k_next"] == w["k"]
+    Z = workloads.rademacher(n, w["probes"], step=0)
+    U, stb = lib.solve_block(op, _dev(Z), rc=rc, tol=w["tol"])
+    assert stb["status"] == 0 and stb["k_used"] == w["k"]
+    g = np.array(lib.mll_grad(op, alpha, U, _dev(Z)))
+    print("full-size gradient", g, "alpha its", st["iters"], "probe its", stb["iters"], flush=True)
+    ref, scale = OG.lml_grad_hutchinson_blocked(OP.round_fp32(X), 0, ell, s2, sig2, _np(alpha),
+                                                _np(U), Z, with_scale=True)
+    for j in range(3):
+        assert abs(g[j] - ref[j]) <= 2e-5 * scale[j] + 1e-9, (j, g[j], ref[j], scale[j])
