@@ -18,6 +18,9 @@
 namespace dcg {
 
 constexpr int kEigThreads = 1024;
+// Problems up to this (even) size keep the eigenvectors in LDS:
+// packed matrix 44 KB + V 87 KB.
+constexpr int kEigSmall = 104;
 
 __device__ __forceinline__ int pk_idx(int i, int j, int m2) {
   if (i > j) {
@@ -151,18 +154,26 @@ struct EigArgs {
   int *info;            // [0] = columns kept (k_next), [1] = rank of F, [2..3] sweeps
 };
 
+// MAXM: the largest (even) m the instance takes.  VLDS: the eigenvector
+// matrix V of the two Jacobi solves lives in LDS next to the packed matrix
+// (small problems; every Jacobi round updates all of V), else in global work
+// memory.
+template <int MAXM, bool VLDS>
 __global__ __launch_bounds__(kEigThreads) void harmonic_ritz_kernel(EigArgs A) {
-  constexpr int kPacked = (kMaxZ * (kMaxZ + 1)) / 2;
+  constexpr int kPacked = (MAXM * (MAXM + 1)) / 2;
   __shared__ double Ap[kPacked];
-  __shared__ double sc[kMaxZ];
-  __shared__ double lam[kMaxZ];
-  __shared__ int keep[kMaxZ];
+  __shared__ double Vl[VLDS ? MAXM * MAXM : 1];
+  __shared__ double sc[MAXM];
+  __shared__ double lam[MAXM];
+  __shared__ int keep[MAXM];
   __shared__ int nkeep;
-  __shared__ int sel[kMaxZ];
+  __shared__ int sel[MAXM];
   __shared__ JacobiLds L;
   const int m = A.m, tid = threadIdx.x;
   const int m2 = m + (m & 1);
-  constexpr int ld = kMaxZ;
+  constexpr int ld = kMaxZ;                   // B and T (global work)
+  constexpr int ldv = VLDS ? MAXM : kMaxZ;    // V
+  double *V = VLDS ? Vl : A.V;
 
   // 1. scaled F
   for (int i = tid; i < m; i += kEigThreads) {
@@ -178,7 +189,7 @@ __global__ __launch_bounds__(kEigThreads) void harmonic_ritz_kernel(EigArgs A) {
     Ap[pk_idx(i, j, m2)] = v;
   }
   __syncthreads();
-  const int sw1 = jacobi(Ap, m, A.V, ld, L);
+  const int sw1 = jacobi(Ap, m, V, ldv, L);
 
   // 2. drop the numerically null directions of F
   for (int i = tid; i < m; i += kEigThreads) lam[i] = Ap[pk_idx(i, i, m2)];
@@ -198,7 +209,7 @@ __global__ __launch_bounds__(kEigThreads) void harmonic_ritz_kernel(EigArgs A) {
   for (int e = tid; e < m * r; e += kEigThreads) {
     const int i = e / r, t = e % r;
     const int col = keep[t];
-    A.B[i * ld + t] = sc[i] * A.V[i * ld + col] / std::sqrt(lam[col]);
+    A.B[i * ld + t] = sc[i] * V[i * ldv + col] / std::sqrt(lam[col]);
   }
   __syncthreads();
   // T = G B   (m x r)
@@ -225,7 +236,7 @@ __global__ __launch_bounds__(kEigThreads) void harmonic_ritz_kernel(EigArgs A) {
     Ap[pk_idx(t1, t2, r2)] = v;
   }
   __syncthreads();
-  const int sw2 = jacobi(Ap, r, A.V, ld, L);
+  const int sw2 = jacobi(Ap, r, V, ldv, L);
   for (int t = tid; t < r; t += kEigThreads) lam[t] = Ap[pk_idx(t, t, r2)];
   __syncthreads();
   // 3. selection: stable rank by theta (descending if largest)
@@ -244,7 +255,7 @@ __global__ __launch_bounds__(kEigThreads) void harmonic_ritz_kernel(EigArgs A) {
     const int i = e / kk, s = e % kk;
     const int t = sel[s];
     double v = 0.0;
-    for (int u = 0; u < r; ++u) v += A.B[i * ld + u] * A.V[u * ld + t];
+    for (int u = 0; u < r; ++u) v += A.B[i * ld + u] * V[u * ldv + t];
     A.U[i * kMaxK + s] = v;
   }
   for (int s = tid; s < kk; s += kEigThreads) A.theta[s] = lam[sel[s]];
@@ -272,7 +283,10 @@ void enqueue_harmonic_ritz(hipStream_t s, const double *F, const double *G, int 
   a.U = U;
   a.theta = theta;
   a.info = info;
-  hipLaunchKernelGGL(harmonic_ritz_kernel, dim3(1), dim3(kEigThreads), 0, s, a);
+  if (m + (m & 1) <= kEigSmall)
+    hipLaunchKernelGGL((harmonic_ritz_kernel<kEigSmall, true>), dim3(1), dim3(kEigThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((harmonic_ritz_kernel<kMaxZ, false>), dim3(1), dim3(kEigThreads), 0, s, a);
 }
 
 size_t harmonic_ritz_work_doubles() { return size_t(3) * kMaxZ * kMaxZ; }
