@@ -10,6 +10,7 @@
 // and all sums are FP64.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "blas.h"
 
@@ -49,7 +50,8 @@ size_t exact_partial_doubles(int64_t n_pad) {
 // reduction x = k ln2 + r with |r| <= ln2 / 2 (ln 2 split into a double and
 // its FP64 tail, so the fused reduction is exact to ~2^-106), the Taylor
 // series of e^r to degree 13 (remainder below 2e-18 relative), and 2^k
-// applied with ldexp.  Arguments below -745.5 give 0.
+// applied with ldexp.  Arguments below -745.5 give 0 (the clamp keeps the
+// reduction finite for arbitrarily large arguments).
 __device__ __forceinline__ double exp_nonpos(double x) {
   x = fmax(x, -745.5);
   const double k = __builtin_rint(x * 1.4426950408889634);   // 1 / ln 2
@@ -184,10 +186,13 @@ __global__ __launch_bounds__(256, 2) void symv64_kernel(Symv64Args A) {
     cbn.load(A.xc, c1b + lc, lg);
     pjn = A.vin[c1b + lc];
   }
-  for (int t = 0; t < tiles; ++t) {
+  // One column tile; DG: the tile lies in the diagonal block pair, where the
+  // exact diagonal gets distance zero and no column partials are formed.
+  // The diagonal block pair comes first in chunk 0 and runs as its own loop.
+  auto step = [&](const int t, auto dg) {
+    constexpr bool DG = decltype(dg)::value;
     const int dl = d0 + t / NCT;
     const int ct = t % NCT;
-    const bool diag = (dl == 0);
 #pragma unroll
     for (int tr = 0; tr < TR; ++tr) {
       r2n[tr] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -201,14 +206,16 @@ __global__ __launch_bounds__(256, 2) void symv64_kernel(Symv64Args A) {
     double cs = 0.0;
 #pragma unroll
     for (int tr = 0; tr < TR; ++tr) {
-      const bool dz = diag && ct == w * TR + tr;
+      bool dz = false;
+      if constexpr (DG) dz = (ct == w * TR + tr);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
+        double r2v = r2c[tr][v];
         // the exact diagonal: distance zero by definition
-        const double r2v = (dz && lg + 4 * v == lc) ? 0.0 : r2c[tr][v];
+        if constexpr (DG) r2v = (dz && lg + 4 * v == lc) ? 0.0 : r2v;
         const double kv = kval64<KERN>(r2v, A.c0, A.c1);
         accr[tr][v] = fma(kv, pjc, accr[tr][v]);
-        cs = fma(kv, pi[tr][v], cs);
+        if constexpr (!DG) cs = fma(kv, pi[tr][v], cs);
       }
     }
 #pragma unroll
@@ -216,7 +223,7 @@ __global__ __launch_bounds__(256, 2) void symv64_kernel(Symv64Args A) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
       __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);
     }
-    if (!diag) {
+    if constexpr (!DG) {
       cs += __shfl_xor(cs, 16);
       cs += __shfl_xor(cs, 32);
       if (lg == 0) colpart[w][16 * ct + lc] = cs;
@@ -235,7 +242,11 @@ __global__ __launch_bounds__(256, 2) void symv64_kernel(Symv64Args A) {
     cbn = cbn2;
     pjc = pjn;
     pjn = pjn2;
-  }
+  };
+  int t = 0;
+  if (d0 == 0)
+    for (const int tdiag = min(tiles, NCT); t < tdiag; ++t) step(t, std::true_type());
+  for (; t < tiles; ++t) step(t, std::false_type());
 #pragma unroll
   for (int tr = 0; tr < TR; ++tr) {
 #pragma unroll
