@@ -152,12 +152,14 @@ int dcg_matvec_exact(dcg_op_t op, const double *V, double *Y, int64_t m);
  * row partials.  DCG_E_ARG outside the range. */
 int dcg_set_sweep_items(dcg_op_t op, int items);
 
-/* Autotuner of the sweep plan: times `reps` single-vector sweeps (1..1000)
+/* Autotuner of the sweep plans: times `reps` single-vector sweeps (1..1000)
  * for each distinct plan of the targets 256, 512, ..., 8192 on the
  * operator's stream, keeps the fastest and returns it in *items_out with its
- * time per sweep in *ms_out (either may be NULL).  Overwrites the operator's
- * staged vector and partial sums, so it must not overlap a solve with the
- * same operator.  FP64 operators have a fixed plan: nothing is timed. */
+ * time per sweep in *ms_out (either may be NULL); the FP64 sweep (refinement
+ * residuals, FP64 operators) gets its own plan the same way, timed reps / 4
+ * times (for an FP64 operator *items_out and *ms_out describe that one).
+ * Overwrites the operator's staged vectors and partial sums, so it must not
+ * overlap a solve with the same operator. */
 int dcg_tune_operator(dcg_op_t op, int reps, int *items_out, double *ms_out);
 
 void dcg_destroy_operator(dcg_op_t op);

@@ -29,20 +29,21 @@ int exact_stride(int d) {
   return 4 * (ks + (ks & 1));
 }
 
-MatvecPlan exact_plan(int64_t n_pad) {
+MatvecPlan exact_plan(int64_t n_pad, int items) {
   MatvecPlan p;
   p.blk = 128;
   p.nb = static_cast<int>(n_pad / p.blk);
   p.dmax = p.nb / 2;
   const int ndelta = p.dmax + 1;
-  p.chunk = static_cast<int>(std::max<int64_t>(1, cdiv(int64_t(ndelta) * p.nb, 2048)));
+  p.chunk = static_cast<int>(std::max<int64_t>(1, cdiv(int64_t(ndelta) * p.nb, items)));
   p.nchunk = static_cast<int>(cdiv(ndelta, p.chunk));
   p.grid = int64_t(p.nb) * p.nchunk;
   return p;
 }
 
 size_t exact_partial_doubles(int64_t n_pad) {
-  const MatvecPlan p = exact_plan(n_pad);
+  // chunks per row block grow with the item target
+  const MatvecPlan p = exact_plan(n_pad, kSweepItemsMax);
   return size_t(p.nchunk + p.dmax) * size_t(n_pad);
 }
 
@@ -296,12 +297,9 @@ static void launch64(const dcg_operator_s *op, const Symv64Args &a, int64_t grid
   }
 }
 
-// Y = A V with the FP64 operator, vector by vector; `done` (optional) turns
-// every launch into a no-op once a solve has finished.
-int matvec_exact_done(const dcg_operator_s *op, const double *V, double *Y, int64_t m,
-                      const int *done) {
-  const int64_t n = op->g.n, n_pad = op->g.n_pad;
-  const MatvecPlan p = exact_plan(n_pad);
+static Symv64Args exact_args(const dcg_operator_s *op, const int *done, MatvecPlan *plan) {
+  const int64_t n_pad = op->g.n_pad;
+  const MatvecPlan p = exact_plan(n_pad, op->exact_items);
   Symv64Args a;
   a.xr = op->x64r;
   a.xc = op->x64c;
@@ -321,14 +319,34 @@ int matvec_exact_done(const dcg_operator_s *op, const double *V, double *Y, int6
     a.c0 = 0.0;
     a.c1 = std::sqrt(op->kernel == DCG_MATERN32 ? 3.0 : 5.0) / op->ell;
   }
+  *plan = p;
+  return a;
+}
+
+// The FP64 pair sweep over the staged vector op->vin64 (partial sums only).
+int launch_exact_sweep(const dcg_operator_s *op, const int *done) {
+  MatvecPlan p;
+  const Symv64Args a = exact_args(op, done, &p);
+  if (op->kernel == DCG_RBF) launch64<DCG_RBF>(op, a, p.grid);
+  else if (op->kernel == DCG_MATERN32) launch64<DCG_MATERN32>(op, a, p.grid);
+  else launch64<DCG_MATERN52>(op, a, p.grid);
+  return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
+}
+
+// Y = A V with the FP64 operator, vector by vector; `done` (optional) turns
+// every launch into a no-op once a solve has finished.
+int matvec_exact_done(const dcg_operator_s *op, const double *V, double *Y, int64_t m,
+                      const int *done) {
+  const int64_t n = op->g.n, n_pad = op->g.n_pad;
+  MatvecPlan p;
+  const Symv64Args a = exact_args(op, done, &p);
   for (int64_t col = 0; col < m; ++col) {
     const double *Vc = V + col * n;
     double *Yc = Y + col * n;
     hipLaunchKernelGGL(stage64, dim3(static_cast<unsigned>(cdiv(n_pad, 256))), dim3(256), 0,
                        op->stream, Vc, n, n_pad, op->vin64, done);
-    if (op->kernel == DCG_RBF) launch64<DCG_RBF>(op, a, p.grid);
-    else if (op->kernel == DCG_MATERN32) launch64<DCG_MATERN32>(op, a, p.grid);
-    else launch64<DCG_MATERN52>(op, a, p.grid);
+    const int st = launch_exact_sweep(op, done);
+    if (st != DCG_OK) return st;
     hipLaunchKernelGGL(reduce64, dim3(static_cast<unsigned>(cdiv(n, 256))), dim3(256), 0,
                        op->stream, a.prow, a.pcol, n, n_pad, p.nchunk, p.dmax, p.nb, op->s2,
                        op->sigma2, Vc, Yc, done);

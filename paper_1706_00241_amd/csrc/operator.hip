@@ -13,6 +13,8 @@ static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 int exact_stride(int d);
 size_t exact_partial_doubles(int64_t n_pad);
+MatvecPlan exact_plan(int64_t n_pad, int items);
+int launch_exact_sweep(const dcg_operator_s *op, const int *done);
 
 // Round an FP64 value to bfloat16, to nearest with ties to even, in one
 // rounding step from the FP64 value (8 significant bits).  Values below the
@@ -168,6 +170,51 @@ static OpLayout op_layout(const Geometry &g) {
   return L;
 }
 
+// Time `reps` launches of `run` for each distinct plan of the targets and
+// keep the fastest in *field; returns the best target and its time.
+template <class PlanOf, class Run>
+static int tune_field(hipStream_t s, int reps, int *field, PlanOf plan_of, Run run, int *best_out,
+                      float *ms_out) {
+  static const int cand[] = {256, 512, 1024, 2048, 4096, 8192};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess) return DCG_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return DCG_E_HIP;
+  }
+  const int keep = *field;
+  int best = keep, last_chunk = -1, status = DCG_OK;
+  float best_ms = -1.0f;
+  for (int items : cand) {
+    const MatvecPlan p = plan_of(items);
+    if (p.chunk == last_chunk) continue;   // the same plan as the previous target
+    last_chunk = p.chunk;
+    *field = items;
+    status = run();   // warm-up
+    if (status != DCG_OK) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { status = DCG_E_HIP; break; }
+    for (int r = 0; r < reps && status == DCG_OK; ++r) status = run();
+    if (status != DCG_OK) break;
+    float ms = 0.0f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      status = DCG_E_HIP;
+      break;
+    }
+    ms /= static_cast<float>(reps);
+    if (best_ms < 0.0f || ms < best_ms) {
+      best_ms = ms;
+      best = items;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *field = (status == DCG_OK) ? best : keep;
+  *best_out = best;
+  *ms_out = best_ms;
+  return status;
+}
+
 }  // namespace dcg
 
 using namespace dcg;
@@ -208,6 +255,7 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel, doubl
   op->stream = static_cast<hipStream_t>(stream);
   op->generation = 1;
   op->sweep_items = kSweepItemsDefault;
+  op->exact_items = kSweepItemsDefault;
   op->x64r = reinterpret_cast<double *>(base + L.x64r);
   op->x64c = reinterpret_cast<double *>(base + L.x64c);
   op->vin64 = reinterpret_cast<double *>(base + L.vin64);
@@ -271,54 +319,32 @@ int dcg_set_sweep_items(dcg_op_t op, int items) {
 
 int dcg_tune_operator(dcg_op_t op, int reps, int *items_out, double *ms_out) {
   if (op == nullptr || reps < 1 || reps > 1000) return DCG_E_ARG;
-  if (op->g.prec == DCG_PREC_FP64) {
-    // the FP64 sweep has a fixed plan
-    if (items_out != nullptr) *items_out = op->sweep_items;
-    if (ms_out != nullptr) *ms_out = 0.0;
-    return DCG_OK;
-  }
-  static const int cand[] = {256, 512, 1024, 2048, 4096, 8192};
   hipStream_t s = op->stream;
-  // the sweep's cost does not depend on the vector's values
-  if (hipMemsetAsync(op->vin, 0, size_t(op->g.n_pad) * 4 * sizeof(float), s) != hipSuccess)
+  int best = op->sweep_items, best64 = op->exact_items;
+  float ms = 0.0f, ms64 = 0.0f;
+  // the sweeps' costs do not depend on the vector's values
+  if (hipMemsetAsync(op->vin64, 0, size_t(op->g.n_pad) * sizeof(double), s) != hipSuccess)
     return DCG_E_HIP;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (hipEventCreate(&e0) != hipSuccess) return DCG_E_HIP;
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return DCG_E_HIP;
+  // FP64 sweep (refinement residuals, FP64 operators): a few launches
+  int st = tune_field(
+      s, std::max(1, reps / 4), &op->exact_items,
+      [&](int items) { return exact_plan(op->g.n_pad, items); },
+      [&]() { return launch_exact_sweep(op, nullptr); }, &best64, &ms64);
+  if (st != DCG_OK) return st;
+  if (op->g.prec != DCG_PREC_FP64) {
+    if (hipMemsetAsync(op->vin, 0, size_t(op->g.n_pad) * 4 * sizeof(float), s) != hipSuccess)
+      return DCG_E_HIP;
+    st = tune_field(
+        s, reps, &op->sweep_items,
+        [&](int items) { return make_plan(op->g.n_pad, sweep_blk(op->g, 1), items); },
+        [&]() { return launch_symv_sweep(op, 1, nullptr); }, &best, &ms);
+    if (st != DCG_OK) return st;
+  } else {
+    best = best64;
+    ms = ms64;
   }
-  const int keep = op->sweep_items;
-  int best = keep, last_chunk = -1, status = DCG_OK;
-  float best_ms = -1.0f;
-  for (int items : cand) {
-    const MatvecPlan p = make_plan(op->g.n_pad, sweep_blk(op->g, 1), items);
-    if (p.chunk == last_chunk) continue;   // the same plan as the previous target
-    last_chunk = p.chunk;
-    op->sweep_items = items;
-    status = launch_symv_sweep(op, 1, nullptr);   // warm-up
-    if (status != DCG_OK) break;
-    if (hipEventRecord(e0, s) != hipSuccess) { status = DCG_E_HIP; break; }
-    for (int r = 0; r < reps && status == DCG_OK; ++r) status = launch_symv_sweep(op, 1, nullptr);
-    if (status != DCG_OK) break;
-    float ms = 0.0f;
-    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-      status = DCG_E_HIP;
-      break;
-    }
-    ms /= static_cast<float>(reps);
-    if (best_ms < 0.0f || ms < best_ms) {
-      best_ms = ms;
-      best = items;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  op->sweep_items = (status == DCG_OK) ? best : keep;
-  if (status != DCG_OK) return status;
   if (items_out != nullptr) *items_out = best;
-  if (ms_out != nullptr) *ms_out = best_ms;
+  if (ms_out != nullptr) *ms_out = ms;
   return DCG_OK;
 }
 

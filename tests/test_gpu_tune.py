@@ -64,22 +64,22 @@ def test_tuner_returns_candidate(lib, prec):
     X = g.standard_normal((20000, 16))
     ell = workloads.median_distance(X)
     op = lib.Operator(_dev(X), 0, ell, 1.0, 1e-2, prec=prec)
-    items, ms = op.tune(reps=3)
-    assert items in CANDIDATES
-    if prec == 3:
-        assert ms == 0.0
-    else:
-        assert ms > 0.0
-        print(f"prec {prec}: tuned items {items}, {ms:.3f} ms per sweep", flush=True)
+    items, ms = op.tune(reps=4)
+    assert items in CANDIDATES and ms > 0.0
+    print(f"prec {prec}: tuned items {items}, {ms:.3f} ms per sweep", flush=True)
     # the product under the tuned plan, on sampled rows computed by the oracle
     v = g.standard_normal(20000)
     y = _np(op.matvec(_dev(v)))
     Xr = OP.round_points(X, prec)
+    y64 = _np(op.matvec_exact(_dev(v)))    # the FP64 sweep under its tuned plan
     for i in g.choice(20000, size=32, replace=False):
         ki = OK.gram(Xr[i:i + 1], 0, ell, 1.0, Y=Xr)[0]
         ki[i] += 1e-2
         tol = 2e-5 if prec != 3 else 1e-12
         assert abs(y[i] - ki @ v) <= tol * (np.abs(ki) @ np.abs(v))
+        k64 = OK.gram(X[i:i + 1], 0, ell, 1.0, Y=X)[0]
+        k64[i] += 1e-2
+        assert abs(y64[i] - k64 @ v) <= 1e-12 * (np.abs(k64) @ np.abs(v))
 
 
 def test_tuned_batch_equals_single(lib):
