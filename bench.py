@@ -348,7 +348,8 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     for i, st in enumerate(stats):
         print(f"system {args.warmup + i}: {st['iters']} its, {st['outer_steps']} outer, "
-              f"{st['t_total_ms']:.1f} ms (refresh {st['t_refresh_ms']:.1f}), "
+              f"{st['t_total_ms']:.1f} ms (refresh {st['t_refresh_ms']:.1f}: m {st['refresh_dim']} "
+              f"rank {st['refresh_rank']} sweeps {st['refresh_sweeps']}), "
               f"res {st['rel_res_true']:.2e}, status {st['status']}", file=sys.stderr, flush=True)
     bad = [st for st in stats if st["status"] != 0 or st["rel_res_true"] > w["tol"]]
     if bad:

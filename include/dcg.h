@@ -113,6 +113,9 @@ typedef struct {
   double t_init_ms, t_loop_ms, t_refresh_ms, t_total_ms;
   int sweeps_timed;          /* profile = 1: matvec sweeps timed             */
   double t_sweeps_ms;        /* profile = 1: their summed device time        */
+  int refresh_dim;           /* columns of Z = [W, P] in the last extraction */
+  int refresh_rank;          /* of them kept after dropping F's null space   */
+  int refresh_sweeps[2];     /* Jacobi sweeps of its two eigenproblems       */
 } dcg_stats;
 
 /* ---------------------------------------------------------------- operator

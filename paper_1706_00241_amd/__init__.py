@@ -53,10 +53,13 @@ class Stats(ctypes.Structure):
                 ("rel_res_true", ctypes.c_double), ("t_init_ms", ctypes.c_double),
                 ("t_loop_ms", ctypes.c_double), ("t_refresh_ms", ctypes.c_double),
                 ("t_total_ms", ctypes.c_double), ("sweeps_timed", ctypes.c_int),
-                ("t_sweeps_ms", ctypes.c_double)]
+                ("t_sweeps_ms", ctypes.c_double), ("refresh_dim", ctypes.c_int),
+                ("refresh_rank", ctypes.c_int), ("refresh_sweeps", ctypes.c_int * 2)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["refresh_sweeps"] = list(self.refresh_sweeps)
+        return d
 
 
 _lib = None

@@ -58,11 +58,21 @@ struct JacobiLds {
 
 // Eigen-decomposition of the packed symmetric m x m matrix Ap (LDS, padded
 // to even m2 with zero rows).  On return Ap is diagonal (eigenvalues) and V
-// (global, row-major, ld = ldv) holds the eigenvectors in its columns.
-// Returns the number of sweeps used.
+// (row-major, ld = ldv) holds the eigenvectors in its columns.  Returns the
+// number of sweeps used.  MAXM bounds m2.  A round's work items are split
+// into (a, b) = (e / P, e % P) with the quotient from an FP32 product:
+// for e < 2^15 and P <= 96, (e + 1/2) / P is at least 1 / (2P) away from an
+// integer, far above the FP32 rounding, so the floor is exact (checked for
+// every P <= 96 and e < 20000).
+__device__ __forceinline__ int div_small(int e, float inv) {
+  return static_cast<int>((static_cast<float>(e) + 0.5f) * inv);
+}
+
+template <int MAXM>
 __device__ int jacobi(double *Ap, int m, double *V, int ldv, JacobiLds &L) {
   const int m2 = m + (m & 1);
   const int P = m2 / 2;
+  const float invP = 1.0f / static_cast<float>(P > 0 ? P : 1);
   const int tid = threadIdx.x;
   for (int e = tid; e < m * m; e += kEigThreads) V[(e / m) * ldv + e % m] = (e / m == e % m) ? 1.0 : 0.0;
   __syncthreads();
@@ -102,7 +112,7 @@ __device__ int jacobi(double *Ap, int m, double *V, int ldv, JacobiLds &L) {
       }
       __syncthreads();
       for (int e = tid; e < P * P; e += kEigThreads) {
-        const int a = e / P, b = e % P;
+        const int a = div_small(e, invP), b = e - a * P;
         if (a > b) continue;
         const double sa = L.sn[a], sb = L.sn[b];
         if (sa == 0.0 && sb == 0.0) continue;
@@ -129,7 +139,7 @@ __device__ int jacobi(double *Ap, int m, double *V, int ldv, JacobiLds &L) {
         }
       }
       for (int e = tid; e < m * P; e += kEigThreads) {
-        const int i = e / P, b = e % P;
+        const int i = div_small(e, invP), b = e - i * P;
         const double sb = L.sn[b];
         if (sb == 0.0) continue;
         const int pb = L.pp[b], qb = L.qq[b];
@@ -189,7 +199,7 @@ __global__ __launch_bounds__(kEigThreads) void harmonic_ritz_kernel(EigArgs A) {
     Ap[pk_idx(i, j, m2)] = v;
   }
   __syncthreads();
-  const int sw1 = jacobi(Ap, m, V, ldv, L);
+  const int sw1 = jacobi<MAXM>(Ap, m, V, ldv, L);
 
   // 2. drop the numerically null directions of F
   for (int i = tid; i < m; i += kEigThreads) lam[i] = Ap[pk_idx(i, i, m2)];
@@ -236,7 +246,7 @@ __global__ __launch_bounds__(kEigThreads) void harmonic_ritz_kernel(EigArgs A) {
     Ap[pk_idx(t1, t2, r2)] = v;
   }
   __syncthreads();
-  const int sw2 = jacobi(Ap, r, V, ldv, L);
+  const int sw2 = jacobi<MAXM>(Ap, r, V, ldv, L);
   for (int t = tid; t < r; t += kEigThreads) lam[t] = Ap[pk_idx(t, t, r2)];
   __syncthreads();
   // 3. selection: stable rank by theta (descending if largest)

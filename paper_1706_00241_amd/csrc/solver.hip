@@ -753,6 +753,17 @@ size_t dcg_solve_workspace_bytes(int64_t n, int k, int L) {
   return solve_layout(n).total;
 }
 
+// What the last extraction looked like (the handle keeps it).
+static int with_refresh(dcg_stats *st, const dcg_recycle_s *rc, int status) {
+  if (rc != nullptr) {
+    st->refresh_dim = rc->L_eff;
+    st->refresh_rank = rc->rank_F;
+    st->refresh_sweeps[0] = rc->sweeps[0];
+    st->refresh_sweeps[1] = rc->sweeps[1];
+  }
+  return status;
+}
+
 int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_t rc,
               const dcg_params *p, dcg_stats *st, void *ws, size_t ws_bytes) {
   dcg_stats local;
@@ -791,12 +802,12 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
       st->matvecs += 1;
     }
     st->t_total_ms = ms_since(t0);
-    return st->status;
+    return with_refresh(st, rc, st->status);
   }
   if (p->refine == 2) {
     const int code = refine_fcg(op, b, x, x_given, rc, p, st, ws, B);
     st->t_total_ms = ms_since(t0);
-    return code;
+    return with_refresh(st, rc, code);
   }
   // ---- iterative refinement: r_t = b - A64 x_t, A~ d_t = r_t, x += d_t
   double *rhs = B.tmp1, *delta = B.tmp2;
@@ -850,7 +861,7 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
   st->rel_res_true = rel;
   st->status = status;
   st->t_total_ms = ms_since(t0);
-  return status;
+  return with_refresh(st, rc, status);
 }
 
 }  // extern "C"
