@@ -6,11 +6,17 @@
 //   S = diag(F)^-1/2,  S F S = Q Lam Q^T,  keep lam > tau max(lam),
 //   B = S Q_keep Lam_keep^-1/2  (B^T F B = I),
 //   C = B^T G B = Y Theta Y^T,  U = B Y   (U^T F U = I).
-// With nothing dropped this is exactly the symmetric-definite problem.  Both
-// symmetric eigenproblems are solved by cyclic Jacobi with the round-robin
-// (tournament) ordering, so that the m/2 rotations of a round are disjoint
-// and applied in parallel by one workgroup.  The working matrix stays in LDS
-// as a packed upper triangle; eigenvectors accumulate in global memory.
+// With nothing dropped this is exactly the symmetric-definite problem, and
+// then any B with B^T F B = I gives the same pairs.  The kernel first tries
+// the cheap one, B = S R^-1 from the Cholesky factor S F S = R^T R, and keeps
+// it when a bound proves that the drop rule would keep every direction:
+// lam_min >= 1 / trace((S F S)^-1) = 1 / |R^-1|_F^2 and lam_max <= the
+// largest absolute row sum, so 1 / |R^-1|_F^2 > tau * (row sum) means
+// lam_min > tau lam_max.  Otherwise (or if a pivot is too small) it takes the
+// eigendecomposition route above.  The symmetric eigenproblems are solved by
+// cyclic Jacobi with the round-robin (tournament) ordering, so that the m/2
+// rotations of a round are disjoint and applied in parallel by one
+// workgroup.  The working matrix stays in LDS as a packed upper triangle.
 #include <cmath>
 
 #include "blas.h"
@@ -162,6 +168,7 @@ struct EigArgs {
   double *U;            // m x k out, row-major ld = kMaxK
   double *theta;        // k out
   int *info;            // [0] = columns kept (k_next), [1] = rank of F, [2..3] sweeps
+                        // ([2] = 0: the Cholesky route)
 };
 
 // MAXM: the largest (even) m the instance takes.  VLDS: the eigenvector
@@ -177,6 +184,7 @@ __global__ __launch_bounds__(kEigThreads) void harmonic_ritz_kernel(EigArgs A) {
   __shared__ double lam[MAXM];
   __shared__ int keep[MAXM];
   __shared__ int nkeep;
+  __shared__ double lbound;
   __shared__ int sel[MAXM];
   __shared__ JacobiLds L;
   const int m = A.m, tid = threadIdx.x;
@@ -185,42 +193,116 @@ __global__ __launch_bounds__(kEigThreads) void harmonic_ritz_kernel(EigArgs A) {
   constexpr int ldv = VLDS ? MAXM : kMaxZ;    // V
   double *V = VLDS ? Vl : A.V;
 
-  // 1. scaled F
+  // 1. scaled F, and a bound on its largest eigenvalue (largest absolute
+  // row sum)
   for (int i = tid; i < m; i += kEigThreads) {
     const double f = A.F[i * m + i];
     sc[i] = (f > 0.0) ? 1.0 / std::sqrt(f) : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < m2 * m2; e += kEigThreads) {
-    const int i = e / m2, j = e % m2;
-    if (i > j) continue;
-    double v = 0.0;
-    if (i < m && j < m) v = 0.5 * (A.F[i * m + j] + A.F[j * m + i]) * sc[i] * sc[j];
-    Ap[pk_idx(i, j, m2)] = v;
+  auto load_scaled_f = [&]() {
+    for (int e = tid; e < m2 * m2; e += kEigThreads) {
+      const int i = e / m2, j = e % m2;
+      if (i > j) continue;
+      double v = 0.0;
+      if (i < m && j < m) v = 0.5 * (A.F[i * m + j] + A.F[j * m + i]) * sc[i] * sc[j];
+      Ap[pk_idx(i, j, m2)] = v;
+    }
+  };
+  load_scaled_f();
+  for (int i = tid; i < m; i += kEigThreads) {
+    double s = 0.0;
+    for (int j = 0; j < m; ++j) s += fabs(0.5 * (A.F[i * m + j] + A.F[j * m + i]) * sc[i] * sc[j]);
+    lam[i] = s;
   }
-  __syncthreads();
-  const int sw1 = jacobi<MAXM>(Ap, m, V, ldv, L);
-
-  // 2. drop the numerically null directions of F
-  for (int i = tid; i < m; i += kEigThreads) lam[i] = Ap[pk_idx(i, i, m2)];
   __syncthreads();
   if (tid == 0) {
-    double lmax = 0.0;
-    for (int i = 0; i < m; ++i) lmax = fmax(lmax, lam[i]);
-    int r = 0;
-    for (int i = 0; i < m; ++i)
-      if (lam[i] > A.tau * lmax && lam[i] > 0.0) keep[r++] = i;
-    nkeep = r;
+    double b = 0.0;
+    for (int i = 0; i < m; ++i) b = fmax(b, lam[i]);
+    lbound = b;
   }
   __syncthreads();
-  const int r = nkeep;
-  const int r2 = r + (r & 1);
-  // B = S Q_keep Lam^-1/2   (m x r, ld)
-  for (int e = tid; e < m * r; e += kEigThreads) {
-    const int i = e / r, t = e % r;
-    const int col = keep[t];
-    A.B[i * ld + t] = sc[i] * V[i * ldv + col] / std::sqrt(lam[col]);
+  const double floor_lam = A.tau * lbound;
+
+  // 2a. Cholesky S F S = R^T R in place (R in the packed upper triangle,
+  // 1 / R_jj in lam).  Every thread reads the same pivot, so the exit is
+  // uniform; a pivot at or below tau * bound means lam_min is too.
+  bool chol = floor_lam > 0.0;
+  for (int j = 0; chol && j < m; ++j) {
+    const double piv = Ap[pk_idx(j, j, m2)];
+    if (!(piv > floor_lam)) {
+      chol = false;
+      break;
+    }
+    const double rinv = 1.0 / std::sqrt(piv);
+    for (int l = j + 1 + tid; l < m; l += kEigThreads) Ap[pk_idx(j, l, m2)] *= rinv;
+    if (tid == 0) lam[j] = rinv;
+    __syncthreads();
+    const int w = m - j - 1;
+    for (int e = tid; e < w * w; e += kEigThreads) {
+      const int a = e / w, b = e - a * w;
+      if (a > b) continue;
+      const int i = j + 1 + a, l = j + 1 + b;
+      Ap[pk_idx(i, l, m2)] -= Ap[pk_idx(j, i, m2)] * Ap[pk_idx(j, l, m2)];
+    }
+    __syncthreads();
   }
+  // R^-1 (upper triangular) into V, one column per thread by back
+  // substitution, and its squared Frobenius norm
+  if (chol) {
+    double tr = 0.0;
+    for (int c = tid; c < m; c += kEigThreads) {
+      const double xcc = lam[c];
+      V[c * ldv + c] = xcc;
+      tr += xcc * xcc;
+      for (int i = c - 1; i >= 0; --i) {
+        const int base = pk_idx(i, i, m2);
+        double s = 0.0;
+        for (int l = i + 1; l <= c; ++l) s += Ap[base + (l - i)] * V[l * ldv + c];
+        const double x = -s * lam[i];
+        V[i * ldv + c] = x;
+        tr += x * x;
+      }
+      for (int i = c + 1; i < m; ++i) V[i * ldv + c] = 0.0;
+    }
+    tr = eig_block_sum(tr, L.red);
+    chol = tr * floor_lam < 1.0;
+  }
+
+  int r, sw1 = 0;
+  if (chol) {
+    // B = S R^-1   (m x m, ld)
+    r = m;
+    for (int e = tid; e < m * m; e += kEigThreads) {
+      const int i = e / m, t = e % m;
+      A.B[i * ld + t] = sc[i] * V[i * ldv + t];
+    }
+  } else {
+    // 2b. S F S = Q Lam Q^T; drop the numerically null directions of F
+    __syncthreads();
+    load_scaled_f();
+    __syncthreads();
+    sw1 = jacobi<MAXM>(Ap, m, V, ldv, L);
+    for (int i = tid; i < m; i += kEigThreads) lam[i] = Ap[pk_idx(i, i, m2)];
+    __syncthreads();
+    if (tid == 0) {
+      double lmax = 0.0;
+      for (int i = 0; i < m; ++i) lmax = fmax(lmax, lam[i]);
+      int nk = 0;
+      for (int i = 0; i < m; ++i)
+        if (lam[i] > A.tau * lmax && lam[i] > 0.0) keep[nk++] = i;
+      nkeep = nk;
+    }
+    __syncthreads();
+    r = nkeep;
+    // B = S Q_keep Lam^-1/2   (m x r, ld)
+    for (int e = tid; e < m * r; e += kEigThreads) {
+      const int i = e / r, t = e % r;
+      const int col = keep[t];
+      A.B[i * ld + t] = sc[i] * V[i * ldv + col] / std::sqrt(lam[col]);
+    }
+  }
+  const int r2 = r + (r & 1);
   __syncthreads();
   // T = G B   (m x r)
   for (int e = tid; e < m * r; e += kEigThreads) {
