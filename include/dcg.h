@@ -96,6 +96,12 @@ typedef struct {
                           1 after every one, 2 once after the last one, from
                           the directions of all inner solves in order (up to
                           L; W unchanged meanwhile); DCG_E_ARG otherwise     */
+  int ritz_route;      /* reduction of F in the harmonic Ritz problem (Eq. 7):
+                          0: Cholesky when a bound shows that no direction of
+                          F would be dropped as numerically null, else the
+                          eigendecomposition; 1: always the eigendecomposition
+                          (both give the same pairs when nothing is dropped);
+                          DCG_E_ARG otherwise                                 */
 } dcg_params;
 
 /* Per-solve statistics (host struct, filled by dcg_solve). */
@@ -115,7 +121,8 @@ typedef struct {
   double t_sweeps_ms;        /* profile = 1: their summed device time        */
   int refresh_dim;           /* columns of Z = [W, P] in the last extraction */
   int refresh_rank;          /* of them kept after dropping F's null space   */
-  int refresh_sweeps[2];     /* Jacobi sweeps of its two eigenproblems       */
+  int refresh_sweeps[2];     /* Jacobi sweeps of its two eigenproblems (the
+                                first is 0 when F was reduced by Cholesky)  */
 } dcg_stats;
 
 /* ---------------------------------------------------------------- operator

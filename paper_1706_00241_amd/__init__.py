@@ -42,7 +42,8 @@ class Params(ctypes.Structure):
                 ("check_every", ctypes.c_int), ("refine", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("refine_max", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("true_residual", ctypes.c_int),
-                ("profile", ctypes.c_int), ("refresh_every", ctypes.c_int)]
+                ("profile", ctypes.c_int), ("refresh_every", ctypes.c_int),
+                ("ritz_route", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -345,15 +346,26 @@ def _refine_mode(refine):
     raise ValueError(f"refine must be False, True/'ir' or 'fcg', not {refine!r}")
 
 
+def _ritz_route(route):
+    if route in ("auto", 0):
+        return 0
+    if route in ("eigen", 1):
+        return 1
+    raise ValueError(f"ritz_route must be 'auto' or 'eigen', not {route!r}")
+
+
 def solve(op, b, x0=None, rc=None, tol=1e-6, max_iter=0, L=0, select_largest=True,
           check_every=8, refine=False, inner_tol=1e-4, refine_max=20, use_graph=True,
-          true_residual=False, profile=False, refresh_every=False, ws=None, out=None):
+          true_residual=False, profile=False, refresh_every=False, ritz_route="auto", ws=None,
+          out=None):
     """Deflated CG (Algorithm 1) for A x = b; returns (x, stats dict).
 
     rc=None runs plain CG; with a Recycle the solve uses its W and leaves the
     next W' (harmonic Ritz vectors, Eq. 7) in it.  refine=True (or "ir") runs
     iterative refinement to ``tol`` against the FP64 operator, refine="fcg"
     flexible CG in FP64 with the inner deflated solve as preconditioner.
+    ritz_route="eigen" reduces F in the harmonic Ritz problem by its
+    eigendecomposition even where the Cholesky reduction is safe.
     """
     torch = _torch()
     lib = load()
@@ -370,7 +382,8 @@ def solve(op, b, x0=None, rc=None, tol=1e-6, max_iter=0, L=0, select_largest=Tru
                select_largest=1 if select_largest else 0, check_every=int(check_every),
                refine=_refine_mode(refine), inner_tol=float(inner_tol), refine_max=int(refine_max),
                use_graph=1 if use_graph else 0, true_residual=1 if true_residual else 0,
-               profile=1 if profile else 0, refresh_every=_refresh_mode(refresh_every))
+               profile=1 if profile else 0, refresh_every=_refresh_mode(refresh_every),
+               ritz_route=_ritz_route(ritz_route))
     st = Stats()
     with _ordered(op.stream):
         status = lib.dcg_solve(op.handle, b.data_ptr(), out.data_ptr(), x_given,
@@ -408,7 +421,7 @@ def solve_block(op, B, rc=None, tol=1e-6, max_iter=0, check_every=8, out=None):
 
 
 def solve_batched(ops, bs, rcs=None, x0s=None, tol=1e-6, max_iter=0, L=0, select_largest=True,
-                  check_every=8, use_graph=True, true_residual=False, ws=None):
+                  check_every=8, use_graph=True, true_residual=False, ritz_route="auto", ws=None):
     """Independent systems ops[s] x_s = bs[s], each by deflated CG with the
     basis of rcs[s] (or plain CG for a None entry) and the extraction of the
     next basis, iterated in lockstep.  The operators must share one stream.
@@ -441,7 +454,8 @@ def solve_batched(ops, bs, rcs=None, x0s=None, tol=1e-6, max_iter=0, L=0, select
         _wsbuf, ptr, size = ws
     p = Params(tol=float(tol), max_iter=int(max_iter), L=int(L),
                select_largest=1 if select_largest else 0, check_every=int(check_every),
-               use_graph=1 if use_graph else 0, true_residual=1 if true_residual else 0)
+               use_graph=1 if use_graph else 0, true_residual=1 if true_residual else 0,
+               ritz_route=_ritz_route(ritz_route))
     st = (Stats * count)()
     with _ordered(ops[0].stream):
         status = lib.dcg_solve_batched(count, h_ops, h_b, h_x, x_given, h_rc, ctypes.byref(p),

@@ -193,7 +193,9 @@ int dcg_solve_batched(int count, const dcg_op_t *ops, const double *const *b, do
   if (count < 1 || count > kMaxBatch || ops == nullptr || b == nullptr || x == nullptr ||
       p == nullptr)
     return DCG_E_ARG;
-  if (!(p->tol >= 0.0) || p->check_every < 0 || p->refine != 0) return DCG_E_ARG;
+  if (!(p->tol >= 0.0) || p->check_every < 0 || p->refine != 0 || p->ritz_route < 0 ||
+      p->ritz_route > 1)
+    return DCG_E_ARG;
   std::vector<int64_t> ns(count);
   std::set<const void *> seen_op, seen_rc;
   for (int s = 0; s < count; ++s) {

@@ -132,8 +132,8 @@ void enqueue_block_axpy(hipStream_t s, double *Y, const double *X, double alpha,
 void enqueue_small_spd_inverse(hipStream_t s, const double *M, int k, double *Minv, double *work,
                                int *info);
 void enqueue_harmonic_ritz(hipStream_t s, const double *F, const double *G, int m, int k,
-                           int largest, double tau, double *work, double *U, double *theta,
-                           int *info);
+                           int largest, int route, double tau, double *work, double *U,
+                           double *theta, int *info);
 size_t harmonic_ritz_work_doubles();
 
 // matvec.hip

@@ -163,6 +163,7 @@ __device__ int jacobi(double *Ap, int m, double *V, int ldv, JacobiLds &L) {
 struct EigArgs {
   const double *F, *G;  // m x m row-major (ld = m)
   int m, k, largest;
+  int route;            // 0: try Cholesky first, 1: eigendecomposition only
   double tau;
   double *V, *B, *T;    // kMaxZ x kMaxZ work (global)
   double *U;            // m x k out, row-major ld = kMaxK
@@ -227,7 +228,7 @@ __global__ __launch_bounds__(kEigThreads) void harmonic_ritz_kernel(EigArgs A) {
   // 2a. Cholesky S F S = R^T R in place (R in the packed upper triangle,
   // 1 / R_jj in lam).  Every thread reads the same pivot, so the exit is
   // uniform; a pivot at or below tau * bound means lam_min is too.
-  bool chol = floor_lam > 0.0;
+  bool chol = A.route == 0 && floor_lam > 0.0;
   for (int j = 0; chol && j < m; ++j) {
     const double piv = Ap[pk_idx(j, j, m2)];
     if (!(piv > floor_lam)) {
@@ -360,14 +361,15 @@ __global__ __launch_bounds__(kEigThreads) void harmonic_ritz_kernel(EigArgs A) {
 }
 
 void enqueue_harmonic_ritz(hipStream_t s, const double *F, const double *G, int m, int k,
-                           int largest, double tau, double *work, double *U, double *theta,
-                           int *info) {
+                           int largest, int route, double tau, double *work, double *U,
+                           double *theta, int *info) {
   EigArgs a;
   a.F = F;
   a.G = G;
   a.m = m;
   a.k = k;
   a.largest = largest;
+  a.route = route;
   a.tau = tau;
   a.V = work;
   a.B = work + kMaxZ * kMaxZ;

@@ -395,8 +395,8 @@ int extract_basis(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_params *p, in
   if (mz <= 0) return DCG_OK;
   enqueue_tsgemm_tn(s, rc->AZ, rc->Z, n, mz, mz, rc->gemm, kGemmPartDoubles, rc->F, mz, 1);
   enqueue_tsgemm_tn(s, rc->AZ, rc->AZ, n, mz, mz, rc->gemm, kGemmPartDoubles, rc->G, mz, 1);
-  enqueue_harmonic_ritz(s, rc->F, rc->G, mz, rc->k, p->select_largest, 1e-12, rc->eigw, rc->U,
-                        rc->small, rc->info);
+  enqueue_harmonic_ritz(s, rc->F, rc->G, mz, rc->k, p->select_largest, p->ritz_route, 1e-12,
+                        rc->eigw, rc->U, rc->small, rc->info);
   int info[4] = {0, 0, 0, 0};
   HIPCHK(hipMemcpyAsync(info, rc->info, sizeof(info), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(rc->theta, rc->small, sizeof(double) * kMaxK, hipMemcpyDeviceToHost, s));
@@ -772,7 +772,7 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
   std::memset(st, 0, sizeof(*st));
   if (op == nullptr || b == nullptr || x == nullptr || p == nullptr) return st->status = DCG_E_ARG;
   if (!(p->tol >= 0.0) || p->check_every < 0 || p->refine < 0 || p->refine > 2 ||
-      p->refresh_every < 0 || p->refresh_every > 2)
+      p->refresh_every < 0 || p->refresh_every > 2 || p->ritz_route < 0 || p->ritz_route > 1)
     return st->status = DCG_E_ARG;
   if (rc != nullptr && rc->n != op->g.n) return st->status = DCG_E_ARG;
   if (ws == nullptr || ws_bytes < solve_layout(op->g.n).total) return st->status = DCG_E_WORKSPACE;

@@ -179,6 +179,71 @@ def test_defcg_sequence_parity_small(lib, prec, tol, th_rtol):
     assert sum(its[1:]) < sum(p.iters for p in plain[1:])
 
 
+@pytest.mark.parametrize("k,L,sigma2", [(8, 12, 1e-2), (32, 96, 1e-2), (64, 64, 3e-2)])
+def test_ritz_routes_match_oracle(lib, k, L, sigma2):
+    """Both reductions of F in the harmonic Ritz problem (Eq. 7): Cholesky,
+    taken where a bound shows that nothing would be dropped, and the
+    eigendecomposition, forced with ritz_route="eigen".  FP64 operator,
+    three systems of the n = 1024 sequence: each route's harmonic Ritz values
+    against the oracle's (rtol 1e-6), and the two routes' recycled spaces
+    equal.  With (8, 12) the stored directions are A-conjugate to rounding
+    and the automatic choice is always Cholesky.  In the two larger cases
+    the first system's directions have lost A-conjugacy (F is numerically
+    singular: the spectrum is a few large eigenvalues over a cluster at
+    sigma2, whose early Ritz values converge), so the automatic choice must
+    fall back to the eigendecomposition and drop F's null directions as the
+    oracle does.  Z has more than 104 columns later in both (the instance
+    that keeps its eigenvectors in global memory): with (32, 96) F stays
+    singular there, with (64, 64) and sigma2 = 3e-2 it is well conditioned
+    (110 and 119 columns), so that instance's Cholesky route runs.
+    The kept directions then include some with lam down to 1e-12 lam_max,
+    where B carries lam^-1/2 ~ 1e6 and the FP64 rounding of F (~1e-16) moves
+    theta by ~1e-4 relative; GPU and oracle also build Z from two FP64 CG
+    runs that have lost conjugacy differently.  Their Ritz values are
+    compared to rtol 1e-3 there (and on the later systems, whose W comes from
+    that extraction); the two routes' spaces still agree to rounding."""
+    w = workloads.small(systems=3)
+    X = w["X"]
+    n = X.shape[0]
+    tol = 1e-8
+    mats = [OK.operator(X, w["kernel"], ell, 1.0, sigma2) for ell in w["ells"]]
+    bs = [A @ w["xstar"] + w["noise"][i] for i, A in enumerate(mats)]
+    ref = OS.solve_sequence(mats, bs, k=k, L=L, tol=tol)
+    op = lib.Operator(_dev(X), w["kernel"], w["ells"][0], 1.0, sigma2, prec=3)
+    rcs = {route: lib.Recycle(n, k, L) for route in ("auto", "eigen")}
+    chosen = []
+    for i, (ell, A, b) in enumerate(zip(w["ells"], mats, bs)):
+        op.set_hyper(ell, 1.0, sigma2)
+        Ws, its = {}, {}
+        for route, rc in rcs.items():
+            x, st = lib.solve(op, _dev(b), rc=rc, tol=tol, ritz_route=route)
+            print(f"system {i} {route}: {st['iters']} its, Z {st['refresh_dim']} rank "
+                  f"{st['refresh_rank']} sweeps {st['refresh_sweeps']}", flush=True)
+            assert st["status"] == 0
+            assert np.linalg.norm(b - A @ _np(x)) / np.linalg.norm(b) <= 3 * tol
+            cholesky = st["refresh_sweeps"][0] == 0
+            if route == "auto":
+                chosen.append((cholesky, st["refresh_rank"] < st["refresh_dim"],
+                               st["refresh_dim"]))
+            else:
+                assert not cholesky
+            if cholesky:
+                assert st["refresh_rank"] == st["refresh_dim"]
+            th_rtol = 1e-6 if (k, L) == (8, 12) else 1e-3
+            np.testing.assert_allclose(np.array(rc.theta()), ref[i].theta, rtol=th_rtol)
+            Ws[route], its[route] = _np(rc.get_W()), st["iters"]
+        assert abs(its["auto"] - its["eigen"]) <= 1
+        Qa, _ = np.linalg.qr(Ws["auto"])
+        Qb, _ = np.linalg.qr(Ws["eigen"])
+        assert np.linalg.svd(Qa.T @ Qb, compute_uv=False).min() >= 1 - 1e-6
+    if (k, L) == (8, 12):
+        assert all(c for c, _, _ in chosen)
+    else:
+        assert not chosen[0][0] and chosen[0][1]
+    if (k, L) == (64, 64):
+        assert any(c and dim > 104 for c, _, dim in chosen[1:])
+
+
 def test_recycled_basis_is_A_orthonormal(lib):
     w = workloads.small(n=900)
     X = w["X"][:900]
