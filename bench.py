@@ -34,11 +34,12 @@ sys.path.insert(0, ROOT)
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz of non-packed VALU issue
 PEAK_VALU_SLOTS = 256 * 64 * 2.4e9
 # VALU issue slots per unique pair of the symmetric sweep (transcendentals
-# v_exp_f32 / v_sqrt_f32 count 2 slots: measured half rate on gfx950):
-#   RBF        exp2(c r2)                    mul + exp(2) + 2 fma        = 5
-#   Matern-3/2 sqrt, exp, (1 + c t) e        sqrt(2) + mul + exp(2) + fma + mul + 2 fma = 8
-#   Matern-5/2 sqrt, exp, (1 + t + t^2/3) e  sqrt(2) + mul + exp(2) + 2 fma + mul + 2 fma = 10
-SLOTS_PER_PAIR = {0: 5, 1: 8, 2: 10}
+# v_exp_f32 / v_sqrt_f32 count 2 slots: measured half rate on gfx950).  The
+# points are pre-scaled so that r2 = (c r)^2 needs no hyperparameter multiply:
+#   RBF        exp2(-r2)                               exp(2) + 2 fma = 4
+#   Matern-3/2 u = sqrt r2, (1 + ln2 u) 2^-u           sqrt(2) + exp(2) + fma + mul + 2 fma = 7
+#   Matern-5/2 (1 + ln2 u + ln2^2 r2 / 3) 2^-u         sqrt(2) + exp(2) + 2 fma + mul + 2 fma = 9
+SLOTS_PER_PAIR = {0: 4, 1: 7, 2: 9}
 # HBM bytes per launch of the sweep measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled by a 256 MiB copy) for this workload and this version of
 # the kernel; None for any other configuration.

@@ -2,12 +2,16 @@
 
 Test infrastructure only (see ``oracle/__init__``).
 
-The precision form evaluates the distance GEMM on rounded points x~ = rnd(x)
-and defines the low-precision operator as the exact kernel matrix on those
-points, A~ = K(X~, X~) + sigma^2 I.  It therefore stays SPD, and iterative
-refinement against the FP64 operator A = K(X, X) + sigma^2 I recovers the
-FP64 solution.  The paper itself fixes no precision; this is the reading the
-library implements, restated here from the number-format definitions:
+The precision form evaluates the distance GEMM on rounded scaled points and
+defines the low-precision operator as the exact kernel matrix on the points
+they represent, x~ = rnd(c x) / c, A~ = K(X~, X~) + sigma^2 I.  It therefore
+stays SPD, and iterative refinement against the FP64 operator
+A = K(X, X) + sigma^2 I recovers the FP64 solution.  The scale c (see
+``point_scale``) depends on the kernel and the lengthscale only: it makes the
+squared distance of the scaled points the argument of a base-2 exponential,
+so the product evaluates no hyperparameter per pair.  The paper itself fixes
+no precision; this is the reading the library implements, restated here from
+the number-format definitions:
 
 * fp32: IEEE-754 binary32, round to nearest, ties to even (numpy's cast).
 * bf16: bfloat16 = the upper 16 bits of binary32 (8 exponent bits, 7 stored
@@ -16,9 +20,28 @@ library implements, restated here from the number-format definitions:
 * bf16x2: the pair hi + lo with hi = bf16(x), lo = bf16(x - hi).
 """
 
+import math
+
 import numpy as np
 
 PREC_FP32, PREC_BF16, PREC_BF16X2, PREC_FP64 = 0, 1, 2, 3
+RBF, MATERN32, MATERN52 = 0, 1, 2
+LOG2E = 1.4426950408889634     # the double nearest log2(e)
+
+
+def point_scale(kernel, ell):
+    """Scale c of the points before rounding (FP64, the operations in this
+    order, so the value is the library's bit for bit).
+
+    RBF: exp(-r^2 / (2 ell^2)) = 2^-((c r)^2) with c^2 = log2(e) / (2 ell^2).
+    Matern with nu2 = 3 or 5: t = sqrt(nu2) r / ell, e^-t = 2^-(c r) with
+    c = sqrt(nu2) log2(e) / ell.
+    """
+    if kernel == RBF:
+        return math.sqrt(0.5 * LOG2E) / ell
+    if kernel in (MATERN32, MATERN52):
+        return math.sqrt(3.0 if kernel == MATERN32 else 5.0) * LOG2E / ell
+    raise ValueError(f"unknown kernel id {kernel}")
 
 
 def round_fp32(x):
@@ -58,14 +81,14 @@ def round_bf16x2(x):
     return hi + lo
 
 
-def round_points(X, prec):
-    """Points in the operator's compute precision (returned as FP64)."""
-    if prec == PREC_FP32:
-        return round_fp32(X)
-    if prec == PREC_BF16:
-        return round_bf16(X)
-    if prec == PREC_BF16X2:
-        return round_bf16x2(X)
+def round_points(X, prec, kernel, ell):
+    """The points the operator of precision ``prec`` represents, as FP64:
+    rnd(c X) / c with c = point_scale(kernel, ell) (X itself for FP64)."""
+    X = np.asarray(X, dtype=np.float64)
     if prec == PREC_FP64:
-        return np.asarray(X, dtype=np.float64).copy()
-    raise ValueError(f"unknown precision {prec}")
+        return X.copy()
+    rnd = {PREC_FP32: round_fp32, PREC_BF16: round_bf16, PREC_BF16X2: round_bf16x2}.get(prec)
+    if rnd is None:
+        raise ValueError(f"unknown precision {prec}")
+    c = point_scale(kernel, ell)
+    return rnd(c * X) / c

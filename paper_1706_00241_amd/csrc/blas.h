@@ -14,7 +14,6 @@ struct SymvArgs {
   float *pcol;
   int64_t n_pad;
   int nb, dmax, chunk, nchunk;
-  float c0, c1, c2;
   const int *done;    // optional: skip the launch once the solve converged
 };
 
@@ -137,7 +136,13 @@ void enqueue_harmonic_ritz(hipStream_t s, const double *F, const double *G, int 
 size_t harmonic_ritz_work_doubles();
 
 // matvec.hip
-void kernel_constants(int kernel, double ell, float *c0, float *c1, float *c2);
+// Scale c applied to the points of the low-precision operands, so that the
+// squared distance of the operands is (c r)^2 and the kernel needs no
+// hyperparameter in its pair loop: sqrt(log2(e) / 2) / ell for RBF,
+// sqrt(nu2) log2(e) / ell for Matern (nu2 = 3, 5).
+double point_scale(int kernel, double ell);
+constexpr float kLn2 = 0.69314718055994531f;
+constexpr float kLn2Sq3 = 0.16015085096464213f;   // ln2^2 / 3
 int launch_symv_sweep(const dcg_operator_s *op, int mv, const int *done);
 int launch_symv_sweep_from(const dcg_operator_s *op, int mv, const float *vin, const int *done);
 SymvArgs symv_args(const dcg_operator_s *op, int mv, const float *vin, const int *done,

@@ -127,19 +127,21 @@ __device__ __forceinline__ f32x16 dist_tile(const GOp<BF16, KS> &a, const GOp<BF
   return acc;
 }
 
-// kappa (kernel without s2) and its derivative with respect to log ell.
+// kappa (kernel without s2) and its derivative with respect to log ell, from
+// the squared distance r2 = (c r)^2 of the operands (points scaled by
+// c = point_scale(kernel, ell)).
 template <int KERN>
-__device__ __forceinline__ void kval_dlog(float r2, float c0, float c1, float c2, float cd,
-                                          float *k, float *dk) {
+__device__ __forceinline__ void kval_dlog(float r2, float *k, float *dk) {
   if constexpr (KERN == DCG_RBF) {
-    // kappa = exp2(c0 r2), d kappa / d log ell = kappa r2 / ell^2 (cd = 1/ell^2)
-    const float e = __builtin_amdgcn_exp2f(r2 * c0);
+    // kappa = exp2(-r2); d kappa / d log ell = kappa r^2 / ell^2 = kappa 2 ln2 r2
+    const float e = __builtin_amdgcn_exp2f(-r2);
     *k = e;
-    *dk = e * fabsf(r2) * cd;
+    *dk = e * fabsf(r2) * (2.0f * kLn2);
   } else {
-    const float t0 = __builtin_amdgcn_sqrtf(fabsf(r2));
-    const float e = __builtin_amdgcn_exp2f(t0 * c0);
-    const float t = t0 * c1;  // sqrt(nu2) r / ell
+    // u = c r, t = sqrt(nu2) r / ell = ln2 u, e^-t = 2^-u
+    const float u = __builtin_amdgcn_sqrtf(fabsf(r2));
+    const float e = __builtin_amdgcn_exp2f(-u);
+    const float t = u * kLn2;
     if constexpr (KERN == DCG_MATERN32) {
       *k = (1.0f + t) * e;
       *dk = t * t * e;                              // t^2 e^-t
@@ -158,7 +160,7 @@ struct GradArgs {
   double *partial;  // [grid][2]: sum kappa w, sum dkappa w
   int64_t n_pad;
   int nb, dmax, chunk, nchunk;
-  float c0, c1, c2, cd, invP;
+  float invP;
 };
 
 // One wave = 32 rows; 4 waves = 128-row blocks; circulant block pairs as in
@@ -213,7 +215,7 @@ __global__ __launch_bounds__(256, 2) void grad_sweep(GradArgs A) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         float kv, dv;
-        kval_dlog<KERN>(r2[v], A.c0, A.c1, A.c2, A.cd, &kv, &dv);
+        kval_dlog<KERN>(r2[v], &kv, &dv);
         // diagonal block: every ordered pair once; otherwise the pair and its mirror
         const float wv = diag ? fmaf(-A.invP, uz[v], ai[v] * aj)
                               : fmaf(-A.invP, uz[v] + zu[v], 2.0f * ai[v] * aj);
@@ -348,8 +350,6 @@ int dcg_mll_grad(dcg_op_t op, const double *alpha, const double *U, const double
   a.dmax = p.dmax;
   a.chunk = p.chunk;
   a.nchunk = p.nchunk;
-  kernel_constants(op->kernel, op->ell, &a.c0, &a.c1, &a.c2);
-  a.cd = static_cast<float>(1.0 / (op->ell * op->ell));
   a.invP = static_cast<float>(1.0 / double(P));
   const bool bf = op->g.prec == DCG_PREC_BF16;
   int rc;

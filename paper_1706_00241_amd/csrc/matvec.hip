@@ -90,23 +90,27 @@ size_t matvec_partial_floats(int64_t n_pad, int mv, int blk) {
   return size_t(2 * p.nchunk + p.dmax) * size_t(n_pad) * size_t(mv);
 }
 
-// Kernel value without the s2 factor, from the squared distance.
-//   RBF:        exp2(c0 r2),                 c0 = -log2(e) / (2 ell^2)
-//   Matern-3/2: (1 + c1 t) exp2(c0 t),       t = |r|, c0 = -sqrt3 log2(e)/ell, c1 = sqrt3/ell
-//   Matern-5/2: (1 + c1 t + c2 t^2) exp2(c0 t), c0 = -sqrt5 log2(e)/ell,
-//               c1 = sqrt5/ell, c2 = 5/(3 ell^2)
-// |r2| absorbs the tiny negative values FP32 rounding can give at r ~ 0.
+// Kernel value without the s2 factor, from the squared distance of the
+// operands, whose points are pre-scaled by c = point_scale(kernel, ell) so
+// that r2 = (c r)^2 feeds exp2 directly:
+//   RBF:        exp2(-r2)                              c^2 = log2(e) / (2 ell^2)
+//   Matern-3/2: (1 + ln2 u) exp2(-u),          u = c r, c = sqrt3 log2(e) / ell
+//   Matern-5/2: (1 + ln2 u + ln2^2 u^2 / 3) exp2(-u),   c = sqrt5 log2(e) / ell
+// (for the Matern kernels t = sqrt(nu2) r / ell = u ln2, so e^-t = 2^-u).  No
+// multiply by a hyperparameter is left in the pair loop.  |r2| absorbs the
+// tiny negative values FP32 rounding can give at r ~ 0.
 template <int KERN>
-__device__ __forceinline__ float kval(float r2, float c0, float c1, float c2) {
+__device__ __forceinline__ float kval(float r2) {
   if constexpr (KERN == DCG_RBF) {
-    return __builtin_amdgcn_exp2f(r2 * c0);
+    return __builtin_amdgcn_exp2f(-r2);
   } else {
-    const float t = __builtin_amdgcn_sqrtf(fabsf(r2));
-    const float e = __builtin_amdgcn_exp2f(t * c0);
+    const float r2a = fabsf(r2);
+    const float u = __builtin_amdgcn_sqrtf(r2a);
+    const float e = __builtin_amdgcn_exp2f(-u);
     if constexpr (KERN == DCG_MATERN32) {
-      return fmaf(t, c1, 1.0f) * e;
+      return fmaf(kLn2, u, 1.0f) * e;
     } else {
-      return fmaf(t, fmaf(t, c2, c1), 1.0f) * e;
+      return fmaf(kLn2, u, fmaf(kLn2Sq3, r2a, 1.0f)) * e;
     }
   }
 }
@@ -221,7 +225,6 @@ __device__ __forceinline__ void symv_body(const SymvArgs &A, const int64_t item)
 #pragma unroll
     for (int m = 0; m < MV; ++m) pj[m] = A.vin[m * n_pad + cb0 + lc];
   }
-  const float c0 = A.c0, c1 = A.c1, c2 = A.c2;
 
   // One column tile.  DG: the tile lies in the diagonal block pair (offset
   // 0), where the exact diagonal gets distance zero and no column partials
@@ -254,7 +257,7 @@ __device__ __forceinline__ void symv_body(const SymvArgs &A, const int64_t item)
       }
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const float kv = kval<KERN>(r2[v], c0, c1, c2);
+        const float kv = kval<KERN>(r2[v]);
 #pragma unroll
         for (int m = 0; m < MV; ++m) {
           accr[m][tr][v] = fmaf(kv, pj[m], accr[m][tr][v]);
@@ -386,20 +389,10 @@ __global__ __launch_bounds__(256) void stage_vectors(const double *V, int64_t n,
 
 // ----------------------------------------------------------------- dispatch
 
-void kernel_constants(int kernel, double ell, float *c0, float *c1, float *c2) {
+double point_scale(int kernel, double ell) {
   const double log2e = 1.4426950408889634;
-  if (kernel == DCG_RBF) {
-    *c0 = static_cast<float>(-log2e / (2.0 * ell * ell));
-    *c1 = *c2 = 0.0f;
-  } else if (kernel == DCG_MATERN32) {
-    *c0 = static_cast<float>(-std::sqrt(3.0) * log2e / ell);
-    *c1 = static_cast<float>(std::sqrt(3.0) / ell);
-    *c2 = 0.0f;
-  } else {
-    *c0 = static_cast<float>(-std::sqrt(5.0) * log2e / ell);
-    *c1 = static_cast<float>(std::sqrt(5.0) / ell);
-    *c2 = static_cast<float>(5.0 / (3.0 * ell * ell));
-  }
+  if (kernel == DCG_RBF) return std::sqrt(0.5 * log2e) / ell;
+  return std::sqrt(kernel == DCG_MATERN32 ? 3.0 : 5.0) * log2e / ell;
 }
 
 template <int KERN, int KS, int MV, bool BF16>
@@ -455,7 +448,6 @@ SymvArgs symv_args(const dcg_operator_s *op, int mv, const float *vin, const int
   a.chunk = p.chunk;
   a.nchunk = p.nchunk;
   a.done = done;
-  kernel_constants(op->kernel, op->ell, &a.c0, &a.c1, &a.c2);
   if (grid != nullptr) *grid = p.grid;
   return a;
 }

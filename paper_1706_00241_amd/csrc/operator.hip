@@ -42,25 +42,56 @@ __global__ __launch_bounds__(256) void check_finite(const double *X, int64_t cou
     if (!isfinite(X[e])) atomicOr(flag, 1);
 }
 
-// One thread per (padded) point: rounded coordinates, squared norm from the
-// rounded coordinates, and the augmented row / column operands.
-__global__ __launch_bounds__(256) void prepare_points(const double *X, int64_t n, int64_t n_pad,
-                                                      int d, int prec, int kstride, int stride64,
-                                                      void *xr, void *xc, double *x64r,
-                                                      double *x64c) {
+// FP64 operands of the exact operator, one thread per (padded) point, from
+// the input points (once, when the operator is created).
+__global__ __launch_bounds__(256) void prepare_exact(const double *X, int64_t n, int64_t n_pad,
+                                                     int d, int stride64, double *x64r,
+                                                     double *x64c) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n_pad) return;
   const bool real = i < n;
+  // FP64 operands of the exact operator: [-2x, a, 1] and [x, 1, a] with a
+  // the squared norm of the unrounded point, element k stored at
+  // (k % 4) * ksp + k / 4 (the K-step layout of the 16x16x4 FP64 MFMA)
+  const int ksp = stride64 / 4;
+  double *r64 = x64r + i * stride64;
+  double *c64 = x64c + i * stride64;
+  double a64 = 0.0;
+  for (int t = 0; t < stride64; ++t) r64[t] = c64[t] = 0.0;
+  for (int t = 0; t < d; ++t) {
+    const double xv = real ? X[i * d + t] : 0.0;
+    a64 += xv * xv;
+    r64[(t & 3) * ksp + (t >> 2)] = -2.0 * xv;
+    c64[(t & 3) * ksp + (t >> 2)] = xv;
+  }
+  r64[(d & 3) * ksp + (d >> 2)] = a64;
+  r64[((d + 1) & 3) * ksp + ((d + 1) >> 2)] = 1.0;
+  c64[(d & 3) * ksp + (d >> 2)] = 1.0;
+  c64[((d + 1) & 3) * ksp + ((d + 1) >> 2)] = a64;
+}
+
+// Low-precision operands, one thread per (padded) point: the point scaled
+// by `scale` (point_scale of the kernel and lengthscale) and rounded, the
+// squared norm of the rounded scaled point, and the augmented row / column
+// operands.  The coordinates come from the FP64 column operand, which holds
+// x_t at (t % 4) * (stride64 / 4) + t / 4; run at creation and whenever the
+// lengthscale changes.
+__global__ __launch_bounds__(256) void prepare_lowprec(const double *x64c, int64_t n,
+                                                       int64_t n_pad, int d, int prec,
+                                                       int kstride, int stride64, double scale,
+                                                       void *xr, void *xc) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n_pad) return;
+  const bool real = i < n;
+  const int ksp = stride64 / 4;
   double a = 0.0;
-  if (prec == DCG_PREC_FP64) {
-    // exact operator: only the FP64 copy below
-  } else if (prec == DCG_PREC_BF16X2) {
+  if (prec == DCG_PREC_BF16X2) {
     // x = hi + lo, both bf16; the operand columns hold the four product
     // pairings so that <xr_i, xc_j> = a_i + a_j - 2 (hi_i + lo_i).(hi_j + lo_j)
     uint16_t *r = static_cast<uint16_t *>(xr) + i * kstride;
     uint16_t *c = static_cast<uint16_t *>(xc) + i * kstride;
     for (int t = 0; t < d; ++t) {
-      const double xv0 = real ? X[i * d + t] : 0.0;
+      const double xv0 = real ? scale * x64c[i * stride64 + (t & 3) * ksp + (t >> 2)] : 0.0;
       const uint16_t hi = bf16_from_double(xv0);
       const uint16_t lo = bf16_from_double(xv0 - bf16_to_double(hi));
       const double xv = bf16_to_double(hi) + bf16_to_double(lo);
@@ -87,7 +118,8 @@ __global__ __launch_bounds__(256) void prepare_points(const double *X, int64_t n
     uint16_t *r = static_cast<uint16_t *>(xr) + i * kstride;
     uint16_t *c = static_cast<uint16_t *>(xc) + i * kstride;
     for (int t = 0; t < d; ++t) {
-      const uint16_t h = real ? bf16_from_double(X[i * d + t]) : uint16_t(0);
+      const uint16_t h =
+          real ? bf16_from_double(scale * x64c[i * stride64 + (t & 3) * ksp + (t >> 2)]) : uint16_t(0);
       const double xv = bf16_to_double(h);
       a += xv * xv;
       c[t] = h;
@@ -109,7 +141,8 @@ __global__ __launch_bounds__(256) void prepare_points(const double *X, int64_t n
     const int half = kstride / 2;
     for (int t = 0; t < kstride; ++t) r[t] = c[t] = 0.0f;
     for (int t = 0; t < d; ++t) {
-      const float xv = real ? static_cast<float>(X[i * d + t]) : 0.0f;
+      const float xv =
+          real ? static_cast<float>(scale * x64c[i * stride64 + (t & 3) * ksp + (t >> 2)]) : 0.0f;
       a += double(xv) * double(xv);
       c[(t & 1) * half + (t >> 1)] = xv;
       r[(t & 1) * half + (t >> 1)] = -2.0f * xv;
@@ -120,24 +153,15 @@ __global__ __launch_bounds__(256) void prepare_points(const double *X, int64_t n
     c[(d & 1) * half + (d >> 1)] = af;
     c[((d + 1) & 1) * half + ((d + 1) >> 1)] = 1.0f;
   }
-  // FP64 operands of the exact operator: [-2x, a, 1] and [x, 1, a] with a
-  // the squared norm of the unrounded point, element k stored at
-  // (k % 4) * ksp + k / 4 (the K-step layout of the 16x16x4 FP64 MFMA)
-  const int ksp = stride64 / 4;
-  double *r64 = x64r + i * stride64;
-  double *c64 = x64c + i * stride64;
-  double a64 = 0.0;
-  for (int t = 0; t < stride64; ++t) r64[t] = c64[t] = 0.0;
-  for (int t = 0; t < d; ++t) {
-    const double xv = real ? X[i * d + t] : 0.0;
-    a64 += xv * xv;
-    r64[(t & 3) * ksp + (t >> 2)] = -2.0 * xv;
-    c64[(t & 3) * ksp + (t >> 2)] = xv;
-  }
-  r64[(d & 3) * ksp + (d >> 2)] = a64;
-  r64[((d + 1) & 3) * ksp + ((d + 1) >> 2)] = 1.0;
-  c64[(d & 3) * ksp + (d >> 2)] = 1.0;
-  c64[((d + 1) & 3) * ksp + ((d + 1) >> 2)] = a64;
+}
+
+static int launch_prepare_lowprec(const dcg_operator_s *op) {
+  if (op->g.prec == DCG_PREC_FP64) return DCG_OK;
+  const Geometry &g = op->g;
+  hipLaunchKernelGGL(prepare_lowprec, dim3(static_cast<unsigned>(cdiv(g.n_pad, 256))), dim3(256),
+                     0, op->stream, op->x64c, g.n, g.n_pad, g.d, g.prec, g.kstride,
+                     exact_stride(g.d), point_scale(op->kernel, op->ell), op->xr, op->xc);
+  return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
 }
 
 // ----------------------------------------------------------- workspace
@@ -271,10 +295,10 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel, doubl
   const int64_t count = n * d;
   hipLaunchKernelGGL(check_finite, dim3(static_cast<unsigned>(std::min<int64_t>(1024, cdiv(count, 256)))),
                      dim3(256), 0, op->stream, X, count, flag);
-  hipLaunchKernelGGL(prepare_points, dim3(static_cast<unsigned>(cdiv(g.n_pad, 256))), dim3(256), 0,
-                     op->stream, X, n, g.n_pad, g.d, g.prec, g.kstride, exact_stride(g.d),
-                     op->xr, op->xc, op->x64r, op->x64c);
+  hipLaunchKernelGGL(prepare_exact, dim3(static_cast<unsigned>(cdiv(g.n_pad, 256))), dim3(256), 0,
+                     op->stream, X, n, g.n_pad, g.d, exact_stride(g.d), op->x64r, op->x64c);
   ok = ok && hipGetLastError() == hipSuccess;
+  ok = ok && launch_prepare_lowprec(op) == DCG_OK;
   ok = ok && hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, op->stream) == hipSuccess;
   ok = ok && hipStreamSynchronize(op->stream) == hipSuccess;
   if (!ok) {
@@ -294,11 +318,13 @@ int dcg_set_hyper(dcg_op_t op, double ell, double s2, double sigma2) {
   if (!(ell > 0.0) || !(s2 > 0.0) || !(sigma2 >= 0.0) || !std::isfinite(ell) ||
       !std::isfinite(s2) || !std::isfinite(sigma2))
     return DCG_E_ARG;
+  const bool rescale = ell != op->ell;
   op->ell = ell;
   op->s2 = s2;
   op->sigma2 = sigma2;
   op->generation += 1;
-  return DCG_OK;
+  // the low-precision operands carry the lengthscale (point_scale)
+  return rescale ? launch_prepare_lowprec(op) : DCG_OK;
 }
 
 int dcg_matvec(dcg_op_t op, const double *V, double *Y, int64_t m) {

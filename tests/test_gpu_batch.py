@@ -203,7 +203,7 @@ def test_batched_ragged_full_size_sampled_rows(lib):
             assert sts[s]["status"] == 0, (s, sts[s])
             x = _np(xs[s])
             b = q["b"]
-            Xr = OP.round_points(q["X"], 0)
+            Xr = OP.round_points(q["X"], 0, q["kernel"], q["ells"][t])
             rows = g.choice(len(b), size=8, replace=False)
             for i in rows:
                 ki = OK.gram(Xr[i:i + 1], q["kernel"], q["ells"][t], q["s2"], Y=Xr)[0]

@@ -33,7 +33,7 @@ def test_block_solve_columns(lib, prec, tol, deflate):
     g = np.random.default_rng(31)
     X = g.standard_normal((n, 5))
     ell = workloads.median_distance(X)
-    Xr = OP.round_points(X, prec)
+    Xr = OP.round_points(X, prec, 0, ell)
     A = OK.operator(Xr, 0, ell, 1.0, 1e-2)
     B = g.standard_normal((n, m))
     op = lib.Operator(_dev(X), 0, ell, 1.0, 1e-2, prec=prec)
@@ -67,7 +67,7 @@ def test_mll_grad_sweep_matches_oracle(lib, kern, prec):
     w = workloads.gp_hyper(n=1200)
     X, y = w["X"], w["y"]
     ell, s2, sig2 = math.exp(w["log_ell"]), 1.3, 0.1
-    Xr = OP.round_points(X, prec)
+    Xr = OP.round_points(X, prec, kern, ell)
     A = OK.operator(Xr, kern, ell, s2, sig2)
     Z = workloads.rademacher(1200, 16, step=0)
     alpha = np.linalg.solve(A, y)
@@ -101,7 +101,7 @@ def test_mll_autograd_against_exact_gradient(lib):
         val.backward()
     assert gpc.last["probe_stats"]["k_used"] == 16
     ell, s2, sig2 = (math.exp(v) for v in theta.detach().tolist())
-    Xr = OP.round_fp32(X)
+    Xr = OP.round_points(X, 0, 0, ell)
     exact = OG.lml_grad_exact(Xr, y, 0, ell, s2, sig2)
     hut = OG.lml_grad_hutchinson(Xr, y, 0, ell, s2, sig2, Z)
     g = theta.grad.numpy()
@@ -147,7 +147,7 @@ def test_mll_grad_full_size_differentiation_workload(lib):
     assert stb["status"] == 0 and stb["k_used"] == w["k"]
     g = np.array(lib.mll_grad(op, alpha, U, _dev(Z)))
     print("full-size gradient", g, "alpha its", st["iters"], "probe its", stb["iters"], flush=True)
-    ref, scale = OG.lml_grad_hutchinson_blocked(OP.round_fp32(X), 0, ell, s2, sig2, _np(alpha),
+    ref, scale = OG.lml_grad_hutchinson_blocked(OP.round_points(X, 0, 0, ell), 0, ell, s2, sig2, _np(alpha),
                                                 _np(U), Z, with_scale=True)
     for j in range(3):
         assert abs(g[j] - ref[j]) <= 2e-5 * scale[j] + 1e-9, (j, g[j], ref[j], scale[j])

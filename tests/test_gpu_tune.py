@@ -37,7 +37,7 @@ def test_every_plan_matches_oracle(lib, prec, items):
     op.set_sweep_items(items)
     v = g.standard_normal(n)
     y = _np(op.matvec(_dev(v)))
-    A = OK.operator(OP.round_points(X, prec), 2, ell, 1.1, 1e-2)
+    A = OK.operator(OP.round_points(X, prec, 2, ell), 2, ell, 1.1, 1e-2)
     err = np.abs(y - A @ v) / (np.abs(A) @ np.abs(v))
     assert err.max() <= 2e-5
     # a solve under this plan converges to the tolerance
@@ -70,7 +70,7 @@ def test_tuner_returns_candidate(lib, prec):
     # the product under the tuned plan, on sampled rows computed by the oracle
     v = g.standard_normal(20000)
     y = _np(op.matvec(_dev(v)))
-    Xr = OP.round_points(X, prec)
+    Xr = OP.round_points(X, prec, 0, ell)
     y64 = _np(op.matvec_exact(_dev(v)))    # the FP64 sweep under its tuned plan
     for i in g.choice(20000, size=32, replace=False):
         ki = OK.gram(Xr[i:i + 1], 0, ell, 1.0, Y=Xr)[0]

@@ -118,12 +118,41 @@ def test_round_bf16x2():
     exact = np.ldexp(np.round(np.ldexp(x, 13)), -13)[np.abs(x) >= 0.5]
     exact = exact[np.abs(exact) < 4]
     np.testing.assert_array_equal(P.round_bf16x2(exact), exact)
-    assert P.round_points(np.array([[0.1]]), P.PREC_BF16X2)[0, 0] == P.round_bf16x2(np.array([0.1]))[0]
+    c = P.point_scale(P.RBF, 1.0)
+    assert P.round_points(np.array([[0.1]]), P.PREC_BF16X2, P.RBF, 1.0)[0, 0] == \
+        P.round_bf16x2(np.array([0.1 * c]))[0] / c
 
 
 def test_round_fp32():
     assert P.round_fp32(np.array([0.1]))[0] == float(np.float32(0.1))
-    assert P.round_points(np.array([[0.1]]), P.PREC_FP64)[0, 0] == 0.1
+    assert P.round_points(np.array([[0.1]]), P.PREC_FP64, P.MATERN52, 0.3)[0, 0] == 0.1
+
+
+def test_point_scale_gives_base2_forms_of_the_kernels():
+    """With u = c r, c = point_scale(kernel, ell), the forms the low-precision
+    product evaluates equal the textbook kernels: RBF 2^-(u^2), Matern-3/2
+    (1 + ln2 u) 2^-u, Matern-5/2 (1 + ln2 u + ln2^2 u^2 / 3) 2^-u."""
+    assert (P.RBF, P.MATERN32, P.MATERN52) == (K.RBF, K.MATERN32, K.MATERN52)
+    assert P.LOG2E == np.log2(np.e)
+    r = np.linspace(0.0, 6.0, 241)
+    ln2 = np.log(2.0)
+    for ell in (0.3, 1.0, 2.2937):
+        u = P.point_scale(K.RBF, ell) * r
+        np.testing.assert_allclose(2.0 ** -(u * u), K.kernel_from_r2(r * r, K.RBF, ell, 1.0),
+                                   rtol=1e-13)
+        u = P.point_scale(K.MATERN32, ell) * r
+        np.testing.assert_allclose((1 + ln2 * u) * 2.0 ** -u,
+                                   K.kernel_from_r2(r * r, K.MATERN32, ell, 1.0), rtol=1e-13)
+        u = P.point_scale(K.MATERN52, ell) * r
+        np.testing.assert_allclose((1 + ln2 * u + ln2 * ln2 * u * u / 3) * 2.0 ** -u,
+                                   K.kernel_from_r2(r * r, K.MATERN52, ell, 1.0), rtol=1e-13)
+    # the represented points: the scaled points' rounding, scaled back
+    X = np.random.default_rng(9).uniform(-1, 1, (50, 4))
+    for prec, rnd in ((P.PREC_FP32, P.round_fp32), (P.PREC_BF16, P.round_bf16)):
+        c = P.point_scale(K.MATERN52, 0.8)
+        Xr = P.round_points(X, prec, K.MATERN52, 0.8)
+        np.testing.assert_allclose(Xr * c, rnd(c * X), rtol=2e-16, atol=0)
+        assert np.abs(Xr - X).max() > 0
 
 
 def test_sqdist_gemm_matches_difference_form():
