@@ -183,7 +183,7 @@ def main_ragged(args):
         "n_gpus": 1, "steps": steps, "warmup": warm,
         "ms_per_step": round(t_batched * 1e3 / steps, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp32 MFMA distances, f32 kernel values, f64 CG", "data": "synthetic",
+        "dtype": "fp32 points (three bf16 terms on bf16 MFMA), f32 kernel values, f64 CG", "data": "synthetic",
         "config": {"workload": "ragged: 64 sequences, n log-uniform [2048, 32768], d=8, "
                                "RBF/Matern-3/2, sigma2 log-uniform [1e-4, 1e-1], k=16 L=24 tol 1e-6",
                    "sum_n": sum(ns), "sweep_items": sorted(set(items))},
@@ -264,7 +264,7 @@ def main_gp(args):
         "value": round(ms * 1e3, 2), "unit": "ms/step", "n_gpus": 1,
         "steps": total - args.warmup, "warmup": args.warmup, "ms_per_step": round(ms * 1e3, 2),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp32 MFMA distances, f32 kernel values, f64 CG", "data": "synthetic",
+        "dtype": "fp32 points (three bf16 terms on bf16 MFMA), f32 kernel values, f64 CG", "data": "synthetic",
         "config": {"workload": "gp_hyper: n=32768 d=16 RBF, y = sin-sum + 0.1 noise, "
                                "16 Rademacher probes per step, k=32 L=48, tol 1e-6, Adam lr 0.05",
                    "adam_steps": total},

@@ -72,7 +72,7 @@ static BatchLayout batch_layout(int count, const int64_t *n) {
 
 // One group of systems whose sweeps share a kernel instantiation.
 struct SweepGroup {
-  int prec, ksteps;
+  int opk, ksteps;
   int first, count;   // range in the device item table
   int64_t total;      // work items of the group
 };
@@ -87,7 +87,7 @@ static int enqueue_batch_step(hipStream_t s, int count, dcg_operator_s *const *o
                               const std::vector<SolveCtx> &ctx, const BatchPlan &plan,
                               const BatchItem *d_items, const CgArgs *d_args) {
   for (const SweepGroup &g : plan.groups) {
-    const int st = launch_symv_batched(d_items + g.first, g.count, g.total, g.ksteps, g.prec, s);
+    const int st = launch_symv_batched(d_items + g.first, g.count, g.total, g.ksteps, g.opk, s);
     if (st != DCG_OK) return st;
   }
   for (int i : plan.direct) {
@@ -124,16 +124,15 @@ static int build_tables(const std::vector<int> &act, dcg_operator_s *const *ops,
     plan->nq_max = std::max(plan->nq_max, ctx[s].a.nblk_q);
     plan->nx_max = std::max(plan->nx_max, xr_grid(ctx[s].a));
     plan->np_max = std::max(plan->np_max, ctx[s].a.nblk_p);
-    // bf16 and bf16x2 operands share the bf16 kernels
-    const int pc = (op->g.prec == DCG_PREC_BF16X2) ? DCG_PREC_BF16 : op->g.prec;
-    if (symv_batched_supported(op->g.prec, op->g.ksteps))
-      by_shape[{pc, op->g.ksteps}].push_back(s);
+    // bf16 and bf16x2 operands share the bf16 kernels (one operand kind)
+    if (op->g.prec != DCG_PREC_FP64 && symv_batched_supported(op->g.opk, op->g.ksteps))
+      by_shape[{op->g.opk, op->g.ksteps}].push_back(s);
     else
       plan->direct.push_back(s);
   }
   for (const auto &kv : by_shape) {
     SweepGroup g;
-    g.prec = kv.first.first;
+    g.opk = kv.first.first;
     g.ksteps = kv.first.second;
     g.first = static_cast<int>(items.size());
     g.count = static_cast<int>(kv.second.size());

@@ -147,8 +147,8 @@ int launch_symv_sweep(const dcg_operator_s *op, int mv, const int *done);
 int launch_symv_sweep_from(const dcg_operator_s *op, int mv, const float *vin, const int *done);
 SymvArgs symv_args(const dcg_operator_s *op, int mv, const float *vin, const int *done,
                    int64_t *grid);
-bool symv_batched_supported(int prec, int ksteps);
-int launch_symv_batched(const BatchItem *d_items, int count, int64_t total, int ksteps, int prec,
+bool symv_batched_supported(int opk, int ksteps);
+int launch_symv_batched(const BatchItem *d_items, int count, int64_t total, int ksteps, int opk,
                         hipStream_t s);
 ReduceArgs reduce_args(const dcg_operator_s *op, int mv, const double *V, double *Y);
 int matvec_lowprec(const dcg_operator_s *op, const double *V, double *Y, int64_t m);

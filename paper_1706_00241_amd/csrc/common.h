@@ -36,10 +36,23 @@ struct Carve {
 // Row operand  xr_i = [-2 x_i, 1.., a_i parts, 0 pad]
 // Col operand  xc_j = [  x_j, a_j parts, 1.., 0 pad]
 // so that <xr_i, xc_j> = a_i + a_j - 2 x_i.x_j = |x_i - x_j|^2.
+//
+// Operand kinds of the low-precision sweep:
+//   kOpBf16       bf16 pieces (bf16: x~; bf16x2: hi, lo), FP32 row sums within
+//                 a work item (the operator's own error is far above them);
+//   kOpBf16Acc64  the FP32 operator's points, each FP32 coordinate split
+//                 exactly into three bf16 terms h + m + l; the six products
+//                 above 2^-24 (hh, hm, mh, hl, lh, mm) go through bf16 MFMA,
+//                 and row sums carry FP64 accumulators across block pairs;
+//   kOpF32        FP32 MFMA operands (the FP32 operator for d > 33, where
+//                 6d + 6 terms need more than 13 bf16 K-steps).
+enum OperandKind { kOpBf16 = 0, kOpBf16Acc64 = 1, kOpF32 = 2 };
+
 struct Geometry {
   int64_t n, n_pad;  // n_pad: multiple of the block size of both schedules
   int d;
   int prec;
+  int opk;           // OperandKind of the low-precision operands
   int ksteps;        // MFMA K steps (bf16: 16 per step, fp32: 2 per step)
   int kstride;       // elements per point row in the stored operand arrays
 };
@@ -56,12 +69,13 @@ struct MatvecPlan {
 };
 
 // Tile rows (of 32) per wave in the symmetric sweep: two for the
-// single-vector kernel unless its bf16 operands are wide (register budget).
-// The device kernel applies the same rule to its template parameters.
-inline int sweep_tile_rows(int mv, int prec, int ksteps) {
-  return (mv == 1 && (prec == DCG_PREC_FP32 || ksteps <= 9)) ? 2 : 1;
+// single-vector kernel unless its bf16 operands are wide (register budget;
+// the FP64 row accumulators of kOpBf16Acc64 take 64 more).  The host plans
+// and the device kernel's template parameters use this one rule.
+__host__ __device__ constexpr int sweep_tile_rows(int mv, int opk, int ksteps) {
+  return (mv == 1 && (opk == kOpF32 || ksteps <= (opk == kOpBf16Acc64 ? 4 : 9))) ? 2 : 1;
 }
-inline int sweep_blk(const Geometry &g, int mv) { return 128 * sweep_tile_rows(mv, g.prec, g.ksteps); }
+inline int sweep_blk(const Geometry &g, int mv) { return 128 * sweep_tile_rows(mv, g.opk, g.ksteps); }
 
 // Work items of one pair sweep: the plan groups block offsets into chunks so
 // that a sweep has about `items` work items.  The default suits one large

@@ -290,6 +290,10 @@ static int launch_grad(const dcg_operator_s *op, const GradArgs &a, int64_t grid
       case 3: hipLaunchKernelGGL((grad_sweep<KERN, 3, true>), g, b, 0, op->stream, a); return 0;
       case 4: hipLaunchKernelGGL((grad_sweep<KERN, 4, true>), g, b, 0, op->stream, a); return 0;
       case 5: hipLaunchKernelGGL((grad_sweep<KERN, 5, true>), g, b, 0, op->stream, a); return 0;
+      case 7: hipLaunchKernelGGL((grad_sweep<KERN, 7, true>), g, b, 0, op->stream, a); return 0;
+      case 9: hipLaunchKernelGGL((grad_sweep<KERN, 9, true>), g, b, 0, op->stream, a); return 0;
+      case 13: hipLaunchKernelGGL((grad_sweep<KERN, 13, true>), g, b, 0, op->stream, a); return 0;
+      case 17: hipLaunchKernelGGL((grad_sweep<KERN, 17, true>), g, b, 0, op->stream, a); return 0;
     }
   } else {
     switch (ks) {
@@ -351,7 +355,8 @@ int dcg_mll_grad(dcg_op_t op, const double *alpha, const double *U, const double
   a.chunk = p.chunk;
   a.nchunk = p.nchunk;
   a.invP = static_cast<float>(1.0 / double(P));
-  const bool bf = op->g.prec == DCG_PREC_BF16;
+  // bf16 terms (bf16 points, or FP32 points as three bf16 terms) or FP32
+  const bool bf = op->g.opk != kOpF32;
   int rc;
   if (op->kernel == DCG_RBF) rc = bf ? launch_grad<DCG_RBF, true>(op, a, p.grid) : launch_grad<DCG_RBF, false>(op, a, p.grid);
   else if (op->kernel == DCG_MATERN32) rc = bf ? launch_grad<DCG_MATERN32, true>(op, a, p.grid) : launch_grad<DCG_MATERN32, false>(op, a, p.grid);

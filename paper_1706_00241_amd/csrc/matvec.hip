@@ -53,6 +53,7 @@ Geometry make_geometry(int64_t n, int d, int prec) {
   g.d = d;
   g.prec = prec;
   g.n_pad = ((n + 255) / 256) * 256;
+  g.opk = kOpBf16;
   if (prec == DCG_PREC_FP64) {
     g.ksteps = 0;  // the exact FP64 product needs no MFMA operands
     g.kstride = 0;
@@ -62,7 +63,14 @@ Geometry make_geometry(int64_t n, int d, int prec) {
   } else if (prec == DCG_PREC_BF16X2) {
     g.ksteps = bf16_bucket((4 * d + 6 + 15) / 16);
     g.kstride = 16 * g.ksteps;
+  } else if (6 * d + 6 <= 16 * 13) {
+    // FP32 points as three exact bf16 terms: six products per coordinate
+    // and the squared norm in three terms on each side
+    g.opk = kOpBf16Acc64;
+    g.ksteps = bf16_bucket((6 * d + 6 + 15) / 16);
+    g.kstride = 16 * g.ksteps;
   } else {
+    g.opk = kOpF32;
     g.ksteps = fp32_bucket((d + 2 + 1) / 2);
     g.kstride = 2 * ((g.ksteps + 3) / 4) * 4;
   }
@@ -164,9 +172,10 @@ __device__ __forceinline__ f32x16 tile_r2(const Operand<BF16, KS> &a, const Oper
 }
 
 
-template <int KERN, int KS, int MV, bool BF16>
+template <int KERN, int KS, int MV, int OPK>
 __device__ __forceinline__ void symv_body(const SymvArgs &A, const int64_t item) {
-  constexpr int TR = (MV == 1 && (!BF16 || KS <= 9)) ? 2 : 1;  // = sweep_tile_rows
+  constexpr bool BF16 = OPK != kOpF32;
+  constexpr int TR = sweep_tile_rows(MV, OPK, KS);
   constexpr int BLK = 4 * 32 * TR;
   constexpr int NCT = BLK / 32;
   __shared__ float colpart[MV][4][BLK];
@@ -184,13 +193,14 @@ __device__ __forceinline__ void symv_body(const SymvArgs &A, const int64_t item)
   const int64_t n_pad = A.n_pad;
   const int64_t rowbase = int64_t(I) * BLK + w * 32 * TR;
 
-  // Row sums: FP32 runs over the 8 column tiles of one block pair, then FP64
-  // across block pairs for FP32 operands (single-vector kernel).  With bf16
-  // operands the operator's own error (the rounding of the points) is orders
-  // above FP32 summation over one work item's few block pairs, and dropping
-  // the FP64 accumulators frees the registers for two tile rows per wave and
-  // three waves per SIMD.  Work items are summed in FP64 either way.
-  constexpr bool ACC64 = (MV == 1) && !BF16;
+  // Row sums: FP32 runs over the column tiles of one block pair, then FP64
+  // across block pairs for the FP32 operator (single-vector kernel).  With
+  // bf16 or split-bf16 points the operator's own error (the rounding of the
+  // points) is orders above FP32 summation over one work item's few block
+  // pairs, and dropping the FP64 accumulators frees the registers for two
+  // tile rows per wave and three waves per SIMD.  Work items are summed in
+  // FP64 either way.
+  constexpr bool ACC64 = (MV == 1) && OPK != kOpBf16;
   Operand<BF16, KS> ra[TR];
   float pi[MV][TR][16];
   float accr[MV][TR][16];
@@ -340,16 +350,16 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t G) {
   return (bid < Gm) ? (bid % 8) * (Gm / 8) + bid / 8 : bid;
 }
 
-template <int KERN, int KS, int MV, bool BF16>
+template <int KERN, int KS, int MV, int OPK>
 __global__ __launch_bounds__(256, 2) void symv_kernel(SymvArgs A) {
   if (A.done != nullptr && *A.done != 0) return;
-  symv_body<KERN, KS, MV, BF16>(A, xcd_remap(blockIdx.x, int64_t(A.nb) * A.nchunk));
+  symv_body<KERN, KS, MV, OPK>(A, xcd_remap(blockIdx.x, int64_t(A.nb) * A.nchunk));
 }
 
 // Many operators in one launch: the grid is the concatenation of every
 // system's work items; a workgroup finds its system by binary search over
 // the first-item offsets and skips systems that have converged.
-template <int KS, bool BF16>
+template <int KS, int OPK>
 __global__ __launch_bounds__(256, 2) void symv_batched(const BatchItem *sys, int count,
                                                        int64_t total) {
   const int64_t g = xcd_remap(blockIdx.x, total);
@@ -362,9 +372,9 @@ __global__ __launch_bounds__(256, 2) void symv_batched(const BatchItem *sys, int
   const BatchItem &B = sys[lo];
   if (B.a.done != nullptr && *B.a.done != 0) return;
   const int64_t item = g - B.item0;
-  if (B.kernel == DCG_RBF) symv_body<DCG_RBF, KS, 1, BF16>(B.a, item);
-  else if (B.kernel == DCG_MATERN32) symv_body<DCG_MATERN32, KS, 1, BF16>(B.a, item);
-  else symv_body<DCG_MATERN52, KS, 1, BF16>(B.a, item);
+  if (B.kernel == DCG_RBF) symv_body<DCG_RBF, KS, 1, OPK>(B.a, item);
+  else if (B.kernel == DCG_MATERN32) symv_body<DCG_MATERN32, KS, 1, OPK>(B.a, item);
+  else symv_body<DCG_MATERN52, KS, 1, OPK>(B.a, item);
 }
 
 // Finish y = s2 * (sum of partials) + sigma2 v for the first `cols` vectors.
@@ -395,37 +405,46 @@ double point_scale(int kernel, double ell) {
   return std::sqrt(kernel == DCG_MATERN32 ? 3.0 : 5.0) * log2e / ell;
 }
 
-template <int KERN, int KS, int MV, bool BF16>
+template <int KERN, int KS, int MV, int OPK>
 static void launch_symv(const SymvArgs &a, int64_t grid, hipStream_t s) {
-  hipLaunchKernelGGL((symv_kernel<KERN, KS, MV, BF16>), dim3(static_cast<unsigned>(grid)),
+  hipLaunchKernelGGL((symv_kernel<KERN, KS, MV, OPK>), dim3(static_cast<unsigned>(grid)),
                      dim3(256), 0, s, a);
+}
+
+template <int KERN, int MV, int OPK>
+static int dispatch_bf16(int ks, const SymvArgs &a, int64_t grid, hipStream_t s) {
+  if (OPK == kOpBf16Acc64 && ks > 13) return -1;
+  switch (ks) {
+    case 1: launch_symv<KERN, 1, MV, OPK>(a, grid, s); return 0;
+    case 2: launch_symv<KERN, 2, MV, OPK>(a, grid, s); return 0;
+    case 3: launch_symv<KERN, 3, MV, OPK>(a, grid, s); return 0;
+    case 4: launch_symv<KERN, 4, MV, OPK>(a, grid, s); return 0;
+    case 5: launch_symv<KERN, 5, MV, OPK>(a, grid, s); return 0;
+    case 7: launch_symv<KERN, 7, MV, OPK>(a, grid, s); return 0;
+    case 9: launch_symv<KERN, 9, MV, OPK>(a, grid, s); return 0;
+    case 13: launch_symv<KERN, 13, MV, OPK>(a, grid, s); return 0;
+    case 17:
+      if constexpr (OPK == kOpBf16) {
+        launch_symv<KERN, 17, MV, OPK>(a, grid, s);
+        return 0;
+      }
+  }
+  return -1;
 }
 
 template <int KERN, int MV>
 static int dispatch_ks(const dcg_operator_s *op, const SymvArgs &a, int64_t grid) {
   const int ks = op->g.ksteps;
   hipStream_t s = op->stream;
-  if (op->g.prec == DCG_PREC_BF16 || op->g.prec == DCG_PREC_BF16X2) {
-    switch (ks) {
-      case 1: launch_symv<KERN, 1, MV, true>(a, grid, s); return 0;
-      case 2: launch_symv<KERN, 2, MV, true>(a, grid, s); return 0;
-      case 3: launch_symv<KERN, 3, MV, true>(a, grid, s); return 0;
-      case 4: launch_symv<KERN, 4, MV, true>(a, grid, s); return 0;
-      case 5: launch_symv<KERN, 5, MV, true>(a, grid, s); return 0;
-      case 7: launch_symv<KERN, 7, MV, true>(a, grid, s); return 0;
-      case 9: launch_symv<KERN, 9, MV, true>(a, grid, s); return 0;
-      case 13: launch_symv<KERN, 13, MV, true>(a, grid, s); return 0;
-      case 17: launch_symv<KERN, 17, MV, true>(a, grid, s); return 0;
-    }
-  } else {
-    switch (ks) {
-      case 5: launch_symv<KERN, 5, MV, false>(a, grid, s); return 0;
-      case 9: launch_symv<KERN, 9, MV, false>(a, grid, s); return 0;
-      case 13: launch_symv<KERN, 13, MV, false>(a, grid, s); return 0;
-      case 17: launch_symv<KERN, 17, MV, false>(a, grid, s); return 0;
-      case 25: launch_symv<KERN, 25, MV, false>(a, grid, s); return 0;
-      case 33: launch_symv<KERN, 33, MV, false>(a, grid, s); return 0;
-    }
+  if (op->g.opk == kOpBf16) return dispatch_bf16<KERN, MV, kOpBf16>(ks, a, grid, s);
+  if (op->g.opk == kOpBf16Acc64) return dispatch_bf16<KERN, MV, kOpBf16Acc64>(ks, a, grid, s);
+  switch (ks) {
+    case 5: launch_symv<KERN, 5, MV, kOpF32>(a, grid, s); return 0;
+    case 9: launch_symv<KERN, 9, MV, kOpF32>(a, grid, s); return 0;
+    case 13: launch_symv<KERN, 13, MV, kOpF32>(a, grid, s); return 0;
+    case 17: launch_symv<KERN, 17, MV, kOpF32>(a, grid, s); return 0;
+    case 25: launch_symv<KERN, 25, MV, kOpF32>(a, grid, s); return 0;
+    case 33: launch_symv<KERN, 33, MV, kOpF32>(a, grid, s); return 0;
   }
   return -1;
 }
@@ -453,37 +472,43 @@ SymvArgs symv_args(const dcg_operator_s *op, int mv, const float *vin, const int
 }
 
 // The batched sweep is built for the two-tile-row single-vector kernels.
-bool symv_batched_supported(int prec, int ksteps) {
-  if (prec == DCG_PREC_BF16 || prec == DCG_PREC_BF16X2)
+bool symv_batched_supported(int opk, int ksteps) {
+  if (opk == kOpBf16 || opk == kOpBf16Acc64)
     return (ksteps >= 1 && ksteps <= 5) || ksteps == 7 || ksteps == 9;
-  if (prec == DCG_PREC_FP32) return ksteps == 5 || ksteps == 9 || ksteps == 13 || ksteps == 17;
+  if (opk == kOpF32) return ksteps == 5 || ksteps == 9 || ksteps == 13 || ksteps == 17;
   return false;
 }
 
-int launch_symv_batched(const BatchItem *d_items, int count, int64_t total, int ksteps, int prec,
-                        hipStream_t s) {
-  if (!symv_batched_supported(prec, ksteps) || total < 1) return DCG_E_ARG;
+template <int OPK>
+static void launch_batched_bf16(const BatchItem *d_items, int count, int64_t total, int ksteps,
+                                hipStream_t s) {
   const dim3 g(static_cast<unsigned>(total)), b(256);
-  if (prec == DCG_PREC_BF16 || prec == DCG_PREC_BF16X2) {
-    switch (ksteps) {
-      case 1: hipLaunchKernelGGL((symv_batched<1, true>), g, b, 0, s, d_items, count, total); break;
-      case 2: hipLaunchKernelGGL((symv_batched<2, true>), g, b, 0, s, d_items, count, total); break;
-      case 3: hipLaunchKernelGGL((symv_batched<3, true>), g, b, 0, s, d_items, count, total); break;
-      case 4: hipLaunchKernelGGL((symv_batched<4, true>), g, b, 0, s, d_items, count, total); break;
-      case 5: hipLaunchKernelGGL((symv_batched<5, true>), g, b, 0, s, d_items, count, total); break;
-      case 7: hipLaunchKernelGGL((symv_batched<7, true>), g, b, 0, s, d_items, count, total); break;
-      default: hipLaunchKernelGGL((symv_batched<9, true>), g, b, 0, s, d_items, count, total); break;
-    }
-  } else if (prec == DCG_PREC_FP32) {
-    switch (ksteps) {
-      case 5: hipLaunchKernelGGL((symv_batched<5, false>), g, b, 0, s, d_items, count, total); break;
-      case 9: hipLaunchKernelGGL((symv_batched<9, false>), g, b, 0, s, d_items, count, total); break;
-      case 13: hipLaunchKernelGGL((symv_batched<13, false>), g, b, 0, s, d_items, count, total); break;
-      case 17: hipLaunchKernelGGL((symv_batched<17, false>), g, b, 0, s, d_items, count, total); break;
-      default: return DCG_E_ARG;
-    }
+  switch (ksteps) {
+    case 1: hipLaunchKernelGGL((symv_batched<1, OPK>), g, b, 0, s, d_items, count, total); break;
+    case 2: hipLaunchKernelGGL((symv_batched<2, OPK>), g, b, 0, s, d_items, count, total); break;
+    case 3: hipLaunchKernelGGL((symv_batched<3, OPK>), g, b, 0, s, d_items, count, total); break;
+    case 4: hipLaunchKernelGGL((symv_batched<4, OPK>), g, b, 0, s, d_items, count, total); break;
+    case 5: hipLaunchKernelGGL((symv_batched<5, OPK>), g, b, 0, s, d_items, count, total); break;
+    case 7: hipLaunchKernelGGL((symv_batched<7, OPK>), g, b, 0, s, d_items, count, total); break;
+    default: hipLaunchKernelGGL((symv_batched<9, OPK>), g, b, 0, s, d_items, count, total); break;
+  }
+}
+
+int launch_symv_batched(const BatchItem *d_items, int count, int64_t total, int ksteps, int opk,
+                        hipStream_t s) {
+  if (!symv_batched_supported(opk, ksteps) || total < 1) return DCG_E_ARG;
+  const dim3 g(static_cast<unsigned>(total)), b(256);
+  if (opk == kOpBf16) {
+    launch_batched_bf16<kOpBf16>(d_items, count, total, ksteps, s);
+  } else if (opk == kOpBf16Acc64) {
+    launch_batched_bf16<kOpBf16Acc64>(d_items, count, total, ksteps, s);
   } else {
-    return DCG_E_ARG;
+    switch (ksteps) {
+      case 5: hipLaunchKernelGGL((symv_batched<5, kOpF32>), g, b, 0, s, d_items, count, total); break;
+      case 9: hipLaunchKernelGGL((symv_batched<9, kOpF32>), g, b, 0, s, d_items, count, total); break;
+      case 13: hipLaunchKernelGGL((symv_batched<13, kOpF32>), g, b, 0, s, d_items, count, total); break;
+      default: hipLaunchKernelGGL((symv_batched<17, kOpF32>), g, b, 0, s, d_items, count, total); break;
+    }
   }
   return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
 }

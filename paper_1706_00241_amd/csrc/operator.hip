@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void prepare_exact(const double *X, int64_t n,
 // x_t at (t % 4) * (stride64 / 4) + t / 4; run at creation and whenever the
 // lengthscale changes.
 __global__ __launch_bounds__(256) void prepare_lowprec(const double *x64c, int64_t n,
-                                                       int64_t n_pad, int d, int prec,
+                                                       int64_t n_pad, int d, int prec, int opk,
                                                        int kstride, int stride64, double scale,
                                                        void *xr, void *xc) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
@@ -135,6 +135,43 @@ __global__ __launch_bounds__(256) void prepare_lowprec(const double *x64c, int64
     c[d + 0] = ah;  c[d + 1] = am;  c[d + 2] = al;
     c[d + 3] = one; c[d + 4] = one; c[d + 5] = one;
     for (int t = d + 6; t < kstride; ++t) r[t] = c[t] = 0;
+  } else if (opk == kOpBf16Acc64) {
+    // FP32 coordinate x = h + m + l, three bf16 terms (exact for every FP32
+    // value); one column per kept pairing (row term, column term): (h,h)
+    // (h,m) (m,h) (h,l) (l,h) (m,m), the row side carrying the factor -2
+    // (exact in bf16).  The dropped m.l, l.m, l.l are below 2^-26 |x_i x_j|.
+    uint16_t *r = static_cast<uint16_t *>(xr) + i * kstride;
+    uint16_t *c = static_cast<uint16_t *>(xc) + i * kstride;
+    for (int t = 0; t < d; ++t) {
+      const float xf =
+          real ? static_cast<float>(scale * x64c[i * stride64 + (t & 3) * ksp + (t >> 2)]) : 0.0f;
+      const double xv = xf;
+      a += xv * xv;
+      const uint16_t h = bf16_from_double(xv);
+      const double r1 = xv - bf16_to_double(h);
+      const uint16_t m = bf16_from_double(r1);
+      const uint16_t lo = bf16_from_double(r1 - bf16_to_double(m));
+      const uint16_t h2 = bf16_from_double(-2.0 * bf16_to_double(h));
+      const uint16_t m2 = bf16_from_double(-2.0 * bf16_to_double(m));
+      const uint16_t l2 = bf16_from_double(-2.0 * bf16_to_double(lo));
+      r[t] = h2;          c[t] = h;
+      r[d + t] = h2;      c[d + t] = m;
+      r[2 * d + t] = m2;  c[2 * d + t] = h;
+      r[3 * d + t] = h2;  c[3 * d + t] = lo;
+      r[4 * d + t] = l2;  c[4 * d + t] = h;
+      r[5 * d + t] = m2;  c[5 * d + t] = m;
+    }
+    const uint16_t ah = bf16_from_double(a);
+    const double rem1 = a - bf16_to_double(ah);
+    const uint16_t am = bf16_from_double(rem1);
+    const uint16_t al = bf16_from_double(rem1 - bf16_to_double(am));
+    const uint16_t one = 0x3F80;
+    const int o = 6 * d;
+    r[o + 0] = one; r[o + 1] = one; r[o + 2] = one;
+    r[o + 3] = ah;  r[o + 4] = am;  r[o + 5] = al;
+    c[o + 0] = ah;  c[o + 1] = am;  c[o + 2] = al;
+    c[o + 3] = one; c[o + 4] = one; c[o + 5] = one;
+    for (int t = o + 6; t < kstride; ++t) r[t] = c[t] = 0;
   } else {
     float *r = static_cast<float *>(xr) + i * kstride;
     float *c = static_cast<float *>(xc) + i * kstride;
@@ -159,7 +196,7 @@ static int launch_prepare_lowprec(const dcg_operator_s *op) {
   if (op->g.prec == DCG_PREC_FP64) return DCG_OK;
   const Geometry &g = op->g;
   hipLaunchKernelGGL(prepare_lowprec, dim3(static_cast<unsigned>(cdiv(g.n_pad, 256))), dim3(256),
-                     0, op->stream, op->x64c, g.n, g.n_pad, g.d, g.prec, g.kstride,
+                     0, op->stream, op->x64c, g.n, g.n_pad, g.d, g.prec, g.opk, g.kstride,
                      exact_stride(g.d), point_scale(op->kernel, op->ell), op->xr, op->xc);
   return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
 }
@@ -172,9 +209,7 @@ struct OpLayout {
 
 static OpLayout op_layout(const Geometry &g) {
   const int st64 = exact_stride(g.d);
-  const size_t esz = (g.prec == DCG_PREC_BF16 || g.prec == DCG_PREC_BF16X2)
-                         ? 2
-                         : (g.prec == DCG_PREC_FP64 ? 0 : 4);
+  const size_t esz = (g.prec == DCG_PREC_FP64) ? 0 : (g.opk == kOpF32 ? 4 : 2);
   Carve c(nullptr, 0);
   OpLayout L;
   L.x64r = c.off = align256(c.off); c.off += size_t(g.n_pad) * st64 * 8;
