@@ -139,7 +139,8 @@ __global__ __launch_bounds__(256) void prepare_lowprec(const double *x64c, int64
     // FP32 coordinate x = h + m + l, three bf16 terms (exact for every FP32
     // value); one column per kept pairing (row term, column term): (h,h)
     // (h,m) (m,h) (h,l) (l,h) (m,m), the row side carrying the factor -2
-    // (exact in bf16).  The dropped m.l, l.m, l.l are below 2^-26 |x_i x_j|.
+    // (exact in bf16).  |m| <= 2^-8 |x| and |l| <= 2^-17 |x|, so the dropped
+    // m.l, l.m, l.l add up to at most 2^-24 |x_i x_j|: one FP32 rounding.
     uint16_t *r = static_cast<uint16_t *>(xr) + i * kstride;
     uint16_t *c = static_cast<uint16_t *>(xc) + i * kstride;
     for (int t = 0; t < d; ++t) {

@@ -167,3 +167,21 @@ def test_sqdist_gemm_matches_difference_form():
     Z = K.sqdist_gemm(X, X)
     assert np.all(Z >= 0.0)
     assert np.all(np.diag(Z) <= 1e-13 * 2.0 * np.sum(X * X, 1))
+
+
+def test_fp32_values_are_three_exact_bf16_terms():
+    """The FP32 operator's operands carry each FP32 coordinate as h + m + l
+    with h = bf16(x), m = bf16(x - h), l = bf16(x - h - m): the sum is x
+    exactly, across magnitudes; |m| <= 2^-8 |x| and |l| <= 2^-17 |x|, so each
+    dropped product m.l is at most 2^-25 |x|^2."""
+    g = np.random.default_rng(12)
+    x = np.concatenate([g.standard_normal(200_000) * s for s in (1e-3, 1.0, 7.0, 1e3)]
+                       + [np.ldexp(g.uniform(1, 2, 100_000), g.integers(-90, 90, 100_000))])
+    x = P.round_fp32(x)
+    h = P.round_bf16(x)
+    m = P.round_bf16(x - h)
+    l = P.round_bf16(x - h - m)
+    np.testing.assert_array_equal(h + m + l, x)
+    assert np.all(np.abs(m) <= 2.0 ** -8 * np.abs(x))
+    assert np.all(np.abs(l) <= 2.0 ** -17 * np.abs(x))
+    assert np.all(np.abs(m * l) <= 2.0 ** -25 * x * x)
