@@ -234,6 +234,31 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given,
               dcg_recycle_t rc, const dcg_params *p, dcg_stats *st, void *ws,
               size_t ws_bytes);
 
+/* --------------------------------------------- extraction on its own
+ * The harmonic Ritz step of section 2.3 (Eq. 7) on caller-given Z and AZ,
+ * with the kernels that refresh W at the end of dcg_solve: F = (AZ)^T Z and
+ * G = (AZ)^T AZ (symmetrised), G u = theta F u solved in the range of F
+ * (directions of the diagonally scaled F with eigenvalue <= 1e-12 of the
+ * largest dropped), the k largest (largest != 0) or smallest theta kept,
+ * W' = Z U with U^T F U = I.
+ *  Z, AZ      device FP64 n x m, column-major (ld n); 1 <= m <= 192.
+ *  k          columns wanted, 1..64.
+ *  route      reduction of F, as dcg_params.ritz_route (0 or 1).
+ *  W_out      device FP64 n x k, column-major; the first *k_out columns are
+ *             written, *k_out = min(k, number of kept directions).
+ *  theta_out  host double[k]: the kept values in selection order.
+ *  rank_out   host int (may be NULL): directions of F kept.
+ *  stream     HIP stream of the call (NULL: the null stream); the call
+ *             returns once the results are in place.
+ *  ws         device workspace of dcg_harmonic_ritz_workspace_bytes(n, m)
+ *             bytes, 256-byte aligned, caller-owned.
+ * Errors: DCG_E_ARG (null pointer, sizes or route out of range),
+ * DCG_E_WORKSPACE, DCG_E_HIP. */
+size_t dcg_harmonic_ritz_workspace_bytes(int64_t n, int m);
+int dcg_harmonic_ritz(const double *Z, const double *AZ, int64_t n, int m, int k, int largest,
+                      int route, double *W_out, double *theta_out, int *k_out, int *rank_out,
+                      void *stream, void *ws, size_t ws_bytes);
+
 /* ------------------------------------------------ many right-hand sides
  * X = A^{-1} B for m <= 64 columns at once: every column runs its own
  * deflated CG (Algorithm 1) with the basis W held by rc (reused as it is, no

@@ -113,6 +113,13 @@ _SIGS = {
                                     ctypes.c_void_p, ctypes.c_int64,
                                     ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
                                     ctypes.c_size_t]),
+    "dcg_harmonic_ritz_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int]),
+    "dcg_harmonic_ritz": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_size_t]),
     "dcg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "dcg_version": (ctypes.c_char_p, []),
 }
@@ -479,6 +486,32 @@ def mll_grad(op, alpha, U, Z):
         _check(lib.dcg_mll_grad(op.handle, a.data_ptr(), Uc.data_ptr(), Zc.data_ptr(),
                                 Uc.shape[0], g, ptr, size), "dcg_mll_grad")
     return [g[0], g[1], g[2]]
+
+
+def harmonic_ritz(Z, AZ, k, largest=True, ritz_route="auto"):
+    """The harmonic Ritz extraction (section 2.3, Eq. 7) on given Z and AZ
+    (n x m device tensors): returns (W' = Z U as an n x k_out tensor, the kept
+    Ritz values, the number of directions of F kept).  Runs on the caller's
+    current stream."""
+    torch = _torch()
+    lib = load()
+    dev = Z.device
+    n, m = Z.shape
+    Zc = _colmajor(Z)
+    AZc = _colmajor(AZ.to(dev))
+    nbytes = lib.dcg_harmonic_ritz_workspace_bytes(n, m)
+    if nbytes == 0:
+        raise DcgError(-1, "dcg_harmonic_ritz_workspace_bytes")
+    _wsbuf, ptr, size = _workspace(nbytes, dev)
+    W = torch.zeros((k, n), dtype=torch.float64, device=dev)
+    th = (ctypes.c_double * k)()
+    kout, rank = ctypes.c_int(0), ctypes.c_int(0)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    _check(lib.dcg_harmonic_ritz(Zc.data_ptr(), AZc.data_ptr(), n, m, int(k), 1 if largest else 0,
+                                 _ritz_route(ritz_route), W.data_ptr(), th, ctypes.byref(kout),
+                                 ctypes.byref(rank), stream, ptr, size), "dcg_harmonic_ritz")
+    kk = kout.value
+    return W[:kk].t(), [th[i] for i in range(kk)], rank.value
 
 
 class GPMarginalLikelihood:

@@ -864,4 +864,62 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
   return with_refresh(st, rc, status);
 }
 
+// ------------------------------------------- extraction on given Z, AZ
+
+static size_t ritz_ws_layout(int64_t n, int m, size_t *off) {
+  Carve c(nullptr, 0);
+  off[0] = c.off = align256(c.off); c.off += size_t(m) * m * 8;                 // F
+  off[1] = c.off = align256(c.off); c.off += size_t(m) * m * 8;                 // G
+  off[2] = c.off = align256(c.off); c.off += harmonic_ritz_work_doubles() * 8;  // eigensolver
+  off[3] = c.off = align256(c.off); c.off += size_t(kMaxZ) * kMaxK * 8;         // U
+  off[4] = c.off = align256(c.off); c.off += size_t(kMaxK) * 8;                 // theta
+  off[5] = c.off = align256(c.off); c.off += 4 * sizeof(int);                   // info
+  off[6] = c.off = align256(c.off); c.off += kGemmPartDoubles * 8;              // F, G partials
+  (void)n;
+  return align256(c.off);
+}
+
+size_t dcg_harmonic_ritz_workspace_bytes(int64_t n, int m) {
+  if (n < 1 || m < 1 || m > kMaxZ) return 0;
+  size_t off[7];
+  return ritz_ws_layout(n, m, off);
+}
+
+int dcg_harmonic_ritz(const double *Z, const double *AZ, int64_t n, int m, int k, int largest,
+                      int route, double *W_out, double *theta_out, int *k_out, int *rank_out,
+                      void *stream, void *ws, size_t ws_bytes) {
+  if (Z == nullptr || AZ == nullptr || W_out == nullptr || theta_out == nullptr ||
+      k_out == nullptr || n < 1 || m < 1 || m > kMaxZ || k < 1 || k > kMaxK || route < 0 ||
+      route > 1)
+    return DCG_E_ARG;
+  size_t off[7];
+  if (ws == nullptr || ws_bytes < ritz_ws_layout(n, m, off)) return DCG_E_WORKSPACE;
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return DCG_E_WORKSPACE;
+  char *b = static_cast<char *>(ws);
+  double *F = reinterpret_cast<double *>(b + off[0]);
+  double *G = reinterpret_cast<double *>(b + off[1]);
+  double *eigw = reinterpret_cast<double *>(b + off[2]);
+  double *U = reinterpret_cast<double *>(b + off[3]);
+  double *th = reinterpret_cast<double *>(b + off[4]);
+  int *info_d = reinterpret_cast<int *>(b + off[5]);
+  double *part = reinterpret_cast<double *>(b + off[6]);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  enqueue_tsgemm_tn(s, AZ, Z, n, m, m, part, kGemmPartDoubles, F, m, 1);
+  enqueue_tsgemm_tn(s, AZ, AZ, n, m, m, part, kGemmPartDoubles, G, m, 1);
+  enqueue_harmonic_ritz(s, F, G, m, k, largest != 0, route, 1e-12, eigw, U, th, info_d);
+  int info[4] = {0, 0, 0, 0};
+  double theta[kMaxK];
+  HIPCHK(hipMemcpyAsync(info, info_d, sizeof(info), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(theta, th, sizeof(theta), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int knew = info[0];
+  if (knew > 0) enqueue_ts_times_small(s, Z, n, m, U, kMaxK, knew, W_out);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  for (int i = 0; i < knew; ++i) theta_out[i] = theta[i];
+  *k_out = knew;
+  if (rank_out != nullptr) *rank_out = info[1];
+  return DCG_OK;
+}
+
 }  // extern "C"
