@@ -135,6 +135,11 @@ def load(path=LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with "
                            "`python -m paper_1706_00241_amd.build`")
+    # torch first: the library then binds the HIP runtime torch has loaded
+    # (the same soname), so device pointers and streams from torch are valid
+    # in it; loaded first, it would bind the system runtime and torch a copy
+    # of its own
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
