@@ -62,9 +62,12 @@ def parse():
                     help="relative tolerance of each inner (low-precision) solve; the bf16 "
                          "operator contracts the refinement error by ~0.1 per step, so "
                          "tighter inner solves only add iterations")
-    ap.add_argument("--refresh", choices=["first", "accum"], default="first",
-                    help="refresh W after the first inner solve, or once per system from the "
-                         "directions of all its inner solves")
+    ap.add_argument("--refresh", choices=["first", "every", "accum"], default="first",
+                    help="refresh W after the first inner solve, after every inner solve, or "
+                         "once per system from the directions of all its inner solves")
+    ap.add_argument("--ritz-route", choices=["auto", "eigen"], default="auto",
+                    help="reduction of F in the harmonic Ritz problem (Cholesky where a bound "
+                         "allows it, or always the eigendecomposition)")
     ap.add_argument("--refine", choices=["ir", "fcg"], default="ir",
                     help="outer loop: iterative refinement or flexible CG in FP64")
     ap.add_argument("--no-tune", action="store_true",
@@ -327,7 +330,7 @@ def main():
     ws = dcg.SolveWorkspace(n, dev)
     x = torch.empty(n, dtype=torch.float64, device=dev)
     kw = dict(tol=w["tol"], refine=args.refine, inner_tol=args.inner_tol, ws=ws, out=x,
-              refresh_every=args.refresh,
+              refresh_every=args.refresh, ritz_route=args.ritz_route,
               check_every=8)
 
     for i in range(args.warmup):
