@@ -141,8 +141,11 @@ size_t harmonic_ritz_work_doubles();
 // hyperparameter in its pair loop: sqrt(log2(e) / 2) / ell for RBF,
 // sqrt(nu2) log2(e) / ell for Matern (nu2 = 3, 5).
 double point_scale(int kernel, double ell);
-constexpr float kLn2 = 0.69314718055994531f;
-constexpr float kLn2Sq3 = 0.16015085096464213f;   // ln2^2 / 3
+// ln 2 and ln^2 2 / 3, the latter derived from the former at compile time
+constexpr double kLn2d = 0.6931471805599453;   // the double nearest ln 2
+constexpr double kLn2Sq3d = kLn2d * kLn2d / 3.0;
+constexpr float kLn2 = static_cast<float>(kLn2d);
+constexpr float kLn2Sq3 = static_cast<float>(kLn2Sq3d);
 int launch_symv_sweep(const dcg_operator_s *op, int mv, const int *done);
 int launch_symv_sweep_from(const dcg_operator_s *op, int mv, const float *vin, const int *done);
 SymvArgs symv_args(const dcg_operator_s *op, int mv, const float *vin, const int *done,

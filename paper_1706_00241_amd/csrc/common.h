@@ -98,6 +98,7 @@ struct dcg_operator_s {
   uint64_t generation;   // bumped by every hyperparameter change
   int sweep_items;       // work-item target of the low-precision pair sweep
   int exact_items;       // work-item target of the FP64 pair sweep
+  double *x64;           // the points, FP64, n_pad x d row-major (operand source)
   double *x64r, *x64c;   // FP64 augmented operands of the exact operator
   double *vin64;         // staged FP64 input vector, n_pad
   double *part64;        // partial sums of the FP64 sweep

@@ -47,31 +47,28 @@ size_t exact_partial_doubles(int64_t n_pad) {
   return size_t(p.nchunk + p.dmax) * size_t(n_pad);
 }
 
-// e^x for x <= 0 (and small positive x), to within one ulp: Cody-Waite
-// reduction x = k ln2 + r with |r| <= ln2 / 2 (ln 2 split into a double and
-// its FP64 tail, so the fused reduction is exact to ~2^-106), the Taylor
-// series of e^r to degree 13 (remainder below 2e-18 relative), and 2^k
-// applied with ldexp.  Arguments below -745.5 give 0 (the clamp keeps the
-// reduction finite for arbitrarily large arguments).
-__device__ __forceinline__ double exp_nonpos(double x) {
-  x = fmax(x, -745.5);
-  const double k = __builtin_rint(x * 1.4426950408889634);   // 1 / ln 2
-  double r = fma(-k, 0.6931471805599453, x);                  // ln 2, double part
-  r = fma(-k, 2.3190468138462996e-17, r);                     // ln 2, tail
-  double p = 1.6059043836821613e-10;                          // 1 / 13!
-  p = fma(p, r, 2.08767569878681e-09);                        // 1 / 12!
-  p = fma(p, r, 2.505210838544172e-08);
-  p = fma(p, r, 2.755731922398589e-07);
-  p = fma(p, r, 2.7557319223985893e-06);
-  p = fma(p, r, 2.48015873015873e-05);
-  p = fma(p, r, 0.0001984126984126984);
-  p = fma(p, r, 0.001388888888888889);
-  p = fma(p, r, 0.008333333333333333);
-  p = fma(p, r, 0.041666666666666664);
-  p = fma(p, r, 0.16666666666666666);
-  p = fma(p, r, 0.5);
-  p = fma(p, r, 1.0);
-  p = fma(p, r, 1.0);
+// 2^x for x <= 0 (and small positive x), to about one ulp: k = rint(x) and
+// f = x - k in [-1/2, 1/2] (the subtraction is exact), 2^f by its degree-11
+// interpolating polynomial at the 12 Chebyshev nodes of [-1/2, 1/2]
+// (coefficients solved in 60-digit decimal arithmetic; the FMA Horner
+// evaluation stays within 1.3e-16 relative on the interval), and 2^k applied
+// with ldexp.  Arguments below -1100 give 0.
+__device__ __forceinline__ double exp2_nonpos(double x) {
+  x = fmax(x, -1100.0);
+  const double k = __builtin_rint(x);
+  const double f = x - k;
+  double p = 4.4558179083360645e-10;
+  p = fma(p, f, 7.074194297288521e-09);
+  p = fma(p, f, 1.0178057087733941e-07);
+  p = fma(p, f, 1.3215432535912375e-06);
+  p = fma(p, f, 1.5252733841556773e-05);
+  p = fma(p, f, 0.00015403530463724353);
+  p = fma(p, f, 0.001333355814640647);
+  p = fma(p, f, 0.009618129107587256);
+  p = fma(p, f, 0.055504108664821625);
+  p = fma(p, f, 0.24022650695910158);
+  p = fma(p, f, 0.6931471805599453);
+  p = fma(p, f, 1.0);
   return __builtin_amdgcn_ldexp(p, static_cast<int>(k));
 }
 
@@ -90,15 +87,20 @@ __device__ __forceinline__ double sqrt_nonneg(double a) {
   return fma(d, h, g);
 }
 
+// Kernel value without s2 from the squared distance r2 = (c r)^2 of the
+// operands (points pre-scaled by c = point_scale(kernel, ell)):
+//   RBF 2^-r2;  Matern (u = c r, t = sqrt(nu2) r / ell = ln2 u):
+//   3/2: (1 + ln2 u) 2^-u,  5/2: (1 + ln2 u + ln2^2 r2 / 3) 2^-u.
 template <int KERN>
-__device__ __forceinline__ double kval64(double r2, double c0, double c1) {
+__device__ __forceinline__ double kval64(double r2) {
   if constexpr (KERN == DCG_RBF) {
-    return exp_nonpos(r2 * c0);  // c0 = -1 / (2 ell^2)
+    return exp2_nonpos(-r2);
   } else {
-    const double t = sqrt_nonneg(fabs(r2)) * c1;  // c1 = sqrt(3)/ell or sqrt(5)/ell
-    const double e = exp_nonpos(-t);
-    if constexpr (KERN == DCG_MATERN32) return (1.0 + t) * e;
-    else return fma(t, fma(t, 1.0 / 3.0, 1.0), 1.0) * e;
+    const double r2a = fabs(r2);
+    const double u = sqrt_nonneg(r2a);
+    const double e = exp2_nonpos(-u);
+    if constexpr (KERN == DCG_MATERN32) return fma(kLn2d, u, 1.0) * e;
+    else return fma(kLn2d, u, fma(kLn2Sq3d, r2a, 1.0)) * e;
   }
 }
 
@@ -123,7 +125,6 @@ struct Symv64Args {
   double *prow, *pcol;
   int64_t n_pad;
   int nb, dmax, chunk, nchunk;
-  double c0, c1;
   const int *done;
 };
 
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(256, 2) void symv64_kernel(Symv64Args A) {
         double r2v = r2c[tr][v];
         // the exact diagonal: distance zero by definition
         if constexpr (DG) r2v = (dz && lg + 4 * v == lc) ? 0.0 : r2v;
-        const double kv = kval64<KERN>(r2v, A.c0, A.c1);
+        const double kv = kval64<KERN>(r2v);
         accr[tr][v] = fma(kv, pjc, accr[tr][v]);
         if constexpr (!DG) cs = fma(kv, pi[tr][v], cs);
       }
@@ -312,13 +313,6 @@ static Symv64Args exact_args(const dcg_operator_s *op, const int *done, MatvecPl
   a.chunk = p.chunk;
   a.nchunk = p.nchunk;
   a.done = done;
-  if (op->kernel == DCG_RBF) {
-    a.c0 = -1.0 / (2.0 * op->ell * op->ell);
-    a.c1 = 0.0;
-  } else {
-    a.c0 = 0.0;
-    a.c1 = std::sqrt(op->kernel == DCG_MATERN32 ? 3.0 : 5.0) / op->ell;
-  }
   *plan = p;
   return a;
 }

@@ -42,27 +42,35 @@ __global__ __launch_bounds__(256) void check_finite(const double *X, int64_t cou
     if (!isfinite(X[e])) atomicOr(flag, 1);
 }
 
-// FP64 operands of the exact operator, one thread per (padded) point, from
-// the input points (once, when the operator is created).
-__global__ __launch_bounds__(256) void prepare_exact(const double *X, int64_t n, int64_t n_pad,
-                                                     int d, int stride64, double *x64r,
+// The input points as an FP64 copy (n_pad x d, row-major, zero rows past
+// n), once when the operator is created: the source of every operand build.
+__global__ __launch_bounds__(256) void copy_points(const double *X, int64_t n, int64_t n_pad,
+                                                   int d, double *x64) {
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= n_pad * d) return;
+  x64[e] = (e < n * d) ? X[e] : 0.0;
+}
+
+// FP64 operands of the exact operator, one thread per (padded) point:
+// [-2y, a, 1] and [y, 1, a] with y = scale * x (point_scale of the kernel
+// and lengthscale, so the MFMA gives (c r)^2) and a = |y|^2, element k
+// stored at (k % 4) * ksp + k / 4 (the K-step layout of the 16x16x4 FP64
+// MFMA).  Run at creation and whenever the lengthscale changes.
+__global__ __launch_bounds__(256) void prepare_exact(const double *x64, int64_t n_pad, int d,
+                                                     int stride64, double scale, double *x64r,
                                                      double *x64c) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n_pad) return;
-  const bool real = i < n;
-  // FP64 operands of the exact operator: [-2x, a, 1] and [x, 1, a] with a
-  // the squared norm of the unrounded point, element k stored at
-  // (k % 4) * ksp + k / 4 (the K-step layout of the 16x16x4 FP64 MFMA)
   const int ksp = stride64 / 4;
   double *r64 = x64r + i * stride64;
   double *c64 = x64c + i * stride64;
   double a64 = 0.0;
   for (int t = 0; t < stride64; ++t) r64[t] = c64[t] = 0.0;
   for (int t = 0; t < d; ++t) {
-    const double xv = real ? X[i * d + t] : 0.0;
-    a64 += xv * xv;
-    r64[(t & 3) * ksp + (t >> 2)] = -2.0 * xv;
-    c64[(t & 3) * ksp + (t >> 2)] = xv;
+    const double yv = scale * x64[i * d + t];
+    a64 += yv * yv;
+    r64[(t & 3) * ksp + (t >> 2)] = -2.0 * yv;
+    c64[(t & 3) * ksp + (t >> 2)] = yv;
   }
   r64[(d & 3) * ksp + (d >> 2)] = a64;
   r64[((d + 1) & 3) * ksp + ((d + 1) >> 2)] = 1.0;
@@ -73,17 +81,15 @@ __global__ __launch_bounds__(256) void prepare_exact(const double *X, int64_t n,
 // Low-precision operands, one thread per (padded) point: the point scaled
 // by `scale` (point_scale of the kernel and lengthscale) and rounded, the
 // squared norm of the rounded scaled point, and the augmented row / column
-// operands.  The coordinates come from the FP64 column operand, which holds
-// x_t at (t % 4) * (stride64 / 4) + t / 4; run at creation and whenever the
-// lengthscale changes.
-__global__ __launch_bounds__(256) void prepare_lowprec(const double *x64c, int64_t n,
+// operands, from the FP64 copy of the points; run at creation and whenever
+// the lengthscale changes.
+__global__ __launch_bounds__(256) void prepare_lowprec(const double *x64, int64_t n,
                                                        int64_t n_pad, int d, int prec, int opk,
-                                                       int kstride, int stride64, double scale,
-                                                       void *xr, void *xc) {
+                                                       int kstride, double scale, void *xr,
+                                                       void *xc) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n_pad) return;
   const bool real = i < n;
-  const int ksp = stride64 / 4;
   double a = 0.0;
   if (prec == DCG_PREC_BF16X2) {
     // x = hi + lo, both bf16; the operand columns hold the four product
@@ -91,7 +97,7 @@ __global__ __launch_bounds__(256) void prepare_lowprec(const double *x64c, int64
     uint16_t *r = static_cast<uint16_t *>(xr) + i * kstride;
     uint16_t *c = static_cast<uint16_t *>(xc) + i * kstride;
     for (int t = 0; t < d; ++t) {
-      const double xv0 = real ? scale * x64c[i * stride64 + (t & 3) * ksp + (t >> 2)] : 0.0;
+      const double xv0 = real ? scale * x64[i * d + t] : 0.0;
       const uint16_t hi = bf16_from_double(xv0);
       const uint16_t lo = bf16_from_double(xv0 - bf16_to_double(hi));
       const double xv = bf16_to_double(hi) + bf16_to_double(lo);
@@ -119,7 +125,7 @@ __global__ __launch_bounds__(256) void prepare_lowprec(const double *x64c, int64
     uint16_t *c = static_cast<uint16_t *>(xc) + i * kstride;
     for (int t = 0; t < d; ++t) {
       const uint16_t h =
-          real ? bf16_from_double(scale * x64c[i * stride64 + (t & 3) * ksp + (t >> 2)]) : uint16_t(0);
+          real ? bf16_from_double(scale * x64[i * d + t]) : uint16_t(0);
       const double xv = bf16_to_double(h);
       a += xv * xv;
       c[t] = h;
@@ -145,7 +151,7 @@ __global__ __launch_bounds__(256) void prepare_lowprec(const double *x64c, int64
     uint16_t *c = static_cast<uint16_t *>(xc) + i * kstride;
     for (int t = 0; t < d; ++t) {
       const float xf =
-          real ? static_cast<float>(scale * x64c[i * stride64 + (t & 3) * ksp + (t >> 2)]) : 0.0f;
+          real ? static_cast<float>(scale * x64[i * d + t]) : 0.0f;
       const double xv = xf;
       a += xv * xv;
       const uint16_t h = bf16_from_double(xv);
@@ -180,7 +186,7 @@ __global__ __launch_bounds__(256) void prepare_lowprec(const double *x64c, int64
     for (int t = 0; t < kstride; ++t) r[t] = c[t] = 0.0f;
     for (int t = 0; t < d; ++t) {
       const float xv =
-          real ? static_cast<float>(scale * x64c[i * stride64 + (t & 3) * ksp + (t >> 2)]) : 0.0f;
+          real ? static_cast<float>(scale * x64[i * d + t]) : 0.0f;
       a += double(xv) * double(xv);
       c[(t & 1) * half + (t >> 1)] = xv;
       r[(t & 1) * half + (t >> 1)] = -2.0f * xv;
@@ -193,19 +199,23 @@ __global__ __launch_bounds__(256) void prepare_lowprec(const double *x64c, int64
   }
 }
 
-static int launch_prepare_lowprec(const dcg_operator_s *op) {
-  if (op->g.prec == DCG_PREC_FP64) return DCG_OK;
+// Both operand sets for the operator's kernel and lengthscale.
+static int launch_prepare(const dcg_operator_s *op) {
   const Geometry &g = op->g;
-  hipLaunchKernelGGL(prepare_lowprec, dim3(static_cast<unsigned>(cdiv(g.n_pad, 256))), dim3(256),
-                     0, op->stream, op->x64c, g.n, g.n_pad, g.d, g.prec, g.opk, g.kstride,
-                     exact_stride(g.d), point_scale(op->kernel, op->ell), op->xr, op->xc);
+  const double c = point_scale(op->kernel, op->ell);
+  const dim3 grid(static_cast<unsigned>(cdiv(g.n_pad, 256)));
+  hipLaunchKernelGGL(prepare_exact, grid, dim3(256), 0, op->stream, op->x64, g.n_pad, g.d,
+                     exact_stride(g.d), c, op->x64r, op->x64c);
+  if (g.prec != DCG_PREC_FP64)
+    hipLaunchKernelGGL(prepare_lowprec, grid, dim3(256), 0, op->stream, op->x64, g.n, g.n_pad,
+                       g.d, g.prec, g.opk, g.kstride, c, op->xr, op->xc);
   return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
 }
 
 // ----------------------------------------------------------- workspace
 
 struct OpLayout {
-  size_t x64r, x64c, vin64, part64, xr, xc, vin, part, ytmp, flag, total;
+  size_t x64, x64r, x64c, vin64, part64, xr, xc, vin, part, ytmp, flag, total;
 };
 
 static OpLayout op_layout(const Geometry &g) {
@@ -213,6 +223,7 @@ static OpLayout op_layout(const Geometry &g) {
   const size_t esz = (g.prec == DCG_PREC_FP64) ? 0 : (g.opk == kOpF32 ? 4 : 2);
   Carve c(nullptr, 0);
   OpLayout L;
+  L.x64 = c.off = align256(c.off); c.off += size_t(g.n_pad) * g.d * 8;
   L.x64r = c.off = align256(c.off); c.off += size_t(g.n_pad) * st64 * 8;
   L.x64c = c.off = align256(c.off); c.off += size_t(g.n_pad) * st64 * 8;
   L.vin64 = c.off = align256(c.off); c.off += size_t(g.n_pad) * 8;
@@ -316,6 +327,7 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel, doubl
   op->generation = 1;
   op->sweep_items = kSweepItemsDefault;
   op->exact_items = kSweepItemsDefault;
+  op->x64 = reinterpret_cast<double *>(base + L.x64);
   op->x64r = reinterpret_cast<double *>(base + L.x64r);
   op->x64c = reinterpret_cast<double *>(base + L.x64c);
   op->vin64 = reinterpret_cast<double *>(base + L.vin64);
@@ -331,10 +343,10 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel, doubl
   const int64_t count = n * d;
   hipLaunchKernelGGL(check_finite, dim3(static_cast<unsigned>(std::min<int64_t>(1024, cdiv(count, 256)))),
                      dim3(256), 0, op->stream, X, count, flag);
-  hipLaunchKernelGGL(prepare_exact, dim3(static_cast<unsigned>(cdiv(g.n_pad, 256))), dim3(256), 0,
-                     op->stream, X, n, g.n_pad, g.d, exact_stride(g.d), op->x64r, op->x64c);
+  hipLaunchKernelGGL(copy_points, dim3(static_cast<unsigned>(cdiv(g.n_pad * g.d, 256))), dim3(256),
+                     0, op->stream, X, n, g.n_pad, g.d, op->x64);
   ok = ok && hipGetLastError() == hipSuccess;
-  ok = ok && launch_prepare_lowprec(op) == DCG_OK;
+  ok = ok && launch_prepare(op) == DCG_OK;
   ok = ok && hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, op->stream) == hipSuccess;
   ok = ok && hipStreamSynchronize(op->stream) == hipSuccess;
   if (!ok) {
@@ -359,8 +371,8 @@ int dcg_set_hyper(dcg_op_t op, double ell, double s2, double sigma2) {
   op->s2 = s2;
   op->sigma2 = sigma2;
   op->generation += 1;
-  // the low-precision operands carry the lengthscale (point_scale)
-  return rescale ? launch_prepare_lowprec(op) : DCG_OK;
+  // the operands carry the lengthscale (point_scale)
+  return rescale ? launch_prepare(op) : DCG_OK;
 }
 
 int dcg_matvec(dcg_op_t op, const double *V, double *Y, int64_t m) {
