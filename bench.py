@@ -43,7 +43,7 @@ SLOTS_PER_PAIR = {0: 4, 1: 7, 2: 9}
 # HBM bytes per launch of the sweep measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled by a 256 MiB copy) for this workload and this version of
 # the kernel; None for any other configuration.
-SWEEP_TRAFFIC = {("bf16", 65536, 32, 2, 8192): 115.7e6}
+SWEEP_TRAFFIC = {("bf16", 65536, 32, 2, 8192): 112.7e6}
 
 
 def parse():
