@@ -20,6 +20,12 @@ of F (reading of the paper's silence on this case, listed in the design doc):
 which reduces to the plain definition when nothing is dropped.  U is
 F-orthonormal, so W'^T A W' = U^T F U = I for the operator that produced Z.
 Ties in theta are broken by a stable sort on the original column index.
+
+The standard Rayleigh-Ritz extraction, which section 2.3 sets the harmonic
+one against, is offered too: the pairs of (Z^T A Z) y = theta (Z^T Z) y, the
+Galerkin condition Z^T (A w - theta w) = 0 instead of the harmonic
+(AZ)^T (A w - theta w) = 0.  It is solved by the same reduction with Z^T Z in
+the role of F, so W' = Z U has orthonormal columns (U^T Z^T Z U = I).
 """
 
 import numpy as np
@@ -63,3 +69,34 @@ def harmonic_ritz(Z, AZ, k, largest=True, drop_tol=1e-12):
     idx = select(theta, min(k, theta.shape[0]), largest)
     U = U[:, idx]
     return Z @ U, AZ @ U, theta[idx], U
+
+
+def rayleigh_ritz_FE(Z, AZ):
+    """F = Z^T A Z (formed as (AZ)^T Z) and E = Z^T Z, both symmetrised."""
+    F = AZ.T @ Z
+    E = Z.T @ Z
+    return 0.5 * (F + F.T), 0.5 * (E + E.T)
+
+
+def rayleigh_ritz(Z, AZ, k, largest=True, drop_tol=1e-12):
+    """Rayleigh-Ritz extraction of the next basis: the pairs of
+    F y = theta E y solved in the range of E (same reduction as the harmonic
+    problem, E in the role of F); returns (W_new, AW_new, theta_sel, U) as
+    ``harmonic_ritz`` does, with U^T E U = I (orthonormal W_new)."""
+    F, E = rayleigh_ritz_FE(Z, AZ)
+    theta, U = harmonic_ritz_pairs(E, F, drop_tol)
+    idx = select(theta, min(k, theta.shape[0]), largest)
+    U = U[:, idx]
+    return Z @ U, AZ @ U, theta[idx], U
+
+
+HARMONIC, RAYLEIGH = 0, 1
+
+
+def extract(Z, AZ, k, largest=True, kind=HARMONIC, drop_tol=1e-12):
+    """The extraction of the next basis by kind (harmonic or Rayleigh-Ritz)."""
+    if kind == HARMONIC:
+        return harmonic_ritz(Z, AZ, k, largest, drop_tol)
+    if kind == RAYLEIGH:
+        return rayleigh_ritz(Z, AZ, k, largest, drop_tol)
+    raise ValueError(f"unknown extraction {kind}")

@@ -19,7 +19,7 @@ from . import ritz as _ritz
 
 
 def solve_sequence(matvecs, bs, k, L, tol, recycle=True, sigma2s=None,
-                   x_inits=None, largest=True, max_iter=None):
+                   x_inits=None, largest=True, max_iter=None, extraction=_ritz.HARMONIC):
     """Solve A_i x_i = b_i for i = 0..len-1.
 
     matvecs : list of callables v -> A_i v (or dense matrices)
@@ -51,7 +51,7 @@ def solve_sequence(matvecs, bs, k, L, tol, recycle=True, sigma2s=None,
             else:
                 Z, AZ = res.P, res.AP
             if Z.shape[1] > 0:
-                W, AW_prev_op, theta, _ = _ritz.harmonic_ritz(Z, AZ, k, largest)
+                W, AW_prev_op, theta, _ = _ritz.extract(Z, AZ, k, largest, extraction)
                 res.theta = theta
         out.append(res)
     return out

@@ -173,6 +173,60 @@ def test_harmonic_ritz_rank_deficient_F():
     assert np.all(np.isfinite(Wn))
 
 
+def test_rayleigh_ritz_full_basis_and_invariant_subspace():
+    """With Z spanning the whole space the Ritz values are the spectrum; with
+    an invariant subspace inside span(Z) its eigenvalues come out exactly."""
+    A, _ = workloads.spd_with_spectrum(np.linspace(1.0, 9.0, 12), seed=3)
+    Z = np.random.default_rng(0).standard_normal((12, 12))
+    _, _, theta, _ = RZ.rayleigh_ritz(Z, A @ Z, k=12)
+    np.testing.assert_allclose(np.sort(theta), np.linspace(1.0, 9.0, 12), rtol=1e-10)
+    A, W, _ = _deflation_case()
+    g = np.random.default_rng(2)
+    Z = np.hstack([W[:, :3], g.standard_normal((A.shape[0], 4))])
+    Wn, AWn, theta, _ = RZ.rayleigh_ritz(Z, A @ Z, k=3)
+    np.testing.assert_allclose(np.sort(theta), [300.0, 420.0, 500.0], rtol=1e-10)
+    np.testing.assert_allclose(Wn.T @ Wn, np.eye(3), atol=1e-10)     # orthonormal Ritz vectors
+    np.testing.assert_allclose(AWn, A @ Wn, rtol=1e-10, atol=1e-10)
+
+
+def test_ritz_galerkin_conditions_and_interlacing():
+    """The defining conditions of the two extractions on a generic basis:
+    Rayleigh-Ritz Z^T (A w - theta w) = 0, harmonic (AZ)^T (A w - theta w) = 0;
+    the Rayleigh-Ritz values interlace the spectrum (Cauchy): the j-th
+    largest lies between the j-th largest and the (n - m + j)-th largest
+    eigenvalue; both sets lie inside [lambda_min, lambda_max]."""
+    _, A, _ = _kernel_system(n=150, seed=12)
+    lam = np.sort(np.linalg.eigvalsh(A))[::-1]
+    m = 20
+    Z = np.random.default_rng(5).standard_normal((150, m))
+    AZ = A @ Z
+    for kind, test_space in ((RZ.RAYLEIGH, Z), (RZ.HARMONIC, AZ)):
+        Wn, AWn, theta, _ = RZ.extract(Z, AZ, k=m, kind=kind)
+        R = AWn - Wn * theta[None, :]
+        scale = np.linalg.norm(test_space) * np.linalg.norm(AWn)
+        assert np.abs(test_space.T @ R).max() <= 1e-10 * scale, kind
+        assert theta.min() >= lam[-1] * (1 - 1e-9) and theta.max() <= lam[0] * (1 + 1e-9)
+    _, _, th_rr, _ = RZ.rayleigh_ritz(Z, AZ, k=m)
+    th_rr = np.sort(th_rr)[::-1]
+    n = 150
+    for j in range(m):
+        assert lam[n - m + j] * (1 - 1e-9) <= th_rr[j] <= lam[j] * (1 + 1e-9), j
+    # largest selection is descending, smallest ascending
+    assert np.all(np.diff(RZ.rayleigh_ritz(Z, AZ, 5)[2]) <= 0)
+    assert np.all(np.diff(RZ.rayleigh_ritz(Z, AZ, 5, largest=False)[2]) >= 0)
+
+
+def test_rayleigh_ritz_rank_deficient_Z():
+    """Repeated columns make Z^T Z singular: the repeats are dropped and the
+    values are those of the basis without them."""
+    _, A, _ = _kernel_system(n=90, seed=13)
+    Z0 = np.random.default_rng(6).standard_normal((90, 8))
+    Z = np.hstack([Z0, Z0[:, :3]])
+    _, _, th, _ = RZ.rayleigh_ritz(Z, A @ Z, k=5)
+    _, _, th0, _ = RZ.rayleigh_ritz(Z0, A @ Z0, k=5)
+    np.testing.assert_allclose(th, th0, rtol=1e-9)
+
+
 def test_sequence_first_system_is_cg_and_deflation_helps():
     w = workloads.small(n=400, d=4, systems=4)
     mats = [K.operator(w["X"], w["kernel"], ell, w["s2"], w["sigma2"]) for ell in w["ells"]]
