@@ -65,6 +65,10 @@ def parse():
     ap.add_argument("--refresh", choices=["first", "every", "accum"], default="first",
                     help="refresh W after the first inner solve, after every inner solve, or "
                          "once per system from the directions of all its inner solves")
+    ap.add_argument("--extraction", choices=["harmonic", "rayleigh"], default="harmonic",
+                    help="next basis by harmonic Ritz (Eq. 7) or by Rayleigh-Ritz")
+    ap.add_argument("--select", choices=["largest", "smallest"], default="largest",
+                    help="keep the Ritz pairs of the largest or of the smallest values")
     ap.add_argument("--ritz-route", choices=["auto", "eigen"], default="auto",
                     help="reduction of F in the harmonic Ritz problem (Cholesky where a bound "
                          "allows it, or always the eigendecomposition)")
@@ -331,6 +335,7 @@ def main():
     x = torch.empty(n, dtype=torch.float64, device=dev)
     kw = dict(tol=w["tol"], refine=args.refine, inner_tol=args.inner_tol, ws=ws, out=x,
               refresh_every=args.refresh, ritz_route=args.ritz_route,
+              extraction=args.extraction, select_largest=args.select == "largest",
               check_every=8)
 
     for i in range(args.warmup):
@@ -385,6 +390,7 @@ def main():
                                 f"sigma2=1e-3*0.9^i k={w['k']} L={w['L']} refine to 1e-8"),
                    "systems_timed": args.steps, "first_system": args.warmup,
                    "refine": args.refine, "refresh": args.refresh, "inner_tol": args.inner_tol,
+                   "extraction": args.extraction, "select": args.select,
                    "sweep_items": items},
         "iters_per_solve": round(sum(s["iters"] for s in stats) / args.steps, 1),
         "matvecs_per_solve": round(sum(s["matvecs"] for s in stats) / args.steps, 1),

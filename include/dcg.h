@@ -102,6 +102,11 @@ typedef struct {
                           eigendecomposition; 1: always the eigendecomposition
                           (both give the same pairs when nothing is dropped);
                           DCG_E_ARG otherwise                                 */
+  int extraction;      /* the next basis from span(Z), Z = [W, P_L] (section
+                          2.3): 0 harmonic Ritz, G u = theta F u (Eq. 7),
+                          W' A-orthonormal; 1 Rayleigh-Ritz,
+                          (Z^T A Z) y = theta (Z^T Z) y, W' orthonormal;
+                          DCG_E_ARG otherwise                                 */
 } dcg_params;
 
 /* Per-solve statistics (host struct, filled by dcg_solve). */
@@ -235,12 +240,13 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given,
               size_t ws_bytes);
 
 /* --------------------------------------------- extraction on its own
- * The harmonic Ritz step of section 2.3 (Eq. 7) on caller-given Z and AZ,
- * with the kernels that refresh W at the end of dcg_solve: F = (AZ)^T Z and
- * G = (AZ)^T AZ (symmetrised), G u = theta F u solved in the range of F
- * (directions of the diagonally scaled F with eigenvalue <= 1e-12 of the
- * largest dropped), the k largest (largest != 0) or smallest theta kept,
- * W' = Z U with U^T F U = I.
+ * The refresh step of section 2.3 on caller-given Z and AZ, with the kernels
+ * that refresh W at the end of dcg_solve.  Harmonic Ritz (extraction = 0,
+ * Eq. 7): F = (AZ)^T Z and G = (AZ)^T AZ; Rayleigh-Ritz (extraction = 1):
+ * F = Z^T Z and G = (AZ)^T Z (all symmetrised).  G u = theta F u is solved
+ * in the range of F (directions of the diagonally scaled F with eigenvalue
+ * <= 1e-12 of the largest dropped), the k largest (largest != 0) or
+ * smallest theta kept, W' = Z U with U^T F U = I.
  *  Z, AZ      device FP64 n x m, column-major (ld n); 1 <= m <= 192.
  *  k          columns wanted, 1..64.
  *  route      reduction of F, as dcg_params.ritz_route (0 or 1).
@@ -252,12 +258,12 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given,
  *             returns once the results are in place.
  *  ws         device workspace of dcg_harmonic_ritz_workspace_bytes(n, m)
  *             bytes, 256-byte aligned, caller-owned.
- * Errors: DCG_E_ARG (null pointer, sizes or route out of range),
- * DCG_E_WORKSPACE, DCG_E_HIP. */
-size_t dcg_harmonic_ritz_workspace_bytes(int64_t n, int m);
-int dcg_harmonic_ritz(const double *Z, const double *AZ, int64_t n, int m, int k, int largest,
-                      int route, double *W_out, double *theta_out, int *k_out, int *rank_out,
-                      void *stream, void *ws, size_t ws_bytes);
+ * Errors: DCG_E_ARG (null pointer, sizes, extraction or route out of
+ * range), DCG_E_WORKSPACE, DCG_E_HIP. */
+size_t dcg_extract_basis_workspace_bytes(int64_t n, int m);
+int dcg_extract_basis(const double *Z, const double *AZ, int64_t n, int m, int k, int largest,
+                      int extraction, int route, double *W_out, double *theta_out, int *k_out,
+                      int *rank_out, void *stream, void *ws, size_t ws_bytes);
 
 /* ------------------------------------------------ many right-hand sides
  * X = A^{-1} B for m <= 64 columns at once: every column runs its own

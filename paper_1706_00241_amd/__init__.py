@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("refine_max", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("true_residual", ctypes.c_int),
                 ("profile", ctypes.c_int), ("refresh_every", ctypes.c_int),
-                ("ritz_route", ctypes.c_int)]
+                ("ritz_route", ctypes.c_int), ("extraction", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -113,10 +113,11 @@ _SIGS = {
                                     ctypes.c_void_p, ctypes.c_int64,
                                     ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
                                     ctypes.c_size_t]),
-    "dcg_harmonic_ritz_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int]),
-    "dcg_harmonic_ritz": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+    "dcg_extract_basis_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int]),
+    "dcg_extract_basis": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_size_t]),
@@ -366,10 +367,18 @@ def _ritz_route(route):
     raise ValueError(f"ritz_route must be 'auto' or 'eigen', not {route!r}")
 
 
+def _extraction(kind):
+    if kind in ("harmonic", 0):
+        return 0
+    if kind in ("rayleigh", 1):
+        return 1
+    raise ValueError(f"extraction must be 'harmonic' or 'rayleigh', not {kind!r}")
+
+
 def solve(op, b, x0=None, rc=None, tol=1e-6, max_iter=0, L=0, select_largest=True,
           check_every=8, refine=False, inner_tol=1e-4, refine_max=20, use_graph=True,
-          true_residual=False, profile=False, refresh_every=False, ritz_route="auto", ws=None,
-          out=None):
+          true_residual=False, profile=False, refresh_every=False, ritz_route="auto",
+          extraction="harmonic", ws=None, out=None):
     """Deflated CG (Algorithm 1) for A x = b; returns (x, stats dict).
 
     rc=None runs plain CG; with a Recycle the solve uses its W and leaves the
@@ -377,7 +386,8 @@ def solve(op, b, x0=None, rc=None, tol=1e-6, max_iter=0, L=0, select_largest=Tru
     iterative refinement to ``tol`` against the FP64 operator, refine="fcg"
     flexible CG in FP64 with the inner deflated solve as preconditioner.
     ritz_route="eigen" reduces F in the harmonic Ritz problem by its
-    eigendecomposition even where the Cholesky reduction is safe.
+    eigendecomposition even where the Cholesky reduction is safe;
+    extraction="rayleigh" extracts the next W by Rayleigh-Ritz instead.
     """
     torch = _torch()
     lib = load()
@@ -395,7 +405,7 @@ def solve(op, b, x0=None, rc=None, tol=1e-6, max_iter=0, L=0, select_largest=Tru
                refine=_refine_mode(refine), inner_tol=float(inner_tol), refine_max=int(refine_max),
                use_graph=1 if use_graph else 0, true_residual=1 if true_residual else 0,
                profile=1 if profile else 0, refresh_every=_refresh_mode(refresh_every),
-               ritz_route=_ritz_route(ritz_route))
+               ritz_route=_ritz_route(ritz_route), extraction=_extraction(extraction))
     st = Stats()
     with _ordered(op.stream):
         status = lib.dcg_solve(op.handle, b.data_ptr(), out.data_ptr(), x_given,
@@ -433,7 +443,8 @@ def solve_block(op, B, rc=None, tol=1e-6, max_iter=0, check_every=8, out=None):
 
 
 def solve_batched(ops, bs, rcs=None, x0s=None, tol=1e-6, max_iter=0, L=0, select_largest=True,
-                  check_every=8, use_graph=True, true_residual=False, ritz_route="auto", ws=None):
+                  check_every=8, use_graph=True, true_residual=False, ritz_route="auto",
+                  extraction="harmonic", ws=None):
     """Independent systems ops[s] x_s = bs[s], each by deflated CG with the
     basis of rcs[s] (or plain CG for a None entry) and the extraction of the
     next basis, iterated in lockstep.  The operators must share one stream.
@@ -467,7 +478,7 @@ def solve_batched(ops, bs, rcs=None, x0s=None, tol=1e-6, max_iter=0, L=0, select
     p = Params(tol=float(tol), max_iter=int(max_iter), L=int(L),
                select_largest=1 if select_largest else 0, check_every=int(check_every),
                use_graph=1 if use_graph else 0, true_residual=1 if true_residual else 0,
-               ritz_route=_ritz_route(ritz_route))
+               ritz_route=_ritz_route(ritz_route), extraction=_extraction(extraction))
     st = (Stats * count)()
     with _ordered(ops[0].stream):
         status = lib.dcg_solve_batched(count, h_ops, h_b, h_x, x_given, h_rc, ctypes.byref(p),
@@ -493,28 +504,29 @@ def mll_grad(op, alpha, U, Z):
     return [g[0], g[1], g[2]]
 
 
-def harmonic_ritz(Z, AZ, k, largest=True, ritz_route="auto"):
-    """The harmonic Ritz extraction (section 2.3, Eq. 7) on given Z and AZ
-    (n x m device tensors): returns (W' = Z U as an n x k_out tensor, the kept
-    Ritz values, the number of directions of F kept).  Runs on the caller's
-    current stream."""
+def extract_basis(Z, AZ, k, largest=True, extraction="harmonic", ritz_route="auto"):
+    """The extraction of the next basis (section 2.3: harmonic Ritz, Eq. 7, or
+    Rayleigh-Ritz) on given Z and AZ (n x m device tensors): returns (W' = Z U
+    as an n x k_out tensor, the kept Ritz values, the number of directions of
+    the metric kept).  Runs on the caller's current stream."""
     torch = _torch()
     lib = load()
     dev = Z.device
     n, m = Z.shape
     Zc = _colmajor(Z)
     AZc = _colmajor(AZ.to(dev))
-    nbytes = lib.dcg_harmonic_ritz_workspace_bytes(n, m)
+    nbytes = lib.dcg_extract_basis_workspace_bytes(n, m)
     if nbytes == 0:
-        raise DcgError(-1, "dcg_harmonic_ritz_workspace_bytes")
+        raise DcgError(-1, "dcg_extract_basis_workspace_bytes")
     _wsbuf, ptr, size = _workspace(nbytes, dev)
     W = torch.zeros((k, n), dtype=torch.float64, device=dev)
     th = (ctypes.c_double * k)()
     kout, rank = ctypes.c_int(0), ctypes.c_int(0)
     stream = torch.cuda.current_stream(dev).cuda_stream
-    _check(lib.dcg_harmonic_ritz(Zc.data_ptr(), AZc.data_ptr(), n, m, int(k), 1 if largest else 0,
-                                 _ritz_route(ritz_route), W.data_ptr(), th, ctypes.byref(kout),
-                                 ctypes.byref(rank), stream, ptr, size), "dcg_harmonic_ritz")
+    _check(lib.dcg_extract_basis(Zc.data_ptr(), AZc.data_ptr(), n, m, int(k), 1 if largest else 0,
+                                 _extraction(extraction), _ritz_route(ritz_route), W.data_ptr(),
+                                 th, ctypes.byref(kout), ctypes.byref(rank), stream, ptr, size),
+           "dcg_extract_basis")
     kk = kout.value
     return W[:kk].t(), [th[i] for i in range(kk)], rank.value
 

@@ -193,7 +193,7 @@ int dcg_solve_batched(int count, const dcg_op_t *ops, const double *const *b, do
       p == nullptr)
     return DCG_E_ARG;
   if (!(p->tol >= 0.0) || p->check_every < 0 || p->refine != 0 || p->ritz_route < 0 ||
-      p->ritz_route > 1)
+      p->ritz_route > 1 || p->extraction < 0 || p->extraction > 1)
     return DCG_E_ARG;
   std::vector<int64_t> ns(count);
   std::set<const void *> seen_op, seen_rc;

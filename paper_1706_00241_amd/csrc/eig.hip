@@ -1,5 +1,7 @@
-// Harmonic Ritz extraction on the device: the small generalized eigenproblem
-// G u = theta F u of section 2.3 (Eq. 7), F = (AZ)^T Z, G = (AZ)^T AZ.
+// The extraction's small generalized eigenproblem G u = theta F u on the
+// device (section 2.3): harmonic Ritz (Eq. 7) F = (AZ)^T Z, G = (AZ)^T AZ,
+// or Rayleigh-Ritz F = Z^T Z, G = Z^T A Z.  Below, "F" is the matrix in the
+// role of the metric.
 //
 // F is SPD in exact arithmetic but can be numerically singular when CG has
 // lost A-conjugacy, so the problem is solved in the range of F:

@@ -386,15 +386,29 @@ int solve_loop(dcg_operator_s *op, const dcg_params *p, SolveCtx *ctx, InnerResu
 }
 
 
-// The harmonic Ritz extraction of W' = Z U (section 2.3, Eq. 7) from the
-// first mz columns of Z = [W, stored directions] and AZ.
+// The pencil (G, F) of the extraction from the m columns of Z and AZ:
+// harmonic Ritz (Eq. 7) G = (AZ)^T AZ, F = (AZ)^T Z; Rayleigh-Ritz
+// G = (AZ)^T Z, F = Z^T Z.  Both symmetrised, m x m.
+static void enqueue_extraction_pencil(hipStream_t s, const double *Z, const double *AZ, int64_t n,
+                                      int m, int extraction, double *part, double *F, double *G) {
+  if (extraction == 1) {
+    enqueue_tsgemm_tn(s, Z, Z, n, m, m, part, kGemmPartDoubles, F, m, 1);
+    enqueue_tsgemm_tn(s, AZ, Z, n, m, m, part, kGemmPartDoubles, G, m, 1);
+  } else {
+    enqueue_tsgemm_tn(s, AZ, Z, n, m, m, part, kGemmPartDoubles, F, m, 1);
+    enqueue_tsgemm_tn(s, AZ, AZ, n, m, m, part, kGemmPartDoubles, G, m, 1);
+  }
+}
+
+// The extraction of W' = Z U (section 2.3: harmonic Ritz, Eq. 7, or
+// Rayleigh-Ritz) from the first mz columns of Z = [W, stored directions] and
+// AZ.
 int extract_basis(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_params *p, int mz,
                   InnerResult *out) {
   hipStream_t s = op->stream;
   const int64_t n = op->g.n;
   if (mz <= 0) return DCG_OK;
-  enqueue_tsgemm_tn(s, rc->AZ, rc->Z, n, mz, mz, rc->gemm, kGemmPartDoubles, rc->F, mz, 1);
-  enqueue_tsgemm_tn(s, rc->AZ, rc->AZ, n, mz, mz, rc->gemm, kGemmPartDoubles, rc->G, mz, 1);
+  enqueue_extraction_pencil(s, rc->Z, rc->AZ, n, mz, p->extraction, rc->gemm, rc->F, rc->G);
   enqueue_harmonic_ritz(s, rc->F, rc->G, mz, rc->k, p->select_largest, p->ritz_route, 1e-12,
                         rc->eigw, rc->U, rc->small, rc->info);
   int info[4] = {0, 0, 0, 0};
@@ -772,7 +786,8 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
   std::memset(st, 0, sizeof(*st));
   if (op == nullptr || b == nullptr || x == nullptr || p == nullptr) return st->status = DCG_E_ARG;
   if (!(p->tol >= 0.0) || p->check_every < 0 || p->refine < 0 || p->refine > 2 ||
-      p->refresh_every < 0 || p->refresh_every > 2 || p->ritz_route < 0 || p->ritz_route > 1)
+      p->refresh_every < 0 || p->refresh_every > 2 || p->ritz_route < 0 || p->ritz_route > 1 ||
+      p->extraction < 0 || p->extraction > 1)
     return st->status = DCG_E_ARG;
   if (rc != nullptr && rc->n != op->g.n) return st->status = DCG_E_ARG;
   if (ws == nullptr || ws_bytes < solve_layout(op->g.n).total) return st->status = DCG_E_WORKSPACE;
@@ -879,18 +894,18 @@ static size_t ritz_ws_layout(int64_t n, int m, size_t *off) {
   return align256(c.off);
 }
 
-size_t dcg_harmonic_ritz_workspace_bytes(int64_t n, int m) {
+size_t dcg_extract_basis_workspace_bytes(int64_t n, int m) {
   if (n < 1 || m < 1 || m > kMaxZ) return 0;
   size_t off[7];
   return ritz_ws_layout(n, m, off);
 }
 
-int dcg_harmonic_ritz(const double *Z, const double *AZ, int64_t n, int m, int k, int largest,
-                      int route, double *W_out, double *theta_out, int *k_out, int *rank_out,
-                      void *stream, void *ws, size_t ws_bytes) {
+int dcg_extract_basis(const double *Z, const double *AZ, int64_t n, int m, int k, int largest,
+                      int extraction, int route, double *W_out, double *theta_out, int *k_out,
+                      int *rank_out, void *stream, void *ws, size_t ws_bytes) {
   if (Z == nullptr || AZ == nullptr || W_out == nullptr || theta_out == nullptr ||
       k_out == nullptr || n < 1 || m < 1 || m > kMaxZ || k < 1 || k > kMaxK || route < 0 ||
-      route > 1)
+      route > 1 || extraction < 0 || extraction > 1)
     return DCG_E_ARG;
   size_t off[7];
   if (ws == nullptr || ws_bytes < ritz_ws_layout(n, m, off)) return DCG_E_WORKSPACE;
@@ -904,8 +919,7 @@ int dcg_harmonic_ritz(const double *Z, const double *AZ, int64_t n, int m, int k
   int *info_d = reinterpret_cast<int *>(b + off[5]);
   double *part = reinterpret_cast<double *>(b + off[6]);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  enqueue_tsgemm_tn(s, AZ, Z, n, m, m, part, kGemmPartDoubles, F, m, 1);
-  enqueue_tsgemm_tn(s, AZ, AZ, n, m, m, part, kGemmPartDoubles, G, m, 1);
+  enqueue_extraction_pencil(s, Z, AZ, n, m, extraction, part, F, G);
   enqueue_harmonic_ritz(s, F, G, m, k, largest != 0, route, 1e-12, eigw, U, th, info_d);
   int info[4] = {0, 0, 0, 0};
   double theta[kMaxK];

@@ -95,24 +95,25 @@ def test_batched_arguments_without_gpu(L):
     assert L.dcg_solve_batched(2, null2, null2, null2, 0, None, ctypes.byref(pr), st, None, 0) == -1
 
 
-def test_harmonic_ritz_arguments_without_gpu(L):
+def test_extract_basis_arguments_without_gpu(L):
     import paper_1706_00241_amd as dcg
-    assert L.dcg_harmonic_ritz_workspace_bytes(1000, 160) > 2 * 160 * 160 * 8
-    assert L.dcg_harmonic_ritz_workspace_bytes(1000, 193) == 0
-    assert L.dcg_harmonic_ritz_workspace_bytes(0, 10) == 0
+    assert L.dcg_extract_basis_workspace_bytes(1000, 160) > 2 * 160 * 160 * 8
+    assert L.dcg_extract_basis_workspace_bytes(1000, 193) == 0
+    assert L.dcg_extract_basis_workspace_bytes(0, 10) == 0
     buf = ctypes.create_string_buffer(4096)
     th = (ctypes.c_double * 64)()
     k, r = ctypes.c_int(0), ctypes.c_int(0)
-    args = lambda **kw: dict(dict(Z=buf, AZ=buf, n=100, m=10, k=4, largest=1, route=0, W=buf,
-                                  th=th, k_out=ctypes.byref(k)), **kw)
+    args = lambda **kw: dict(dict(Z=buf, AZ=buf, n=100, m=10, k=4, largest=1, kind=0, route=0,
+                                  W=buf, th=th, k_out=ctypes.byref(k)), **kw)
     def call(a):
-        return L.dcg_harmonic_ritz(a["Z"], a["AZ"], a["n"], a["m"], a["k"], a["largest"],
-                                   a["route"], a["W"], a["th"], a["k_out"], ctypes.byref(r), None,
-                                   buf, 16)
+        return L.dcg_extract_basis(a["Z"], a["AZ"], a["n"], a["m"], a["k"], a["largest"],
+                                   a["kind"], a["route"], a["W"], a["th"], a["k_out"],
+                                   ctypes.byref(r), None, buf, 16)
     # every argument error is found before any HIP call; then the workspace
     assert call(args(Z=None)) == -1
     assert call(args(m=0)) == -1
     assert call(args(m=193)) == -1
     assert call(args(k=65)) == -1
     assert call(args(route=2)) == -1
+    assert call(args(kind=2)) == -1
     assert call(args()) == -6

@@ -207,7 +207,7 @@ def test_ritz_routes_match_oracle(lib, k, L, sigma2):
     whose W comes from that extraction), and the GPU basis is checked for the defining
     properties W^T A W = I and (AW)^T AW = diag(theta) with the dense FP64 A.
     The extraction itself on identical inputs is pinned by
-    test_harmonic_ritz_on_given_Z_matches_oracle.  The two routes' spaces
+    test_extraction_on_given_Z_matches_oracle.  The two routes' spaces
     agree to rounding in every case."""
     w = workloads.small(systems=3)
     X = w["X"]
@@ -258,24 +258,28 @@ def test_ritz_routes_match_oracle(lib, k, L, sigma2):
         assert any(c and dim > 104 for c, _, dim in chosen[1:])
 
 
+@pytest.mark.parametrize("kind", ["harmonic", "rayleigh"])
 @pytest.mark.parametrize("route", ["auto", "eigen"])
 @pytest.mark.parametrize("n,m,k,dup,largest", [(600, 40, 8, 0, True), (600, 40, 8, 0, False),
                                                (600, 60, 8, 20, True), (900, 150, 32, 0, True),
                                                (900, 150, 16, 30, True)])
-def test_harmonic_ritz_on_given_Z_matches_oracle(lib, route, n, m, k, dup, largest):
-    """The extraction kernels alone (dcg_harmonic_ritz), fed a Z and AZ = A Z
+def test_extraction_on_given_Z_matches_oracle(lib, kind, route, n, m, k, dup, largest):
+    """The extraction kernels alone (dcg_extract_basis), fed a Z and AZ = A Z
     that the oracle also gets: the same Ritz values (rtol 1e-10) and the same
-    W' = Z U column by column (up to sign).  Z is Gaussian; with dup > 0 its
-    last columns repeat earlier ones, so F is singular and both sides drop
-    the repeated directions (rank m - dup).  m = 150 runs the instance that
-    keeps its eigenvectors in global memory."""
+    W' = Z U column by column (up to sign), for harmonic and Rayleigh-Ritz
+    extraction.  Z is Gaussian; with dup > 0 its last columns repeat earlier
+    ones, so the metric (F, or Z^T Z) is singular and both sides drop the
+    repeated directions (rank m - dup).  m = 150 runs the instance that keeps
+    its eigenvectors in global memory."""
     g = np.random.default_rng(n + m + dup)
     A = OK.operator(g.standard_normal((n, 4)), 0, 1.0, 1.0, 1e-2)
     Z0 = g.standard_normal((n, m - dup))
     Z = np.hstack([Z0, Z0[:, :dup]]) if dup else Z0
     AZ = A @ Z
-    Wg, thg, rank = lib.harmonic_ritz(_dev(Z), _dev(AZ), k, largest=largest, ritz_route=route)
-    Wr, _, thr, _ = ORZ.harmonic_ritz(Z, AZ, k, largest=largest)
+    Wg, thg, rank = lib.extract_basis(_dev(Z), _dev(AZ), k, largest=largest, extraction=kind,
+                                      ritz_route=route)
+    Wr, _, thr, _ = ORZ.extract(Z, AZ, k, largest=largest,
+                                kind=ORZ.RAYLEIGH if kind == "rayleigh" else ORZ.HARMONIC)
     assert rank == m - dup
     assert len(thg) == k
     np.testing.assert_allclose(thg, thr, rtol=1e-10)
@@ -283,8 +287,37 @@ def test_harmonic_ritz_on_given_Z_matches_oracle(lib, route, n, m, k, dup, large
     for i in range(k):
         w = Wg[:, i] * np.sign(Wg[:, i] @ Wr[:, i])
         assert np.linalg.norm(w - Wr[:, i]) <= 1e-8 * np.linalg.norm(Wr[:, i]), i
-    # U^T F U = I: W' is A-orthonormal
-    np.testing.assert_allclose(Wg.T @ A @ Wg, np.eye(k), atol=1e-9)
+    # U^T F U = I: W' is A-orthonormal (harmonic) or orthonormal (Rayleigh-Ritz)
+    metric = A if kind == "harmonic" else np.eye(n)
+    np.testing.assert_allclose(Wg.T @ metric @ Wg, np.eye(k), atol=1e-9)
+
+
+@pytest.mark.parametrize("largest", [True, False])
+def test_rayleigh_ritz_sequence_matches_oracle(lib, largest):
+    """The n = 1024 sequence with Rayleigh-Ritz extraction (FP64 operator,
+    def-CG(8, 12), tol 1e-8), largest or smallest Ritz values kept: the
+    oracle's iteration counts within 2, its Ritz values to rtol 1e-6, true
+    residuals at the tolerance, and an orthonormal recycled basis."""
+    w = workloads.small()
+    X = w["X"]
+    n = X.shape[0]
+    tol = 1e-8
+    mats = [OK.operator(X, w["kernel"], ell, 1.0, w["sigma2"]) for ell in w["ells"]]
+    bs = [A @ w["xstar"] + w["noise"][i] for i, A in enumerate(mats)]
+    ref = OS.solve_sequence(mats, bs, k=8, L=12, tol=tol, largest=largest,
+                            extraction=ORZ.RAYLEIGH)
+    op = lib.Operator(_dev(X), w["kernel"], w["ells"][0], 1.0, w["sigma2"], prec=3)
+    rc = lib.Recycle(n, 8, 12)
+    for i, (ell, A, b) in enumerate(zip(w["ells"], mats, bs)):
+        op.set_hyper(ell, 1.0, w["sigma2"])
+        x, st = lib.solve(op, _dev(b), rc=rc, tol=tol, extraction="rayleigh",
+                          select_largest=largest)
+        assert st["status"] == 0
+        assert np.linalg.norm(b - A @ _np(x)) / np.linalg.norm(b) <= 3 * tol
+        assert abs(st["iters"] - ref[i].iters) <= 2, (i, st["iters"], ref[i].iters)
+        np.testing.assert_allclose(np.array(rc.theta()), ref[i].theta, rtol=1e-6)
+        Wg = _np(rc.get_W())
+        np.testing.assert_allclose(Wg.T @ Wg, np.eye(Wg.shape[1]), atol=1e-9)
 
 
 def test_recycled_basis_is_A_orthonormal(lib):
