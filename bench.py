@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--sweep-items", type=int, default=0, metavar="N",
                     help="use this sweep plan (work-item target) instead of tuning; for "
                          "profiling runs that should launch only the timed plan")
-    ap.add_argument("--workload", choices=["bf16_shift", "ragged", "gp_hyper"],
+    ap.add_argument("--workload", choices=["bf16_shift", "ragged", "gp_hyper", "fp32_walk"],
                     default="bf16_shift",
                     help="bf16_shift: the headline sequence; ragged: the batching form (64 "
                          "independent sequences, one batched solve per step); gp_hyper: the "
@@ -205,6 +205,71 @@ def main_ragged(args):
         sys.exit(1)
 
 
+def main_walk(args):
+    """FP32 sequence: n = 16384, d = 16, RBF, sigma2 = 1e-2, 20 systems on a
+    log-ell random walk (step 0.05), fixed b, k = 32, L = 48, tol 1e-6.  One
+    step = one system: set_hyper (the operands follow ell), AW for the new
+    operator (a block product), the deflated solve and the refresh.  The same
+    systems are then solved by plain CG.  Matvecs count the block product."""
+    import torch
+
+    import paper_1706_00241_amd as dcg
+    import workloads
+
+    dcg.load()
+    w = workloads.fp32_walk()
+    n = w["X"].shape[0]
+    dev = torch.device("cuda:0")
+    X = torch.as_tensor(w["X"], device=dev)
+    b = torch.as_tensor(w["b"], device=dev)
+    op = dcg.Operator(X, w["kernel"], w["ells"][0], w["s2"], w["sigma2"], prec=dcg.PREC_FP32)
+    items, _ = op.tune(reps=5)
+    ws = dcg.SolveWorkspace(n, dev)
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    systems = len(w["ells"])
+    warm = min(args.warmup, systems - 1)
+
+    def run(rc):
+        rows = []
+        for t, ell in enumerate(w["ells"]):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            op.set_hyper(ell, w["s2"], w["sigma2"])
+            _, st = dcg.solve(op, b, rc=rc, tol=w["tol"], ws=ws, out=x, true_residual=True)
+            torch.cuda.synchronize()
+            rows.append((st["iters"], st["matvecs"], (time.perf_counter() - t0) * 1e3,
+                         st["rel_res_true"], st["status"]))
+        return rows
+
+    rows = run(dcg.Recycle(n, w["k"], w["L"], device=dev))
+    for t, r in enumerate(rows):
+        print(f"system {t}: {r[0]} its, {r[1]} matvecs, {r[2]:.2f} ms, res {r[3]:.2e}",
+              file=sys.stderr, flush=True)
+    timed = rows[warm:]
+    ms = sum(r[2] for r in timed) / len(timed)
+    out = {
+        "metric": "ms per solve, FP32 deflated CG on a log-ell random walk, n=16384, 1 GPU",
+        "value": round(ms, 3), "unit": "ms/solve", "n_gpus": 1,
+        "steps": len(timed), "warmup": warm, "ms_per_step": round(ms, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32 points (three bf16 terms on bf16 MFMA), f32 kernel values, f64 CG",
+        "data": "synthetic",
+        "config": {"workload": "fp32_walk: n=16384 d=16 X~N(0,1) RBF sigma2=1e-2, 20 systems, "
+                               "log-ell walk step 0.05, k=32 L=48 tol 1e-6", "sweep_items": items},
+        "matvecs_per_solve": round(sum(r[1] for r in timed) / len(timed), 1),
+        "iters_per_solve": round(sum(r[0] for r in timed) / len(timed), 1),
+        "failed_solves": sum(1 for r in rows if r[4] != 0),
+    }
+    if not args.no_plain:
+        prow = run(None)[warm:]
+        out["plain_ms_per_solve"] = round(sum(r[2] for r in prow) / len(prow), 3)
+        out["plain_matvecs_per_solve"] = round(sum(r[1] for r in prow) / len(prow), 1)
+        out["speedup_vs_plain"] = round(out["plain_ms_per_solve"] / ms, 3)
+    print(json.dumps(out), flush=True)
+    if out["failed_solves"]:
+        sys.exit(1)
+
+
 def main_gp(args):
     """Differentiation form: GP hyperparameter optimisation, n = 32768, d = 16,
     RBF, FP32 operator, Adam (lr 0.05) on theta = (log ell, log s2, log
@@ -301,6 +366,8 @@ def main():
         return main_ragged(args)
     if args.workload == "gp_hyper":
         return main_gp(args)
+    if args.workload == "fp32_walk":
+        return main_walk(args)
     import numpy as np
     import torch
 
