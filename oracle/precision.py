@@ -18,13 +18,17 @@ the number-format definitions:
   mantissa bits).  Rounding is to nearest, ties to even, applied to the FP64
   value directly (one rounding, never via fp32 first).
 * bf16x2: the pair hi + lo with hi = bf16(x), lo = bf16(x - hi).
+* fp16: IEEE-754 binary16 (5 exponent bits, 10 stored mantissa bits,
+  subnormals below 2^-14), round to nearest, ties to even, applied to the
+  FP64 value directly.
 """
 
 import math
 
 import numpy as np
 
-PREC_FP32, PREC_BF16, PREC_BF16X2, PREC_FP64 = 0, 1, 2, 3
+PREC_FP32, PREC_BF16, PREC_BF16X2, PREC_FP64, PREC_FP16 = 0, 1, 2, 3, 4
+FP16_MAX = 65504.0
 RBF, MATERN32, MATERN52 = 0, 1, 2
 LOG2E = 1.4426950408889634     # the double nearest log2(e)
 
@@ -81,13 +85,36 @@ def round_bf16x2(x):
     return hi + lo
 
 
+def round_fp16(x):
+    """Round FP64 values to the nearest binary16 (ties to even), as FP64.
+
+    For |x| >= 2^-14 (normal range) the spacing is 2^(e-10) with
+    2^e <= |x| < 2^(e+1); below it the spacing is 2^-24 (subnormals).  Scale
+    so that the spacing is 1, round half-to-even (numpy.rint), scale back.
+    Values whose rounding exceeds the largest finite binary16 are rejected.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    nz = x != 0
+    ax = np.abs(x[nz])
+    _, fe = np.frexp(ax)                 # ax = m 2^fe with 0.5 <= m < 1
+    e = np.maximum(fe - 1.0, -14.0)      # binade exponent, clamped at the subnormals
+    q = np.rint(np.ldexp(ax, (10 - e).astype(int)))
+    val = np.ldexp(q, (e - 10).astype(int))
+    if np.any(val > FP16_MAX):
+        raise ValueError("values beyond the binary16 range")
+    out[nz] = np.sign(x[nz]) * val
+    return out
+
+
 def round_points(X, prec, kernel, ell):
     """The points the operator of precision ``prec`` represents, as FP64:
     rnd(c X) / c with c = point_scale(kernel, ell) (X itself for FP64)."""
     X = np.asarray(X, dtype=np.float64)
     if prec == PREC_FP64:
         return X.copy()
-    rnd = {PREC_FP32: round_fp32, PREC_BF16: round_bf16, PREC_BF16X2: round_bf16x2}.get(prec)
+    rnd = {PREC_FP32: round_fp32, PREC_BF16: round_bf16, PREC_BF16X2: round_bf16x2,
+           PREC_FP16: round_fp16}.get(prec)
     if rnd is None:
         raise ValueError(f"unknown precision {prec}")
     c = point_scale(kernel, ell)

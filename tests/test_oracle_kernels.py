@@ -185,3 +185,22 @@ def test_fp32_values_are_three_exact_bf16_terms():
     assert np.all(np.abs(m) <= 2.0 ** -8 * np.abs(x))
     assert np.all(np.abs(l) <= 2.0 ** -17 * np.abs(x))
     assert np.all(np.abs(m * l) <= 2.0 ** -25 * x * x)
+
+
+def test_round_fp16_matches_python_half_packing():
+    """binary16 rounding against Python's own half-precision packing (struct
+    format 'e', round half to even from the double), over normal and
+    subnormal magnitudes, exact ties and the largest finite value."""
+    import struct
+    g = np.random.default_rng(21)
+    x = np.concatenate([g.standard_normal(20000) * s for s in (1e-6, 1e-3, 1.0, 30.0, 3000.0)]
+                       + [np.ldexp(np.arange(1, 2049, dtype=np.float64) + 0.5, -11),   # ties
+                          np.ldexp(np.arange(0, 1024, dtype=np.float64) + 0.5, -24),   # subnormal ties
+                          np.array([65504.0, -65504.0, 2.0 ** -14, 2.0 ** -24, 0.0])])
+    ref = np.array([struct.unpack("<e", struct.pack("<e", v))[0] for v in x])
+    np.testing.assert_array_equal(P.round_fp16(x), ref)
+    with pytest.raises(ValueError):
+        P.round_fp16(np.array([65520.0]))
+    c = P.point_scale(P.MATERN52, 0.7)
+    np.testing.assert_allclose(P.round_points(np.array([[0.3]]), P.PREC_FP16, P.MATERN52, 0.7) * c,
+                               P.round_fp16(np.array([[0.3 * c]])), rtol=2e-16)
