@@ -56,7 +56,7 @@ def parse():
                     help="ell = 0.5 as written (an almost diagonal operator)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--prec", choices=["bf16", "bf16x2", "fp32"], default="bf16",
+    ap.add_argument("--prec", choices=["bf16", "bf16x2", "fp32", "fp16"], default="bf16",
                     help="operator precision of the inner solves")
     ap.add_argument("--inner-tol", type=float, default=1e-2,
                     help="relative tolerance of each inner (low-precision) solve; the bf16 "
@@ -387,7 +387,8 @@ def main():
     dev = torch.device("cuda:0")
     X = torch.as_tensor(w["X"], device=dev)
     b = torch.as_tensor(w["b"], device=dev)
-    prec = {"bf16": dcg.PREC_BF16, "bf16x2": dcg.PREC_BF16X2, "fp32": dcg.PREC_FP32}[args.prec]
+    prec = {"bf16": dcg.PREC_BF16, "bf16x2": dcg.PREC_BF16X2, "fp32": dcg.PREC_FP32,
+            "fp16": dcg.PREC_FP16}[args.prec]
     op = dcg.Operator(X, w["kernel"], w["ell"], 1.0, w["sigma2s"][0], prec=prec)
     items = 2048
     if args.sweep_items > 0:
@@ -450,7 +451,10 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16 MFMA distances, f32 kernel values, f64 CG",
+        "dtype": {"bf16": "bf16", "bf16x2": "split bf16", "fp16": "fp16",
+                  "fp32": "fp32 points (three bf16 terms on bf16 MFMA)"}[args.prec]
+                 + (" MFMA distances" if args.prec != "fp32" else "")
+                 + ", f32 kernel values, f64 CG",
         "data": "synthetic",
         "config": {"workload": ("bf16_shift" + ("_literal" if args.literal else "")
                                 + f": n={n} d={d} X~U[-1,1] matern52 ell={w['ell']:.4f} "

@@ -55,7 +55,11 @@ enum dcg_prec {
   DCG_PREC_BF16X2 = 2,  /* points as a pair hi + lo of bf16 (16 significant
                            bits); the distance GEMM takes the four bf16
                            products hi.hi, hi.lo, lo.hi, lo.lo on MFMA         */
-  DCG_PREC_FP64 = 3     /* exact FP64 operator                                 */
+  DCG_PREC_FP64 = 3,    /* exact FP64 operator                                 */
+  DCG_PREC_FP16 = 4     /* fp16 points (11 significant bits), fp16 MFMA; the
+                           scaled points and their squared norms must stay
+                           inside the fp16 range (dcg_create_operator and
+                           dcg_set_hyper return DCG_E_ARG otherwise)          */
 };
 
 enum dcg_status {
@@ -137,17 +141,21 @@ typedef struct {
 /* Bytes of workspace the operator needs (256-byte aligned base required). */
 size_t dcg_operator_workspace_bytes(int64_t n, int64_t d, int prec);
 
-/* Round X to prec, store it with its squared norms in the workspace, and
- * keep (kernel, ell, s2, sigma2).  X: device FP64 row-major n x d, read
- * only here (a copy is kept).  stream: a hipStream_t (NULL = default).
- * Requires n >= 1, 1 <= d <= 64, ell > 0, s2 > 0, sigma2 >= 0.
- * Returns DCG_E_NONFINITE if X holds NaN/Inf. */
+/* Scale X by the kernel's lengthscale factor, round it to prec, store it
+ * with its squared norms in the workspace, and keep (kernel, ell, s2,
+ * sigma2).  X: device FP64 row-major n x d, read only here (a copy is
+ * kept).  stream: a hipStream_t (NULL = default).  Requires n >= 1,
+ * 1 <= d <= 64, ell > 0, s2 > 0, sigma2 >= 0.  Returns DCG_E_NONFINITE if
+ * X holds NaN/Inf, DCG_E_ARG if fp16 operands would leave the fp16 range. */
 int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel,
                         double ell, double s2, double sigma2, int prec,
                         void *workspace, size_t ws_bytes, void *stream,
                         dcg_op_t *out);
 
-/* Change the hyperparameters (the next system of a sequence). */
+/* Change the hyperparameters (the next system of a sequence).  A new ell
+ * rebuilds the operands on the operator's stream; for fp16 operands that
+ * leave the fp16 range the call returns DCG_E_ARG and keeps the previous
+ * hyperparameters. */
 int dcg_set_hyper(dcg_op_t op, double ell, double s2, double sigma2);
 
 /* Y = A V with the operator's compute precision; V, Y device FP64

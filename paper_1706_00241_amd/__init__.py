@@ -24,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdcg.so")
 
 RBF, MATERN32, MATERN52 = 0, 1, 2
-PREC_FP32, PREC_BF16, PREC_BF16X2, PREC_FP64 = 0, 1, 2, 3
+PREC_FP32, PREC_BF16, PREC_BF16X2, PREC_FP64, PREC_FP16 = 0, 1, 2, 3, 4
 STATUS = {0: "ok", 1: "not converged", -1: "invalid argument", -2: "not SPD",
           -3: "non-finite", -4: "W rank deficient", -5: "HIP error",
           -6: "workspace"}

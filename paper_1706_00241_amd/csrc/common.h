@@ -45,8 +45,10 @@ struct Carve {
 //                 above 2^-24 (hh, hm, mh, hl, lh, mm) go through bf16 MFMA,
 //                 and row sums carry FP64 accumulators across block pairs;
 //   kOpF32        FP32 MFMA operands (the FP32 operator for d > 33, where
-//                 6d + 6 terms need more than 13 bf16 K-steps).
-enum OperandKind { kOpBf16 = 0, kOpBf16Acc64 = 1, kOpF32 = 2 };
+//                 6d + 6 terms need more than 13 bf16 K-steps);
+//   kOpF16        fp16 points (11 significant bits) on fp16 MFMA, FP32 row
+//                 sums within a work item as for bf16.
+enum OperandKind { kOpBf16 = 0, kOpBf16Acc64 = 1, kOpF32 = 2, kOpF16 = 3 };
 
 struct Geometry {
   int64_t n, n_pad;  // n_pad: multiple of the block size of both schedules
@@ -99,6 +101,7 @@ struct dcg_operator_s {
   int sweep_items;       // work-item target of the low-precision pair sweep
   int exact_items;       // work-item target of the FP64 pair sweep
   double *x64;           // the points, FP64, n_pad x d row-major (operand source)
+  int *flag;             // device flag word: operand preparation problems
   double *x64r, *x64c;   // FP64 augmented operands of the exact operator
   double *vin64;         // staged FP64 input vector, n_pad
   double *part64;        // partial sums of the FP64 sweep

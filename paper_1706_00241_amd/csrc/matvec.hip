@@ -31,6 +31,7 @@
 namespace dcg {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 
 static int bf16_bucket(int ks) {
@@ -57,7 +58,8 @@ Geometry make_geometry(int64_t n, int d, int prec) {
   if (prec == DCG_PREC_FP64) {
     g.ksteps = 0;  // the exact FP64 product needs no MFMA operands
     g.kstride = 0;
-  } else if (prec == DCG_PREC_BF16) {
+  } else if (prec == DCG_PREC_BF16 || prec == DCG_PREC_FP16) {
+    g.opk = (prec == DCG_PREC_FP16) ? kOpF16 : kOpBf16;
     g.ksteps = (d + 6 + 15) / 16;
     g.kstride = 16 * g.ksteps;
   } else if (prec == DCG_PREC_BF16X2) {
@@ -123,25 +125,21 @@ __device__ __forceinline__ float kval(float r2) {
   }
 }
 
-template <bool BF16, int KS>
-struct Operand;
-
-template <int KS>
-struct Operand<true, KS> {
-  bf16x8 v[KS];
+// Operand registers of one tile row: 16-bit terms (bf16 or fp16 bit
+// patterns, 8 per lane per K-step) or FP32 values.
+template <int OPK, int KS>
+struct Operand {
+  uint4 v[KS];
   __device__ __forceinline__ void load(const void *base, int64_t point, int kstride, int lh) {
     const uint4 *p = reinterpret_cast<const uint4 *>(
         static_cast<const uint16_t *>(base) + point * kstride + 8 * lh);
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      uint4 u = p[2 * s];
-      v[s] = __builtin_bit_cast(bf16x8, u);
-    }
+    for (int s = 0; s < KS; ++s) v[s] = p[2 * s];
   }
 };
 
 template <int KS>
-struct Operand<false, KS> {
+struct Operand<kOpF32, KS> {
   static constexpr int KS4 = (KS + 3) / 4;
   float v[KS4 * 4];
   __device__ __forceinline__ void load(const void *base, int64_t point, int kstride, int lh) {
@@ -158,15 +156,19 @@ struct Operand<false, KS> {
   }
 };
 
-template <bool BF16, int KS>
-__device__ __forceinline__ f32x16 tile_r2(const Operand<BF16, KS> &a, const Operand<BF16, KS> &b) {
+template <int OPK, int KS>
+__device__ __forceinline__ f32x16 tile_r2(const Operand<OPK, KS> &a, const Operand<OPK, KS> &b) {
   f32x16 acc = {};
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
-    if constexpr (BF16)
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v[s], b.v[s], acc, 0, 0, 0);
-    else
+    if constexpr (OPK == kOpF32)
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[s], b.v[s], acc, 0, 0, 0);
+    else if constexpr (OPK == kOpF16)
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a.v[s]),
+                                                   __builtin_bit_cast(f16x8, b.v[s]), acc, 0, 0, 0);
+    else
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a.v[s]),
+                                                    __builtin_bit_cast(bf16x8, b.v[s]), acc, 0, 0, 0);
   }
   return acc;
 }
@@ -174,7 +176,6 @@ __device__ __forceinline__ f32x16 tile_r2(const Operand<BF16, KS> &a, const Oper
 
 template <int KERN, int KS, int MV, int OPK>
 __device__ __forceinline__ void symv_body(const SymvArgs &A, const int64_t item) {
-  constexpr bool BF16 = OPK != kOpF32;
   constexpr int TR = sweep_tile_rows(MV, OPK, KS);
   constexpr int BLK = 4 * 32 * TR;
   constexpr int NCT = BLK / 32;
@@ -200,8 +201,8 @@ __device__ __forceinline__ void symv_body(const SymvArgs &A, const int64_t item)
   // pairs, and dropping the FP64 accumulators frees the registers for two
   // tile rows per wave and three waves per SIMD.  Work items are summed in
   // FP64 either way.
-  constexpr bool ACC64 = (MV == 1) && OPK != kOpBf16;
-  Operand<BF16, KS> ra[TR];
+  constexpr bool ACC64 = (MV == 1) && (OPK == kOpBf16Acc64 || OPK == kOpF32);
+  Operand<OPK, KS> ra[TR];
   float pi[MV][TR][16];
   float accr[MV][TR][16];
   double acc64[ACC64 ? MV : 1][TR][16];
@@ -227,7 +228,7 @@ __device__ __forceinline__ void symv_body(const SymvArgs &A, const int64_t item)
     return int64_t(J) * BLK + 32 * (t % NCT);
   };
 
-  Operand<BF16, KS> cb, cbn;
+  Operand<OPK, KS> cb, cbn;
   float pj[MV], pjn[MV];
   if (tiles > 0) {
     const int64_t cb0 = colbase_of(0);
@@ -256,7 +257,7 @@ __device__ __forceinline__ void symv_body(const SymvArgs &A, const int64_t item)
     for (int m = 0; m < MV; ++m) cs[m] = 0.0f;
 #pragma unroll
     for (int tr = 0; tr < TR; ++tr) {
-      f32x16 r2 = tile_r2<BF16, KS>(ra[tr], cb);
+      f32x16 r2 = tile_r2<OPK, KS>(ra[tr], cb);
       if constexpr (DG) {
         if (ct == w * TR + tr) {
           // the exact diagonal: distance zero by definition
@@ -424,7 +425,7 @@ static int dispatch_bf16(int ks, const SymvArgs &a, int64_t grid, hipStream_t s)
     case 9: launch_symv<KERN, 9, MV, OPK>(a, grid, s); return 0;
     case 13: launch_symv<KERN, 13, MV, OPK>(a, grid, s); return 0;
     case 17:
-      if constexpr (OPK == kOpBf16) {
+      if constexpr (OPK == kOpBf16 || OPK == kOpF16) {
         launch_symv<KERN, 17, MV, OPK>(a, grid, s);
         return 0;
       }
@@ -438,6 +439,7 @@ static int dispatch_ks(const dcg_operator_s *op, const SymvArgs &a, int64_t grid
   hipStream_t s = op->stream;
   if (op->g.opk == kOpBf16) return dispatch_bf16<KERN, MV, kOpBf16>(ks, a, grid, s);
   if (op->g.opk == kOpBf16Acc64) return dispatch_bf16<KERN, MV, kOpBf16Acc64>(ks, a, grid, s);
+  if (op->g.opk == kOpF16) return dispatch_bf16<KERN, MV, kOpF16>(ks, a, grid, s);
   switch (ks) {
     case 5: launch_symv<KERN, 5, MV, kOpF32>(a, grid, s); return 0;
     case 9: launch_symv<KERN, 9, MV, kOpF32>(a, grid, s); return 0;
@@ -473,7 +475,7 @@ SymvArgs symv_args(const dcg_operator_s *op, int mv, const float *vin, const int
 
 // The batched sweep is built for the two-tile-row single-vector kernels.
 bool symv_batched_supported(int opk, int ksteps) {
-  if (opk == kOpBf16 || opk == kOpBf16Acc64)
+  if (opk == kOpBf16 || opk == kOpBf16Acc64 || opk == kOpF16)
     return (ksteps >= 1 && ksteps <= 5) || ksteps == 7 || ksteps == 9;
   if (opk == kOpF32) return ksteps == 5 || ksteps == 9 || ksteps == 13 || ksteps == 17;
   return false;
@@ -502,6 +504,8 @@ int launch_symv_batched(const BatchItem *d_items, int count, int64_t total, int 
     launch_batched_bf16<kOpBf16>(d_items, count, total, ksteps, s);
   } else if (opk == kOpBf16Acc64) {
     launch_batched_bf16<kOpBf16Acc64>(d_items, count, total, ksteps, s);
+  } else if (opk == kOpF16) {
+    launch_batched_bf16<kOpF16>(d_items, count, total, ksteps, s);
   } else {
     switch (ksteps) {
       case 5: hipLaunchKernelGGL((symv_batched<5, kOpF32>), g, b, 0, s, d_items, count, total); break;

@@ -36,6 +36,47 @@ __device__ __forceinline__ double bf16_to_double(uint16_t h) {
   return static_cast<double>(__uint_as_float(uint32_t(h) << 16));
 }
 
+// Round an FP64 value to binary16, to nearest with ties to even, in one
+// rounding step from the FP64 value (11 significant bits; subnormals below
+// 2^-14, spacing 2^-24).  A value that rounds beyond the largest finite
+// binary16 sets *ovf and gives infinity.
+__device__ __forceinline__ uint16_t f16_from_double(double x, int *ovf) {
+  const uint64_t u = static_cast<uint64_t>(__double_as_longlong(x));
+  const uint32_t sign = static_cast<uint32_t>(u >> 63) << 15;
+  const uint64_t mag = u & 0x7fffffffffffffffull;
+  const int e = static_cast<int>(mag >> 52) - 1023;
+  if (mag == 0 || e < -25) return static_cast<uint16_t>(sign);   // below half of 2^-24
+  if (e > 15) {
+    *ovf = 1;
+    return static_cast<uint16_t>(sign | 0x7c00);
+  }
+  const uint64_t m = (mag & ((1ull << 52) - 1)) | (1ull << 52);   // 53-bit significand
+  // keep 11 bits (normal) or fewer (subnormal: spacing fixed at 2^-24)
+  const int shift = (e >= -14) ? 42 : 42 + (-14 - e);
+  uint64_t q = m >> shift;
+  const uint64_t rem = m & ((1ull << shift) - 1);
+  const uint64_t half = 1ull << (shift - 1);
+  if (rem > half || (rem == half && (q & 1))) q += 1;
+  if (e < -14) return static_cast<uint16_t>(sign | q);   // q <= 1024: 1024 is 2^-14 itself
+  uint32_t eb = static_cast<uint32_t>(e + 15);
+  if (q == 2048) {
+    q = 1024;
+    eb += 1;
+  }
+  if (eb >= 31) {
+    *ovf = 1;
+    return static_cast<uint16_t>(sign | 0x7c00);
+  }
+  return static_cast<uint16_t>(sign | (eb << 10) | (q & 0x3ff));
+}
+
+__device__ __forceinline__ double f16_to_double(uint16_t h) {
+  const int eb = (h >> 10) & 0x1f;
+  const double m = static_cast<double>(h & 0x3ff);
+  const double v = (eb == 0) ? std::ldexp(m, -24) : std::ldexp(m + 1024.0, eb - 25);
+  return (h & 0x8000) ? -v : v;
+}
+
 __global__ __launch_bounds__(256) void check_finite(const double *X, int64_t count, int *flag) {
   for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < count;
        e += int64_t(gridDim.x) * 256)
@@ -86,7 +127,7 @@ __global__ __launch_bounds__(256) void prepare_exact(const double *x64, int64_t 
 __global__ __launch_bounds__(256) void prepare_lowprec(const double *x64, int64_t n,
                                                        int64_t n_pad, int d, int prec, int opk,
                                                        int kstride, double scale, void *xr,
-                                                       void *xc) {
+                                                       void *xc, int *flag) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n_pad) return;
   const bool real = i < n;
@@ -141,6 +182,29 @@ __global__ __launch_bounds__(256) void prepare_lowprec(const double *x64, int64_
     c[d + 0] = ah;  c[d + 1] = am;  c[d + 2] = al;
     c[d + 3] = one; c[d + 4] = one; c[d + 5] = one;
     for (int t = d + 6; t < kstride; ++t) r[t] = c[t] = 0;
+  } else if (prec == DCG_PREC_FP16) {
+    // as bf16, with binary16 terms (the same column layout)
+    uint16_t *r = static_cast<uint16_t *>(xr) + i * kstride;
+    uint16_t *c = static_cast<uint16_t *>(xc) + i * kstride;
+    int ovf = 0;
+    for (int t = 0; t < d; ++t) {
+      const uint16_t h = real ? f16_from_double(scale * x64[i * d + t], &ovf) : uint16_t(0);
+      const double xv = f16_to_double(h);
+      a += xv * xv;
+      c[t] = h;
+      r[t] = f16_from_double(-2.0 * xv, &ovf);   // exact unless it overflows
+    }
+    const uint16_t ah = f16_from_double(a, &ovf);
+    const double rem1 = a - f16_to_double(ah);
+    const uint16_t am = f16_from_double(rem1, &ovf);
+    const uint16_t al = f16_from_double(rem1 - f16_to_double(am), &ovf);
+    const uint16_t one = 0x3C00;
+    r[d + 0] = one; r[d + 1] = one; r[d + 2] = one;
+    r[d + 3] = ah;  r[d + 4] = am;  r[d + 5] = al;
+    c[d + 0] = ah;  c[d + 1] = am;  c[d + 2] = al;
+    c[d + 3] = one; c[d + 4] = one; c[d + 5] = one;
+    for (int t = d + 6; t < kstride; ++t) r[t] = c[t] = 0;
+    if (ovf) atomicOr(flag, 4);
   } else if (opk == kOpBf16Acc64) {
     // FP32 coordinate x = h + m + l, three bf16 terms (exact for every FP32
     // value); one column per kept pairing (row term, column term): (h,h)
@@ -199,17 +263,29 @@ __global__ __launch_bounds__(256) void prepare_lowprec(const double *x64, int64_
   }
 }
 
-// Both operand sets for the operator's kernel and lengthscale.
+// Both operand sets for the operator's kernel and lengthscale.  fp16
+// operands are checked for overflow (the call then waits for the stream and
+// returns DCG_E_ARG if a scaled point or squared norm left the fp16 range).
 static int launch_prepare(const dcg_operator_s *op) {
   const Geometry &g = op->g;
   const double c = point_scale(op->kernel, op->ell);
   const dim3 grid(static_cast<unsigned>(cdiv(g.n_pad, 256)));
+  const bool check = g.prec == DCG_PREC_FP16;
+  if (check && hipMemsetAsync(op->flag, 0, sizeof(int), op->stream) != hipSuccess) return DCG_E_HIP;
   hipLaunchKernelGGL(prepare_exact, grid, dim3(256), 0, op->stream, op->x64, g.n_pad, g.d,
                      exact_stride(g.d), c, op->x64r, op->x64c);
   if (g.prec != DCG_PREC_FP64)
     hipLaunchKernelGGL(prepare_lowprec, grid, dim3(256), 0, op->stream, op->x64, g.n, g.n_pad,
-                       g.d, g.prec, g.opk, g.kstride, c, op->xr, op->xc);
-  return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
+                       g.d, g.prec, g.opk, g.kstride, c, op->xr, op->xc, op->flag);
+  if (hipGetLastError() != hipSuccess) return DCG_E_HIP;
+  if (check) {
+    int h = 0;
+    if (hipMemcpyAsync(&h, op->flag, sizeof(int), hipMemcpyDeviceToHost, op->stream) != hipSuccess ||
+        hipStreamSynchronize(op->stream) != hipSuccess)
+      return DCG_E_HIP;
+    if (h & 4) return DCG_E_ARG;
+  }
+  return DCG_OK;
 }
 
 // ----------------------------------------------------------- workspace
@@ -294,7 +370,7 @@ extern "C" {
 
 size_t dcg_operator_workspace_bytes(int64_t n, int64_t d, int prec) {
   if (n < 1 || d < 1 || d > kMaxD) return 0;
-  if (prec < DCG_PREC_FP32 || prec > DCG_PREC_FP64) return 0;
+  if (prec < DCG_PREC_FP32 || prec > DCG_PREC_FP16) return 0;
   return op_layout(make_geometry(n, static_cast<int>(d), prec)).total;
 }
 
@@ -305,11 +381,11 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel, doubl
   *out = nullptr;
   if (X == nullptr || n < 1 || d < 1 || d > kMaxD) return DCG_E_ARG;
   if (kernel < DCG_RBF || kernel > DCG_MATERN52) return DCG_E_ARG;
-  if (prec < DCG_PREC_FP32 || prec > DCG_PREC_FP64) return DCG_E_ARG;
+  if (prec < DCG_PREC_FP32 || prec > DCG_PREC_FP16) return DCG_E_ARG;
   if (!(ell > 0.0) || !(s2 > 0.0) || !(sigma2 >= 0.0) || !std::isfinite(ell) ||
       !std::isfinite(s2) || !std::isfinite(sigma2))
     return DCG_E_ARG;
-  if (prec == DCG_PREC_BF16 && d + 6 > 80) return DCG_E_ARG;
+  if ((prec == DCG_PREC_BF16 || prec == DCG_PREC_FP16) && d + 6 > 80) return DCG_E_ARG;
   const Geometry g = make_geometry(n, static_cast<int>(d), prec);
   if (g.ksteps < 0) return DCG_E_ARG;
   const OpLayout L = op_layout(g);
@@ -337,16 +413,17 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel, doubl
   op->vin = reinterpret_cast<float *>(base + L.vin);
   op->part = reinterpret_cast<float *>(base + L.part);
   op->ytmp = reinterpret_cast<double *>(base + L.ytmp);
+  // flag word 0: non-finite input; word 1: operand preparation (fp16 range)
   int *flag = reinterpret_cast<int *>(base + L.flag);
+  op->flag = flag + 1;
   int hflag = 0;
-  bool ok = hipMemsetAsync(flag, 0, sizeof(int), op->stream) == hipSuccess;
+  bool ok = hipMemsetAsync(flag, 0, 2 * sizeof(int), op->stream) == hipSuccess;
   const int64_t count = n * d;
   hipLaunchKernelGGL(check_finite, dim3(static_cast<unsigned>(std::min<int64_t>(1024, cdiv(count, 256)))),
                      dim3(256), 0, op->stream, X, count, flag);
   hipLaunchKernelGGL(copy_points, dim3(static_cast<unsigned>(cdiv(g.n_pad * g.d, 256))), dim3(256),
                      0, op->stream, X, n, g.n_pad, g.d, op->x64);
   ok = ok && hipGetLastError() == hipSuccess;
-  ok = ok && launch_prepare(op) == DCG_OK;
   ok = ok && hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, op->stream) == hipSuccess;
   ok = ok && hipStreamSynchronize(op->stream) == hipSuccess;
   if (!ok) {
@@ -356,6 +433,13 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel, doubl
   if (hflag != 0) {
     delete op;
     return DCG_E_NONFINITE;
+  }
+  int st = launch_prepare(op);
+  if (st == DCG_OK && hipStreamSynchronize(op->stream) != hipSuccess) st = DCG_E_HIP;
+  if (st != DCG_OK) {
+    (void)hipStreamSynchronize(op->stream);
+    delete op;
+    return st;   // DCG_E_ARG: fp16 operands out of range for this lengthscale
   }
   *out = op;
   return DCG_OK;
@@ -367,12 +451,24 @@ int dcg_set_hyper(dcg_op_t op, double ell, double s2, double sigma2) {
       !std::isfinite(s2) || !std::isfinite(sigma2))
     return DCG_E_ARG;
   const bool rescale = ell != op->ell;
+  const double old[3] = {op->ell, op->s2, op->sigma2};
   op->ell = ell;
   op->s2 = s2;
   op->sigma2 = sigma2;
   op->generation += 1;
+  if (!rescale) return DCG_OK;
   // the operands carry the lengthscale (point_scale)
-  return rescale ? launch_prepare(op) : DCG_OK;
+  const int st = launch_prepare(op);
+  if (st == DCG_E_ARG) {
+    // fp16 operands out of range for this lengthscale: keep the previous
+    // hyperparameters and their operands
+    op->ell = old[0];
+    op->s2 = old[1];
+    op->sigma2 = old[2];
+    op->generation += 1;
+    (void)launch_prepare(op);
+  }
+  return st;
 }
 
 int dcg_matvec(dcg_op_t op, const double *V, double *Y, int64_t m) {

@@ -40,6 +40,8 @@ def test_workspace_queries(L):
     assert L.dcg_operator_workspace_bytes(0, 32, 1) == 0
     assert L.dcg_operator_workspace_bytes(100, 65, 1) == 0
     assert L.dcg_operator_workspace_bytes(100, 8, 7) == 0
+    assert L.dcg_operator_workspace_bytes(100, 8, 4) > 0       # fp16
+    assert L.dcg_operator_workspace_bytes(100, 8, 5) == 0
     assert L.dcg_recycle_workspace_bytes(1000, 8, 12) >= 1000 * 20 * 8 * 2
     assert L.dcg_recycle_workspace_bytes(1000, 8, 4) == 0       # L < k
     assert L.dcg_recycle_workspace_bytes(1000, 65, 100) == 0    # k too large

@@ -40,7 +40,7 @@ def _points(n, d, seed, dist="normal"):
     return g.standard_normal((n, d))
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 4])
 @pytest.mark.parametrize("kern", [0, 1, 2])
 @pytest.mark.parametrize("n,d,m", [(1, 3, 1), (200, 3, 1), (777, 8, 2), (1500, 16, 5),
                                    (2500, 32, 1), (600, 33, 3), (300, 1, 1)])
@@ -380,13 +380,15 @@ def test_exact_eigenvector_deflation(lib, prec, sigma2, tol):
     assert np.linalg.norm(b - A @ xn) / np.linalg.norm(b) <= tol + 2 * _floor(op, A, xn, b)
 
 
-def test_refinement_reaches_1e8_bf16(lib):
-    """Precision form at small size: bf16 distances, FP64 refinement to 1e-8."""
+@pytest.mark.parametrize("prec", [1, 4])
+def test_refinement_reaches_1e8_bf16(lib, prec):
+    """Precision form at small size: bf16 (or fp16) distances, FP64
+    refinement to 1e-8."""
     w = workloads.bf16_shift(n=3000)
     X = w["X"]
     A64 = OK.operator(X, w["kernel"], w["ell"], 1.0, w["sigma2s"][0])
     b = w["b"]
-    op = lib.Operator(_dev(X), w["kernel"], w["ell"], 1.0, w["sigma2s"][0], prec=1)
+    op = lib.Operator(_dev(X), w["kernel"], w["ell"], 1.0, w["sigma2s"][0], prec=prec)
     rc = lib.Recycle(3000, 16, 24)
     x, st = lib.solve(op, _dev(b), rc=rc, tol=1e-8, refine=True, inner_tol=1e-4)
     x = _np(x)
@@ -397,6 +399,28 @@ def test_refinement_reaches_1e8_bf16(lib):
     x_ref = np.linalg.solve(A64, b)
     err_A = np.sqrt((x - x_ref) @ A64 @ (x - x_ref) / (x_ref @ A64 @ x_ref))
     assert err_A <= 1e-7
+
+
+def test_fp16_operands_out_of_range(lib):
+    """fp16 operands need the scaled points and their squared norms inside
+    the fp16 range: creation with a lengthscale that breaks it returns
+    DCG_E_ARG, and so does set_hyper, which then keeps the previous
+    hyperparameters (the product is unchanged)."""
+    g = np.random.default_rng(31)
+    X = g.standard_normal((500, 16))
+    with pytest.raises(lib.DcgError) as e:
+        lib.Operator(_dev(X), 0, 1e-3, 1.0, 1e-2, prec=4)
+    assert e.value.status == -1
+    op = lib.Operator(_dev(X), 0, 2.0, 1.0, 1e-2, prec=4)
+    v = _dev(g.standard_normal(500))
+    y0 = op.matvec(v)
+    with pytest.raises(lib.DcgError) as e:
+        op.set_hyper(1e-3, 1.0, 1e-2)
+    assert e.value.status == -1
+    assert torch.equal(op.matvec(v), y0)
+    A = OK.operator(OP.round_points(X, 4, 0, 2.0), 0, 2.0, 1.0, 1e-2)
+    ref = A @ _np(v)
+    assert np.abs(_np(y0) - ref).max() <= 2e-5 * (np.abs(A) @ np.abs(_np(v))).max()
 
 
 @pytest.mark.parametrize("prec,inner_tol", [(1, 1e-2), (1, 1e-1), (0, 1e-3)])
