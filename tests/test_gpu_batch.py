@@ -73,7 +73,7 @@ def _run_both(lib, seqs, prec, k, L, tol, precs=None, steps=None):
     return out
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3, 4])
 def test_batched_equals_single_bitwise(lib, prec):
     """Ragged RBF / Matern-3/2 systems of 150..2500 rows, d = 8, each with
     its own recycled basis over a 3-step sequence."""
@@ -90,13 +90,14 @@ def test_batched_equals_single_bitwise(lib, prec):
 
 def test_batched_mixed_layouts_bitwise(lib):
     """One batch holding every operand layout: bf16 and bf16x2 systems share
-    one batched sweep group when their MFMA K steps agree, FP32 systems form
-    their own group, and FP64 systems or wide bf16x2 operands (more K steps
-    than the batched kernels take) are swept one by one in the same step."""
+    one batched sweep group when their MFMA K steps agree, FP32 and fp16
+    systems form groups of their own, and FP64 systems or wide bf16x2
+    operands (more K steps than the batched kernels take) are swept one by
+    one in the same step."""
     g = np.random.default_rng(workloads.SEED_BASE + 77)
     seqs = []
-    shapes = [(700, 8), (1300, 16), (400, 24), (900, 8), (1100, 27), (257, 5), (1600, 8)]
-    precs = [1, 2, 2, 0, 1, 3, 1]
+    shapes = [(700, 8), (1300, 16), (400, 24), (900, 8), (1100, 27), (257, 5), (1600, 8), (800, 8)]
+    precs = [1, 2, 2, 0, 1, 3, 1, 4]
     for s, (n, d) in enumerate(shapes):
         X = g.standard_normal((n, d))
         ell = workloads.median_distance(X)
