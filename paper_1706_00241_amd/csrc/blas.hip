@@ -146,7 +146,12 @@ __device__ __forceinline__ void cg_matvec_finish_body(const CgArgs &a, const uns
       a.q[i] = qi;
       pq += pi * qi;
       if (a.Z != nullptr && j < a.L) {
-        a.Z[int64_t(a.koff + j) * a.n + i] = pi;
+        // store the direction the product was formed from: the low-precision
+        // sweep multiplies the FP32 copy of p, so that copy (exact in FP64)
+        // is the column of Z whose product is q; AZ then matches A~ Z to the
+        // sweep's own evaluation error, and so does AW' = (AZ) U
+        a.Z[int64_t(a.koff + j) * a.n + i] =
+            (a.qdirect != nullptr) ? pi : static_cast<double>(a.p32[i]);
         a.AZ[int64_t(a.koff + j) * a.n + i] = qi;
       }
     }
