@@ -128,6 +128,7 @@ void enqueue_tsgemm_tn(hipStream_t s, const double *A, const double *B, int64_t 
 void enqueue_ts_times_small(hipStream_t s, const double *X, int64_t n, int m, const double *U,
                             int ldu, int kout, double *Y);
 void enqueue_block_axpy(hipStream_t s, double *Y, const double *X, double alpha, int64_t count);
+void enqueue_round_to_fp32(hipStream_t s, double *Y, int64_t count);
 void enqueue_small_spd_inverse(hipStream_t s, const double *M, int k, double *Minv, double *work,
                                int *info);
 void enqueue_harmonic_ritz(hipStream_t s, const double *F, const double *G, int m, int k,

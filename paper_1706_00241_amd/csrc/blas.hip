@@ -589,6 +589,12 @@ __global__ __launch_bounds__(256) void block_axpy(double *Y, const double *X, do
   if (e < count) Y[e] += alpha * X[e];
 }
 
+// Y = fp32(Y) elementwise, in place.
+__global__ __launch_bounds__(256) void round_to_fp32(double *Y, int64_t count) {
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e < count) Y[e] = static_cast<double>(static_cast<float>(Y[e]));
+}
+
 // Symmetrise M (k x k, row-major), Cholesky M = R R^T, Minv = M^{-1}.
 // One block; info = 0 on success, 1 if a pivot is not positive.
 __global__ __launch_bounds__(256) void small_spd_inverse(const double *Min, int k, double *Minv,
@@ -671,6 +677,12 @@ void enqueue_block_axpy(hipStream_t s, double *Y, const double *X, double alpha,
   if (count <= 0) return;
   hipLaunchKernelGGL(block_axpy, dim3(static_cast<unsigned>(cdiv(count, 256))), dim3(256), 0, s, Y,
                      X, alpha, count);
+}
+
+void enqueue_round_to_fp32(hipStream_t s, double *Y, int64_t count) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(round_to_fp32, dim3(static_cast<unsigned>(cdiv(count, 256))), dim3(256), 0, s,
+                     Y, count);
 }
 
 void enqueue_small_spd_inverse(hipStream_t s, const double *M, int k, double *Minv, double *work,

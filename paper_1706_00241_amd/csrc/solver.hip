@@ -135,6 +135,10 @@ static int refresh_AW(dcg_operator_s *op, dcg_recycle_s *rc, int *matvecs) {
     // only the diagonal shift changed: A_new W = A_old W + (s_new - s_old) W
     enqueue_block_axpy(op->stream, rc->AZ, rc->Z, op->sigma2 - rc->aw_sigma2, n * k);
   } else {
+    // the low-precision sweep multiplies the FP32 copy of W: make W that
+    // copy (it is only a basis), so that AW is A~ W to the sweep's
+    // evaluation error rather than to W's rounding
+    if (op->g.prec != DCG_PREC_FP64) enqueue_round_to_fp32(op->stream, rc->Z, n * k);
     const int st = matvec_lowprec(op, rc->Z, rc->AZ, k);
     if (st != DCG_OK) return st;
     *matvecs += k;
