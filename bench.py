@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--prec", choices=["bf16", "bf16x2", "fp32", "fp16"], default="bf16",
                     help="operator precision of the inner solves")
-    ap.add_argument("--inner-tol", type=float, default=1e-2,
+    ap.add_argument("--inner-tol", type=float, default=2e-2,
                     help="relative tolerance of each inner (low-precision) solve; the bf16 "
                          "operator contracts the refinement error by ~0.1 per step, so "
                          "tighter inner solves only add iterations")
