@@ -21,6 +21,9 @@ sequence   sequences of related systems with the recycled basis carried
 refine     mixed-precision iterative refinement around the deflated solve.
 gp         GP log marginal likelihood, its exact gradient and the Hutchinson
            estimator of its trace term (GP model adaptation, section 1).
+gpc        Laplace-approximation GP classification: the Newton iteration
+           whose restructured systems A = I + H^1/2 K H^1/2 form the
+           paper's own sequence (section 3).
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 against closed forms, brute force on tiny inputs, library routines for
