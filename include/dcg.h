@@ -158,6 +158,17 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel,
  * hyperparameters. */
 int dcg_set_hyper(dcg_op_t op, double ell, double s2, double sigma2);
 
+/* Diagonal scaling of the operator: A = D K D + sigma2 I, the form of the
+ * Laplace-approximation systems of section 3 (Eq. 10, D = H^{1/2}).
+ * D: device FP64 n-vector of finite entries >= 0, copied into the operator
+ * workspace (the caller's buffer is free on return), or NULL to remove the
+ * scaling.  Every product of dcg_matvec, dcg_matvec_exact and dcg_solve then
+ * applies it; the low-precision sweep multiplies fp32(D v).  dcg_solve_block,
+ * dcg_solve_batched and dcg_mll_grad reject a scaled operator (DCG_E_ARG).
+ * A recycled AW is recomputed at the next solve.  Returns DCG_E_NONFINITE
+ * (and leaves the operator unscaled) for a negative or non-finite entry. */
+int dcg_set_diag(dcg_op_t op, const double *D);
+
 /* Y = A V with the operator's compute precision; V, Y device FP64
  * column-major n x m, m >= 1, V and Y must not overlap (Algorithm 1's
  * products A p_j; m > 1 is the block product used for AW). */
@@ -328,6 +339,41 @@ size_t dcg_mll_grad_workspace_bytes(int64_t n);
 int dcg_mll_grad(dcg_op_t op, const double *alpha, const double *U,
                  const double *Z, int64_t P, double *grad3, void *ws,
                  size_t ws_bytes);
+
+/* ------------------------------------------ Laplace GP classification
+ * Newton's method for the mode of the latent function under a GP prior with
+ * the operator's kernel (K = s2 K0) and the logistic likelihood
+ * p(y_i | f_i) = 1 / (1 + exp(-y_i f_i)) (section 3, Eqs. 8-10).  From
+ * f_0 = 0 each step forms, with pi = sigma(f), H = pi (1 - pi), D = H^{1/2}:
+ *   b~ = H f + (y + 1)/2 - pi,  A = I + D K D,  b = D K b~,
+ * solves A z = b with dcg_solve (x_{-1} = 0; W carried over from one step's
+ * system to the next through rc, AW recomputed for each new A), then
+ *   a = b~ - D z,  f = K a,  Psi = sum_i log sigma(y_i f_i) - a^T f / 2,
+ * and stops once Psi grows by less than psi_tol (the paper uses 1).  The
+ * products with K use the FP64 operator when the operator is FP64 or
+ * p->refine > 0, else the operator's precision.
+ *  op          operator without a diagonal scaling (DCG_E_ARG otherwise);
+ *              its sigma2 is not used (the systems have a unit shift) and
+ *              is left as it was.
+ *  y           device FP64 n-vector of labels, each -1 or +1 (DCG_E_ARG
+ *              otherwise).
+ *  rc, p       recycle handle (or NULL: plain CG) and solver parameters, as
+ *              for dcg_solve.
+ *  f, a        device FP64 n-vectors: on exit the last Newton iterate and
+ *              its a (f = K a).
+ *  psi         host array of max_newton + 1 doubles (may be NULL): Psi at
+ *              f_0 and after every step taken.
+ *  newton_steps host: steps taken.  stats: host array of max_newton
+ *              dcg_stats (may be NULL), one per solve.
+ *  ws          dcg_laplace_gpc_workspace_bytes(n) bytes, 256-byte aligned.
+ * Returns DCG_OK when the Psi test stopped the loop, DCG_NOT_CONVERGED after
+ * max_newton steps, or the first error of a solve or product (a solve that
+ * ends DCG_NOT_CONVERGED does not stop the loop). */
+size_t dcg_laplace_gpc_workspace_bytes(int64_t n);
+int dcg_laplace_gpc(dcg_op_t op, const double *y, dcg_recycle_t rc,
+                    const dcg_params *p, int max_newton, double psi_tol,
+                    double *f, double *a, double *psi, int *newton_steps,
+                    dcg_stats *stats, void *ws, size_t ws_bytes);
 
 /* Human-readable name of a status code (static string). */
 const char *dcg_status_string(int status);

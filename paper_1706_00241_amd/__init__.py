@@ -74,6 +74,7 @@ _SIGS = {
                                            ctypes.POINTER(ctypes.c_void_p)]),
     "dcg_set_hyper": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double]),
+    "dcg_set_diag": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "dcg_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
     "dcg_matvec_exact": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_int64]),
@@ -121,6 +122,13 @@ _SIGS = {
                                          ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_size_t]),
+    "dcg_laplace_gpc_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
+    "dcg_laplace_gpc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.POINTER(Params), ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Stats),
+                                       ctypes.c_void_p, ctypes.c_size_t]),
     "dcg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "dcg_version": (ctypes.c_char_p, []),
 }
@@ -227,6 +235,17 @@ class Operator:
         _check(load().dcg_set_hyper(self.handle, float(ell), float(s2), float(sigma2)),
                "dcg_set_hyper")
         self.ell, self.s2, self.sigma2 = float(ell), float(s2), float(sigma2)
+
+    def set_diag(self, D=None):
+        """A = D K D + sigma2 I from now on (D: (n,) nonnegative); None removes it."""
+        torch = _torch()
+        ptr = None
+        if D is not None:
+            self._dsc_src = D.to(device=self.device, dtype=torch.float64).contiguous()
+            ptr = self._dsc_src.data_ptr()
+        with _ordered(self.stream):
+            _check(load().dcg_set_diag(self.handle, ptr), "dcg_set_diag")
+        self._dsc_src = None
 
     def _mv(self, fn, V):
         torch = _torch()
@@ -417,6 +436,39 @@ def solve(op, b, x0=None, rc=None, tol=1e-6, max_iter=0, L=0, select_largest=Tru
 
 def version():
     return load().dcg_version().decode()
+
+
+def laplace_gpc(op, y, rc=None, max_newton=50, psi_tol=1.0, tol=1e-5, max_iter=0, L=0,
+                select_largest=True, check_every=8, refine=False, inner_tol=1e-4,
+                refine_max=20, use_graph=True, ritz_route="auto", extraction="harmonic"):
+    """Laplace GPC mode by Newton's method (section 3, Eqs. 8-10), each
+    system A = I + D K D solved by deflated CG with W carried over through
+    ``rc``.  y: (n,) labels in {-1, +1}.  Returns (f, a, psi list, list of
+    per-solve stats dicts, status)."""
+    torch = _torch()
+    lib = load()
+    y = y.to(device=op.device, dtype=torch.float64).contiguous()
+    f = torch.empty(op.n, dtype=torch.float64, device=op.device)
+    a = torch.empty_like(f)
+    nbytes = lib.dcg_laplace_gpc_workspace_bytes(op.n)
+    ws, ptr, size = _workspace(nbytes, op.device)
+    p = Params(tol=float(tol), max_iter=int(max_iter), L=int(L),
+               select_largest=1 if select_largest else 0, check_every=int(check_every),
+               refine=_refine_mode(refine), inner_tol=float(inner_tol), refine_max=int(refine_max),
+               use_graph=1 if use_graph else 0, true_residual=0, profile=0, refresh_every=0,
+               ritz_route=_ritz_route(ritz_route), extraction=_extraction(extraction))
+    psi = (ctypes.c_double * (max_newton + 1))()
+    stats = (Stats * max_newton)()
+    steps = ctypes.c_int()
+    with _ordered(op.stream):
+        status = lib.dcg_laplace_gpc(op.handle, y.data_ptr(), rc.handle if rc is not None else None,
+                                     ctypes.byref(p), int(max_newton), float(psi_tol),
+                                     f.data_ptr(), a.data_ptr(), psi, ctypes.byref(steps), stats,
+                                     ptr, size)
+    _check(status, "dcg_laplace_gpc")
+    del ws
+    k = steps.value
+    return f, a, list(psi[:k + 1]), [stats[i].as_dict() for i in range(k)], status
 
 
 def solve_block(op, B, rc=None, tol=1e-6, max_iter=0, check_every=8, out=None):

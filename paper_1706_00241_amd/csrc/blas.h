@@ -31,6 +31,7 @@ struct ReduceArgs {
   int64_t n, n_pad;
   int nchunk, dmax, blk, nb, mv;
   double s2, sigma2;
+  const double *dsc; // diagonal scaling D (A = D K D + sigma2 I), or null
   const double *V;   // n x mv (ld n)
   double *Y;         // n x mv (ld n)
 };
@@ -116,7 +117,8 @@ __global__ void init_residual(const double *b, const double *Ax, double *x, doub
 __global__ void defl_start(double *x, double *t, const double *W, const double *cvec, int64_t n,
                            int k);
 __global__ void init_direction(const double *r, const double *W, const double *mu, int64_t n,
-                               int64_t n_pad, int k, double *p, float *p32, double *part,
+                               int64_t n_pad, int k, const double *dsc, double *p, float *p32,
+                               double *part,
                                unsigned *counter, SolveState *S, double tol, double *hist_res);
 
 __global__ void residual_norms(const double *b, const double *Ax, int64_t n, double *out,

@@ -142,7 +142,9 @@ __device__ __forceinline__ void cg_matvec_finish_body(const CgArgs &a, const uns
     if (sg == 0 && i < a.n) {
       const double tot = (seg[0][r] + seg[1][r]) + (seg[2][r] + seg[3][r]);
       const double pi = a.p[i];
-      const double qi = (a.qdirect != nullptr) ? tot : fma(a.red.s2, tot, a.red.sigma2 * pi);
+      const double di = (a.red.dsc != nullptr) ? a.red.dsc[i] : 1.0;
+      const double qi =
+          (a.qdirect != nullptr) ? tot : fma(a.red.s2 * di, tot, a.red.sigma2 * pi);
       a.q[i] = qi;
       pq += pi * qi;
       if (a.Z != nullptr && j < a.L) {
@@ -150,8 +152,14 @@ __device__ __forceinline__ void cg_matvec_finish_body(const CgArgs &a, const uns
         // sweep multiplies the FP32 copy of p, so that copy (exact in FP64)
         // is the column of Z whose product is q; AZ then matches A~ Z to the
         // sweep's own evaluation error, and so does AW' = (AZ) U
-        a.Z[int64_t(a.koff + j) * a.n + i] =
-            (a.qdirect != nullptr) ? pi : static_cast<double>(a.p32[i]);
+        // (with a diagonal scaling the sweep multiplied fp32(d p): store
+        // that copy divided by d, whose scaled product the sweep formed)
+        double zi = pi;
+        if (a.qdirect == nullptr) {
+          zi = static_cast<double>(a.p32[i]);
+          if (a.red.dsc != nullptr) zi = (di != 0.0) ? zi / di : pi;
+        }
+        a.Z[int64_t(a.koff + j) * a.n + i] = zi;
         a.AZ[int64_t(a.koff + j) * a.n + i] = qi;
       }
     }
@@ -353,7 +361,7 @@ __device__ __forceinline__ void cg_update_p_body(const CgArgs &a, const unsigned
   a.x[i] = xn;
   const double s = ri + S->beta * pi - wmu;
   a.p[i] = s;
-  a.p32[i] = static_cast<float>(s);
+  a.p32[i] = static_cast<float>((a.red.dsc != nullptr) ? a.red.dsc[i] * s : s);
 }
 
 // Kernels: one solve (arguments by value), or many columns / systems at once
@@ -454,7 +462,8 @@ __global__ __launch_bounds__(256) void init_residual(const double *b, const doub
 // p_0 = r_0 - W mu_0, rho = r_0^T r_0, FP32 copy of p (padded with zeros).
 __global__ __launch_bounds__(256) void init_direction(const double *r, const double *W,
                                                       const double *mu, int64_t n, int64_t n_pad,
-                                                      int k, double *p, float *p32, double *part,
+                                                      int k, const double *dsc, double *p,
+                                                      float *p32, double *part,
                                                       unsigned *counter, SolveState *S,
                                                       double tol, double *hist_res) {
   __shared__ double lds[8];
@@ -469,7 +478,7 @@ __global__ __launch_bounds__(256) void init_direction(const double *r, const dou
       double s = ri;
       for (int c = 0; c < k; ++c) s -= W[int64_t(c) * n + i] * mm[c];
       p[i] = s;
-      p32[i] = static_cast<float>(s);
+      p32[i] = static_cast<float>((dsc != nullptr) ? dsc[i] * s : s);
       rr += ri * ri;
     } else {
       p32[i] = 0.0f;

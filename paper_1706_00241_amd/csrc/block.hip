@@ -131,6 +131,7 @@ int dcg_solve_block(dcg_op_t op, const double *B, double *X, int64_t m, dcg_recy
   if (st == nullptr) st = &local;
   std::memset(st, 0, sizeof(*st));
   if (op == nullptr || B == nullptr || X == nullptr || p == nullptr) return st->status = DCG_E_ARG;
+  if (op->has_dsc) return st->status = DCG_E_ARG;   // not supported with a diagonal scaling
   if (m < 1 || m > kMaxBlockCols || !(p->tol >= 0.0)) return st->status = DCG_E_ARG;
   if (rc != nullptr && rc->n != op->g.n) return st->status = DCG_E_ARG;
   const int64_t n = op->g.n, n_pad = op->g.n_pad;

@@ -102,6 +102,9 @@ struct dcg_operator_s {
   int exact_items;       // work-item target of the FP64 pair sweep
   double *x64;           // the points, FP64, n_pad x d row-major (operand source)
   int *flag;             // device flag word: operand preparation problems
+  double *dsc;           // diagonal scaling D of A = D K D + sigma2 I (n_pad)
+  int has_dsc;           // 1: dsc applies
+  uint64_t dsc_version;  // bumped by every dcg_set_diag
   double *x64r, *x64c;   // FP64 augmented operands of the exact operator
   double *vin64;         // staged FP64 input vector, n_pad
   double *part64;        // partial sums of the FP64 sweep
@@ -120,6 +123,7 @@ struct dcg_recycle_s {
   const dcg_operator_s *aw_op;
   uint64_t aw_gen;
   double aw_ell, aw_s2, aw_sigma2;
+  uint64_t aw_dsc;       // the operator's dsc_version when AW was formed
   int n_theta;
   double theta[dcg::kMaxK];
   double *Z;             // n x (k + L): [W | P_L]

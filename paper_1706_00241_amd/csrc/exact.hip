@@ -263,19 +263,21 @@ __global__ __launch_bounds__(256, 2) void symv64_kernel(Symv64Args A) {
   }
 }
 
-// v -> zero-padded FP64 copy (n_pad).
+// v (times the diagonal scaling d if given) -> zero-padded FP64 copy (n_pad).
 __global__ __launch_bounds__(256) void stage64(const double *V, int64_t n, int64_t n_pad,
-                                               double *out, const int *done) {
+                                               const double *dsc, double *out, const int *done) {
   if (done != nullptr && *done != 0) return;
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (i < n_pad) out[i] = (i < n) ? V[i] : 0.0;
+  if (i < n_pad) out[i] = (i < n) ? ((dsc != nullptr) ? dsc[i] * V[i] : V[i]) : 0.0;
 }
 
-// y = s2 * (row partials + column partials, fixed order) + sigma2 v.
+// y = s2 * (row partials + column partials, fixed order) + sigma2 v; with a
+// diagonal scaling, y = d * s2 * (partials) + sigma2 v.
 __global__ __launch_bounds__(256) void reduce64(const double *prow, const double *pcol,
                                                 int64_t n, int64_t n_pad, int nchunk, int dmax,
-                                                int nb, double s2, double sigma2, const double *V,
-                                                double *Y, const int *done) {
+                                                int nb, double s2, double sigma2,
+                                                const double *dsc, const double *V, double *Y,
+                                                const int *done) {
   if (done != nullptr && *done != 0) return;
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n) return;
@@ -284,7 +286,7 @@ __global__ __launch_bounds__(256) void reduce64(const double *prow, const double
   const int J = static_cast<int>(i / 128);
   const int dlim = ((nb % 2) == 0 && J < nb / 2) ? dmax - 1 : dmax;
   for (int dl = 1; dl <= dlim; ++dl) s += pcol[int64_t(dl - 1) * n_pad + i];
-  Y[i] = fma(s2, s, sigma2 * V[i]);
+  Y[i] = fma((dsc != nullptr) ? s2 * dsc[i] : s2, s, sigma2 * V[i]);
 }
 
 template <int KERN>
@@ -334,16 +336,17 @@ int matvec_exact_done(const dcg_operator_s *op, const double *V, double *Y, int6
   const int64_t n = op->g.n, n_pad = op->g.n_pad;
   MatvecPlan p;
   const Symv64Args a = exact_args(op, done, &p);
+  const double *dsc = op->has_dsc ? op->dsc : nullptr;
   for (int64_t col = 0; col < m; ++col) {
     const double *Vc = V + col * n;
     double *Yc = Y + col * n;
     hipLaunchKernelGGL(stage64, dim3(static_cast<unsigned>(cdiv(n_pad, 256))), dim3(256), 0,
-                       op->stream, Vc, n, n_pad, op->vin64, done);
+                       op->stream, Vc, n, n_pad, dsc, op->vin64, done);
     const int st = launch_exact_sweep(op, done);
     if (st != DCG_OK) return st;
     hipLaunchKernelGGL(reduce64, dim3(static_cast<unsigned>(cdiv(n, 256))), dim3(256), 0,
                        op->stream, a.prow, a.pcol, n, n_pad, p.nchunk, p.dmax, p.nb, op->s2,
-                       op->sigma2, Vc, Yc, done);
+                       op->sigma2, dsc, Vc, Yc, done);
     if (hipGetLastError() != hipSuccess) return DCG_E_HIP;
   }
   return DCG_OK;

@@ -321,7 +321,7 @@ int dcg_mll_grad(dcg_op_t op, const double *alpha, const double *U, const double
                  double *grad3, void *ws, size_t ws_bytes) {
   if (op == nullptr || alpha == nullptr || U == nullptr || Z == nullptr || grad3 == nullptr)
     return DCG_E_ARG;
-  if (P < 1 || P > kMaxProbes) return DCG_E_ARG;
+  if (P < 1 || P > kMaxProbes || op->has_dsc) return DCG_E_ARG;
   if (op->g.prec != DCG_PREC_FP32 && op->g.prec != DCG_PREC_BF16) return DCG_E_ARG;
   const int64_t n = op->g.n, n_pad = op->g.n_pad;
   if (ws == nullptr || ws_bytes < grad_workspace_bytes(n_pad)) return DCG_E_WORKSPACE;

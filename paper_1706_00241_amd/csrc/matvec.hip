@@ -378,24 +378,30 @@ __global__ __launch_bounds__(256, 2) void symv_batched(const BatchItem *sys, int
   else symv_body<DCG_MATERN52, KS, 1, OPK>(B.a, item);
 }
 
-// Finish y = s2 * (sum of partials) + sigma2 v for the first `cols` vectors.
+// Finish y = s2 * (sum of partials) + sigma2 v for the first `cols` vectors
+// (with a diagonal scaling: y = d * s2 * (sum) + sigma2 v).
 __global__ __launch_bounds__(256) void symv_reduce(ReduceArgs A, int cols) {
   const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (e >= A.n * cols) return;
   const int m = static_cast<int>(e / A.n);
   const int64_t i = e % A.n;
   const double s = sum_partials(A, m, i);
-  A.Y[m * A.n + i] = fma(A.s2, s, A.sigma2 * A.V[m * A.n + i]);
+  const double s2 = (A.dsc != nullptr) ? A.s2 * A.dsc[i] : A.s2;
+  A.Y[m * A.n + i] = fma(s2, s, A.sigma2 * A.V[m * A.n + i]);
 }
 
-// FP64 -> FP32 staging of up to 4 vectors, zero padded to n_pad.
+// FP64 -> FP32 staging of up to 4 vectors (times the diagonal scaling d if
+// given), zero padded to n_pad.
 __global__ __launch_bounds__(256) void stage_vectors(const double *V, int64_t n, int64_t n_pad,
-                                                     int mv, int mvs, float *out) {
+                                                     int mv, int mvs, const double *dsc,
+                                                     float *out) {
   const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (e >= n_pad * mvs) return;
   const int m = static_cast<int>(e / n_pad);
   const int64_t i = e % n_pad;
-  out[e] = (m < mv && i < n) ? static_cast<float>(V[m * n + i]) : 0.0f;
+  float v = 0.0f;
+  if (m < mv && i < n) v = static_cast<float>((dsc != nullptr) ? dsc[i] * V[m * n + i] : V[m * n + i]);
+  out[e] = v;
 }
 
 // ----------------------------------------------------------------- dispatch
@@ -552,6 +558,7 @@ ReduceArgs reduce_args(const dcg_operator_s *op, int mv, const double *V, double
   r.mv = mv;
   r.s2 = op->s2;
   r.sigma2 = op->sigma2;
+  r.dsc = op->has_dsc ? op->dsc : nullptr;
   r.V = V;
   r.Y = Y;
   return r;
@@ -569,7 +576,8 @@ int matvec_lowprec(const dcg_operator_s *op, const double *V, double *Y, int64_t
     const double *Vc = V + done_cols * n;
     double *Yc = Y + done_cols * n;
     hipLaunchKernelGGL(stage_vectors, dim3(static_cast<unsigned>(cdiv(n_pad * mv, 256))), dim3(256),
-                       0, op->stream, Vc, n, n_pad, cols, mv, op->vin);
+                       0, op->stream, Vc, n, n_pad, cols, mv, op->has_dsc ? op->dsc : nullptr,
+                       op->vin);
     int rc = launch_symv_sweep(op, mv, nullptr);
     if (rc != DCG_OK) return rc;
     // only the first `cols` staged vectors are real; reduce those

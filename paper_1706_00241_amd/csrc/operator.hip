@@ -83,6 +83,20 @@ __global__ __launch_bounds__(256) void check_finite(const double *X, int64_t cou
     if (!isfinite(X[e])) atomicOr(flag, 1);
 }
 
+// Copy of a diagonal scaling (zero padded to n_pad); flags entries that are
+// negative or not finite.
+__global__ __launch_bounds__(256) void copy_diag(const double *D, int64_t n, int64_t n_pad,
+                                                 double *out, int *flag) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n_pad) return;
+  double v = 0.0;
+  if (i < n) {
+    v = D[i];
+    if (!(v >= 0.0) || !isfinite(v)) atomicOr(flag, 8);
+  }
+  out[i] = v;
+}
+
 // The input points as an FP64 copy (n_pad x d, row-major, zero rows past
 // n), once when the operator is created: the source of every operand build.
 __global__ __launch_bounds__(256) void copy_points(const double *X, int64_t n, int64_t n_pad,
@@ -291,7 +305,7 @@ static int launch_prepare(const dcg_operator_s *op) {
 // ----------------------------------------------------------- workspace
 
 struct OpLayout {
-  size_t x64, x64r, x64c, vin64, part64, xr, xc, vin, part, ytmp, flag, total;
+  size_t x64, x64r, x64c, vin64, part64, xr, xc, vin, part, ytmp, dsc, flag, total;
 };
 
 static OpLayout op_layout(const Geometry &g) {
@@ -312,6 +326,7 @@ static OpLayout op_layout(const Geometry &g) {
     c.off += std::max(matvec_partial_floats(g.n_pad, 1, sweep_blk(g, 1)),
                       matvec_partial_floats(g.n_pad, 4, sweep_blk(g, 4))) * 4;
   L.ytmp = c.off = align256(c.off); c.off += size_t(g.n_pad) * 4 * 8;
+  L.dsc = c.off = align256(c.off); c.off += size_t(g.n_pad) * 8;
   L.flag = c.off = align256(c.off); c.off += 256;
   L.total = align256(c.off);
   return L;
@@ -413,6 +428,9 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel, doubl
   op->vin = reinterpret_cast<float *>(base + L.vin);
   op->part = reinterpret_cast<float *>(base + L.part);
   op->ytmp = reinterpret_cast<double *>(base + L.ytmp);
+  op->dsc = reinterpret_cast<double *>(base + L.dsc);
+  op->has_dsc = 0;
+  op->dsc_version = 0;
   // flag word 0: non-finite input; word 1: operand preparation (fp16 range)
   int *flag = reinterpret_cast<int *>(base + L.flag);
   op->flag = flag + 1;
@@ -469,6 +487,36 @@ int dcg_set_hyper(dcg_op_t op, double ell, double s2, double sigma2) {
     (void)launch_prepare(op);
   }
   return st;
+}
+
+int dcg_set_diag(dcg_op_t op, const double *D) {
+  if (op == nullptr) return DCG_E_ARG;
+  if (D == nullptr) {
+    if (op->has_dsc) {
+      op->has_dsc = 0;
+      op->dsc_version += 1;
+      op->generation += 1;
+    }
+    return DCG_OK;
+  }
+  const int64_t n = op->g.n, n_pad = op->g.n_pad;
+  int h = 0;
+  if (hipMemsetAsync(op->flag, 0, sizeof(int), op->stream) != hipSuccess) return DCG_E_HIP;
+  hipLaunchKernelGGL(copy_diag, dim3(static_cast<unsigned>(cdiv(n_pad, 256))), dim3(256), 0,
+                     op->stream, D, n, n_pad, op->dsc, op->flag);
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(&h, op->flag, sizeof(int), hipMemcpyDeviceToHost, op->stream) != hipSuccess ||
+      hipStreamSynchronize(op->stream) != hipSuccess)
+    return DCG_E_HIP;
+  op->dsc_version += 1;
+  op->generation += 1;
+  if (h & 8) {
+    // the copy is unusable: the operator goes back to no scaling
+    op->has_dsc = 0;
+    return DCG_E_NONFINITE;
+  }
+  op->has_dsc = 1;
+  return DCG_OK;
 }
 
 int dcg_matvec(dcg_op_t op, const double *V, double *Y, int64_t m) {

@@ -131,14 +131,15 @@ static int refresh_AW(dcg_operator_s *op, dcg_recycle_s *rc, int *matvecs) {
   const int64_t n = rc->n;
   const bool same_op = rc->aw_state == 1 && rc->aw_op == op;
   if (same_op && rc->aw_gen == op->generation) return DCG_OK;
-  if (same_op && rc->aw_ell == op->ell && rc->aw_s2 == op->s2) {
+  if (same_op && rc->aw_ell == op->ell && rc->aw_s2 == op->s2 && rc->aw_dsc == op->dsc_version) {
     // only the diagonal shift changed: A_new W = A_old W + (s_new - s_old) W
     enqueue_block_axpy(op->stream, rc->AZ, rc->Z, op->sigma2 - rc->aw_sigma2, n * k);
   } else {
     // the low-precision sweep multiplies the FP32 copy of W: make W that
     // copy (it is only a basis), so that AW is A~ W to the sweep's
     // evaluation error rather than to W's rounding
-    if (op->g.prec != DCG_PREC_FP64) enqueue_round_to_fp32(op->stream, rc->Z, n * k);
+    if (op->g.prec != DCG_PREC_FP64 && !op->has_dsc)
+      enqueue_round_to_fp32(op->stream, rc->Z, n * k);
     const int st = matvec_lowprec(op, rc->Z, rc->AZ, k);
     if (st != DCG_OK) return st;
     *matvecs += k;
@@ -149,6 +150,7 @@ static int refresh_AW(dcg_operator_s *op, dcg_recycle_s *rc, int *matvecs) {
   rc->aw_ell = op->ell;
   rc->aw_s2 = op->s2;
   rc->aw_sigma2 = op->sigma2;
+  rc->aw_dsc = op->dsc_version;
   rc->w_version += 1;
   return DCG_OK;
 }
@@ -289,7 +291,8 @@ int solve_init(dcg_operator_s *op, const double *b, double *x, int x_given,
     enqueue_ts_dot(s, rc->AZ, n, k, B.r, B.part_h, B.counter + 1, Minv, B.S->mu);
   }
   hipLaunchKernelGGL(init_direction, dim3(static_cast<unsigned>(cdiv(n_pad, 256))), dim3(256), 0, s,
-                     B.r, rc ? rc->Z : nullptr, B.S->mu, n, n_pad, k, B.p, op->vin, B.part,
+                     B.r, rc ? rc->Z : nullptr, B.S->mu, n, n_pad, k,
+                     op->has_dsc ? op->dsc : nullptr, B.p, op->vin, B.part,
                      B.counter, B.S, tol, B.hist_res);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
@@ -442,6 +445,7 @@ int extract_basis(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_params *p, in
   rc->aw_ell = op->ell;
   rc->aw_s2 = op->s2;
   rc->aw_sigma2 = op->sigma2;
+  rc->aw_dsc = op->dsc_version;
   out->k_next = knew;
   return DCG_OK;
 }

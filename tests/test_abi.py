@@ -46,6 +46,10 @@ def test_workspace_queries(L):
     assert L.dcg_recycle_workspace_bytes(1000, 8, 4) == 0       # L < k
     assert L.dcg_recycle_workspace_bytes(1000, 65, 100) == 0    # k too large
     assert L.dcg_solve_workspace_bytes(1000, 0, 0) > 0
+    # the Newton loop: one solve's workspace plus b~, K b~ / b and z
+    assert L.dcg_laplace_gpc_workspace_bytes(1000) >= \
+        L.dcg_solve_workspace_bytes(1000, 0, 0) + 3 * 1000 * 8
+    assert L.dcg_laplace_gpc_workspace_bytes(0) == 0
 
 
 def test_argument_validation_without_gpu(L):
@@ -68,6 +72,11 @@ def test_argument_validation_without_gpu(L):
     assert L.dcg_set_sweep_items(None, 2048) == -1
     assert L.dcg_tune_operator(None, 5, None, None) == -1
     assert L.dcg_matvec(None, None, None, 1) == -1
+    assert L.dcg_set_diag(None, None) == -1
+    steps = ctypes.c_int(7)
+    assert L.dcg_laplace_gpc(None, None, None, ctypes.byref(p), 5, 1.0, None, None, None,
+                             ctypes.byref(steps), None, None, 0) == -1
+    assert steps.value == 0
     assert L.dcg_status_string(-2).decode().startswith("operator not positive")
     assert "gfx950" in L.dcg_version().decode()
 

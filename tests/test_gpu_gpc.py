@@ -1,0 +1,211 @@
+"""GPU parity of the diagonally scaled operator A = D K D + sigma2 I and of
+the Laplace GPC Newton loop (section 3, Eqs. 8-10) against the FP64 oracle.
+
+Tolerances of the Newton loop: the oracle runs the same iteration with
+dense solves on the kernel matrix of the same rounded points, so what is
+left is the solver tolerance and the operator's evaluation error.  With
+exact arithmetic CG on these 1500-point problems the latent f deviates from
+the dense-solve mode by about 2.5e-8 (tol 1e-10) and 1e-6 (tol 1e-8) of
+max |f|, and a 1e-7 relative perturbation of K (the FP32 evaluation error)
+moves it by 3e-6; the bounds below leave a factor 20-40 above those.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import gpc as OG
+from oracle import kernels as OK
+from oracle import precision as OP
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float64), device="cuda")
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _diag(n, seed):
+    g = np.random.default_rng(seed)
+    D = np.sqrt(g.uniform(0.0, 0.25, n))      # the range of sqrt(pi (1 - pi))
+    D[::17] = 0.0                             # saturated points: H = 0
+    return D
+
+
+@pytest.mark.parametrize("prec", [0, 1, 3, 4])
+@pytest.mark.parametrize("kern", [0, 2])
+@pytest.mark.parametrize("n,d,m", [(200, 3, 1), (1500, 16, 3), (777, 64, 2)])
+def test_scaled_matvec_parity(lib, prec, kern, n, d, m):
+    g = np.random.default_rng(n + d)
+    X = g.standard_normal((n, d))
+    ell = workloads.median_distance(X)
+    s2, sigma2 = 2.5, 1.0
+    op = lib.Operator(_dev(X), kern, ell, s2, sigma2, prec=prec)
+    D = _diag(n, 3)
+    op.set_diag(_dev(D))
+    V = g.standard_normal((n, m))
+    A = D[:, None] * OK.operator(OP.round_points(X, prec, kern, ell), kern, ell, s2, 0.0) \
+        * D[None, :] + sigma2 * np.eye(n)
+    Y = _np(op.matvec(_dev(V)))
+    bound = 1e-12 if prec == 3 else 2e-5
+    err = np.abs(Y - A @ V) / (np.abs(A) @ np.abs(V))
+    assert err.max() <= bound, err.max()
+    # the FP64 operator on the unrounded points, scaled the same way
+    Ae = D[:, None] * OK.operator(X, kern, ell, s2, 0.0) * D[None, :] + sigma2 * np.eye(n)
+    Ye = _np(op.matvec_exact(_dev(V)))
+    err = np.abs(Ye - Ae @ V) / (np.abs(Ae) @ np.abs(V))
+    assert err.max() <= 1e-12, err.max()
+    # removing the scaling gives the plain operator back
+    op.set_diag(None)
+    A0 = OK.operator(OP.round_points(X, prec, kern, ell), kern, ell, s2, sigma2)
+    err = np.abs(_np(op.matvec(_dev(V))) - A0 @ V) / (np.abs(A0) @ np.abs(V))
+    assert err.max() <= bound, err.max()
+
+
+def test_scaled_operator_rejected_where_unsupported(lib):
+    n = 300
+    X = np.random.default_rng(0).standard_normal((n, 4))
+    op = lib.Operator(_dev(X), 0, 1.0, 1.0, 1.0, prec=0)
+    bad = np.ones(n)
+    bad[5] = -1.0
+    with pytest.raises(lib.DcgError) as e:
+        op.set_diag(_dev(bad))
+    assert e.value.status == -3
+    bad[5] = np.nan
+    with pytest.raises(lib.DcgError):
+        op.set_diag(_dev(bad))
+    op.set_diag(_dev(np.full(n, 0.5)))
+    B = _dev(np.ones((n, 2)))
+    with pytest.raises(lib.DcgError):
+        lib.solve_block(op, B)
+    with pytest.raises(lib.DcgError):
+        lib.solve_batched([op], [B[:, 0]])
+    # the Newton loop wants an unscaled operator
+    y = _dev(np.where(np.arange(n) % 2 == 0, 1.0, -1.0))
+    with pytest.raises(lib.DcgError):
+        lib.laplace_gpc(op, y)
+    op.set_diag(None)
+    yb = y.clone()
+    yb[3] = 0.5
+    with pytest.raises(lib.DcgError) as e:
+        lib.laplace_gpc(op, yb)
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("prec,tol", [(3, 1e-8), (0, 1e-6)])
+def test_scaled_solve_parity(lib, prec, tol):
+    """Deflated CG on a sequence of scaled systems I + D_i K D_i: the oracle's
+    true residual of every solution is within the tolerance plus twice the
+    operator's evaluation floor (measured per solution)."""
+    w = workloads.gpc(n=1500, d=16)
+    X = w["X"]
+    n = X.shape[0]
+    Kr = OK.gram(OP.round_points(X, prec, w["kernel"], w["ell"]), w["kernel"], w["ell"], w["s2"])
+    op = lib.Operator(_dev(X), w["kernel"], w["ell"], w["s2"], 1.0, prec=prec)
+    rc = lib.Recycle(n, 8, 12)
+    g = np.random.default_rng(4)
+    b = g.standard_normal(n)
+    for i in range(3):
+        D = _diag(n, 10 + i)
+        op.set_diag(_dev(D))
+        A = np.eye(n) + D[:, None] * Kr * D[None, :]
+        x, st = lib.solve(op, _dev(b), rc=rc, tol=tol)
+        assert st["status"] == 0
+        x = _np(x)
+        res = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+        # the GPU operator's distance from the oracle's, |(A_gpu - A) x| / |b|
+        floor = np.linalg.norm(_np(op.matvec(_dev(x))) - A @ x) / np.linalg.norm(b)
+        assert res <= 1.01 * tol + 2 * floor, (i, res, floor)
+
+
+def _gpc_problem(n=1500, d=16):
+    w = workloads.gpc(n=n, d=d)
+    return w, w["X"], w["y"]
+
+
+@pytest.mark.parametrize("prec,refine,tol,ftol,psitol,psifin",
+                         [(3, False, 1e-10, 1e-6, 1e-8, 1e-9),
+                          (0, False, 1e-8, 1e-4, 1e-5, 1e-6),
+                          (1, False, 1e-6, 1e-3, 4e-4, 2e-5),
+                          (1, True, 1e-8, 5e-5, 1e-5, 1e-8)])
+def test_laplace_gpc_matches_oracle(lib, prec, refine, tol, ftol, psitol, psifin):
+    """The Newton loop against the oracle's (dense solves): the same number
+    of Newton steps, Psi at every step (an unconverged step's Psi moves with
+    the solve's error: exact-arithmetic CG deviates by up to 6.5e-7 at tol
+    1e-8 and 2e-5 at tol 1e-6, the last Psi by 7e-10 and 3.3e-7; a 1e-6
+    relative error in K moves every Psi by 1e-6), the mode f and a."""
+    w, X, y = _gpc_problem()
+    n = X.shape[0]
+    # refinement runs the products with K in FP64 on the unrounded points
+    Xr = X if refine else OP.round_points(X, prec, w["kernel"], w["ell"])
+    Km = OK.gram(Xr, w["kernel"], w["ell"], w["s2"])
+    f_ref, a_ref, psi_ref, _ = OG.laplace_mode(Km, y, psi_tol=w["psi_tol"])
+    op = lib.Operator(_dev(X), w["kernel"], w["ell"], w["s2"], 0.3, prec=prec)
+    rc = lib.Recycle(n, w["k"], w["L"])
+    f, a, psi, stats, status = lib.laplace_gpc(op, _dev(y), rc=rc, tol=tol,
+                                               psi_tol=w["psi_tol"], refine=refine,
+                                               inner_tol=1e-2)
+    assert status == 0
+    assert len(psi) == len(psi_ref), (psi, psi_ref)
+    assert all(s["status"] == 0 for s in stats)
+    np.testing.assert_allclose(psi, psi_ref, rtol=psitol)
+    assert abs(psi[-1] - psi_ref[-1]) <= psifin * abs(psi_ref[-1]), (psi[-1], psi_ref[-1])
+    f, a = _np(f), _np(a)
+    assert np.abs(f - f_ref).max() <= ftol * np.abs(f_ref).max()
+    assert np.abs(a - a_ref).max() <= ftol * np.abs(a_ref).max() * 10
+    # the operator leaves unscaled, with its own shift
+    A0 = OK.operator(Xr, w["kernel"], w["ell"], w["s2"], 0.3)
+    v = np.random.default_rng(0).standard_normal(n)
+    mv = op.matvec_exact if refine else op.matvec
+    err = np.abs(_np(mv(_dev(v))) - A0 @ v) / (np.abs(A0) @ np.abs(v))
+    assert err.max() <= (1e-12 if prec == 3 or refine else 2e-5)
+
+
+def test_laplace_gpc_recycling_saves_iterations(lib):
+    """W carried across the Newton systems: fewer CG steps after the first
+    system than plain CG at the same tolerance (Fig. 2, right), and the
+    first system is plain CG either way."""
+    w, X, y = _gpc_problem()
+    n = X.shape[0]
+    op = lib.Operator(_dev(X), w["kernel"], w["ell"], w["s2"], 0.0, prec=3)
+    _, _, psi_p, st_p, _ = lib.laplace_gpc(op, _dev(y), rc=None, tol=w["tol"])
+    rc = lib.Recycle(n, w["k"], w["L"])
+    _, _, psi_d, st_d, _ = lib.laplace_gpc(op, _dev(y), rc=rc, tol=w["tol"])
+    its_p = [s["iters"] for s in st_p]
+    its_d = [s["iters"] for s in st_d]
+    assert len(its_p) == len(its_d) >= 3
+    assert its_d[0] == its_p[0]
+    assert sum(its_d[1:]) < sum(its_p[1:]), (its_d, its_p)
+    assert all(s["k_used"] == w["k"] for s in st_d[1:])
+    # the final Psi of either run is within 7e-6 of the dense-solve mode's
+    # at tol 1e-5 (intermediate Psi values move with each solve's error)
+    assert abs(psi_d[-1] - psi_p[-1]) <= 3e-5 * abs(psi_p[-1])
+
+
+def test_laplace_gpc_full_size_sampled(lib):
+    """The full-size problem (n = 36551, d = 64, FP32 operator, tol 1e-5):
+    Psi never decreases, the returned Psi is the oracle's Psi of the returned
+    (f, a), and f = K a on sampled rows, each row of K formed by the oracle."""
+    w = workloads.gpc()
+    X, y = w["X"], w["y"]
+    n = X.shape[0]
+    op = lib.Operator(_dev(X), w["kernel"], w["ell"], w["s2"], 0.0, prec=0)
+    rc = lib.Recycle(n, w["k"], w["L"])
+    f, a, psi, stats, status = lib.laplace_gpc(op, _dev(y), rc=rc, tol=w["tol"],
+                                               psi_tol=w["psi_tol"])
+    assert status == 0 and len(psi) >= 3
+    assert np.all(np.diff(psi) > -1e-8 * np.abs(psi[1:]))
+    f, a = _np(f), _np(a)
+    psi_o = OG.log_lik(y, f) - 0.5 * (a @ f)
+    assert abs(psi_o - psi[-1]) <= 1e-10 * abs(psi_o)
+    Xr = OP.round_points(X, 0, w["kernel"], w["ell"])
+    rows = np.random.default_rng(1).choice(n, 24, replace=False)
+    Krows = OK.gram(Xr[rows], w["kernel"], w["ell"], w["s2"], Y=Xr)
+    err = np.abs(Krows @ a - f[rows]) / (np.abs(Krows) @ np.abs(a))
+    assert err.max() <= 2e-5, err.max()

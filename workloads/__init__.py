@@ -18,6 +18,11 @@ Workloads (kernel-regression systems A = K_theta(X, X) + sigma^2 I):
                  sigma2_i = 1e-3 * 0.9^i, fixed b ~ N(0,1), 10 systems.
 * ``gp_hyper``   n=32768, d=16, X ~ N(0,1), y = sum_c a_c sin(X w_c) + 0.1 eps,
                  RBF, Rademacher probes.
+* ``gpc``        Laplace GP classification (the systems A = I + D K D of the
+                 Newton iteration): n=36551 points in d=64, two classes of
+                 6 Gaussian modes each (centres ~ N(0, I), spread 0.7), 5%
+                 of the labels flipped, RBF, ell = 0.5 x median pairwise
+                 distance, s2 = 100; a stand-in for the 3-vs-5 digits set.
 * ``ragged``     64 sequences, n log-uniform in [2048, 32768], d=8, RBF or
                  Matern-3/2 (fair coin), sigma2 log-uniform [1e-4, 1e-1],
                  ell_0 = median heuristic, log-ell walk 0.05, 5 systems each.
@@ -91,6 +96,19 @@ def gp_hyper(n=32768, d=16, probes=16, components=4):
     return dict(X=X, y=y, kernel=RBF, log_ell=np.log(median_distance(X)),
                 log_s2=0.0, log_sigma2=np.log(0.1), probes=probes, k=32, L=48,
                 tol=1e-6, lr=0.05)
+
+
+def gpc(n=36551, d=64, modes=6, spread=0.7, flip=0.05):
+    """Two-class point cloud and labels in {-1, +1} for Laplace GPC."""
+    g = rng(5)
+    centres = g.standard_normal((2, modes, d))
+    cls = (g.random(n) < 0.5).astype(np.int64)
+    mode = g.integers(modes, size=n)
+    X = centres[cls, mode] + spread * g.standard_normal((n, d))
+    y = np.where(cls == 1, 1.0, -1.0)
+    y[g.random(n) < flip] *= -1.0
+    return dict(X=X, y=y, kernel=RBF, ell=0.5 * median_distance(X), s2=100.0,
+                k=8, L=12, tol=1e-5, psi_tol=1.0)
 
 
 def rademacher(n, P, step, index=3):
