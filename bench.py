@@ -79,11 +79,16 @@ def parse():
     ap.add_argument("--sweep-items", type=int, default=0, metavar="N",
                     help="use this sweep plan (work-item target) instead of tuning; for "
                          "profiling runs that should launch only the timed plan")
-    ap.add_argument("--workload", choices=["bf16_shift", "ragged", "gp_hyper", "fp32_walk"],
+    ap.add_argument("--workload", choices=["bf16_shift", "ragged", "gp_hyper", "fp32_walk",
+                                           "gpc", "gpc64"],
                     default="bf16_shift",
                     help="bf16_shift: the headline sequence; ragged: the batching form (64 "
                          "independent sequences, one batched solve per step); gp_hyper: the "
-                         "differentiation form (Adam on the GP marginal likelihood)")
+                         "differentiation form (Adam on the GP marginal likelihood); "
+                         "fp32_walk: FP32 log-ell walk; gpc: Laplace GP classification "
+                         "(the paper's own test problem, the whole Newton loop per step) on "
+                         "784-pixel data with the stored kernel matrix; gpc64: the same loop "
+                         "at d = 64 with the matrix-free FP32 operator")
     ap.add_argument("--adam-steps", type=int, default=50,
                     help="gp_hyper: Adam steps in all (the first --warmup are not timed)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -270,6 +275,91 @@ def main_walk(args):
         sys.exit(1)
 
 
+def main_gpc(args):
+    """Laplace GP classification (section 3): Newton's method for the mode
+    from f = 0 until Psi grows by less than 1, each system A = I + D K D
+    solved to 1e-5 by def-CG(8, 12) with W carried from one Newton system to
+    the next.  One step = one whole Newton loop (every system, its K products,
+    Psi); the same loop is then run with plain CG.
+
+    gpc: the paper-shaped data, n = 36551 pixel-like points in d = 784, RBF
+    with s2 = 10; the stored operator (K0 formed once in FP64, kept in HBM as
+    FP32, every product one streaming pass with FP64 accumulation; forming
+    K0 is outside the timed loop, as it is fixed across the Newton steps).
+    gpc64: n = 36551 two-class points in d = 64, s2 = 100, the matrix-free
+    FP32 operator (FP32 MFMA distances, FP32 kernel values)."""
+    import torch
+
+    import paper_1706_00241_amd as dcg
+    import workloads
+
+    dcg.load()
+    stored = args.workload == "gpc"
+    w = workloads.gpc_pixels() if stored else workloads.gpc()
+    n, d = w["X"].shape
+    dev = torch.device("cuda:0")
+    X = torch.as_tensor(w["X"], device=dev)
+    y = torch.as_tensor(w["y"], device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = dcg.Operator(X, w["kernel"], w["ell"], w["s2"], 0.0,
+                      prec=dcg.PREC_STORED if stored else dcg.PREC_FP32)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    items, _ = op.tune(reps=5)
+
+    def run(rc_args):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc = dcg.Recycle(n, *rc_args, device=dev) if rc_args else None
+        _, _, psi, stats, status = dcg.laplace_gpc(op, y, rc=rc, tol=w["tol"],
+                                                   psi_tol=w["psi_tol"])
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, psi, stats, status
+
+    for _ in range(args.warmup):
+        run((w["k"], w["L"]))
+    runs = [run((w["k"], w["L"])) for _ in range(args.steps)]
+    ms = sum(r[0] for r in runs) / len(runs)
+    _, psi, stats, status = runs[-1]
+    its = [s["iters"] for s in stats]
+    for t, s in enumerate(stats):
+        print(f"newton {t + 1}: {s['iters']} its, {s['matvecs']} matvecs, "
+              f"{s['t_total_ms']:.2f} ms, psi {psi[t + 1]:.3f}", file=sys.stderr, flush=True)
+    if stored:
+        data = (f"gpc: n={n} d={d} pixel-like points in (0,1) (logistic of 16 Gaussian blobs), "
+                f"labels from a smooth random function, RBF ell=0.5 x median distance s2=10")
+        dtype = "f32 stored kernel matrix (formed in f64), f64 accumulation, CG and Newton terms"
+    else:
+        data = (f"gpc64: n={n} d={d}, two classes of 6 Gaussian modes, 5% labels flipped, "
+                f"RBF ell=0.5 x median distance s2=100")
+        dtype = "fp32 points on fp32 MFMA, f32 kernel values, f64 CG and Newton terms"
+    out = {
+        "metric": f"ms per Laplace-GPC mode (whole Newton loop), def-CG(8,12) to 1e-5, "
+                  f"n={n}, 1 GPU",
+        "value": round(ms, 2), "unit": "ms/mode", "n_gpus": 1, "steps": len(runs),
+        "warmup": args.warmup, "ms_per_step": round(ms, 2), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": data + ", Newton from f=0 until dPsi < 1, def-CG(8,12) tol 1e-5",
+                   "sweep_items": items},
+        "operator_build_ms": round(build_ms, 1),
+        "newton_steps": len(stats), "iters_per_system": its,
+        "matvecs_total": sum(s["matvecs"] for s in stats),
+        "solve_ms_total": round(sum(s["t_total_ms"] for s in stats), 2),
+        "psi": [round(v, 3) for v in psi], "status": status,
+        "failed_solves": sum(1 for s in stats if s["status"] != 0),
+    }
+    if not args.no_plain:
+        prow = [run(None) for _ in range(max(1, min(args.steps, 3)))]
+        out["plain_ms_per_mode"] = round(sum(r[0] for r in prow) / len(prow), 2)
+        out["plain_iters_per_system"] = [s["iters"] for s in prow[-1][2]]
+        out["plain_matvecs_total"] = sum(s["matvecs"] for s in prow[-1][2])
+        out["speedup_vs_plain"] = round(out["plain_ms_per_mode"] / ms, 3)
+    print(json.dumps(out), flush=True)
+    if out["failed_solves"] or status != 0:
+        sys.exit(1)
+
+
 def main_gp(args):
     """Differentiation form: GP hyperparameter optimisation, n = 32768, d = 16,
     RBF, FP32 operator, Adam (lr 0.05) on theta = (log ell, log s2, log
@@ -359,13 +449,15 @@ def main_gp(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the row-sharded multi-GPU design is described, not built)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "ragged":
         return main_ragged(args)
     if args.workload == "gp_hyper":
         return main_gp(args)
+    if args.workload in ("gpc", "gpc64"):
+        return main_gpc(args)
     if args.workload == "fp32_walk":
         return main_walk(args)
     import numpy as np

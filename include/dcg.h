@@ -56,10 +56,22 @@ enum dcg_prec {
                            bits); the distance GEMM takes the four bf16
                            products hi.hi, hi.lo, lo.hi, lo.lo on MFMA         */
   DCG_PREC_FP64 = 3,    /* exact FP64 operator                                 */
-  DCG_PREC_FP16 = 4     /* fp16 points (11 significant bits), fp16 MFMA; the
+  DCG_PREC_FP16 = 4,    /* fp16 points (11 significant bits), fp16 MFMA; the
                            scaled points and their squared norms must stay
                            inside the fp16 range (dcg_create_operator and
                            dcg_set_hyper return DCG_E_ARG otherwise)          */
+  DCG_PREC_STORED = 5   /* the unit-amplitude kernel matrix formed once in
+                           FP64 from the unrounded points and stored in FP32
+                           (4 n_pad^2 bytes of workspace, n_pad = n rounded up
+                           to 256; 1 <= d <= 4096): every product streams it
+                           from HBM with FP64 accumulation.  For point
+                           dimensions beyond the pair sweep's 64 and for
+                           sequences that keep the kernel and lengthscale
+                           (s2, sigma2 and a diagonal scaling apply at product
+                           time; a new ell rebuilds the matrix).  No FP64
+                           operator: dcg_matvec_exact, refinement, the block,
+                           batched and gradient entry points return DCG_E_ARG;
+                           dcg_tune_operator has nothing to tune             */
 };
 
 enum dcg_status {
@@ -339,6 +351,30 @@ size_t dcg_mll_grad_workspace_bytes(int64_t n);
 int dcg_mll_grad(dcg_op_t op, const double *alpha, const double *U,
                  const double *Z, int64_t P, double *grad3, void *ws,
                  size_t ws_bytes);
+
+/* ------------------------------------------------ log det by SLQ
+ * Stochastic Lanczos quadrature: the forward value -1/2 log det A of the GP
+ * log marginal likelihood (GP model adaptation, section 1), from the probe
+ * solves the gradient already needs.  The P probe columns of Z run as one
+ * block CG solve (no recycling: the coefficients must describe the Krylov
+ * space of A and z alone) to p->tol (p->max_iter, p->check_every as for
+ * dcg_solve_block); each column's alpha_j, beta_j give its Lanczos
+ * tridiagonal T_j = 1/alpha_j + beta_{j-1}/alpha_{j-1} on the diagonal and
+ * sqrt(beta_j)/alpha_j beside it (at most max_steps steps are used, 1..4096),
+ * and quad[c] = |z_c|^2 e_1^T log(T) e_1 estimates z_c^T log(A) z_c (Gauss
+ * quadrature).  *logdet (may be NULL) = mean of quad: log det A when
+ * E[z z^T] = I (Rademacher probes).
+ *  Z      device FP64 n x P column-major, 1 <= P <= 64.
+ *  quad   host P doubles; steps host P ints (may be NULL): steps used.
+ *  ws     dcg_slq_logdet_workspace_bytes(n, P, max_steps) bytes, aligned.
+ * Operators as for dcg_solve_block (no diagonal scaling, not stored).
+ * Returns the block solve's status (DCG_NOT_CONVERGED if a column did not
+ * reach p->tol: its quadrature still uses the steps taken), DCG_E_NOT_SPD
+ * if a tridiagonal has a non-positive eigenvalue. */
+size_t dcg_slq_logdet_workspace_bytes(int64_t n, int64_t P, int max_steps);
+int dcg_slq_logdet(dcg_op_t op, const double *Z, int64_t P, const dcg_params *p,
+                   int max_steps, double *quad, int *steps, double *logdet,
+                   void *ws, size_t ws_bytes);
 
 /* ------------------------------------------ Laplace GP classification
  * Newton's method for the mode of the latent function under a GP prior with

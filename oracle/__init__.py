@@ -24,6 +24,8 @@ gp         GP log marginal likelihood, its exact gradient and the Hutchinson
 gpc        Laplace-approximation GP classification: the Newton iteration
            whose restructured systems A = I + H^1/2 K H^1/2 form the
            paper's own sequence (section 3).
+slq        log det A by stochastic Lanczos quadrature from the coefficients
+           of plain CG probe solves (the GP log marginal likelihood's value).
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 against closed forms, brute force on tiny inputs, library routines for

@@ -24,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdcg.so")
 
 RBF, MATERN32, MATERN52 = 0, 1, 2
-PREC_FP32, PREC_BF16, PREC_BF16X2, PREC_FP64, PREC_FP16 = 0, 1, 2, 3, 4
+PREC_FP32, PREC_BF16, PREC_BF16X2, PREC_FP64, PREC_FP16, PREC_STORED = 0, 1, 2, 3, 4, 5
 STATUS = {0: "ok", 1: "not converged", -1: "invalid argument", -2: "not SPD",
           -3: "non-finite", -4: "W rank deficient", -5: "HIP error",
           -6: "workspace"}
@@ -129,6 +129,14 @@ _SIGS = {
                                        ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Stats),
                                        ctypes.c_void_p, ctypes.c_size_t]),
+    "dcg_slq_logdet_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int64,
+                                                        ctypes.c_int]),
+    "dcg_slq_logdet": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.POINTER(Params), ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+                                      ctypes.c_size_t]),
     "dcg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "dcg_version": (ctypes.c_char_p, []),
 }
@@ -436,6 +444,30 @@ def solve(op, b, x0=None, rc=None, tol=1e-6, max_iter=0, L=0, select_largest=Tru
 
 def version():
     return load().dcg_version().decode()
+
+
+def slq_logdet(op, Z, tol=1e-6, max_iter=0, max_steps=1024, check_every=8):
+    """log det A by stochastic Lanczos quadrature: one block CG solve over the
+    probe columns of Z (n x P, P <= 64), each column's Lanczos tridiagonal
+    from its CG coefficients.  Returns (estimate, per-probe values, steps)."""
+    torch = _torch()
+    lib = load()
+    Zc = _colmajor(Z.to(device=op.device, dtype=torch.float64))
+    P = Zc.shape[0]
+    nbytes = lib.dcg_slq_logdet_workspace_bytes(op.n, P, int(max_steps))
+    if nbytes == 0:
+        raise DcgError(-1, "dcg_slq_logdet_workspace_bytes")
+    ws, ptr, size = _workspace(nbytes, op.device)
+    p = Params(tol=float(tol), max_iter=int(max_iter), check_every=int(check_every))
+    quad = (ctypes.c_double * P)()
+    steps = (ctypes.c_int * P)()
+    est = ctypes.c_double()
+    with _ordered(op.stream):
+        status = lib.dcg_slq_logdet(op.handle, Zc.data_ptr(), P, ctypes.byref(p), int(max_steps),
+                                    quad, steps, ctypes.byref(est), ptr, size)
+    _check(status, "dcg_slq_logdet")
+    del ws
+    return est.value, list(quad), list(steps)
 
 
 def laplace_gpc(op, y, rc=None, max_newton=50, psi_tol=1.0, tol=1e-5, max_iter=0, L=0,

@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdcg.so")
 SOURCES = ["matvec.hip", "exact.hip", "blas.hip", "eig.hip", "operator.hip", "solver.hip",
-           "block.hip", "grad.hip", "batch.hip", "gpc.hip"]
+           "block.hip", "grad.hip", "batch.hip", "gpc.hip",
+           "stored.hip", "slq.hip"]
 ARCH = "gfx950"
 
 

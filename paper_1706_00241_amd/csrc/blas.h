@@ -92,6 +92,8 @@ struct CgArgs {
   unsigned *counter;
   double *hist_d, *hist_alpha, *hist_beta, *hist_res;
   int hist_cap;
+  double *lz_alpha, *lz_beta;  // every step's alpha_j, beta_j for j < lz_cap (or null)
+  int lz_cap;
   double tol;
   int max_iter;
 };
@@ -158,6 +160,16 @@ int launch_symv_batched(const BatchItem *d_items, int count, int64_t total, int 
                         hipStream_t s);
 ReduceArgs reduce_args(const dcg_operator_s *op, int mv, const double *V, double *Y);
 int matvec_lowprec(const dcg_operator_s *op, const double *V, double *Y, int64_t m);
+// The block solve behind dcg_solve_block, optionally recording every
+// column's CG coefficients (the Lanczos tridiagonal of stochastic Lanczos
+// quadrature) and returning per-column step counts and |b_c|.
+int solve_block_impl(dcg_operator_s *op, const double *B, double *X, int64_t m,
+                     dcg_recycle_s *rc, const dcg_params *p, dcg_stats *st, void *ws,
+                     size_t ws_bytes, double *lz, int lz_cap, int *col_iters, double *col_bnorm);
+// The stored operator (DCG_PREC_STORED): build K0 from the points, products.
+int stored_build_launch(const dcg_operator_s *op);
+int matvec_stored_done(const dcg_operator_s *op, const double *V, double *Y, int64_t m,
+                       const int *done);
 int matvec_exact(const dcg_operator_s *op, const double *V, double *Y, int64_t m);
 int matvec_exact_done(const dcg_operator_s *op, const double *V, double *Y, int64_t m,
                       const int *done);

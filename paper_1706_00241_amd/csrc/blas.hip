@@ -198,6 +198,7 @@ __device__ __forceinline__ void cg_update_xr_body(const CgArgs &a, const unsigne
       a.hist_d[j] = d;
       a.hist_alpha[j] = alpha;
     }
+    if (a.lz_alpha != nullptr && j < a.lz_cap) a.lz_alpha[j] = alpha;
   }
   constexpr int RPT = kXrRows / 256;
   const int64_t i0 = int64_t(rb) * kXrRows + threadIdx.x;
@@ -313,6 +314,7 @@ __device__ __forceinline__ void cg_finalize_body(const CgArgs &a) {
     S->rho = rho_new;
     const int j = S->iter;
     if (j < a.L) a.hist_beta[j] = beta;
+    if (a.lz_beta != nullptr && j < a.lz_cap) a.lz_beta[j] = beta;
     S->iter = j + 1;
     const double rel = std::sqrt(rho_new) / S->bnorm;
     S->relres = rel;

@@ -16,7 +16,6 @@ namespace dcg {
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-constexpr int kMaxBlockCols = 64;
 constexpr int kBlockHist = 1024;
 
 // C (k x m, ld m) = A (k x k, ld k) B (k x m, ld m); one block.
@@ -118,20 +117,19 @@ static BlockLayout block_layout(int64_t n, int64_t m) {
 
 using namespace dcg;
 
-extern "C" {
-
-size_t dcg_solve_block_workspace_bytes(int64_t n, int64_t m) {
-  if (n < 1 || m < 1 || m > kMaxBlockCols) return 0;
-  return block_layout(n, m).total;
-}
-
-int dcg_solve_block(dcg_op_t op, const double *B, double *X, int64_t m, dcg_recycle_t rc,
-                    const dcg_params *p, dcg_stats *st, void *ws, size_t ws_bytes) {
+// The block solve; with lz (device, m x 2 x lz_cap doubles) it also records
+// every column's alpha_j (first lz_cap) and beta_j (next lz_cap) for
+// j < lz_cap, and with col_iters / col_bnorm (host, m each) it returns each
+// column's step count and |b_c|.
+int dcg::solve_block_impl(dcg_op_t op, const double *B, double *X, int64_t m, dcg_recycle_t rc,
+                          const dcg_params *p, dcg_stats *st, void *ws, size_t ws_bytes,
+                          double *lz, int lz_cap, int *col_iters, double *col_bnorm) {
   dcg_stats local;
   if (st == nullptr) st = &local;
   std::memset(st, 0, sizeof(*st));
   if (op == nullptr || B == nullptr || X == nullptr || p == nullptr) return st->status = DCG_E_ARG;
-  if (op->has_dsc) return st->status = DCG_E_ARG;   // not supported with a diagonal scaling
+  // not supported with a diagonal scaling or the stored operator
+  if (op->has_dsc || op->g.prec == DCG_PREC_STORED) return st->status = DCG_E_ARG;
   if (m < 1 || m > kMaxBlockCols || !(p->tol >= 0.0)) return st->status = DCG_E_ARG;
   if (rc != nullptr && rc->n != op->g.n) return st->status = DCG_E_ARG;
   const int64_t n = op->g.n, n_pad = op->g.n_pad;
@@ -228,6 +226,9 @@ int dcg_solve_block(dcg_op_t op, const double *B, double *X, int64_t m, dcg_recy
     a.hist_d = h + kBlockHist;
     a.hist_alpha = h + kBlockHist + kMaxZ;
     a.hist_beta = h + kBlockHist + 2 * kMaxZ;
+    a.lz_alpha = (lz != nullptr) ? lz + c * 2 * lz_cap : nullptr;
+    a.lz_beta = (lz != nullptr) ? lz + c * 2 * lz_cap + lz_cap : nullptr;
+    a.lz_cap = lz_cap;
     a.tol = p->tol;
     a.max_iter = max_iter;
   }
@@ -288,7 +289,23 @@ int dcg_solve_block(dcg_op_t op, const double *B, double *X, int64_t m, dcg_recy
   st->t_init_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   st->t_loop_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
   st->t_total_ms = st->t_init_ms + st->t_loop_ms;
+  for (int64_t c = 0; c < m; ++c) {
+    if (col_iters != nullptr) col_iters[c] = hs[static_cast<size_t>(c)].iter;
+    if (col_bnorm != nullptr) col_bnorm[c] = hs[static_cast<size_t>(c)].bnorm;
+  }
   return status;
+}
+
+extern "C" {
+
+size_t dcg_solve_block_workspace_bytes(int64_t n, int64_t m) {
+  if (n < 1 || m < 1 || m > kMaxBlockCols) return 0;
+  return block_layout(n, m).total;
+}
+
+int dcg_solve_block(dcg_op_t op, const double *B, double *X, int64_t m, dcg_recycle_t rc,
+                    const dcg_params *p, dcg_stats *st, void *ws, size_t ws_bytes) {
+  return solve_block_impl(op, B, X, m, rc, p, st, ws, ws_bytes, nullptr, 0, nullptr, nullptr);
 }
 
 }  // extern "C"

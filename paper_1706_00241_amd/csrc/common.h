@@ -11,10 +11,12 @@
 namespace dcg {
 
 constexpr int kMaxD = 64;
+constexpr int kMaxStoredD = 4096;  // point dimension of the stored operator
 constexpr int kMaxK = 64;          // columns of W
 constexpr int kMaxZ = 192;         // k + L (columns of Z)
 constexpr int kRedBlocks = 256;    // blocks of the grid-stride FP64 reductions
 constexpr int kMaxBatch = 4096;    // systems of one batched solve
+constexpr int kMaxBlockCols = 64;  // right-hand sides of one block solve
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -112,6 +114,7 @@ struct dcg_operator_s {
   float *vin;            // staged FP32 input vectors, n_pad x 4
   float *part;           // partial sums of the symmetric matvec
   double *ytmp;          // n_pad x 4 FP64 staging for products
+  float *kst;            // stored operator: K0, n_pad x n_pad FP32 row-major
 };
 
 struct dcg_recycle_s {

@@ -55,8 +55,8 @@ Geometry make_geometry(int64_t n, int d, int prec) {
   g.prec = prec;
   g.n_pad = ((n + 255) / 256) * 256;
   g.opk = kOpBf16;
-  if (prec == DCG_PREC_FP64) {
-    g.ksteps = 0;  // the exact FP64 product needs no MFMA operands
+  if (prec == DCG_PREC_FP64 || prec == DCG_PREC_STORED) {
+    g.ksteps = 0;  // the exact FP64 product and the stored matrix need no MFMA operands
     g.kstride = 0;
   } else if (prec == DCG_PREC_BF16 || prec == DCG_PREC_FP16) {
     g.opk = (prec == DCG_PREC_FP16) ? kOpF16 : kOpBf16;
@@ -567,6 +567,7 @@ ReduceArgs reduce_args(const dcg_operator_s *op, int mv, const double *V, double
 // Y = A V for m vectors (groups of 4, a last single vector group of 1).
 int matvec_lowprec(const dcg_operator_s *op, const double *V, double *Y, int64_t m) {
   if (op->g.prec == DCG_PREC_FP64) return matvec_exact(op, V, Y, m);
+  if (op->g.prec == DCG_PREC_STORED) return matvec_stored_done(op, V, Y, m, nullptr);
   const int64_t n = op->g.n, n_pad = op->g.n_pad;
   int64_t done_cols = 0;
   while (done_cols < m) {

@@ -282,6 +282,7 @@ __global__ __launch_bounds__(256) void prepare_lowprec(const double *x64, int64_
 // returns DCG_E_ARG if a scaled point or squared norm left the fp16 range).
 static int launch_prepare(const dcg_operator_s *op) {
   const Geometry &g = op->g;
+  if (g.prec == DCG_PREC_STORED) return stored_build_launch(op);
   const double c = point_scale(op->kernel, op->ell);
   const dim3 grid(static_cast<unsigned>(cdiv(g.n_pad, 256)));
   const bool check = g.prec == DCG_PREC_FP16;
@@ -305,29 +306,32 @@ static int launch_prepare(const dcg_operator_s *op) {
 // ----------------------------------------------------------- workspace
 
 struct OpLayout {
-  size_t x64, x64r, x64c, vin64, part64, xr, xc, vin, part, ytmp, dsc, flag, total;
+  size_t x64, x64r, x64c, vin64, part64, xr, xc, vin, part, ytmp, dsc, flag, kst, total;
 };
 
 static OpLayout op_layout(const Geometry &g) {
-  const int st64 = exact_stride(g.d);
-  const size_t esz = (g.prec == DCG_PREC_FP64) ? 0 : (g.opk == kOpF32 ? 4 : 2);
+  const bool stored = g.prec == DCG_PREC_STORED;
+  // the stored operator keeps the points, the staged vector and K0 only
+  const int st64 = stored ? 0 : exact_stride(g.d);
+  const size_t esz = (g.prec == DCG_PREC_FP64 || stored) ? 0 : (g.opk == kOpF32 ? 4 : 2);
   Carve c(nullptr, 0);
   OpLayout L;
   L.x64 = c.off = align256(c.off); c.off += size_t(g.n_pad) * g.d * 8;
   L.x64r = c.off = align256(c.off); c.off += size_t(g.n_pad) * st64 * 8;
   L.x64c = c.off = align256(c.off); c.off += size_t(g.n_pad) * st64 * 8;
   L.vin64 = c.off = align256(c.off); c.off += size_t(g.n_pad) * 8;
-  L.part64 = c.off = align256(c.off); c.off += exact_partial_doubles(g.n_pad) * 8;
+  L.part64 = c.off = align256(c.off); if (!stored) c.off += exact_partial_doubles(g.n_pad) * 8;
   L.xr = c.off = align256(c.off); c.off += size_t(g.n_pad) * g.kstride * esz;
   L.xc = c.off = align256(c.off); c.off += size_t(g.n_pad) * g.kstride * esz;
   L.vin = c.off = align256(c.off); c.off += size_t(g.n_pad) * 4 * 4;
   L.part = c.off = align256(c.off);
-  if (g.prec != DCG_PREC_FP64)
+  if (g.prec != DCG_PREC_FP64 && !stored)
     c.off += std::max(matvec_partial_floats(g.n_pad, 1, sweep_blk(g, 1)),
                       matvec_partial_floats(g.n_pad, 4, sweep_blk(g, 4))) * 4;
   L.ytmp = c.off = align256(c.off); c.off += size_t(g.n_pad) * 4 * 8;
   L.dsc = c.off = align256(c.off); c.off += size_t(g.n_pad) * 8;
   L.flag = c.off = align256(c.off); c.off += 256;
+  L.kst = c.off = align256(c.off); if (stored) c.off += size_t(g.n_pad) * g.n_pad * 4;
   L.total = align256(c.off);
   return L;
 }
@@ -384,8 +388,8 @@ using namespace dcg;
 extern "C" {
 
 size_t dcg_operator_workspace_bytes(int64_t n, int64_t d, int prec) {
-  if (n < 1 || d < 1 || d > kMaxD) return 0;
-  if (prec < DCG_PREC_FP32 || prec > DCG_PREC_FP16) return 0;
+  if (prec < DCG_PREC_FP32 || prec > DCG_PREC_STORED) return 0;
+  if (n < 1 || d < 1 || d > (prec == DCG_PREC_STORED ? kMaxStoredD : kMaxD)) return 0;
   return op_layout(make_geometry(n, static_cast<int>(d), prec)).total;
 }
 
@@ -394,9 +398,10 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel, doubl
                         dcg_op_t *out) {
   if (out == nullptr) return DCG_E_ARG;
   *out = nullptr;
-  if (X == nullptr || n < 1 || d < 1 || d > kMaxD) return DCG_E_ARG;
+  if (prec < DCG_PREC_FP32 || prec > DCG_PREC_STORED) return DCG_E_ARG;
+  if (X == nullptr || n < 1 || d < 1 || d > (prec == DCG_PREC_STORED ? kMaxStoredD : kMaxD))
+    return DCG_E_ARG;
   if (kernel < DCG_RBF || kernel > DCG_MATERN52) return DCG_E_ARG;
-  if (prec < DCG_PREC_FP32 || prec > DCG_PREC_FP16) return DCG_E_ARG;
   if (!(ell > 0.0) || !(s2 > 0.0) || !(sigma2 >= 0.0) || !std::isfinite(ell) ||
       !std::isfinite(s2) || !std::isfinite(sigma2))
     return DCG_E_ARG;
@@ -429,6 +434,7 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel, doubl
   op->part = reinterpret_cast<float *>(base + L.part);
   op->ytmp = reinterpret_cast<double *>(base + L.ytmp);
   op->dsc = reinterpret_cast<double *>(base + L.dsc);
+  op->kst = reinterpret_cast<float *>(base + L.kst);
   op->has_dsc = 0;
   op->dsc_version = 0;
   // flag word 0: non-finite input; word 1: operand preparation (fp16 range)
@@ -526,6 +532,7 @@ int dcg_matvec(dcg_op_t op, const double *V, double *Y, int64_t m) {
 
 int dcg_matvec_exact(dcg_op_t op, const double *V, double *Y, int64_t m) {
   if (op == nullptr || V == nullptr || Y == nullptr || m < 1) return DCG_E_ARG;
+  if (op->g.prec == DCG_PREC_STORED) return DCG_E_ARG;   // no FP64 operator
   return matvec_exact(op, V, Y, m);
 }
 
@@ -537,6 +544,12 @@ int dcg_set_sweep_items(dcg_op_t op, int items) {
 
 int dcg_tune_operator(dcg_op_t op, int reps, int *items_out, double *ms_out) {
   if (op == nullptr || reps < 1 || reps > 1000) return DCG_E_ARG;
+  if (op->g.prec == DCG_PREC_STORED) {
+    // one fixed streaming product: no plan to choose
+    if (items_out != nullptr) *items_out = 0;
+    if (ms_out != nullptr) *ms_out = 0.0;
+    return DCG_OK;
+  }
   hipStream_t s = op->stream;
   int best = op->sweep_items, best64 = op->exact_items;
   float ms = 0.0f, ms64 = 0.0f;

@@ -1,0 +1,158 @@
+// Log-determinant by stochastic Lanczos quadrature, from the coefficients of
+// the CG probe solves (the forward value of the GP log marginal likelihood,
+// whose gradient the probe solves already serve).
+//
+// For SPD A and a probe z, m steps of CG on A x = z from x = 0 define the
+// Lanczos tridiagonal T_m of (A, z / |z|) through their coefficients:
+//   T_00 = 1 / alpha_0,  T_jj = 1 / alpha_j + beta_{j-1} / alpha_{j-1},
+//   T_{j,j+1} = sqrt(beta_j) / alpha_j,
+// and z^T log(A) z is approximated by the m-node Gauss quadrature
+//   |z|^2 e_1^T log(T_m) e_1 = |z|^2 sum_i tau_i^2 log theta_i
+// (theta_i the eigenvalues of T_m, tau_i the first components of its unit
+// eigenvectors; Golub & Meurant).  With Rademacher probes the mean over
+// probes estimates tr log A = log det A (Hutchinson).
+//
+// The probes run as one block solve without recycling (a recycled W would
+// change the Krylov space the coefficients describe); each step records
+// alpha_j and beta_j per column on the device.  The small eigenproblems are
+// solved on the host by implicit symmetric QR steps with Wilkinson shifts
+// (Golub & Van Loan, section 8.3), carrying only the first row of the
+// eigenvector matrix.
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "blas.h"
+#include "common.h"
+
+namespace dcg {
+
+constexpr int kSlqMaxSteps = 4096;
+
+// Eigenvalues (into d) and first eigenvector components (into q, starting
+// from e_1) of the symmetric tridiagonal matrix with diagonal d[0..m) and
+// off-diagonal e[0..m-1).  Returns false if a block fails to converge.
+static bool tridiag_eig_first_row(std::vector<double> &d, std::vector<double> &e,
+                                  std::vector<double> &q) {
+  const int m = static_cast<int>(d.size());
+  q.assign(m, 0.0);
+  if (m == 0) return true;
+  q[0] = 1.0;
+  const double eps = 2.220446049250313e-16;
+  int hi = m - 1;
+  int steps = 0;
+  while (hi > 0) {
+    if (std::fabs(e[hi - 1]) <= eps * (std::fabs(d[hi - 1]) + std::fabs(d[hi]))) {
+      e[hi - 1] = 0.0;
+      --hi;
+      continue;
+    }
+    if (++steps > 50 * m) return false;
+    int lo = hi - 1;
+    while (lo > 0 && std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo]))) --lo;
+    // Wilkinson shift: the eigenvalue of the trailing 2 x 2 block nearer d[hi]
+    const double delta = 0.5 * (d[hi - 1] - d[hi]);
+    const double eh = e[hi - 1];
+    const double sg = (delta >= 0.0) ? 1.0 : -1.0;
+    const double mu = d[hi] - eh * eh / (delta + sg * std::hypot(delta, eh));
+    // implicit QR step on [lo, hi]: the first rotation brings in the shift,
+    // the rest chase the bulge down the band
+    double x = d[lo] - mu, y = e[lo];
+    for (int k = lo; k < hi; ++k) {
+      const double r = std::hypot(x, y);
+      const double c = (r == 0.0) ? 1.0 : x / r;
+      const double s = (r == 0.0) ? 0.0 : -y / r;
+      if (k > lo) e[k - 1] = r;
+      const double a = d[k], b = e[k], cc = d[k + 1];
+      d[k] = c * c * a - 2.0 * c * s * b + s * s * cc;
+      d[k + 1] = s * s * a + 2.0 * c * s * b + c * c * cc;
+      e[k] = c * s * (a - cc) + (c * c - s * s) * b;
+      if (k + 1 < hi) {
+        x = e[k];
+        y = -s * e[k + 1];
+        e[k + 1] = c * e[k + 1];
+      }
+      const double q0 = q[k], q1 = q[k + 1];
+      q[k] = c * q0 - s * q1;
+      q[k + 1] = s * q0 + c * q1;
+    }
+  }
+  return true;
+}
+
+// |z|^2 e_1^T log(T) e_1 for the tridiagonal of m CG steps.
+static int slq_quadrature(const double *alpha, const double *beta, int m, double znorm2,
+                          double *out) {
+  if (m == 0) {
+    *out = 0.0;
+    return DCG_OK;
+  }
+  std::vector<double> d(m), e(std::max(m - 1, 0)), q;
+  for (int j = 0; j < m; ++j) {
+    if (!(alpha[j] > 0.0) || !std::isfinite(alpha[j])) return DCG_E_NOT_SPD;
+    d[j] = 1.0 / alpha[j] + ((j > 0) ? beta[j - 1] / alpha[j - 1] : 0.0);
+    if (j + 1 < m) e[j] = std::sqrt(std::max(beta[j], 0.0)) / alpha[j];
+  }
+  if (!tridiag_eig_first_row(d, e, q)) return DCG_E_NONFINITE;
+  double s = 0.0;
+  for (int i = 0; i < m; ++i) {
+    if (!(d[i] > 0.0)) return DCG_E_NOT_SPD;
+    s += q[i] * q[i] * std::log(d[i]);
+  }
+  *out = znorm2 * s;
+  return DCG_OK;
+}
+
+static size_t slq_block_bytes(int64_t n, int64_t P) { return align256(dcg_solve_block_workspace_bytes(n, P)); }
+
+}  // namespace dcg
+
+using namespace dcg;
+
+extern "C" {
+
+size_t dcg_slq_logdet_workspace_bytes(int64_t n, int64_t P, int max_steps) {
+  if (n < 1 || P < 1 || P > kMaxBlockCols || max_steps < 1 || max_steps > kSlqMaxSteps) return 0;
+  return slq_block_bytes(n, P) + align256(size_t(n) * P * 8) +
+         align256(size_t(P) * 2 * max_steps * 8);
+}
+
+int dcg_slq_logdet(dcg_op_t op, const double *Z, int64_t P, const dcg_params *p, int max_steps,
+                   double *quad, int *steps, double *logdet, void *ws, size_t ws_bytes) {
+  if (op == nullptr || Z == nullptr || p == nullptr || quad == nullptr) return DCG_E_ARG;
+  if (P < 1 || P > kMaxBlockCols || max_steps < 1 || max_steps > kSlqMaxSteps) return DCG_E_ARG;
+  const int64_t n = op->g.n;
+  const size_t need = dcg_slq_logdet_workspace_bytes(n, P, max_steps);
+  if (ws == nullptr || ws_bytes < need) return DCG_E_WORKSPACE;
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return DCG_E_WORKSPACE;
+  char *b = static_cast<char *>(ws);
+  const size_t blk = slq_block_bytes(n, P);
+  double *X = reinterpret_cast<double *>(b + blk);
+  double *lz = reinterpret_cast<double *>(b + blk + align256(size_t(n) * P * 8));
+  std::vector<int> its(static_cast<size_t>(P));
+  std::vector<double> bn(static_cast<size_t>(P));
+  dcg_stats st;
+  int status = solve_block_impl(op, Z, X, P, nullptr, p, &st, ws, blk, lz, max_steps, its.data(),
+                                bn.data());
+  if (status < 0) return status;
+  std::vector<double> h(size_t(P) * 2 * max_steps);
+  if (hipMemcpyAsync(h.data(), lz, h.size() * sizeof(double), hipMemcpyDeviceToHost, op->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(op->stream) != hipSuccess)
+    return DCG_E_HIP;
+  double sum = 0.0;
+  for (int64_t c = 0; c < P; ++c) {
+    const int m = std::min(its[static_cast<size_t>(c)], max_steps);
+    const double *al = h.data() + size_t(c) * 2 * max_steps;
+    const double bn2 = bn[static_cast<size_t>(c)] * bn[static_cast<size_t>(c)];
+    const int qs = slq_quadrature(al, al + max_steps, m, bn2, &quad[c]);
+    if (qs != DCG_OK) return qs;
+    if (steps != nullptr) steps[c] = m;
+    sum += quad[c];
+  }
+  if (logdet != nullptr) *logdet = sum / static_cast<double>(P);
+  return status;
+}
+
+}  // extern "C"

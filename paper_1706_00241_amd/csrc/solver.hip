@@ -138,7 +138,7 @@ static int refresh_AW(dcg_operator_s *op, dcg_recycle_s *rc, int *matvecs) {
     // the low-precision sweep multiplies the FP32 copy of W: make W that
     // copy (it is only a basis), so that AW is A~ W to the sweep's
     // evaluation error rather than to W's rounding
-    if (op->g.prec != DCG_PREC_FP64 && !op->has_dsc)
+    if (op->g.prec != DCG_PREC_FP64 && op->g.prec != DCG_PREC_STORED && !op->has_dsc)
       enqueue_round_to_fp32(op->stream, rc->Z, n * k);
     const int st = matvec_lowprec(op, rc->Z, rc->AZ, k);
     if (st != DCG_OK) return st;
@@ -182,7 +182,7 @@ static CgArgs cg_args(dcg_operator_s *op, const SolveBuffers &B, double *x, dcg_
   CgArgs a;
   a.S = B.S;
   a.red = reduce_args(op, 1, nullptr, nullptr);
-  a.qdirect = (op->g.prec == DCG_PREC_FP64) ? op->ytmp : nullptr;
+  a.qdirect = (op->g.prec == DCG_PREC_FP64 || op->g.prec == DCG_PREC_STORED) ? op->ytmp : nullptr;
   a.mcol = 0;
   a.n = op->g.n;
   a.x = x;
@@ -209,6 +209,9 @@ static CgArgs cg_args(dcg_operator_s *op, const SolveBuffers &B, double *x, dcg_
   a.hist_beta = B.hist_beta;
   a.hist_res = B.hist_res;
   a.hist_cap = kHistCap;
+  a.lz_alpha = nullptr;
+  a.lz_beta = nullptr;
+  a.lz_cap = 0;
   a.tol = tol;
   a.max_iter = max_iter;
   return a;
@@ -223,9 +226,10 @@ static hipError_t record_event(hipEvent_t ev, hipStream_t s, bool in_graph) {
 static int enqueue_cg_step(dcg_operator_s *op, const CgArgs &a, hipEvent_t ev0 = nullptr,
                            hipEvent_t ev1 = nullptr, bool in_graph = false) {
   if (ev0 != nullptr && record_event(ev0, op->stream, in_graph) != hipSuccess) return DCG_E_HIP;
-  const int st = (op->g.prec == DCG_PREC_FP64)
-                     ? matvec_exact_done(op, a.p, op->ytmp, 1, &a.S->done)
-                     : launch_symv_sweep(op, 1, &a.S->done);
+  int st;
+  if (op->g.prec == DCG_PREC_FP64) st = matvec_exact_done(op, a.p, op->ytmp, 1, &a.S->done);
+  else if (op->g.prec == DCG_PREC_STORED) st = matvec_stored_done(op, a.p, op->ytmp, 1, &a.S->done);
+  else st = launch_symv_sweep(op, 1, &a.S->done);
   if (ev1 != nullptr && record_event(ev1, op->stream, in_graph) != hipSuccess) return DCG_E_HIP;
   if (st != DCG_OK) return st;
   hipLaunchKernelGGL(cg_matvec_finish, dim3(static_cast<unsigned>(a.nblk_q)), dim3(256), 0,
@@ -798,6 +802,8 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
       p->extraction < 0 || p->extraction > 1)
     return st->status = DCG_E_ARG;
   if (rc != nullptr && rc->n != op->g.n) return st->status = DCG_E_ARG;
+  // the stored operator has no FP64 counterpart to refine against
+  if (op->g.prec == DCG_PREC_STORED && p->refine != 0) return st->status = DCG_E_ARG;
   if (ws == nullptr || ws_bytes < solve_layout(op->g.n).total) return st->status = DCG_E_WORKSPACE;
   if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return st->status = DCG_E_WORKSPACE;
   const auto t0 = Clock::now();

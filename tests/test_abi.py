@@ -41,7 +41,11 @@ def test_workspace_queries(L):
     assert L.dcg_operator_workspace_bytes(100, 65, 1) == 0
     assert L.dcg_operator_workspace_bytes(100, 8, 7) == 0
     assert L.dcg_operator_workspace_bytes(100, 8, 4) > 0       # fp16
-    assert L.dcg_operator_workspace_bytes(100, 8, 5) == 0
+    # the stored operator: K0 in FP32 over the padded size, any d up to 4096
+    assert L.dcg_operator_workspace_bytes(1000, 784, 5) >= 1024 * 1024 * 4
+    assert L.dcg_operator_workspace_bytes(1000, 4097, 5) == 0
+    assert L.dcg_operator_workspace_bytes(1000, 784, 0) == 0     # sweep operands: d <= 64
+    assert L.dcg_operator_workspace_bytes(100, 8, 6) == 0
     assert L.dcg_recycle_workspace_bytes(1000, 8, 12) >= 1000 * 20 * 8 * 2
     assert L.dcg_recycle_workspace_bytes(1000, 8, 4) == 0       # L < k
     assert L.dcg_recycle_workspace_bytes(1000, 65, 100) == 0    # k too large

@@ -23,6 +23,12 @@ Workloads (kernel-regression systems A = K_theta(X, X) + sigma^2 I):
                  6 Gaussian modes each (centres ~ N(0, I), spread 0.7), 5%
                  of the labels flipped, RBF, ell = 0.5 x median pairwise
                  distance, s2 = 100; a stand-in for the 3-vs-5 digits set.
+* ``gpc_pixels`` the same classification loop on paper-shaped data: n=36551
+                 "images" of 28 x 28 = 784 pixels in (0, 1), x = logistic(3 B z
+                 - 2) with z ~ N(0, I_16) and B 16 Gaussian blobs (centres
+                 U[4, 24]^2, widths U[2, 5] pixels), labels the sign of a
+                 smooth random function of z (sum of 3 sines), RBF, ell =
+                 0.5 x median distance, s2 = 10.
 * ``ragged``     64 sequences, n log-uniform in [2048, 32768], d=8, RBF or
                  Matern-3/2 (fair coin), sigma2 log-uniform [1e-4, 1e-1],
                  ell_0 = median heuristic, log-ell walk 0.05, 5 systems each.
@@ -108,6 +114,23 @@ def gpc(n=36551, d=64, modes=6, spread=0.7, flip=0.05):
     y = np.where(cls == 1, 1.0, -1.0)
     y[g.random(n) < flip] *= -1.0
     return dict(X=X, y=y, kernel=RBF, ell=0.5 * median_distance(X), s2=100.0,
+                k=8, L=12, tol=1e-5, psi_tol=1.0)
+
+
+def gpc_pixels(n=36551, side=28, latent=16):
+    """Pixel-like points in (0, 1)^(side^2) and labels in {-1, +1}."""
+    g = rng(6)
+    yy, xx = np.mgrid[0:side, 0:side]
+    P = np.stack([yy.ravel(), xx.ravel()], 1).astype(np.float64)
+    C = g.uniform(4.0, side - 4.0, (latent, 2))
+    width = g.uniform(2.0, 5.0, latent)
+    B = np.exp(-((P[:, None, :] - C[None]) ** 2).sum(-1) / (2.0 * width ** 2))
+    Z = g.standard_normal((n, latent))
+    X = 1.0 / (1.0 + np.exp(-(3.0 * Z @ B.T - 2.0)))
+    Wc = g.standard_normal((latent, 3)) / np.sqrt(latent)
+    a = g.standard_normal(3)
+    y = np.where(np.sin(2.0 * Z @ Wc) @ a >= 0.0, 1.0, -1.0)
+    return dict(X=X, y=y, kernel=RBF, ell=0.5 * median_distance(X), s2=10.0,
                 k=8, L=12, tol=1e-5, psi_tol=1.0)
 
 
