@@ -71,7 +71,10 @@ enum dcg_prec {
                            time; a new ell rebuilds the matrix).  No FP64
                            operator: dcg_matvec_exact, refinement, the block,
                            batched and gradient entry points return DCG_E_ARG;
-                           dcg_tune_operator has nothing to tune             */
+                           its plan is the rows per block of the product (2,
+                           4, 8 or 16; dcg_set_sweep_items sets it,
+                           dcg_tune_operator times them and keeps the
+                           fastest)                                          */
 };
 
 enum dcg_status {
@@ -196,7 +199,7 @@ int dcg_matvec_exact(dcg_op_t op, const double *V, double *Y, int64_t m);
  * better; fewer items read fewer row partials when the product is finished.
  * Any value gives the same product up to the FP64 summation order of the
  * row partials.  DCG_E_ARG outside the range. */
-int dcg_set_sweep_items(dcg_op_t op, int items);
+int dcg_set_sweep_items(dcg_op_t op, int items);   /* stored operator: 2, 4, 8, 16 rows */
 
 /* Autotuner of the sweep plans: times `reps` single-vector sweeps (1..1000)
  * for each distinct plan of the targets 256, 512, ..., 8192 on the

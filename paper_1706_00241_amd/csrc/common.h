@@ -115,6 +115,7 @@ struct dcg_operator_s {
   float *part;           // partial sums of the symmetric matvec
   double *ytmp;          // n_pad x 4 FP64 staging for products
   float *kst;            // stored operator: K0, n_pad x n_pad FP32 row-major
+  int gemv_rows;         // stored operator: rows per block of the product (0: default)
 };
 
 struct dcg_recycle_s {

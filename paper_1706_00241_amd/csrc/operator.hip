@@ -435,6 +435,7 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel, doubl
   op->ytmp = reinterpret_cast<double *>(base + L.ytmp);
   op->dsc = reinterpret_cast<double *>(base + L.dsc);
   op->kst = reinterpret_cast<float *>(base + L.kst);
+  op->gemv_rows = 0;
   op->has_dsc = 0;
   op->dsc_version = 0;
   // flag word 0: non-finite input; word 1: operand preparation (fp16 range)
@@ -537,19 +538,22 @@ int dcg_matvec_exact(dcg_op_t op, const double *V, double *Y, int64_t m) {
 }
 
 int dcg_set_sweep_items(dcg_op_t op, int items) {
-  if (op == nullptr || items < kSweepItemsMin || items > kSweepItemsMax) return DCG_E_ARG;
+  if (op == nullptr) return DCG_E_ARG;
+  if (op->g.prec == DCG_PREC_STORED) {
+    // rows per block of the streaming product
+    if (items != 2 && items != 4 && items != 8 && items != 16) return DCG_E_ARG;
+    op->gemv_rows = items;
+    return DCG_OK;
+  }
+  if (items < kSweepItemsMin || items > kSweepItemsMax) return DCG_E_ARG;
   op->sweep_items = items;
   return DCG_OK;
 }
 
 int dcg_tune_operator(dcg_op_t op, int reps, int *items_out, double *ms_out) {
   if (op == nullptr || reps < 1 || reps > 1000) return DCG_E_ARG;
-  if (op->g.prec == DCG_PREC_STORED) {
-    // one fixed streaming product: no plan to choose
-    if (items_out != nullptr) *items_out = 0;
-    if (ms_out != nullptr) *ms_out = 0.0;
-    return DCG_OK;
-  }
+  // the stored operator's plan: rows per block of the streaming product
+  if (op->g.prec == DCG_PREC_STORED) return stored_tune(op, reps, items_out, ms_out);
   hipStream_t s = op->stream;
   int best = op->sweep_items, best64 = op->exact_items;
   float ms = 0.0f, ms64 = 0.0f;

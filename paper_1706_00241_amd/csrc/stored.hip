@@ -21,9 +21,10 @@ namespace dcg {
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 constexpr int kBuildTile = 64;   // output tile of the build (64 x 64 per block)
 constexpr int kBuildK = 16;      // coordinates per LDS stage
-constexpr int kGemvRows = 16;    // rows per block of the product
 
 // Kernel value at squared scaled distance q = |x_i - x_j|^2 / ell^2 (FP64,
 // unit amplitude): the textbook forms of the RBF and Matern kernels.
@@ -94,43 +95,65 @@ __global__ __launch_bounds__(256) void stored_stage(const double *V, int64_t n, 
   if (i < n_pad) out[i] = (i < n) ? ((dsc != nullptr) ? dsc[i] * V[i] : V[i]) : 0.0;
 }
 
-// y_i = s2 d_i (K0 xs)_i + sigma2 v_i for kGemvRows rows per block: every
-// thread streams 16-byte pieces of the block's rows (all rows' loads of one
-// piece are independent, so each thread keeps kGemvRows loads in flight),
+// y_i = s2 d_i (K0 xs)_i + sigma2 v_i for ROWS rows per block: every thread
+// streams 16-byte pieces of the block's rows, UNROLL pieces per row at a
+// time, so each thread keeps ROWS x UNROLL independent loads in flight;
 // FP64 accumulators, then a wave shuffle and an LDS step across the 4 waves.
+// K0 is read once per product with non-temporal loads, which keeps the
+// caches for xs.  Fewer rows per block mean more blocks (a shorter tail on 256 compute
+// units) but more re-reads of xs from L2; the tuner picks the variant.
+template <int ROWS, int UNROLL>
 __global__ __launch_bounds__(256) void stored_gemv(const float *K, int64_t n, int64_t n_pad,
                                                    const double *xs, double s2, double sigma2,
                                                    const double *dsc, const double *V, double *Y,
                                                    const int *done) {
   if (done != nullptr && *done != 0) return;
-  __shared__ double red[4][kGemvRows];
-  const int64_t r0 = int64_t(blockIdx.x) * kGemvRows;
-  double acc[kGemvRows];
-  for (int r = 0; r < kGemvRows; ++r) acc[r] = 0.0;
+  __shared__ double red[4][ROWS];
+  const int64_t r0 = int64_t(blockIdx.x) * ROWS;
+  double acc[ROWS];
+  for (int r = 0; r < ROWS; ++r) acc[r] = 0.0;
   const int64_t nq = n_pad / 4;
-  const float4 *K4 = reinterpret_cast<const float4 *>(K + r0 * n_pad);
+  const f32x4 *K4 = reinterpret_cast<const f32x4 *>(K + r0 * n_pad);
   const double2 *x2 = reinterpret_cast<const double2 *>(xs);
-  for (int64_t q = threadIdx.x; q < nq; q += 256) {
+  int64_t q = threadIdx.x;
+  for (; q + (UNROLL - 1) * 256 < nq; q += UNROLL * 256) {
+    f32x4 kr[UNROLL][ROWS];
+    double2 xa[UNROLL], xb[UNROLL];
+    for (int u = 0; u < UNROLL; ++u) {
+      xa[u] = x2[2 * (q + u * 256)];
+      xb[u] = x2[2 * (q + u * 256) + 1];
+      for (int r = 0; r < ROWS; ++r) kr[u][r] = __builtin_nontemporal_load(K4 + r * nq + q + u * 256);
+    }
+    for (int u = 0; u < UNROLL; ++u)
+      for (int r = 0; r < ROWS; ++r) {
+        double s = acc[r];
+        s = fma(static_cast<double>(kr[u][r].x), xa[u].x, s);
+        s = fma(static_cast<double>(kr[u][r].y), xa[u].y, s);
+        s = fma(static_cast<double>(kr[u][r].z), xb[u].x, s);
+        s = fma(static_cast<double>(kr[u][r].w), xb[u].y, s);
+        acc[r] = s;
+      }
+  }
+  for (; q < nq; q += 256) {
     const double2 xa = x2[2 * q], xb = x2[2 * q + 1];
-    float4 kr[kGemvRows];
-    for (int r = 0; r < kGemvRows; ++r) kr[r] = K4[r * nq + q];
-    for (int r = 0; r < kGemvRows; ++r) {
+    for (int r = 0; r < ROWS; ++r) {
+      const f32x4 k = __builtin_nontemporal_load(K4 + r * nq + q);
       double s = acc[r];
-      s = fma(static_cast<double>(kr[r].x), xa.x, s);
-      s = fma(static_cast<double>(kr[r].y), xa.y, s);
-      s = fma(static_cast<double>(kr[r].z), xb.x, s);
-      s = fma(static_cast<double>(kr[r].w), xb.y, s);
+      s = fma(static_cast<double>(k.x), xa.x, s);
+      s = fma(static_cast<double>(k.y), xa.y, s);
+      s = fma(static_cast<double>(k.z), xb.x, s);
+      s = fma(static_cast<double>(k.w), xb.y, s);
       acc[r] = s;
     }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int r = 0; r < kGemvRows; ++r) {
+  for (int r = 0; r < ROWS; ++r) {
     double s = acc[r];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if (lane == 0) red[wave][r] = s;
   }
   __syncthreads();
-  if (threadIdx.x < kGemvRows) {
+  if (threadIdx.x < ROWS) {
     const int r = threadIdx.x;
     const int64_t i = r0 + r;
     if (i < n) {
@@ -139,6 +162,27 @@ __global__ __launch_bounds__(256) void stored_gemv(const float *K, int64_t n, in
       Y[i] = fma(sc, s, sigma2 * V[i]);
     }
   }
+}
+
+// Rows per block of the product's variants (each divides n_pad, a multiple
+// of 256), with the unrolling that keeps 16 loads in flight per thread.
+constexpr int kGemvVariants[] = {16, 8, 4, 2};
+constexpr int kGemvDefaultRows = 4;
+
+static void launch_gemv(const dcg_operator_s *op, int rows, const double *dsc, const double *V,
+                        double *Y, const int *done) {
+  const int64_t n = op->g.n, n_pad = op->g.n_pad;
+  const dim3 g(static_cast<unsigned>(n_pad / rows)), b(256);
+#define DCG_GEMV(R, U)                                                                         \
+  hipLaunchKernelGGL((stored_gemv<R, U>), g, b, 0, op->stream, op->kst, n, n_pad, op->vin64, \
+                     op->s2, op->sigma2, dsc, V, Y, done)
+  switch (rows) {
+    case 16: DCG_GEMV(16, 1); break;
+    case 8: DCG_GEMV(8, 2); break;
+    case 2: DCG_GEMV(2, 8); break;
+    default: DCG_GEMV(4, 4); break;
+  }
+#undef DCG_GEMV
 }
 
 int stored_build_launch(const dcg_operator_s *op) {
@@ -156,11 +200,54 @@ int matvec_stored_done(const dcg_operator_s *op, const double *V, double *Y, int
   for (int64_t c = 0; c < m; ++c) {
     hipLaunchKernelGGL(stored_stage, dim3(static_cast<unsigned>(cdiv(n_pad, 256))), dim3(256), 0,
                        op->stream, V + c * n, n, n_pad, dsc, op->vin64, done);
-    hipLaunchKernelGGL(stored_gemv, dim3(static_cast<unsigned>(n_pad / kGemvRows)), dim3(256), 0,
-                       op->stream, op->kst, n, n_pad, op->vin64, op->s2, op->sigma2, dsc,
-                       V + c * n, Y + c * n, done);
+    launch_gemv(op, (op->gemv_rows > 0) ? op->gemv_rows : kGemvDefaultRows, dsc, V + c * n,
+                Y + c * n, done);
     if (hipGetLastError() != hipSuccess) return DCG_E_HIP;
   }
+  return DCG_OK;
+}
+
+// Time `reps` products with each variant (on a zero vector, so the operator
+// workspace's staged vector is overwritten) and keep the fastest.
+int stored_tune(dcg_operator_s *op, int reps, int *rows_out, double *ms_out) {
+  hipStream_t s = op->stream;
+  if (hipMemsetAsync(op->vin64, 0, size_t(op->g.n_pad) * sizeof(double), s) != hipSuccess)
+    return DCG_E_HIP;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess) return DCG_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return DCG_E_HIP;
+  }
+  int best = kGemvDefaultRows, status = DCG_OK;
+  float best_ms = -1.0f;
+  // the product writes Y = s2 K0 0 + sigma2 * V with V = Y = the zero vector
+  double *Y = op->ytmp;
+  if (hipMemsetAsync(Y, 0, size_t(op->g.n_pad) * sizeof(double), s) != hipSuccess)
+    status = DCG_E_HIP;
+  for (int rows : kGemvVariants) {
+    if (status != DCG_OK) break;
+    launch_gemv(op, rows, nullptr, Y, Y, nullptr);   // warm-up
+    if (hipEventRecord(e0, s) != hipSuccess) { status = DCG_E_HIP; break; }
+    for (int r = 0; r < reps; ++r) launch_gemv(op, rows, nullptr, Y, Y, nullptr);
+    float ms = 0.0f;
+    if (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+        hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      status = DCG_E_HIP;
+      break;
+    }
+    ms /= static_cast<float>(reps);
+    if (best_ms < 0.0f || ms < best_ms) {
+      best_ms = ms;
+      best = rows;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status != DCG_OK) return status;
+  op->gemv_rows = best;
+  if (rows_out != nullptr) *rows_out = best;
+  if (ms_out != nullptr) *ms_out = best_ms;
   return DCG_OK;
 }
 

@@ -238,6 +238,13 @@ def test_stored_matvec_parity(lib, kern, n, d):
     Y = _np(op.matvec(_dev(V)))
     err = np.abs(Y - A @ V) / (np.abs(A) @ np.abs(V))
     assert err.max() <= 2e-7, err.max()
+    # every rows-per-block variant of the product gives the same result up
+    # to the FP64 summation order
+    for rows in (2, 8, 16):
+        op.set_sweep_items(rows)
+        Yv = _np(op.matvec(_dev(V)))
+        assert np.abs(Yv - Y).max() <= 1e-13 * np.abs(Y).max()
+    op.set_sweep_items(4)
     Ae = OK.operator(X, kern, ell, s2, sigma2)
     err = np.abs(Y - Ae @ V) / (np.abs(Ae) @ np.abs(V))
     assert err.max() <= 2e-7, err.max()
@@ -256,7 +263,10 @@ def test_stored_operator_limits(lib):
     n = 400
     X = np.random.default_rng(1).uniform(0.0, 1.0, (n, 300))
     op = lib.Operator(_dev(X), 0, 5.0, 1.0, 0.5, prec=lib.PREC_STORED)
-    assert op.tune() == (0, 0.0)
+    rows, ms = op.tune()
+    assert rows in (2, 4, 8, 16) and ms > 0.0
+    with pytest.raises(lib.DcgError):
+        op.set_sweep_items(256)
     v = _dev(np.ones(n))
     with pytest.raises(lib.DcgError):
         op.matvec_exact(v)
