@@ -61,20 +61,22 @@ enum dcg_prec {
                            inside the fp16 range (dcg_create_operator and
                            dcg_set_hyper return DCG_E_ARG otherwise)          */
   DCG_PREC_STORED = 5   /* the unit-amplitude kernel matrix formed once in
-                           FP64 from the unrounded points and stored in FP32
-                           (4 n_pad^2 bytes of workspace, n_pad = n rounded up
-                           to 256; 1 <= d <= 4096): every product streams it
-                           from HBM with FP64 accumulation.  For point
+                           FP64 from the unrounded points and stored in FP32,
+                           its block upper triangle only (128 x 128 tiles:
+                           about 2 n_pad^2 bytes of workspace, n_pad = n
+                           rounded up to 256; 1 <= d <= 4096): every product
+                           streams it from HBM once, each off-diagonal tile
+                           serving its rows and its columns, with FP64
+                           accumulation.  For point
                            dimensions beyond the pair sweep's 64 and for
                            sequences that keep the kernel and lengthscale
                            (s2, sigma2 and a diagonal scaling apply at product
                            time; a new ell rebuilds the matrix).  No FP64
                            operator: dcg_matvec_exact, refinement, the block,
                            batched and gradient entry points return DCG_E_ARG;
-                           its plan is the rows per block of the product (2,
-                           4, 8 or 16; dcg_set_sweep_items sets it,
-                           dcg_tune_operator times them and keeps the
-                           fastest)                                          */
+                           its product has one plan (dcg_set_sweep_items
+                           returns DCG_E_ARG, dcg_tune_operator times it and
+                           returns the tile size, 128)                        */
 };
 
 enum dcg_status {
@@ -199,7 +201,7 @@ int dcg_matvec_exact(dcg_op_t op, const double *V, double *Y, int64_t m);
  * better; fewer items read fewer row partials when the product is finished.
  * Any value gives the same product up to the FP64 summation order of the
  * row partials.  DCG_E_ARG outside the range. */
-int dcg_set_sweep_items(dcg_op_t op, int items);   /* stored operator: 2, 4, 8, 16 rows */
+int dcg_set_sweep_items(dcg_op_t op, int items);
 
 /* Autotuner of the sweep plans: times `reps` single-vector sweeps (1..1000)
  * for each distinct plan of the targets 256, 512, ..., 8192 on the

@@ -168,7 +168,9 @@ int solve_block_impl(dcg_operator_s *op, const double *B, double *X, int64_t m,
                      size_t ws_bytes, double *lz, int lz_cap, int *col_iters, double *col_bnorm);
 // The stored operator (DCG_PREC_STORED): build K0 from the points, products.
 int stored_build_launch(const dcg_operator_s *op);
-int stored_tune(dcg_operator_s *op, int reps, int *rows_out, double *ms_out);
+int stored_tune(dcg_operator_s *op, int reps, int *items_out, double *ms_out);
+size_t stored_matrix_floats(int64_t n_pad);     // packed block upper triangle
+size_t stored_partial_doubles(int64_t n_pad);   // row and column partials of a product
 int matvec_stored_done(const dcg_operator_s *op, const double *V, double *Y, int64_t m,
                        const int *done);
 int matvec_exact(const dcg_operator_s *op, const double *V, double *Y, int64_t m);

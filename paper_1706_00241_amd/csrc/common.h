@@ -114,8 +114,8 @@ struct dcg_operator_s {
   float *vin;            // staged FP32 input vectors, n_pad x 4
   float *part;           // partial sums of the symmetric matvec
   double *ytmp;          // n_pad x 4 FP64 staging for products
-  float *kst;            // stored operator: K0, n_pad x n_pad FP32 row-major
-  int gemv_rows;         // stored operator: rows per block of the product (0: default)
+  float *kst;            // stored operator: K0's block upper triangle, packed FP32 tiles
+  double *kpart;         // stored operator: row / column partial sums of a product
 };
 
 struct dcg_recycle_s {

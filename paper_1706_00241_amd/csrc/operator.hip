@@ -306,7 +306,7 @@ static int launch_prepare(const dcg_operator_s *op) {
 // ----------------------------------------------------------- workspace
 
 struct OpLayout {
-  size_t x64, x64r, x64c, vin64, part64, xr, xc, vin, part, ytmp, dsc, flag, kst, total;
+  size_t x64, x64r, x64c, vin64, part64, xr, xc, vin, part, ytmp, dsc, flag, kst, kpart, total;
 };
 
 static OpLayout op_layout(const Geometry &g) {
@@ -331,7 +331,8 @@ static OpLayout op_layout(const Geometry &g) {
   L.ytmp = c.off = align256(c.off); c.off += size_t(g.n_pad) * 4 * 8;
   L.dsc = c.off = align256(c.off); c.off += size_t(g.n_pad) * 8;
   L.flag = c.off = align256(c.off); c.off += 256;
-  L.kst = c.off = align256(c.off); if (stored) c.off += size_t(g.n_pad) * g.n_pad * 4;
+  L.kst = c.off = align256(c.off); if (stored) c.off += stored_matrix_floats(g.n_pad) * 4;
+  L.kpart = c.off = align256(c.off); if (stored) c.off += stored_partial_doubles(g.n_pad) * 8;
   L.total = align256(c.off);
   return L;
 }
@@ -435,7 +436,7 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel, doubl
   op->ytmp = reinterpret_cast<double *>(base + L.ytmp);
   op->dsc = reinterpret_cast<double *>(base + L.dsc);
   op->kst = reinterpret_cast<float *>(base + L.kst);
-  op->gemv_rows = 0;
+  op->kpart = reinterpret_cast<double *>(base + L.kpart);
   op->has_dsc = 0;
   op->dsc_version = 0;
   // flag word 0: non-finite input; word 1: operand preparation (fp16 range)
@@ -539,12 +540,7 @@ int dcg_matvec_exact(dcg_op_t op, const double *V, double *Y, int64_t m) {
 
 int dcg_set_sweep_items(dcg_op_t op, int items) {
   if (op == nullptr) return DCG_E_ARG;
-  if (op->g.prec == DCG_PREC_STORED) {
-    // rows per block of the streaming product
-    if (items != 2 && items != 4 && items != 8 && items != 16) return DCG_E_ARG;
-    op->gemv_rows = items;
-    return DCG_OK;
-  }
+  if (op->g.prec == DCG_PREC_STORED) return DCG_E_ARG;   // a fixed tile plan
   if (items < kSweepItemsMin || items > kSweepItemsMax) return DCG_E_ARG;
   op->sweep_items = items;
   return DCG_OK;
@@ -552,7 +548,7 @@ int dcg_set_sweep_items(dcg_op_t op, int items) {
 
 int dcg_tune_operator(dcg_op_t op, int reps, int *items_out, double *ms_out) {
   if (op == nullptr || reps < 1 || reps > 1000) return DCG_E_ARG;
-  // the stored operator's plan: rows per block of the streaming product
+  // the stored operator has one plan: time it
   if (op->g.prec == DCG_PREC_STORED) return stored_tune(op, reps, items_out, ms_out);
   hipStream_t s = op->stream;
   int best = op->sweep_items, best64 = op->exact_items;

@@ -1,10 +1,17 @@
 // The stored operator: the unit-amplitude kernel matrix K0 = K(X, X) / s2
-// formed once in FP64 and kept in HBM as FP32 (n_pad x n_pad, row-major,
-// zero rows and columns past n), for point dimensions too large for the
-// matrix-free pair sweep (the classification data of section 3 has 784
-// coordinates).  K0 is fixed while only s2, sigma2 or the diagonal scaling
-// change (a Newton loop changes only D), so every product is one streaming
-// pass over 4 n_pad^2 bytes: the HBM roofline, not the kernel evaluations.
+// formed once in FP64 and kept in HBM as FP32, for point dimensions too
+// large for the matrix-free pair sweep (the classification data of section 3
+// has 784 coordinates).  K0 is fixed while only s2, sigma2 or the diagonal
+// scaling change (a Newton loop changes only D), so every product is one
+// streaming pass over the stored matrix: the HBM roofline, not the kernel
+// evaluations.
+//
+// Only the block upper triangle is kept: 128 x 128 tiles (I, J), I <= J,
+// each contiguous (row-major inside), packed row by row of tiles.  A product
+// reads every tile once and uses it twice, y_I += K_IJ x_J and (I < J)
+// y_J += K_IJ^T x_I, so it streams 2 n_pad^2 (1 + 1/nb) bytes instead of
+// 4 n_pad^2.  Each tile writes its row and column partial sums; a second
+// kernel adds a row's partials in a fixed order (deterministic results).
 //
 //   y = s2 * D (K0 (D v)) + sigma2 v      (D = I without a scaling)
 //
@@ -24,6 +31,7 @@ static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBuildTile = 64;   // output tile of the build (64 x 64 per block)
+constexpr int kSymB = 128;       // stored tile size
 constexpr int kBuildK = 16;      // coordinates per LDS stage
 
 // Kernel value at squared scaled distance q = |x_i - x_j|^2 / ell^2 (FP64,
@@ -39,13 +47,32 @@ __device__ __forceinline__ double stored_kval(int kernel, double q) {
   return (1.0 + t + t * t / 3.0) * exp(-t);
 }
 
-// K0 in 64 x 64 tiles: squared distances in difference form (no
-// cancellation, zero on the diagonal), coordinates staged through LDS 16 at
-// a time, 4 x 4 outputs per thread.  x64: n_pad x d row-major FP64 with zero
-// rows past n, so every tile's loads stay inside it.
+// Index of stored tile (I, J), I <= J, among nb x nb tiles.
+__host__ __device__ __forceinline__ int64_t sym_tile(int64_t I, int64_t J, int64_t nb) {
+  return I * nb - I * (I - 1) / 2 + (J - I);
+}
+
+size_t stored_matrix_floats(int64_t n_pad) {
+  const int64_t nb = n_pad / kSymB;
+  return size_t(nb * (nb + 1) / 2) * kSymB * kSymB;
+}
+
+size_t stored_partial_doubles(int64_t n_pad) {
+  const int64_t nb = n_pad / kSymB;
+  return size_t(nb * (nb + 1) / 2) * 2 * kSymB;
+}
+
+// K0 in 64 x 64 output tiles (those in the block upper triangle of 128 x 128
+// tiles; the others return at once): squared distances in difference form
+// (no cancellation, zero on the diagonal), coordinates staged through LDS 16
+// at a time, 4 x 4 outputs per thread.  x64: n_pad x d row-major FP64 with
+// zero rows past n, so every tile's loads stay inside it.
 __global__ __launch_bounds__(256) void stored_build(const double *x64, int64_t n, int64_t n_pad,
                                                    int d, int kernel, double inv_ell2,
-                                                   float *K) {
+                                                   int64_t nb, float *K) {
+  const int64_t I = int64_t(blockIdx.y) * kBuildTile / kSymB;
+  const int64_t J = int64_t(blockIdx.x) * kBuildTile / kSymB;
+  if (I > J) return;
   __shared__ double xa[kBuildK][kBuildTile + 1];
   __shared__ double xb[kBuildK][kBuildTile + 1];
   const int64_t i0 = int64_t(blockIdx.y) * kBuildTile, j0 = int64_t(blockIdx.x) * kBuildTile;
@@ -81,7 +108,7 @@ __global__ __launch_bounds__(256) void stored_build(const double *x64, int64_t n
       const int64_t j = j0 + tx + 16 * v;
       const float val =
           (i < n && j < n) ? static_cast<float>(stored_kval(kernel, acc[u][v] * inv_ell2)) : 0.0f;
-      K[i * n_pad + j] = val;
+      K[(sym_tile(I, J, nb) * kSymB + (i % kSymB)) * kSymB + (j % kSymB)] = val;
     }
   }
 }
@@ -95,123 +122,116 @@ __global__ __launch_bounds__(256) void stored_stage(const double *V, int64_t n, 
   if (i < n_pad) out[i] = (i < n) ? ((dsc != nullptr) ? dsc[i] * V[i] : V[i]) : 0.0;
 }
 
-// y_i = s2 d_i (K0 xs)_i + sigma2 v_i for ROWS rows per block: every thread
-// streams 16-byte pieces of the block's rows, UNROLL pieces per row at a
-// time, so each thread keeps ROWS x UNROLL independent loads in flight;
-// FP64 accumulators, then a wave shuffle and an LDS step across the 4 waves.
-// K0 is read once per product with non-temporal loads, which keeps the
-// caches for xs.  Fewer rows per block mean more blocks (a shorter tail on 256 compute
-// units) but more re-reads of xs from L2; the tuner picks the variant.
-template <int ROWS, int UNROLL>
-__global__ __launch_bounds__(256) void stored_gemv(const float *K, int64_t n, int64_t n_pad,
-                                                   const double *xs, double s2, double sigma2,
-                                                   const double *dsc, const double *V, double *Y,
-                                                   const int *done) {
+// One stored tile per block: thread (rg = t / 32, c4 = t % 32) reads the
+// 16-byte pieces c4 of rows rg, rg + 8, ..., rg + 120 (a contiguous 512-byte
+// run per row across 32 lanes, non-temporal: every tile is read once per
+// product), all 16 loads in flight at once.  Each piece gives a row partial
+// (4 products with x_J) and four column partials (times x_I).  The row
+// partials go to LDS and the first 128 threads add each row's 32; the column
+// partials (off-diagonal tiles) go to LDS and the other 128 threads add each
+// column's 8.  FP64 accumulation throughout; no cross-lane shuffles.
+__global__ __launch_bounds__(256) void stored_symv(const float *K, int64_t nb, const double *xs,
+                                                   double *part, const int *done) {
   if (done != nullptr && *done != 0) return;
-  __shared__ double red[4][ROWS];
-  const int64_t r0 = int64_t(blockIdx.x) * ROWS;
-  double acc[ROWS];
-  for (int r = 0; r < ROWS; ++r) acc[r] = 0.0;
-  const int64_t nq = n_pad / 4;
-  const f32x4 *K4 = reinterpret_cast<const f32x4 *>(K + r0 * n_pad);
-  const double2 *x2 = reinterpret_cast<const double2 *>(xs);
-  int64_t q = threadIdx.x;
-  for (; q + (UNROLL - 1) * 256 < nq; q += UNROLL * 256) {
-    f32x4 kr[UNROLL][ROWS];
-    double2 xa[UNROLL], xb[UNROLL];
-    for (int u = 0; u < UNROLL; ++u) {
-      xa[u] = x2[2 * (q + u * 256)];
-      xb[u] = x2[2 * (q + u * 256) + 1];
-      for (int r = 0; r < ROWS; ++r) kr[u][r] = __builtin_nontemporal_load(K4 + r * nq + q + u * 256);
-    }
-    for (int u = 0; u < UNROLL; ++u)
-      for (int r = 0; r < ROWS; ++r) {
-        double s = acc[r];
-        s = fma(static_cast<double>(kr[u][r].x), xa[u].x, s);
-        s = fma(static_cast<double>(kr[u][r].y), xa[u].y, s);
-        s = fma(static_cast<double>(kr[u][r].z), xb[u].x, s);
-        s = fma(static_cast<double>(kr[u][r].w), xb[u].y, s);
-        acc[r] = s;
-      }
+  __shared__ double rs[kSymB][33];   // row partials [row][lane]; padded against bank conflicts
+  __shared__ double cs[8][kSymB];    // column partials [row group][column]
+  const int64_t t = blockIdx.x;
+  // (I, J) of tile t: the largest I with sym_tile(I, I) <= t
+  const double b2 = 2.0 * double(nb) + 1.0;
+  int64_t I = static_cast<int64_t>((b2 - sqrt(fmax(b2 * b2 - 8.0 * double(t), 0.0))) * 0.5);
+  I = (I < 0) ? 0 : (I >= nb ? nb - 1 : I);
+  while (I > 0 && sym_tile(I, I, nb) > t) --I;
+  while (I + 1 < nb && sym_tile(I + 1, I + 1, nb) <= t) ++I;
+  const int64_t J = I + (t - sym_tile(I, I, nb));
+  const int tid = threadIdx.x, c4 = tid & 31, rg = tid >> 5;
+  const f32x4 *Kt = reinterpret_cast<const f32x4 *>(K + t * kSymB * kSymB);
+  const double *xI = xs + I * kSymB, *xJ = xs + J * kSymB;
+  f32x4 kv[kSymB / 8];
+  for (int k = 0; k < kSymB / 8; ++k) kv[k] = __builtin_nontemporal_load(Kt + (rg + 8 * k) * 32 + c4);
+  const double xj0 = xJ[4 * c4], xj1 = xJ[4 * c4 + 1], xj2 = xJ[4 * c4 + 2], xj3 = xJ[4 * c4 + 3];
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+  for (int k = 0; k < kSymB / 8; ++k) {
+    const double k0 = kv[k].x, k1 = kv[k].y, k2 = kv[k].z, k3 = kv[k].w;
+    rs[rg + 8 * k][c4] = fma(k3, xj3, fma(k2, xj2, fma(k1, xj1, k0 * xj0)));
+    const double xi = xI[rg + 8 * k];
+    c0 = fma(k0, xi, c0);
+    c1 = fma(k1, xi, c1);
+    c2 = fma(k2, xi, c2);
+    c3 = fma(k3, xi, c3);
   }
-  for (; q < nq; q += 256) {
-    const double2 xa = x2[2 * q], xb = x2[2 * q + 1];
-    for (int r = 0; r < ROWS; ++r) {
-      const f32x4 k = __builtin_nontemporal_load(K4 + r * nq + q);
-      double s = acc[r];
-      s = fma(static_cast<double>(k.x), xa.x, s);
-      s = fma(static_cast<double>(k.y), xa.y, s);
-      s = fma(static_cast<double>(k.z), xb.x, s);
-      s = fma(static_cast<double>(k.w), xb.y, s);
-      acc[r] = s;
-    }
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int r = 0; r < ROWS; ++r) {
-    double s = acc[r];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) red[wave][r] = s;
-  }
+  cs[rg][4 * c4] = c0;
+  cs[rg][4 * c4 + 1] = c1;
+  cs[rg][4 * c4 + 2] = c2;
+  cs[rg][4 * c4 + 3] = c3;
   __syncthreads();
-  if (threadIdx.x < ROWS) {
-    const int r = threadIdx.x;
-    const int64_t i = r0 + r;
-    if (i < n) {
-      const double s = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
-      const double sc = (dsc != nullptr) ? s2 * dsc[i] : s2;
-      Y[i] = fma(sc, s, sigma2 * V[i]);
-    }
+  double *rowp = part + t * 2 * kSymB;
+  if (tid < kSymB) {
+    double v = 0.0;
+    for (int l = 0; l < 32; ++l) v += rs[tid][l];
+    rowp[tid] = v;
+  } else if (I != J) {
+    // a diagonal tile holds both triangles: its rows cover it
+    const int c = tid - kSymB;
+    double v = 0.0;
+    for (int g = 0; g < 8; ++g) v += cs[g][c];
+    rowp[kSymB + c] = v;
   }
 }
 
-// Rows per block of the product's variants (each divides n_pad, a multiple
-// of 256), with the unrolling that keeps 16 loads in flight per thread.
-constexpr int kGemvVariants[] = {16, 8, 4, 2};
-constexpr int kGemvDefaultRows = 4;
-
-static void launch_gemv(const dcg_operator_s *op, int rows, const double *dsc, const double *V,
-                        double *Y, const int *done) {
-  const int64_t n = op->g.n, n_pad = op->g.n_pad;
-  const dim3 g(static_cast<unsigned>(n_pad / rows)), b(256);
-#define DCG_GEMV(R, U)                                                                         \
-  hipLaunchKernelGGL((stored_gemv<R, U>), g, b, 0, op->stream, op->kst, n, n_pad, op->vin64, \
-                     op->s2, op->sigma2, dsc, V, Y, done)
-  switch (rows) {
-    case 16: DCG_GEMV(16, 1); break;
-    case 8: DCG_GEMV(8, 2); break;
-    case 2: DCG_GEMV(2, 8); break;
-    default: DCG_GEMV(4, 4); break;
-  }
-#undef DCG_GEMV
+// y_i = s2 d_i (sum of row i's partials) + sigma2 v_i: the row partials of
+// tiles (I, J >= I), then the column partials of tiles (J' < I, I), in order.
+__global__ __launch_bounds__(256) void stored_sym_reduce(const double *part, int64_t nb, int64_t n,
+                                                         double s2, double sigma2,
+                                                         const double *dsc, const double *V,
+                                                         double *Y, const int *done) {
+  if (done != nullptr && *done != 0) return;
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int64_t I = i / kSymB, li = i % kSymB;
+  double s = 0.0;
+  for (int64_t J = I; J < nb; ++J) s += part[sym_tile(I, J, nb) * 2 * kSymB + li];
+  for (int64_t J = 0; J < I; ++J) s += part[sym_tile(J, I, nb) * 2 * kSymB + kSymB + li];
+  const double sc = (dsc != nullptr) ? s2 * dsc[i] : s2;
+  Y[i] = fma(sc, s, sigma2 * V[i]);
 }
 
 int stored_build_launch(const dcg_operator_s *op) {
   const int64_t tiles = op->g.n_pad / kBuildTile;
   hipLaunchKernelGGL(stored_build, dim3(static_cast<unsigned>(tiles), static_cast<unsigned>(tiles)),
                      dim3(256), 0, op->stream, op->x64, op->g.n, op->g.n_pad, op->g.d, op->kernel,
-                     1.0 / (op->ell * op->ell), op->kst);
+                     1.0 / (op->ell * op->ell), op->g.n_pad / kSymB, op->kst);
+  return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
+}
+
+static int launch_stored_product(const dcg_operator_s *op, const double *V, double *Y,
+                                 const int *done) {
+  const int64_t n = op->g.n, n_pad = op->g.n_pad, nb = n_pad / kSymB;
+  const double *dsc = op->has_dsc ? op->dsc : nullptr;
+  hipLaunchKernelGGL(stored_stage, dim3(static_cast<unsigned>(cdiv(n_pad, 256))), dim3(256), 0,
+                     op->stream, V, n, n_pad, dsc, op->vin64, done);
+  hipLaunchKernelGGL(stored_symv, dim3(static_cast<unsigned>(nb * (nb + 1) / 2)), dim3(256), 0,
+                     op->stream, op->kst, nb, op->vin64, op->kpart, done);
+  hipLaunchKernelGGL(stored_sym_reduce, dim3(static_cast<unsigned>(cdiv(n, 256))), dim3(256), 0,
+                     op->stream, op->kpart, nb, n, op->s2, op->sigma2, dsc, V, Y, done);
   return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
 }
 
 int matvec_stored_done(const dcg_operator_s *op, const double *V, double *Y, int64_t m,
                        const int *done) {
-  const int64_t n = op->g.n, n_pad = op->g.n_pad;
-  const double *dsc = op->has_dsc ? op->dsc : nullptr;
+  const int64_t n = op->g.n;
   for (int64_t c = 0; c < m; ++c) {
-    hipLaunchKernelGGL(stored_stage, dim3(static_cast<unsigned>(cdiv(n_pad, 256))), dim3(256), 0,
-                       op->stream, V + c * n, n, n_pad, dsc, op->vin64, done);
-    launch_gemv(op, (op->gemv_rows > 0) ? op->gemv_rows : kGemvDefaultRows, dsc, V + c * n,
-                Y + c * n, done);
-    if (hipGetLastError() != hipSuccess) return DCG_E_HIP;
+    const int st = launch_stored_product(op, V + c * n, Y + c * n, done);
+    if (st != DCG_OK) return st;
   }
   return DCG_OK;
 }
 
-// Time `reps` products with each variant (on a zero vector, so the operator
-// workspace's staged vector is overwritten) and keep the fastest.
-int stored_tune(dcg_operator_s *op, int reps, int *rows_out, double *ms_out) {
+// Time `reps` products (of the zero vector into the operator's staging
+// buffer); *items_out is the tile size, the product's fixed plan.
+int stored_tune(dcg_operator_s *op, int reps, int *items_out, double *ms_out) {
   hipStream_t s = op->stream;
-  if (hipMemsetAsync(op->vin64, 0, size_t(op->g.n_pad) * sizeof(double), s) != hipSuccess)
+  double *Y = op->ytmp;
+  if (hipMemsetAsync(Y, 0, size_t(op->g.n_pad) * sizeof(double), s) != hipSuccess)
     return DCG_E_HIP;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess) return DCG_E_HIP;
@@ -219,35 +239,19 @@ int stored_tune(dcg_operator_s *op, int reps, int *rows_out, double *ms_out) {
     (void)hipEventDestroy(e0);
     return DCG_E_HIP;
   }
-  int best = kGemvDefaultRows, status = DCG_OK;
-  float best_ms = -1.0f;
-  // the product writes Y = s2 K0 0 + sigma2 * V with V = Y = the zero vector
-  double *Y = op->ytmp;
-  if (hipMemsetAsync(Y, 0, size_t(op->g.n_pad) * sizeof(double), s) != hipSuccess)
+  int status = launch_stored_product(op, Y, Y, nullptr);   // warm-up
+  float ms = 0.0f;
+  if (status == DCG_OK && hipEventRecord(e0, s) != hipSuccess) status = DCG_E_HIP;
+  for (int r = 0; r < reps && status == DCG_OK; ++r) status = launch_stored_product(op, Y, Y, nullptr);
+  if (status == DCG_OK &&
+      (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+       hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
     status = DCG_E_HIP;
-  for (int rows : kGemvVariants) {
-    if (status != DCG_OK) break;
-    launch_gemv(op, rows, nullptr, Y, Y, nullptr);   // warm-up
-    if (hipEventRecord(e0, s) != hipSuccess) { status = DCG_E_HIP; break; }
-    for (int r = 0; r < reps; ++r) launch_gemv(op, rows, nullptr, Y, Y, nullptr);
-    float ms = 0.0f;
-    if (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
-        hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-      status = DCG_E_HIP;
-      break;
-    }
-    ms /= static_cast<float>(reps);
-    if (best_ms < 0.0f || ms < best_ms) {
-      best_ms = ms;
-      best = rows;
-    }
-  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (status != DCG_OK) return status;
-  op->gemv_rows = best;
-  if (rows_out != nullptr) *rows_out = best;
-  if (ms_out != nullptr) *ms_out = best_ms;
+  if (items_out != nullptr) *items_out = kSymB;
+  if (ms_out != nullptr) *ms_out = ms / static_cast<float>(reps);
   return DCG_OK;
 }
 
