@@ -122,19 +122,21 @@ __global__ __launch_bounds__(256) void stored_stage(const double *V, int64_t n, 
   if (i < n_pad) out[i] = (i < n) ? ((dsc != nullptr) ? dsc[i] * V[i] : V[i]) : 0.0;
 }
 
-// One stored tile per block: thread (rg = t / 32, c4 = t % 32) reads the
-// 16-byte pieces c4 of rows rg, rg + 8, ..., rg + 120 (a contiguous 512-byte
-// run per row across 32 lanes, non-temporal: every tile is read once per
-// product), all 16 loads in flight at once.  Each piece gives a row partial
-// (4 products with x_J) and four column partials (times x_I).  The row
-// partials go to LDS and the first 128 threads add each row's 32; the column
-// partials (off-diagonal tiles) go to LDS and the other 128 threads add each
-// column's 8.  FP64 accumulation throughout; no cross-lane shuffles.
+// One stored tile per block: thread (rg = t / 16, c = t % 16) reads the
+// 16-byte pieces c and c + 16 of rows rg, rg + 16, ..., rg + 112 (each load
+// instruction covers 256 contiguous bytes of a row across 16 lanes;
+// non-temporal, since every tile is read once per product), all 16 loads in
+// flight at once.  Each row's 8 values give a row partial (products with
+// x_J) and 8 column partials (times x_I).  Row partials go to LDS and the
+// first 128 threads add each row's 16; the column partials (off-diagonal
+// tiles) go to LDS and the other 128 threads add each column's 16.  FP64
+// accumulation throughout; no cross-lane shuffles.
 __global__ __launch_bounds__(256) void stored_symv(const float *K, int64_t nb, const double *xs,
                                                    double *part, const int *done) {
   if (done != nullptr && *done != 0) return;
-  __shared__ double rs[kSymB][33];   // row partials [row][lane]; padded against bank conflicts
-  __shared__ double cs[8][kSymB];    // column partials [row group][column]
+  constexpr int kGroups = 16, kRowsPer = kSymB / kGroups;
+  __shared__ double rs[kSymB][kGroups + 1];   // row partials [row][lane], padded
+  __shared__ double cs[kGroups][kSymB];       // column partials [row group][column]
   const int64_t t = blockIdx.x;
   // (I, J) of tile t: the largest I with sym_tile(I, I) <= t
   const double b2 = 2.0 * double(nb) + 1.0;
@@ -143,54 +145,74 @@ __global__ __launch_bounds__(256) void stored_symv(const float *K, int64_t nb, c
   while (I > 0 && sym_tile(I, I, nb) > t) --I;
   while (I + 1 < nb && sym_tile(I + 1, I + 1, nb) <= t) ++I;
   const int64_t J = I + (t - sym_tile(I, I, nb));
-  const int tid = threadIdx.x, c4 = tid & 31, rg = tid >> 5;
+  const int tid = threadIdx.x, c = tid & 15, rg = tid >> 4;
   const f32x4 *Kt = reinterpret_cast<const f32x4 *>(K + t * kSymB * kSymB);
   const double *xI = xs + I * kSymB, *xJ = xs + J * kSymB;
-  f32x4 kv[kSymB / 8];
-  for (int k = 0; k < kSymB / 8; ++k) kv[k] = __builtin_nontemporal_load(Kt + (rg + 8 * k) * 32 + c4);
-  const double xj0 = xJ[4 * c4], xj1 = xJ[4 * c4 + 1], xj2 = xJ[4 * c4 + 2], xj3 = xJ[4 * c4 + 3];
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
-  for (int k = 0; k < kSymB / 8; ++k) {
-    const double k0 = kv[k].x, k1 = kv[k].y, k2 = kv[k].z, k3 = kv[k].w;
-    rs[rg + 8 * k][c4] = fma(k3, xj3, fma(k2, xj2, fma(k1, xj1, k0 * xj0)));
-    const double xi = xI[rg + 8 * k];
-    c0 = fma(k0, xi, c0);
-    c1 = fma(k1, xi, c1);
-    c2 = fma(k2, xi, c2);
-    c3 = fma(k3, xi, c3);
+  f32x4 ka[kRowsPer], kb[kRowsPer];
+  for (int k = 0; k < kRowsPer; ++k) {
+    ka[k] = __builtin_nontemporal_load(Kt + (rg + kGroups * k) * 32 + c);
+    kb[k] = __builtin_nontemporal_load(Kt + (rg + kGroups * k) * 32 + c + 16);
   }
-  cs[rg][4 * c4] = c0;
-  cs[rg][4 * c4 + 1] = c1;
-  cs[rg][4 * c4 + 2] = c2;
-  cs[rg][4 * c4 + 3] = c3;
+  double xj[8], cp[8];
+  for (int e = 0; e < 4; ++e) {
+    xj[e] = xJ[4 * c + e];
+    xj[4 + e] = xJ[64 + 4 * c + e];
+    cp[e] = 0.0;
+    cp[4 + e] = 0.0;
+  }
+  for (int k = 0; k < kRowsPer; ++k) {
+    const double v[8] = {ka[k].x, ka[k].y, ka[k].z, ka[k].w, kb[k].x, kb[k].y, kb[k].z, kb[k].w};
+    double r = v[0] * xj[0];
+    for (int e = 1; e < 8; ++e) r = fma(v[e], xj[e], r);
+    rs[rg + kGroups * k][c] = r;
+    const double xi = xI[rg + kGroups * k];
+    for (int e = 0; e < 8; ++e) cp[e] = fma(v[e], xi, cp[e]);
+  }
+  for (int e = 0; e < 4; ++e) {
+    cs[rg][4 * c + e] = cp[e];
+    cs[rg][64 + 4 * c + e] = cp[4 + e];
+  }
   __syncthreads();
   double *rowp = part + t * 2 * kSymB;
   if (tid < kSymB) {
     double v = 0.0;
-    for (int l = 0; l < 32; ++l) v += rs[tid][l];
+    for (int l = 0; l < kGroups; ++l) v += rs[tid][l];
     rowp[tid] = v;
   } else if (I != J) {
     // a diagonal tile holds both triangles: its rows cover it
-    const int c = tid - kSymB;
+    const int col = tid - kSymB;
     double v = 0.0;
-    for (int g = 0; g < 8; ++g) v += cs[g][c];
-    rowp[kSymB + c] = v;
+    for (int g = 0; g < kGroups; ++g) v += cs[g][col];
+    rowp[kSymB + col] = v;
   }
 }
 
-// y_i = s2 d_i (sum of row i's partials) + sigma2 v_i: the row partials of
-// tiles (I, J >= I), then the column partials of tiles (J' < I, I), in order.
-__global__ __launch_bounds__(256) void stored_sym_reduce(const double *part, int64_t nb, int64_t n,
-                                                         double s2, double sigma2,
-                                                         const double *dsc, const double *V,
-                                                         double *Y, const int *done) {
+// y_i = s2 d_i (sum of row i's partials) + sigma2 v_i.  Row i of block I
+// has one partial per tile column m: the column partial of tile (m, I) for
+// m < I, the row partial of tile (I, m) for m >= I.  Eight independent
+// accumulators (m mod 8) keep eight loads in flight per thread, added in a
+// fixed order at the end; 64-thread blocks spread the rows over the chip.
+__global__ __launch_bounds__(64) void stored_sym_reduce(const double *part, int64_t nb, int64_t n,
+                                                        double s2, double sigma2,
+                                                        const double *dsc, const double *V,
+                                                        double *Y, const int *done) {
   if (done != nullptr && *done != 0) return;
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t i = int64_t(blockIdx.x) * 64 + threadIdx.x;
   if (i >= n) return;
   const int64_t I = i / kSymB, li = i % kSymB;
-  double s = 0.0;
-  for (int64_t J = I; J < nb; ++J) s += part[sym_tile(I, J, nb) * 2 * kSymB + li];
-  for (int64_t J = 0; J < I; ++J) s += part[sym_tile(J, I, nb) * 2 * kSymB + kSymB + li];
+  double acc[8];
+  for (int a = 0; a < 8; ++a) acc[a] = 0.0;
+  int64_t m = 0;
+  for (; m + 8 <= nb; m += 8)
+    for (int a = 0; a < 8; ++a) {
+      const int64_t mm = m + a;
+      acc[a] += (mm < I) ? part[sym_tile(mm, I, nb) * 2 * kSymB + kSymB + li]
+                         : part[sym_tile(I, mm, nb) * 2 * kSymB + li];
+    }
+  for (; m < nb; ++m)
+    acc[m % 8] += (m < I) ? part[sym_tile(m, I, nb) * 2 * kSymB + kSymB + li]
+                          : part[sym_tile(I, m, nb) * 2 * kSymB + li];
+  const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   const double sc = (dsc != nullptr) ? s2 * dsc[i] : s2;
   Y[i] = fma(sc, s, sigma2 * V[i]);
 }
@@ -211,7 +233,7 @@ static int launch_stored_product(const dcg_operator_s *op, const double *V, doub
                      op->stream, V, n, n_pad, dsc, op->vin64, done);
   hipLaunchKernelGGL(stored_symv, dim3(static_cast<unsigned>(nb * (nb + 1) / 2)), dim3(256), 0,
                      op->stream, op->kst, nb, op->vin64, op->kpart, done);
-  hipLaunchKernelGGL(stored_sym_reduce, dim3(static_cast<unsigned>(cdiv(n, 256))), dim3(256), 0,
+  hipLaunchKernelGGL(stored_sym_reduce, dim3(static_cast<unsigned>(cdiv(n, 64))), dim3(64), 0,
                      op->stream, op->kpart, nb, n, op->s2, op->sigma2, dsc, V, Y, done);
   return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
 }
