@@ -620,8 +620,10 @@ class GPMarginalLikelihood:
     theta = (log ell, log s2, log sigma2).
 
     forward: alpha = A^{-1} y by deflated CG with the recycled basis of `rc`
-    (refreshed by every solve), value = -1/2 y^T alpha - n/2 log(2 pi).  The
-    value leaves out -1/2 log|A|: it is not formed.
+    (refreshed by every solve), value = -1/2 y^T alpha - n/2 log(2 pi); with
+    ``GPContext(logdet=True)`` also -1/2 log|A| estimated by stochastic
+    Lanczos quadrature over the context's probes (one more block solve,
+    plain CG, since the quadrature needs the probes' own Krylov spaces).
     backward: the probe solves U = A^{-1} Z reuse the same recycled W (the
     adjoint of the symmetric solve is the same solve), then one fused sweep
     gives the full gradient, log-determinant term included (Hutchinson).
@@ -641,9 +643,10 @@ class GPMarginalLikelihood:
 
 
 class GPContext:
-    def __init__(self, op, y, rc, probes, tol=1e-6, probe_tol=None):
+    def __init__(self, op, y, rc, probes, tol=1e-6, probe_tol=None, logdet=False):
         self.op, self.y, self.rc, self.probes = op, y, rc, probes
         self.tol = tol
+        self.logdet = bool(logdet)
         self.probe_tol = tol if probe_tol is None else probe_tol
         self.last = {}
 
@@ -664,6 +667,11 @@ def _make_mll_function():
             ctx.gpc = gpc
             ctx.alpha = alpha
             value = -0.5 * float(torch.dot(gpc.y.to(alpha), alpha)) - 0.5 * op.n * math.log(2 * math.pi)
+            if gpc.logdet:
+                est, quad, steps = slq_logdet(op, gpc.probes, tol=gpc.probe_tol)
+                gpc.last["logdet"] = est
+                gpc.last["logdet_steps"] = steps
+                value -= 0.5 * est
             return theta.new_tensor(value)
 
         @staticmethod

@@ -92,3 +92,27 @@ def test_slq_rejects_bad_arguments(lib):
     op.set_diag(_dev(np.full(100, 0.5)))
     with pytest.raises(lib.DcgError):
         lib.slq_logdet(op, _dev(np.ones((100, 2))))
+
+
+def test_marginal_likelihood_value_with_logdet(lib):
+    """GPContext(logdet=True): the forward value is -1/2 y^T A^{-1} y
+    - 1/2 (SLQ log det) - n/2 log 2 pi, the SLQ term matching the mean of the
+    probes' dense z^T log(A) z."""
+    import math
+    w = workloads.small(n=900)
+    X = w["X"]
+    n = X.shape[0]
+    ell, s2, sigma2 = 1.1, 1.3, 0.05
+    y = np.random.default_rng(8).standard_normal(n)
+    Z = workloads.rademacher(n, 8, step=1)
+    op = lib.Operator(_dev(X), w["kernel"], ell, s2, sigma2, prec=3)
+    rc = lib.Recycle(n, 8, 12)
+    ctx = lib.GPContext(op, _dev(y), rc, _dev(Z), tol=1e-11, logdet=True)
+    theta = torch.tensor([math.log(ell), math.log(s2), math.log(sigma2)], dtype=torch.float64)
+    val = float(lib.GPMarginalLikelihood.apply(theta, ctx))
+    A = OK.operator(X, w["kernel"], ell, s2, sigma2)
+    lam, V = np.linalg.eigh(A)
+    ld = np.mean([Z[:, p] @ (V @ (np.log(lam) * (V.T @ Z[:, p]))) for p in range(8)])
+    ref = -0.5 * y @ np.linalg.solve(A, y) - 0.5 * ld - 0.5 * n * math.log(2 * math.pi)
+    assert abs(ctx.last["logdet"] - ld) <= 1e-7 * abs(ld)
+    assert abs(val - ref) <= 1e-7 * abs(ref), (val, ref)
