@@ -72,8 +72,9 @@ enum dcg_prec {
                            sequences that keep the kernel and lengthscale
                            (s2, sigma2 and a diagonal scaling apply at product
                            time; a new ell rebuilds the matrix).  No FP64
-                           operator: dcg_matvec_exact, refinement, the block,
-                           batched and gradient entry points return DCG_E_ARG;
+                           operator: dcg_matvec_exact, refinement, the
+                           batched and gradient entry points return DCG_E_ARG
+                           (dcg_solve_block and dcg_slq_logdet accept it);
                            its product has one plan (dcg_set_sweep_items
                            returns DCG_E_ARG, dcg_tune_operator times it and
                            returns the tile size, 128)                        */
@@ -308,7 +309,10 @@ int dcg_extract_basis(const double *Z, const double *AZ, int64_t n, int m, int k
  * are block sweeps over four columns at a time, so each kernel value is
  * evaluated once per four columns.  B, X: device FP64 n x m column-major;
  * x_{-1} = 0.  p->tol, max_iter, check_every apply per column; st->iters is
- * the largest column count, st->status the worst column status. */
+ * the largest column count, st->status the worst column status.  FP64 and
+ * stored operators form each column's product on its own and accept a
+ * diagonal scaling (dcg_set_diag); the low-precision operators refuse one
+ * (DCG_E_ARG). */
 size_t dcg_solve_block_workspace_bytes(int64_t n, int64_t m);
 int dcg_solve_block(dcg_op_t op, const double *B, double *X, int64_t m,
                     dcg_recycle_t rc, const dcg_params *p, dcg_stats *st,
@@ -372,7 +376,9 @@ int dcg_mll_grad(dcg_op_t op, const double *alpha, const double *U,
  *  Z      device FP64 n x P column-major, 1 <= P <= 64.
  *  quad   host P doubles; steps host P ints (may be NULL): steps used.
  *  ws     dcg_slq_logdet_workspace_bytes(n, P, max_steps) bytes, aligned.
- * Operators as for dcg_solve_block (no diagonal scaling, not stored).
+ * Operators as for dcg_solve_block (a diagonal scaling only on FP64 and
+ * stored operators: then log det (D K D + sigma2 I), e.g. the Laplace
+ * evidence term log det (I + D K D)).
  * Returns the block solve's status (DCG_NOT_CONVERGED if a column did not
  * reach p->tol: its quadrature still uses the steps taken), DCG_E_NOT_SPD
  * if a tridiagonal has a non-positive eigenvalue. */

@@ -128,8 +128,11 @@ int dcg::solve_block_impl(dcg_op_t op, const double *B, double *X, int64_t m, dc
   if (st == nullptr) st = &local;
   std::memset(st, 0, sizeof(*st));
   if (op == nullptr || B == nullptr || X == nullptr || p == nullptr) return st->status = DCG_E_ARG;
-  // not supported with a diagonal scaling or the stored operator
-  if (op->has_dsc || op->g.prec == DCG_PREC_STORED) return st->status = DCG_E_ARG;
+  // products finished per column (FP64 and stored operators) take any
+  // diagonal scaling; the four-column low-precision sweep takes none
+  const bool stored = op->g.prec == DCG_PREC_STORED;
+  const bool direct = op->g.prec == DCG_PREC_FP64 || stored;
+  if (op->has_dsc && !direct) return st->status = DCG_E_ARG;
   if (m < 1 || m > kMaxBlockCols || !(p->tol >= 0.0)) return st->status = DCG_E_ARG;
   if (rc != nullptr && rc->n != op->g.n) return st->status = DCG_E_ARG;
   const int64_t n = op->g.n, n_pad = op->g.n_pad;
@@ -155,7 +158,6 @@ int dcg::solve_block_impl(dcg_op_t op, const double *B, double *X, int64_t m, dc
   double *gemm = reinterpret_cast<double *>(base + Lb.gemm);
   const size_t gemm_cap = size_t(64) * kMaxK * m;
   const int max_iter = p->max_iter > 0 ? p->max_iter : static_cast<int>(std::min<int64_t>(10 * n, 1 << 30));
-  const bool fp64 = op->g.prec == DCG_PREC_FP64;
 
   int matvecs = 0;
   int k = 0;
@@ -197,8 +199,8 @@ int dcg::solve_block_impl(dcg_op_t op, const double *B, double *X, int64_t m, dc
     CgArgs &a = args[static_cast<size_t>(c)];
     std::memset(&a, 0, sizeof(a));
     a.S = S + c;
-    if (!fp64) a.red = reduce_args(op, 4, nullptr, nullptr);
-    a.qdirect = fp64 ? Q + c * n : nullptr;
+    if (!direct) a.red = reduce_args(op, 4, nullptr, nullptr);
+    a.qdirect = direct ? Q + c * n : nullptr;
     a.mcol = static_cast<int>(c % 4);
     a.n = n;
     a.x = X + c * n;
@@ -242,9 +244,10 @@ int dcg::solve_block_impl(dcg_op_t op, const double *B, double *X, int64_t m, dc
   int sweeps = 0;
   while (true) {
     for (int step = 0; step < chunk; ++step) {
-      if (fp64) {
+      if (direct) {
         for (int64_t c = 0; c < m; ++c) {
-          const int rcode = matvec_exact_done(op, P + c * n, Q + c * n, 1, &S[c].done);
+          const int rcode = stored ? matvec_stored_done(op, P + c * n, Q + c * n, 1, &S[c].done)
+                                   : matvec_exact_done(op, P + c * n, Q + c * n, 1, &S[c].done);
           if (rcode != DCG_OK) return st->status = rcode;
         }
         hipLaunchKernelGGL(cg_matvec_finish_multi, dim3(static_cast<unsigned>(nq), static_cast<unsigned>(m)),
@@ -281,7 +284,7 @@ int dcg::solve_block_impl(dcg_op_t op, const double *B, double *X, int64_t m, dc
     else if (status == DCG_OK && x.relres > p->tol) status = DCG_NOT_CONVERGED;
   }
   st->iters = iters;
-  st->matvecs = matvecs + (fp64 ? iters * static_cast<int>(m) : sweeps * 4);
+  st->matvecs = matvecs + (direct ? iters * static_cast<int>(m) : sweeps * 4);
   st->k_used = k;
   st->k_next = k;
   st->rel_res_recursive = worst;

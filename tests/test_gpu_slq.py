@@ -89,6 +89,8 @@ def test_slq_rejects_bad_arguments(lib):
         lib.slq_logdet(op, _dev(np.ones((100, 65))))        # more than 64 probes
     with pytest.raises(lib.DcgError):
         lib.slq_logdet(op, _dev(np.ones((100, 2))), max_steps=0)
+    # a diagonal scaling on a low-precision operator: the four-column sweep
+    # takes none
     op.set_diag(_dev(np.full(100, 0.5)))
     with pytest.raises(lib.DcgError):
         lib.slq_logdet(op, _dev(np.ones((100, 2))))
