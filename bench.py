@@ -89,6 +89,8 @@ def parse():
                          "(the paper's own test problem, the whole Newton loop per step) on "
                          "784-pixel data with the stored kernel matrix; gpc64: the same loop "
                          "at d = 64 with the matrix-free FP32 operator")
+    ap.add_argument("--gpc-stored", action="store_true",
+                    help="gpc64: use the stored kernel matrix instead of the matrix-free sweep")
     ap.add_argument("--adam-steps", type=int, default=50,
                     help="gp_hyper: Adam steps in all (the first --warmup are not timed)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -294,8 +296,8 @@ def main_gpc(args):
     import workloads
 
     dcg.load()
-    stored = args.workload == "gpc"
-    w = workloads.gpc_pixels() if stored else workloads.gpc()
+    stored = args.workload == "gpc" or args.gpc_stored
+    w = workloads.gpc_pixels() if args.workload == "gpc" else workloads.gpc()
     n, d = w["X"].shape
     dev = torch.device("cuda:0")
     X = torch.as_tensor(w["X"], device=dev)
@@ -326,13 +328,15 @@ def main_gpc(args):
     for t, s in enumerate(stats):
         print(f"newton {t + 1}: {s['iters']} its, {s['matvecs']} matvecs, "
               f"{s['t_total_ms']:.2f} ms, psi {psi[t + 1]:.3f}", file=sys.stderr, flush=True)
-    if stored:
+    if args.workload == "gpc":
         data = (f"gpc: n={n} d={d} pixel-like points in (0,1) (logistic of 16 Gaussian blobs), "
                 f"labels from a smooth random function, RBF ell=0.5 x median distance s2=10")
-        dtype = "f32 stored kernel matrix (formed in f64), f64 accumulation, CG and Newton terms"
     else:
         data = (f"gpc64: n={n} d={d}, two classes of 6 Gaussian modes, 5% labels flipped, "
                 f"RBF ell=0.5 x median distance s2=100")
+    if stored:
+        dtype = "f32 stored kernel matrix (formed in f64), f64 accumulation, CG and Newton terms"
+    else:
         dtype = "fp32 points on fp32 MFMA, f32 kernel values, f64 CG and Newton terms"
     out = {
         "metric": f"ms per Laplace-GPC mode (whole Newton loop), def-CG(8,12) to 1e-5, "
