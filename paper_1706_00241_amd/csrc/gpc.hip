@@ -14,8 +14,6 @@
 
 #include <algorithm>
 #include <cmath>
-#include <cstring>
-#include <vector>
 
 #include "blas.h"
 #include "common.h"

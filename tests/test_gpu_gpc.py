@@ -362,3 +362,21 @@ def test_stored_block_solve_and_slq_with_scaling(lib):
     lam, V = np.linalg.eigh(A)
     ref = np.array([Z[:, p] @ (V @ (np.log(lam) * (V.T @ Z[:, p]))) for p in range(6)])
     np.testing.assert_allclose(quad, ref, rtol=1e-7)
+
+
+@pytest.mark.parametrize("prec", [0, 5])
+def test_laplace_gpc_deterministic(lib, prec):
+    """Two runs of the Newton loop (fresh recycle handles) give bitwise equal
+    f, a and Psi: every reduction, the stored operator's partial sums
+    included, adds in a fixed order."""
+    w = workloads.gpc_pixels(n=1200) if prec == 5 else workloads.gpc(n=1200, d=16)
+    X, y = w["X"], w["y"]
+    n = X.shape[0]
+    op = lib.Operator(_dev(X), w["kernel"], w["ell"], w["s2"], 0.0, prec=prec)
+    runs = []
+    for _ in range(2):
+        rc = lib.Recycle(n, w["k"], w["L"])
+        runs.append(lib.laplace_gpc(op, _dev(y), rc=rc, tol=w["tol"], psi_tol=w["psi_tol"]))
+    (f1, a1, p1, s1, _), (f2, a2, p2, s2, _) = runs
+    assert torch.equal(f1, f2) and torch.equal(a1, a2)
+    assert p1 == p2 and [s["iters"] for s in s1] == [s["iters"] for s in s2]
