@@ -9,7 +9,7 @@ iterates: ``cg`` simply calls ``defcg`` with no W, which is the paper's own
 statement that the first system of a sequence is solved by normal CG (Fig. 1
 caption).
 
-Readings of the paper used here (each is listed in the design doc):
+Readings of the paper used here:
 * residual sign r = b - A x (Algorithm 1), not the gradient sign of Eq. 2;
 * stopping test on the recursive relative residual |r_j|_2 / |b|_2 <= tol,
   checked before each iteration (the relative error of section 3);

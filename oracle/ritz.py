@@ -11,7 +11,7 @@ largest theta (Fig. 1 caption); selecting the smallest is an option.
 F is symmetric in exact arithmetic (A is); it is symmetrised, as is G.  When
 F is SPD the pairs are those of ``scipy.linalg.eigh(G, F)``.  When loss of
 A-conjugacy makes F numerically singular the problem is solved in the range
-of F (reading of the paper's silence on this case, listed in the design doc):
+of F (a reading where the paper is silent on this case):
 
     S = diag(F)^(-1/2),  S F S = Q Lam Q^T,  keep lam > drop_tol * max(lam),
     B = S Q_keep Lam_keep^(-1/2)      (B^T F B = I)

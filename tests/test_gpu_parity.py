@@ -1,6 +1,6 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
-Tolerances (derivation in DESIGN.md, "Parity tolerances"):
+Tolerances:
 * low-precision products: |y_gpu - y_ref|_i <= 2e-5 * (|A| |v|)_i, with y_ref
   the oracle's FP64 product on the *same rounded points* (the operator is the
   exact kernel matrix of the rounded points; the only error left is FP32
