@@ -54,6 +54,13 @@ def test_workspace_queries(L):
     assert L.dcg_laplace_gpc_workspace_bytes(1000) >= \
         L.dcg_solve_workspace_bytes(1000, 0, 0) + 3 * 1000 * 8
     assert L.dcg_laplace_gpc_workspace_bytes(0) == 0
+    # SLQ: the block solve's workspace, the probe solutions and 2 x max_steps
+    # coefficients per probe
+    assert L.dcg_slq_logdet_workspace_bytes(1000, 16, 512) >= \
+        L.dcg_solve_block_workspace_bytes(1000, 16) + 1000 * 16 * 8 + 16 * 2 * 512 * 8
+    assert L.dcg_slq_logdet_workspace_bytes(1000, 65, 512) == 0
+    assert L.dcg_slq_logdet_workspace_bytes(1000, 16, 0) == 0
+    assert L.dcg_slq_logdet_workspace_bytes(1000, 16, 4097) == 0
 
 
 def test_argument_validation_without_gpu(L):
@@ -81,6 +88,8 @@ def test_argument_validation_without_gpu(L):
     assert L.dcg_laplace_gpc(None, None, None, ctypes.byref(p), 5, 1.0, None, None, None,
                              ctypes.byref(steps), None, None, 0) == -1
     assert steps.value == 0
+    quad = (ctypes.c_double * 2)()
+    assert L.dcg_slq_logdet(None, None, 2, ctypes.byref(p), 64, quad, None, None, None, 0) == -1
     assert L.dcg_status_string(-2).decode().startswith("operator not positive")
     assert "gfx950" in L.dcg_version().decode()
 
