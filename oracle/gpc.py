@@ -64,3 +64,16 @@ def laplace_mode(K, y, solve=None, psi_tol=1.0, max_newton=50, f0=None):
         if psi[-1] - psi[-2] < psi_tol:
             break
     return f, a, psi, systems
+
+
+def log_evidence(K, y, f, a):
+    """The Laplace approximation to log p(y | X) at the mode f (f = K a):
+    Psi(f) - 1/2 log det(I + D K D), D = H^(1/2) (the third term of the
+    objective whose first two terms stop the Newton loop)."""
+    _, H, _ = newton_terms(y, f)
+    D = np.sqrt(H)
+    B = np.eye(len(f)) + D[:, None] * np.asarray(K) * D[None, :]
+    sign, logdet = np.linalg.slogdet(B)
+    assert sign > 0
+    psi = log_lik(y, f) - 0.5 * (np.asarray(a) @ np.asarray(f))
+    return psi - 0.5 * logdet, psi, logdet
