@@ -422,6 +422,20 @@ int dcg_laplace_gpc(dcg_op_t op, const double *y, dcg_recycle_t rc,
                     double *f, double *a, double *psi, int *newton_steps,
                     dcg_stats *stats, void *ws, size_t ws_bytes);
 
+/* The Laplace approximation to the log evidence at a mode f (f = K a, as
+ * dcg_laplace_gpc returns them): Psi(f) - 1/2 log det(I + D K D), D = H^{1/2}
+ * at f (the third term of the objective, Eq. 8), the determinant by
+ * stochastic Lanczos quadrature (dcg_slq_logdet) over the P probe columns of
+ * Z on the operator scaled by D with a unit shift.  FP64 and stored operators
+ * only, without a scaling of their own (DCG_E_ARG otherwise); the operator
+ * leaves unscaled with its own shift.  evidence (host) required; psi and
+ * logdet (host) may be NULL.  Returns the probe solve's status. */
+size_t dcg_laplace_evidence_workspace_bytes(int64_t n, int64_t P, int max_steps);
+int dcg_laplace_evidence(dcg_op_t op, const double *y, const double *f,
+                         const double *a, const double *Z, int64_t P,
+                         const dcg_params *p, int max_steps, double *evidence,
+                         double *psi, double *logdet, void *ws, size_t ws_bytes);
+
 /* Human-readable name of a status code (static string). */
 const char *dcg_status_string(int status);
 

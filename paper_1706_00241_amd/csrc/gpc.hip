@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "blas.h"
 #include "common.h"
@@ -245,6 +246,58 @@ int dcg_laplace_gpc(dcg_op_t op, const double *y, dcg_recycle_t rc, const dcg_pa
   op->generation += 1;
   if (newton_steps != nullptr) *newton_steps = steps;
   if (hipStreamSynchronize(s) != hipSuccess && code >= 0) code = DCG_E_HIP;
+  return code;
+}
+
+size_t dcg_laplace_evidence_workspace_bytes(int64_t n, int64_t P, int max_steps) {
+  const size_t slq = dcg_slq_logdet_workspace_bytes(n, P, max_steps);
+  if (slq == 0) return 0;
+  return align256(slq) + align256(size_t(n) * 8) + align256(kPsiBlocks * 8);
+}
+
+int dcg_laplace_evidence(dcg_op_t op, const double *y, const double *f, const double *a,
+                         const double *Z, int64_t P, const dcg_params *p, int max_steps,
+                         double *evidence, double *psi, double *logdet, void *ws,
+                         size_t ws_bytes) {
+  if (op == nullptr || y == nullptr || f == nullptr || a == nullptr || Z == nullptr ||
+      p == nullptr || evidence == nullptr)
+    return DCG_E_ARG;
+  // the probe solves take the scaling only where each product is formed on
+  // its own (FP64 and stored operators)
+  if (op->has_dsc || (op->g.prec != DCG_PREC_FP64 && op->g.prec != DCG_PREC_STORED))
+    return DCG_E_ARG;
+  const size_t need = dcg_laplace_evidence_workspace_bytes(op->g.n, P, max_steps);
+  if (need == 0) return DCG_E_ARG;
+  if (ws == nullptr || ws_bytes < need) return DCG_E_WORKSPACE;
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return DCG_E_WORKSPACE;
+  const int64_t n = op->g.n, n_pad = op->g.n_pad;
+  const size_t slq = align256(dcg_slq_logdet_workspace_bytes(n, P, max_steps));
+  char *b = static_cast<char *>(ws);
+  double *bt = reinterpret_cast<double *>(b + slq);
+  double *part = reinterpret_cast<double *>(b + slq + align256(size_t(n) * 8));
+  double ps = 0.0;
+  int code = psi_value(op, y, f, a, part, &ps);
+  if (code != DCG_OK) return code;
+  // D = H^{1/2} at f into the operator's scaling; B = I + D K D
+  hipLaunchKernelGGL(gpc_terms, dim3(static_cast<unsigned>(cdiv(n_pad, 256))), dim3(256), 0,
+                     op->stream, y, f, n, n_pad, op->dsc, bt);
+  if (hipGetLastError() != hipSuccess) return DCG_E_HIP;
+  const double sigma2_user = op->sigma2;
+  op->sigma2 = 1.0;
+  op->has_dsc = 1;
+  op->dsc_version += 1;
+  op->generation += 1;
+  std::vector<double> quad(static_cast<size_t>(P));
+  double ld = 0.0;
+  code = dcg_slq_logdet(op, Z, P, p, max_steps, quad.data(), nullptr, &ld, ws, slq);
+  op->has_dsc = 0;
+  op->sigma2 = sigma2_user;
+  op->dsc_version += 1;
+  op->generation += 1;
+  if (code < 0) return code;
+  *evidence = ps - 0.5 * ld;
+  if (psi != nullptr) *psi = ps;
+  if (logdet != nullptr) *logdet = ld;
   return code;
 }
 

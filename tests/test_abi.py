@@ -61,6 +61,9 @@ def test_workspace_queries(L):
     assert L.dcg_slq_logdet_workspace_bytes(1000, 65, 512) == 0
     assert L.dcg_slq_logdet_workspace_bytes(1000, 16, 0) == 0
     assert L.dcg_slq_logdet_workspace_bytes(1000, 16, 4097) == 0
+    assert L.dcg_laplace_evidence_workspace_bytes(1000, 16, 512) > \
+        L.dcg_slq_logdet_workspace_bytes(1000, 16, 512) + 1000 * 8
+    assert L.dcg_laplace_evidence_workspace_bytes(1000, 65, 512) == 0
 
 
 def test_argument_validation_without_gpu(L):

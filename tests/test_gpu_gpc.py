@@ -380,3 +380,40 @@ def test_laplace_gpc_deterministic(lib, prec):
     (f1, a1, p1, s1, _), (f2, a2, p2, s2, _) = runs
     assert torch.equal(f1, f2) and torch.equal(a1, a2)
     assert p1 == p2 and [s["iters"] for s in s1] == [s["iters"] for s in s2]
+
+
+@pytest.mark.parametrize("prec", [3, 5])
+def test_laplace_evidence_matches_oracle(lib, prec):
+    """Laplace log evidence at the GPU's mode: Psi equals the oracle's Psi of
+    the same (f, a); the SLQ log det(I + D K D) equals the mean of the
+    probes' dense z^T log(B) z (B formed by the oracle at the same f) to
+    1e-7; the evidence is Psi - 1/2 log det."""
+    if prec == 5:
+        w = workloads.gpc_pixels(n=700)
+        Km = _stored_ref(w["X"], w["kernel"], w["ell"], w["s2"])
+    else:
+        w = workloads.gpc(n=700, d=8)
+        Km = OK.gram(w["X"], w["kernel"], w["ell"], w["s2"])
+    X, y = w["X"], w["y"]
+    n = X.shape[0]
+    op = lib.Operator(_dev(X), w["kernel"], w["ell"], w["s2"], 0.25, prec=prec)
+    f, a, psi, _, status = lib.laplace_gpc(op, _dev(y), rc=lib.Recycle(n, 8, 12), tol=1e-10)
+    assert status == 0
+    Z = workloads.rademacher(n, 16, step=3)
+    ev, ps, ld = lib.laplace_evidence(op, _dev(y), f, a, _dev(Z), tol=1e-10)
+    f, a = _np(f), _np(a)
+    _, ps_o, ld_exact = OG.log_evidence(Km, y, f, a)
+    assert abs(ps - ps_o) <= 1e-10 * abs(ps_o)
+    assert abs(ps - psi[-1]) <= 1e-10 * abs(ps_o)
+    _, H, _ = OG.newton_terms(y, f)
+    D = np.sqrt(H)
+    B = np.eye(n) + D[:, None] * Km * D[None, :]
+    lam, V = np.linalg.eigh(B)
+    ref = np.mean([Z[:, p] @ (V @ (np.log(lam) * (V.T @ Z[:, p]))) for p in range(16)])
+    assert abs(ld - ref) <= 1e-7 * abs(ref), (ld, ref, ld_exact)
+    assert abs(ev - (ps - 0.5 * ld)) <= 1e-12 * abs(ev)
+    # the operator leaves unscaled with its own shift
+    v = np.random.default_rng(3).standard_normal(n)
+    A0 = Km + 0.25 * np.eye(n)
+    err = np.abs(_np(op.matvec(_dev(v))) - A0 @ v) / (np.abs(A0) @ np.abs(v))
+    assert err.max() <= 2e-7
