@@ -417,3 +417,21 @@ def test_laplace_evidence_matches_oracle(lib, prec):
     A0 = Km + 0.25 * np.eye(n)
     err = np.abs(_np(op.matvec(_dev(v))) - A0 @ v) / (np.abs(A0) @ np.abs(v))
     assert err.max() <= 2e-7
+
+
+@pytest.mark.parametrize("kern", [1, 2])
+def test_stored_laplace_gpc_matern(lib, kern):
+    """The Newton loop on the stored operator with the Matern kernels
+    (n = 800, d = 784) against the oracle's dense-solve loop on s2 fp32(K0)."""
+    w = workloads.gpc_pixels(n=800)
+    X, y = w["X"], w["y"]
+    n = X.shape[0]
+    Km = _stored_ref(X, kern, w["ell"], w["s2"])
+    f_ref, a_ref, psi_ref, _ = OG.laplace_mode(Km, y, psi_tol=w["psi_tol"])
+    op = lib.Operator(_dev(X), kern, w["ell"], w["s2"], 0.0, prec=lib.PREC_STORED)
+    f, a, psi, stats, status = lib.laplace_gpc(op, _dev(y), rc=lib.Recycle(n, 8, 12), tol=1e-10,
+                                               psi_tol=w["psi_tol"])
+    assert status == 0 and len(psi) == len(psi_ref)
+    np.testing.assert_allclose(psi, psi_ref, rtol=1e-8)
+    f = _np(f)
+    assert np.abs(f - f_ref).max() <= 1e-6 * np.abs(f_ref).max()
