@@ -19,6 +19,14 @@ Readings of the paper used here:
 * the first L directions p_0 .. p_{L-1} are stored together with A p_j and
   the scalars of that step (P_L of section 2.3).
 
+``reproject=True`` adds one step that Algorithm 1 does not have: after each
+update of x and r, the component of r that W^T r_j = 0 excludes in exact
+arithmetic is removed again, c = (W^T A W)^{-1} W^T r, x += W c, r -= (AW) c,
+before rho, beta, mu and the next direction are formed.  In exact arithmetic
+c = 0 and the iterates are Algorithm 1's; with rounding or inexact products
+it keeps W^T r_j at rounding level instead of letting it grow.  The library
+iterates this way; the literal Algorithm 1 stays the default here.
+
 ``A`` may be a dense matrix or a callable v -> A v.
 """
 
@@ -51,7 +59,7 @@ class DefCGResult:
 
 
 def defcg(A, b, x_init=None, W=None, AW=None, tol=1e-8, L=0, max_iter=None,
-          store_all=False):
+          store_all=False, reproject=False):
     """Deflated CG (Algorithm 1).  W (n x k) empty or None gives plain CG.
 
     Parameters
@@ -63,6 +71,7 @@ def defcg(A, b, x_init=None, W=None, AW=None, tol=1e-8, L=0, max_iter=None,
     tol      relative residual tolerance
     L        number of leading iterations whose directions are stored
     store_all  also keep every residual (for invariant tests)
+    reproject  remove W^T r from r after every step (see the module notes)
     """
     mv = _as_matvec(A)
     b = np.asarray(b, dtype=np.float64)
@@ -122,6 +131,10 @@ def defcg(A, b, x_init=None, W=None, AW=None, tol=1e-8, L=0, max_iter=None,
             res.alpha.append(alpha)
         x = x + alpha * p
         r = r - alpha * q
+        if deflate and reproject:
+            c = msolve(W.T @ r)
+            x = x + W @ c
+            r = r - AW @ c
         rho_new = r @ r
         beta = rho_new / rho
         rho = rho_new

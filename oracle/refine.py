@@ -23,7 +23,7 @@ from . import ritz as _ritz
 
 
 def refine(A64, A_low, b, tol=1e-8, inner_tol=1e-4, k=0, L=0, max_outer=20, extract="every",
-           W=None, AW=None):
+           W=None, AW=None, reproject=False):
     """Returns (x, history of |r_t|/|b|, list of inner DefCGResult, (W, AW)).
 
     extract (with k > 0) says when the recycled basis is refreshed (section
@@ -33,7 +33,8 @@ def refine(A64, A_low, b, tol=1e-8, inner_tol=1e-4, k=0, L=0, max_outer=20, extr
                for all inner solves of one call);
       "accum": once, after the last inner solve, from the directions of the
                inner solves in order, up to L of them (W is unchanged meanwhile).
-    W, AW: a basis carried in (AW its product with A~)."""
+    W, AW: a basis carried in (AW its product with A~).
+    reproject: passed to the inner ``defcg`` (remove W^T r after every step)."""
     mv64 = A64 if callable(A64) else (lambda v, A=np.asarray(A64): A @ v)
     mvl = A_low if callable(A_low) else (lambda v, A=np.asarray(A_low): A @ v)
     if extract not in ("every", "first", "accum"):
@@ -56,7 +57,7 @@ def refine(A64, A_low, b, tol=1e-8, inner_tol=1e-4, k=0, L=0, max_outer=20, extr
             store = L - sum(P.shape[1] for P in P_acc)
         else:
             store = 0
-        res = _cg.defcg(mvl, r, W=W, AW=AW, tol=inner_tol, L=store)
+        res = _cg.defcg(mvl, r, W=W, AW=AW, tol=inner_tol, L=store, reproject=reproject)
         inner.append(res)
         x = x + res.x
         if store > 0 and res.P.shape[1] > 0:
