@@ -84,9 +84,13 @@ enum dcg_status {
   DCG_OK = 0,
   DCG_NOT_CONVERGED = 1,   /* max_iter reached; x and stats are valid      */
   DCG_E_ARG = -1,          /* invalid argument (size, pointer, enum value)  */
-  DCG_E_NOT_SPD = -2,      /* p^T A p <= 0 or W^T A W not positive definite */
-  DCG_E_NONFINITE = -3,    /* NaN/Inf met in the iteration                  */
-  DCG_E_W_RANK = -4,       /* recycled basis numerically rank deficient     */
+  DCG_E_NOT_SPD = -2,      /* p^T A p <= 0 in the iteration                 */
+  DCG_E_NONFINITE = -3,    /* NaN/Inf met in the iteration, or in W^T A W   */
+  DCG_E_W_RANK = -4,       /* recycled basis numerically rank deficient: a
+                              Cholesky pivot of W^T A W is at most 1e-12 of
+                              the diagonal entry it started from (e.g. W with
+                              repeated columns); found when a solve starts,
+                              before its first CG step                      */
   DCG_E_HIP = -5,          /* a HIP runtime call failed                     */
   DCG_E_WORKSPACE = -6     /* workspace too small or misaligned             */
 };
@@ -111,7 +115,8 @@ typedef struct {
                           product; always done when refine > 0)              */
   int profile;         /* 1: time every matvec sweep with HIP events on the
                           operator's stream (recorded inside the iteration
-                          graph when use_graph = 1)                          */
+                          graph when use_graph = 1), and with refine = 1 the
+                          FP64 pair sweep of every refinement residual      */
   int refresh_every;   /* refine > 0 only, when the inner solves refresh W:
                           0 after the first inner solve of each dcg_solve
                           call (the operator does not change between them),
@@ -150,6 +155,11 @@ typedef struct {
   int refresh_rank;          /* of them kept after dropping F's null space   */
   int refresh_sweeps[2];     /* Jacobi sweeps of its two eigenproblems (the
                                 first is 0 when F was reduced by Cholesky)  */
+  int exact_sweeps_timed;    /* profile = 1, refine = 1: FP64 pair sweeps of
+                                the refinement residuals timed              */
+  double t_exact_sweeps_ms;  /* profile = 1, refine = 1: their summed device
+                                time (HIP events on the operator's stream
+                                around each sweep kernel)                   */
 } dcg_stats;
 
 /* ---------------------------------------------------------------- operator
@@ -229,7 +239,10 @@ int dcg_recycle_create(int64_t n, int k, int L, void *workspace,
                        size_t ws_bytes, dcg_recycle_t *out);
 
 /* Set W from a device FP64 n x kw block (kw <= k, kw = 0 clears it); AW is
- * recomputed for the operator of the next solve. */
+ * recomputed for the operator of the next solve.  The columns are not
+ * checked here: the next solve returns DCG_E_W_RANK, before any CG step,
+ * if they are numerically dependent against A (repeated columns, say), and
+ * DCG_E_NONFINITE if W^T A W holds a NaN or Inf. */
 int dcg_recycle_set_W(dcg_recycle_t rc, const double *W, int kw);
 
 /* Copy the current W (n x k_used) to the device array W_out (may be NULL)
@@ -293,7 +306,7 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given,
  *  rank_out   host int (may be NULL): directions of F kept.
  *  stream     HIP stream of the call (NULL: the null stream); the call
  *             returns once the results are in place.
- *  ws         device workspace of dcg_harmonic_ritz_workspace_bytes(n, m)
+ *  ws         device workspace of dcg_extract_basis_workspace_bytes(n, m)
  *             bytes, 256-byte aligned, caller-owned.
  * Errors: DCG_E_ARG (null pointer, sizes, extraction or route out of
  * range), DCG_E_WORKSPACE, DCG_E_HIP. */
@@ -361,6 +374,20 @@ int dcg_mll_grad(dcg_op_t op, const double *alpha, const double *U,
                  const double *Z, int64_t P, double *grad3, void *ws,
                  size_t ws_bytes);
 
+/* ------------------------------------------ GP log marginal likelihood
+ * The value of the GP log marginal likelihood of y under A = K + sigma2 I
+ * (GP model adaptation, section 1; Rasmussen & Williams eq. 5.8) from
+ * alpha = A^{-1} y, e.g. as dcg_solve returned it:
+ *   *value = -1/2 y^T alpha - (n/2) log(2 pi) - 1/2 log det A,
+ * the last term only when logdet is given (a host pointer to log det A, e.g.
+ * dcg_slq_logdet's estimate; NULL leaves the term out).  y, alpha: device
+ * FP64 n-vectors (n of the operator); value: host.  y^T alpha is summed on
+ * the operator's stream in a fixed order (one workgroup), which the call
+ * synchronises.  DCG_E_ARG for a null pointer or a non-finite *logdet,
+ * DCG_E_NONFINITE when y^T alpha is not finite. */
+int dcg_mll_value(dcg_op_t op, const double *y, const double *alpha, const double *logdet,
+                  double *value);
+
 /* ------------------------------------------------ log det by SLQ
  * Stochastic Lanczos quadrature: the forward value -1/2 log det A of the GP
  * log marginal likelihood (GP model adaptation, section 1), from the probe
@@ -398,7 +425,9 @@ int dcg_slq_logdet(dcg_op_t op, const double *Z, int64_t P, const dcg_params *p,
  *   a = b~ - D z,  f = K a,  Psi = sum_i log sigma(y_i f_i) - a^T f / 2,
  * and stops once Psi grows by less than psi_tol (the paper uses 1).  The
  * products with K use the FP64 operator when the operator is FP64 or
- * p->refine > 0, else the operator's precision.
+ * p->refine > 0, else the operator's precision.  A stored operator
+ * (DCG_PREC_STORED) has no FP64 operator: with p->refine != 0 the call
+ * returns DCG_E_ARG before enqueuing any work.
  *  op          operator without a diagonal scaling (DCG_E_ARG otherwise);
  *              its sigma2 is not used (the systems have a unit shift) and
  *              is left as it was.

@@ -55,7 +55,8 @@ class Stats(ctypes.Structure):
                 ("t_loop_ms", ctypes.c_double), ("t_refresh_ms", ctypes.c_double),
                 ("t_total_ms", ctypes.c_double), ("sweeps_timed", ctypes.c_int),
                 ("t_sweeps_ms", ctypes.c_double), ("refresh_dim", ctypes.c_int),
-                ("refresh_rank", ctypes.c_int), ("refresh_sweeps", ctypes.c_int * 2)]
+                ("refresh_rank", ctypes.c_int), ("refresh_sweeps", ctypes.c_int * 2),
+                ("exact_sweeps_timed", ctypes.c_int), ("t_exact_sweeps_ms", ctypes.c_double)]
 
     def as_dict(self):
         d = {name: getattr(self, name) for name, _ in self._fields_}
@@ -114,6 +115,9 @@ _SIGS = {
                                     ctypes.c_void_p, ctypes.c_int64,
                                     ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
                                     ctypes.c_size_t]),
+    "dcg_mll_value": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]),
     "dcg_extract_basis_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int]),
     "dcg_extract_basis": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -624,6 +628,21 @@ def mll_grad(op, alpha, U, Z):
     return [g[0], g[1], g[2]]
 
 
+def mll_value(op, y, alpha, logdet=None):
+    """-1/2 y^T alpha - n/2 log(2 pi) [- 1/2 logdet]: the GP log marginal
+    likelihood from alpha = A^{-1} y (the sum is taken by the library)."""
+    torch = _torch()
+    lib = load()
+    y = y.to(device=op.device, dtype=torch.float64).contiguous()
+    a = alpha.to(device=op.device, dtype=torch.float64).contiguous()
+    out = ctypes.c_double()
+    ld = None if logdet is None else ctypes.byref(ctypes.c_double(float(logdet)))
+    with _ordered(op.stream):
+        _check(lib.dcg_mll_value(op.handle, y.data_ptr(), a.data_ptr(), ld, ctypes.byref(out)),
+               "dcg_mll_value")
+    return out.value
+
+
 def extract_basis(Z, AZ, k, largest=True, extraction="harmonic", ritz_route="auto"):
     """The extraction of the next basis (section 2.3: harmonic Ritz, Eq. 7, or
     Rayleigh-Ritz) on given Z and AZ (n x m device tensors): returns (W' = Z U
@@ -656,13 +675,16 @@ class GPMarginalLikelihood:
     theta = (log ell, log s2, log sigma2).
 
     forward: alpha = A^{-1} y by deflated CG with the recycled basis of `rc`
-    (refreshed by every solve), value = -1/2 y^T alpha - n/2 log(2 pi); with
+    (refreshed by every solve), value = -1/2 y^T alpha - n/2 log(2 pi)
+    assembled by the library (dcg_mll_value); with
     ``GPContext(logdet=True)`` also -1/2 log|A| estimated by stochastic
     Lanczos quadrature over the context's probes (one more block solve,
     plain CG, since the quadrature needs the probes' own Krylov spaces).
     backward: the probe solves U = A^{-1} Z reuse the same recycled W (the
     adjoint of the symmetric solve is the same solve), then one fused sweep
     gives the full gradient, log-determinant term included (Hutchinson).
+    The backward sets the operator back to the forward's hyperparameters
+    when another forward has changed them in between.
 
     Use through ``GPMarginalLikelihood.apply(theta, ctx_obj)`` where ctx_obj
     is a ``GPContext`` holding the operator, y, the recycle handle and the
@@ -696,23 +718,30 @@ def _make_mll_function():
         def forward(ctx, theta, gpc):
             th = theta.detach().double().cpu().tolist()
             op = gpc.op
-            op.set_hyper(math.exp(th[0]), math.exp(th[1]), math.exp(th[2]))
+            hyper = (math.exp(th[0]), math.exp(th[1]), math.exp(th[2]))
+            op.set_hyper(*hyper)
             alpha, st = solve(op, gpc.y, rc=gpc.rc, tol=gpc.tol)
             alpha = alpha.clone()
             gpc.last = {"alpha_stats": st}
             ctx.gpc = gpc
             ctx.alpha = alpha
-            value = -0.5 * float(torch.dot(gpc.y.to(alpha), alpha)) - 0.5 * op.n * math.log(2 * math.pi)
+            # the hyperparameters of this forward: the backward runs its probe
+            # solves and derivative sweep at them, whatever the operator holds
+            # by then (another forward may have moved it, e.g. a line search)
+            ctx.hyper = hyper
+            logdet = None
             if gpc.logdet:
-                est, quad, steps = slq_logdet(op, gpc.probes, tol=gpc.probe_tol)
-                gpc.last["logdet"] = est
+                logdet, quad, steps = slq_logdet(op, gpc.probes, tol=gpc.probe_tol)
+                gpc.last["logdet"] = logdet
                 gpc.last["logdet_steps"] = steps
-                value -= 0.5 * est
+            value = mll_value(op, gpc.y, alpha, logdet)
             return theta.new_tensor(value)
 
         @staticmethod
         def backward(ctx, grad_out):
             gpc = ctx.gpc
+            if (gpc.op.ell, gpc.op.s2, gpc.op.sigma2) != ctx.hyper:
+                gpc.op.set_hyper(*ctx.hyper)
             U, st = solve_block(gpc.op, gpc.probes, rc=gpc.rc, tol=gpc.probe_tol)
             gpc.last["probe_stats"] = st
             g = mll_grad(gpc.op, ctx.alpha, U, gpc.probes)

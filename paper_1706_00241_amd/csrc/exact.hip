@@ -333,6 +333,8 @@ int launch_exact_sweep(const dcg_operator_s *op, const int *done) {
 // every launch into a no-op once a solve has finished.
 int matvec_exact_done(const dcg_operator_s *op, const double *V, double *Y, int64_t m,
                       const int *done) {
+  // the stored operator keeps no FP64 operands (their workspace is not laid out)
+  if (op->g.prec == DCG_PREC_STORED) return DCG_E_ARG;
   const int64_t n = op->g.n, n_pad = op->g.n_pad;
   MatvecPlan p;
   const Symv64Args a = exact_args(op, done, &p);
@@ -354,6 +356,28 @@ int matvec_exact_done(const dcg_operator_s *op, const double *V, double *Y, int6
 
 int matvec_exact(const dcg_operator_s *op, const double *V, double *Y, int64_t m) {
   return matvec_exact_done(op, V, Y, m, nullptr);
+}
+
+// One FP64 product (m = 1) with HIP events recorded on the operator's stream
+// right before and after the pair sweep, so the caller can time the sweep
+// kernel alone.
+int matvec_exact_timed(const dcg_operator_s *op, const double *V, double *Y, hipEvent_t ev0,
+                       hipEvent_t ev1) {
+  if (op->g.prec == DCG_PREC_STORED) return DCG_E_ARG;
+  const int64_t n = op->g.n, n_pad = op->g.n_pad;
+  MatvecPlan p;
+  const Symv64Args a = exact_args(op, nullptr, &p);
+  const double *dsc = op->has_dsc ? op->dsc : nullptr;
+  hipLaunchKernelGGL(stage64, dim3(static_cast<unsigned>(cdiv(n_pad, 256))), dim3(256), 0,
+                     op->stream, V, n, n_pad, dsc, op->vin64, nullptr);
+  if (hipEventRecord(ev0, op->stream) != hipSuccess) return DCG_E_HIP;
+  const int st = launch_exact_sweep(op, nullptr);
+  if (st != DCG_OK) return st;
+  if (hipEventRecord(ev1, op->stream) != hipSuccess) return DCG_E_HIP;
+  hipLaunchKernelGGL(reduce64, dim3(static_cast<unsigned>(cdiv(n, 256))), dim3(256), 0,
+                     op->stream, a.prow, a.pcol, n, n_pad, p.nchunk, p.dmax, p.nb, op->s2,
+                     op->sigma2, dsc, V, Y, nullptr);
+  return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
 }
 
 }  // namespace dcg

@@ -151,6 +151,9 @@ int dcg_laplace_gpc(dcg_op_t op, const double *y, dcg_recycle_t rc, const dcg_pa
     return DCG_E_ARG;
   if (max_newton < 1 || !(psi_tol >= 0.0) || op->has_dsc) return DCG_E_ARG;
   if (rc != nullptr && rc->n != op->g.n) return DCG_E_ARG;
+  // refinement needs the FP64 operator, which the stored operator does not
+  // have (checked before any work is enqueued)
+  if (op->g.prec == DCG_PREC_STORED && p->refine != 0) return DCG_E_ARG;
   const int64_t n = op->g.n, n_pad = op->g.n_pad;
   const GpcLayout L = gpc_layout(n);
   if (ws == nullptr || ws_bytes < L.total) return DCG_E_WORKSPACE;

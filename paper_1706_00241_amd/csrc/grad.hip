@@ -306,11 +306,53 @@ static int launch_grad(const dcg_operator_s *op, const GradArgs &a, int64_t grid
   return -1;
 }
 
+// out[0] = y^T alpha, one block of 1024 threads: each thread sums a strided
+// subsequence, then a fixed tree (bitwise reproducible).
+__global__ __launch_bounds__(1024) void dot_one_block(const double *y, const double *alpha,
+                                                      int64_t n, double *out) {
+  __shared__ double lds[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) s += y[i] * alpha[i];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) lds[w] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < 16; ++i) t += lds[i];
+    out[0] = t;
+  }
+}
+
 }  // namespace dcg
 
 using namespace dcg;
 
 extern "C" {
+
+int dcg_mll_value(dcg_op_t op, const double *y, const double *alpha, const double *logdet,
+                  double *value) {
+  if (op == nullptr || y == nullptr || alpha == nullptr || value == nullptr) return DCG_E_ARG;
+  if (logdet != nullptr && !std::isfinite(*logdet)) return DCG_E_ARG;
+  const int64_t n = op->g.n;
+  hipStream_t s = op->stream;
+  // the operator's product staging holds the one-double result (calls on one
+  // operator do not overlap)
+  hipLaunchKernelGGL(dot_one_block, dim3(1), dim3(1024), 0, s, y, alpha, n, op->ytmp);
+  double ya = 0.0;
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(&ya, op->ytmp, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return DCG_E_HIP;
+  if (!std::isfinite(ya)) return DCG_E_NONFINITE;
+  // -1/2 y^T A^{-1} y - n/2 log(2 pi) [- 1/2 log det A]
+  const double two_pi = 6.283185307179586;
+  double v = -0.5 * ya - 0.5 * static_cast<double>(n) * std::log(two_pi);
+  if (logdet != nullptr) v -= 0.5 * (*logdet);
+  *value = v;
+  return DCG_OK;
+}
 
 size_t dcg_mll_grad_workspace_bytes(int64_t n) {
   if (n < 1) return 0;

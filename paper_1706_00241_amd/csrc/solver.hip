@@ -3,9 +3,10 @@
 // mixed-precision iterative refinement around it.
 //
 // Per CG step four kernels run on the operator's stream: the symmetric pair
-// sweep (q = A p partials), the product finish with d = p^T q and alpha, the
-// x / r update with rho and h = (AW)^T r, and the direction update
-// p = beta p + r - W mu.  All scalars stay on the device; the host reads the
+// sweep (q = A p partials), the product finish with d = p^T q and alpha (in
+// its last block), the pass over r' = r - alpha q with rho' and
+// h = (AW)^T r' whose last block runs the scalar step (re-projection, mu,
+// beta, the convergence test), and the direction update p = beta p + r - W mu.  All scalars stay on the device; the host reads the
 // solve state once per chunk of iterations (optionally replayed as one
 // captured hipGraph), so the loop has one host round trip per chunk.
 #include <algorithm>
@@ -42,7 +43,7 @@ static SolveLayout solve_layout(int64_t n) {
   };
   const size_t nb = size_t(std::max<int64_t>(2 * cdiv(n, 64) + 2, kRedBlocks));
   L.S = take(sizeof(SolveState));
-  L.counter = take(sizeof(unsigned) * 4);
+  L.counter = take(sizeof(unsigned) * 8);
   L.r = take(size_t(n) * 8);
   L.p = take(size_t(n) * 8);
   L.q = take(size_t(n) * 8);
@@ -171,7 +172,10 @@ int deflation_setup(dcg_operator_s *op, dcg_recycle_s *rc, int *matvecs) {
   int info = 0;
   HIPCHK(hipMemcpyAsync(&info, rc->info, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (info != 0) return DCG_E_NOT_SPD;
+  // W^T A W is SPD for a full-rank W and an SPD operator: a failed
+  // factorisation means W (against A) is numerically rank deficient
+  if (info == 2) return DCG_E_NONFINITE;
+  if (info != 0) return DCG_E_W_RANK;
   rc->m_valid = 1;
   rc->m_version = rc->w_version;
   return DCG_OK;
@@ -203,7 +207,8 @@ static CgArgs cg_args(dcg_operator_s *op, const SolveBuffers &B, double *x, dcg_
   a.part = B.part;
   a.part2 = B.part + std::max<int64_t>(a.nblk_q, 1);
   a.part_h = B.part_h;
-  a.counter = B.counter;
+  // counters 0-3 serve the set-up kernels, 4-5 the tails of the step kernels
+  a.counter = B.counter + 4;
   a.hist_d = B.hist_d;
   a.hist_alpha = B.hist_alpha;
   a.hist_beta = B.hist_beta;
@@ -236,7 +241,6 @@ static int enqueue_cg_step(dcg_operator_s *op, const CgArgs &a, hipEvent_t ev0 =
                      op->stream, a);
   hipLaunchKernelGGL(cg_update_xr, dim3(static_cast<unsigned>(xr_grid(a))), dim3(256), 0,
                      op->stream, a);
-  hipLaunchKernelGGL(cg_finalize, dim3(1), dim3(256), 0, op->stream, a);
   hipLaunchKernelGGL(cg_update_p, dim3(static_cast<unsigned>(a.nblk_p)), dim3(256), 0,
                      op->stream, a);
   return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
@@ -263,7 +267,7 @@ int solve_init(dcg_operator_s *op, const double *b, double *x, int x_given,
   }
   int matvecs = 0;
   const double *Minv = nullptr;
-  HIPCHK(hipMemsetAsync(B.counter, 0, sizeof(unsigned) * 4, s));
+  HIPCHK(hipMemsetAsync(B.counter, 0, sizeof(unsigned) * 8, s));
   HIPCHK(hipMemsetAsync(B.S, 0, sizeof(SolveState), s));
   if (k > 0) {
     int st = deflation_setup(op, rc, &matvecs);
@@ -845,11 +849,27 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
   double rel = 0.0;
   int status = DCG_NOT_CONVERGED;
   RefineStore store(p, rc);
+  // profile: HIP events around each FP64 sweep, read after the residual's
+  // host synchronisation below
+  hipEvent_t pev[2] = {nullptr, nullptr};
+  if (p->profile)
+    for (int e = 0; e < 2; ++e)
+      if (hipEventCreateWithFlags(&pev[e], hipEventDisableSystemFence) != hipSuccess)
+        pev[e] = nullptr;
+  const bool tex = pev[0] != nullptr && pev[1] != nullptr;
+  struct EvFree {
+    hipEvent_t *e;
+    ~EvFree() {
+      for (int i = 0; i < 2; ++i)
+        if (e[i] != nullptr) (void)hipEventDestroy(e[i]);
+    }
+  } ev_free{pev};
   for (int t = 0; t <= outer_max; ++t) {
     // from x = 0 the first residual is b itself
     const bool zero_start = (t == 0 && !x_given);
     if (!zero_start) {
-      int rcode = matvec_exact(op, x, B.tmp3, 1);
+      int rcode = tex ? matvec_exact_timed(op, x, B.tmp3, pev[0], pev[1])
+                      : matvec_exact(op, x, B.tmp3, 1);
       if (rcode != DCG_OK) return st->status = rcode;
       st->matvecs_exact += 1;
     }
@@ -860,6 +880,13 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
     double h[2];
     HIPCHK(hipMemcpyAsync(h, B.S->cvec, sizeof(h), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (tex && !zero_start) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, pev[0], pev[1]) == hipSuccess) {
+        st->t_exact_sweeps_ms += ms;
+        st->exact_sweeps_timed += 1;
+      }
+    }
     rel = (h[1] > 0.0) ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
     if (!std::isfinite(rel)) { status = DCG_E_NONFINITE; break; }
     if (rel <= p->tol) { status = DCG_OK; break; }
