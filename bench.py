@@ -35,15 +35,41 @@ sys.path.insert(0, ROOT)
 PEAK_VALU_SLOTS = 256 * 64 * 2.4e9
 # VALU issue slots per unique pair of the symmetric sweep (transcendentals
 # v_exp_f32 / v_sqrt_f32 count 2 slots: measured half rate on gfx950).  The
-# points are pre-scaled so that r2 = (c r)^2 needs no hyperparameter multiply:
+# compiled bf16 inner loop issues 7.56 VALU instructions per pair for
+# Matern-5/2 (242 per iteration of 32 pairs a lane), 7 of them the formulation
+# below.  The points are pre-scaled so that r2 = (c r)^2 needs no
+# hyperparameter multiply:
 #   RBF        exp2(-r2)                               exp(2) + 2 fma = 4
 #   Matern-3/2 u = sqrt r2, (1 + ln2 u) 2^-u           sqrt(2) + exp(2) + fma + mul + 2 fma = 7
 #   Matern-5/2 (1 + ln2 u + ln2^2 r2 / 3) 2^-u         sqrt(2) + exp(2) + 2 fma + mul + 2 fma = 9
 SLOTS_PER_PAIR = {0: 4, 1: 7, 2: 9}
+# FP64 issue slots per unique pair of the FP64 sweep (refinement residuals):
+# the distance on FP64 MFMA, 9 K-steps of 4 = 36 FMAs per pair for d = 32
+# (one 16x16x4 FP64 MFMA does 1024 FMAs, at the same DP rate as the VALU),
+# plus the FP64 VALU instructions of the kernel's formulation: exp2 16 (max,
+# rint, subtract, 11 Horner FMAs, convert, ldexp), sqrt 9 (max, rsq, 2 mul,
+# 5 FMA), the Matern polynomial 3 (5/2) or 2 (3/2), the row and column FMAs 2.
+# The compiled inner loop issues 33.5 / 32.5 / 21.5 VALU instructions per
+# pair (Matern-5/2, 3/2, RBF): the formulation plus address and select work.
+DP_SLOTS_PER_PAIR = {0: 36 + 18, 1: 36 + 29, 2: 36 + 30}
+PEAK_DP_SLOTS = 256 * 64 * 2.4e9
 # HBM bytes per launch of the sweep measured with rocprofv3 FETCH_SIZE /
-# WRITE_SIZE (scaled by a 256 MiB copy) for this workload and this version of
-# the kernel; None for any other configuration.
-SWEEP_TRAFFIC = {("bf16", 65536, 32, 2, 8192): 112.7e6}
+# WRITE_SIZE (scaled by a 256 MiB copy) for this workload, valid while the
+# sweep's source is the one the counters were taken from (its SHA-256 prefix);
+# None for any other configuration or source.
+SWEEP_TRAFFIC = {("bf16", 65536, 32, 2, 8192): (112.7e6, None)}
+
+
+def sweep_traffic(prec, n, d, kernel, items):
+    import hashlib
+    entry = SWEEP_TRAFFIC.get((prec, n, d, kernel, items))
+    if entry is None:
+        return None
+    value, sha = entry
+    src = os.path.join(ROOT, "paper_1706_00241_amd", "csrc", "matvec.hip")
+    with open(src, "rb") as f:
+        now = hashlib.sha256(f.read()).hexdigest()[:16]
+    return value if sha is not None and now == sha else None
 
 
 def parse():
@@ -56,6 +82,8 @@ def parse():
                     help="ell = 0.5 as written (an almost diagonal operator)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-literal", action="store_true",
+                    help="skip the short ell = 0.5 (as written) line")
     ap.add_argument("--prec", choices=["bf16", "bf16x2", "fp32", "fp16"], default="bf16",
                     help="operator precision of the inner solves")
     ap.add_argument("--inner-tol", type=float, default=2e-2,
@@ -89,6 +117,9 @@ def parse():
                          "(the paper's own test problem, the whole Newton loop per step) on "
                          "784-pixel data with the stored kernel matrix; gpc64: the same loop "
                          "at d = 64 with the matrix-free FP32 operator")
+    ap.add_argument("--refine-walk", action="store_true",
+                    help="fp32_walk: refine against the FP64 operator so that the tolerance "
+                         "holds for the true residual")
     ap.add_argument("--gpc-stored", action="store_true",
                     help="gpc64: use the stored kernel matrix instead of the matrix-free sweep")
     ap.add_argument("--adam-steps", type=int, default=50,
@@ -99,28 +130,61 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w, matvecs_per_solve, exact_per_solve, rows=384):
-    """The FP64 oracle's blocked matvec on `rows` rows of the same operator,
-    scaled to a full product and to the GPU's products per solve."""
-    import numpy as np
+_ORACLE = {}
+
+
+def _oracle_init():
+    # one BLAS thread per worker: the pool itself spreads over the cores
     from threadpoolctl import threadpool_limits
+    _ORACLE["limits"] = threadpool_limits(1)
+
+
+def _oracle_rows(bounds):
     from oracle import kernels as OK
+    lo, hi = bounds
+    X = _ORACLE["X"]
+    return lo, OK.gram(X[lo:hi], _ORACLE["kernel"], _ORACLE["ell"], 1.0, X) @ _ORACLE["v"]
+
+
+def oracle_product_seconds(w, block=256):
+    """Wall time of one full product of the FP64 oracle, K(X, X) v over all n
+    rows in its dense-row form (oracle.kernels.gram row blocks times v), on
+    the host cores: a pool of one process per core (the cores this process
+    may run on, at most 16, the CPU share of a one-GPU machine), each taking
+    blocks of `block` rows.  Called before anything touches the GPU (the
+    pool forks).  Returns (seconds, processes, cores in the affinity mask)."""
+    import multiprocessing as mp
+    import numpy as np
     X = w["X"]
     n = X.shape[0]
-    v = np.random.default_rng(0).standard_normal(n)
-    idx = np.arange(rows)
-    with threadpool_limits(1):
+    affinity = len(os.sched_getaffinity(0))
+    procs = max(1, min(affinity, 16))
+    _ORACLE.update(X=X, kernel=w["kernel"], ell=w["ell"],
+                   v=np.random.default_rng(0).standard_normal(n))
+    chunks = [(lo, min(n, lo + block)) for lo in range(0, n, block)]
+    with mp.get_context("fork").Pool(procs, initializer=_oracle_init) as pool:
+        pool.map(_oracle_rows, [(0, 8)] * procs)            # imports, first touch
         t0 = time.perf_counter()
-        y = OK.gram(X[idx], w["kernel"], w["ell"], 1.0, X) @ v
+        parts = pool.map(_oracle_rows, chunks, chunksize=1)
         t = time.perf_counter() - t0
+    y = np.empty(n)
+    for lo, part in parts:
+        y[lo:lo + part.shape[0]] = part
     assert np.all(np.isfinite(y))
-    per_matvec = t * n / rows
-    total = per_matvec * (matvecs_per_solve + exact_per_solve)
-    return {"value": round(total * 1e3, 1), "unit": "ms/solve", "cores": 1, "kind": "oracle",
-            "sample": f"oracle FP64 dense-row product on {rows} of {n} rows ({t:.2f} s), "
-                      f"scaled to one full product ({per_matvec:.1f} s) times the "
-                      f"{matvecs_per_solve + exact_per_solve:.1f} products per solve of the "
-                      f"GPU run; one thread"}
+    return t, procs, affinity
+
+
+def cpu_baseline(t_product, procs, affinity, n, products_per_solve):
+    """The oracle's time per solve: one full oracle product (timed) times the
+    products (low-precision and FP64 alike, the oracle has only FP64) that
+    the GPU run needed per solve; the oracle's vector work per step is O(n)
+    against the product's O(n^2 d) and is not counted."""
+    total = t_product * products_per_solve
+    return {"value": round(total * 1e3, 1), "unit": "ms/solve", "cores": procs, "kind": "oracle",
+            "sample": f"one full FP64 oracle product (oracle.kernels.gram rows x v, all {n} rows) "
+                      f"on {procs} processes ({affinity} cores in the affinity mask, the pool "
+                      f"capped at 16): {t_product:.2f} s, times the {products_per_solve:.1f} "
+                      f"products per solve of the GPU run"}
 
 
 def main_ragged(args):
@@ -236,16 +300,23 @@ def main_walk(args):
     systems = len(w["ells"])
     warm = min(args.warmup, systems - 1)
 
+    refine = args.refine_walk
+
     def run(rc):
         rows = []
         for t, ell in enumerate(w["ells"]):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             op.set_hyper(ell, w["s2"], w["sigma2"])
-            _, st = dcg.solve(op, b, rc=rc, tol=w["tol"], ws=ws, out=x, true_residual=True)
+            if refine:
+                # FP64 residuals: the 1e-6 tolerance holds for the true residual
+                _, st = dcg.solve(op, b, rc=rc, tol=w["tol"], ws=ws, out=x, refine=True,
+                                  inner_tol=1e-3)
+            else:
+                _, st = dcg.solve(op, b, rc=rc, tol=w["tol"], ws=ws, out=x, true_residual=True)
             torch.cuda.synchronize()
             rows.append((st["iters"], st["matvecs"], (time.perf_counter() - t0) * 1e3,
-                         st["rel_res_true"], st["status"]))
+                         st["rel_res_true"], st["status"], st["matvecs_exact"]))
         return rows
 
     rows = run(dcg.Recycle(n, w["k"], w["L"], device=dev))
@@ -254,6 +325,7 @@ def main_walk(args):
               file=sys.stderr, flush=True)
     timed = rows[warm:]
     ms = sum(r[2] for r in timed) / len(timed)
+    res_true = sorted(r[3] for r in rows)
     out = {
         "metric": "ms per solve, FP32 deflated CG on a log-ell random walk, n=16384, 1 GPU",
         "value": round(ms, 3), "unit": "ms/solve", "n_gpus": 1,
@@ -262,10 +334,21 @@ def main_walk(args):
         "dtype": "fp32 points (three bf16 terms on bf16 MFMA), f32 kernel values, f64 CG",
         "data": "synthetic",
         "config": {"workload": "fp32_walk: n=16384 d=16 X~N(0,1) RBF sigma2=1e-2, 20 systems, "
-                               "log-ell walk step 0.05, k=32 L=48 tol 1e-6", "sweep_items": items},
+                               "log-ell walk step 0.05, k=32 L=48, "
+                               + ("tol 1e-6 on the FP64 true residual (refinement against the "
+                                  "FP64 operator, inner tol 1e-3)" if refine else
+                                  "tol 1e-6 on the recursive residual; the true residual "
+                                  f"reached is {res_true[-1]:.1e} at most (the FP32 operator's "
+                                  "evaluation floor, rel_res_true_*)"),
+                   "sweep_items": items, "refine": bool(refine)},
         "matvecs_per_solve": round(sum(r[1] for r in timed) / len(timed), 1),
+        "exact_matvecs_per_solve": round(sum(r[5] for r in timed) / len(timed), 1),
         "iters_per_solve": round(sum(r[0] for r in timed) / len(timed), 1),
-        "failed_solves": sum(1 for r in rows if r[4] != 0),
+        "rel_res_true_max": res_true[-1],
+        "rel_res_true_median": _median(res_true),
+        "rel_res_true_of": ("|b - A64 x| / |b|, FP64 operator on the unrounded points" if refine
+                            else "|b - A x| / |b| with the solve's own FP32 operator"),
+        "failed_solves": sum(1 for r in rows if r[4] != 0 or (refine and r[3] > w["tol"])),
     }
     if not args.no_plain:
         prow = run(None)[warm:]
@@ -483,6 +566,28 @@ def main_gp(args):
     print(json.dumps(out), flush=True)
 
 
+def _median(v):
+    v = sorted(v)
+    m = len(v) // 2
+    return v[m] if len(v) % 2 else 0.5 * (v[m - 1] + v[m])
+
+
+def run_sequence(dcg, op, rc, w, b, kw, first, count, profile=False):
+    """Solve systems first .. first + count - 1 of the configured sigma2
+    sequence, restarting it after its last system (system i has sigma2_{i mod
+    10}); returns the per-solve stats with each solve's wall time."""
+    sig = w["sigma2s"]
+    out = []
+    for i in range(first, first + count):
+        t0 = time.perf_counter()
+        op.set_hyper(w["ell"], 1.0, sig[i % len(sig)])
+        _, st = dcg.solve(op, b, rc=rc, profile=profile, **kw)
+        st["wall_ms"] = (time.perf_counter() - t0) * 1e3
+        st["system"] = i
+        out.append(st)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -497,11 +602,17 @@ def main():
         return main_gpc(args)
     if args.workload == "fp32_walk":
         return main_walk(args)
-    import numpy as np
+    import workloads
+
+    # the configured sequence: ten systems sigma2_i = 1e-3 * 0.9^i
+    w = workloads.bf16_shift(n=args.n, systems=10, literal=args.literal)
+    n, d = w["X"].shape
+    # the oracle's product on the host cores, before anything touches the GPU
+    cpu = oracle_product_seconds(w) if not args.no_cpu else None
+
     import torch
 
     import paper_1706_00241_amd as dcg
-    import workloads
 
     dcg.load()
     if args.copy_calibration > 0:
@@ -511,8 +622,6 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    w = workloads.bf16_shift(n=args.n, systems=args.warmup + args.steps, literal=args.literal)
-    n, d = w["X"].shape
     dev = torch.device("cuda:0")
     X = torch.as_tensor(w["X"], device=dev)
     b = torch.as_tensor(w["b"], device=dev)
@@ -535,25 +644,19 @@ def main():
               extraction=args.extraction, select_largest=args.select == "largest",
               check_every=8)
 
-    for i in range(args.warmup):
-        op.set_hyper(w["ell"], 1.0, w["sigma2s"][i])
-        _, st = dcg.solve(op, b, rc=rc, **kw)
-        print(f"warmup system {i}: {st['iters']} its, {st['outer_steps']} outer, "
+    for st in run_sequence(dcg, op, rc, w, b, kw, 0, args.warmup):
+        print(f"warmup system {st['system']}: {st['iters']} its, {st['outer_steps']} outer, "
               f"{st['t_total_ms']:.1f} ms, res {st['rel_res_true']:.2e}", file=sys.stderr,
               flush=True)
 
-    stats = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.warmup, args.warmup + args.steps):
-        op.set_hyper(w["ell"], 1.0, w["sigma2s"][i])
-        _, st = dcg.solve(op, b, rc=rc, profile=True, **kw)
-        stats.append(st)
+    stats = run_sequence(dcg, op, rc, w, b, kw, args.warmup, args.steps, profile=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    for i, st in enumerate(stats):
-        print(f"system {args.warmup + i}: {st['iters']} its, {st['outer_steps']} outer, "
+    for st in stats:
+        print(f"system {st['system']}: {st['iters']} its, {st['outer_steps']} outer, "
               f"{st['t_total_ms']:.1f} ms (refresh {st['t_refresh_ms']:.1f}: m {st['refresh_dim']} "
               f"rank {st['refresh_rank']} sweeps {st['refresh_sweeps']}), "
               f"res {st['rel_res_true']:.2e}, status {st['status']}", file=sys.stderr, flush=True)
@@ -568,6 +671,11 @@ def main():
     slots = pairs * SLOTS_PER_PAIR[w["kernel"]]
     achieved = slots / t_sweep
     gflops = n * n * (2 * d + 2) / t_sweep / 1e9
+    ex_n = sum(st["exact_sweeps_timed"] for st in stats)
+    t_ex = sum(st["t_exact_sweeps_ms"] for st in stats) / max(1, ex_n) * 1e-3    # s
+    walls = [st["wall_ms"] for st in stats]
+    mean = lambda key: sum(st[key] for st in stats) / len(stats)
+    t_other = mean("t_total_ms") - mean("t_init_ms") - mean("t_loop_ms") - mean("t_refresh_ms")
 
     out = {
         "metric": "time-to-tol per solve & matvec GFLOP/s: deflated vs plain CG, n=65536, 1 GPU",
@@ -587,39 +695,58 @@ def main():
         "data": "synthetic",
         "config": {"workload": ("bf16_shift" + ("_literal" if args.literal else "")
                                 + f": n={n} d={d} X~U[-1,1] matern52 ell={w['ell']:.4f} "
-                                f"sigma2=1e-3*0.9^i k={w['k']} L={w['L']} refine to 1e-8"),
+                                f"sigma2=1e-3*0.9^i (i mod 10) k={w['k']} L={w['L']} "
+                                f"refine to 1e-8"),
                    "systems_timed": args.steps, "first_system": args.warmup,
+                   "sequence_length": len(w["sigma2s"]),
                    "refine": args.refine, "refresh": args.refresh, "inner_tol": args.inner_tol,
                    "extraction": args.extraction, "select": args.select,
                    "sweep_items": items},
-        "iters_per_solve": round(sum(s["iters"] for s in stats) / args.steps, 1),
-        "matvecs_per_solve": round(sum(s["matvecs"] for s in stats) / args.steps, 1),
-        "exact_matvecs_per_solve": round(sum(s["matvecs_exact"] for s in stats) / args.steps, 1),
+        "ms_per_solve_median": round(_median(walls), 2),
+        "ms_per_solve_min": round(min(walls), 2),
+        "phases_ms_per_solve": {
+            "init": round(mean("t_init_ms"), 2),
+            "cg_loop": round(mean("t_loop_ms"), 2),
+            "refresh": round(mean("t_refresh_ms"), 2),
+            "fp64_residuals_and_host": round(t_other, 2)},
+        "iters_per_solve": round(mean("iters"), 1),
+        "matvecs_per_solve": round(mean("matvecs"), 1),
+        "exact_matvecs_per_solve": round(mean("matvecs_exact"), 1),
+        "rel_res_true_max": max(st["rel_res_true"] for st in stats),
         "matvec_ms": round(t_sweep * 1e3, 4),
         "matvec_gflops": round(gflops, 1),
         "gpair_per_s": round(n * n / t_sweep / 1e9, 1),
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 2),
                      "peak": round(PEAK_VALU_SLOTS / 1e12, 2), "unit": "TOP/s",
                      "frac": round(achieved / PEAK_VALU_SLOTS, 3),
-                     "traffic": SWEEP_TRAFFIC.get((args.prec, n, d, w["kernel"], items)),
+                     "traffic": sweep_traffic(args.prec, n, d, w["kernel"], items),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                      "kernel": "symv_kernel (symmetric pair sweep)",
                      "per_launch": f"{pairs:.4g} unique pairs x {SLOTS_PER_PAIR[w['kernel']]} "
                                    "VALU slots"},
     }
+    if ex_n:
+        # the FP64 pair sweep of the refinement residuals: FP64 MFMA distances
+        # and FP64 kernel values share the DP issue rate (78.6 TFLOP/s = one
+        # FP64 FMA per lane and clock either way)
+        dp = pairs * DP_SLOTS_PER_PAIR[w["kernel"]]
+        out["roofline_fp64"] = {
+            "bound": "fp64", "achieved": round(dp / t_ex / 1e12, 2),
+            "peak": round(PEAK_DP_SLOTS / 1e12, 2), "unit": "T DP-slots/s",
+            "frac": round(dp / t_ex / PEAK_DP_SLOTS, 3), "ms": round(t_ex * 1e3, 4),
+            "launches_timed": ex_n, "kernel": "symv64_kernel (FP64 pair sweep)",
+            "per_launch": f"{pairs:.4g} unique pairs x {DP_SLOTS_PER_PAIR[w['kernel']]} FP64 "
+                          "issue slots (MFMA FMAs and VALU instructions)"}
 
     if not args.no_plain:
         # the same systems by plain CG inside the same refinement
-        tp = []
         torch.cuda.synchronize()
         p0 = time.perf_counter()
-        for i in range(args.warmup, args.warmup + args.steps):
-            op.set_hyper(w["ell"], 1.0, w["sigma2s"][i])
-            _, st = dcg.solve(op, b, rc=None, **kw)
-            tp.append(st)
+        tp = run_sequence(dcg, op, None, w, b, kw, args.warmup, args.steps)
         torch.cuda.synchronize()
         plain_ms = (time.perf_counter() - p0) * 1e3 / args.steps
         out["plain_ms_per_solve"] = round(plain_ms, 2)
+        out["plain_ms_per_solve_median"] = round(_median([st["wall_ms"] for st in tp]), 2)
         out["plain_matvecs_per_solve"] = round(sum(s["matvecs"] for s in tp) / args.steps, 1)
         out["plain_exact_matvecs_per_solve"] = round(
             sum(s["matvecs_exact"] for s in tp) / args.steps, 1)
@@ -627,9 +754,29 @@ def main():
         print(f"plain CG: {plain_ms:.1f} ms/solve, {out['plain_matvecs_per_solve']} matvecs",
               file=sys.stderr, flush=True)
 
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, out["matvecs_per_solve"],
-                                           out["exact_matvecs_per_solve"])
+    if not args.literal and not args.no_literal:
+        # the configuration as written (ell = 0.5: K is close to I, CG needs a
+        # few steps and deflation has nothing to remove), same points and b
+        wl = workloads.bf16_shift(n=args.n, systems=10, literal=True)
+        opl = dcg.Operator(X, wl["kernel"], wl["ell"], 1.0, wl["sigma2s"][0], prec=prec)
+        rcl = dcg.Recycle(n, wl["k"], wl["L"], device=dev)
+        run_sequence(dcg, opl, rcl, wl, b, kw, 0, 2)
+        lit = run_sequence(dcg, opl, rcl, wl, b, kw, 2, 5)
+        litp = run_sequence(dcg, opl, None, wl, b, kw, 2, 5)
+        out["literal"] = {
+            "config": f"ell=0.5 as written, systems 2-6 of the sequence",
+            "ms_per_solve": round(sum(s["wall_ms"] for s in lit) / len(lit), 2),
+            "plain_ms_per_solve": round(sum(s["wall_ms"] for s in litp) / len(litp), 2),
+            "iters_per_solve": round(sum(s["iters"] for s in lit) / len(lit), 1),
+            "plain_iters_per_solve": round(sum(s["iters"] for s in litp) / len(litp), 1),
+            "outer_steps_per_solve": round(sum(s["outer_steps"] for s in lit) / len(lit), 1),
+            "rel_res_true_max": max(s["rel_res_true"] for s in lit + litp)}
+        del opl, rcl
+
+    if cpu is not None:
+        t_prod, procs, affinity = cpu
+        out["cpu_baseline"] = cpu_baseline(t_prod, procs, affinity, n,
+                                           out["matvecs_per_solve"] + out["exact_matvecs_per_solve"])
     print(json.dumps(out), flush=True)
 
 

@@ -82,6 +82,65 @@ def test_mll_grad_sweep_matches_oracle(lib, kern, prec):
         assert abs(g[j] - ref[j]) <= 2e-5 * scales[j] + 1e-9, (j, g[j], ref[j], scales[j])
 
 
+def test_mll_value_matches_oracle(lib):
+    """dcg_mll_value: -1/2 y^T alpha - n/2 log 2 pi (- 1/2 log det A) summed
+    by the library, against the oracle's exact log marginal likelihood (dense
+    Cholesky, Rasmussen & Williams eq. 5.8) when fed the exact alpha and the
+    exact log det, and the determinant term left out when none is given."""
+    w = workloads.gp_hyper(n=1300)
+    X, y = w["X"], w["y"]
+    ell, s2, sig2 = math.exp(w["log_ell"]), 1.1, 0.2
+    op = lib.Operator(_dev(X), 0, ell, s2, sig2, prec=3)
+    A = OK.operator(X, 0, ell, s2, sig2)
+    alpha = np.linalg.solve(A, y)
+    ld = np.linalg.slogdet(A)[1]
+    ref = OG.lml(X, y, 0, ell, s2, sig2)
+    v = lib.mll_value(op, _dev(y), _dev(alpha), logdet=ld)
+    assert v == pytest.approx(ref, rel=1e-12, abs=1e-9)
+    v0 = lib.mll_value(op, _dev(y), _dev(alpha))
+    assert v0 - v == pytest.approx(0.5 * ld, rel=1e-12, abs=1e-9)
+    with pytest.raises(lib.DcgError) as e:
+        lib.mll_value(op, _dev(y), _dev(alpha), logdet=float("nan"))
+    assert e.value.status == -1
+
+
+def test_mll_backward_after_another_forward(lib):
+    """The backward of a forward at theta_a, taken after a second forward at
+    theta_b moved the operator: it runs at theta_a (the operator is set back
+    to the first forward's hyperparameters), so it gives the gradient of a
+    lone forward/backward at theta_a (to the probe solves' tolerance), not
+    theta_b's."""
+    w = workloads.gp_hyper(n=1500)
+    X, y = w["X"], w["y"]
+    Z = _dev(workloads.rademacher(1500, 16, step=2))
+    th_a = [w["log_ell"], 0.0, math.log(0.1)]
+    th_b = [w["log_ell"] + 0.3, 0.2, math.log(0.05)]
+
+    def fresh():
+        op = lib.Operator(_dev(X), 0, 1.0, 1.0, 0.1, prec=0)
+        return lib.GPContext(op, _dev(y), lib.Recycle(1500, 16, 24), Z, tol=1e-8)
+
+    def grad_alone(th):
+        t = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+        lib.GPMarginalLikelihood.apply(t, fresh()).backward()
+        return t.grad.numpy().copy()
+
+    g_a, g_b = grad_alone(th_a), grad_alone(th_b)
+    gpc = fresh()
+    ta = torch.tensor(th_a, dtype=torch.float64, requires_grad=True)
+    tb = torch.tensor(th_b, dtype=torch.float64, requires_grad=True)
+    va = lib.GPMarginalLikelihood.apply(ta, gpc)
+    lib.GPMarginalLikelihood.apply(tb, gpc)          # moves the operator to theta_b
+    va.backward()
+    g = ta.grad.numpy()
+    # the probe solves start from different recycled bases, so they agree to
+    # the solver tolerance on the FP32 operator (as GPU vs oracle elsewhere)
+    np.testing.assert_allclose(g, g_a, rtol=1e-4, atol=1e-4 * np.abs(g_a).max())
+    assert np.abs(g - g_b).max() > 1e-2 * np.abs(g_a).max()
+    # the operator is at theta_a again
+    assert gpc.op.ell == pytest.approx(math.exp(th_a[0]), rel=1e-15)
+
+
 def test_mll_autograd_against_exact_gradient(lib):
     """torch.autograd.Function: the backward (probe solves reusing W, fused
     sweep) against the oracle's exact dense gradient within the Hutchinson

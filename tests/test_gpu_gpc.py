@@ -281,6 +281,43 @@ def test_stored_operator_limits(lib):
     assert st["status"] == 0 and res <= 1.01e-10, res
 
 
+def test_stored_laplace_gpc_refuses_refinement(lib):
+    """The Newton loop on a stored operator with refinement asked for: the
+    stored operator has no FP64 counterpart, so dcg_laplace_gpc returns
+    DCG_E_ARG through the C ABI before it enqueues anything (the outputs and
+    the operator are untouched, and the operator still works)."""
+    import ctypes
+    n = 300
+    X = np.random.default_rng(2).uniform(0.0, 1.0, (n, 40))
+    y = np.where(np.random.default_rng(3).standard_normal(n) > 0, 1.0, -1.0)
+    op = lib.Operator(_dev(X), 0, 3.0, 1.0, 0.0, prec=lib.PREC_STORED)
+    L = lib.load()
+    yd = _dev(y)
+    f = torch.full((n,), 7.0, dtype=torch.float64, device="cuda")
+    a = torch.full((n,), 7.0, dtype=torch.float64, device="cuda")
+    nbytes = L.dcg_laplace_gpc_workspace_bytes(n)
+    ws = torch.zeros(nbytes + 256, dtype=torch.uint8, device="cuda")
+    ptr = ws.data_ptr() + (-ws.data_ptr()) % 256
+    torch.cuda.synchronize()
+    for refine in (1, 2):
+        p = lib.Params(tol=1e-6, check_every=8, refine=refine, inner_tol=1e-2, refine_max=10,
+                       use_graph=1)
+        steps = ctypes.c_int(-1)
+        psi = (ctypes.c_double * 6)()
+        stats = (lib.Stats * 5)()
+        rc = L.dcg_laplace_gpc(op.handle, yd.data_ptr(), None, ctypes.byref(p), 5, 1.0,
+                               f.data_ptr(), a.data_ptr(), psi, ctypes.byref(steps), stats,
+                               ptr, nbytes)
+        assert rc == -1, rc
+        assert steps.value == -1
+    torch.cuda.synchronize()
+    assert float(f.min()) == 7.0 and float(a.max()) == 7.0
+    # the operator is unchanged: no scaling, its own shift
+    v = _dev(np.ones(n))
+    ref = (_stored_ref(X, 0, 3.0, 1.0)) @ np.ones(n)
+    assert np.abs(_np(op.matvec(v)) - ref).max() <= 2e-7 * np.abs(ref).max()
+
+
 def test_stored_laplace_gpc_matches_oracle(lib):
     """The Newton loop on the pixel-like data at n = 1500, d = 784 with the
     stored operator, against the oracle's loop with dense solves on

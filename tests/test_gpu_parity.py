@@ -20,6 +20,8 @@ from oracle import ritz as ORZ
 from oracle import sequence as OS
 import workloads
 
+from emulation import fit_eta, noisy_product
+
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
@@ -100,6 +102,14 @@ def test_matvec_full_size_sampled_rows(lib):
         assert abs(y[i] - ref) <= 2e-5 * scale, (i, y[i], ref)
 
 
+def _gpu_eta(op, A, seed=17):
+    """The per-term error level of the GPU operator against the oracle's dense
+    matrix of the same points (the error model of tests/emulation.py),
+    measured on one random vector."""
+    v = np.random.default_rng(seed).standard_normal(A.shape[0])
+    return fit_eta(A, v, _np(op.matvec(_dev(v))))
+
+
 def _floor(op, A, x, b):
     """|(A_gpu - A_ref) x| / |b|: how far the GPU operator is from the oracle's."""
     ax_gpu = _np(op.matvec(_dev(x)))
@@ -169,19 +179,29 @@ def test_defcg_sequence_parity_small(lib, prec, tol, th_rtol):
         assert len(th) == 8
         np.testing.assert_allclose(th, ref[i].theta, rtol=th_rtol)
     ref_its = [r.iters for r in ref]
-    # FP64 operator: the same iteration within rounding; FP32 operator: its
-    # evaluation error (~1e-7 of |A||p|) slows CG by up to ~11% on this
-    # sequence (first system 78-79 steps against the oracle's exact 71, with
-    # either rounding of the points; plain CG likewise)
-    slack, frac = (2, 0.0) if prec == 3 else (3, 0.15)
-    for a, c in zip(its, ref_its):
-        assert abs(a - c) <= max(slack, frac * c), (its, ref_its)
+    if prec == 3:
+        # FP64 operator: the same iteration within rounding
+        for a, c in zip(its, ref_its):
+            assert abs(a - c) <= 2, (its, ref_its)
+    else:
+        # FP32 operator: its evaluation error delays CG.  The delay is bounded
+        # by the oracle's own iteration with per-term product errors of 1e-7
+        # and 3e-7 on this sequence (test_oracle_emulation.py: every system
+        # within [exact - 1, 1.15 exact]); the GPU operator's error level is
+        # measured here and must lie inside that range, and the counts inside
+        # the band (two steps of margin for the error model)
+        eta = _gpu_eta(op, mats[-1])
+        print(f"FP32 operator per-term error {eta:.2e}; its {its} oracle {ref_its}", flush=True)
+        assert eta <= 3e-7, eta
+        for a, c in zip(its, ref_its):
+            assert c - 3 <= a <= 1.15 * c + 2, (its, ref_its)
     # recycling pays: fewer steps than plain CG on the later systems
     plain = OS.solve_sequence(mats, bs, k=8, L=12, tol=tol, recycle=False)
     assert sum(its[1:]) < sum(p.iters for p in plain[1:])
 
 
-@pytest.mark.parametrize("k,L,sigma2", [(8, 12, 1e-2), (32, 96, 1e-2), (64, 64, 3e-2)])
+@pytest.mark.parametrize("k,L,sigma2", [(8, 12, 1e-2), (16, 24, 1e-2), (32, 96, 1e-2),
+                                        (64, 64, 3e-2)])
 def test_ritz_routes_match_oracle(lib, k, L, sigma2):
     """Both reductions of F in the harmonic Ritz problem (Eq. 7): Cholesky,
     taken where a bound shows that nothing would be dropped, and the
@@ -206,6 +226,10 @@ def test_ritz_routes_match_oracle(lib, k, L, sigma2):
     are compared with the oracle's (rtol 1e-3, also on the later systems,
     whose W comes from that extraction), and the GPU basis is checked for the defining
     properties W^T A W = I and (AW)^T AW = diag(theta) with the dense FP64 A.
+    Every Ritz value is compared (rtol 1e-6) on each system whose
+    extraction, and every extraction before it in the sequence, kept all of
+    F's directions: all systems of (8, 12) and of (16, 24) (whose F has
+    smallest scaled eigenvalue ratios 0.14, 0.92, 0.93 in the oracle).
     The extraction itself on identical inputs is pinned by
     test_extraction_on_given_Z_matches_oracle.  The two routes' spaces
     agree to rounding in every case."""
@@ -219,6 +243,7 @@ def test_ritz_routes_match_oracle(lib, k, L, sigma2):
     op = lib.Operator(_dev(X), w["kernel"], w["ells"][0], 1.0, sigma2, prec=3)
     rcs = {route: lib.Recycle(n, k, L) for route in ("auto", "eigen")}
     chosen = []
+    full_rank_chain = {route: True for route in rcs}
     for i, (ell, A, b) in enumerate(zip(w["ells"], mats, bs)):
         op.set_hyper(ell, 1.0, sigma2)
         Ws, its = {}, {}
@@ -238,7 +263,10 @@ def test_ritz_routes_match_oracle(lib, k, L, sigma2):
                 assert st["refresh_rank"] == st["refresh_dim"]
             th = np.array(rc.theta())
             Wg = _np(rc.get_W())
-            if (k, L) == (8, 12):
+            full_rank_chain[route] &= st["refresh_rank"] == st["refresh_dim"]
+            if (k, L) in ((8, 12), (16, 24)):
+                assert full_rank_chain[route]
+            if full_rank_chain[route]:
                 np.testing.assert_allclose(th, ref[i].theta, rtol=1e-6)
             else:
                 np.testing.assert_allclose(th[:16], ref[i].theta[:16], rtol=1e-3)
@@ -250,7 +278,7 @@ def test_ritz_routes_match_oracle(lib, k, L, sigma2):
         Qa, _ = np.linalg.qr(Ws["auto"])
         Qb, _ = np.linalg.qr(Ws["eigen"])
         assert np.linalg.svd(Qa.T @ Qb, compute_uv=False).min() >= 1 - 1e-6
-    if (k, L) == (8, 12):
+    if (k, L) in ((8, 12), (16, 24)):
         assert all(c for c, _, _ in chosen)
     else:
         assert not chosen[0][0] and chosen[0][1]
@@ -345,7 +373,15 @@ def test_recycled_basis_is_A_orthonormal(lib):
 @pytest.mark.parametrize("prec,sigma2,tol", [(3, 1e-2, 1e-8), (3, 1e-3, 1e-8), (0, 1e-2, 1e-6)])
 def test_exact_eigenvector_deflation(lib, prec, sigma2, tol):
     """W = exact eigenvectors of the 8 largest eigenvalues (oracle eigh):
-    def-CG needs fewer steps than plain CG, as many as the oracle def-CG."""
+    def-CG needs fewer steps than plain CG, as many as the oracle def-CG up
+    to the spread that the GPU operator's own error level causes: the
+    oracle's iteration (with the library's re-projection) is rerun with
+    per-term product errors of twice the level measured on the GPU operator
+    (at least one FP64 rounding, 3e-16) over several seeds, and the GPU's
+    counts must lie in the band those runs span, two steps of margin on
+    either side (FP32: three).  test_oracle_emulation.py shows why a band is
+    needed: at kappa 4.9e5 rounding alone moves FP64 counts by several
+    steps, and FP32 evaluation error inflates them by 30-40% here."""
     n = 800
     X = _points(n, 4, seed=21)
     ell = workloads.median_distance(X)
@@ -359,23 +395,24 @@ def test_exact_eigenvector_deflation(lib, prec, sigma2, tol):
     rc.set_W(_dev(W))
     x, st = lib.solve(op, _dev(b), rc=rc, tol=tol)
     plain_x, plain = lib.solve(op, _dev(b), tol=tol)
-    ref = OC.defcg(A, b, W=W, tol=tol)
+    ref = OC.defcg(A, b, W=W, tol=tol, reproject=True)
     ref_plain = OC.cg(A, b, tol=tol)
     assert st["status"] == 0 and st["k_used"] == 8
     assert st["iters"] < plain["iters"]
+    eta = _gpu_eta(op, A)
+    eta_e = max(2.0 * eta, 3e-16)
+    seeds = range(6) if prec == 3 else range(4)
+    emu = [OC.defcg(noisy_product(A, eta_e, s), b, W=W, AW=A @ W, tol=tol,
+                    reproject=True).iters for s in seeds]
+    margin = 2 if prec == 3 else 3
+    lo, hi = min(emu + [ref.iters]) - margin, max(emu + [ref.iters]) + margin
+    print(f"prec {prec} sigma2 {sigma2}: eta {eta:.2e}; GPU {st['iters']} / plain "
+          f"{plain['iters']}; oracle {ref.iters} / {ref_plain.iters}; emulated {emu}", flush=True)
+    assert lo <= st["iters"] <= hi, (st["iters"], lo, hi)
     if prec == 3:
-        # FP64 operator: the same iteration up to rounding.  At kappa ~ 5e5
-        # (sigma2 = 1e-3) the oracle's literal Algorithm 1 drifts (W^T r_j
-        # grows with rounding) while the GPU re-projects r_j every step, so
-        # the counts may differ by a few percent there.
-        frac = 0.02 if sigma2 >= 1e-2 else 0.05
-        assert abs(st["iters"] - ref.iters) <= max(3, frac * ref.iters), (st["iters"], ref.iters)
-        assert abs(plain["iters"] - ref_plain.iters) <= max(3, frac * ref_plain.iters)
-    else:
-        # FP32 operator: inexact products delay CG on this ill-conditioned
-        # system (kappa ~ 5e4; the oracle with 1e-8 |A||p| noise needs 1.8x
-        # the exact count); bound the delay
-        assert st["iters"] <= 1.5 * ref.iters, (st["iters"], ref.iters)
+        emu_p = [OC.cg(noisy_product(A, eta_e, s), b, tol=tol).iters for s in seeds]
+        lo, hi = min(emu_p + [ref_plain.iters]) - 2, max(emu_p + [ref_plain.iters]) + 2
+        assert lo <= plain["iters"] <= hi, (plain["iters"], emu_p, ref_plain.iters)
     xn = _np(x)
     assert np.linalg.norm(b - A @ xn) / np.linalg.norm(b) <= tol + 2 * _floor(op, A, xn, b)
 
@@ -399,6 +436,115 @@ def test_refinement_reaches_1e8_bf16(lib, prec):
     x_ref = np.linalg.solve(A64, b)
     err_A = np.sqrt((x - x_ref) @ A64 @ (x - x_ref) / (x_ref @ A64 @ x_ref))
     assert err_A <= 1e-7
+
+
+def test_precision_form_reduced_headline_matches_oracle(lib):
+    """The precision form at the headline's k, L and inner tolerance on a
+    reduced size: n = 8192 points U[-1, 1]^32, Matern-5/2, ell = 0.5 x median
+    distance, bf16 operands, def-CG(64, 96) inner solves to 2e-2, refinement
+    against the FP64 operator to 1e-8, W refreshed after the first inner
+    solve of each system, three systems of the sigma2 = 1e-3 * 0.9^i
+    sequence.  The oracle runs the same refinement (oracle.refine, extract =
+    "first", the library's re-projection) on the same rounded points, W and
+    AW carried with the exact shift update.  Per system:
+    * outer steps within one of the oracle's;
+    * the oracle's dense FP64 true residual of the GPU solution <= 1.05e-8,
+      and the library's own report of it within 1e-3 of that;
+    * the A-norm error against the Cholesky solution <= 1e-7;
+    * the extracted harmonic Ritz values (theta_i = |A w_i|^2 of the oracle's
+      A-orthonormal basis): the leading 16 within the spread that the GPU
+      operator's error level causes, measured by rerunning the oracle's
+      first system with per-term product errors of twice that level (two
+      seeds; tests/emulation.py), times three, and at least 1e-9."""
+    import scipy.linalg as sl
+    from oracle import refine as ORF
+    n, k, L = 8192, 64, 96
+    w = workloads.bf16_shift(n=n, systems=3)
+    X, b, kern, ell = w["X"], w["b"], w["kernel"], w["ell"]
+    Xr = OP.round_points(X, 1, kern, ell)
+    K64 = OK.gram(X, kern, ell, 1.0)
+    Klo = OK.gram(Xr, kern, ell, 1.0)
+    op = lib.Operator(_dev(X), kern, ell, 1.0, w["sigma2s"][0], prec=1)
+    rc = lib.Recycle(n, k, L)
+    bn = np.linalg.norm(b)
+    W = AW = None
+    s2_prev = None
+    spread = None
+    for i, s2 in enumerate(w["sigma2s"]):
+        op.set_hyper(ell, 1.0, s2)
+        x, st = lib.solve(op, _dev(b), rc=rc, tol=1e-8, refine=True, inner_tol=2e-2,
+                          refresh_every="first")
+        x = _np(x)
+        A64 = K64 + s2 * np.eye(n)
+        Alo = Klo + s2 * np.eye(n)
+        if W is not None:
+            AW = AW + (s2 - s2_prev) * W
+        W_in, AW_in = W, AW
+        xr, hist, inner, (W, AW) = ORF.refine(A64, Alo, b, tol=1e-8, inner_tol=2e-2, k=k, L=L,
+                                              extract="first", W=W_in, AW=AW_in, reproject=True)
+        s2_prev = s2
+        th_ref = np.sort(np.sum(AW * AW, axis=0))[::-1]
+        th = np.array(rc.theta())
+        if i == 0:
+            eta = _gpu_eta(op, Alo)
+            devs = []
+            for seed in (0, 1):
+                _, _, _, (We, AWe) = ORF.refine(A64, noisy_product(Alo, 2 * eta, seed), b,
+                                                tol=1e-8, inner_tol=2e-2, k=k, L=L,
+                                                extract="first", reproject=True, max_outer=1)
+                th_e = np.sort(np.sum(AWe * AWe, axis=0))[::-1]
+                devs.append(np.abs(th_e[:16] - th_ref[:16]) / th_ref[:16])
+            spread = np.maximum(3 * np.max(devs, axis=0), 1e-9)
+        res = np.linalg.norm(b - A64 @ x) / bn
+        x_ref = sl.cho_solve(sl.cho_factor(A64), b)
+        err_A = np.sqrt((x - x_ref) @ A64 @ (x - x_ref) / (x_ref @ A64 @ x_ref))
+        print(f"system {i}: outer {st['outer_steps']} vs {len(inner)}, its {st['iters']} vs "
+              f"{sum(r.iters for r in inner)}, k {st['k_used']}->{st['k_next']}, res {res:.2e}, "
+              f"errA {err_A:.2e}, theta dev {np.abs(th[:16] - th_ref[:16]).max() / th_ref[0]:.1e}",
+              flush=True)
+        assert st["status"] == 0
+        assert abs(st["outer_steps"] - len(inner)) <= 1, (st["outer_steps"], len(inner))
+        assert res <= 1.05e-8, res
+        assert abs(res - st["rel_res_true"]) <= 1e-3 * res + 1e-15
+        assert err_A <= 1e-7, err_A
+        assert len(th) == st["k_next"] and abs(len(th) - len(th_ref)) <= 2
+        rel = np.abs(th[:16] - th_ref[:16]) / th_ref[:16]
+        assert np.all(rel <= (spread if i == 0 else 3 * spread)), (i, rel, spread)
+    assert st["k_used"] == k
+
+
+def test_precision_form_full_size_residual_rows(lib):
+    """The benchmark's configuration at full size (n = 65536, d = 32,
+    Matern-5/2, bf16, def-CG(64, 96), inner tolerance 2e-2, refinement to
+    1e-8, the sweep plan of 8192 work items), first two systems of the
+    sequence: on 48 sampled rows the oracle forms (b - A64 x)_i one row at a
+    time from the unrounded points; the library's FP64 product agrees with
+    each row to 1e-12 of (|A64| |x|)_i, so the residual the library reports
+    is the true residual, and every sampled |r_i| is below 1e-8 |b| plus the
+    rows' FP64 rounding."""
+    w = workloads.bf16_shift()
+    X, b, kern, ell = w["X"], w["b"], w["kernel"], w["ell"]
+    n = X.shape[0]
+    op = lib.Operator(_dev(X), kern, ell, 1.0, w["sigma2s"][0], prec=1)
+    op.set_sweep_items(8192)
+    rc = lib.Recycle(n, w["k"], w["L"])
+    rows = np.random.default_rng(13).choice(n, 48, replace=False)
+    krows = OK.gram(X[rows], kern, ell, 1.0, X)
+    bn = np.linalg.norm(b)
+    for i, s2 in enumerate(w["sigma2s"][:2]):
+        op.set_hyper(ell, 1.0, s2)
+        x, st = lib.solve(op, _dev(b), rc=rc, tol=1e-8, refine=True, inner_tol=2e-2)
+        assert st["status"] == 0 and st["rel_res_true"] <= 1e-8
+        y = _np(op.matvec_exact(x))
+        x = _np(x)
+        ax = krows @ x + s2 * x[rows]
+        scale = np.abs(krows) @ np.abs(x) + s2 * np.abs(x[rows])
+        assert np.all(np.abs(y[rows] - ax) <= 1e-12 * scale), np.max(np.abs(y[rows] - ax) / scale)
+        r = b[rows] - ax
+        assert np.all(np.abs(r) <= 1e-8 * bn + 1e-15 * scale), (np.abs(r).max() / bn)
+        print(f"system {i}: {st['iters']} its, {st['outer_steps']} outer, reported residual "
+              f"{st['rel_res_true']:.2e}, sampled max |r_i|/|b| {np.abs(r).max() / bn:.2e}",
+              flush=True)
 
 
 def test_fp16_operands_out_of_range(lib):
@@ -599,3 +745,131 @@ def test_edge_cases(lib):
     # max_iter reached: not converged, x still returned
     x, st = lib.solve(op, _dev(np.ones(40)), tol=1e-14, max_iter=2)
     assert st["status"] == 1 and st["iters"] == 2
+
+
+def test_failure_injection_statuses(lib):
+    """Failure paths as normal status returns (nothing faults): a recycled
+    basis with repeated columns gives DCG_E_W_RANK before the first CG step
+    (W^T A W is singular), a NaN or Inf in W gives DCG_E_NONFINITE, and a
+    NaN or Inf in b gives DCG_E_NONFINITE from the iteration, with and
+    without a basis and with refinement.  The handles stay usable: a
+    full-rank basis afterwards solves as usual."""
+    n = 600
+    X = _points(n, 4, seed=41)
+    ell = workloads.median_distance(X)
+    A = OK.operator(X, 0, ell, 1.0, 1e-2)
+    lam, Q = np.linalg.eigh(A)
+    b = np.random.default_rng(5).standard_normal(n)
+    for prec in (3, 0, 1):
+        op = lib.Operator(_dev(X), 0, ell, 1.0, 1e-2, prec=prec)
+        rc = lib.Recycle(n, 8, 12)
+        Wdup = Q[:, -8:].copy()
+        Wdup[:, 5] = Wdup[:, 2]                     # a repeated column
+        rc.set_W(_dev(Wdup))
+        with pytest.raises(lib.DcgError) as e:
+            lib.solve(op, _dev(b), rc=rc, tol=1e-8)
+        assert e.value.status == -4, (prec, e.value.status)
+        with pytest.raises(lib.DcgError) as e:
+            lib.solve(op, _dev(b), rc=rc, tol=1e-8, refine=prec != 3, inner_tol=1e-2)
+        assert e.value.status == -4
+        # nearly repeated: the columns differ by 1e-9 of their norm
+        Wnear = Q[:, -8:].copy()
+        Wnear[:, 5] = Wnear[:, 2] + 1e-9 * Q[:, 0]
+        rc.set_W(_dev(Wnear))
+        with pytest.raises(lib.DcgError) as e:
+            lib.solve(op, _dev(b), rc=rc, tol=1e-8)
+        assert e.value.status == -4
+        Wnan = Q[:, -8:].copy()
+        Wnan[7, 3] = np.nan
+        rc.set_W(_dev(Wnan))
+        with pytest.raises(lib.DcgError) as e:
+            lib.solve(op, _dev(b), rc=rc, tol=1e-8)
+        assert e.value.status == -3
+        # a good basis: the handle works again
+        rc.set_W(_dev(Q[:, -8:]))
+        x, st = lib.solve(op, _dev(b), rc=rc, tol=1e-6)
+        assert st["status"] == 0 and st["k_used"] == 8
+        for bad in (np.nan, np.inf):
+            bb = b.copy()
+            bb[123] = bad
+            for kw in (dict(), dict(rc=rc), dict(refine=prec != 3, inner_tol=1e-2)):
+                with pytest.raises(lib.DcgError) as e:
+                    lib.solve(op, _dev(bb), tol=1e-8, **kw)
+                assert e.value.status == -3, (prec, bad, kw, e.value.status)
+        x, st = lib.solve(op, _dev(b), rc=rc, tol=1e-6)
+        assert st["status"] == 0
+
+
+def test_fp32_walk_full_size_matches_oracle(lib):
+    """The FP32 log-lengthscale walk at full size (n = 16384, d = 16, RBF,
+    sigma2 = 1e-2, 20 systems, def-CG(32, 48), tol 1e-6), the configuration
+    of the fp32_walk benchmark, against the oracle's run of the same walk on
+    the same FP32-rounded points (tests/golden/fp32_walk_n16384.json, written
+    by tests/golden/make_fp32_walk.py from oracle/ alone):
+    * step counts: within the band the oracle spans with exact products and
+      with per-term product errors of 1e-7 (two seeds; the FP32 operator's
+      level, checked here on the first operator), three steps of margin;
+    * the leading 8 harmonic Ritz values: within three times the largest
+      deviation the emulated runs show from the exact ones, and at least
+      1e-6 relative;
+    * the solutions: on 48 sampled rows per system the oracle forms A x one
+      row at a time; the GPU operator's product agrees with each to 2e-5 of
+      (|A| |x|)_i (its product bound), so the residual the library reports
+      with its own operator is the operator's.
+    Plain CG (the last five systems) likewise against the oracle's plain runs."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "fp32_walk_n16384.json")))
+    runs = gold["runs"]
+    w = workloads.fp32_walk()
+    X, b = w["X"], w["b"]
+    n = X.shape[0]
+    assert [round(v, 12) for v in gold["ells"]] == [round(v, 12) for v in w["ells"]]
+    op = lib.Operator(_dev(X), w["kernel"], w["ells"][0], w["s2"], w["sigma2"], prec=0)
+    rc = lib.Recycle(n, w["k"], w["L"])
+    rows = np.random.default_rng(19).choice(n, 48, replace=False)
+    for i, ell in enumerate(w["ells"]):
+        op.set_hyper(ell, w["s2"], w["sigma2"])
+        x, st = lib.solve(op, _dev(b), rc=rc, tol=w["tol"], true_residual=True)
+        assert st["status"] == 0
+        exact = [runs["literal"]["iters"][i], runs["reproject"]["iters"][i]]
+        emu = [runs[f"emulated{s}"]["iters"][i] for s in (0, 1)]
+        lo, hi = min(exact + emu) - 3, max(exact + emu) + 3
+        th = np.array(rc.theta())
+        th_ref = np.array(runs["reproject"]["theta"][i])
+        dev = max(np.max(np.abs(np.array(runs[f"emulated{s}"]["theta"][i][:8]) - th_ref[:8])
+                         / th_ref[:8]) for s in (0, 1))
+        rel = np.abs(th[:8] - th_ref[:8]) / th_ref[:8]
+        Xr = OP.round_points(X[rows], 0, w["kernel"], ell)
+        Xall = OP.round_points(X, 0, w["kernel"], ell)
+        krows = OK.gram(Xr, w["kernel"], ell, w["s2"], Xall)
+        xn = _np(x)
+        ax = krows @ xn + w["sigma2"] * xn[rows]
+        scale = np.abs(krows) @ np.abs(xn) + w["sigma2"] * np.abs(xn[rows])
+        y = _np(op.matvec(x))
+        print(f"system {i}: GPU {st['iters']} its, oracle exact {exact} emulated {emu}; "
+              f"theta rel dev {rel.max():.1e} (emulated {dev:.1e}); "
+              f"own residual {st['rel_res_true']:.1e}", flush=True)
+        assert lo <= st["iters"] <= hi, (i, st["iters"], lo, hi)
+        assert np.all(rel <= max(3 * dev, 1e-6)), (i, rel, dev)
+        assert np.all(np.abs(y[rows] - ax) <= 2e-5 * scale)
+    # the FP32 operator's error level is the one the band was drawn at
+    # (measured on 2048 sampled rows of the last operator)
+    Xr0 = OP.round_points(X, 0, w["kernel"], w["ells"][-1])
+    sub = np.random.default_rng(3).choice(n, 2048, replace=False)
+    A_sub = OK.gram(Xr0[sub], w["kernel"], w["ells"][-1], w["s2"], Xr0)
+    v = np.random.default_rng(4).standard_normal(n)
+    y = _np(op.matvec(_dev(v)))[sub] - w["sigma2"] * v[sub]
+    e = (y - A_sub @ v) / np.sqrt((A_sub * A_sub) @ (v * v))
+    eta = float(np.sqrt(np.mean(e * e)))
+    print(f"FP32 operator per-term error {eta:.2e}", flush=True)
+    assert eta <= 1e-7, eta
+    for i in range(15, 20):
+        op.set_hyper(w["ells"][i], w["s2"], w["sigma2"])
+        _, st = lib.solve(op, _dev(b), tol=w["tol"])
+        exact = runs["plain"]["iters"][i]
+        emu = [runs[f"emulated_plain{s}"]["iters"][i] for s in (0, 1)]
+        lo, hi = min([exact] + emu) - 3, max([exact] + emu) + 3
+        print(f"plain system {i}: GPU {st['iters']}, oracle {exact}, emulated {emu}", flush=True)
+        assert st["status"] == 0 and lo <= st["iters"] <= hi, (i, st["iters"], lo, hi)
