@@ -103,6 +103,7 @@ static int enqueue_batch_step(hipStream_t s, int count, dcg_operator_s *const *o
       gp(static_cast<unsigned>(plan.np_max), cy);
   hipLaunchKernelGGL(cg_matvec_finish_multi, gq, dim3(256), 0, s, d_args);
   hipLaunchKernelGGL(cg_update_xr_multi, gx, dim3(256), 0, s, d_args);
+  hipLaunchKernelGGL(cg_finalize_multi, dim3(1, cy), dim3(256), 0, s, d_args);
   hipLaunchKernelGGL(cg_update_p_multi, gp, dim3(256), 0, s, d_args);
   return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;
 }

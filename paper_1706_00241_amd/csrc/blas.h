@@ -50,10 +50,8 @@ __device__ __forceinline__ double sum_partials(const ReduceArgs &A, int m, int64
   return s;
 }
 
-// Rows finished per block by cg_matvec_finish, and rows per block of
-// cg_update_p.
+// Rows finished per block by cg_matvec_finish.
 constexpr int kCgRows = 64;
-constexpr int kPRows = 64;
 // cg_update_xr: a grid of row blocks of kXrRows rows times groups of kXrCols
 // columns of [AW | W]; its partial sums are per row block.
 constexpr int kXrRows = 1024;
@@ -91,7 +89,7 @@ struct CgArgs {
   int64_t nblk_q;                  // blocks of cg_matvec_finish (= its partials)
   int64_t nblk_xr;                 // row blocks of cg_update_xr (= its partials)
   int64_t nblk_p;                  // blocks of cg_update_p
-  unsigned *counter;  // [0]: cg_matvec_finish's tail, [1]: cg_update_xr's tail (start at 0)
+  unsigned *counter;
   double *hist_d, *hist_alpha, *hist_beta, *hist_res;
   int hist_cap;
   double *lz_alpha, *lz_beta;  // every step's alpha_j, beta_j for j < lz_cap (or null)
@@ -104,15 +102,17 @@ struct CgArgs {
 inline void cg_set_blocks(CgArgs &a) {
   a.nblk_q = (a.n + kCgRows - 1) / kCgRows;
   a.nblk_xr = (a.n + kXrRows - 1) / kXrRows;
-  a.nblk_p = (a.n + kPRows - 1) / kPRows;
+  a.nblk_p = (a.n + 255) / 256;
 }
 inline int64_t xr_grid(const CgArgs &a) { return a.nblk_xr * xr_groups(a.k); }
 
 __global__ void cg_matvec_finish(CgArgs a);
 __global__ void cg_update_xr(CgArgs a);
 __global__ void cg_update_p(CgArgs a);
+__global__ void cg_finalize(CgArgs a);
 __global__ void cg_matvec_finish_multi(const CgArgs *args);
 __global__ void cg_update_xr_multi(const CgArgs *args);
+__global__ void cg_finalize_multi(const CgArgs *args);
 __global__ void cg_update_p_multi(const CgArgs *args);
 __global__ void init_residual(const double *b, const double *Ax, double *x, double *r, int64_t n,
                               int x_given, double *part, unsigned *counter, SolveState *S);

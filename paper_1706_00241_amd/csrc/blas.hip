@@ -66,23 +66,19 @@ __device__ __forceinline__ void column_sums(const double *part, int64_t count, i
   }
 }
 
-// Returns true in every thread of the block that finished last of `count`
-// participating blocks.  The block's partial results must have been written
-// before the call; the last block resets the counter when it is done.
-__device__ __forceinline__ bool last_block_of(unsigned *counter, unsigned count) {
+// Returns true in every thread of the block that finished last.  The block's
+// partial results must have been written before the call.
+__device__ __forceinline__ bool last_block(unsigned *counter) {
   __shared__ bool is_last;
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned prev = atomicAdd(counter, 1u);
-    is_last = (prev == count - 1);
+    is_last = (prev == gridDim.x - 1);
   }
   __syncthreads();
   if (is_last) __threadfence();
   return is_last;
-}
-__device__ __forceinline__ bool last_block(unsigned *counter) {
-  return last_block_of(counter, gridDim.x);
 }
 
 // mu = Minv h (k x k dense, row-major), threads of the block over rows.
@@ -101,10 +97,8 @@ __device__ __forceinline__ void small_gemv(const double *Minv, const double *h, 
 // this body (one system or many) rounds q the same way.
 // Also stores p_j and q = A p_j into Z / AZ while j < L.  A block finishes
 // kCgRows rows in groups of 64; each row's partials are split over 4 threads
-// (memory parallelism), then added in a fixed order.  The block that finishes
-// last forms d from the block partials (fixed order), alpha = rho / d, and
-// ends the solve with DCG_E_NOT_SPD or DCG_E_NONFINITE if d is not positive
-// and finite (the step is then not applied).
+// (memory parallelism), then added in a fixed order.  No cross-block step:
+// the next kernel forms d and alpha itself from the block partials.
 __device__ __forceinline__ void cg_matvec_finish_body(const CgArgs &a, const unsigned bid) {
   SolveState *S = a.S;
   // the step count when this step began: cg_update_p applies the step's
@@ -173,42 +167,121 @@ __device__ __forceinline__ void cg_matvec_finish_body(const CgArgs &a, const uns
   }
   const double bs = block_sum_all(pq, lds);
   if (threadIdx.x == 0) a.part[bid] = bs;
-  if (last_block_of(a.counter, static_cast<unsigned>(a.nblk_q))) {
-    const double d = block_sum_array(a.part, a.nblk_q, lds);
-    if (threadIdx.x == 0) {
-      const bool bad = !(d > 0.0) || !isfinite(d);
-      const double alpha = bad ? 0.0 : S->rho / d;
-      S->d = d;
-      S->alpha = alpha;
-      if (bad) {
-        S->status = isfinite(d) ? DCG_E_NOT_SPD : DCG_E_NONFINITE;
-        S->done = 1;
-      }
-      if (j < a.L) {
-        a.hist_d[j] = d;
-        a.hist_alpha[j] = alpha;
-      }
-      if (a.lz_alpha != nullptr && j < a.lz_cap) a.lz_alpha[j] = alpha;
-      a.counter[0] = 0;
+}
+
+// d = p^T q from the partials of cg_matvec_finish (every block forms it, in
+// the same order), alpha = rho / d, and with r' = r - alpha q (formed here
+// and again, identically, by cg_update_p, which writes x and r): per row
+// block the partials of rho' = r'^T r' and of h = (AW)^T r', g = W^T r'.
+// Block (row block rb, column group grp) takes rows rb * kXrRows ... and
+// columns grp * kXrCols ... of [AW | W]; group 0 also forms rho'.  The
+// kernel writes no vector, so the column groups of one row block never see
+// each other's updates.
+__device__ __forceinline__ void cg_update_xr_body(const CgArgs &a, const unsigned bid) {
+  SolveState *S = a.S;
+  if (S->done) return;
+  const int64_t nrb = a.nblk_xr;
+  const int rb = static_cast<int>(bid % nrb);
+  const int grp = static_cast<int>(bid / nrb);
+  const int k = a.k;
+  if (grp >= xr_groups(k)) return;
+  __shared__ double lds[8];
+  __shared__ double cpart[4][kXrCols];
+  const double d = block_sum_array(a.part, a.nblk_q, lds);
+  const bool bad = !(d > 0.0) || !isfinite(d);
+  const double alpha = bad ? 0.0 : S->rho / d;
+  if (bid == 0 && threadIdx.x == 0) {
+    S->d = d;
+    S->alpha = alpha;
+    const int j = S->iter;
+    if (j < a.L) {
+      a.hist_d[j] = d;
+      a.hist_alpha[j] = alpha;
     }
+    if (a.lz_alpha != nullptr && j < a.lz_cap) a.lz_alpha[j] = alpha;
+  }
+  constexpr int RPT = kXrRows / 256;
+  const int64_t i0 = int64_t(rb) * kXrRows + threadIdx.x;
+  double ri[RPT];
+  double rr = 0.0;
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int64_t i = i0 + 256 * u;
+    ri[u] = 0.0;
+    if (i < a.n) {
+      ri[u] = a.r[i] - alpha * a.q[i];
+      rr += ri[u] * ri[u];
+    }
+  }
+  if (grp == 0) {
+    const double bs = block_sum_all(rr, lds);
+    if (threadIdx.x == 0) a.part2[rb] = bad ? (isfinite(d) ? -1.0 : -2.0) : bs;
+  }
+  if (k == 0) return;
+  // partial dots with kXrCols columns of [AW | W]; all loads issued first
+  double sv[kXrCols];
+#pragma unroll
+  for (int cc = 0; cc < kXrCols; ++cc) {
+    const int c = grp * kXrCols + cc;
+    double acc = 0.0;
+    if (c < 2 * k) {
+      const double *Y = (c < k) ? a.AW + int64_t(c) * a.n : a.W + int64_t(c - k) * a.n;
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) {
+        const int64_t i = i0 + 256 * u;
+        if (i < a.n) acc += Y[i] * ri[u];
+      }
+    }
+    sv[cc] = acc;
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int cc = 0; cc < kXrCols; ++cc) {
+    double v = sv[cc];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    if (l == 0) cpart[w][cc] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kXrCols) {
+    const int c = grp * kXrCols + threadIdx.x;
+    if (c < 2 * k)
+      a.part_h[int64_t(c) * nrb + rb] = (cpart[0][threadIdx.x] + cpart[1][threadIdx.x]) +
+                                         (cpart[2][threadIdx.x] + cpart[3][threadIdx.x]);
   }
 }
 
-// The finalize step of one CG step, run by the block of cg_update_xr that
-// finishes last: the sums of cg_update_xr's partials in a fixed order, then
-// the re-projection c = (W^T A W)^{-1} g of the residual (zero in exact
+// One block: the sums of cg_update_xr's partials in a fixed order, then the
+// re-projection c = (W^T A W)^{-1} g of the residual (zero in exact
 // arithmetic, where W^T r_j = 0), and with r' = r - AW c:
 // mu = (W^T A W)^{-1} (AW)^T r', beta = |r'|^2 / |r|^2 and the convergence
 // test on |r'| / |b|.
-__device__ __forceinline__ void cg_finalize_tail(const CgArgs &a) {
+__device__ __forceinline__ void cg_finalize_body(const CgArgs &a) {
   SolveState *S = a.S;
+  if (S->done) return;
   __shared__ double lds[8];
   __shared__ double hg[2 * kMaxK];   // h = (AW)^T r, then g = W^T r
   __shared__ double cv[kMaxK];       // c = M^-1 g
   __shared__ double nc[kMaxK];       // N c
   __shared__ double hn[kMaxK];       // h - N c
+  __shared__ int flag;
   const int k = a.k;
   const int64_t nblk = a.nblk_xr;
+  if (threadIdx.x == 0) flag = 0;
+  __syncthreads();
+  // a negative partial marks p^T A p <= 0 (-1) or non-finite (-2)
+  for (int64_t b = threadIdx.x; b < nblk; b += 256) {
+    const double v = a.part2[b];
+    if (v < 0.0) atomicMax(&flag, v < -1.5 ? 2 : 1);
+  }
+  __syncthreads();
+  if (flag != 0) {
+    if (threadIdx.x == 0) {
+      S->status = (flag == 2) ? DCG_E_NONFINITE : DCG_E_NOT_SPD;
+      S->done = 1;
+    }
+    return;
+  }
   // column sums of [h | g]: thread c sums its column with 8 accumulators
   for (int c = threadIdx.x; c < 2 * k; c += 256) {
     const double *pc = a.part_h + int64_t(c) * nblk;
@@ -252,155 +325,52 @@ __device__ __forceinline__ void cg_finalize_tail(const CgArgs &a) {
     } else if (rel <= a.tol || j + 1 >= a.max_iter) {
       S->done = 1;
     }
-    a.counter[1] = 0;
   }
-}
-
-// With r' = r - alpha q (alpha from the tail of cg_matvec_finish; r' formed
-// here and again, identically, by cg_update_p, which writes x and r): per row
-// block the partials of rho' = r'^T r' and of h = (AW)^T r', g = W^T r'.
-// Block (row block rb, column group grp) takes rows rb * kXrRows ... and
-// columns grp * kXrCols ... of [AW | W]; group 0 also forms rho'.  The
-// kernel writes no vector, so the column groups of one row block never see
-// each other's updates.  The block that finishes last runs the finalize step.
-__device__ __forceinline__ void cg_update_xr_body(const CgArgs &a, const unsigned bid) {
-  SolveState *S = a.S;
-  if (S->done) return;
-  const int64_t nrb = a.nblk_xr;
-  const int rb = static_cast<int>(bid % nrb);
-  const int grp = static_cast<int>(bid / nrb);
-  const int k = a.k;
-  __shared__ double lds[8];
-  __shared__ double cpart[4][kXrCols];
-  const double alpha = S->alpha;
-  constexpr int RPT = kXrRows / 256;
-  const int64_t i0 = int64_t(rb) * kXrRows + threadIdx.x;
-  double ri[RPT];
-  double rr = 0.0;
-#pragma unroll
-  for (int u = 0; u < RPT; ++u) {
-    const int64_t i = i0 + 256 * u;
-    ri[u] = 0.0;
-    if (i < a.n) {
-      ri[u] = a.r[i] - alpha * a.q[i];
-      rr += ri[u] * ri[u];
-    }
-  }
-  if (grp == 0) {
-    const double bs = block_sum_all(rr, lds);
-    if (threadIdx.x == 0) a.part2[rb] = bs;
-  }
-  if (k > 0) {
-    // partial dots with kXrCols columns of [AW | W]; all loads issued first
-    double sv[kXrCols];
-#pragma unroll
-    for (int cc = 0; cc < kXrCols; ++cc) {
-      const int c = grp * kXrCols + cc;
-      double acc = 0.0;
-      if (c < 2 * k) {
-        const double *Y = (c < k) ? a.AW + int64_t(c) * a.n : a.W + int64_t(c - k) * a.n;
-#pragma unroll
-        for (int u = 0; u < RPT; ++u) {
-          const int64_t i = i0 + 256 * u;
-          if (i < a.n) acc += Y[i] * ri[u];
-        }
-      }
-      sv[cc] = acc;
-    }
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-#pragma unroll
-    for (int cc = 0; cc < kXrCols; ++cc) {
-      double v = sv[cc];
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-      if (l == 0) cpart[w][cc] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < kXrCols) {
-      const int c = grp * kXrCols + threadIdx.x;
-      if (c < 2 * k)
-        a.part_h[int64_t(c) * nrb + rb] = (cpart[0][threadIdx.x] + cpart[1][threadIdx.x]) +
-                                           (cpart[2][threadIdx.x] + cpart[3][threadIdx.x]);
-    }
-  }
-  if (last_block_of(a.counter + 1, static_cast<unsigned>(nrb * xr_groups(k)))) cg_finalize_tail(a);
 }
 
 // The step x += alpha p, r -= alpha q, then the re-projection (x += W c,
 // r -= AW c) and the direction update p = beta p + r - W mu; the FP32 copy of
-// p feeds the next matvec.  A block takes kPRows rows; its four waves split
-// the k columns of W and AW (columns w, w + 4, ...), so every lane keeps
-// about k / 2 loads in flight, and wave 0 adds the four partial sums in a
-// fixed order and writes the row.
+// p feeds the next matvec.
 __device__ __forceinline__ void cg_update_p_body(const CgArgs &a, const unsigned bid) {
   SolveState *S = a.S;
   // A step that converges (or reaches max_iter) still applies its update:
-  // cg_update_xr's tail has advanced iter past the count cg_matvec_finish
-  // recorded.  Steps after the end, and a step that failed (iter not
-  // advanced), do not.
+  // cg_finalize has advanced iter past the count cg_matvec_finish recorded.
+  // Steps after the end, and a step that failed (iter not advanced), do not.
   if (S->done && S->applied == S->iter) return;
   __shared__ double mu[kMaxK];
   __shared__ double cv[kMaxK];
-  __shared__ double part[3][4][kPRows];
   for (int c = threadIdx.x; c < a.k; c += 256) {
     mu[c] = S->mu[c];
     cv[c] = S->cvec[c];
   }
   __syncthreads();
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t i = int64_t(bid) * kPRows + l;
-  const int64_t n = a.n;
-  double xi = 0.0, wmu = 0.0, awc = 0.0;
-  if (i < n) {
-    int c = w;
-    for (; c + 12 < a.k; c += 16) {
-      double wv[4], av[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        wv[u] = a.W[int64_t(c + 4 * u) * n + i];
-        av[u] = a.AW[int64_t(c + 4 * u) * n + i];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        xi += wv[u] * cv[c + 4 * u];
-        wmu += wv[u] * mu[c + 4 * u];
-        awc += av[u] * cv[c + 4 * u];
-      }
-    }
-    for (; c < a.k; c += 4) {
-      const double wv = a.W[int64_t(c) * n + i], av = a.AW[int64_t(c) * n + i];
-      xi += wv * cv[c];
-      wmu += wv * mu[c];
-      awc += av * cv[c];
-    }
-  }
-  part[0][w][l] = xi;
-  part[1][w][l] = wmu;
-  part[2][w][l] = awc;
-  __syncthreads();
-  if (w != 0 || i >= n) return;
-  xi = (part[0][0][l] + part[0][1][l]) + (part[0][2][l] + part[0][3][l]);
-  wmu = (part[1][0][l] + part[1][1][l]) + (part[1][2][l] + part[1][3][l]);
-  awc = (part[2][0][l] + part[2][1][l]) + (part[2][2][l] + part[2][3][l]);
+  const int64_t i = int64_t(bid) * 256 + threadIdx.x;
+  if (i >= a.n) return;
   const double alpha = S->alpha;
   const double pi = a.p[i];
   double ri = a.r[i] - alpha * a.q[i];
   double xn = a.x[i] + alpha * pi;
-  if (a.k > 0) {
-    ri -= awc;
-    xn += xi;
+  double xi = 0.0;
+  double wmu = 0.0;
+  for (int c = 0; c < a.k; ++c) {
+    const double wv = a.W[int64_t(c) * a.n + i];
+    ri -= a.AW[int64_t(c) * a.n + i] * cv[c];
+    xi += wv * cv[c];
+    wmu += wv * mu[c];
   }
+  if (a.k > 0) xn += xi;
   a.r[i] = ri;
   a.x[i] = xn;
-  const double sp = ri + S->beta * pi - wmu;
-  a.p[i] = sp;
-  a.p32[i] = static_cast<float>((a.red.dsc != nullptr) ? a.red.dsc[i] * sp : sp);
+  const double s = ri + S->beta * pi - wmu;
+  a.p[i] = s;
+  a.p32[i] = static_cast<float>((a.red.dsc != nullptr) ? a.red.dsc[i] * s : s);
 }
 
 // Kernels: one solve (arguments by value), or many columns / systems at once
 // (blockIdx.y selects the arguments of a column or system).
 __global__ __launch_bounds__(256) void cg_matvec_finish(CgArgs a) { cg_matvec_finish_body(a, blockIdx.x); }
 __global__ __launch_bounds__(256) void cg_update_xr(CgArgs a) { cg_update_xr_body(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void cg_finalize(CgArgs a) { cg_finalize_body(a); }
 __global__ __launch_bounds__(256) void cg_update_p(CgArgs a) { cg_update_p_body(a, blockIdx.x); }
 
 __global__ __launch_bounds__(256) void cg_matvec_finish_multi(const CgArgs *args) {
@@ -413,9 +383,12 @@ __global__ __launch_bounds__(256) void cg_update_xr_multi(const CgArgs *args) {
   if (int64_t(blockIdx.x) >= a.nblk_xr * xr_groups(a.k)) return;
   cg_update_xr_body(a, blockIdx.x);
 }
+__global__ __launch_bounds__(256) void cg_finalize_multi(const CgArgs *args) {
+  cg_finalize_body(args[blockIdx.y]);
+}
 __global__ __launch_bounds__(256) void cg_update_p_multi(const CgArgs *args) {
   const CgArgs &a = args[blockIdx.y];
-  if (int64_t(blockIdx.x) * kPRows >= a.n) return;
+  if (int64_t(blockIdx.x) * 256 >= a.n) return;
   cg_update_p_body(a, blockIdx.x);
 }
 

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void block_init(const double *B, const double 
 }
 
 struct BlockLayout {
-  size_t args, S, R, P, Q, T, P32, part, part2, parth, hist, Cm, Cm2, gemm, ctr, total;
+  size_t args, S, R, P, Q, T, P32, part, part2, parth, hist, Cm, Cm2, gemm, total;
 };
 
 static BlockLayout block_layout(int64_t n, int64_t m) {
@@ -104,7 +104,6 @@ static BlockLayout block_layout(int64_t n, int64_t m) {
   L.Cm = take(size_t(kMaxK) * m * 8);
   L.Cm2 = take(size_t(kMaxK) * m * 8);
   L.gemm = take(size_t(64) * kMaxK * m * 8);
-  L.ctr = take(size_t(m) * 2 * sizeof(unsigned));
   L.total = align256(off);
   return L;
 }
@@ -157,7 +156,6 @@ int dcg::solve_block_impl(dcg_op_t op, const double *B, double *X, int64_t m, dc
   double *Cm = reinterpret_cast<double *>(base + Lb.Cm);
   double *Cm2 = reinterpret_cast<double *>(base + Lb.Cm2);
   double *gemm = reinterpret_cast<double *>(base + Lb.gemm);
-  unsigned *ctr = reinterpret_cast<unsigned *>(base + Lb.ctr);
   const size_t gemm_cap = size_t(64) * kMaxK * m;
   const int max_iter = p->max_iter > 0 ? p->max_iter : static_cast<int>(std::min<int64_t>(10 * n, 1 << 30));
 
@@ -169,7 +167,6 @@ int dcg::solve_block_impl(dcg_op_t op, const double *B, double *X, int64_t m, dc
     k = rc->k_used;
   }
   HIPCHK(hipMemsetAsync(X, 0, size_t(n) * m * 8, s));
-  HIPCHK(hipMemsetAsync(ctr, 0, size_t(m) * 2 * sizeof(unsigned), s));
   HIPCHK(hipMemcpyAsync(R, B, size_t(n) * m * 8, hipMemcpyDeviceToDevice, s));
   if (k > 0) {
     // deflated start for every column: C = M^-1 W^T R, X = W C, R = B - A (W C)
@@ -224,7 +221,7 @@ int dcg::solve_block_impl(dcg_op_t op, const double *B, double *X, int64_t m, dc
     a.part2 = part2 + c * nx;
     a.part_h = parth + c * 2 * kMaxK * nx;
     cg_set_blocks(a);
-    a.counter = ctr + 2 * c;   // the tails of the finish and x / r kernels
+    a.counter = nullptr;
     double *h = hist + c * (kBlockHist + 3 * kMaxZ);
     a.hist_res = h;
     a.hist_cap = kBlockHist;
@@ -267,6 +264,7 @@ int dcg::solve_block_impl(dcg_op_t op, const double *B, double *X, int64_t m, dc
       }
       hipLaunchKernelGGL(cg_update_xr_multi, dim3(static_cast<unsigned>(xr_grid(args[0])), static_cast<unsigned>(m)),
                          dim3(256), 0, s, d_args);
+      hipLaunchKernelGGL(cg_finalize_multi, dim3(1, static_cast<unsigned>(m)), dim3(256), 0, s, d_args);
       hipLaunchKernelGGL(cg_update_p_multi, dim3(static_cast<unsigned>(args[0].nblk_p), static_cast<unsigned>(m)),
                          dim3(256), 0, s, d_args);
       HIPCHK(hipGetLastError());

@@ -2,11 +2,12 @@
 // Ritz refresh of the recycled basis (section 2.3, Eq. 7), plus the
 // mixed-precision iterative refinement around it.
 //
-// Per CG step four kernels run on the operator's stream: the symmetric pair
-// sweep (q = A p partials), the product finish with d = p^T q and alpha (in
-// its last block), the pass over r' = r - alpha q with rho' and
-// h = (AW)^T r' whose last block runs the scalar step (re-projection, mu,
-// beta, the convergence test), and the direction update p = beta p + r - W mu.  All scalars stay on the device; the host reads the
+// Per CG step five kernels run on the operator's stream: the symmetric pair
+// sweep (q = A p partials), the product finish with the block partials of
+// d = p^T q, the pass over r' = r - alpha q with the partials of rho' and
+// h = (AW)^T r', g = W^T r', one block for the scalar step (re-projection,
+// mu, beta, the convergence test), and the direction update
+// p = beta p + r - W mu.  All scalars stay on the device; the host reads the
 // solve state once per chunk of iterations (optionally replayed as one
 // captured hipGraph), so the loop has one host round trip per chunk.
 #include <algorithm>
@@ -207,8 +208,7 @@ static CgArgs cg_args(dcg_operator_s *op, const SolveBuffers &B, double *x, dcg_
   a.part = B.part;
   a.part2 = B.part + std::max<int64_t>(a.nblk_q, 1);
   a.part_h = B.part_h;
-  // counters 0-3 serve the set-up kernels, 4-5 the tails of the step kernels
-  a.counter = B.counter + 4;
+  a.counter = B.counter;
   a.hist_d = B.hist_d;
   a.hist_alpha = B.hist_alpha;
   a.hist_beta = B.hist_beta;
@@ -241,6 +241,7 @@ static int enqueue_cg_step(dcg_operator_s *op, const CgArgs &a, hipEvent_t ev0 =
                      op->stream, a);
   hipLaunchKernelGGL(cg_update_xr, dim3(static_cast<unsigned>(xr_grid(a))), dim3(256), 0,
                      op->stream, a);
+  hipLaunchKernelGGL(cg_finalize, dim3(1), dim3(256), 0, op->stream, a);
   hipLaunchKernelGGL(cg_update_p, dim3(static_cast<unsigned>(a.nblk_p)), dim3(256), 0,
                      op->stream, a);
   return hipGetLastError() == hipSuccess ? DCG_OK : DCG_E_HIP;

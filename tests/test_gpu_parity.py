@@ -409,7 +409,9 @@ def test_exact_eigenvector_deflation(lib, prec, sigma2, tol):
     print(f"prec {prec} sigma2 {sigma2}: eta {eta:.2e}; GPU {st['iters']} / plain "
           f"{plain['iters']}; oracle {ref.iters} / {ref_plain.iters}; emulated {emu}", flush=True)
     assert lo <= st["iters"] <= hi, (st["iters"], lo, hi)
-    if prec == 3:
+    if prec == 3 and ref_plain.iters <= n // 2:
+        # (beyond n / 2 steps the count of finite-precision CG follows the
+        # rounding order of its inner products, which no band pins down)
         emu_p = [OC.cg(noisy_product(A, eta_e, s), b, tol=tol).iters for s in seeds]
         lo, hi = min(emu_p + [ref_plain.iters]) - 2, max(emu_p + [ref_plain.iters]) + 2
         assert lo <= plain["iters"] <= hi, (plain["iters"], emu_p, ref_plain.iters)
@@ -455,7 +457,8 @@ def test_precision_form_reduced_headline_matches_oracle(lib):
       A-orthonormal basis): the leading 16 within the spread that the GPU
       operator's error level causes, measured by rerunning the oracle's
       first system with per-term product errors of twice that level (two
-      seeds; tests/emulation.py), times three, and at least 1e-9."""
+      seeds; tests/emulation.py), times three, and at least 1e-6 theta_1
+      (Weyl's bound for the FP32 evaluation error of the operator)."""
     import scipy.linalg as sl
     from oracle import refine as ORF
     n, k, L = 8192, 64, 96
@@ -508,9 +511,19 @@ def test_precision_form_reduced_headline_matches_oracle(lib):
         assert abs(res - st["rel_res_true"]) <= 1e-3 * res + 1e-15
         assert err_A <= 1e-7, err_A
         assert len(th) == st["k_next"] and abs(len(th) - len(th_ref)) <= 2
+        # Weyl: an operator error E moves every eigenvalue by at most
+        # |E|_2 <= eps |A|_2 (entrywise positive kernel matrix, eps the
+        # largest relative error of an FP32-evaluated entry, below 1e-6), so
+        # no value is held closer than 1e-6 theta_1
         rel = np.abs(th[:16] - th_ref[:16]) / th_ref[:16]
-        assert np.all(rel <= (spread if i == 0 else 3 * spread)), (i, rel, spread)
-    assert st["k_used"] == k
+        bound = np.maximum(spread if i == 0 else 3 * spread, 1e-6 * th_ref[0] / th_ref[:16])
+        assert np.all(rel <= bound), (i, rel, bound)
+        # the basis carried over is the previous extraction's (at this size the
+        # first inner solve stops after fewer than k steps, so fewer than k
+        # directions exist to keep)
+        if i > 0:
+            assert st["k_used"] == k_prev, (st["k_used"], k_prev)
+        k_prev = st["k_next"]
 
 
 def test_precision_form_full_size_residual_rows(lib):
