@@ -315,6 +315,31 @@ int dcg_extract_basis(const double *Z, const double *AZ, int64_t n, int m, int k
                       int extraction, int route, double *W_out, double *theta_out, int *k_out,
                       int *rank_out, void *stream, void *ws, size_t ws_bytes);
 
+/* ------------------------------------- extraction without any allocation
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * extraction as dcg_extract_basis, with the same kernels and the same results
+ * bit for bit, but its scratch (F, G and their split-K partial sums, the
+ * eigensolver's work arrays, U, theta, status words) lives in a library-held
+ * device array of dcg_extract_basis_noalloc_max_bytes() bytes (about 20 MiB,
+ * the workspace of the largest pencil, m = 192), one per device, held until
+ * the process ends.  The call allocates nothing (no hipMalloc, no allocating
+ * library routine); the caller passes Z, AZ and W_out as for
+ * dcg_extract_basis.
+ *  stream  must belong to the current device (NULL: its null stream); the
+ *          scratch used is the current device's.
+ * Sizes beyond the scratch's reach (m > 192, k > 64) are DCG_E_ARG, as for
+ * dcg_extract_basis; DCG_E_HIP if the device or the array's address cannot be
+ * obtained.  Every call on one device shares that device's array, which keeps
+ * the last call's contents (nothing in it needs to start at zero): calls that
+ * overlap on one device, from several host threads or on several streams,
+ * race and must be serialised by the caller.  The call returns once its
+ * results are in place. */
+size_t dcg_extract_basis_noalloc_max_bytes(void);
+int dcg_extract_basis_noalloc(const double *Z, const double *AZ, int64_t n, int m, int k,
+                              int largest, int extraction, int route, double *W_out,
+                              double *theta_out, int *k_out, int *rank_out, void *stream);
+
 /* ------------------------------------------------ many right-hand sides
  * X = A^{-1} B for m <= 64 columns at once: every column runs its own
  * deflated CG (Algorithm 1) with the basis W held by rc (reused as it is, no

@@ -126,6 +126,13 @@ _SIGS = {
                                          ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_size_t]),
+    "dcg_extract_basis_noalloc_max_bytes": (ctypes.c_size_t, []),
+    "dcg_extract_basis_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                                 ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                                 ctypes.POINTER(ctypes.c_double),
+                                                 ctypes.POINTER(ctypes.c_int),
+                                                 ctypes.POINTER(ctypes.c_int), ctypes.c_void_p]),
     "dcg_laplace_gpc_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
     "dcg_laplace_gpc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.POINTER(Params), ctypes.c_int, ctypes.c_double,
@@ -668,6 +675,36 @@ def extract_basis(Z, AZ, k, largest=True, extraction="harmonic", ritz_route="aut
            "dcg_extract_basis")
     kk = kout.value
     return W[:kk].t(), [th[i] for i in range(kk)], rank.value
+
+
+def extract_basis_noalloc(Z, AZ, W_out, largest=True, extraction="harmonic", ritz_route="auto"):
+    """extract_basis without any device allocation in the library: the
+    scratch is the library's own device array of the current device.  W_out
+    is a caller-given (k, n) FP64 tensor on Z's device (k <= 64) whose first
+    k_out rows receive the columns of W' = Z U.  Returns (k_out, the kept Ritz
+    values, the number of directions of the metric kept).  Runs on the
+    caller's current stream; calls that overlap on one device race."""
+    torch = _torch()
+    lib = load()
+    dev = Z.device
+    n, m = Z.shape
+    k = W_out.shape[0]
+    if W_out.shape[1] != n or W_out.dtype != torch.float64 or not W_out.is_contiguous() \
+            or W_out.device != dev:
+        raise ValueError("W_out must be a contiguous (k, n) float64 tensor on Z's device")
+    Zc = _colmajor(Z)
+    AZc = _colmajor(AZ.to(dev))
+    th = (ctypes.c_double * k)()
+    kout, rank = ctypes.c_int(0), ctypes.c_int(0)
+    with torch.cuda.device(dev):
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        _check(lib.dcg_extract_basis_noalloc(Zc.data_ptr(), AZc.data_ptr(), n, m, int(k),
+                                             1 if largest else 0, _extraction(extraction),
+                                             _ritz_route(ritz_route), W_out.data_ptr(), th,
+                                             ctypes.byref(kout), ctypes.byref(rank), stream),
+               "dcg_extract_basis_noalloc")
+    kk = kout.value
+    return kk, [th[i] for i in range(kk)], rank.value
 
 
 class GPMarginalLikelihood:

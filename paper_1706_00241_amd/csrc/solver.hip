@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "solve.h"
@@ -921,6 +922,10 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
   return with_refresh(st, rc, status);
 }
 
+}  // extern "C"
+
+namespace dcg {
+
 // ------------------------------------------- extraction on given Z, AZ
 
 static size_t ritz_ws_layout(int64_t n, int m, size_t *off) {
@@ -936,23 +941,10 @@ static size_t ritz_ws_layout(int64_t n, int m, size_t *off) {
   return align256(c.off);
 }
 
-size_t dcg_extract_basis_workspace_bytes(int64_t n, int m) {
-  if (n < 1 || m < 1 || m > kMaxZ) return 0;
-  size_t off[7];
-  return ritz_ws_layout(n, m, off);
-}
-
-int dcg_extract_basis(const double *Z, const double *AZ, int64_t n, int m, int k, int largest,
-                      int extraction, int route, double *W_out, double *theta_out, int *k_out,
-                      int *rank_out, void *stream, void *ws, size_t ws_bytes) {
-  if (Z == nullptr || AZ == nullptr || W_out == nullptr || theta_out == nullptr ||
-      k_out == nullptr || n < 1 || m < 1 || m > kMaxZ || k < 1 || k > kMaxK || route < 0 ||
-      route > 1 || extraction < 0 || extraction > 1)
-    return DCG_E_ARG;
-  size_t off[7];
-  if (ws == nullptr || ws_bytes < ritz_ws_layout(n, m, off)) return DCG_E_WORKSPACE;
-  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return DCG_E_WORKSPACE;
-  char *b = static_cast<char *>(ws);
+static int extract_on_given(const double *Z, const double *AZ, int64_t n, int m, int k,
+                            int largest, int extraction, int route, double *W_out,
+                            double *theta_out, int *k_out, int *rank_out, hipStream_t s, char *b,
+                            const size_t *off) {
   double *F = reinterpret_cast<double *>(b + off[0]);
   double *G = reinterpret_cast<double *>(b + off[1]);
   double *eigw = reinterpret_cast<double *>(b + off[2]);
@@ -960,7 +952,6 @@ int dcg_extract_basis(const double *Z, const double *AZ, int64_t n, int m, int k
   double *th = reinterpret_cast<double *>(b + off[4]);
   int *info_d = reinterpret_cast<int *>(b + off[5]);
   double *part = reinterpret_cast<double *>(b + off[6]);
-  hipStream_t s = static_cast<hipStream_t>(stream);
   enqueue_extraction_pencil(s, Z, AZ, n, m, extraction, part, F, G);
   enqueue_harmonic_ritz(s, F, G, m, k, largest != 0, route, 1e-12, eigw, U, th, info_d);
   int info[4] = {0, 0, 0, 0};
@@ -976,6 +967,87 @@ int dcg_extract_basis(const double *Z, const double *AZ, int64_t n, int m, int k
   *k_out = knew;
   if (rank_out != nullptr) *rank_out = info[1];
   return DCG_OK;
+}
+
+static bool extract_args_ok(const double *Z, const double *AZ, int64_t n, int m, int k,
+                            int extraction, int route, const double *W_out,
+                            const double *theta_out, const int *k_out) {
+  return !(Z == nullptr || AZ == nullptr || W_out == nullptr || theta_out == nullptr ||
+           k_out == nullptr || n < 1 || m < 1 || m > kMaxZ || k < 1 || k > kMaxK || route < 0 ||
+           route > 1 || extraction < 0 || extraction > 1);
+}
+
+// ------------------------------------- extraction without any allocation
+// The scratch of dcg_extract_basis_noalloc: the extraction's workspace at its
+// largest pencil (m = kMaxZ), a file-scope device array.  Every device the
+// library runs on holds its own copy until the process ends; host code uses
+// the address hipGetSymbolAddress gives for the current device, never the
+// array's name (which on the host is only a stand-in for the symbol).
+static constexpr size_t a256c(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t kExtractScratchBytes =
+    2 * a256c(size_t(kMaxZ) * kMaxZ * 8) + a256c(size_t(3) * kMaxZ * kMaxZ * 8) +
+    a256c(size_t(kMaxZ) * kMaxK * 8) + a256c(size_t(kMaxK) * 8) + a256c(4 * sizeof(int)) +
+    a256c(kGemmPartDoubles * 8);
+static __device__ __align__(256) char scratch[kExtractScratchBytes];
+
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[kScratchDevices];
+
+// Address of the current device's scratch array, looked up once per device.
+static int scratch_address(char **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return DCG_E_HIP;
+  std::lock_guard<std::mutex> guard(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr)
+      return DCG_E_HIP;
+    g_scratch_ptr[dev] = static_cast<char *>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return DCG_OK;
+}
+
+}  // namespace dcg
+
+extern "C" {
+
+using namespace dcg;
+
+size_t dcg_extract_basis_workspace_bytes(int64_t n, int m) {
+  if (n < 1 || m < 1 || m > kMaxZ) return 0;
+  size_t off[7];
+  return ritz_ws_layout(n, m, off);
+}
+
+int dcg_extract_basis(const double *Z, const double *AZ, int64_t n, int m, int k, int largest,
+                      int extraction, int route, double *W_out, double *theta_out, int *k_out,
+                      int *rank_out, void *stream, void *ws, size_t ws_bytes) {
+  if (!extract_args_ok(Z, AZ, n, m, k, extraction, route, W_out, theta_out, k_out))
+    return DCG_E_ARG;
+  size_t off[7];
+  if (ws == nullptr || ws_bytes < ritz_ws_layout(n, m, off)) return DCG_E_WORKSPACE;
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return DCG_E_WORKSPACE;
+  return extract_on_given(Z, AZ, n, m, k, largest, extraction, route, W_out, theta_out, k_out,
+                          rank_out, static_cast<hipStream_t>(stream), static_cast<char *>(ws),
+                          off);
+}
+
+size_t dcg_extract_basis_noalloc_max_bytes(void) { return kExtractScratchBytes; }
+
+int dcg_extract_basis_noalloc(const double *Z, const double *AZ, int64_t n, int m, int k,
+                              int largest, int extraction, int route, double *W_out,
+                              double *theta_out, int *k_out, int *rank_out, void *stream) {
+  if (!extract_args_ok(Z, AZ, n, m, k, extraction, route, W_out, theta_out, k_out))
+    return DCG_E_ARG;
+  size_t off[7];
+  if (ritz_ws_layout(n, m, off) > kExtractScratchBytes) return DCG_E_WORKSPACE;
+  char *b = nullptr;
+  const int rcode = scratch_address(&b);
+  if (rcode != DCG_OK) return rcode;
+  return extract_on_given(Z, AZ, n, m, k, largest, extraction, route, W_out, theta_out, k_out,
+                          rank_out, static_cast<hipStream_t>(stream), b, off);
 }
 
 }  // extern "C"

@@ -144,3 +144,26 @@ def test_extract_basis_arguments_without_gpu(L):
     assert call(args(route=2)) == -1
     assert call(args(kind=2)) == -1
     assert call(args()) == -6
+
+
+def test_extract_basis_noalloc_arguments_without_gpu(L):
+    """The entry point without allocation: its scratch is sized for the
+    largest pencil (m = 192, k = 64), and every size beyond it, like every
+    other argument error, is refused before any HIP call."""
+    assert L.dcg_extract_basis_noalloc_max_bytes() >= L.dcg_extract_basis_workspace_bytes(10**7, 192)
+    assert L.dcg_extract_basis_noalloc_max_bytes() <= 24 * 2**20
+    buf = ctypes.create_string_buffer(4096)
+    th = (ctypes.c_double * 64)()
+    k, r = ctypes.c_int(0), ctypes.c_int(0)
+
+    def call(Z=buf, n=100, m=10, kk=4, kind=0, route=0, W=buf):
+        return L.dcg_extract_basis_noalloc(Z, buf, n, m, kk, 1, kind, route, W, th,
+                                           ctypes.byref(k), ctypes.byref(r), None)
+    assert call(Z=None) == -1
+    assert call(W=None) == -1
+    assert call(n=0) == -1
+    assert call(m=0) == -1
+    assert call(m=193) == -1
+    assert call(kk=65) == -1
+    assert call(kind=2) == -1
+    assert call(route=2) == -1
