@@ -54,7 +54,10 @@ class DefCGResult:
         self.d = []             # d_j = p_j^T A p_j
         self.alpha = []
         self.beta = []
-        self.mu = []            # mu_j (k-vectors)
+        self.mu = []            # mu_j (k-vectors), j = 0 .. L_eff
+        self.rho = []           # rho_j = r_j^T r_j, j = 0 .. L_eff
+        self.cvec = []          # re-projection coefficients c_{j+1}, j < L_eff
+        self.p_next = None      # p_{L_eff}, the direction after the stored ones
         self.r_final = None
 
 
@@ -113,6 +116,7 @@ def defcg(A, b, x_init=None, W=None, AW=None, tol=1e-8, L=0, max_iter=None,
 
     rho = r @ r
     res.res_hist.append(np.sqrt(rho) / bnorm)
+    res.rho.append(rho)
     Ps, APs = [], []
     all_r = [r.copy()] if store_all else None
     all_p = [p.copy()] if store_all else None
@@ -135,6 +139,8 @@ def defcg(A, b, x_init=None, W=None, AW=None, tol=1e-8, L=0, max_iter=None,
             c = msolve(W.T @ r)
             x = x + W @ c
             r = r - AW @ c
+            if j < L:
+                res.cvec.append(c)
         rho_new = r @ r
         beta = rho_new / rho
         rho = rho_new
@@ -145,13 +151,18 @@ def defcg(A, b, x_init=None, W=None, AW=None, tol=1e-8, L=0, max_iter=None,
             p = beta * p + r
         if j < L:
             res.beta.append(beta)
+            res.rho.append(rho)
             if deflate:
                 res.mu.append(mu)
+            if j + 1 == L:
+                res.p_next = p.copy()
         j += 1
         res.res_hist.append(np.sqrt(rho) / bnorm)
         if store_all:
             all_r.append(r.copy())
             all_p.append(p.copy())
+    if j < L:
+        res.p_next = p.copy()
     res.x = x
     res.iters = j
     res.converged = np.sqrt(rho) / bnorm <= tol

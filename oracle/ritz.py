@@ -26,6 +26,30 @@ one against, is offered too: the pairs of (Z^T A Z) y = theta (Z^T Z) y, the
 Galerkin condition Z^T (A w - theta w) = 0 instead of the harmonic
 (AZ)^T (A w - theta w) = 0.  It is solved by the same reduction with Z^T Z in
 the role of F, so W' = Z U has orthonormal columns (U^T Z^T Z U = I).
+
+The implicit extraction forms F and G without products of tall matrices,
+from the quantities Algorithm 1 stores in its first L steps (d_j, alpha_j,
+beta_j, mu_j, p_j) plus rho_j = r_j^T r_j, as section 2.3 says Saad et al.
+(2000) did.  The identities it rests on, all exact in exact arithmetic for
+the iterates of Algorithm 1 (with W empty: plain CG):
+* A-conjugacy: (AW)^T p_j = 0 and p_i^T A p_j = 0 (i != j), so
+  F = blockdiag(W^T A W, diag(d_j));
+* the residual update r_{j+1} = r_j - alpha_j A p_j - (AW) c_{j+1} (c = 0 in
+  Algorithm 1; the re-projection's coefficients otherwise), so
+  A p_j = (r_j - r_{j+1} - (AW) c_{j+1}) / alpha_j;
+* the definition of mu_j: (AW)^T r_j = (W^T A W) mu_j;
+* mutually orthogonal residuals: r_i^T r_j = 0 for i != j.
+Then (AW)^T A p_j = (M (mu_j - mu_{j+1}) - N c_{j+1}) / alpha_j with
+M = W^T A W, N = (AW)^T AW, and (A p_i)^T (A p_j) expands into the residual
+Gram matrix (diagonal rho_j + rho_{j+1}, first off-diagonals -rho_{j+1}),
+the cross terms (M (mu_i - mu_{i+1}))^T c_{j+1} and c_{i+1}^T N c_{j+1}.
+The products A p_j themselves follow from the directions: the direction
+update p_j = beta_{j-1} p_{j-1} + r_j - W mu_j gives r_j from P and W, so
+A P_L = [P_L, p_L] T + W (mu_j - mu_{j+1}) / alpha_j - (AW) c_{j+1} / alpha_j
+with a tridiagonal-band T, and AW' = [AW, A P_L] U needs no stored A P_L.
+In finite precision every identity holds only to the loss of orthogonality
+and conjugacy of the iteration, so the implicit pencil is an approximation
+of the explicit one, close in the first steps.
 """
 
 import numpy as np
@@ -90,7 +114,7 @@ def rayleigh_ritz(Z, AZ, k, largest=True, drop_tol=1e-12):
     return Z @ U, AZ @ U, theta[idx], U
 
 
-HARMONIC, RAYLEIGH = 0, 1
+HARMONIC, RAYLEIGH, IMPLICIT = 0, 1, 2
 
 
 def extract(Z, AZ, k, largest=True, kind=HARMONIC, drop_tol=1e-12):
@@ -100,3 +124,85 @@ def extract(Z, AZ, k, largest=True, kind=HARMONIC, drop_tol=1e-12):
     if kind == RAYLEIGH:
         return rayleigh_ritz(Z, AZ, k, largest, drop_tol)
     raise ValueError(f"unknown extraction {kind}")
+
+
+def implicit_pencil(M, N, d, alpha, rho, mu=None, c=None):
+    """F and G of Eq. 7 for Z = [W, P_L] from the quantities of the first L
+    steps (see the module notes).
+
+    M, N   W^T A W and (AW)^T AW (k x k; ignored with k = 0)
+    d      d_j = p_j^T A p_j, j = 0 .. L-1
+    alpha  alpha_j, j = 0 .. L-1
+    rho    rho_j = r_j^T r_j, j = 0 .. L
+    mu     mu_j, j = 0 .. L (k-vectors), or None with k = 0
+    c      re-projection coefficients c_{j+1}, j = 0 .. L-1, or None (zero)
+    """
+    L = len(d)
+    k = 0 if mu is None or len(mu) == 0 else len(mu[0])
+    m = k + L
+    F = np.zeros((m, m))
+    G = np.zeros((m, m))
+    d = np.asarray(d, dtype=np.float64)
+    al = np.asarray(alpha, dtype=np.float64)
+    rh = np.asarray(rho, dtype=np.float64)
+    F[k:, k:] = np.diag(d)
+    # residual Gram terms of (A p_i)^T (A p_j) alpha_i alpha_j
+    S = np.zeros((L, L))
+    for j in range(L):
+        S[j, j] = rh[j] + rh[j + 1]
+        if j + 1 < L:
+            S[j, j + 1] = S[j + 1, j] = -rh[j + 1]
+    if k > 0:
+        M = 0.5 * (M + M.T)
+        N = 0.5 * (N + N.T)
+        F[:k, :k] = M
+        G[:k, :k] = N
+        Mu = np.column_stack(mu)                     # k x (L + 1)
+        Cc = np.zeros((k, L)) if c is None or len(c) == 0 else np.column_stack(c)
+        Dm = M @ (Mu[:, :L] - Mu[:, 1:L + 1])        # (AW)^T (r_j - r_{j+1})
+        G[:k, k:] = (Dm - N @ Cc) / al[None, :]
+        G[k:, :k] = G[:k, k:].T
+        # (r_i - r_{i+1})^T (AW) c_{j+1} and c_{i+1}^T N c_{j+1}
+        X = Dm.T @ Cc
+        S = S - X - X.T + Cc.T @ N @ Cc
+    G[k:, k:] = S / (al[:, None] * al[None, :])
+    return F, G
+
+
+def implied_AP(P, p_next, W, AW, alpha, beta, mu=None, c=None):
+    """A P_L from the recurrences (see the module notes): with
+    r_j = p_j - beta_{j-1} p_{j-1} + W mu_j (r_0 = p_0 + W mu_0),
+    A p_j = (r_j - r_{j+1} - (AW) c_{j+1}) / alpha_j."""
+    n, L = P.shape
+    Pe = np.hstack([P, p_next[:, None]])
+    R = Pe.copy()
+    R[:, 1:] -= Pe[:, :-1] * np.asarray(beta, dtype=np.float64)[None, :L]
+    if W is not None and W.shape[1] > 0:
+        R += W @ np.column_stack(mu)
+    AP = (R[:, :L] - R[:, 1:]) / np.asarray(alpha, dtype=np.float64)[None, :]
+    if c is not None and len(c) > 0:
+        AP -= (AW @ np.column_stack(c)) / np.asarray(alpha, dtype=np.float64)[None, :]
+    return AP
+
+
+def implicit_extract(res, W, AW, k, largest=True, drop_tol=1e-12):
+    """The next basis by the implicit extraction, from a DefCGResult ``res``
+    of the solve with basis W (n x k0, or None) and AW: F, G by
+    ``implicit_pencil``, the pairs as for the harmonic extraction, W' = Z U
+    and AW' = [AW, implied A P_L] U.  Returns (W', AW', theta_sel, U)."""
+    L = len(res.d)
+    has_w = W is not None and W.shape[1] > 0
+    if has_w:
+        M, N = W.T @ AW, AW.T @ AW
+        mu, Z, AWs = res.mu[:L + 1], np.hstack([W, res.P]), AW
+    else:
+        M = N = None
+        mu, Z, AWs = None, res.P, None
+    cv = res.cvec[:L] if has_w else None
+    F, G = implicit_pencil(M, N, res.d, res.alpha, res.rho[:L + 1], mu, cv)
+    AP = implied_AP(res.P, res.p_next, W if has_w else None, AWs, res.alpha, res.beta, mu, cv)
+    AZ = np.hstack([AW, AP]) if has_w else AP
+    theta, U = harmonic_ritz_pairs(F, G, drop_tol)
+    idx = select(theta, min(k, theta.shape[0]), largest)
+    U = U[:, idx]
+    return Z @ U, AZ @ U, theta[idx], U

@@ -9,7 +9,9 @@ later system is solved by def-CG(k, L) with the basis extracted from the
 previous solve.  AW must be the product with the *current* operator: it is
 recomputed with k products for a new operator, or, when only sigma^2 changes
 (A_{i+1} = A_i + (s_{i+1} - s_i) I), updated exactly as
-(AZ) U + (sigma2_{i+1} - sigma2_i) W'.
+(AZ) U + (sigma2_{i+1} - sigma2_i) W'.  The implicit extraction
+(``ritz.IMPLICIT``) takes F, G and A P_L from the solve's stored quantities
+instead of its stored products.
 """
 
 import numpy as np
@@ -54,7 +56,11 @@ class Sequence:
                 AZ = np.hstack([AW, res.AP])
             else:
                 Z, AZ = res.P, res.AP
-            if Z.shape[1] > 0:
+            if Z.shape[1] > 0 and self.extraction == _ritz.IMPLICIT:
+                self.W, self.AW_prev_op, theta, _ = _ritz.implicit_extract(res, W, AW, self.k,
+                                                                           self.largest)
+                res.theta = theta
+            elif Z.shape[1] > 0:
                 self.W, self.AW_prev_op, theta, _ = _ritz.extract(Z, AZ, self.k, self.largest,
                                                                   self.extraction)
                 res.theta = theta
