@@ -185,11 +185,16 @@ def implied_AP(P, p_next, W, AW, alpha, beta, mu=None, c=None):
     return AP
 
 
-def implicit_extract(res, W, AW, k, largest=True, drop_tol=1e-12):
+def implicit_extract(res, W, AW, k, largest=True, drop_tol=1e-12, cleanup=True):
     """The next basis by the implicit extraction, from a DefCGResult ``res``
     of the solve with basis W (n x k0, or None) and AW: F, G by
     ``implicit_pencil``, the pairs as for the harmonic extraction, W' = Z U
-    and AW' = [AW, implied A P_L] U.  Returns (W', AW', theta_sel, U)."""
+    and AW' = [AW, implied A P_L] U.  With ``cleanup`` the harmonic problem
+    is solved once more on span(W') with its explicit metric (AW')^T W' and
+    (AW')^T AW', which drops directions that came out numerically dependent
+    (the implicit F assumes conjugate directions, and finite precision
+    loses conjugacy; see test_oracle_implicit.py); in exact arithmetic the
+    second problem returns W' itself.  Returns (W', AW', theta_sel, U)."""
     L = len(res.d)
     has_w = W is not None and W.shape[1] > 0
     if has_w:
@@ -205,4 +210,11 @@ def implicit_extract(res, W, AW, k, largest=True, drop_tol=1e-12):
     theta, U = harmonic_ritz_pairs(F, G, drop_tol)
     idx = select(theta, min(k, theta.shape[0]), largest)
     U = U[:, idx]
-    return Z @ U, AZ @ U, theta[idx], U
+    W1, AW1, th1 = Z @ U, AZ @ U, theta[idx]
+    if not cleanup:
+        return W1, AW1, th1, U
+    F2, G2 = harmonic_ritz_FG(W1, AW1)
+    theta2, U2 = harmonic_ritz_pairs(F2, G2, drop_tol)
+    idx2 = select(theta2, theta2.shape[0], largest)
+    U2 = U2[:, idx2]
+    return W1 @ U2, AW1 @ U2, theta2[idx2], U @ U2

@@ -111,3 +111,39 @@ def test_implicit_sequence_counts():
         ra, rb = a.step(A, bb), b_.step(A, bb)
         assert abs(ra.iters - rb.iters) <= 1, (i, ra.iters, rb.iters)
         np.testing.assert_allclose(rb.theta, ra.theta, rtol=1e-6)
+
+
+def test_implicit_pencil_ghosts_and_cleanup():
+    """Where the implicit pencil breaks: the precision form's first system at
+    n = 3000 (bf16-rounded points, Matern-5/2, sigma2 = 1e-3, kappa ~ 1e5),
+    plain CG to 2e-2 storing 24 directions, k = 16, exact FP64 products.
+    The largest eigenvalue converges within these steps, the stored
+    directions lose conjugacy, and two of them become nearly parallel: the
+    explicit F = P^T A P (formed from the vectors) has a null direction,
+    which its drop rule removes, while the implicit F = diag(d_j) cannot show
+    it.  The implicit pencil then reports the top harmonic Ritz value twice
+    (a ghost pair) and W' has a null direction in the A-metric.  The second
+    harmonic problem on span(W') (``cleanup``) removes the ghost: what is
+    left is A-orthonormal and carries the explicit extraction's leading
+    values."""
+    import workloads
+    from oracle import precision as OP
+    w = workloads.bf16_shift(n=3000, systems=1)
+    X, b, kern, ell = w["X"], w["b"], w["kernel"], w["ell"]
+    Xr = OP.round_points(X, 1, kern, ell)
+    A = OK.operator(Xr, kern, ell, 1.0, w["sigma2s"][0])
+    res = OC.cg(A, b, tol=2e-2, L=24)
+    Fx, _ = ORZ.harmonic_ritz_FG(res.P, res.AP)
+    s = 1.0 / np.sqrt(np.diag(Fx))
+    assert np.linalg.eigvalsh(Fx * s[:, None] * s[None, :])[0] < 1e-12
+    W0, _, th0, _ = ORZ.implicit_extract(res, None, None, 16, cleanup=False)
+    assert abs(th0[1] - th0[0]) <= 1e-10 * th0[0]            # the ghost
+    M0 = W0.T @ A @ W0
+    assert np.linalg.eigvalsh(0.5 * (M0 + M0.T))[0] < 1e-10   # W' rank deficient
+    W1, AW1, th1, _ = ORZ.implicit_extract(res, None, None, 16)
+    W2, _, th2, _ = ORZ.harmonic_ritz(res.P, res.AP, 16)
+    k1 = W1.shape[1]
+    assert 8 <= k1 < 16
+    np.testing.assert_allclose(W1.T @ A @ W1, np.eye(k1), atol=1e-8)
+    np.testing.assert_allclose(th1, th2[:k1], rtol=1e-8)
+    assert _rel(AW1, A @ W1) < 1e-9
