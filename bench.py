@@ -93,8 +93,10 @@ def parse():
     ap.add_argument("--refresh", choices=["first", "every", "accum"], default="first",
                     help="refresh W after the first inner solve, after every inner solve, or "
                          "once per system from the directions of all its inner solves")
-    ap.add_argument("--extraction", choices=["harmonic", "rayleigh"], default="harmonic",
-                    help="next basis by harmonic Ritz (Eq. 7) or by Rayleigh-Ritz")
+    ap.add_argument("--extraction", choices=["harmonic", "rayleigh", "implicit"], default="harmonic",
+                    help="next basis by harmonic Ritz (Eq. 7, F and G as tall products), by "
+                         "Rayleigh-Ritz, or by harmonic Ritz with F and G from the stored "
+                         "scalars of the first L steps (no stored A P_L)")
     ap.add_argument("--select", choices=["largest", "smallest"], default="largest",
                     help="keep the Ritz pairs of the largest or of the smallest values")
     ap.add_argument("--ritz-route", choices=["auto", "eigen"], default="auto",
@@ -122,6 +124,9 @@ def parse():
                          "holds for the true residual")
     ap.add_argument("--gpc-stored", action="store_true",
                     help="gpc64: use the stored kernel matrix instead of the matrix-free sweep")
+    ap.add_argument("--gpc-points", choices=["stored", "bf16", "fp16"], default="stored",
+                    help="gpc (784 coordinates): the stored kernel matrix, or the matrix-free "
+                         "LDS-staged sweep of bf16 / fp16 points")
     ap.add_argument("--adam-steps", type=int, default=50,
                     help="gp_hyper: Adam steps in all (the first --warmup are not timed)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -387,7 +392,8 @@ def main_gpc(args):
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    stored = args.workload == "gpc" or args.gpc_stored
+    wide = args.workload == "gpc" and args.gpc_points != "stored"
+    stored = (args.workload == "gpc" and not wide) or args.gpc_stored
     w = workloads.gpc_pixels() if args.workload == "gpc" else workloads.gpc()
     n, d = w["X"].shape
     dev = torch.device("cuda:0")
@@ -395,8 +401,11 @@ def main_gpc(args):
     y = torch.as_tensor(w["y"], device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    op = dcg.Operator(X, w["kernel"], w["ell"], w["s2"], 0.0,
-                      prec=dcg.PREC_STORED if stored else dcg.PREC_FP32)
+    if wide:
+        prec = dcg.PREC_BF16 if args.gpc_points == "bf16" else dcg.PREC_FP16
+    else:
+        prec = dcg.PREC_STORED if stored else dcg.PREC_FP32
+    op = dcg.Operator(X, w["kernel"], w["ell"], w["s2"], 0.0, prec=prec)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
     items, _ = op.tune(reps=5)
@@ -427,6 +436,9 @@ def main_gpc(args):
                 f"RBF ell=0.5 x median distance s2=100")
     if stored:
         dtype = "f32 stored kernel matrix (formed in f64), f64 accumulation, CG and Newton terms"
+    elif wide:
+        dtype = (f"{args.gpc_points} points on {args.gpc_points} MFMA (LDS-staged), f32 kernel "
+                 f"values, f64 CG and Newton terms")
     else:
         dtype = "fp32 points on fp32 MFMA, f32 kernel values, f64 CG and Newton terms"
     out = {
@@ -469,6 +481,26 @@ def main_gpc(args):
         traffic = 2775.5e6 if (args.workload == "gpc" and n == 36551) else None
         out["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0,
                            "unit": "GB/s", "frac": round(gbs / 8000.0, 4), "traffic": traffic}
+    if wide:
+        # the dominant kernel: the LDS-staged pair sweep; algorithmic work 2 d
+        # MFMA flops per unique pair (the distance contraction), timed with HIP
+        # events on the operator's stream around whole products
+        v = torch.ones(n, dtype=torch.float64, device=dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        op.matvec(v)
+        e0.record(op.stream)
+        for _ in range(reps):
+            op.matvec(v)
+        e1.record(op.stream)
+        e1.synchronize()
+        t = e0.elapsed_time(e1) / reps
+        flops = 2.0 * d * n * (n - 1) / 2
+        tf = flops / (t * 1e-3) / 1e12
+        out["product_ms"] = round(t, 4)
+        out["roofline"] = {"bound": "mfma", "achieved": round(tf, 1), "peak": 2500.0,
+                           "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4), "traffic": None,
+                           "per_launch": f"{n * (n - 1) // 2:.3e} unique pairs x 2 d flops"}
     if not args.no_plain:
         prow = [run(None) for _ in range(max(1, min(args.steps, 3)))]
         out["plain_ms_per_mode"] = round(sum(r[0] for r in prow) / len(prow), 2)

@@ -133,6 +133,16 @@ typedef struct {
                           2.3): 0 harmonic Ritz, G u = theta F u (Eq. 7),
                           W' A-orthonormal; 1 Rayleigh-Ritz,
                           (Z^T A Z) y = theta (Z^T Z) y, W' orthonormal;
+                          2 harmonic Ritz with F and G formed from the
+                          scalars of the first L steps (d_j, alpha_j,
+                          beta_j, rho_j, mu_j and the re-projection's
+                          coefficients; section 2.3, after Saad et al.)
+                          instead of tall products, and AW' from the
+                          residual recurrence: the solve stores the FP64
+                          directions p_0 .. p_L and no products A p_j.
+                          dcg_solve only (the batched solve and
+                          dcg_extract_basis refuse it), not with the pooled
+                          refresh of refine (refresh_every = 2);
                           DCG_E_ARG otherwise                                 */
 } dcg_params;
 

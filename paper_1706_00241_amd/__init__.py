@@ -419,7 +419,9 @@ def _extraction(kind):
         return 0
     if kind in ("rayleigh", 1):
         return 1
-    raise ValueError(f"extraction must be 'harmonic' or 'rayleigh', not {kind!r}")
+    if kind in ("implicit", 2):
+        return 2
+    raise ValueError(f"extraction must be 'harmonic', 'rayleigh' or 'implicit', not {kind!r}")
 
 
 def solve(op, b, x0=None, rc=None, tol=1e-6, max_iter=0, L=0, select_largest=True,

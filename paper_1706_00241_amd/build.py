@@ -19,7 +19,9 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdcg.so")
 SOURCES = ["matvec.hip", "exact.hip", "blas.hip", "eig.hip", "operator.hip", "solver.hip",
            "block.hip", "grad.hip", "batch.hip", "gpc.hip",
-           "stored.hip", "slq.hip"]
+           "stored.hip", "slq.hip", "implicit.hip", "wide.hip"]
+# host-only C++ (no kernels): built by the host compiler alone
+HOST_SOURCES = ["host.cpp"]
 ARCH = "gfx950"
 
 
@@ -34,6 +36,29 @@ def flags():
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
+
+
+def host_cxx():
+    p = shutil.which("g++")
+    if p is None:
+        raise RuntimeError("g++ not found: the host compiler is required")
+    return p
+
+
+def host_flags():
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(hipcc())))
+    return ["-O2", "-std=c++17", "-fPIC", "-D__HIP_PLATFORM_AMD__",
+            "-I", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"),
+            "-Wall", "-Wno-unused-function"]
+
+
+def _compile_host(src, objdir):
+    obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+    cmd = [host_cxx()] + host_flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"g++ failed for {src}:\n{r.stderr}")
+    return obj
 
 
 def _compile(src, objdir):
@@ -52,6 +77,7 @@ def build(verbose=False):
     os.makedirs(objdir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
         objs = list(ex.map(lambda s: _compile(s, objdir), SOURCES))
+        objs += list(ex.map(lambda s: _compile_host(s, objdir), HOST_SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -200,8 +200,8 @@ int dcg_solve_batched(int count, const dcg_op_t *ops, const double *const *b, do
   for (int s = 0; s < count; ++s) {
     dcg_operator_s *op = ops[s];
     if (op == nullptr || b[s] == nullptr || x[s] == nullptr) return DCG_E_ARG;
-    // not supported with a diagonal scaling or the stored operator
-    if (op->has_dsc || op->g.prec == DCG_PREC_STORED) return DCG_E_ARG;
+    // not supported with a diagonal scaling, the stored operator or wide points
+    if (op->has_dsc || op->g.prec == DCG_PREC_STORED || sweep_wide(op->g)) return DCG_E_ARG;
     // each system sweeps into its operator's own partial buffers
     if (!seen_op.insert(op).second) return DCG_E_ARG;
     if (op->stream != ops[0]->stream) return DCG_E_ARG;

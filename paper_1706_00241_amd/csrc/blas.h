@@ -96,6 +96,11 @@ struct CgArgs {
   int lz_cap;
   double tol;
   int max_iter;
+  // implicit extraction: rho_{j+1}, mu_{j+1} (rows of kMaxK) and the
+  // re-projection's c_{j+1} (rows of kMaxK) recorded for j < L; Z then holds
+  // the FP64 directions p_0 .. p_L and AZ is not written
+  double *hist_rho = nullptr, *hist_mu = nullptr, *hist_c = nullptr;
+  int implicit = 0;
 };
 
 // Block counts of the per-step kernels for a.n and a.k.
@@ -129,8 +134,24 @@ void enqueue_ts_dot(hipStream_t s, const double *Y, int64_t n, int m, const doub
                     double *part, unsigned *counter, const double *Minv, double *out);
 void enqueue_tsgemm_tn(hipStream_t s, const double *A, const double *B, int64_t n, int ma, int mb,
                        double *part, size_t part_cap, double *C, int ldc, int symmetrise);
+// Y (+)= X U; columns of X from round_from on are read as the FP32 copy the
+// low-precision sweep multiplies (with the diagonal scaling dsc, if any).
 void enqueue_ts_times_small(hipStream_t s, const double *X, int64_t n, int m, const double *U,
-                            int ldu, int kout, double *Y);
+                            int ldu, int kout, double *Y, int round_from = 1 << 30,
+                            const double *dsc = nullptr, int accumulate = 0);
+// The implicit extraction (implicit.hip): the quantities of the first L
+// steps of a solve, F and G from them, and the coefficients of AW'.
+struct ImplicitHist {
+  const double *d, *alpha, *beta;  // j < L
+  const double *rho;               // j <= L
+  const double *mu;                // rows j <= L of kMaxK doubles
+  const double *cv;                // re-projection c_{j+1}, rows j < L of kMaxK doubles
+};
+void enqueue_implicit_pencil(hipStream_t s, const ImplicitHist &h, const double *M,
+                             const double *N, int k, int L, double *scratch, double *F,
+                             double *G);
+void enqueue_implicit_aw_coef(hipStream_t s, const ImplicitHist &h, const double *U, int k, int L,
+                              int kout, double *S1, double *S2);
 void enqueue_block_axpy(hipStream_t s, double *Y, const double *X, double alpha, int64_t count);
 void enqueue_round_to_fp32(hipStream_t s, double *Y, int64_t count);
 void enqueue_small_spd_inverse(hipStream_t s, const double *M, int k, double *Minv, double *work,
@@ -152,6 +173,8 @@ constexpr double kLn2Sq3d = kLn2d * kLn2d / 3.0;
 constexpr float kLn2 = static_cast<float>(kLn2d);
 constexpr float kLn2Sq3 = static_cast<float>(kLn2Sq3d);
 int launch_symv_sweep(const dcg_operator_s *op, int mv, const int *done);
+// wide.hip: the LDS-staged sweep of bf16 / fp16 operands with d > kMaxD
+int launch_symv_wide(const dcg_operator_s *op, const SymvArgs &a, int64_t grid);
 int launch_symv_sweep_from(const dcg_operator_s *op, int mv, const float *vin, const int *done);
 SymvArgs symv_args(const dcg_operator_s *op, int mv, const float *vin, const int *done,
                    int64_t *grid);

@@ -90,6 +90,17 @@ __device__ __forceinline__ void small_gemv(const double *Minv, const double *h, 
   }
 }
 
+// The same product with the matrix staged in LDS, rows padded to kMaxK + 1
+// (so that the threads of a wave read distinct banks); same summation order.
+__device__ __forceinline__ void small_gemv_lds(const double *Ms, const double *h, double *mu,
+                                               int k) {
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s += Ms[c * (kMaxK + 1) + j] * h[j];
+    mu[c] = s;
+  }
+}
+
 // ------------------------------------------------------ CG iteration kernels
 
 // q = s2 * sum(partials) + sigma2 p and the block partials of d = p^T q.
@@ -147,7 +158,11 @@ __device__ __forceinline__ void cg_matvec_finish_body(const CgArgs &a, const uns
           (a.qdirect != nullptr) ? tot : fma(a.red.s2 * di, tot, a.red.sigma2 * pi);
       a.q[i] = qi;
       pq += pi * qi;
-      if (a.Z != nullptr && j < a.L) {
+      if (a.Z != nullptr && a.implicit && j <= a.L) {
+        // the implicit extraction keeps the FP64 directions p_0 .. p_L (the
+        // residuals, and so A p_j, follow from them) and no products
+        a.Z[int64_t(a.koff + j) * a.n + i] = pi;
+      } else if (a.Z != nullptr && j < a.L) {
         // store the direction the product was formed from: the low-precision
         // sweep multiplies the FP32 copy of p, so that copy (exact in FP64)
         // is the column of Z whose product is q; AZ then matches A~ Z to the
@@ -187,6 +202,29 @@ __device__ __forceinline__ void cg_update_xr_body(const CgArgs &a, const unsigne
   if (grp >= xr_groups(k)) return;
   __shared__ double lds[8];
   __shared__ double cpart[4][kXrCols];
+  constexpr int RPT = kXrRows / 256;
+  const int64_t i0 = int64_t(rb) * kXrRows + threadIdx.x;
+  // This block's rows of r, q and of its kXrCols columns of [AW | W] do not
+  // depend on alpha: load them first, so that the reduction of d below runs
+  // while they are in flight.
+  double rv[RPT], qv[RPT];
+  double yv[kXrCols][RPT];
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int64_t i = i0 + 256 * u;
+    rv[u] = (i < a.n) ? a.r[i] : 0.0;
+    qv[u] = (i < a.n) ? a.q[i] : 0.0;
+  }
+#pragma unroll
+  for (int cc = 0; cc < kXrCols; ++cc) {
+    const int c = grp * kXrCols + cc;
+    const double *Y = (c < k) ? a.AW + int64_t(c) * a.n : a.W + int64_t(c - k) * a.n;
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int64_t i = i0 + 256 * u;
+      yv[cc][u] = (c < 2 * k && i < a.n) ? Y[i] : 0.0;
+    }
+  }
   const double d = block_sum_array(a.part, a.nblk_q, lds);
   const bool bad = !(d > 0.0) || !isfinite(d);
   const double alpha = bad ? 0.0 : S->rho / d;
@@ -200,8 +238,6 @@ __device__ __forceinline__ void cg_update_xr_body(const CgArgs &a, const unsigne
     }
     if (a.lz_alpha != nullptr && j < a.lz_cap) a.lz_alpha[j] = alpha;
   }
-  constexpr int RPT = kXrRows / 256;
-  const int64_t i0 = int64_t(rb) * kXrRows + threadIdx.x;
   double ri[RPT];
   double rr = 0.0;
 #pragma unroll
@@ -209,7 +245,7 @@ __device__ __forceinline__ void cg_update_xr_body(const CgArgs &a, const unsigne
     const int64_t i = i0 + 256 * u;
     ri[u] = 0.0;
     if (i < a.n) {
-      ri[u] = a.r[i] - alpha * a.q[i];
+      ri[u] = rv[u] - alpha * qv[u];
       rr += ri[u] * ri[u];
     }
   }
@@ -218,20 +254,14 @@ __device__ __forceinline__ void cg_update_xr_body(const CgArgs &a, const unsigne
     if (threadIdx.x == 0) a.part2[rb] = bad ? (isfinite(d) ? -1.0 : -2.0) : bs;
   }
   if (k == 0) return;
-  // partial dots with kXrCols columns of [AW | W]; all loads issued first
+  // partial dots with kXrCols columns of [AW | W]
   double sv[kXrCols];
 #pragma unroll
   for (int cc = 0; cc < kXrCols; ++cc) {
-    const int c = grp * kXrCols + cc;
     double acc = 0.0;
-    if (c < 2 * k) {
-      const double *Y = (c < k) ? a.AW + int64_t(c) * a.n : a.W + int64_t(c - k) * a.n;
 #pragma unroll
-      for (int u = 0; u < RPT; ++u) {
-        const int64_t i = i0 + 256 * u;
-        if (i < a.n) acc += Y[i] * ri[u];
-      }
-    }
+    for (int u = 0; u < RPT; ++u)
+      if (i0 + 256 * u < a.n) acc += yv[cc][u] * ri[u];
     sv[cc] = acc;
   }
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -264,10 +294,20 @@ __device__ __forceinline__ void cg_finalize_body(const CgArgs &a) {
   __shared__ double cv[kMaxK];       // c = M^-1 g
   __shared__ double nc[kMaxK];       // N c
   __shared__ double hn[kMaxK];       // h - N c
+  __shared__ double Ms[kMaxK * (kMaxK + 1)];   // M^-1 and N, rows padded by one
+  __shared__ double Ns[kMaxK * (kMaxK + 1)];
   __shared__ int flag;
   const int k = a.k;
   const int64_t nblk = a.nblk_xr;
+  const int jstep = S->iter;   // read before thread 0 advances it below
+  const bool record = a.hist_rho != nullptr && jstep < a.L;
   if (threadIdx.x == 0) flag = 0;
+  // the small matrices come in (coalesced) while the partials are summed
+  for (int e = threadIdx.x; e < k * k; e += 256) {
+    const int r = e / k, c = e % k;
+    Ms[r * (kMaxK + 1) + c] = a.Minv[e];
+    Ns[r * (kMaxK + 1) + c] = a.N[e];
+  }
   __syncthreads();
   // a negative partial marks p^T A p <= 0 (-1) or non-finite (-2)
   for (int64_t b = threadIdx.x; b < nblk; b += 256) {
@@ -294,16 +334,21 @@ __device__ __forceinline__ void cg_finalize_body(const CgArgs &a) {
     hg[c] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   }
   const double rho_raw = block_sum_array(a.part2, nblk, lds);   // includes barriers
-  small_gemv(a.Minv, hg + k, cv, k);
+  small_gemv_lds(Ms, hg + k, cv, k);
   __syncthreads();
-  small_gemv(a.N, cv, nc, k);
+  small_gemv_lds(Ns, cv, nc, k);
   __syncthreads();
   for (int c = threadIdx.x; c < k; c += 256) {
     hn[c] = hg[c] - nc[c];
     S->cvec[c] = cv[c];
+    if (record) a.hist_c[int64_t(jstep) * kMaxK + c] = cv[c];
   }
   __syncthreads();
-  small_gemv(a.Minv, hn, S->mu, k);
+  small_gemv_lds(Ms, hn, S->mu, k);
+  // each thread records the entries of mu it formed
+  if (record)
+    for (int c = threadIdx.x; c < k; c += blockDim.x)
+      a.hist_mu[int64_t(jstep + 1) * kMaxK + c] = S->mu[c];
   if (threadIdx.x == 0) {
     // |r - AW c|^2 = |r|^2 - 2 c^T h + c^T N c
     double corr = 0.0;
@@ -314,6 +359,7 @@ __device__ __forceinline__ void cg_finalize_body(const CgArgs &a) {
     S->rho = rho_new;
     const int j = S->iter;
     if (j < a.L) a.hist_beta[j] = beta;
+    if (record) a.hist_rho[j + 1] = rho_new;
     if (a.lz_beta != nullptr && j < a.lz_cap) a.lz_beta[j] = beta;
     S->iter = j + 1;
     const double rel = std::sqrt(rho_new) / S->bnorm;
@@ -565,12 +611,16 @@ __global__ __launch_bounds__(256) void tsgemm_sum(const double *part, int nchunk
   C[i * ldc + j] = s;
 }
 
-// Y[:, j] = X[:, 0:m] U[:, j] for j < kout (U row-major m x ldu), 32 columns
-// per pass with U staged in LDS.
+// Y[:, j] (+)= X[:, 0:m] U[:, j] for j < kout (U row-major m x ldu), 32
+// columns per pass with U staged in LDS.  Columns c >= round_from of X are
+// taken as the FP32 copy the low-precision sweep multiplies (fp32(x), or
+// fp32(d x) / d with a diagonal scaling d, x itself where d = 0); accumulate
+// adds to Y instead of overwriting it.
 __global__ __launch_bounds__(256) void ts_times_small(const double *X, int64_t n, int m,
                                                       const double *U, int ldu, int kout,
-                                                      double *Y) {
-  __shared__ double Us[kMaxZ][32];
+                                                      double *Y, int round_from,
+                                                      const double *dsc, int accumulate) {
+  __shared__ double Us[kMaxZ + 1][32];
   const int j0 = blockIdx.y * 32;
   const int jn = std::min(32, kout - j0);
   for (int e = threadIdx.x; e < m * 32; e += 256) {
@@ -580,17 +630,25 @@ __global__ __launch_bounds__(256) void ts_times_small(const double *X, int64_t n
   __syncthreads();
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n) return;
+  const double di = (dsc != nullptr) ? dsc[i] : 1.0;
   double acc[32];
 #pragma unroll
   for (int j = 0; j < 32; ++j) acc[j] = 0.0;
   for (int c = 0; c < m; ++c) {
-    const double xv = X[int64_t(c) * n + i];
+    double xv = X[int64_t(c) * n + i];
+    if (c >= round_from) {
+      if (dsc == nullptr) xv = static_cast<double>(static_cast<float>(xv));
+      else if (di != 0.0) xv = static_cast<double>(static_cast<float>(di * xv)) / di;
+    }
 #pragma unroll
     for (int j = 0; j < 32; ++j) acc[j] += xv * Us[c][j];
   }
 #pragma unroll
   for (int j = 0; j < 32; ++j)
-    if (j < jn) Y[int64_t(j0 + j) * n + i] = acc[j];
+    if (j < jn) {
+      double *y = Y + int64_t(j0 + j) * n + i;
+      *y = accumulate ? *y + acc[j] : acc[j];
+    }
 }
 
 // Y += alpha X (n x m blocks, same layout).
@@ -689,10 +747,11 @@ void enqueue_tsgemm_tn(hipStream_t s, const double *A, const double *B, int64_t 
 }
 
 void enqueue_ts_times_small(hipStream_t s, const double *X, int64_t n, int m, const double *U,
-                            int ldu, int kout, double *Y) {
+                            int ldu, int kout, double *Y, int round_from, const double *dsc,
+                            int accumulate) {
   if (kout <= 0 || n <= 0) return;
   hipLaunchKernelGGL(ts_times_small, dim3(static_cast<unsigned>(cdiv(n, 256)), (kout + 31) / 32),
-                     dim3(256), 0, s, X, n, m, U, ldu, kout, Y);
+                     dim3(256), 0, s, X, n, m, U, ldu, kout, Y, round_from, dsc, accumulate);
 }
 
 void enqueue_block_axpy(hipStream_t s, double *Y, const double *X, double alpha, int64_t count) {

@@ -133,6 +133,7 @@ int dcg::solve_block_impl(dcg_op_t op, const double *B, double *X, int64_t m, dc
   const bool stored = op->g.prec == DCG_PREC_STORED;
   const bool direct = op->g.prec == DCG_PREC_FP64 || stored;
   if (op->has_dsc && !direct) return st->status = DCG_E_ARG;
+  if (sweep_wide(op->g)) return st->status = DCG_E_ARG;   // single-vector sweep only
   if (m < 1 || m > kMaxBlockCols || !(p->tol >= 0.0)) return st->status = DCG_E_ARG;
   if (rc != nullptr && rc->n != op->g.n) return st->status = DCG_E_ARG;
   const int64_t n = op->g.n, n_pad = op->g.n_pad;

@@ -10,7 +10,8 @@
 
 namespace dcg {
 
-constexpr int kMaxD = 64;
+constexpr int kMaxD = 64;          // point dimension of the register-operand pair sweep
+constexpr int kMaxWideD = 4096;    // point dimension of the LDS-staged sweep (bf16, fp16)
 constexpr int kMaxStoredD = 4096;  // point dimension of the stored operator
 constexpr int kMaxK = 64;          // columns of W
 constexpr int kMaxZ = 192;         // k + L (columns of Z)
@@ -79,7 +80,15 @@ struct MatvecPlan {
 __host__ __device__ constexpr int sweep_tile_rows(int mv, int opk, int ksteps) {
   return (mv == 1 && (opk == kOpF32 || ksteps <= (opk == kOpBf16Acc64 ? 4 : 9))) ? 2 : 1;
 }
-inline int sweep_blk(const Geometry &g, int mv) { return 128 * sweep_tile_rows(mv, g.opk, g.ksteps); }
+// bf16 and fp16 operands of more than kMaxD coordinates go through the
+// LDS-staged sweep (wide.hip): single vectors, 256-point blocks, no FP64
+// operator (the FP64 sweep holds its operands in registers).
+inline bool sweep_wide(const Geometry &g) {
+  return (g.prec == DCG_PREC_BF16 || g.prec == DCG_PREC_FP16) && g.d > kMaxD;
+}
+inline int sweep_blk(const Geometry &g, int mv) {
+  return sweep_wide(g) ? 256 : 128 * sweep_tile_rows(mv, g.opk, g.ksteps);
+}
 
 // Work items of one pair sweep: the plan groups block offsets into chunks so
 // that a sweep has about `items` work items.  The default suits one large
@@ -117,6 +126,14 @@ struct dcg_operator_s {
   float *kst;            // stored operator: K0's block upper triangle, packed FP32 tiles
   double *kpart;         // stored operator: row / column partial sums of a product
 };
+
+namespace dcg {
+// Whether the operator has the FP64 operator of the unrounded points (the
+// refinement residuals): not for the stored matrix, not for wide points.
+inline bool has_exact(const dcg_operator_s *op) {
+  return op->g.prec != DCG_PREC_STORED && !sweep_wide(op->g);
+}
+}  // namespace dcg
 
 struct dcg_recycle_s {
   int64_t n;

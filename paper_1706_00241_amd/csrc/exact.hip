@@ -13,39 +13,13 @@
 #include <type_traits>
 
 #include "blas.h"
+#include "host.h"
 
 namespace dcg {
 
-typedef __attribute__((ext_vector_type(4))) double f64x4;
-
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-int exact_ksteps(int d) {
-  const int ks = (d + 2 + 3) / 4;
-  return ks <= 3 ? 3 : ks <= 5 ? 5 : ks <= 9 ? 9 : 17;
-}
-int exact_stride(int d) {
-  const int ks = exact_ksteps(d);
-  return 4 * (ks + (ks & 1));
-}
-
-MatvecPlan exact_plan(int64_t n_pad, int items) {
-  MatvecPlan p;
-  p.blk = 128;
-  p.nb = static_cast<int>(n_pad / p.blk);
-  p.dmax = p.nb / 2;
-  const int ndelta = p.dmax + 1;
-  p.chunk = static_cast<int>(std::max<int64_t>(1, cdiv(int64_t(ndelta) * p.nb, items)));
-  p.nchunk = static_cast<int>(cdiv(ndelta, p.chunk));
-  p.grid = int64_t(p.nb) * p.nchunk;
-  return p;
-}
-
-size_t exact_partial_doubles(int64_t n_pad) {
-  // chunks per row block grow with the item target
-  const MatvecPlan p = exact_plan(n_pad, kSweepItemsMax);
-  return size_t(p.nchunk + p.dmax) * size_t(n_pad);
-}
+typedef __attribute__((ext_vector_type(4))) double f64x4;
 
 // 2^x for x <= 0 (and small positive x), to about one ulp: k = rint(x) and
 // f = x - k in [-1/2, 1/2] (the subtraction is exact), 2^f by its degree-11
@@ -334,7 +308,7 @@ int launch_exact_sweep(const dcg_operator_s *op, const int *done) {
 int matvec_exact_done(const dcg_operator_s *op, const double *V, double *Y, int64_t m,
                       const int *done) {
   // the stored operator keeps no FP64 operands (their workspace is not laid out)
-  if (op->g.prec == DCG_PREC_STORED) return DCG_E_ARG;
+  if (!has_exact(op)) return DCG_E_ARG;
   const int64_t n = op->g.n, n_pad = op->g.n_pad;
   MatvecPlan p;
   const Symv64Args a = exact_args(op, done, &p);
@@ -363,7 +337,7 @@ int matvec_exact(const dcg_operator_s *op, const double *V, double *Y, int64_t m
 // kernel alone.
 int matvec_exact_timed(const dcg_operator_s *op, const double *V, double *Y, hipEvent_t ev0,
                        hipEvent_t ev1) {
-  if (op->g.prec == DCG_PREC_STORED) return DCG_E_ARG;
+  if (!has_exact(op)) return DCG_E_ARG;
   const int64_t n = op->g.n, n_pad = op->g.n_pad;
   MatvecPlan p;
   const Symv64Args a = exact_args(op, nullptr, &p);

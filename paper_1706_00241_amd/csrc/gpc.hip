@@ -153,7 +153,7 @@ int dcg_laplace_gpc(dcg_op_t op, const double *y, dcg_recycle_t rc, const dcg_pa
   if (rc != nullptr && rc->n != op->g.n) return DCG_E_ARG;
   // refinement needs the FP64 operator, which the stored operator does not
   // have (checked before any work is enqueued)
-  if (op->g.prec == DCG_PREC_STORED && p->refine != 0) return DCG_E_ARG;
+  if (!has_exact(op) && p->refine != 0) return DCG_E_ARG;
   const int64_t n = op->g.n, n_pad = op->g.n_pad;
   const GpcLayout L = gpc_layout(n);
   if (ws == nullptr || ws_bytes < L.total) return DCG_E_WORKSPACE;

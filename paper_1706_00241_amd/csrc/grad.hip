@@ -365,6 +365,7 @@ int dcg_mll_grad(dcg_op_t op, const double *alpha, const double *U, const double
     return DCG_E_ARG;
   if (P < 1 || P > kMaxProbes || op->has_dsc) return DCG_E_ARG;
   if (op->g.prec != DCG_PREC_FP32 && op->g.prec != DCG_PREC_BF16) return DCG_E_ARG;
+  if (sweep_wide(op->g)) return DCG_E_ARG;
   const int64_t n = op->g.n, n_pad = op->g.n_pad;
   if (ws == nullptr || ws_bytes < grad_workspace_bytes(n_pad)) return DCG_E_WORKSPACE;
   if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return DCG_E_WORKSPACE;

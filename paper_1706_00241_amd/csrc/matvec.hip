@@ -27,103 +27,12 @@
 #include <type_traits>
 
 #include "blas.h"
+#include "host.h"
+#include "sweep.h"
 
 namespace dcg {
 
-typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
-typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
-typedef __attribute__((ext_vector_type(16))) float f32x16;
-
-static int bf16_bucket(int ks) {
-  const int b[] = {1, 2, 3, 4, 5, 7, 9, 13, 17};
-  for (int v : b)
-    if (ks <= v) return v;
-  return -1;
-}
-
-static int fp32_bucket(int ks) {
-  const int b[] = {5, 9, 13, 17, 25, 33};
-  for (int v : b)
-    if (ks <= v) return v;
-  return -1;
-}
-
-Geometry make_geometry(int64_t n, int d, int prec) {
-  Geometry g;
-  g.n = n;
-  g.d = d;
-  g.prec = prec;
-  g.n_pad = ((n + 255) / 256) * 256;
-  g.opk = kOpBf16;
-  if (prec == DCG_PREC_FP64 || prec == DCG_PREC_STORED) {
-    g.ksteps = 0;  // the exact FP64 product and the stored matrix need no MFMA operands
-    g.kstride = 0;
-  } else if (prec == DCG_PREC_BF16 || prec == DCG_PREC_FP16) {
-    g.opk = (prec == DCG_PREC_FP16) ? kOpF16 : kOpBf16;
-    g.ksteps = (d + 6 + 15) / 16;
-    g.kstride = 16 * g.ksteps;
-  } else if (prec == DCG_PREC_BF16X2) {
-    g.ksteps = bf16_bucket((4 * d + 6 + 15) / 16);
-    g.kstride = 16 * g.ksteps;
-  } else if (6 * d + 6 <= 16 * 13) {
-    // FP32 points as three exact bf16 terms: six products per coordinate
-    // and the squared norm in three terms on each side
-    g.opk = kOpBf16Acc64;
-    g.ksteps = bf16_bucket((6 * d + 6 + 15) / 16);
-    g.kstride = 16 * g.ksteps;
-  } else {
-    g.opk = kOpF32;
-    g.ksteps = fp32_bucket((d + 2 + 1) / 2);
-    g.kstride = 2 * ((g.ksteps + 3) / 4) * 4;
-  }
-  return g;
-}
-
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
-
-MatvecPlan make_plan(int64_t n_pad, int blk, int items) {
-  MatvecPlan p;
-  p.blk = blk;
-  p.nb = static_cast<int>(n_pad / p.blk);
-  p.dmax = p.nb / 2;
-  const int ndelta = p.dmax + 1;
-  p.chunk = static_cast<int>(std::max<int64_t>(1, cdiv(int64_t(ndelta) * p.nb, items)));
-  p.nchunk = static_cast<int>(cdiv(ndelta, p.chunk));
-  p.grid = int64_t(p.nb) * p.nchunk;
-  return p;
-}
-
-size_t matvec_partial_floats(int64_t n_pad, int mv, int blk) {
-  // chunks per row block grow with the item target
-  MatvecPlan p = make_plan(n_pad, blk, kSweepItemsMax);
-  // row partials are FP64 (two floats each), column partials FP32
-  return size_t(2 * p.nchunk + p.dmax) * size_t(n_pad) * size_t(mv);
-}
-
-// Kernel value without the s2 factor, from the squared distance of the
-// operands, whose points are pre-scaled by c = point_scale(kernel, ell) so
-// that r2 = (c r)^2 feeds exp2 directly:
-//   RBF:        exp2(-r2)                              c^2 = log2(e) / (2 ell^2)
-//   Matern-3/2: (1 + ln2 u) exp2(-u),          u = c r, c = sqrt3 log2(e) / ell
-//   Matern-5/2: (1 + ln2 u + ln2^2 u^2 / 3) exp2(-u),   c = sqrt5 log2(e) / ell
-// (for the Matern kernels t = sqrt(nu2) r / ell = u ln2, so e^-t = 2^-u).  No
-// multiply by a hyperparameter is left in the pair loop.  |r2| absorbs the
-// tiny negative values FP32 rounding can give at r ~ 0.
-template <int KERN>
-__device__ __forceinline__ float kval(float r2) {
-  if constexpr (KERN == DCG_RBF) {
-    return __builtin_amdgcn_exp2f(-r2);
-  } else {
-    const float r2a = fabsf(r2);
-    const float u = __builtin_amdgcn_sqrtf(r2a);
-    const float e = __builtin_amdgcn_exp2f(-u);
-    if constexpr (KERN == DCG_MATERN32) {
-      return fmaf(kLn2, u, 1.0f) * e;
-    } else {
-      return fmaf(kLn2, u, fmaf(kLn2Sq3, r2a, 1.0f)) * e;
-    }
-  }
-}
 
 // Operand registers of one tile row: 16-bit terms (bf16 or fp16 bit
 // patterns, 8 per lane per K-step) or FP32 values.
@@ -343,14 +252,6 @@ __device__ __forceinline__ void symv_body(const SymvArgs &A, const int64_t item)
   }
 }
 
-// Work items are dealt to the 8 XCDs round-robin; the remap gives one XCD a
-// run of consecutive items, i.e. neighbouring row blocks that share most
-// column blocks, so they share that XCD's L2.
-__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t G) {
-  const int64_t Gm = G - G % 8;
-  return (bid < Gm) ? (bid % 8) * (Gm / 8) + bid / 8 : bid;
-}
-
 template <int KERN, int KS, int MV, int OPK>
 __global__ __launch_bounds__(256, 2) void symv_kernel(SymvArgs A) {
   if (A.done != nullptr && *A.done != 0) return;
@@ -526,6 +427,7 @@ int launch_symv_batched(const BatchItem *d_items, int count, int64_t total, int 
 int launch_symv_sweep_from(const dcg_operator_s *op, int mv, const float *vin, const int *done) {
   int64_t grid = 0;
   const SymvArgs a = symv_args(op, mv, vin, done, &grid);
+  if (sweep_wide(op->g)) return mv == 1 ? launch_symv_wide(op, a, grid) : DCG_E_ARG;
   int rc = -1;
   if (mv == 1) {
     if (op->kernel == DCG_RBF) rc = dispatch_ks<DCG_RBF, 1>(op, a, grid);
@@ -572,7 +474,7 @@ int matvec_lowprec(const dcg_operator_s *op, const double *V, double *Y, int64_t
   int64_t done_cols = 0;
   while (done_cols < m) {
     const int64_t left = m - done_cols;
-    const int mv = (left >= 2) ? 4 : 1;
+    const int mv = (left >= 2 && !sweep_wide(op->g)) ? 4 : 1;
     const int cols = static_cast<int>(std::min<int64_t>(left, mv));
     const double *Vc = V + done_cols * n;
     double *Yc = Y + done_cols * n;

@@ -6,14 +6,12 @@
 #include <new>
 
 #include "blas.h"
+#include "host.h"
 
 namespace dcg {
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-int exact_stride(int d);
-size_t exact_partial_doubles(int64_t n_pad);
-MatvecPlan exact_plan(int64_t n_pad, int items);
 int launch_exact_sweep(const dcg_operator_s *op, const int *done);
 
 // Round an FP64 value to bfloat16, to nearest with ties to even, in one
@@ -287,8 +285,9 @@ static int launch_prepare(const dcg_operator_s *op) {
   const dim3 grid(static_cast<unsigned>(cdiv(g.n_pad, 256)));
   const bool check = g.prec == DCG_PREC_FP16;
   if (check && hipMemsetAsync(op->flag, 0, sizeof(int), op->stream) != hipSuccess) return DCG_E_HIP;
-  hipLaunchKernelGGL(prepare_exact, grid, dim3(256), 0, op->stream, op->x64, g.n_pad, g.d,
-                     exact_stride(g.d), c, op->x64r, op->x64c);
+  if (!sweep_wide(g))
+    hipLaunchKernelGGL(prepare_exact, grid, dim3(256), 0, op->stream, op->x64, g.n_pad, g.d,
+                       exact_stride(g.d), c, op->x64r, op->x64c);
   if (g.prec != DCG_PREC_FP64)
     hipLaunchKernelGGL(prepare_lowprec, grid, dim3(256), 0, op->stream, op->x64, g.n, g.n_pad,
                        g.d, g.prec, g.opk, g.kstride, c, op->xr, op->xc, op->flag);
@@ -305,14 +304,23 @@ static int launch_prepare(const dcg_operator_s *op) {
 
 // ----------------------------------------------------------- workspace
 
+// Point dimensions each precision's products take.
+static int64_t max_dims(int prec) {
+  if (prec == DCG_PREC_STORED) return kMaxStoredD;
+  if (prec == DCG_PREC_BF16 || prec == DCG_PREC_FP16) return kMaxWideD;
+  return kMaxD;
+}
+
 struct OpLayout {
   size_t x64, x64r, x64c, vin64, part64, xr, xc, vin, part, ytmp, dsc, flag, kst, kpart, total;
 };
 
 static OpLayout op_layout(const Geometry &g) {
   const bool stored = g.prec == DCG_PREC_STORED;
-  // the stored operator keeps the points, the staged vector and K0 only
-  const int st64 = stored ? 0 : exact_stride(g.d);
+  // the stored operator keeps the points, the staged vector and K0 only;
+  // wide points have no FP64 operator
+  const bool no64 = stored || sweep_wide(g);
+  const int st64 = no64 ? 0 : exact_stride(g.d);
   const size_t esz = (g.prec == DCG_PREC_FP64 || stored) ? 0 : (g.opk == kOpF32 ? 4 : 2);
   Carve c(nullptr, 0);
   OpLayout L;
@@ -320,7 +328,7 @@ static OpLayout op_layout(const Geometry &g) {
   L.x64r = c.off = align256(c.off); c.off += size_t(g.n_pad) * st64 * 8;
   L.x64c = c.off = align256(c.off); c.off += size_t(g.n_pad) * st64 * 8;
   L.vin64 = c.off = align256(c.off); c.off += size_t(g.n_pad) * 8;
-  L.part64 = c.off = align256(c.off); if (!stored) c.off += exact_partial_doubles(g.n_pad) * 8;
+  L.part64 = c.off = align256(c.off); if (!no64) c.off += exact_partial_doubles(g.n_pad) * 8;
   L.xr = c.off = align256(c.off); c.off += size_t(g.n_pad) * g.kstride * esz;
   L.xc = c.off = align256(c.off); c.off += size_t(g.n_pad) * g.kstride * esz;
   L.vin = c.off = align256(c.off); c.off += size_t(g.n_pad) * 4 * 4;
@@ -390,7 +398,7 @@ extern "C" {
 
 size_t dcg_operator_workspace_bytes(int64_t n, int64_t d, int prec) {
   if (prec < DCG_PREC_FP32 || prec > DCG_PREC_STORED) return 0;
-  if (n < 1 || d < 1 || d > (prec == DCG_PREC_STORED ? kMaxStoredD : kMaxD)) return 0;
+  if (n < 1 || d < 1 || d > max_dims(prec)) return 0;
   return op_layout(make_geometry(n, static_cast<int>(d), prec)).total;
 }
 
@@ -400,13 +408,11 @@ int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel, doubl
   if (out == nullptr) return DCG_E_ARG;
   *out = nullptr;
   if (prec < DCG_PREC_FP32 || prec > DCG_PREC_STORED) return DCG_E_ARG;
-  if (X == nullptr || n < 1 || d < 1 || d > (prec == DCG_PREC_STORED ? kMaxStoredD : kMaxD))
-    return DCG_E_ARG;
+  if (X == nullptr || n < 1 || d < 1 || d > max_dims(prec)) return DCG_E_ARG;
   if (kernel < DCG_RBF || kernel > DCG_MATERN52) return DCG_E_ARG;
   if (!(ell > 0.0) || !(s2 > 0.0) || !(sigma2 >= 0.0) || !std::isfinite(ell) ||
       !std::isfinite(s2) || !std::isfinite(sigma2))
     return DCG_E_ARG;
-  if ((prec == DCG_PREC_BF16 || prec == DCG_PREC_FP16) && d + 6 > 80) return DCG_E_ARG;
   const Geometry g = make_geometry(n, static_cast<int>(d), prec);
   if (g.ksteps < 0) return DCG_E_ARG;
   const OpLayout L = op_layout(g);
@@ -534,7 +540,7 @@ int dcg_matvec(dcg_op_t op, const double *V, double *Y, int64_t m) {
 
 int dcg_matvec_exact(dcg_op_t op, const double *V, double *Y, int64_t m) {
   if (op == nullptr || V == nullptr || Y == nullptr || m < 1) return DCG_E_ARG;
-  if (op->g.prec == DCG_PREC_STORED) return DCG_E_ARG;   // no FP64 operator
+  if (!has_exact(op)) return DCG_E_ARG;   // no FP64 operator
   return matvec_exact(op, V, Y, m);
 }
 
@@ -557,11 +563,14 @@ int dcg_tune_operator(dcg_op_t op, int reps, int *items_out, double *ms_out) {
   if (hipMemsetAsync(op->vin64, 0, size_t(op->g.n_pad) * sizeof(double), s) != hipSuccess)
     return DCG_E_HIP;
   // FP64 sweep (refinement residuals, FP64 operators): a few launches
-  int st = tune_field(
-      s, std::max(1, reps / 4), &op->exact_items,
-      [&](int items) { return exact_plan(op->g.n_pad, items); },
-      [&]() { return launch_exact_sweep(op, nullptr); }, &best64, &ms64);
-  if (st != DCG_OK) return st;
+  int st = DCG_OK;
+  if (has_exact(op)) {
+    st = tune_field(
+        s, std::max(1, reps / 4), &op->exact_items,
+        [&](int items) { return exact_plan(op->g.n_pad, items); },
+        [&]() { return launch_exact_sweep(op, nullptr); }, &best64, &ms64);
+    if (st != DCG_OK) return st;
+  }
   if (op->g.prec != DCG_PREC_FP64) {
     if (hipMemsetAsync(op->vin, 0, size_t(op->g.n_pad) * 4 * sizeof(float), s) != hipSuccess)
       return DCG_E_HIP;

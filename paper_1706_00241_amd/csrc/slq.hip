@@ -25,84 +25,11 @@
 
 #include "blas.h"
 #include "common.h"
+#include "host.h"
 
 namespace dcg {
 
 constexpr int kSlqMaxSteps = 4096;
-
-// Eigenvalues (into d) and first eigenvector components (into q, starting
-// from e_1) of the symmetric tridiagonal matrix with diagonal d[0..m) and
-// off-diagonal e[0..m-1).  Returns false if a block fails to converge.
-static bool tridiag_eig_first_row(std::vector<double> &d, std::vector<double> &e,
-                                  std::vector<double> &q) {
-  const int m = static_cast<int>(d.size());
-  q.assign(m, 0.0);
-  if (m == 0) return true;
-  q[0] = 1.0;
-  const double eps = 2.220446049250313e-16;
-  int hi = m - 1;
-  int steps = 0;
-  while (hi > 0) {
-    if (std::fabs(e[hi - 1]) <= eps * (std::fabs(d[hi - 1]) + std::fabs(d[hi]))) {
-      e[hi - 1] = 0.0;
-      --hi;
-      continue;
-    }
-    if (++steps > 50 * m) return false;
-    int lo = hi - 1;
-    while (lo > 0 && std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo]))) --lo;
-    // Wilkinson shift: the eigenvalue of the trailing 2 x 2 block nearer d[hi]
-    const double delta = 0.5 * (d[hi - 1] - d[hi]);
-    const double eh = e[hi - 1];
-    const double sg = (delta >= 0.0) ? 1.0 : -1.0;
-    const double mu = d[hi] - eh * eh / (delta + sg * std::hypot(delta, eh));
-    // implicit QR step on [lo, hi]: the first rotation brings in the shift,
-    // the rest chase the bulge down the band
-    double x = d[lo] - mu, y = e[lo];
-    for (int k = lo; k < hi; ++k) {
-      const double r = std::hypot(x, y);
-      const double c = (r == 0.0) ? 1.0 : x / r;
-      const double s = (r == 0.0) ? 0.0 : -y / r;
-      if (k > lo) e[k - 1] = r;
-      const double a = d[k], b = e[k], cc = d[k + 1];
-      d[k] = c * c * a - 2.0 * c * s * b + s * s * cc;
-      d[k + 1] = s * s * a + 2.0 * c * s * b + c * c * cc;
-      e[k] = c * s * (a - cc) + (c * c - s * s) * b;
-      if (k + 1 < hi) {
-        x = e[k];
-        y = -s * e[k + 1];
-        e[k + 1] = c * e[k + 1];
-      }
-      const double q0 = q[k], q1 = q[k + 1];
-      q[k] = c * q0 - s * q1;
-      q[k + 1] = s * q0 + c * q1;
-    }
-  }
-  return true;
-}
-
-// |z|^2 e_1^T log(T) e_1 for the tridiagonal of m CG steps.
-static int slq_quadrature(const double *alpha, const double *beta, int m, double znorm2,
-                          double *out) {
-  if (m == 0) {
-    *out = 0.0;
-    return DCG_OK;
-  }
-  std::vector<double> d(m), e(std::max(m - 1, 0)), q;
-  for (int j = 0; j < m; ++j) {
-    if (!(alpha[j] > 0.0) || !std::isfinite(alpha[j])) return DCG_E_NOT_SPD;
-    d[j] = 1.0 / alpha[j] + ((j > 0) ? beta[j - 1] / alpha[j - 1] : 0.0);
-    if (j + 1 < m) e[j] = std::sqrt(std::max(beta[j], 0.0)) / alpha[j];
-  }
-  if (!tridiag_eig_first_row(d, e, q)) return DCG_E_NONFINITE;
-  double s = 0.0;
-  for (int i = 0; i < m; ++i) {
-    if (!(d[i] > 0.0)) return DCG_E_NOT_SPD;
-    s += q[i] * q[i] * std::log(d[i]);
-  }
-  *out = znorm2 * s;
-  return DCG_OK;
-}
 
 static size_t slq_block_bytes(int64_t n, int64_t P) { return align256(dcg_solve_block_workspace_bytes(n, P)); }
 

@@ -23,6 +23,7 @@ struct SolveBuffers {
   SolveState *S;
   unsigned *counter;
   double *r, *p, *q, *part, *part_h, *hist_res, *hist_d, *hist_alpha, *hist_beta;
+  double *hist_rho, *hist_mu, *hist_c;   // the implicit extraction's records
   double *tmp1, *tmp2, *tmp3;
   double *fD, *fQ;   // refinement directions (only with a refinement-sized workspace)
 };

@@ -30,8 +30,8 @@ constexpr size_t kGemmPartDoubles = size_t(64) * kMaxZ * kMaxZ;
 constexpr int kFcgCap = 32;
 
 struct SolveLayout {
-  size_t S, counter, r, p, q, part, part_h, hist_res, hist_d, hist_alpha, hist_beta, tmp1, tmp2,
-      tmp3, core, fD, fQ, total;
+  size_t S, counter, r, p, q, part, part_h, hist_res, hist_d, hist_alpha, hist_beta, hist_rho,
+      hist_mu, hist_c, tmp1, tmp2, tmp3, core, fD, fQ, total;
 };
 
 static SolveLayout solve_layout(int64_t n) {
@@ -55,6 +55,9 @@ static SolveLayout solve_layout(int64_t n) {
   L.hist_d = take(size_t(kMaxZ) * 8);
   L.hist_alpha = take(size_t(kMaxZ) * 8);
   L.hist_beta = take(size_t(kMaxZ) * 8);
+  L.hist_rho = take(size_t(kMaxZ + 1) * 8);
+  L.hist_mu = take(size_t(kMaxZ + 1) * kMaxK * 8);
+  L.hist_c = take(size_t(kMaxZ) * kMaxK * 8);
   L.tmp1 = take(size_t(n) * 8);
   L.tmp2 = take(size_t(n) * 8);
   L.tmp3 = take(size_t(n) * 8);
@@ -85,7 +88,7 @@ static RecycleLayout recycle_layout(int64_t n, int k, int L) {
     return o;
   };
   const size_t kz = size_t(k + L);
-  R.Z = take(size_t(n) * kz * 8);
+  R.Z = take(size_t(n) * (kz + 1) * 8);   // + p_L for the implicit extraction
   R.AZ = take(size_t(n) * kz * 8);
   R.Wt = take(size_t(n) * k * 8);
   R.AWt = take(size_t(n) * k * 8);
@@ -119,6 +122,9 @@ SolveBuffers solve_buffers(void *ws, int64_t n) {
   B.hist_d = reinterpret_cast<double *>(b + L.hist_d);
   B.hist_alpha = reinterpret_cast<double *>(b + L.hist_alpha);
   B.hist_beta = reinterpret_cast<double *>(b + L.hist_beta);
+  B.hist_rho = reinterpret_cast<double *>(b + L.hist_rho);
+  B.hist_mu = reinterpret_cast<double *>(b + L.hist_mu);
+  B.hist_c = reinterpret_cast<double *>(b + L.hist_c);
   B.tmp1 = reinterpret_cast<double *>(b + L.tmp1);
   B.tmp2 = reinterpret_cast<double *>(b + L.tmp2);
   B.tmp3 = reinterpret_cast<double *>(b + L.tmp3);
@@ -290,7 +296,11 @@ int solve_init(dcg_operator_s *op, const double *b, double *x, int x_given,
   if (k > 0) {
     // x_0 = x_{-1} + W (W^T A W)^{-1} W^T r_{-1};  r_0 = b - A x_0, formed as
     // r_{-1} - A (W c) with one product, so that r_0 is the residual of the
-    // operator itself and not of the (slightly inexact) stored AW
+    // operator itself and not of the stored AW (after an extraction whose
+    // metric F was nearly singular, AW' = (AZ) U carries the products'
+    // evaluation error amplified by U; with r_{-1} - (AW) c the n = 65536
+    // sequence needed 348 steps and 13 refinement steps on such a system
+    // instead of 169 and 9)
     enqueue_ts_dot(s, rc->Z, n, k, B.r, B.part_h, B.counter + 1, Minv, B.S->cvec);
     hipLaunchKernelGGL(defl_start, grid, dim3(256), 0, s, x, B.p, rc->Z, B.S->cvec, n, k);
     int st = matvec_lowprec(op, B.p, B.q, 1);
@@ -310,6 +320,16 @@ int solve_init(dcg_operator_s *op, const double *b, double *x, int x_given,
 
   ctx->B = B;
   ctx->a = cg_args(op, B, x, rc, Minv, k, L, koff, tol, max_iter);
+  if (rc != nullptr && sp.extract && p->extraction == 2 && L > 0) {
+    // the implicit extraction: rho_0 and mu_0 of the start, then every step's
+    // rho_{j+1}, mu_{j+1}, c_{j+1} (cg_finalize) and the FP64 directions
+    ctx->a.implicit = 1;
+    ctx->a.hist_rho = B.hist_rho;
+    ctx->a.hist_mu = B.hist_mu;
+    ctx->a.hist_c = B.hist_c;
+    HIPCHK(hipMemcpyAsync(B.hist_rho, &B.S->rho, 8, hipMemcpyDeviceToDevice, s));
+    if (k > 0) HIPCHK(hipMemcpyAsync(B.hist_mu, B.S->mu, size_t(k) * 8, hipMemcpyDeviceToDevice, s));
+  }
   ctx->k = k;
   ctx->L = L;
   ctx->koff = koff;
@@ -417,6 +437,45 @@ static void enqueue_extraction_pencil(hipStream_t s, const double *Z, const doub
   }
 }
 
+// After the pencil's eigenproblem has been enqueued: read its status, form
+// W' = Z U and AW' (by `form`, which enqueues both into rc->Wt, rc->AWt),
+// move them into the first columns of Z and AZ and record the new basis.
+template <class Form>
+static int finish_extraction(dcg_operator_s *op, dcg_recycle_s *rc, int mz, InnerResult *out,
+                             Form form) {
+  hipStream_t s = op->stream;
+  const int64_t n = op->g.n;
+  int info[4] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(info, rc->info, sizeof(info), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(rc->theta, rc->small, sizeof(double) * kMaxK, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int knew = info[0];
+  rc->rank_F = info[1];
+  rc->sweeps[0] = info[2];
+  rc->sweeps[1] = info[3];
+  if (knew > 0) {
+    form(knew);
+    HIPCHK(hipMemcpyAsync(rc->Z, rc->Wt, size_t(n) * knew * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(rc->AZ, rc->AWt, size_t(n) * knew * 8, hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  rc->k_used = knew;
+  rc->n_theta = knew;
+  rc->w_version += 1;
+  rc->L_eff = mz;
+  // AW' is the product with this operator
+  rc->aw_state = 1;
+  rc->aw_op = op;
+  rc->aw_gen = op->generation;
+  rc->aw_ell = op->ell;
+  rc->aw_s2 = op->s2;
+  rc->aw_sigma2 = op->sigma2;
+  rc->aw_dsc = op->dsc_version;
+  out->k_next = knew;
+  return DCG_OK;
+}
+
 // The extraction of W' = Z U (section 2.3: harmonic Ritz, Eq. 7, or
 // Rayleigh-Ritz) from the first mz columns of Z = [W, stored directions] and
 // AZ.
@@ -428,19 +487,84 @@ int extract_basis(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_params *p, in
   enqueue_extraction_pencil(s, rc->Z, rc->AZ, n, mz, p->extraction, rc->gemm, rc->F, rc->G);
   enqueue_harmonic_ritz(s, rc->F, rc->G, mz, rc->k, p->select_largest, p->ritz_route, 1e-12,
                         rc->eigw, rc->U, rc->small, rc->info);
+  return finish_extraction(op, rc, mz, out, [&](int knew) {
+    enqueue_ts_times_small(s, rc->Z, n, mz, rc->U, kMaxK, knew, rc->Wt);
+    enqueue_ts_times_small(s, rc->AZ, n, mz, rc->U, kMaxK, knew, rc->AWt);
+  });
+}
+
+// The implicit extraction (section 2.3, the F and G that Saad et al. formed
+// from the stored scalars): F, G from the records of the solve's first L_eff
+// steps (implicit.hip), the same eigenproblem, W' = [W, P] U with P read as
+// the FP32 copies the low-precision sweep multiplied, and
+// AW' = [W, P, p_L] S1 + AW S2 from the residual recurrence, so no product
+// A p_j was stored.  Z holds the FP64 directions p_0 .. p_L after W.
+//
+// The implicit F = blockdiag(M, diag(d_j)) assumes A-conjugate directions;
+// once the iteration has lost conjugacy (an extreme Ritz value converged) two
+// stored directions can be nearly parallel, which the scalars do not show,
+// and W' comes out numerically rank deficient.  A second harmonic problem on
+// span(W') with its explicit metric (AW')^T W' and (AW')^T AW' (k-column
+// products, against k + L for the explicit extraction) drops such
+// directions; where W' is sound it returns W' itself (the harmonic Ritz
+// vectors of span(Z) are those of span(W') with the same values).
+static int extract_implicit(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_params *p,
+                            const SolveCtx *ctx, int iters, InnerResult *out) {
+  hipStream_t s = op->stream;
+  const int64_t n = op->g.n;
+  const int k = ctx->k, Le = std::min(ctx->L, iters);
+  const int mz = k + Le;
+  if (mz <= 0) return DCG_OK;
+  // p_{Le}: still the current direction unless step Le ran and stored it
+  if (iters <= ctx->L)
+    HIPCHK(hipMemcpyAsync(rc->Z + int64_t(ctx->koff + Le) * n, ctx->B.p, size_t(n) * 8,
+                          hipMemcpyDeviceToDevice, s));
+  ImplicitHist h;
+  h.d = ctx->B.hist_d;
+  h.alpha = ctx->B.hist_alpha;
+  h.beta = ctx->B.hist_beta;
+  h.rho = ctx->B.hist_rho;
+  h.mu = ctx->B.hist_mu;
+  h.cv = ctx->B.hist_c;
+  // scratch in the split-K area the tall products would have used
+  double *terms = rc->gemm;                                   // 2 x kMaxZ x kMaxK
+  double *S1 = rc->gemm + 2 * size_t(kMaxZ) * kMaxK;          // (kMaxZ + 1) x kMaxK
+  double *S2 = S1 + size_t(kMaxZ + 1) * kMaxK;                // kMaxK x kMaxK
+  double *part = S2 + size_t(kMaxK) * kMaxK;                  // split-K partials (k x k)
+  const size_t part_cap = kGemmPartDoubles - size_t(part - rc->gemm);
+  enqueue_implicit_pencil(s, h, rc->M, rc->N, k, Le, terms, rc->F, rc->G);
+  enqueue_harmonic_ritz(s, rc->F, rc->G, mz, rc->k, p->select_largest, p->ritz_route, 1e-12,
+                        rc->eigw, rc->U, rc->small, rc->info);
   int info[4] = {0, 0, 0, 0};
   HIPCHK(hipMemcpyAsync(info, rc->info, sizeof(info), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(rc->theta, rc->small, sizeof(double) * kMaxK, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  const int knew = info[0];
+  const int k1 = info[0];
   rc->rank_F = info[1];
   rc->sweeps[0] = info[2];
   rc->sweeps[1] = info[3];
-  if (knew > 0) {
-    enqueue_ts_times_small(s, rc->Z, n, mz, rc->U, kMaxK, knew, rc->Wt);
-    enqueue_ts_times_small(s, rc->AZ, n, mz, rc->U, kMaxK, knew, rc->AWt);
-    HIPCHK(hipMemcpyAsync(rc->Z, rc->Wt, size_t(n) * knew * 8, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(rc->AZ, rc->AWt, size_t(n) * knew * 8, hipMemcpyDeviceToDevice, s));
+  int knew = 0;
+  if (k1 > 0) {
+    const bool lowprec = ctx->a.qdirect == nullptr;
+    enqueue_ts_times_small(s, rc->Z, n, mz, rc->U, kMaxK, k1, rc->Wt, lowprec ? k : (1 << 30),
+                           op->has_dsc ? op->dsc : nullptr);
+    enqueue_implicit_aw_coef(s, h, rc->U, k, Le, k1, S1, S2);
+    enqueue_ts_times_small(s, rc->Z, n, mz + 1, S1, kMaxK, k1, rc->AWt);
+    if (k > 0)
+      enqueue_ts_times_small(s, rc->AZ, n, k, S2, kMaxK, k1, rc->AWt, 1 << 30, nullptr, 1);
+    // the second, explicit harmonic problem on span(W')
+    enqueue_tsgemm_tn(s, rc->AWt, rc->Wt, n, k1, k1, part, part_cap, rc->F, k1, 1);
+    enqueue_tsgemm_tn(s, rc->AWt, rc->AWt, n, k1, k1, part, part_cap, rc->G, k1, 1);
+    enqueue_harmonic_ritz(s, rc->F, rc->G, k1, k1, p->select_largest, p->ritz_route, 1e-12,
+                          rc->eigw, rc->U, rc->small, rc->info);
+    int info2[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(info2, rc->info, sizeof(info2), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(rc->theta, rc->small, sizeof(double) * kMaxK, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    knew = info2[0];
+    if (knew > 0) {
+      enqueue_ts_times_small(s, rc->Wt, n, k1, rc->U, kMaxK, knew, rc->Z);
+      enqueue_ts_times_small(s, rc->AWt, n, k1, rc->U, kMaxK, knew, rc->AZ);
+    }
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
@@ -448,7 +572,6 @@ int extract_basis(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_params *p, in
   rc->n_theta = knew;
   rc->w_version += 1;
   rc->L_eff = mz;
-  // AW' = (AZ) U is the product with this operator
   rc->aw_state = 1;
   rc->aw_op = op;
   rc->aw_gen = op->generation;
@@ -466,7 +589,9 @@ int solve_extract(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_params *p, So
                   InnerResult *out) {
   const auto t2 = Clock::now();
   if (rc != nullptr && ctx->extract && out->status >= 0) {
-    const int st = extract_basis(op, rc, p, ctx->koff + std::min(ctx->L, out->iters), out);
+    const int st = ctx->a.implicit
+                       ? extract_implicit(op, rc, p, ctx, out->iters, out)
+                       : extract_basis(op, rc, p, ctx->koff + std::min(ctx->L, out->iters), out);
     if (st != DCG_OK) return st;
   }
   out->t_refresh = ms_since(t2);
@@ -805,11 +930,14 @@ int dcg_solve(dcg_op_t op, const double *b, double *x, int x_given, dcg_recycle_
   if (op == nullptr || b == nullptr || x == nullptr || p == nullptr) return st->status = DCG_E_ARG;
   if (!(p->tol >= 0.0) || p->check_every < 0 || p->refine < 0 || p->refine > 2 ||
       p->refresh_every < 0 || p->refresh_every > 2 || p->ritz_route < 0 || p->ritz_route > 1 ||
-      p->extraction < 0 || p->extraction > 1)
+      p->extraction < 0 || p->extraction > 2 ||
+      // the implicit extraction describes one Krylov sequence, not the
+      // pooled directions of several inner solves
+      (p->extraction == 2 && p->refine != 0 && p->refresh_every == 2))
     return st->status = DCG_E_ARG;
   if (rc != nullptr && rc->n != op->g.n) return st->status = DCG_E_ARG;
   // the stored operator has no FP64 counterpart to refine against
-  if (op->g.prec == DCG_PREC_STORED && p->refine != 0) return st->status = DCG_E_ARG;
+  if (!has_exact(op) && p->refine != 0) return st->status = DCG_E_ARG;
   if (ws == nullptr || ws_bytes < solve_layout(op->g.n).total) return st->status = DCG_E_WORKSPACE;
   if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return st->status = DCG_E_WORKSPACE;
   const auto t0 = Clock::now();

@@ -38,7 +38,13 @@ def test_exports_every_declared_symbol(L):
 def test_workspace_queries(L):
     assert L.dcg_operator_workspace_bytes(65536, 32, 1) > 65536 * 32 * 8
     assert L.dcg_operator_workspace_bytes(0, 32, 1) == 0
-    assert L.dcg_operator_workspace_bytes(100, 65, 1) == 0
+    assert L.dcg_operator_workspace_bytes(100, 65, 0) == 0       # FP32 points: d <= 64
+    assert L.dcg_operator_workspace_bytes(100, 65, 3) == 0       # FP64 operator: d <= 64
+    # bf16 / fp16 points beyond 64 coordinates: the LDS-staged sweep, K padded
+    # to slices of 64, no FP64 operands
+    assert L.dcg_operator_workspace_bytes(1000, 784, 1) >= 1024 * 832 * 2 * 2
+    assert L.dcg_operator_workspace_bytes(1000, 4096, 4) > 0
+    assert L.dcg_operator_workspace_bytes(1000, 4097, 1) == 0
     assert L.dcg_operator_workspace_bytes(100, 8, 7) == 0
     assert L.dcg_operator_workspace_bytes(100, 8, 4) > 0       # fp16
     # the stored operator: K0 in FP32 over the padded size, any d up to 4096
