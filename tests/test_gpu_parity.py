@@ -829,7 +829,8 @@ def test_fp32_walk_full_size_matches_oracle(lib):
       row at a time; the GPU operator's product agrees with each to 2e-5 of
       (|A| |x|)_i (its product bound), so the residual the library reports
       with its own operator is the operator's.
-    Plain CG (the last five systems) likewise against the oracle's plain runs."""
+    Plain CG (the last five systems) against the oracle's plain runs, with
+    the band widened by the spread of the two emulated plain runs."""
     import json
     import os
     gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
@@ -883,6 +884,11 @@ def test_fp32_walk_full_size_matches_oracle(lib):
         _, st = lib.solve(op, _dev(b), tol=w["tol"])
         exact = runs["plain"]["iters"][i]
         emu = [runs[f"emulated_plain{s}"]["iters"][i] for s in (0, 1)]
-        lo, hi = min([exact] + emu) - 3, max([exact] + emu) + 3
+        # plain CG's count at this error level is set by its loss of
+        # orthogonality and moves with the rounding itself: the two
+        # emulated seeds differ by up to 14 steps, so the band is widened
+        # on each side by that spread (the deflated runs above stay tight)
+        spread = max(3, max(emu) - min(emu))
+        lo, hi = min([exact] + emu) - spread, max([exact] + emu) + spread
         print(f"plain system {i}: GPU {st['iters']}, oracle {exact}, emulated {emu}", flush=True)
         assert st["status"] == 0 and lo <= st["iters"] <= hi, (i, st["iters"], lo, hi)
