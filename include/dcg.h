@@ -137,9 +137,12 @@ typedef struct {
                           scalars of the first L steps (d_j, alpha_j,
                           beta_j, rho_j, mu_j and the re-projection's
                           coefficients; section 2.3, after Saad et al.)
-                          instead of tall products, and AW' from the
-                          residual recurrence: the solve stores the FP64
-                          directions p_0 .. p_L and no products A p_j.
+                          instead of tall products; the solve stores the
+                          FP64 directions p_0 .. p_L and no products A p_j.
+                          AW' comes from the residual recurrence on the
+                          FP64 operator and from k' products of W' on the
+                          others (a second harmonic problem on span(W')
+                          then drops pairs the scalars could not resolve).
                           dcg_solve only (the batched solve and
                           dcg_extract_basis refuse it), not with the pooled
                           refresh of refine (refresh_every = 2);

@@ -496,9 +496,10 @@ int extract_basis(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_params *p, in
 // The implicit extraction (section 2.3, the F and G that Saad et al. formed
 // from the stored scalars): F, G from the records of the solve's first L_eff
 // steps (implicit.hip), the same eigenproblem, W' = [W, P] U with P read as
-// the FP32 copies the low-precision sweep multiplied, and
-// AW' = [W, P, p_L] S1 + AW S2 from the residual recurrence, so no product
-// A p_j was stored.  Z holds the FP64 directions p_0 .. p_L after W.
+// the FP32 copies the low-precision sweep multiplied, and AW' either from the
+// residual recurrence, AW' = [W, P, p_L] S1 + AW S2 (FP64 operator), or as
+// k' products of W' (every other operator), so that no product A p_j is
+// stored.  Z holds the FP64 directions p_0 .. p_L after W.
 //
 // The implicit F = blockdiag(M, diag(d_j)) assumes A-conjugate directions;
 // once the iteration has lost conjugacy (an extreme Ritz value converged) two
@@ -509,7 +510,7 @@ int extract_basis(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_params *p, in
 // directions; where W' is sound it returns W' itself (the harmonic Ritz
 // vectors of span(Z) are those of span(W') with the same values).
 static int extract_implicit(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_params *p,
-                            const SolveCtx *ctx, int iters, InnerResult *out) {
+                            SolveCtx *ctx, int iters, InnerResult *out) {
   hipStream_t s = op->stream;
   const int64_t n = op->g.n;
   const int k = ctx->k, Le = std::min(ctx->L, iters);
@@ -547,14 +548,37 @@ static int extract_implicit(dcg_operator_s *op, dcg_recycle_s *rc, const dcg_par
     const bool lowprec = ctx->a.qdirect == nullptr;
     enqueue_ts_times_small(s, rc->Z, n, mz, rc->U, kMaxK, k1, rc->Wt, lowprec ? k : (1 << 30),
                            op->has_dsc ? op->dsc : nullptr);
-    enqueue_implicit_aw_coef(s, h, rc->U, k, Le, k1, S1, S2);
-    enqueue_ts_times_small(s, rc->Z, n, mz + 1, S1, kMaxK, k1, rc->AWt);
-    if (k > 0)
-      enqueue_ts_times_small(s, rc->AZ, n, k, S2, kMaxK, k1, rc->AWt, 1 << 30, nullptr, 1);
-    // the second, explicit harmonic problem on span(W')
+    if (op->g.prec == DCG_PREC_FP64) {
+      enqueue_implicit_aw_coef(s, h, rc->U, k, Le, k1, S1, S2);
+      enqueue_ts_times_small(s, rc->Z, n, mz + 1, S1, kMaxK, k1, rc->AWt);
+      if (k > 0)
+        enqueue_ts_times_small(s, rc->AZ, n, k, S2, kMaxK, k1, rc->AWt, 1 << 30, nullptr, 1);
+    } else {
+      // An FP32-accumulated product is exact only to ~1e-7 of (|A| |p|)_i,
+      // and U, drawn from a metric that cannot see lost conjugacy, can
+      // combine nearly parallel directions with large coefficients: the
+      // implied products of such a combination are then dominated by those
+      // errors (measured: 34% of |AW'| at n = 65536 with bf16 points after
+      // one recycled system), and the harmonic problem below would pick
+      // exactly those directions as its largest values.  Here AW' is the
+      // operator's own product of W' (k1 columns), as in refresh_AW.
+      if (op->g.prec != DCG_PREC_STORED && !op->has_dsc)
+        enqueue_round_to_fp32(s, rc->Wt, n * k1);
+      const int st = matvec_lowprec(op, rc->Wt, rc->AWt, k1);
+      if (st != DCG_OK) return st;
+      ctx->matvecs += k1;
+    }
+    // the second, explicit harmonic problem on span(W').  Its metric drops
+    // a direction at tau times the largest eigenvalue of the scaled F, which
+    // bounds the growth of the products' errors through U by 1/sqrt(tau):
+    // FP32-accumulated products (~1e-7 relative) need tau = 1e-4 to keep
+    // AW' at their own error level (at 1e-12, the n = 65536 bf16 sequence
+    // kept an error of 2.5e-4 of |AW'|); columns that close to dependent are
+    // the ghost pairs the cleanup is for.
+    const double tau = (op->g.prec == DCG_PREC_FP64) ? 1e-12 : 1e-4;
     enqueue_tsgemm_tn(s, rc->AWt, rc->Wt, n, k1, k1, part, part_cap, rc->F, k1, 1);
     enqueue_tsgemm_tn(s, rc->AWt, rc->AWt, n, k1, k1, part, part_cap, rc->G, k1, 1);
-    enqueue_harmonic_ritz(s, rc->F, rc->G, k1, k1, p->select_largest, p->ritz_route, 1e-12,
+    enqueue_harmonic_ritz(s, rc->F, rc->G, k1, k1, p->select_largest, p->ritz_route, tau,
                           rc->eigw, rc->U, rc->small, rc->info);
     int info2[4] = {0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(info2, rc->info, sizeof(info2), hipMemcpyDeviceToHost, s));

@@ -46,9 +46,8 @@ def test_implicit_sequence_matches_oracle(lib, prec, tol, th_rtol):
                             reproject=True)
     op = lib.Operator(_dev(X), w["kernel"], w["ells"][0], 1.0, w["sigma2"], prec=prec)
     rc = lib.Recycle(n, 8, 12)
-    # FP32: the implied products are the sweep's (2e-5 of (|A| |p|)_i each),
-    # combined through U, whose entries grow as the metric F nears
-    # singularity; measured up to 3.9e-5 of (|A| |W'|)_i on this sequence
+    # FP64: AW' from the recurrence; FP32: the sweep's products of W'
+    # (2e-5 of (|A| |p|)_i each), combined through the cleanup's U
     prod_tol = 1e-10 if prec == 3 else 1e-4
     for i, (ell, A, b) in enumerate(zip(w["ells"], mats, bs)):
         op.set_hyper(ell, 1.0, w["sigma2"])
@@ -98,8 +97,9 @@ def test_implicit_refinement_bf16(lib):
     """Refinement to 1e-8 with bf16 inner solves (n = 3000, Matern-5/2,
     def-CG(16, 24), refresh after the first inner solve, three systems of
     the sigma2 sequence) with the implicit extraction: every system reaches
-    the tolerance in the dense FP64 residual, and the step counts stay within
-    15% (+2) of the explicit extraction's on the same sequence."""
+    the tolerance in the dense FP64 residual, the recycled AW is the bf16
+    operator's product of W (1e-4 of (|A| |W|)_i), and the step counts stay
+    within 15% (+2) of the explicit extraction's on the same sequence."""
     w = workloads.bf16_shift(n=3000, systems=3)
     X, b, kern, ell = w["X"], w["b"], w["kernel"], w["ell"]
     K64 = OK.gram(X, kern, ell, 1.0)
@@ -117,6 +117,11 @@ def test_implicit_refinement_bf16(lib):
             res = np.linalg.norm(b - A64 @ _np(x)) / np.linalg.norm(b)
             assert res <= 1.05e-8, (kind, res)
             its[kind].append(st["iters"])
+            # the recycled AW is the bf16 operator's product of W
+            W, AW = _np(rc.get_W()), _np(rc.get_AW())
+            Ab = OK.operator(OP.round_points(X, 1, kern, ell), kern, ell, 1.0, s2)
+            err = np.max(np.abs(AW - Ab @ W) / (np.abs(Ab) @ np.abs(W)))
+            assert err <= 1e-4, (kind, err)
     print(f"steps: {its}", flush=True)
     for a, c in zip(its["implicit"], its["harmonic"]):
         assert a <= 1.15 * c + 2, its
@@ -141,3 +146,30 @@ def test_implicit_refused_where_undefined(lib):
     # and the handle still works
     _, st = lib.solve(op, b, rc=rc, tol=1e-6, extraction="implicit")
     assert st["status"] == 0 and st["k_next"] == 8
+
+
+def test_implicit_headline_sequence(lib):
+    """The implicit extraction on the first four systems of the n = 65536
+    sigma2 sequence (bf16 points, Matern-5/2, def-CG(64, 96), refinement to
+    1e-8 with inner solves to 2e-2, refresh after the first inner solve):
+    every system meets the tolerance, and after each extraction the recycled
+    AW is the operator's product of W (relative Frobenius difference 1e-4;
+    the bf16 sweep's own products differ by ~1e-5).  Regression for implied
+    products that, combined through a U built without the lost conjugacy,
+    were off by 34% after the first recycled system (the refined solve of
+    the next system then broke down)."""
+    w = workloads.bf16_shift(n=65536, systems=4)
+    X, b = _dev(w["X"]), _dev(w["b"])
+    op = lib.Operator(X, w["kernel"], w["ell"], 1.0, w["sigma2s"][0], prec=1)
+    rc = lib.Recycle(65536, w["k"], w["L"])
+    for i, s2 in enumerate(w["sigma2s"]):
+        op.set_hyper(w["ell"], 1.0, s2)
+        _, st = lib.solve(op, b, rc=rc, tol=w["tol"], refine=True, inner_tol=2e-2,
+                          extraction="implicit", max_iter=4000, refine_max=16)
+        W, AW = rc.get_W(), rc.get_AW()
+        rel = float(torch.linalg.norm(AW - op.matvec(W.contiguous())) / torch.linalg.norm(AW))
+        print(f"system {i}: its {st['iters']} outer {st['outer_steps']} k_next {st['k_next']} "
+              f"res {st['rel_res_true']:.2e} |AW - A W| / |AW| {rel:.1e}", flush=True)
+        assert st["status"] == 0 and st["rel_res_true"] <= w["tol"]
+        assert st["k_next"] >= w["k"] // 2
+        assert rel <= 1e-4, (i, rel)
