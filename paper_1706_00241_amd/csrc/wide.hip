@@ -12,8 +12,8 @@
 // current one feeds the matrix cores), each wave accumulating a 64 x 128
 // part of the 256 x 256 distance tile in eight 32x32x16 MFMA tiles.  The
 // slices are stored with the 16-byte groups of a row XOR-swizzled by the row
-// index, so that the 32 rows a fragment read touches fall in distinct LDS
-// banks.  After the last slice the kernel values are formed in registers on
+// index, so that the rows a fragment read serves together fall in distinct
+// LDS banks.  After the last slice the kernel values are formed in registers on
 // the MFMA output layout and folded into FP32 row sums (accumulated in LDS
 // across the work item's block pairs) and per-block-pair column sums.
 #include <algorithm>
@@ -40,8 +40,15 @@ __device__ __forceinline__ f32x16 wide_mfma(const u32x4 &a, const u32x4 &b, cons
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-// Slot of the 16-byte group g (0..7) of row `row` in a slice.
-__device__ __forceinline__ int wide_slot(int row, int g) { return row * 8 + (g ^ (row & 7)); }
+// Slot of the 16-byte group g (0..7) of row `row` in a slice.  A fragment
+// read takes group g of 32 consecutive rows; the 128-byte rows put rows of
+// equal parity on the same half of 256 bytes of banks, so the group is
+// XOR-ed with row mod 8 and with bit 3 of the row: any 8 consecutive rows
+// use 8 distinct 16-byte bank groups, and any 16 use 16 distinct groups of
+// 256 bytes (rows r and r + 8 differ in the low bit of the XOR).
+__device__ __forceinline__ int wide_slot(int row, int g) {
+  return row * 8 + (g ^ (row & 7) ^ ((row >> 3) & 1));
+}
 
 template <int KERN, int OPK>
 __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
