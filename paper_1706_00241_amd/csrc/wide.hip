@@ -26,9 +26,16 @@
 namespace dcg {
 
 constexpr int kWideRows = 256;  // points per block (rows and columns)
-constexpr int kWideKC = 64;     // K elements per LDS slice (four MFMA K-steps)
+constexpr int kWideKC = 32;     // K elements per LDS stage (two MFMA K-steps)
+constexpr int kWideSlots = kWideRows * 4;   // 16-byte slots of one operand in a stage
+
+// s_waitcnt immediates that wait for the vector-memory counter only
+// (vmcnt in bits 3:0, expcnt 6:4 and lgkmcnt 11:8 left at their maxima)
+constexpr int kVmcnt0 = 0xF70, kVmcnt4 = 0xF74, kVmcnt8 = 0xF78;
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void global_void;
 
 template <int OPK>
 __device__ __forceinline__ f32x16 wide_mfma(const u32x4 &a, const u32x4 &b, const f32x16 &c) {
@@ -40,14 +47,13 @@ __device__ __forceinline__ f32x16 wide_mfma(const u32x4 &a, const u32x4 &b, cons
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-// Slot of the 16-byte group g (0..7) of row `row` in a slice.  A fragment
-// read takes group g of 32 consecutive rows; the 128-byte rows put rows of
-// equal parity on the same half of 256 bytes of banks, so the group is
-// XOR-ed with row mod 8 and with bit 3 of the row: any 8 consecutive rows
-// use 8 distinct 16-byte bank groups, and any 16 use 16 distinct groups of
-// 256 bytes (rows r and r + 8 differ in the low bit of the XOR).
+// Slot of the 16-byte group g (0..3) of row `row` in a stage (64-byte rows).
+// A fragment read takes group g of 32 consecutive rows, served 16 lanes at a
+// time over 256 bytes of banks: rows r and r + 4 share those bytes' quarter,
+// so the group is XOR-ed with bits 2-3 of the row and any 16 consecutive
+// rows use 16 distinct 16-byte bank groups.
 __device__ __forceinline__ int wide_slot(int row, int g) {
-  return row * 8 + (g ^ (row & 7) ^ ((row >> 3) & 1));
+  return row * 4 + (g ^ ((row >> 2) & 3));
 }
 
 template <int KERN, int OPK>
@@ -68,8 +74,12 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
   const int kst = A.kstride;             // a multiple of kWideKC
   const int nkc = kst / kWideKC;
 
-  __shared__ u32x4 As[2][kWideRows * 8];
-  __shared__ u32x4 Bs[2][kWideRows * 8];
+  // four stages: slots [0, kWideSlots) the row block's operand, the rest
+  // the column block's
+  __shared__ u32x4 St0[2 * kWideSlots];
+  __shared__ u32x4 St1[2 * kWideSlots];
+  __shared__ u32x4 St2[2 * kWideSlots];
+  __shared__ u32x4 St3[2 * kWideSlots];
   __shared__ float rowacc[2][kWideRows];
   __shared__ float colpart[4][kWideRows];
   __shared__ float vrow[kWideRows];      // the input vector on this row block
@@ -80,70 +90,101 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
 
   const uint16_t *xr = static_cast<const uint16_t *>(A.xr);
   const uint16_t *xc = static_cast<const uint16_t *>(A.xc);
-  // staging: this thread moves rows srow + 64 i (i < 4), group sg, of both
-  // operand blocks
-  const int srow = tid >> 3, sg = tid & 7;
+  // Loads: a stage is 32 chunks of 1 KB (64 slots), written by direct
+  // global-to-LDS loads, lane l of a load to slot 64 (chunk) + l.  Waves 0-3
+  // load the row block's operand (chunks 4 wr + i, i < 4), waves 4-7 the
+  // column block's; a lane fetches the row and group its slot holds.
+  const int opsel = wc;
+  int go0, go1, go2, go3;                // element offsets within the block
+  {
+    int s = (4 * wr + 0) * 64 + l, row = s >> 2;
+    go0 = row * kst + 8 * ((s & 3) ^ ((row >> 2) & 3));
+    s = (4 * wr + 1) * 64 + l; row = s >> 2;
+    go1 = row * kst + 8 * ((s & 3) ^ ((row >> 2) & 3));
+    s = (4 * wr + 2) * 64 + l; row = s >> 2;
+    go2 = row * kst + 8 * ((s & 3) ^ ((row >> 2) & 3));
+    s = (4 * wr + 3) * 64 + l; row = s >> 2;
+    go3 = row * kst + 8 * ((s & 3) ^ ((row >> 2) & 3));
+  }
+  const int dst0 = opsel * kWideSlots + (4 * wr) * 64;   // this wave's first chunk
+
+#define DCG_WIDE_ISSUE(BUF, kc)                                                              \
+  do {                                                                                       \
+    const uint16_t *src = base + (kc) * kWideKC;                                             \
+    __builtin_amdgcn_global_load_lds((global_void *)(src + go0), (lds_void *)&BUF[dst0], 16, \
+                                     0, 0);                                                  \
+    __builtin_amdgcn_global_load_lds((global_void *)(src + go1),                             \
+                                     (lds_void *)&BUF[dst0 + 64], 16, 0, 0);                 \
+    __builtin_amdgcn_global_load_lds((global_void *)(src + go2),                             \
+                                     (lds_void *)&BUF[dst0 + 128], 16, 0, 0);                \
+    __builtin_amdgcn_global_load_lds((global_void *)(src + go3),                             \
+                                     (lds_void *)&BUF[dst0 + 192], 16, 0, 0);                \
+  } while (0)
+#define DCG_WIDE_COMPUTE(BUF)                                                                \
+  do {                                                                                       \
+    _Pragma("unroll") for (int ks = 0; ks < kWideKC / 16; ++ks) {                            \
+      const int g = 2 * ks + lh;                                                             \
+      const u32x4 a0 = BUF[wide_slot(64 * wr + lc, g)];                                      \
+      const u32x4 a1 = BUF[wide_slot(64 * wr + 32 + lc, g)];                                 \
+      const u32x4 b0 = BUF[kWideSlots + wide_slot(128 * wc + lc, g)];                        \
+      const u32x4 b1 = BUF[kWideSlots + wide_slot(128 * wc + 32 + lc, g)];                   \
+      const u32x4 b2 = BUF[kWideSlots + wide_slot(128 * wc + 64 + lc, g)];                   \
+      const u32x4 b3 = BUF[kWideSlots + wide_slot(128 * wc + 96 + lc, g)];                   \
+      acc[0][0] = wide_mfma<OPK>(a0, b0, acc[0][0]);                                         \
+      acc[0][1] = wide_mfma<OPK>(a0, b1, acc[0][1]);                                         \
+      acc[0][2] = wide_mfma<OPK>(a0, b2, acc[0][2]);                                         \
+      acc[0][3] = wide_mfma<OPK>(a0, b3, acc[0][3]);                                         \
+      acc[1][0] = wide_mfma<OPK>(a1, b0, acc[1][0]);                                         \
+      acc[1][1] = wide_mfma<OPK>(a1, b1, acc[1][1]);                                         \
+      acc[1][2] = wide_mfma<OPK>(a1, b2, acc[1][2]);                                         \
+      acc[1][3] = wide_mfma<OPK>(a1, b3, acc[1][3]);                                         \
+    }                                                                                        \
+  } while (0)
+// One stage s in buffer CUR: wait until this wave's loads of stage s have
+// landed (those of s + 1 and s + 2 may still be in flight: four loads per
+// stage, retired in order), then the barrier makes every wave's loads of s
+// visible and frees NXT (read at step s - 1, whose reads every wave has
+// waited for before its MFMAs) for stage s + 3.  A plain s_barrier: the
+// release fence of __syncthreads would wait for the loads still in flight
+// too; the empty asm statements keep the compiler from moving LDS accesses
+// across it.
+#define DCG_WIDE_STEP(CUR, NXT, s)                                                           \
+  do {                                                                                       \
+    if ((s) + 2 < nkc) __builtin_amdgcn_s_waitcnt(kVmcnt8);                                  \
+    else if ((s) + 1 < nkc) __builtin_amdgcn_s_waitcnt(kVmcnt4);                             \
+    else __builtin_amdgcn_s_waitcnt(kVmcnt0);                                                \
+    asm volatile("" ::: "memory");                                                           \
+    __builtin_amdgcn_s_barrier();                                                            \
+    asm volatile("" ::: "memory");                                                           \
+    if ((s) + 3 < nkc) DCG_WIDE_ISSUE(NXT, (s) + 3);                                         \
+    DCG_WIDE_COMPUTE(CUR);                                                                   \
+  } while (0)
 
   for (int dl = d0; dl < d1; ++dl) {
     int J = I + dl;
     if (J >= nb) J -= nb;
-    const uint16_t *ablk = xr + int64_t(I) * kWideRows * kst + int64_t(srow) * kst + sg * 8;
-    const uint16_t *bblk = xc + int64_t(J) * kWideRows * kst + int64_t(srow) * kst + sg * 8;
-    const int64_t rstep = int64_t(64) * kst;
+    const uint16_t *base =
+        (opsel == 0 ? xr + int64_t(I) * kWideRows * kst : xc + int64_t(J) * kWideRows * kst);
     f32x16 acc[2][4];
 #pragma unroll
     for (int tr = 0; tr < 2; ++tr)
 #pragma unroll
       for (int tc = 0; tc < 4; ++tc) acc[tr][tc] = f32x16{};
-    u32x4 sa0, sa1, sa2, sa3, sb0, sb1, sb2, sb3;
-#define DCG_WIDE_GLOAD(kc)                                                        \
-  do {                                                                            \
-    const int64_t ko = int64_t(kc) * kWideKC;                                     \
-    sa0 = *reinterpret_cast<const u32x4 *>(ablk + ko);                            \
-    sb0 = *reinterpret_cast<const u32x4 *>(bblk + ko);                            \
-    sa1 = *reinterpret_cast<const u32x4 *>(ablk + rstep + ko);                    \
-    sb1 = *reinterpret_cast<const u32x4 *>(bblk + rstep + ko);                    \
-    sa2 = *reinterpret_cast<const u32x4 *>(ablk + 2 * rstep + ko);                \
-    sb2 = *reinterpret_cast<const u32x4 *>(bblk + 2 * rstep + ko);                \
-    sa3 = *reinterpret_cast<const u32x4 *>(ablk + 3 * rstep + ko);                \
-    sb3 = *reinterpret_cast<const u32x4 *>(bblk + 3 * rstep + ko);                \
-  } while (0)
-#define DCG_WIDE_LSTORE(buf)                                                      \
-  do {                                                                            \
-    As[buf][wide_slot(srow, sg)] = sa0;                                           \
-    Bs[buf][wide_slot(srow, sg)] = sb0;                                           \
-    As[buf][wide_slot(srow + 64, sg)] = sa1;                                      \
-    Bs[buf][wide_slot(srow + 64, sg)] = sb1;                                      \
-    As[buf][wide_slot(srow + 128, sg)] = sa2;                                     \
-    Bs[buf][wide_slot(srow + 128, sg)] = sb2;                                     \
-    As[buf][wide_slot(srow + 192, sg)] = sa3;                                     \
-    Bs[buf][wide_slot(srow + 192, sg)] = sb3;                                     \
-  } while (0)
-    DCG_WIDE_GLOAD(0);
-    DCG_WIDE_LSTORE(0);
+    // every wave is done with the previous block pair's stages and stores
+    __builtin_amdgcn_s_waitcnt(kVmcnt0);
     __syncthreads();
-    for (int kc = 0; kc < nkc; ++kc) {
-      const int buf = kc & 1;
-      if (kc + 1 < nkc) DCG_WIDE_GLOAD(kc + 1);
-#pragma unroll
-      for (int ks = 0; ks < kWideKC / 16; ++ks) {
-        const int g = 2 * ks + lh;   // this lane's 8 elements of the K-step
-        u32x4 af[2], bf[4];
-#pragma unroll
-        for (int tr = 0; tr < 2; ++tr) af[tr] = As[buf][wide_slot(64 * wr + 32 * tr + lc, g)];
-#pragma unroll
-        for (int tc = 0; tc < 4; ++tc) bf[tc] = Bs[buf][wide_slot(128 * wc + 32 * tc + lc, g)];
-#pragma unroll
-        for (int tr = 0; tr < 2; ++tr)
-#pragma unroll
-          for (int tc = 0; tc < 4; ++tc) acc[tr][tc] = wide_mfma<OPK>(af[tr], bf[tc], acc[tr][tc]);
-      }
-      // the other slice buffer was last read before the previous barrier
-      if (kc + 1 < nkc) DCG_WIDE_LSTORE(buf ^ 1);
-      __syncthreads();
+    DCG_WIDE_ISSUE(St0, 0);
+    if (1 < nkc) DCG_WIDE_ISSUE(St1, 1);
+    if (2 < nkc) DCG_WIDE_ISSUE(St2, 2);
+    for (int kc = 0; kc < nkc; kc += 4) {
+      DCG_WIDE_STEP(St0, St3, kc);
+      if (kc + 1 < nkc) DCG_WIDE_STEP(St1, St0, kc + 1);
+      if (kc + 2 < nkc) DCG_WIDE_STEP(St2, St1, kc + 2);
+      if (kc + 3 < nkc) DCG_WIDE_STEP(St3, St2, kc + 3);
     }
-#undef DCG_WIDE_GLOAD
-#undef DCG_WIDE_LSTORE
+#undef DCG_WIDE_ISSUE
+#undef DCG_WIDE_COMPUTE
+#undef DCG_WIDE_STEP
 
     // kernel values on the MFMA output layout: lane l holds column l % 32
     // and rows 8 (v / 4) + 4 (l / 32) + v % 4 of each 32x32 tile
