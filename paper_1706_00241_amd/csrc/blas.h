@@ -81,6 +81,9 @@ struct CgArgs {
   double *x, *r, *p, *q;
   float *p32;
   const double *W, *AW, *Minv;
+  // FP32 copies of W and AW (exactly W's and AW's values), read instead of
+  // them by cg_update_xr and cg_update_p when set
+  const float *W32 = nullptr, *AW32 = nullptr;
   const double *N;  // (AW)^T AW, k x k
   int k;
   double *Z, *AZ;   // storage of p_j / A p_j for j < L at column koff + j
@@ -154,6 +157,8 @@ void enqueue_implicit_aw_coef(hipStream_t s, const ImplicitHist &h, const double
                               int kout, double *S1, double *S2);
 void enqueue_block_axpy(hipStream_t s, double *Y, const double *X, double alpha, int64_t count);
 void enqueue_round_to_fp32(hipStream_t s, double *Y, int64_t count);
+// Y32 = (float) Y, element-wise.
+void enqueue_to_float(hipStream_t s, const double *Y, float *Y32, int64_t count);
 void enqueue_small_spd_inverse(hipStream_t s, const double *M, int k, double *Minv, double *work,
                                int *info);
 void enqueue_harmonic_ritz(hipStream_t s, const double *F, const double *G, int m, int k,

@@ -206,23 +206,39 @@ __device__ __forceinline__ void cg_update_xr_body(const CgArgs &a, const unsigne
   const int64_t i0 = int64_t(rb) * kXrRows + threadIdx.x;
   // This block's rows of r, q and of its kXrCols columns of [AW | W] do not
   // depend on alpha: load them first, so that the reduction of d below runs
-  // while they are in flight.
+  // while they are in flight.  With a basis (k >= 1) the loads are
+  // unconditional (rows past n and columns past 2k read row n - 1 / the
+  // first column of W, which exists) so that none of them waits for another;
+  // the out-of-range values are zeroed after the fact.  Without one (plain
+  // CG: W and AW are null) no column is read.
   double rv[RPT], qv[RPT];
   double yv[kXrCols][RPT];
+  float yf[kXrCols][RPT];
+  int64_t ii[RPT];
 #pragma unroll
   for (int u = 0; u < RPT; ++u) {
     const int64_t i = i0 + 256 * u;
-    rv[u] = (i < a.n) ? a.r[i] : 0.0;
-    qv[u] = (i < a.n) ? a.q[i] : 0.0;
+    ii[u] = (i < a.n) ? i : a.n - 1;
+    rv[u] = a.r[ii[u]];
+    qv[u] = a.q[ii[u]];
   }
+  if (k > 0 && a.W32 != nullptr) {
 #pragma unroll
-  for (int cc = 0; cc < kXrCols; ++cc) {
-    const int c = grp * kXrCols + cc;
-    const double *Y = (c < k) ? a.AW + int64_t(c) * a.n : a.W + int64_t(c - k) * a.n;
+    for (int cc = 0; cc < kXrCols; ++cc) {
+      const int c = grp * kXrCols + cc;
+      const float *Y = (c < k) ? a.AW32 + int64_t(c) * a.n
+                               : a.W32 + int64_t(c < 2 * k ? c - k : 0) * a.n;
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      const int64_t i = i0 + 256 * u;
-      yv[cc][u] = (c < 2 * k && i < a.n) ? Y[i] : 0.0;
+      for (int u = 0; u < RPT; ++u) yf[cc][u] = Y[ii[u]];
+    }
+  } else if (k > 0) {
+#pragma unroll
+    for (int cc = 0; cc < kXrCols; ++cc) {
+      const int c = grp * kXrCols + cc;
+      const double *Y = (c < k) ? a.AW + int64_t(c) * a.n
+                                : a.W + int64_t(c < 2 * k ? c - k : 0) * a.n;
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) yv[cc][u] = Y[ii[u]];
     }
   }
   const double d = block_sum_array(a.part, a.nblk_q, lds);
@@ -254,6 +270,15 @@ __device__ __forceinline__ void cg_update_xr_body(const CgArgs &a, const unsigne
     if (threadIdx.x == 0) a.part2[rb] = bad ? (isfinite(d) ? -1.0 : -2.0) : bs;
   }
   if (k == 0) return;
+#pragma unroll
+  for (int cc = 0; cc < kXrCols; ++cc) {
+    const bool colok = grp * kXrCols + cc < 2 * k;
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const double y = (a.W32 != nullptr) ? static_cast<double>(yf[cc][u]) : yv[cc][u];
+      yv[cc][u] = (colok && i0 + 256 * u < a.n) ? y : 0.0;
+    }
+  }
   // partial dots with kXrCols columns of [AW | W]
   double sv[kXrCols];
 #pragma unroll
@@ -302,18 +327,40 @@ __device__ __forceinline__ void cg_finalize_body(const CgArgs &a) {
   const int jstep = S->iter;   // read before thread 0 advances it below
   const bool record = a.hist_rho != nullptr && jstep < a.L;
   if (threadIdx.x == 0) flag = 0;
-  // the small matrices come in (coalesced) while the partials are summed
+  // Every load is issued before the first barrier, so that one memory
+  // latency covers them all: the rows of M^-1 and N into LDS (coalesced),
+  // this thread's share of the rho partials (a negative partial marks
+  // p^T A p <= 0 (-1) or non-finite (-2)), and, for threads c < 2k, column
+  // c of the [h | g] partials into eight accumulators (acc[u] sums the
+  // entries u, u + 8, u + 16, ... in order; the outer loop is unrolled so
+  // that several rounds of loads are in flight, not to change that order).
   for (int e = threadIdx.x; e < k * k; e += 256) {
     const int r = e / k, c = e % k;
     Ms[r * (kMaxK + 1) + c] = a.Minv[e];
     Ns[r * (kMaxK + 1) + c] = a.N[e];
   }
-  __syncthreads();
-  // a negative partial marks p^T A p <= 0 (-1) or non-finite (-2)
+  double rr = 0.0;
+  int fl = 0;
   for (int64_t b = threadIdx.x; b < nblk; b += 256) {
     const double v = a.part2[b];
-    if (v < 0.0) atomicMax(&flag, v < -1.5 ? 2 : 1);
+    if (v < 0.0) fl = max(fl, v < -1.5 ? 2 : 1);
+    rr += v;
   }
+  const int m2 = 2 * k;
+  double csum = 0.0;
+  if (threadIdx.x < m2) {
+    const double *pc = a.part_h + int64_t(threadIdx.x) * nblk;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t b = 0;
+#pragma unroll 8
+    for (; b + 8 <= nblk; b += 8)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += pc[b + u];
+    for (; b < nblk; ++b) acc[0] += pc[b];
+    csum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  }
+  __syncthreads();   // flag's initial value is visible to every thread
+  if (fl != 0) atomicMax(&flag, fl);
   __syncthreads();
   if (flag != 0) {
     if (threadIdx.x == 0) {
@@ -322,18 +369,8 @@ __device__ __forceinline__ void cg_finalize_body(const CgArgs &a) {
     }
     return;
   }
-  // column sums of [h | g]: thread c sums its column with 8 accumulators
-  for (int c = threadIdx.x; c < 2 * k; c += 256) {
-    const double *pc = a.part_h + int64_t(c) * nblk;
-    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int64_t b = 0;
-    for (; b + 8 <= nblk; b += 8)
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] += pc[b + u];
-    for (; b < nblk; ++b) acc[0] += pc[b];
-    hg[c] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-  }
-  const double rho_raw = block_sum_array(a.part2, nblk, lds);   // includes barriers
+  if (threadIdx.x < m2) hg[threadIdx.x] = csum;
+  const double rho_raw = block_sum_all(rr, lds);   // includes barriers
   small_gemv_lds(Ms, hg + k, cv, k);
   __syncthreads();
   small_gemv_lds(Ns, cv, nc, k);
@@ -398,11 +435,20 @@ __device__ __forceinline__ void cg_update_p_body(const CgArgs &a, const unsigned
   double xn = a.x[i] + alpha * pi;
   double xi = 0.0;
   double wmu = 0.0;
-  for (int c = 0; c < a.k; ++c) {
-    const double wv = a.W[int64_t(c) * a.n + i];
-    ri -= a.AW[int64_t(c) * a.n + i] * cv[c];
-    xi += wv * cv[c];
-    wmu += wv * mu[c];
+  if (a.W32 != nullptr) {
+    for (int c = 0; c < a.k; ++c) {
+      const double wv = static_cast<double>(a.W32[int64_t(c) * a.n + i]);
+      ri -= static_cast<double>(a.AW32[int64_t(c) * a.n + i]) * cv[c];
+      xi += wv * cv[c];
+      wmu += wv * mu[c];
+    }
+  } else {
+    for (int c = 0; c < a.k; ++c) {
+      const double wv = a.W[int64_t(c) * a.n + i];
+      ri -= a.AW[int64_t(c) * a.n + i] * cv[c];
+      xi += wv * cv[c];
+      wmu += wv * mu[c];
+    }
   }
   if (a.k > 0) xn += xi;
   a.r[i] = ri;
@@ -664,6 +710,11 @@ __global__ __launch_bounds__(256) void round_to_fp32(double *Y, int64_t count) {
   if (e < count) Y[e] = static_cast<double>(static_cast<float>(Y[e]));
 }
 
+__global__ __launch_bounds__(256) void to_float(const double *Y, float *Y32, int64_t count) {
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e < count) Y32[e] = static_cast<float>(Y[e]);
+}
+
 // Symmetrise M (k x k, row-major), Cholesky M = R R^T, Minv = M^{-1}.
 // One block.  info = 0 on success; 2 if M holds a NaN or Inf; 1 if a pivot
 // is at most kRankTol times the diagonal entry it started from (the square
@@ -758,6 +809,12 @@ void enqueue_block_axpy(hipStream_t s, double *Y, const double *X, double alpha,
   if (count <= 0) return;
   hipLaunchKernelGGL(block_axpy, dim3(static_cast<unsigned>(cdiv(count, 256))), dim3(256), 0, s, Y,
                      X, alpha, count);
+}
+
+void enqueue_to_float(hipStream_t s, const double *Y, float *Y32, int64_t count) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(to_float, dim3(static_cast<unsigned>(cdiv(count, 256))), dim3(256), 0, s, Y,
+                     Y32, count);
 }
 
 void enqueue_round_to_fp32(hipStream_t s, double *Y, int64_t count) {

@@ -211,6 +211,8 @@ int dcg::solve_block_impl(dcg_op_t op, const double *B, double *X, int64_t m, dc
     a.p32 = P32 + c * n_pad;
     a.W = k > 0 ? rc->Z : nullptr;
     a.AW = k > 0 ? rc->AZ : nullptr;
+    a.W32 = (k > 0 && rc->w32_valid) ? rc->W32 : nullptr;
+    a.AW32 = (k > 0 && rc->w32_valid) ? rc->AW32 : nullptr;
     a.Minv = k > 0 ? rc->Minv : nullptr;
     a.N = k > 0 ? rc->N : nullptr;
     a.k = k;

@@ -159,6 +159,9 @@ struct dcg_recycle_s {
   double *small;         // misc small device scalars / vectors
   int *info;             // device status words of the extraction
   double *gemm;          // split-K partials of the tall-skinny products
+  float *W32, *AW32;     // n x k: FP32 copies of W and AW for the per-step
+                         // kernels of low-precision operators (w32_valid)
+  int w32_valid;
   uint64_t w_version;    // bumped whenever W or AW changes
   uint64_t m_version;    // w_version when M, N, M^{-1} were formed
   int m_valid;

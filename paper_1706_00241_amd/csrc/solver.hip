@@ -75,7 +75,7 @@ size_t solve_workspace_total(int64_t n, bool refine) {
 }
 
 struct RecycleLayout {
-  size_t Z, AZ, Wt, AWt, F, G, U, eigw, M, Minv, Mwork, N, small, info, gemm, total;
+  size_t Z, AZ, Wt, AWt, W32, AW32, F, G, U, eigw, M, Minv, Mwork, N, small, info, gemm, total;
 };
 
 static RecycleLayout recycle_layout(int64_t n, int k, int L) {
@@ -92,6 +92,8 @@ static RecycleLayout recycle_layout(int64_t n, int k, int L) {
   R.AZ = take(size_t(n) * kz * 8);
   R.Wt = take(size_t(n) * k * 8);
   R.AWt = take(size_t(n) * k * 8);
+  R.W32 = take(size_t(n) * k * 4);
+  R.AW32 = take(size_t(n) * k * 4);
   R.F = take(size_t(kMaxZ) * kMaxZ * 8);
   R.G = take(size_t(kMaxZ) * kMaxZ * 8);
   R.U = take(size_t(kMaxZ) * kMaxK * 8);
@@ -174,9 +176,29 @@ int deflation_setup(dcg_operator_s *op, dcg_recycle_s *rc, int *matvecs) {
   if (rc->m_valid && rc->m_version == rc->w_version) return DCG_OK;
   hipStream_t s = op->stream;
   const int64_t n = rc->n;
+  // With bf16 or fp16 points (8 or 11 significant bits: the operator is off
+  // the kernel matrix by ~1e-3 relative) the per-step kernels read FP32
+  // copies of W and AW, half the bytes of the two passes over them each
+  // step.  W and AW are rounded to FP32 values first, so that M, N and
+  // every later use see exactly the values the copies hold.  Not for FP32
+  // or split-bf16 points, whose solves run to 1e-6 on the operator itself
+  // (there the rounding added steps: 219 -> 224 on the 16384-point walk),
+  // and not with a diagonal scaling, where the sweep multiplies fp32(D w)
+  // rather than fp32(w) and W keeps its FP64 values (as in refresh_AW).
+  const bool lowprec =
+      (op->g.prec == DCG_PREC_BF16 || op->g.prec == DCG_PREC_FP16) && !op->has_dsc;
+  if (lowprec) {
+    enqueue_round_to_fp32(s, rc->Z, n * k);
+    enqueue_round_to_fp32(s, rc->AZ, n * k);
+  }
   enqueue_tsgemm_tn(s, rc->Z, rc->AZ, n, k, k, rc->gemm, kGemmPartDoubles, rc->M, k, 1);
   enqueue_tsgemm_tn(s, rc->AZ, rc->AZ, n, k, k, rc->gemm, kGemmPartDoubles, rc->N, k, 1);
   enqueue_small_spd_inverse(s, rc->M, k, rc->Minv, rc->Mwork, rc->info);
+  rc->w32_valid = 0;
+  if (lowprec) {
+    enqueue_to_float(s, rc->Z, rc->W32, n * k);
+    enqueue_to_float(s, rc->AZ, rc->AW32, n * k);
+  }
   int info = 0;
   HIPCHK(hipMemcpyAsync(&info, rc->info, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -186,6 +208,7 @@ int deflation_setup(dcg_operator_s *op, dcg_recycle_s *rc, int *matvecs) {
   if (info != 0) return DCG_E_W_RANK;
   rc->m_valid = 1;
   rc->m_version = rc->w_version;
+  rc->w32_valid = lowprec ? 1 : 0;
   return DCG_OK;
 }
 
@@ -204,6 +227,10 @@ static CgArgs cg_args(dcg_operator_s *op, const SolveBuffers &B, double *x, dcg_
   a.p32 = op->vin;
   a.W = rc ? rc->Z : nullptr;
   a.AW = rc ? rc->AZ : nullptr;
+  if (rc != nullptr && k > 0 && rc->w32_valid) {
+    a.W32 = rc->W32;
+    a.AW32 = rc->AW32;
+  }
   a.Minv = Minv;
   a.N = rc ? rc->N : nullptr;
   a.k = k;
@@ -885,6 +912,8 @@ int dcg_recycle_create(int64_t n, int k, int L, void *workspace, size_t ws_bytes
   rc->small = reinterpret_cast<double *>(b + R.small);
   rc->info = reinterpret_cast<int *>(b + R.info);
   rc->gemm = reinterpret_cast<double *>(b + R.gemm);
+  rc->W32 = reinterpret_cast<float *>(b + R.W32);
+  rc->AW32 = reinterpret_cast<float *>(b + R.AW32);
   *out = rc;
   return DCG_OK;
 }
