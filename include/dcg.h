@@ -229,10 +229,13 @@ int dcg_set_sweep_items(dcg_op_t op, int items);
 
 /* Autotuner of the sweep plans: times `reps` single-vector sweeps (1..1000)
  * for each distinct plan of the targets 256, 512, ..., 8192 on the
- * operator's stream, keeps the fastest and returns it in *items_out with its
- * time per sweep in *ms_out (either may be NULL); the FP64 sweep (refinement
- * residuals, FP64 operators) gets its own plan the same way, timed reps / 4
- * times (for an FP64 operator *items_out and *ms_out describe that one).
+ * operator's stream, keeps the fastest (a larger target replaces a smaller
+ * one only when it is more than 1% faster, so that timing noise does not
+ * pick between nearly equal plans, which differ in the summation order of
+ * the partial sums) and returns it in *items_out with its time per sweep in
+ * *ms_out (either may be NULL); the FP64 sweep (refinement residuals, FP64
+ * operators) gets its own plan the same way, timed max(2, reps / 2) times
+ * (for an FP64 operator *items_out and *ms_out describe that one).
  * Overwrites the operator's staged vectors and partial sums, so it must not
  * overlap a solve with the same operator. */
 int dcg_tune_operator(dcg_op_t op, int reps, int *items_out, double *ms_out);

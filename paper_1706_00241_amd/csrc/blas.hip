@@ -334,18 +334,20 @@ __device__ __forceinline__ void cg_finalize_body(const CgArgs &a) {
   // c of the [h | g] partials into eight accumulators (acc[u] sums the
   // entries u, u + 8, u + 16, ... in order; the outer loop is unrolled so
   // that several rounds of loads are in flight, not to change that order).
-  for (int e = threadIdx.x; e < k * k; e += 256) {
-    const int r = e / k, c = e % k;
-    Ms[r * (kMaxK + 1) + c] = a.Minv[e];
-    Ns[r * (kMaxK + 1) + c] = a.N[e];
+  // (the loads are unconditional, with clamped indices, so that none waits
+  // for another; only in-range values are kept)
+  constexpr int kStage = kMaxK * kMaxK / 256;
+  const int kk = k * k;
+  double mv[kStage], nv[kStage];
+  if (kk > 0) {
+#pragma unroll
+    for (int t = 0; t < kStage; ++t) {
+      const int e = min(static_cast<int>(threadIdx.x) + 256 * t, kk - 1);
+      mv[t] = a.Minv[e];
+      nv[t] = a.N[e];
+    }
   }
-  double rr = 0.0;
-  int fl = 0;
-  for (int64_t b = threadIdx.x; b < nblk; b += 256) {
-    const double v = a.part2[b];
-    if (v < 0.0) fl = max(fl, v < -1.5 ? 2 : 1);
-    rr += v;
-  }
+  const double v0 = a.part2[min(static_cast<int64_t>(threadIdx.x), nblk - 1)];
   const int m2 = 2 * k;
   double csum = 0.0;
   if (threadIdx.x < m2) {
@@ -358,6 +360,28 @@ __device__ __forceinline__ void cg_finalize_body(const CgArgs &a) {
       for (int u = 0; u < 8; ++u) acc[u] += pc[b + u];
     for (; b < nblk; ++b) acc[0] += pc[b];
     csum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  }
+  double rr = 0.0;
+  int fl = 0;
+  if (threadIdx.x < nblk) {
+    if (v0 < 0.0) fl = v0 < -1.5 ? 2 : 1;
+    rr = v0;
+  }
+  for (int64_t b = threadIdx.x + 256; b < nblk; b += 256) {
+    const double v = a.part2[b];
+    if (v < 0.0) fl = max(fl, v < -1.5 ? 2 : 1);
+    rr += v;
+  }
+  if (kk > 0) {
+#pragma unroll
+    for (int t = 0; t < kStage; ++t) {
+      const int e = static_cast<int>(threadIdx.x) + 256 * t;
+      if (e < kk) {
+        const int r = e / k, c = e % k;
+        Ms[r * (kMaxK + 1) + c] = mv[t];
+        Ns[r * (kMaxK + 1) + c] = nv[t];
+      }
+    }
   }
   __syncthreads();   // flag's initial value is visible to every thread
   if (fl != 0) atomicMax(&flag, fl);
