@@ -57,19 +57,33 @@ PEAK_DP_SLOTS = 256 * 64 * 2.4e9
 # WRITE_SIZE (scaled by a 256 MiB copy) for this workload, valid while the
 # sweep's source is the one the counters were taken from (its SHA-256 prefix);
 # None for any other configuration or source.
-SWEEP_TRAFFIC = {("bf16", 65536, 32, 2, 8192): (112.7e6, None)}
+SWEEP_TRAFFIC = {("bf16", 65536, 32, 2, 8192): (112.6e6, "be188e5c358a333e")}
+# the same for the wide pair sweep (bf16 points, GPC pixel workload), keyed by
+# (points, n, d) and valid for the source of csrc/wide.hip it was taken from
+WIDE_TRAFFIC = {("bf16", 36551, 784): (4938.7e6, "ad0f4075ca14a375")}
+
+
+def _source_sha(name):
+    import hashlib
+    src = os.path.join(ROOT, "paper_1706_00241_amd", "csrc", name)
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def sweep_traffic(prec, n, d, kernel, items):
-    import hashlib
     entry = SWEEP_TRAFFIC.get((prec, n, d, kernel, items))
     if entry is None:
         return None
     value, sha = entry
-    src = os.path.join(ROOT, "paper_1706_00241_amd", "csrc", "matvec.hip")
-    with open(src, "rb") as f:
-        now = hashlib.sha256(f.read()).hexdigest()[:16]
-    return value if sha is not None and now == sha else None
+    return value if sha is not None and _source_sha("matvec.hip") == sha else None
+
+
+def wide_traffic(points, n, d):
+    entry = WIDE_TRAFFIC.get((points, n, d))
+    if entry is None:
+        return None
+    value, sha = entry
+    return value if _source_sha("wide.hip") == sha else None
 
 
 def parse():
@@ -499,7 +513,10 @@ def main_gpc(args):
         tf = flops / (t * 1e-3) / 1e12
         out["product_ms"] = round(t, 4)
         out["roofline"] = {"bound": "mfma", "achieved": round(tf, 1), "peak": 2500.0,
-                           "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4), "traffic": None,
+                           "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4),
+                           "traffic": wide_traffic(args.gpc_points, n, d),
+                           "traffic_unit": "bytes per launch of symv_wide_kernel (rocprofv3 "
+                                           "FETCH_SIZE + WRITE_SIZE)",
                            "per_launch": f"{n * (n - 1) // 2:.3e} unique pairs x 2 d flops"}
     if not args.no_plain:
         prow = [run(None) for _ in range(max(1, min(args.steps, 3)))]
