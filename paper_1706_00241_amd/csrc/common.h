@@ -98,8 +98,22 @@ constexpr int kSweepItemsDefault = 2048;
 constexpr int kSweepItemsMax = 8192;
 
 MatvecPlan make_plan(int64_t n_pad, int blk, int items = kSweepItemsDefault);
+// The wide sweep's tiled schedule (256-point blocks): groups of kWideGroup
+// row blocks; tile (group, part) is kWideGroup x 4 work items (a, b), item
+// (a, b) taking row block I = kWideGroup g + a and the pairs (I, I + u),
+// u = 4 s + b - a in [0, ndel(I)), for the steps s of its part.  At a step
+// the 32 items of a tile touch 8 row blocks and 4 column blocks, which they
+// share in one XCD's L2.  Fields: chunk = steps per part, nchunk = 4 x parts
+// (row-partial slots per row block: slot 4 part + b), grid = the tiles, padded
+// to a multiple of 8, times 32.
+constexpr int kWideGroup = 8;
+MatvecPlan wide_plan(int64_t n_pad, int items);
+int wide_steps(int nb);   // steps s per row block group
+// The plan of the operator's single-vector (mv = 1) or four-vector sweep.
+MatvecPlan sweep_plan(const Geometry &g, int mv, int items);
 // Partial-sum floats of a sweep, for the largest plan any item target gives.
 size_t matvec_partial_floats(int64_t n_pad, int mv, int blk);
+size_t wide_partial_floats(int64_t n_pad);
 
 }  // namespace dcg
 

@@ -70,6 +70,40 @@ MatvecPlan make_plan(int64_t n_pad, int blk, int items) {
   return p;
 }
 
+int wide_steps(int nb) {
+  // u = 4 s + b - a must reach ndel - 1 <= nb / 2 for a = kWideGroup - 1
+  const int ndel_max = nb / 2 + 1;
+  return static_cast<int>(cdiv(int64_t(ndel_max) + kWideGroup - 1, 4));
+}
+
+MatvecPlan wide_plan(int64_t n_pad, int items) {
+  MatvecPlan p;
+  p.blk = 256;
+  p.nb = static_cast<int>(n_pad / p.blk);
+  p.dmax = p.nb / 2;
+  const int S = wide_steps(p.nb);
+  const int64_t groups = cdiv(p.nb, kWideGroup);
+  // parts so that the sweep has about `items` work items of 32 per tile
+  const int64_t want = std::max<int64_t>(1, items / (32 * groups));
+  const int parts0 = static_cast<int>(std::min<int64_t>(want, S));
+  p.chunk = static_cast<int>(cdiv(S, parts0));
+  const int parts = static_cast<int>(cdiv(S, p.chunk));
+  p.nchunk = 4 * parts;
+  p.grid = cdiv(groups * parts, 8) * 8 * 32;
+  return p;
+}
+
+MatvecPlan sweep_plan(const Geometry &g, int mv, int items) {
+  if (sweep_wide(g)) return wide_plan(g.n_pad, items);
+  return make_plan(g.n_pad, sweep_blk(g, mv), items);
+}
+
+size_t wide_partial_floats(int64_t n_pad) {
+  // the most slots: one part per step
+  const int nb = static_cast<int>(n_pad / 256);
+  return size_t(2 * 4 * wide_steps(nb) + nb / 2) * size_t(n_pad);
+}
+
 size_t matvec_partial_floats(int64_t n_pad, int mv, int blk) {
   // chunks per row block grow with the item target
   MatvecPlan p = make_plan(n_pad, blk, kSweepItemsMax);

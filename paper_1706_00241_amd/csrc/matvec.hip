@@ -362,7 +362,7 @@ static int dispatch_ks(const dcg_operator_s *op, const SymvArgs &a, int64_t grid
 // vectors) and its grid.
 SymvArgs symv_args(const dcg_operator_s *op, int mv, const float *vin, const int *done,
                    int64_t *grid) {
-  MatvecPlan p = make_plan(op->g.n_pad, sweep_blk(op->g, mv), op->sweep_items);
+  MatvecPlan p = sweep_plan(op->g, mv, op->sweep_items);
   SymvArgs a;
   a.xr = op->xr;
   a.xc = op->xc;
@@ -447,7 +447,7 @@ int launch_symv_sweep(const dcg_operator_s *op, int mv, const int *done) {
 }
 
 ReduceArgs reduce_args(const dcg_operator_s *op, int mv, const double *V, double *Y) {
-  MatvecPlan p = make_plan(op->g.n_pad, sweep_blk(op->g, mv), op->sweep_items);
+  MatvecPlan p = sweep_plan(op->g, mv, op->sweep_items);
   ReduceArgs r;
   r.prow = reinterpret_cast<const double *>(op->part);
   r.pcol = op->part + size_t(2 * p.nchunk) * op->g.n_pad * mv;

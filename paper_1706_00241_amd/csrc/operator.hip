@@ -333,7 +333,9 @@ static OpLayout op_layout(const Geometry &g) {
   L.xc = c.off = align256(c.off); c.off += size_t(g.n_pad) * g.kstride * esz;
   L.vin = c.off = align256(c.off); c.off += size_t(g.n_pad) * 4 * 4;
   L.part = c.off = align256(c.off);
-  if (g.prec != DCG_PREC_FP64 && !stored)
+  if (sweep_wide(g))
+    c.off += wide_partial_floats(g.n_pad) * 4;
+  else if (g.prec != DCG_PREC_FP64 && !stored)
     c.off += std::max(matvec_partial_floats(g.n_pad, 1, sweep_blk(g, 1)),
                       matvec_partial_floats(g.n_pad, 4, sweep_blk(g, 4))) * 4;
   L.ytmp = c.off = align256(c.off); c.off += size_t(g.n_pad) * 4 * 8;
@@ -580,7 +582,7 @@ int dcg_tune_operator(dcg_op_t op, int reps, int *items_out, double *ms_out) {
       return DCG_E_HIP;
     st = tune_field(
         s, reps, &op->sweep_items,
-        [&](int items) { return make_plan(op->g.n_pad, sweep_blk(op->g, 1), items); },
+        [&](int items) { return sweep_plan(op->g, 1, items); },
         [&]() { return launch_symv_sweep(op, 1, nullptr); }, &best, &ms);
     if (st != DCG_OK) return st;
   } else {

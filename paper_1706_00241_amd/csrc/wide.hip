@@ -3,19 +3,21 @@
 // when the distance contraction, not the kernel evaluation, dominates the
 // pair cost (2 (d + 6) MFMA flops against ~10 VALU slots per pair).
 //
-// Same circulant schedule of 256-point block pairs, work items and partial
-// layout as the narrow sweep (matvec.hip), so the product is finished by the
-// same kernels.  A work item (one 512-thread workgroup, eight waves) takes a
-// row block I and a run of offsets; for each block pair (I, J) the augmented
-// operands of both blocks stream through LDS in 64-element slices of K
-// (double-buffered: the next slice's global loads are in flight while the
-// current one feeds the matrix cores), each wave accumulating a 64 x 128
+// The same 256-point block pairs and partial layout as the narrow sweep
+// (matvec.hip), so the product is finished by the same kernels, under a
+// tiled schedule (wide_plan): a work item (one 512-thread workgroup, eight
+// waves) takes a row block I of a group of eight and every fourth block
+// offset of a range, so that the 32 items of a tile, run together on one
+// XCD, touch eight row and four column blocks at a time and share them in
+// its L2.  For each block pair (I, J) the augmented operands of both blocks
+// stream through LDS in 32-element slices of K (four stages filled three
+// ahead by direct global-to-LDS loads), each wave accumulating a 64 x 128
 // part of the 256 x 256 distance tile in eight 32x32x16 MFMA tiles.  The
 // slices are stored with the 16-byte groups of a row XOR-swizzled by the row
 // index, so that the rows a fragment read serves together fall in distinct
-// LDS banks.  After the last slice the kernel values are formed in registers on
-// the MFMA output layout and folded into FP32 row sums (accumulated in LDS
-// across the work item's block pairs) and per-block-pair column sums.
+// LDS banks.  After the last slice the kernel values are formed in registers
+// on the MFMA output layout and folded into FP32 row sums (accumulated in
+// LDS across the work item's block pairs) and per-block-pair column sums.
 #include <algorithm>
 #include <cmath>
 
@@ -32,6 +34,9 @@ constexpr int kWideSlots = kWideRows * 4;   // 16-byte slots of one operand in a
 // s_waitcnt immediates that wait for the vector-memory counter only
 // (vmcnt in bits 3:0, expcnt 6:4 and lgkmcnt 11:8 left at their maxima)
 constexpr int kVmcnt0 = 0xF70, kVmcnt4 = 0xF74, kVmcnt8 = 0xF78;
+// ... and the one that waits for the LDS / scalar-memory counter only
+// (lgkmcnt 0, vmcnt and expcnt at their maxima)
+constexpr int kLgkm0 = 0xC07F;
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
@@ -47,6 +52,21 @@ __device__ __forceinline__ f32x16 wide_mfma(const u32x4 &a, const u32x4 &b, cons
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
+// A barrier for LDS traffic only: this wave's LDS accesses are complete
+// (lgkmcnt), the global loads in flight are not waited for (the release
+// fence of __syncthreads would); the empty asm statements keep the compiler
+// from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(kLgkm0);
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Steps per row block group of the tiled schedule (as wide_steps on the
+// host).
+__device__ __forceinline__ int wide_steps_dev(int nb) { return (nb / 2 + 1 + kWideGroup - 1 + 3) / 4; }
+
 // Slot of the 16-byte group g (0..3) of row `row` in a stage (64-byte rows).
 // A fragment read takes group g of 32 consecutive rows, served 16 lanes at a
 // time over 256 bytes of banks: rows r and r + 4 share those bytes' quarter,
@@ -59,13 +79,23 @@ __device__ __forceinline__ int wide_slot(int row, int g) {
 template <int KERN, int OPK>
 __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
   if (A.done != nullptr && *A.done != 0) return;
-  const int64_t item = xcd_remap(blockIdx.x, int64_t(A.nb) * A.nchunk);
-  const int I = static_cast<int>(item / A.nchunk);
-  const int c = static_cast<int>(item % A.nchunk);
+  // Tiles are dealt to the XCDs round-robin (workgroup w goes to XCD w mod
+  // 8), each XCD running its tiles' 32 work items back to back, so that the
+  // items that share a tile's blocks share an L2.
   const int nb = A.nb;
+  const int parts = A.nchunk / 4;
+  const int64_t tiles = int64_t((nb + kWideGroup - 1) / kWideGroup) * parts;
+  const int64_t j = blockIdx.x >> 3;
+  const int64_t tile = (j >> 5) * 8 + (blockIdx.x & 7);
+  if (tile >= tiles) return;
+  const int grp = static_cast<int>(tile / parts), part = static_cast<int>(tile % parts);
+  const int ia = static_cast<int>((j & 31) >> 2), ib = static_cast<int>(j & 3);
+  const int I = kWideGroup * grp + ia;
+  if (I >= nb) return;
   const int ndel = ((nb % 2) == 0 && I >= nb / 2) ? A.dmax : A.dmax + 1;
-  const int d0 = c * A.chunk;
-  const int d1 = min(d0 + A.chunk, ndel);
+  const int s0 = part * A.chunk;
+  const int s1 = min(s0 + A.chunk, wide_steps_dev(nb));
+  const int c = 4 * part + ib;   // this item's row-partial slot
 
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, lc = l & 31, lh = l >> 5;
@@ -120,69 +150,102 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
     __builtin_amdgcn_global_load_lds((global_void *)(src + go3),                             \
                                      (lds_void *)&BUF[dst0 + 192], 16, 0, 0);                \
   } while (0)
+#define DCG_WIDE_MFMAS(a0, a1, b0, b1, b2, b3)                                               \
+  acc[0][0] = wide_mfma<OPK>(a0, b0, acc[0][0]);                                             \
+  acc[0][1] = wide_mfma<OPK>(a0, b1, acc[0][1]);                                             \
+  acc[0][2] = wide_mfma<OPK>(a0, b2, acc[0][2]);                                             \
+  acc[0][3] = wide_mfma<OPK>(a0, b3, acc[0][3]);                                             \
+  acc[1][0] = wide_mfma<OPK>(a1, b0, acc[1][0]);                                             \
+  acc[1][1] = wide_mfma<OPK>(a1, b1, acc[1][1]);                                             \
+  acc[1][2] = wide_mfma<OPK>(a1, b2, acc[1][2]);                                             \
+  acc[1][3] = wide_mfma<OPK>(a1, b3, acc[1][3])
+#define DCG_WIDE_FRAGS(BUF, g, a0, a1, b0, b1, b2, b3)                                       \
+  const u32x4 a0 = BUF[wide_slot(64 * wr + lc, g)];                                          \
+  const u32x4 a1 = BUF[wide_slot(64 * wr + 32 + lc, g)];                                     \
+  const u32x4 b0 = BUF[kWideSlots + wide_slot(128 * wc + lc, g)];                            \
+  const u32x4 b1 = BUF[kWideSlots + wide_slot(128 * wc + 32 + lc, g)];                       \
+  const u32x4 b2 = BUF[kWideSlots + wide_slot(128 * wc + 64 + lc, g)];                       \
+  const u32x4 b3 = BUF[kWideSlots + wide_slot(128 * wc + 96 + lc, g)]
+// both K-steps' fragments are read before the first MFMA (the scheduling
+// barrier keeps the compiler from sinking the reads to their uses), so that
+// all twelve reads are in flight together
 #define DCG_WIDE_COMPUTE(BUF)                                                                \
   do {                                                                                       \
-    _Pragma("unroll") for (int ks = 0; ks < kWideKC / 16; ++ks) {                            \
-      const int g = 2 * ks + lh;                                                             \
-      const u32x4 a0 = BUF[wide_slot(64 * wr + lc, g)];                                      \
-      const u32x4 a1 = BUF[wide_slot(64 * wr + 32 + lc, g)];                                 \
-      const u32x4 b0 = BUF[kWideSlots + wide_slot(128 * wc + lc, g)];                        \
-      const u32x4 b1 = BUF[kWideSlots + wide_slot(128 * wc + 32 + lc, g)];                   \
-      const u32x4 b2 = BUF[kWideSlots + wide_slot(128 * wc + 64 + lc, g)];                   \
-      const u32x4 b3 = BUF[kWideSlots + wide_slot(128 * wc + 96 + lc, g)];                   \
-      acc[0][0] = wide_mfma<OPK>(a0, b0, acc[0][0]);                                         \
-      acc[0][1] = wide_mfma<OPK>(a0, b1, acc[0][1]);                                         \
-      acc[0][2] = wide_mfma<OPK>(a0, b2, acc[0][2]);                                         \
-      acc[0][3] = wide_mfma<OPK>(a0, b3, acc[0][3]);                                         \
-      acc[1][0] = wide_mfma<OPK>(a1, b0, acc[1][0]);                                         \
-      acc[1][1] = wide_mfma<OPK>(a1, b1, acc[1][1]);                                         \
-      acc[1][2] = wide_mfma<OPK>(a1, b2, acc[1][2]);                                         \
-      acc[1][3] = wide_mfma<OPK>(a1, b3, acc[1][3]);                                         \
-    }                                                                                        \
+    DCG_WIDE_FRAGS(BUF, lh, xa0, xa1, xb0, xb1, xb2, xb3);                                   \
+    DCG_WIDE_FRAGS(BUF, 2 + lh, ya0, ya1, yb0, yb1, yb2, yb3);                               \
+    __builtin_amdgcn_sched_barrier(0);                                                       \
+    DCG_WIDE_MFMAS(xa0, xa1, xb0, xb1, xb2, xb3);                                            \
+    DCG_WIDE_MFMAS(ya0, ya1, yb0, yb1, yb2, yb3);                                            \
   } while (0)
 // One stage s in buffer CUR: wait until this wave's loads of stage s have
 // landed (those of s + 1 and s + 2 may still be in flight: four loads per
-// stage, retired in order), then the barrier makes every wave's loads of s
+// stage, retired in order; at s = 0 everything, since the previous pair's
+// stores were issued after this pair's first loads and stores may retire
+// out of order with loads), then the barrier makes every wave's loads of s
 // visible and frees NXT (read at step s - 1, whose reads every wave has
 // waited for before its MFMAs) for stage s + 3.  A plain s_barrier: the
 // release fence of __syncthreads would wait for the loads still in flight
-// too; the empty asm statements keep the compiler from moving LDS accesses
-// across it.
+// too.
 #define DCG_WIDE_STEP(CUR, NXT, s)                                                           \
   do {                                                                                       \
-    if ((s) + 2 < nkc) __builtin_amdgcn_s_waitcnt(kVmcnt8);                                  \
+    if ((s) == 0) __builtin_amdgcn_s_waitcnt(kVmcnt0);                                       \
+    else if ((s) + 2 < nkc) __builtin_amdgcn_s_waitcnt(kVmcnt8);                             \
     else if ((s) + 1 < nkc) __builtin_amdgcn_s_waitcnt(kVmcnt4);                             \
     else __builtin_amdgcn_s_waitcnt(kVmcnt0);                                                \
-    asm volatile("" ::: "memory");                                                           \
-    __builtin_amdgcn_s_barrier();                                                            \
-    asm volatile("" ::: "memory");                                                           \
+    lds_barrier();                                                                           \
     if ((s) + 3 < nkc) DCG_WIDE_ISSUE(NXT, (s) + 3);                                         \
     DCG_WIDE_COMPUTE(CUR);                                                                   \
   } while (0)
 
-  for (int dl = d0; dl < d1; ++dl) {
+  // the first step at or after st whose pair this item owns (s1 if none)
+  auto next_valid = [&](int st) {
+    for (; st < s1; ++st) {
+      const int u = 4 * st + ib - ia;
+      if (u >= 0 && u < ndel) break;
+    }
+    return st;
+  };
+  auto base_of = [&](int st) {
+    int J = I + 4 * st + ib - ia;
+    if (J >= nb) J -= nb;
+    return opsel == 0 ? xr + int64_t(I) * kWideRows * kst : xc + int64_t(J) * kWideRows * kst;
+  };
+  int st = next_valid(s0);
+  const uint16_t *base = nullptr;
+  if (st < s1) {
+    base = base_of(st);
+    DCG_WIDE_ISSUE(St0, 0);
+    if (1 < nkc) DCG_WIDE_ISSUE(St1, 1);
+    if (2 < nkc) DCG_WIDE_ISSUE(St2, 2);
+  }
+  while (st < s1) {
+    const int dl = 4 * st + ib - ia;   // block offset of this step's pair
     int J = I + dl;
     if (J >= nb) J -= nb;
-    const uint16_t *base =
-        (opsel == 0 ? xr + int64_t(I) * kWideRows * kst : xc + int64_t(J) * kWideRows * kst);
     f32x16 acc[2][4];
 #pragma unroll
     for (int tr = 0; tr < 2; ++tr)
 #pragma unroll
       for (int tc = 0; tc < 4; ++tc) acc[tr][tc] = f32x16{};
-    // every wave is done with the previous block pair's stages and stores
-    __builtin_amdgcn_s_waitcnt(kVmcnt0);
-    __syncthreads();
-    DCG_WIDE_ISSUE(St0, 0);
-    if (1 < nkc) DCG_WIDE_ISSUE(St1, 1);
-    if (2 < nkc) DCG_WIDE_ISSUE(St2, 2);
     for (int kc = 0; kc < nkc; kc += 4) {
       DCG_WIDE_STEP(St0, St3, kc);
       if (kc + 1 < nkc) DCG_WIDE_STEP(St1, St0, kc + 1);
       if (kc + 2 < nkc) DCG_WIDE_STEP(St2, St1, kc + 2);
       if (kc + 3 < nkc) DCG_WIDE_STEP(St3, St2, kc + 3);
     }
+    // every wave is done reading this pair's stages: the next pair's first
+    // three stages load while this pair's epilogue runs
+    const int stn = next_valid(st + 1);
+    __syncthreads();
+    if (stn < s1) {
+      base = base_of(stn);
+      DCG_WIDE_ISSUE(St0, 0);
+      if (1 < nkc) DCG_WIDE_ISSUE(St1, 1);
+      if (2 < nkc) DCG_WIDE_ISSUE(St2, 2);
+    }
 #undef DCG_WIDE_ISSUE
+#undef DCG_WIDE_FRAGS
+#undef DCG_WIDE_MFMAS
 #undef DCG_WIDE_COMPUTE
 #undef DCG_WIDE_STEP
 
@@ -237,13 +300,14 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
         const float s = cs[tc] + __shfl_xor(cs[tc], 32);
         if (lh == 0) colpart[wr][128 * wc + 32 * tc + lc] = s;
       }
-      __syncthreads();
+      lds_barrier();
       for (int e = tid; e < kWideRows; e += 512) {
         const float s = (colpart[0][e] + colpart[1][e]) + (colpart[2][e] + colpart[3][e]);
         A.pcol[int64_t(dl - 1) * n_pad + int64_t(J) * kWideRows + e] = s;
       }
-      __syncthreads();
+      lds_barrier();
     }
+    st = stn;
   }
   __syncthreads();
   for (int e = tid; e < kWideRows; e += 512)
@@ -263,7 +327,7 @@ static void launch_wide_kernel(int kernel, const SymvArgs &a, int64_t grid, hipS
 int launch_symv_wide(const dcg_operator_s *op, const SymvArgs &a, int64_t grid) {
   const Geometry &g = op->g;
   if (!sweep_wide(g) || g.kstride % kWideKC != 0 || sweep_blk(g, 1) != kWideRows ||
-      g.n_pad % kWideRows != 0 || grid < 1)
+      g.n_pad % kWideRows != 0 || grid < 256 || grid % 256 != 0 || a.nchunk % 4 != 0)
     return DCG_E_ARG;
   if (g.opk == kOpF16) launch_wide_kernel<kOpF16>(op->kernel, a, grid, op->stream);
   else launch_wide_kernel<kOpBf16>(op->kernel, a, grid, op->stream);

@@ -4,11 +4,13 @@
 // itself and evaluates the tridiagonal eigenproblems and SLQ quadratures the
 // Python side reads back.  Commands on stdin, one per line:
 //   plans                       check every sweep plan on a grid of sizes
+//   wide                        check the wide sweep's tiled schedule
 //   geometry                    check the operand geometry of every precision
 //   tridiag m d_0..d_{m-1} e_0..e_{m-2}
 //                               eigenvalues and first eigenvector row
 //   slq m znorm2 a_0..a_{m-1} b_0..b_{m-2}
 //                               status and quadrature value
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <iostream>
@@ -73,6 +75,56 @@ static long plans() {
 // FP32 as three bf16 terms 6d + 6, FP32 MFMA operands d + 2 in steps of 2;
 // the FP64 operator d + 2 in steps of 4; the padded size is a multiple of
 // 256 and at least n.
+// The wide sweep's tiled schedule, decoded as the kernel decodes it (work
+// group w: XCD w mod 8, tile (w / 8 / 32) * 8 + w mod 8, item (w / 8) mod 32
+// of the tile): every pair (I, u) with 0 <= u < ndel(I) taken by exactly one
+// item, every row-partial slot (I, c < nchunk) written by exactly one item,
+// every column-partial slot (J, u - 1) that the reduction reads written by
+// exactly one pair, and the partial buffer large enough.
+static long wide_plans() {
+  long count = 0;
+  for (int64_t n_pad = 256; n_pad <= (int64_t(1) << 21); n_pad = n_pad * 5 / 4 / 256 * 256 + 256) {
+    const int nb = static_cast<int>(n_pad / 256);
+    for (int items = kSweepItemsMin; items <= kSweepItemsMax; items *= 2) {
+      const MatvecPlan p = wide_plan(n_pad, items);
+      CHECK(p.blk == 256 && p.nb == nb && p.dmax == nb / 2);
+      CHECK(p.nchunk % 4 == 0 && p.chunk >= 1 && p.grid % 256 == 0);
+      const int parts = p.nchunk / 4, S = wide_steps(nb);
+      CHECK(int64_t(parts) * p.chunk >= S && int64_t(parts - 1) * p.chunk < S);
+      CHECK(size_t(2 * p.nchunk + p.dmax) * size_t(n_pad) <= wide_partial_floats(n_pad));
+      const int64_t tiles = int64_t((nb + kWideGroup - 1) / kWideGroup) * parts;
+      std::vector<int> pair(size_t(nb) * (p.dmax + 1), 0), slot(size_t(nb) * p.nchunk, 0);
+      std::vector<int> col(size_t(nb) * (p.dmax + 1), 0);
+      for (int64_t w = 0; w < p.grid; ++w) {
+        const int64_t j = w >> 3, tile = (j >> 5) * 8 + (w & 7);
+        if (tile >= tiles) continue;
+        const int grp = static_cast<int>(tile / parts), part = static_cast<int>(tile % parts);
+        const int ia = static_cast<int>((j & 31) >> 2), ib = static_cast<int>(j & 3);
+        const int I = kWideGroup * grp + ia;
+        if (I >= nb) continue;
+        const int ndel = ((nb % 2) == 0 && I >= nb / 2) ? p.dmax : p.dmax + 1;
+        slot[size_t(I) * p.nchunk + 4 * part + ib] += 1;
+        for (int st = part * p.chunk; st < std::min(S, (part + 1) * p.chunk); ++st) {
+          const int u = 4 * st + ib - ia;
+          if (u < 0 || u >= ndel) continue;
+          pair[size_t(I) * (p.dmax + 1) + u] += 1;
+          if (u >= 1) col[size_t((I + u) % nb) * (p.dmax + 1) + u] += 1;
+        }
+      }
+      for (int I = 0; I < nb; ++I) {
+        const int ndel = ((nb % 2) == 0 && I >= nb / 2) ? p.dmax : p.dmax + 1;
+        for (int u = 0; u <= p.dmax; ++u) CHECK(pair[size_t(I) * (p.dmax + 1) + u] == (u < ndel ? 1 : 0));
+        for (int c = 0; c < p.nchunk; ++c) CHECK(slot[size_t(I) * p.nchunk + c] == 1);
+        // the reduction reads offsets 1 .. dlim(J) of column block J
+        const int dlim = ((nb % 2) == 0 && I < nb / 2) ? p.dmax - 1 : p.dmax;
+        for (int u = 1; u <= p.dmax; ++u) CHECK(col[size_t(I) * (p.dmax + 1) + u] == (u <= dlim ? 1 : 0));
+      }
+      ++count;
+    }
+  }
+  return count;
+}
+
 static long geometry() {
   long count = 0;
   for (int prec = 0; prec <= 5; ++prec)
@@ -106,6 +158,8 @@ int main() {
   while (std::cin >> cmd) {
     if (cmd == "plans") {
       std::cout << "plans ok " << plans() << "\n";
+    } else if (cmd == "wide") {
+      std::cout << "wide ok " << wide_plans() << "\n";
     } else if (cmd == "geometry") {
       std::cout << "geometry ok " << geometry() << "\n";
     } else if (cmd == "tridiag") {

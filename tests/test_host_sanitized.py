@@ -48,9 +48,10 @@ def _run(exe, text):
 
 
 def test_plans_and_geometry(driver):
-    out = _run(driver, "plans\ngeometry\n")
+    out = _run(driver, "plans\ngeometry\nwide\n")
     assert out[0].startswith("plans ok ") and int(out[0].split()[2]) > 300
     assert out[1].startswith("geometry ok ") and int(out[1].split()[2]) == 6 * 64 * 6
+    assert out[2].startswith("wide ok ") and int(out[2].split()[2]) > 100
 
 
 def _tridiag_cases():
