@@ -39,6 +39,7 @@ constexpr int kVmcnt0 = 0xF70, kVmcnt4 = 0xF74, kVmcnt8 = 0xF78;
 constexpr int kLgkm0 = 0xC07F;
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) void global_void;
 
@@ -112,7 +113,8 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
   __shared__ u32x4 St3[2 * kWideSlots];
   __shared__ float rowacc[2][kWideRows];
   __shared__ float colpart[4][kWideRows];
-  __shared__ float vrow[kWideRows];      // the input vector on this row block
+  __shared__ __attribute__((aligned(16))) float vrow[kWideRows];   // the input vector on this row block
+  __shared__ float vcol[2][kWideRows];   // ... on the column blocks of two pairs
 
   for (int e = tid; e < 2 * kWideRows; e += 512) rowacc[e / kWideRows][e % kWideRows] = 0.0f;
   for (int e = tid; e < kWideRows; e += 512) vrow[e] = A.vin[int64_t(I) * kWideRows + e];
@@ -166,16 +168,16 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
   const u32x4 b1 = BUF[kWideSlots + wide_slot(128 * wc + 32 + lc, g)];                       \
   const u32x4 b2 = BUF[kWideSlots + wide_slot(128 * wc + 64 + lc, g)];                       \
   const u32x4 b3 = BUF[kWideSlots + wide_slot(128 * wc + 96 + lc, g)]
-// both K-steps' fragments are read before the first MFMA (the scheduling
-// barrier keeps the compiler from sinking the reads to their uses), so that
-// all twelve reads are in flight together
 #define DCG_WIDE_COMPUTE(BUF)                                                                \
   do {                                                                                       \
-    DCG_WIDE_FRAGS(BUF, lh, xa0, xa1, xb0, xb1, xb2, xb3);                                   \
-    DCG_WIDE_FRAGS(BUF, 2 + lh, ya0, ya1, yb0, yb1, yb2, yb3);                               \
-    __builtin_amdgcn_sched_barrier(0);                                                       \
-    DCG_WIDE_MFMAS(xa0, xa1, xb0, xb1, xb2, xb3);                                            \
-    DCG_WIDE_MFMAS(ya0, ya1, yb0, yb1, yb2, yb3);                                            \
+    {                                                                                        \
+      DCG_WIDE_FRAGS(BUF, lh, xa0, xa1, xb0, xb1, xb2, xb3);                                 \
+      DCG_WIDE_MFMAS(xa0, xa1, xb0, xb1, xb2, xb3);                                          \
+    }                                                                                        \
+    {                                                                                        \
+      DCG_WIDE_FRAGS(BUF, 2 + lh, ya0, ya1, yb0, yb1, yb2, yb3);                             \
+      DCG_WIDE_MFMAS(ya0, ya1, yb0, yb1, yb2, yb3);                                          \
+    }                                                                                        \
   } while (0)
 // One stage s in buffer CUR: wait until this wave's loads of stage s have
 // landed (those of s + 1 and s + 2 may still be in flight: four loads per
@@ -210,9 +212,27 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
     if (J >= nb) J -= nb;
     return opsel == 0 ? xr + int64_t(I) * kWideRows * kst : xc + int64_t(J) * kWideRows * kst;
   };
+  // this lane's share of the row sums of its 32 rows (two tile rows of 16)
+  float racc[2][16];
+#pragma unroll
+  for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) racc[tr][v] = 0.0f;
+  // the input vector on a pair's column block, loaded into vcol[b] by
+  // direct global-to-LDS loads (waves 0-3, 64 entries each) when the pair's
+  // first stages are issued: it has landed by the pair's first stage wait
+  auto issue_vcol = [&](int b, int st) {
+    int J = I + 4 * st + ib - ia;
+    if (J >= nb) J -= nb;
+    if (w < 4)
+      __builtin_amdgcn_global_load_lds((global_void *)(A.vin + int64_t(J) * kWideRows + 64 * w + l),
+                                       (lds_void *)&vcol[b][64 * w], 4, 0, 0);
+  };
+  int pb = 0;
   int st = next_valid(s0);
   const uint16_t *base = nullptr;
   if (st < s1) {
+    issue_vcol(0, st);
     base = base_of(st);
     DCG_WIDE_ISSUE(St0, 0);
     if (1 < nkc) DCG_WIDE_ISSUE(St1, 1);
@@ -233,11 +253,17 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
       if (kc + 2 < nkc) DCG_WIDE_STEP(St2, St1, kc + 2);
       if (kc + 3 < nkc) DCG_WIDE_STEP(St3, St2, kc + 3);
     }
+    // this pair's column-block vector, read while no direct load is in
+    // flight (the compiler would otherwise wait for the next pair's)
+    float pj[4];
+#pragma unroll
+    for (int tc = 0; tc < 4; ++tc) pj[tc] = vcol[pb][128 * wc + 32 * tc + lc];
     // every wave is done reading this pair's stages: the next pair's first
     // three stages load while this pair's epilogue runs
     const int stn = next_valid(st + 1);
     __syncthreads();
     if (stn < s1) {
+      issue_vcol(pb ^ 1, stn);
       base = base_of(stn);
       DCG_WIDE_ISSUE(St0, 0);
       if (1 < nkc) DCG_WIDE_ISSUE(St1, 1);
@@ -250,47 +276,42 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
 #undef DCG_WIDE_STEP
 
     // kernel values on the MFMA output layout: lane l holds column l % 32
-    // and rows 8 (v / 4) + 4 (l / 32) + v % 4 of each 32x32 tile
+    // and rows 8 (v / 4) + 4 (l / 32) + v % 4 of each 32x32 tile; the row
+    // sums stay per lane (over the lane's columns) for all of the work
+    // item's block pairs and are added across lanes once at its end
     const bool diag = (dl == 0);
-    const int64_t cbase = int64_t(J) * kWideRows + 128 * wc;
-    float pj[4];
+
+    // the exact diagonal of the diagonal block pair: distance zero by
+    // definition (a wave-uniform test per tile)
+    if (diag) {
 #pragma unroll
-    for (int tc = 0; tc < 4; ++tc) pj[tc] = A.vin[cbase + 32 * tc + lc];
+      for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+        for (int tc = 0; tc < 4; ++tc)
+          if (2 * wr + tr == 4 * wc + tc) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+              if (8 * (v >> 2) + 4 * lh + (v & 3) == lc) acc[tr][tc][v] = 0.0f;
+          }
+    }
+    // row sums per lane, and column sums (used off the diagonal block pair,
+    // where the row sums alone cover both triangles)
     float cs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int tr = 0; tr < 2; ++tr) {
-      float rs[16];
+      // the lane's 16 rows of this tile row: four runs of four (16-byte reads)
+      f32x4 vi[4];
 #pragma unroll
-      for (int v = 0; v < 16; ++v) rs[v] = 0.0f;
+      for (int q = 0; q < 4; ++q)
+        vi[q] = *reinterpret_cast<const f32x4 *>(&vrow[64 * wr + 32 * tr + 8 * q + 4 * lh]);
 #pragma unroll
-      for (int tc = 0; tc < 4; ++tc) {
-        f32x16 r2 = acc[tr][tc];
-        if (diag && 2 * wr + tr == 4 * wc + tc) {
-          // the exact diagonal: distance zero by definition
-#pragma unroll
-          for (int v = 0; v < 16; ++v)
-            if (8 * (v >> 2) + 4 * lh + (v & 3) == lc) r2[v] = 0.0f;
-        }
+      for (int tc = 0; tc < 4; ++tc)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-          const float kv = kval<KERN>(r2[v]);
-          rs[v] = fmaf(kv, pj[tc], rs[v]);
-          if (!diag)
-            cs[tc] = fmaf(kv, vrow[64 * wr + 32 * tr + 8 * (v >> 2) + 4 * lh + (v & 3)], cs[tc]);
+          const float kv = kval<KERN>(acc[tr][tc][v]);
+          racc[tr][v] = fmaf(kv, pj[tc], racc[tr][v]);
+          cs[tc] = fmaf(kv, vi[v >> 2][v & 3], cs[tc]);
         }
-      }
-      // row sums of this tile row: over the 32 lanes that hold the same
-      // rows, added into the work item's FP32 accumulator (one writer per row)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        float s = rs[v];
-        s += __shfl_xor(s, 1);
-        s += __shfl_xor(s, 2);
-        s += __shfl_xor(s, 4);
-        s += __shfl_xor(s, 8);
-        s += __shfl_xor(s, 16);
-        if (lc == v) rowacc[wc][64 * wr + 32 * tr + 8 * (v >> 2) + 4 * lh + (v & 3)] += s;
-      }
     }
     // column sums of an off-diagonal block pair: the block's four row
     // quarters added in a fixed order
@@ -308,7 +329,22 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
       lds_barrier();
     }
     st = stn;
+    pb ^= 1;
   }
+  // row sums: over the 32 lanes that hold the same rows, one writer per
+  // row and column half
+#pragma unroll
+  for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      float s = racc[tr][v];
+      s += __shfl_xor(s, 1);
+      s += __shfl_xor(s, 2);
+      s += __shfl_xor(s, 4);
+      s += __shfl_xor(s, 8);
+      s += __shfl_xor(s, 16);
+      if (lc == v) rowacc[wc][64 * wr + 32 * tr + 8 * (v >> 2) + 4 * lh + (v & 3)] = s;
+    }
   __syncthreads();
   for (int e = tid; e < kWideRows; e += 512)
     A.prow[int64_t(c) * n_pad + int64_t(I) * kWideRows + e] =

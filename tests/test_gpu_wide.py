@@ -149,3 +149,31 @@ def test_wide_refusals(lib):
         assert e.value.status == -1
     _, st = lib.solve(op, b, tol=1e-6)
     assert st["status"] == 0
+
+
+@pytest.mark.parametrize("prec", [1, 4])
+def test_wide_full_size_sampled_rows(lib, prec):
+    """The pixel workload at full size (n = 36551, d = 784, RBF, bf16 / fp16
+    points) in the launch configurations of the GPC benchmark (its default
+    plan) and of the plan limits: 24 sampled rows of the product, each row of
+    the kernel matrix formed by the oracle from the same rounded points, to
+    the wide bound; the diagonal block pairs, the last (ragged) row block
+    and both ends of the block-offset range are among the rows."""
+    w = workloads.gpc_pixels()
+    X = w["X"]
+    n = X.shape[0]
+    s2, sigma2 = w["s2"], 0.5
+    op = lib.Operator(_dev(X), w["kernel"], w["ell"], s2, sigma2, prec=prec)
+    Xr = OP.round_points(X, prec, w["kernel"], w["ell"])
+    v = np.random.default_rng(31).standard_normal(n)
+    rows = np.random.default_rng(32).choice(n, 20, replace=False)
+    rows = np.concatenate([rows, [0, 255, n - 256, n - 1]])
+    Kr = OK.gram(Xr[rows], w["kernel"], w["ell"], s2, Xr)
+    ref = Kr @ v + sigma2 * v[rows]
+    scale = np.abs(Kr) @ np.abs(v) + sigma2 * np.abs(v[rows])
+    for items in (256, 2048, 8192):
+        op.set_sweep_items(items)
+        y = _np(op.matvec(_dev(v)))[rows]
+        err = np.abs(y - ref) / scale
+        print(f"prec {prec} items {items}: max error {err.max():.2e}", flush=True)
+        assert err.max() <= _bound(784), (items, err.max())
