@@ -59,8 +59,9 @@ PEAK_DP_SLOTS = 256 * 64 * 2.4e9
 # None for any other configuration or source.
 SWEEP_TRAFFIC = {("bf16", 65536, 32, 2, 8192): (112.6e6, "be188e5c358a333e")}
 # the same for the wide pair sweep (bf16 points, GPC pixel workload), keyed by
-# (points, n, d) and valid for the source of csrc/wide.hip it was taken from
-WIDE_TRAFFIC = {("bf16", 36551, 784): (4938.7e6, "ad0f4075ca14a375")}
+# (points, n, d, work items) and valid for the source of csrc/wide.hip it was
+# taken from
+WIDE_TRAFFIC = {("bf16", 36551, 784, 4096): (2642.4e6, "07454c1ff8b9d67a")}
 
 
 def _source_sha(name):
@@ -78,8 +79,8 @@ def sweep_traffic(prec, n, d, kernel, items):
     return value if sha is not None and _source_sha("matvec.hip") == sha else None
 
 
-def wide_traffic(points, n, d):
-    entry = WIDE_TRAFFIC.get((points, n, d))
+def wide_traffic(points, n, d, items):
+    entry = WIDE_TRAFFIC.get((points, n, d, items))
     if entry is None:
         return None
     value, sha = entry
@@ -514,7 +515,7 @@ def main_gpc(args):
         out["product_ms"] = round(t, 4)
         out["roofline"] = {"bound": "mfma", "achieved": round(tf, 1), "peak": 2500.0,
                            "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4),
-                           "traffic": wide_traffic(args.gpc_points, n, d),
+                           "traffic": wide_traffic(args.gpc_points, n, d, items),
                            "traffic_unit": "bytes per launch of symv_wide_kernel (rocprofv3 "
                                            "FETCH_SIZE + WRITE_SIZE)",
                            "per_launch": f"{n * (n - 1) // 2:.3e} unique pairs x 2 d flops"}
