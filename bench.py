@@ -57,7 +57,7 @@ PEAK_DP_SLOTS = 256 * 64 * 2.4e9
 # WRITE_SIZE (scaled by a 256 MiB copy) for this workload, valid while the
 # sweep's source is the one the counters were taken from (its SHA-256 prefix);
 # None for any other configuration or source.
-SWEEP_TRAFFIC = {("bf16", 65536, 32, 2, 8192): (112.6e6, "be188e5c358a333e")}
+SWEEP_TRAFFIC = {("bf16", 65536, 32, 2, 8192): (112.6e6, "73e7f4b4495c711d")}
 # the same for the wide pair sweep (bf16 points, GPC pixel workload), keyed by
 # (points, n, d, work items) and valid for the source of csrc/wide.hip it was
 # taken from
