@@ -59,9 +59,9 @@ PEAK_DP_SLOTS = 256 * 64 * 2.4e9
 # None for any other configuration or source.
 SWEEP_TRAFFIC = {("bf16", 65536, 32, 2, 8192): (112.6e6, "73e7f4b4495c711d")}
 # the same for the wide pair sweep (bf16 points, GPC pixel workload), keyed by
-# (points, n, d, work items) and valid for the source of csrc/wide.hip it was
-# taken from
-WIDE_TRAFFIC = {("bf16", 36551, 784, 4096): (2642.4e6, "07454c1ff8b9d67a")}
+# (points, n, d, work items) and valid for the sources of csrc/wide.hip (the
+# kernel) and csrc/host.cpp (its operand width) it was taken from
+WIDE_TRAFFIC = {("bf16", 36551, 784, 4096): (2579.1e6, "07454c1ff8b9d67a", "bdc84a605bc288b2")}
 
 
 def _source_sha(name):
@@ -83,8 +83,10 @@ def wide_traffic(points, n, d, items):
     entry = WIDE_TRAFFIC.get((points, n, d, items))
     if entry is None:
         return None
-    value, sha = entry
-    return value if _source_sha("wide.hip") == sha else None
+    value, sha_kernel, sha_host = entry
+    if _source_sha("wide.hip") != sha_kernel or _source_sha("host.cpp") != sha_host:
+        return None
+    return value
 
 
 def parse():

@@ -38,8 +38,8 @@ Geometry make_geometry(int64_t n, int d, int prec) {
     g.kstride = 0;
   } else if (prec == DCG_PREC_BF16 || prec == DCG_PREC_FP16) {
     g.opk = (prec == DCG_PREC_FP16) ? kOpF16 : kOpBf16;
-    // the wide sweep streams K in slices of 64 (four K steps)
-    g.ksteps = (d > kMaxD) ? 4 * ((d + 6 + 63) / 64) : (d + 6 + 15) / 16;
+    // the wide sweep streams K in stages of 32 (two K steps)
+    g.ksteps = (d > kMaxD) ? 2 * ((d + 6 + 31) / 32) : (d + 6 + 15) / 16;
     g.kstride = 16 * g.ksteps;
   } else if (prec == DCG_PREC_BF16X2) {
     g.ksteps = bf16_bucket((4 * d + 6 + 15) / 16);
