@@ -16,8 +16,9 @@
 // slices are stored with the 16-byte groups of a row XOR-swizzled by the row
 // index, so that the rows a fragment read serves together fall in distinct
 // LDS banks.  After the last slice the kernel values are formed in registers
-// on the MFMA output layout and folded into FP32 row sums (accumulated in
-// LDS across the work item's block pairs) and per-block-pair column sums.
+// on the MFMA output layout and folded into FP32 row sums (kept per lane
+// across the work item's block pairs and added across lanes once at its
+// end) and per-block-pair column sums.
 #include <algorithm>
 #include <cmath>
 
