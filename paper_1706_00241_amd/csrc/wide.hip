@@ -10,15 +10,17 @@
 // offset of a range, so that the 32 items of a tile, run together on one
 // XCD, touch eight row and four column blocks at a time and share them in
 // its L2.  For each block pair (I, J) the augmented operands of both blocks
-// stream through LDS in 32-element slices of K (four stages filled three
-// ahead by direct global-to-LDS loads), each wave accumulating a 64 x 128
-// part of the 256 x 256 distance tile in eight 32x32x16 MFMA tiles.  The
+// stream through LDS in 32-element slices of K (four stages: the pair's
+// first three by direct global-to-LDS loads, the rest loaded into registers
+// three stages ahead and written to LDS a stage later), each wave
+// accumulating a 64 x 128 part of the 256 x 256 distance tile in eight
+// 32x32x16 MFMA tiles; the two halves of the waves run a phase apart, so
+// that on each SIMD one wave multiplies while the other reads LDS.  The
 // slices are stored with the 16-byte groups of a row XOR-swizzled by the row
 // index, so that the rows a fragment read serves together fall in distinct
 // LDS banks.  After the last slice the kernel values are formed in registers
-// on the MFMA output layout and folded into FP32 row sums (kept per lane
-// across the work item's block pairs and added across lanes once at its
-// end) and per-block-pair column sums.
+// on the MFMA output layout and folded into FP32 row sums (added across the
+// lanes after each block pair, into LDS) and per-block-pair column sums.
 #include <algorithm>
 #include <cmath>
 
@@ -65,6 +67,13 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("" ::: "memory");
 }
 
+// The value of lane l ^ D (D < 32) by a swizzle within each 32 lanes
+// (bit-mask mode: and-mask 31, xor-mask D).
+template <int D>
+__device__ __forceinline__ float lane_xor(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, x), 0x1F | (D << 10)));
+}
+
 // Steps per row block group of the tiled schedule (as wide_steps on the
 // host).
 __device__ __forceinline__ int wide_steps_dev(int nb) { return (nb / 2 + 1 + kWideGroup - 1 + 3) / 4; }
@@ -100,7 +109,10 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
   const int c = 4 * part + ib;   // this item's row-partial slot
 
   const int tid = threadIdx.x;
-  const int w = tid >> 6, l = tid & 63, lc = l & 31, lh = l >> 5;
+  // the wave index as a scalar (it is uniform): the two wave groups below
+  // branch on it without masking
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l = tid & 63, lc = l & 31, lh = l >> 5;
   const int wr = w & 3, wc = w >> 2;     // rows 64 wr .., columns 128 wc .. of a block pair
   const int64_t n_pad = A.n_pad;
   const int kst = A.kstride;             // a multiple of kWideKC
@@ -162,42 +174,80 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
   acc[1][1] = wide_mfma<OPK>(a1, b1, acc[1][1]);                                             \
   acc[1][2] = wide_mfma<OPK>(a1, b2, acc[1][2]);                                             \
   acc[1][3] = wide_mfma<OPK>(a1, b3, acc[1][3])
-#define DCG_WIDE_FRAGS(BUF, g, a0, a1, b0, b1, b2, b3)                                       \
-  const u32x4 a0 = BUF[wide_slot(64 * wr + lc, g)];                                          \
-  const u32x4 a1 = BUF[wide_slot(64 * wr + 32 + lc, g)];                                     \
-  const u32x4 b0 = BUF[kWideSlots + wide_slot(128 * wc + lc, g)];                            \
-  const u32x4 b1 = BUF[kWideSlots + wide_slot(128 * wc + 32 + lc, g)];                       \
-  const u32x4 b2 = BUF[kWideSlots + wide_slot(128 * wc + 64 + lc, g)];                       \
-  const u32x4 b3 = BUF[kWideSlots + wide_slot(128 * wc + 96 + lc, g)]
-#define DCG_WIDE_COMPUTE(BUF)                                                                \
+  // Inside the stage loop the loads go through registers (four 16-byte
+  // groups per lane, written to LDS a stage later): the direct loads' writes
+  // into LDS held the LDS for longer than register-staged writes do.  The
+  // direct loads remain for each pair's first three stages, which load
+  // during the previous pair's epilogue.
+  u32x4 rs0, rs1, rs2, rs3;
+#define DCG_WIDE_LOADR(kc)                                                                   \
   do {                                                                                       \
-    {                                                                                        \
-      DCG_WIDE_FRAGS(BUF, lh, xa0, xa1, xb0, xb1, xb2, xb3);                                 \
-      DCG_WIDE_MFMAS(xa0, xa1, xb0, xb1, xb2, xb3);                                          \
-    }                                                                                        \
-    {                                                                                        \
-      DCG_WIDE_FRAGS(BUF, 2 + lh, ya0, ya1, yb0, yb1, yb2, yb3);                             \
-      DCG_WIDE_MFMAS(ya0, ya1, yb0, yb1, yb2, yb3);                                          \
-    }                                                                                        \
+    const uint16_t *src = base + (kc) * kWideKC;                                             \
+    rs0 = *reinterpret_cast<const u32x4 *>(src + go0);                                       \
+    rs1 = *reinterpret_cast<const u32x4 *>(src + go1);                                       \
+    rs2 = *reinterpret_cast<const u32x4 *>(src + go2);                                       \
+    rs3 = *reinterpret_cast<const u32x4 *>(src + go3);                                       \
   } while (0)
-// One stage s in buffer CUR: wait until this wave's loads of stage s have
-// landed (those of s + 1 and s + 2 may still be in flight: four loads per
-// stage, retired in order; at s = 0 everything, since the previous pair's
-// stores were issued after this pair's first loads and stores may retire
-// out of order with loads), then the barrier makes every wave's loads of s
-// visible and frees NXT (read at step s - 1, whose reads every wave has
-// waited for before its MFMAs) for stage s + 3.  A plain s_barrier: the
-// release fence of __syncthreads would wait for the loads still in flight
-// too.
-#define DCG_WIDE_STEP(CUR, NXT, s)                                                           \
+#define DCG_WIDE_STORER(BUF)                                                                 \
   do {                                                                                       \
-    if ((s) == 0) __builtin_amdgcn_s_waitcnt(kVmcnt0);                                       \
-    else if ((s) + 2 < nkc) __builtin_amdgcn_s_waitcnt(kVmcnt8);                             \
-    else if ((s) + 1 < nkc) __builtin_amdgcn_s_waitcnt(kVmcnt4);                             \
-    else __builtin_amdgcn_s_waitcnt(kVmcnt0);                                                \
+    BUF[dst0 + l] = rs0;                                                                     \
+    BUF[dst0 + 64 + l] = rs1;                                                                \
+    BUF[dst0 + 128 + l] = rs2;                                                               \
+    BUF[dst0 + 192 + l] = rs3;                                                               \
+  } while (0)
+  // fragments of both K-steps of a stage (16-byte groups lh and 2 + lh of
+  // this wave's two 32-row and four 32-column tiles)
+  u32x4 fa0, fa1, fb0, fb1, fb2, fb3, ga0, ga1, gb0, gb1, gb2, gb3;
+#define DCG_WIDE_READ(BUF)                                                                   \
+  do {                                                                                       \
+    fa0 = BUF[wide_slot(64 * wr + lc, lh)];                                                  \
+    fa1 = BUF[wide_slot(64 * wr + 32 + lc, lh)];                                             \
+    fb0 = BUF[kWideSlots + wide_slot(128 * wc + lc, lh)];                                    \
+    fb1 = BUF[kWideSlots + wide_slot(128 * wc + 32 + lc, lh)];                               \
+    fb2 = BUF[kWideSlots + wide_slot(128 * wc + 64 + lc, lh)];                               \
+    fb3 = BUF[kWideSlots + wide_slot(128 * wc + 96 + lc, lh)];                               \
+    ga0 = BUF[wide_slot(64 * wr + lc, 2 + lh)];                                              \
+    ga1 = BUF[wide_slot(64 * wr + 32 + lc, 2 + lh)];                                         \
+    gb0 = BUF[kWideSlots + wide_slot(128 * wc + lc, 2 + lh)];                                \
+    gb1 = BUF[kWideSlots + wide_slot(128 * wc + 32 + lc, 2 + lh)];                           \
+    gb2 = BUF[kWideSlots + wide_slot(128 * wc + 64 + lc, 2 + lh)];                           \
+    gb3 = BUF[kWideSlots + wide_slot(128 * wc + 96 + lc, 2 + lh)];                           \
+  } while (0)
+#define DCG_WIDE_MULT()                                                                      \
+  do {                                                                                       \
+    DCG_WIDE_MFMAS(fa0, fa1, fb0, fb1, fb2, fb3);                                            \
+    DCG_WIDE_MFMAS(ga0, ga1, gb0, gb1, gb2, gb3);                                            \
+  } while (0)
+// Stage s in buffer CUR: write the staged stage s + 2 (loaded a stage ago)
+// to W2 (stage s - 2's buffer), load stage s + 3 into the staging
+// registers, read the stage's fragments, barrier, multiply, barrier.  The
+// waves of group 1 (columns 128-255 of the pair) pass one barrier more
+// before the stage loop and those of group 0 one more after it, so group 1
+// runs a phase behind: while group 0 multiplies stage s, group 1 reads it,
+// and while group 0 reads stage s + 1, group 1 multiplies s.  Each SIMD
+// holds one wave of each group, so one of its waves issues MFMAs while the
+// other reads LDS.  W2 is free: both groups read stage s - 2 at least two
+// phases ago; stage s + 2 is read after the barriers that follow both
+// groups' writes of it (each barrier waits for this wave's LDS accesses).
+// Plain s_barriers: the release fence of __syncthreads would wait for the
+// loads in flight too.  The MFMAs touch no memory, so scheduling barriers
+// keep them between the two workgroup barriers; the multiplying wave runs at
+// the higher issue priority.
+#define DCG_WIDE_STAGE(CUR, W2, s)                                                           \
+  do {                                                                                       \
+    if ((s) >= 1 && (s) + 2 < nkc) {                                                         \
+      __builtin_amdgcn_s_waitcnt(kVmcnt0);                                                   \
+      DCG_WIDE_STORER(W2);                                                                   \
+    }                                                                                        \
+    if ((s) + 3 < nkc) DCG_WIDE_LOADR((s) + 3);                                              \
+    DCG_WIDE_READ(CUR);                                                                      \
     lds_barrier();                                                                           \
-    if ((s) + 3 < nkc) DCG_WIDE_ISSUE(NXT, (s) + 3);                                         \
-    DCG_WIDE_COMPUTE(CUR);                                                                   \
+    __builtin_amdgcn_sched_barrier(0);                                                       \
+    __builtin_amdgcn_s_setprio(1);                                                           \
+    DCG_WIDE_MULT();                                                                         \
+    __builtin_amdgcn_s_setprio(0);                                                           \
+    __builtin_amdgcn_sched_barrier(0);                                                       \
+    lds_barrier();                                                                           \
   } while (0)
 
   // the first step at or after st whose pair this item owns (s1 if none)
@@ -213,12 +263,6 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
     if (J >= nb) J -= nb;
     return opsel == 0 ? xr + int64_t(I) * kWideRows * kst : xc + int64_t(J) * kWideRows * kst;
   };
-  // this lane's share of the row sums of its 32 rows (two tile rows of 16)
-  float racc[2][16];
-#pragma unroll
-  for (int tr = 0; tr < 2; ++tr)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) racc[tr][v] = 0.0f;
   // the input vector on a pair's column block, loaded into vcol[b] by
   // direct global-to-LDS loads (waves 0-3, 64 entries each) when the pair's
   // first stages are issued: it has landed by the pair's first stage wait
@@ -248,21 +292,26 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
     for (int tr = 0; tr < 2; ++tr)
 #pragma unroll
       for (int tc = 0; tc < 4; ++tc) acc[tr][tc] = f32x16{};
+    // everything this pair's first stages need has landed (and the
+    // previous pair's stores, which may retire out of order with loads)
+    __builtin_amdgcn_s_waitcnt(kVmcnt0);
+    lds_barrier();
+    if (wc != 0) lds_barrier();   // group 1 one phase behind
     for (int kc = 0; kc < nkc; kc += 4) {
-      DCG_WIDE_STEP(St0, St3, kc);
-      if (kc + 1 < nkc) DCG_WIDE_STEP(St1, St0, kc + 1);
-      if (kc + 2 < nkc) DCG_WIDE_STEP(St2, St1, kc + 2);
-      if (kc + 3 < nkc) DCG_WIDE_STEP(St3, St2, kc + 3);
+      DCG_WIDE_STAGE(St0, St2, kc);
+      if (kc + 1 < nkc) DCG_WIDE_STAGE(St1, St3, kc + 1);
+      if (kc + 2 < nkc) DCG_WIDE_STAGE(St2, St0, kc + 2);
+      if (kc + 3 < nkc) DCG_WIDE_STAGE(St3, St1, kc + 3);
     }
+    if (wc == 0) lds_barrier();   // ... and level again: every wave is done
     // this pair's column-block vector, read while no direct load is in
     // flight (the compiler would otherwise wait for the next pair's)
     float pj[4];
 #pragma unroll
     for (int tc = 0; tc < 4; ++tc) pj[tc] = vcol[pb][128 * wc + 32 * tc + lc];
-    // every wave is done reading this pair's stages: the next pair's first
-    // three stages load while this pair's epilogue runs
+    // every wave is done reading this pair's stages (the last barrier): the
+    // next pair's first three stages load while this pair's epilogue runs
     const int stn = next_valid(st + 1);
-    __syncthreads();
     if (stn < s1) {
       issue_vcol(pb ^ 1, stn);
       base = base_of(stn);
@@ -271,10 +320,12 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
       if (2 < nkc) DCG_WIDE_ISSUE(St2, 2);
     }
 #undef DCG_WIDE_ISSUE
-#undef DCG_WIDE_FRAGS
+#undef DCG_WIDE_READ
 #undef DCG_WIDE_MFMAS
-#undef DCG_WIDE_COMPUTE
-#undef DCG_WIDE_STEP
+#undef DCG_WIDE_MULT
+#undef DCG_WIDE_STAGE
+#undef DCG_WIDE_LOADR
+#undef DCG_WIDE_STORER
 
     // kernel values on the MFMA output layout: lane l holds column l % 32
     // and rows 8 (v / 4) + 4 (l / 32) + v % 4 of each 32x32 tile; the row
@@ -305,14 +356,39 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
         vi[q] = *reinterpret_cast<const f32x4 *>(&vrow[64 * wr + 32 * tr + 8 * q + 4 * lh]);
+      float rs[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) rs[v] = 0.0f;
 #pragma unroll
       for (int tc = 0; tc < 4; ++tc)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const float kv = kval<KERN>(acc[tr][tc][v]);
-          racc[tr][v] = fmaf(kv, pj[tc], racc[tr][v]);
+          rs[v] = fmaf(kv, pj[tc], rs[v]);
           cs[tc] = fmaf(kv, vi[v >> 2][v & 3], cs[tc]);
         }
+      // the sums of the 16 rows over the 32 lanes of this lane's half: four
+      // halving exchanges leave entry lc / 2 summed over 16 lanes, the last
+      // one over all 32; lane pairs then add it to the row's LDS sum
+#define DCG_WIDE_HALVE(D, M)                                                                 \
+      {                                                                                      \
+        const bool hi = (lc & (D)) != 0;                                                     \
+        _Pragma("unroll") for (int i = 0; i < (M); ++i) {                                    \
+          const float keep = hi ? rs[(M) + i] : rs[i];                                       \
+          const float send = hi ? rs[i] : rs[(M) + i];                                       \
+          rs[i] = keep + lane_xor<(D)>(send);                                                \
+        }                                                                                    \
+      }
+      DCG_WIDE_HALVE(16, 8);
+      DCG_WIDE_HALVE(8, 4);
+      DCG_WIDE_HALVE(4, 2);
+      DCG_WIDE_HALVE(2, 1);
+#undef DCG_WIDE_HALVE
+      const float rsum = rs[0] + lane_xor<1>(rs[0]);
+      if ((lc & 1) == 0) {
+        const int v = lc >> 1;
+        rowacc[wc][64 * wr + 32 * tr + 8 * (v >> 2) + 4 * lh + (v & 3)] += rsum;
+      }
     }
     // column sums of an off-diagonal block pair: the block's four row
     // quarters added in a fixed order
@@ -332,20 +408,6 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
     st = stn;
     pb ^= 1;
   }
-  // row sums: over the 32 lanes that hold the same rows, one writer per
-  // row and column half
-#pragma unroll
-  for (int tr = 0; tr < 2; ++tr)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      float s = racc[tr][v];
-      s += __shfl_xor(s, 1);
-      s += __shfl_xor(s, 2);
-      s += __shfl_xor(s, 4);
-      s += __shfl_xor(s, 8);
-      s += __shfl_xor(s, 16);
-      if (lc == v) rowacc[wc][64 * wr + 32 * tr + 8 * (v >> 2) + 4 * lh + (v & 3)] = s;
-    }
   __syncthreads();
   for (int e = tid; e < kWideRows; e += 512)
     A.prow[int64_t(c) * n_pad + int64_t(I) * kWideRows + e] =
