@@ -521,11 +521,14 @@ def laplace_evidence(op, y, f, a, Z, tol=1e-8, max_steps=2048, check_every=8):
 
 def laplace_gpc(op, y, rc=None, max_newton=50, psi_tol=1.0, tol=1e-5, max_iter=0, L=0,
                 select_largest=True, check_every=8, refine=False, inner_tol=1e-4,
-                refine_max=20, use_graph=True, ritz_route="auto", extraction="harmonic"):
+                refine_max=20, use_graph=True, ritz_route="auto", extraction="harmonic",
+                profile=False):
     """Laplace GPC mode by Newton's method (section 3, Eqs. 8-10), each
     system A = I + D K D solved by deflated CG with W carried over through
-    ``rc``.  y: (n,) labels in {-1, +1}.  Returns (f, a, psi list, list of
-    per-solve stats dicts, status)."""
+    ``rc``.  y: (n,) labels in {-1, +1}.  With profile, each solve's stats
+    hold the device time of its CG steps' sweeps (HIP events around each
+    sweep launch).  Returns (f, a, psi list, list of per-solve stats dicts,
+    status)."""
     torch = _torch()
     lib = load()
     y = y.to(device=op.device, dtype=torch.float64).contiguous()
@@ -536,8 +539,9 @@ def laplace_gpc(op, y, rc=None, max_newton=50, psi_tol=1.0, tol=1e-5, max_iter=0
     p = Params(tol=float(tol), max_iter=int(max_iter), L=int(L),
                select_largest=1 if select_largest else 0, check_every=int(check_every),
                refine=_refine_mode(refine), inner_tol=float(inner_tol), refine_max=int(refine_max),
-               use_graph=1 if use_graph else 0, true_residual=0, profile=0, refresh_every=0,
-               ritz_route=_ritz_route(ritz_route), extraction=_extraction(extraction))
+               use_graph=1 if use_graph else 0, true_residual=0, profile=1 if profile else 0,
+               refresh_every=0, ritz_route=_ritz_route(ritz_route),
+               extraction=_extraction(extraction))
     psi = (ctypes.c_double * (max_newton + 1))()
     stats = (Stats * max_newton)()
     steps = ctypes.c_int()
