@@ -61,8 +61,8 @@ SWEEP_TRAFFIC = {("bf16", 65536, 32, 2, 8192): (112.6e6, "73e7f4b4495c711d")}
 # the same for the wide pair sweep (bf16 points, GPC pixel workload), keyed by
 # (points, n, d, work items) and valid for the sources of csrc/wide.hip (the
 # kernel) and csrc/host.cpp (its operand width) it was taken from
-WIDE_TRAFFIC = {("bf16", 36551, 784, 8192): (2491.2e6, "064316e7d5e67513", "bdc84a605bc288b2"),
-                ("bf16", 36551, 784, 4096): (2414.1e6, "064316e7d5e67513", "bdc84a605bc288b2")}
+WIDE_TRAFFIC = {("bf16", 36551, 784, 8192): (2491.2e6, "52b46e8a7fcbbc28", "bdc84a605bc288b2"),
+                ("bf16", 36551, 784, 4096): (2414.1e6, "52b46e8a7fcbbc28", "bdc84a605bc288b2")}
 
 
 def _source_sha(name):

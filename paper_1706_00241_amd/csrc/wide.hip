@@ -109,8 +109,8 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
   const int c = 4 * part + ib;   // this item's row-partial slot
 
   const int tid = threadIdx.x;
-  // the wave index as a scalar (it is uniform): the two wave groups below
-  // branch on it without masking
+  // the wave index as a scalar (it is uniform), so that the extra barriers
+  // of the two wave groups below are scalar branches
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l = tid & 63, lc = l & 31, lh = l >> 5;
   const int wr = w & 3, wc = w >> 2;     // rows 64 wr .., columns 128 wc .. of a block pair
@@ -135,10 +135,10 @@ __global__ __launch_bounds__(512, 1) void symv_wide_kernel(SymvArgs A) {
 
   const uint16_t *xr = static_cast<const uint16_t *>(A.xr);
   const uint16_t *xc = static_cast<const uint16_t *>(A.xc);
-  // Loads: a stage is 32 chunks of 1 KB (64 slots), written by direct
-  // global-to-LDS loads, lane l of a load to slot 64 (chunk) + l.  Waves 0-3
-  // load the row block's operand (chunks 4 wr + i, i < 4), waves 4-7 the
-  // column block's; a lane fetches the row and group its slot holds.
+  // Loads: a stage is 32 chunks of 1 KB (64 slots), lane l of a load
+  // writing slot 64 (chunk) + l (directly or from a staging register).
+  // Waves 0-3 load the row block's operand (chunks 4 wr + i, i < 4), waves
+  // 4-7 the column block's; a lane fetches the row and group its slot holds.
   const int opsel = wc;
   int go0, go1, go2, go3;                // element offsets within the block
   {
