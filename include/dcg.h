@@ -51,7 +51,15 @@ enum dcg_kernel { DCG_RBF = 0, DCG_MATERN32 = 1, DCG_MATERN52 = 2 };
  * points evaluated with FP32 accumulation).  FP64 is the exact operator. */
 enum dcg_prec {
   DCG_PREC_FP32 = 0,    /* fp32 points, fp32 MFMA                              */
-  DCG_PREC_BF16 = 1,    /* bf16 points (8 significant bits), bf16 MFMA         */
+  DCG_PREC_BF16 = 1,    /* bf16 points (8 significant bits), bf16 MFMA.  With
+                           bf16 or fp16 points d may exceed 64 (up to 4096):
+                           the product then runs an LDS-staged MFMA tile loop
+                           over the points of 256-point block pairs, single
+                           vectors only (dcg_matvec with m > 1 forms one
+                           column at a time); there is no FP64 operator and no
+                           multi-column sweep: dcg_matvec_exact, refinement,
+                           dcg_solve_block and dcg_solve_batched return
+                           DCG_E_ARG                                           */
   DCG_PREC_BF16X2 = 2,  /* points as a pair hi + lo of bf16 (16 significant
                            bits); the distance GEMM takes the four bf16
                            products hi.hi, hi.lo, lo.hi, lo.lo on MFMA         */
@@ -67,9 +75,9 @@ enum dcg_prec {
                            rounded up to 256; 1 <= d <= 4096): every product
                            streams it from HBM once, each off-diagonal tile
                            serving its rows and its columns, with FP64
-                           accumulation.  For point
-                           dimensions beyond the pair sweep's 64 and for
-                           sequences that keep the kernel and lengthscale
+                           accumulation.  For FP32-accurate kernel values
+                           beyond 64 point dimensions and for sequences that
+                           keep the kernel and lengthscale
                            (s2, sigma2 and a diagonal scaling apply at product
                            time; a new ell rebuilds the matrix).  No FP64
                            operator: dcg_matvec_exact, refinement, the
@@ -186,8 +194,10 @@ size_t dcg_operator_workspace_bytes(int64_t n, int64_t d, int prec);
  * with its squared norms in the workspace, and keep (kernel, ell, s2,
  * sigma2).  X: device FP64 row-major n x d, read only here (a copy is
  * kept).  stream: a hipStream_t (NULL = default).  Requires n >= 1,
- * 1 <= d <= 64, ell > 0, s2 > 0, sigma2 >= 0.  Returns DCG_E_NONFINITE if
- * X holds NaN/Inf, DCG_E_ARG if fp16 operands would leave the fp16 range. */
+ * ell > 0, s2 > 0, sigma2 >= 0, and 1 <= d <= 64 (fp32, bf16x2 and FP64
+ * operators) or 1 <= d <= 4096 (bf16, fp16 and the stored operator).
+ * Returns DCG_E_NONFINITE if X holds NaN/Inf, DCG_E_ARG if fp16 operands
+ * would leave the fp16 range. */
 int dcg_create_operator(const double *X, int64_t n, int64_t d, int kernel,
                         double ell, double s2, double sigma2, int prec,
                         void *workspace, size_t ws_bytes, void *stream,
