@@ -459,7 +459,10 @@ __device__ __forceinline__ void cg_update_p_body(const CgArgs &a, const unsigned
   double xn = a.x[i] + alpha * pi;
   double xi = 0.0;
   double wmu = 0.0;
+  // unrolled so that eight columns' loads are in flight at once (each
+  // accumulator still adds its terms in column order)
   if (a.W32 != nullptr) {
+#pragma unroll 8
     for (int c = 0; c < a.k; ++c) {
       const double wv = static_cast<double>(a.W32[int64_t(c) * a.n + i]);
       ri -= static_cast<double>(a.AW32[int64_t(c) * a.n + i]) * cv[c];
@@ -467,6 +470,7 @@ __device__ __forceinline__ void cg_update_p_body(const CgArgs &a, const unsigned
       wmu += wv * mu[c];
     }
   } else {
+#pragma unroll 8
     for (int c = 0; c < a.k; ++c) {
       const double wv = a.W[int64_t(c) * a.n + i];
       ri -= a.AW[int64_t(c) * a.n + i] * cv[c];
