@@ -96,6 +96,9 @@ __device__ __forceinline__ void small_gemv_lds(const double *Ms, const double *h
                                                int k) {
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
     double s = 0.0;
+    // unrolled so that sixteen entries' LDS reads are in flight (the sum
+    // still runs in column order)
+#pragma unroll 16
     for (int j = 0; j < k; ++j) s += Ms[c * (kMaxK + 1) + j] * h[j];
     mu[c] = s;
   }
@@ -133,11 +136,15 @@ __device__ __forceinline__ void cg_matvec_finish_body(const CgArgs &a, const uns
         const int64_t ps = int64_t(R.mv) * R.n_pad;
         const double *prow = R.prow + int64_t(a.mcol) * R.n_pad;
         const float *pcol = R.pcol + int64_t(a.mcol) * R.n_pad;
+        // (the loops are unrolled so that several loads are in flight; each
+        // accumulator still adds its terms in order)
+#pragma unroll 4
         for (int c = sg; c < R.nchunk; c += 4) s += prow[int64_t(c) * ps + i];
         const int J = static_cast<int>(i / R.blk);
         const int dlim = ((R.nb % 2) == 0 && J < R.nb / 2) ? R.dmax - 1 : R.dmax;
         double s1 = 0.0, s2 = 0.0, s3 = 0.0;
         int dl = 1 + sg;
+#pragma unroll 2
         for (; dl + 12 <= dlim; dl += 16) {
           s += pcol[int64_t(dl - 1) * ps + i];
           s1 += pcol[int64_t(dl + 3) * ps + i];
