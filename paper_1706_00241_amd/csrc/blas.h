@@ -116,6 +116,7 @@ inline int64_t xr_grid(const CgArgs &a) { return a.nblk_xr * xr_groups(a.k); }
 
 __global__ void cg_matvec_finish(CgArgs a);
 __global__ void cg_update_xr(CgArgs a);
+__global__ void cg_update_xr_w32(CgArgs a);   // a.W32 set
 __global__ void cg_update_p(CgArgs a);
 __global__ void cg_finalize(CgArgs a);
 __global__ void cg_matvec_finish_multi(const CgArgs *args);

@@ -199,6 +199,9 @@ __device__ __forceinline__ void cg_matvec_finish_body(const CgArgs &a, const uns
 // columns grp * kXrCols ... of [AW | W]; group 0 also forms rho'.  The
 // kernel writes no vector, so the column groups of one row block never see
 // each other's updates.
+// kW32: the caller guarantees the FP32 copies of W and AW (a.W32 set), so
+// the FP64 column path is compiled out and fewer registers are live.
+template <bool kW32>
 __device__ __forceinline__ void cg_update_xr_body(const CgArgs &a, const unsigned bid) {
   SolveState *S = a.S;
   if (S->done) return;
@@ -229,7 +232,8 @@ __device__ __forceinline__ void cg_update_xr_body(const CgArgs &a, const unsigne
     rv[u] = a.r[ii[u]];
     qv[u] = a.q[ii[u]];
   }
-  if (k > 0 && a.W32 != nullptr) {
+  const bool w32 = kW32 || a.W32 != nullptr;
+  if (k > 0 && w32) {
 #pragma unroll
     for (int cc = 0; cc < kXrCols; ++cc) {
       const int c = grp * kXrCols + cc;
@@ -282,7 +286,7 @@ __device__ __forceinline__ void cg_update_xr_body(const CgArgs &a, const unsigne
     const bool colok = grp * kXrCols + cc < 2 * k;
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
-      const double y = (a.W32 != nullptr) ? static_cast<double>(yf[cc][u]) : yv[cc][u];
+      const double y = w32 ? static_cast<double>(yf[cc][u]) : yv[cc][u];
       yv[cc][u] = (colok && i0 + 256 * u < a.n) ? y : 0.0;
     }
   }
@@ -496,7 +500,8 @@ __device__ __forceinline__ void cg_update_p_body(const CgArgs &a, const unsigned
 // Kernels: one solve (arguments by value), or many columns / systems at once
 // (blockIdx.y selects the arguments of a column or system).
 __global__ __launch_bounds__(256) void cg_matvec_finish(CgArgs a) { cg_matvec_finish_body(a, blockIdx.x); }
-__global__ __launch_bounds__(256) void cg_update_xr(CgArgs a) { cg_update_xr_body(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void cg_update_xr(CgArgs a) { cg_update_xr_body<false>(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void cg_update_xr_w32(CgArgs a) { cg_update_xr_body<true>(a, blockIdx.x); }
 __global__ __launch_bounds__(256) void cg_finalize(CgArgs a) { cg_finalize_body(a); }
 __global__ __launch_bounds__(256) void cg_update_p(CgArgs a) { cg_update_p_body(a, blockIdx.x); }
 
@@ -508,7 +513,7 @@ __global__ __launch_bounds__(256) void cg_matvec_finish_multi(const CgArgs *args
 __global__ __launch_bounds__(256) void cg_update_xr_multi(const CgArgs *args) {
   const CgArgs &a = args[blockIdx.y];
   if (int64_t(blockIdx.x) >= a.nblk_xr * xr_groups(a.k)) return;
-  cg_update_xr_body(a, blockIdx.x);
+  cg_update_xr_body<false>(a, blockIdx.x);
 }
 __global__ __launch_bounds__(256) void cg_finalize_multi(const CgArgs *args) {
   cg_finalize_body(args[blockIdx.y]);

@@ -273,8 +273,12 @@ static int enqueue_cg_step(dcg_operator_s *op, const CgArgs &a, hipEvent_t ev0 =
   if (st != DCG_OK) return st;
   hipLaunchKernelGGL(cg_matvec_finish, dim3(static_cast<unsigned>(a.nblk_q)), dim3(256), 0,
                      op->stream, a);
-  hipLaunchKernelGGL(cg_update_xr, dim3(static_cast<unsigned>(xr_grid(a))), dim3(256), 0,
-                     op->stream, a);
+  if (a.W32 != nullptr)
+    hipLaunchKernelGGL(cg_update_xr_w32, dim3(static_cast<unsigned>(xr_grid(a))), dim3(256), 0,
+                       op->stream, a);
+  else
+    hipLaunchKernelGGL(cg_update_xr, dim3(static_cast<unsigned>(xr_grid(a))), dim3(256), 0,
+                       op->stream, a);
   hipLaunchKernelGGL(cg_finalize, dim3(1), dim3(256), 0, op->stream, a);
   hipLaunchKernelGGL(cg_update_p, dim3(static_cast<unsigned>(a.nblk_p)), dim3(256), 0,
                      op->stream, a);
