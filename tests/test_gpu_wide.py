@@ -43,13 +43,15 @@ def _points(n, d, seed):
 
 @pytest.mark.parametrize("prec", [1, 4])
 @pytest.mark.parametrize("kern", [0, 1, 2])
-@pytest.mark.parametrize("n,d", [(300, 65), (1000, 130), (700, 170), (2600, 784), (256, 4090)])
+@pytest.mark.parametrize("n,d", [(300, 65), (1000, 130), (700, 170), (2600, 784), (256, 4090),
+                                 (2, 100), (37, 785)])
 def test_wide_matvec_parity(lib, prec, kern, n, d):
     """One product (and a four-column block, formed one column at a time)
     against A V of the rounded points; the plan spans 1 to 11 blocks of 256
-    points with a ragged tail; the diagonal block pair gets distance zero.
-    The widths give 3, 5, 6, 25 and 128 stages of 32 K-elements (every
-    remainder modulo the four stage buffers)."""
+    points with a ragged tail, down to two points in one block; the diagonal
+    block pair gets distance zero.  The widths give 3, 4, 5, 6, 25 and 128
+    stages of 32 K-elements (every remainder modulo the four stage
+    buffers)."""
     print(f"wide matvec prec {prec} kern {kern} n {n} d {d}", flush=True)
     X = _points(n, d, seed=n + d)
     ell = workloads.median_distance(X)
