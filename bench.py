@@ -173,7 +173,7 @@ def oracle_product_seconds(w, block=256):
     """Wall time of one full product of the FP64 oracle, K(X, X) v over all n
     rows in its dense-row form (oracle.kernels.gram row blocks times v), on
     the host cores: a pool of one process per core (the cores this process
-    may run on, at most 16, the CPU share of a one-GPU machine), each taking
+    may run on, at most 16: the host's CPU share per GPU), each taking
     blocks of `block` rows.  Called before anything touches the GPU (the
     pool forks).  Returns (seconds, processes, cores in the affinity mask)."""
     import multiprocessing as mp
